@@ -1,0 +1,172 @@
+"""FP64 CPU oracle of the differentiable IDM simulator (arXiv 2412.16750).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+CPU-baseline leg of the benchmark.  The product path (``paper_2412_16750_amd``)
+never imports it, and the two share no code.
+
+The numerical work is in ``idm_oracle.c`` (plain sequential C, double
+precision), which follows Sec. III-A (Eqs. 1-3), Sec. III-B (synchronous
+per-frame update) and Sec. III-C (softplus lower bounds) of the paper, plus a
+hand-derived adjoint and tangent-linear model of the same equations.  The
+MLP oracle for the learned warm start is in ``mlp.py``.
+
+This module only builds/loads that library and marshals NumPy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "idm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+MODE_SOFTPLUS = 0
+MODE_CLAMP = 1
+PARAM_NAMES = ("v0", "T", "a", "b", "s0")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math",
+                               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        d, i, pd, pi = ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p
+        common = [i, d, d, d, d, i, i, pi, i] + [pd] * 6
+        L.oracle_forward.restype = ctypes.c_long
+        L.oracle_forward.argtypes = common + [pd, pd, pd, pd, pd]
+        L.oracle_adjoint.restype = ctypes.c_int
+        L.oracle_adjoint.argtypes = common + [pd, pd, pd, pd, pd, pd, pd]
+        L.oracle_tangent.restype = ctypes.c_int
+        L.oracle_tangent.argtypes = common + [pd, pd, pd, pd, pd, pd, pd]
+        L.oracle_mse.restype = ctypes.c_double
+        L.oracle_mse.argtypes = [i, i, pd, i, pi, pd, pd]
+        L.oracle_mae_sum.restype = ctypes.c_double
+        L.oracle_mae_sum.argtypes = [i, i, pd, i, pi, pd, pd]
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _d(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Problem:
+    """Plain description of one simulation problem in float64."""
+
+    def __init__(self, lane_offsets, params: Dict[str, np.ndarray], p0, v_init, n_steps: int,
+                 dt: float = 0.1, delta: float = 4.0, a_min: float = -10.0,
+                 gap_floor: float = 1e-3, mode: int = MODE_SOFTPLUS):
+        self.lane_offsets = np.ascontiguousarray(np.asarray(lane_offsets, dtype=np.int32))
+        self.n = int(self.lane_offsets[-1])
+        self.n_lanes = len(self.lane_offsets) - 1
+        self.params = {k: _d(params[k]) for k in PARAM_NAMES}
+        self.length = _d(params["length"])
+        self.p0 = _d(p0)
+        self.v_init = _d(v_init)
+        self.n_steps = int(n_steps)
+        self.dt, self.delta, self.a_min, self.gap_floor = float(dt), float(delta), float(a_min), float(gap_floor)
+        self.mode = int(mode)
+
+    @classmethod
+    def from_scenario(cls, sc, params=None, mode=None, n_steps=None):
+        return cls(sc.lane_offsets, params if params is not None else sc.params, sc.p0, sc.v_init,
+                   sc.n_steps if n_steps is None else n_steps, sc.dt, sc.delta, sc.a_min,
+                   sc.gap_floor, sc.mode if mode is None else mode)
+
+    def _head(self):
+        pr = self.params
+        return [self.mode, self.dt, self.delta, self.a_min, self.gap_floor, self.n, self.n_lanes,
+                _p(self.lane_offsets), self.n_steps, _p(pr["v0"]), _p(pr["T"]), _p(pr["a"]),
+                _p(pr["b"]), _p(pr["s0"]), _p(self.length)]
+
+
+def forward(pb: Problem, want_acc: bool = False):
+    """Returns (P, V, A or None, floor_hits); P, V are [(S+1), N] float64."""
+    S, n = pb.n_steps, pb.n
+    P = np.empty((S + 1, n), dtype=np.float64)
+    V = np.empty((S + 1, n), dtype=np.float64)
+    A = np.empty((S, n), dtype=np.float64) if want_acc else None
+    hits = lib().oracle_forward(*pb._head(), _p(pb.p0), _p(pb.v_init), _p(P), _p(V), _p(A))
+    if hits < 0:
+        raise ValueError("oracle_forward: invalid arguments")
+    return P, V, A, int(hits)
+
+
+def adjoint(pb: Problem, P, V, gP, gV=None):
+    """Returns (g_params [5, N] in (v0, T, a, b, s0) order, g_p0 [N], g_v0 [N])."""
+    S, n = pb.n_steps, pb.n
+    gP = _d(gP).reshape(S + 1, n)
+    gV = None if gV is None else _d(gV).reshape(S + 1, n)
+    g = np.empty((5, n), dtype=np.float64)
+    gp0 = np.empty(n, dtype=np.float64)
+    gv0 = np.empty(n, dtype=np.float64)
+    rc = lib().oracle_adjoint(*pb._head(), _p(_d(P)), _p(_d(V)), _p(gP), _p(gV), _p(g), _p(gp0), _p(gv0))
+    if rc != 0:
+        raise ValueError("oracle_adjoint: invalid arguments")
+    return g, gp0, gv0
+
+
+def tangent(pb: Problem, P, V, dprm, dp0, dv0):
+    S, n = pb.n_steps, pb.n
+    dP = np.empty((S + 1, n), dtype=np.float64)
+    dV = np.empty((S + 1, n), dtype=np.float64)
+    rc = lib().oracle_tangent(*pb._head(), _p(_d(P)), _p(_d(V)), _p(_d(dprm).reshape(5, n)), _p(_d(dp0)),
+                              _p(_d(dv0)), _p(dP), _p(dV))
+    if rc != 0:
+        raise ValueError("oracle_tangent: invalid arguments")
+    return dP, dV
+
+
+def mse(P, steps: Sequence[int], target, want_grad: bool = True):
+    """Mean squared error over observed steps; returns (loss, dL/dP or None)."""
+    P = _d(P)
+    S1, n = P.shape
+    steps = np.ascontiguousarray(np.asarray(steps, dtype=np.int32))
+    target = _d(target).reshape(len(steps), n)
+    gP = np.zeros_like(P) if want_grad else None
+    loss = lib().oracle_mse(n, S1 - 1, _p(P), len(steps), _p(steps), _p(target), _p(gP))
+    return float(loss), gP
+
+
+def mae_sum(P, steps: Sequence[int], target, want_grad: bool = True):
+    """The paper's summed absolute reconstruction error (Sec. IV-A, Eq. 4)."""
+    P = _d(P)
+    S1, n = P.shape
+    steps = np.ascontiguousarray(np.asarray(steps, dtype=np.int32))
+    target = _d(target).reshape(len(steps), n)
+    gP = np.zeros_like(P) if want_grad else None
+    loss = lib().oracle_mae_sum(n, S1 - 1, _p(P), len(steps), _p(steps), _p(target), _p(gP))
+    return float(loss), gP
+
+
+def loss_and_grads(pb: Problem, steps, target, dense_grad=None):
+    """Forward + MSE (+ optional dense upstream dL/dP added) + adjoint."""
+    P, V, _, hits = forward(pb)
+    loss, gP = mse(P, steps, target)
+    if dense_grad is not None:
+        gP = gP + _d(dense_grad).reshape(gP.shape)
+    g, gp0, gv0 = adjoint(pb, P, V, gP)
+    return dict(P=P, V=V, loss=loss, g=g, gp0=gp0, gv0=gv0, floor_hits=hits)

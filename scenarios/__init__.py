@@ -1,0 +1,243 @@
+"""Seeded synthetic scenarios for the IDM simulator.
+
+This module only draws random inputs and lays vehicles out on lanes. It holds
+none of the simulation's arithmetic (no gap, acceleration or Euler update), so
+both the FP64 CPU oracle and the HIP path can consume the same inputs.
+
+Workload shapes follow the paper's setting (Sec. III-A: one-dimensional lanes,
+each vehicle following the one directly ahead; Sec. V-A: up to 2 million
+vehicles) and the five workloads the repository measures:
+
+* ``single_lane``  : 1 open lane x 100 vehicles, 1000 steps of 0.1 s.
+* ``scale``        : 2000 lanes x 1000 vehicles = 2M vehicles, 100 steps,
+                     checkpoints every 32 steps.
+* ``uneven``       : 10,000 independent lanes, sizes round(lognormal(5, 1.2))
+                     clipped to [10, 4096], 300 steps.
+* ``fit``          : 100 lanes x 1000 vehicles, 500 steps, observations every
+                     10th step with N(0, 0.5 m) noise.
+* ``warm``         : pairs for the learned warm start, drawn like ``fit``.
+
+Per-vehicle draws (all uniform): v0 in [25, 35] m/s, T in [1, 2] s,
+a in [1, 2] m/s^2, b in [1.5, 3] m/s^2, s0 in [1.5, 3] m; length 5 m;
+bumper-to-bumper initial gaps in [20, 40] m; initial speeds in [10, 25] m/s.
+The tail vehicle of every lane starts at p = 0 and leaders sit ahead of it, so
+every position is non-negative. Lanes are stored head -> tail, contiguously,
+with CSR offsets.
+
+Seeds: params 1000 + c, second (target) params 2000 + c, initial state
+3000 + c, noise 4000 + c, lane sizes 5000 + c, where c is the workload number
+(1..5).  Random numbers are NumPy PCG64 streams (``numpy.random.default_rng``).
+Parameters, speeds and lengths are drawn in float64 and rounded once to float32,
+because the GPU path stores them in float32; the oracle promotes exactly those
+float32 values to float64, so both sides simulate the same problem.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+from typing import Dict, Optional
+
+import numpy as np
+
+PARAM_NAMES = ("v0", "T", "a", "b", "s0")
+
+# Uniform ranges of the per-vehicle IDM parameters.
+PARAM_RANGES = {
+    "v0": (25.0, 35.0),
+    "T": (1.0, 2.0),
+    "a": (1.0, 2.0),
+    "b": (1.5, 3.0),
+    "s0": (1.5, 3.0),
+}
+# Box used when fitting normalised parameters: theta = lo + u * (hi - lo).
+FIT_BOXES = {
+    "v0": (15.0, 45.0),
+    "T": (0.5, 3.0),
+    "a": (0.5, 3.0),
+    "b": (0.5, 4.0),
+    "s0": (0.5, 5.0),
+}
+# Cold start of the fit: the mean of each uniform range.
+COLD_START = {k: 0.5 * (lo + hi) for k, (lo, hi) in PARAM_RANGES.items()}
+
+MODE_SOFTPLUS = 0
+MODE_CLAMP = 1
+
+
+@dataclass
+class Scenario:
+    """One seeded problem: lanes, per-vehicle parameters and initial state."""
+
+    name: str
+    lane_offsets: np.ndarray          # int32 [L+1], vehicles head -> tail
+    params: Dict[str, np.ndarray]     # float32 [N] each: v0, T, a, b, s0, length
+    p0: np.ndarray                    # float64 [N] initial positions (m)
+    v_init: np.ndarray                # float32 [N] initial speeds (m/s)
+    n_steps: int
+    dt: float = 0.1
+    delta: float = 4.0
+    a_min: float = -10.0
+    gap_floor: float = 1e-3
+    mode: int = MODE_SOFTPLUS
+    ckpt_every: int = 32
+    extra: Dict[str, object] = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.lane_offsets[-1])
+
+    @property
+    def n_lanes(self) -> int:
+        return int(len(self.lane_offsets) - 1)
+
+    def with_(self, **kw) -> "Scenario":
+        return replace(self, **kw)
+
+
+def _f32(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64).astype(np.float32))
+
+
+def draw_params(rng: np.random.Generator, n: int) -> Dict[str, np.ndarray]:
+    """Per-vehicle IDM parameters (float32) plus the 5 m vehicle length."""
+    out = {}
+    for k in PARAM_NAMES:
+        lo, hi = PARAM_RANGES[k]
+        out[k] = _f32(rng.uniform(lo, hi, size=n))
+    out["length"] = np.full(n, 5.0, dtype=np.float32)
+    return out
+
+
+def place_lanes(rng: np.random.Generator, lane_offsets: np.ndarray,
+                length: np.ndarray, gap_range=(20.0, 40.0),
+                speed_range=(10.0, 25.0)):
+    """Initial positions (float64) and speeds (float32).
+
+    Within a lane the tail is at 0 and vehicle i-1 (the leader of i) sits at
+    p[i] + length[i-1] + gap[i], with bumper-to-bumper gaps drawn uniformly.
+    """
+    n = int(lane_offsets[-1])
+    gaps = rng.uniform(gap_range[0], gap_range[1], size=n)
+    v = _f32(rng.uniform(speed_range[0], speed_range[1], size=n))
+    p = np.zeros(n, dtype=np.float64)
+    lens = np.asarray(length, dtype=np.float64)
+    for lane in range(len(lane_offsets) - 1):
+        lo, hi = int(lane_offsets[lane]), int(lane_offsets[lane + 1])
+        if hi <= lo:
+            continue
+        # walk from the tail (hi-1) towards the head (lo)
+        seg_gap = gaps[lo + 1:hi]            # gap in front of vehicles lo+1..hi-1
+        seg_len = lens[lo:hi - 1]            # length of their leaders lo..hi-2
+        inc = (seg_gap + seg_len)[::-1]      # tail first
+        pos = np.concatenate([[0.0], np.cumsum(inc)])[::-1]
+        p[lo:hi] = pos
+    return p, v
+
+
+def uniform_lanes(n_lanes: int, lane_len: int) -> np.ndarray:
+    return (np.arange(n_lanes + 1, dtype=np.int64) * lane_len).astype(np.int32)
+
+
+def lognormal_lane_sizes(n_lanes: int, mu: float, sigma: float, lo: int, hi: int,
+                         seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    sizes = np.rint(rng.lognormal(mu, sigma, size=n_lanes))
+    return np.clip(sizes, lo, hi).astype(np.int64)
+
+
+def offsets_from_sizes(sizes) -> np.ndarray:
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=off[1:])
+    if off[-1] >= 2 ** 31:
+        raise ValueError("too many vehicles for int32 offsets")
+    return off.astype(np.int32)
+
+
+def make_scenario(name: str, lane_offsets: np.ndarray, n_steps: int, c: int,
+                  **kw) -> Scenario:
+    n = int(lane_offsets[-1])
+    params = draw_params(np.random.default_rng(1000 + c), n)
+    p0, v = place_lanes(np.random.default_rng(3000 + c), lane_offsets, params["length"])
+    return Scenario(name=name, lane_offsets=np.ascontiguousarray(lane_offsets, dtype=np.int32),
+                    params=params, p0=p0, v_init=v, n_steps=n_steps, **kw)
+
+
+def single_lane(n_vehicles: int = 100, n_steps: int = 1000, mode: int = MODE_SOFTPLUS,
+                **kw) -> Scenario:
+    """Workload 1: one open lane, head on free road."""
+    return make_scenario("single_lane", uniform_lanes(1, n_vehicles), n_steps, 1,
+                         mode=mode, **kw)
+
+
+def scale(n_lanes: int = 2000, lane_len: int = 1000, n_steps: int = 100,
+          ckpt_every: int = 32, **kw) -> Scenario:
+    """Workload 2: 2000 x 1000 = 2M vehicles, 100 steps, checkpoints every 32."""
+    return make_scenario("scale", uniform_lanes(n_lanes, lane_len), n_steps, 2,
+                         ckpt_every=ckpt_every, **kw)
+
+
+def uneven(n_lanes: int = 10000, n_steps: int = 300, mu: float = 5.0, sigma: float = 1.2,
+           lo: int = 10, hi: int = 4096, **kw) -> Scenario:
+    """Workload 3: many independent lanes of lognormal length."""
+    sizes = lognormal_lane_sizes(n_lanes, mu, sigma, lo, hi, 5000 + 3)
+    return make_scenario("uneven", offsets_from_sizes(sizes), n_steps, 3, **kw)
+
+
+def fit(n_lanes: int = 100, lane_len: int = 1000, n_steps: int = 500, obs_every: int = 10,
+        **kw) -> Scenario:
+    """Workload 4: hidden params = the usual draw; observations every 10th step."""
+    sc = make_scenario("fit", uniform_lanes(n_lanes, lane_len), n_steps, 4, **kw)
+    sc.extra["obs_first"] = obs_every
+    sc.extra["obs_stride"] = obs_every
+    return sc
+
+
+def second_params(sc: Scenario, c: int) -> Dict[str, np.ndarray]:
+    """An independent parameter draw for the same vehicles (target generation)."""
+    p = draw_params(np.random.default_rng(2000 + c), sc.n)
+    p["length"] = sc.params["length"].copy()
+    return p
+
+
+def cold_params(sc: Scenario) -> Dict[str, np.ndarray]:
+    out = {k: np.full(sc.n, COLD_START[k], dtype=np.float32) for k in PARAM_NAMES}
+    out["length"] = sc.params["length"].copy()
+    return out
+
+
+def noise(shape, c: int, sigma: float = 0.5) -> np.ndarray:
+    """N(0, sigma) observation noise, float64."""
+    return np.random.default_rng(4000 + c).normal(0.0, sigma, size=shape)
+
+
+def obs_steps(n_steps: int, first: int, stride: int) -> np.ndarray:
+    """Observed step indices first, first+stride, ... <= n_steps."""
+    if first < 0 or stride < 1 or first > n_steps:
+        raise ValueError("bad observation schedule")
+    return np.arange(first, n_steps + 1, stride, dtype=np.int32)
+
+
+def constant_speed_targets(sc: Scenario, steps: np.ndarray, c: int,
+                           sigma: float = 0.5) -> np.ndarray:
+    """Dense synthetic targets for throughput runs: p0 + v_init * t + noise.
+
+    Returns float32 [len(steps)][N].  Only the shape and magnitude matter for a
+    throughput measurement; the values are not produced by any simulator.
+    """
+    t = steps.astype(np.float64)[:, None] * sc.dt
+    base = sc.p0[None, :] + sc.v_init.astype(np.float64)[None, :] * t
+    return (base + noise(base.shape, c, sigma)).astype(np.float32)
+
+
+def subset_lanes(sc: Scenario, lanes) -> Scenario:
+    """A scenario made of the given lanes of ``sc`` (same values, same order)."""
+    lanes = np.asarray(lanes, dtype=np.int64)
+    off = sc.lane_offsets.astype(np.int64)
+    idx = np.concatenate([np.arange(off[l], off[l + 1]) for l in lanes]) if len(lanes) else \
+        np.zeros(0, dtype=np.int64)
+    sizes = off[lanes + 1] - off[lanes]
+    return Scenario(name=sc.name + "_sub", lane_offsets=offsets_from_sizes(sizes),
+                    params={k: np.ascontiguousarray(v[idx]) for k, v in sc.params.items()},
+                    p0=np.ascontiguousarray(sc.p0[idx]), v_init=np.ascontiguousarray(sc.v_init[idx]),
+                    n_steps=sc.n_steps, dt=sc.dt, delta=sc.delta, a_min=sc.a_min,
+                    gap_floor=sc.gap_floor, mode=sc.mode, ckpt_every=sc.ckpt_every,
+                    extra=dict(sc.extra, vehicle_index=idx))
