@@ -1,0 +1,243 @@
+/*
+ * idm.h -- C ABI of the MI355X (gfx950) differentiable IDM traffic simulator.
+ *
+ * Method: "Gradient-based Trajectory Optimization with Parallelized
+ * Differentiable Traffic Simulation" (arXiv 2412.16750).
+ *   - Sec. III-A, Eqs. 1-2: each vehicle's acceleration follows the Intelligent
+ *     Driver Model from its own speed and the gap / speed difference to the
+ *     vehicle directly ahead in its lane (its leader h(i)).
+ *   - Sec. III-A, Eq. 3: explicit Euler update, position with the old speed.
+ *   - Sec. III-B, Fig. 3: all vehicles of a frame are updated synchronously
+ *     from the same frame's state.
+ *   - Sec. III-C: optional softplus lower bounds (s_opt >= 0 and
+ *     a >= max(-v/dt, a_min)), which keep speeds non-negative.
+ *   - Sec. IV-A: parameters are fitted by gradient descent on a trajectory
+ *     loss against observed positions; Adam with box constraints.
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers owned by the caller unless the name ends in
+ *     _host.  The library never frees or retains caller memory.
+ *   - Vehicles are grouped in lanes given by CSR offsets; inside a lane they
+ *     are ordered head -> tail (the leader of vehicle i is i-1 unless i is the
+ *     first vehicle of its lane, which drives on a free road).
+ *   - Per-vehicle arrays have N entries; per-step arrays are step-major
+ *     [(n_steps+1) * N], element k*N + i being vehicle i at step k.
+ *   - Positions are handled as FP64 initial positions p0 plus FP32
+ *     displacements d_k = p_k - p0.
+ *   - Parameter blocks are ordered (v0, T, a, b, s0) = (v_targ, T_pref,
+ *     a_max, a_pref, s_min) in the paper's notation.
+ *   - All compute calls are asynchronous on `stream` (a hipStream_t passed as
+ *     void*), allocate nothing, synchronise nothing, and can be captured in a
+ *     HIP graph.  Arguments are validated before any launch; on error nothing
+ *     is launched, the status is returned and idm_last_error() describes it.
+ *   - Nothing throws across this boundary.
+ */
+#ifndef IDM_H
+#define IDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IDM_OK = 0,
+    IDM_ERR_INVALID_ARG = -1, /* null pointer, non-positive size, NaN, ... */
+    IDM_ERR_LAYOUT = -2,      /* lane offsets not monotone / not covering N, lane too long */
+    IDM_ERR_UNSUPPORTED = -3, /* a value the kernels do not implement (e.g. delta != 4) */
+    IDM_ERR_WORKSPACE = -4,   /* workspace missing or too small */
+    IDM_ERR_HIP = -5          /* a HIP runtime call failed; message has the HIP error */
+} idm_status;
+
+/* Velocity bound. */
+enum {
+    IDM_BOUND_SOFTPLUS = 0, /* Sec. III-C: s* = softplus(s_opt); a* = a_lb + softplus(a - a_lb) */
+    IDM_BOUND_CLAMP = 1     /* textbook IDM, speed clamped: v' = max(v + dt*a, 0) */
+};
+
+/* The simulation problem (Sec. III-A): lanes, step count and constants. */
+typedef struct {
+    int32_t n_vehicles;               /* N >= 1 */
+    int32_t n_lanes;                  /* L >= 1 */
+    int32_t n_steps;                  /* S >= 0 Euler steps of length dt */
+    int32_t ckpt_every;               /* K: checkpoint interval of the forward and block
+                                         length of the backward recompute; 0 = let the
+                                         library choose */
+    float dt;                         /* > 0, seconds */
+    float delta;                      /* free-road exponent; only 4 is implemented */
+    float a_min;                      /* maximum deceleration bound (< 0), e.g. -10 */
+    float gap_floor;                  /* gap used in (s/gap)^2 is max(gap, gap_floor) >= 0 */
+    int32_t bound;                    /* IDM_BOUND_* */
+    const int32_t *lane_offsets_host; /* [L+1], offsets[0] = 0, offsets[L] = N, non-decreasing */
+} idm_problem;
+
+/* Launch shape.  Zero fields mean "choose".  A work-group of `threads`
+ * threads owns `threads * per_thread` consecutive vehicle slots holding
+ * whole lanes; a lane longer than that is rejected (IDM_ERR_LAYOUT). */
+typedef struct {
+    int32_t threads;    /* 64, 128, 256, 512 or 1024 */
+    int32_t per_thread; /* vehicles per thread: 1, 2 or 4 */
+    int32_t ckpt_every; /* K in {4, 8, 16, 32}; overrides the problem's K when > 0 */
+    int32_t grid;       /* >0: persistent grid of that many work-groups walking the bundle
+                           list; 0: one work-group per bundle */
+} idm_tuning;
+
+/* Per-vehicle IDM parameters (Sec. III-A), FP32 [N] each, all > 0. */
+typedef struct {
+    const float *v0;     /* desired speed v_targ (m/s) */
+    const float *T;      /* time headway T_pref (s) */
+    const float *a;      /* maximum acceleration a_max (m/s^2) */
+    const float *b;      /* comfortable deceleration a_pref (m/s^2) */
+    const float *s0;     /* jam distance s_min (m) */
+    const float *length; /* vehicle length (m); the follower subtracts its LEADER's length */
+} idm_params;
+
+/* Observed positions for the fused mean-squared trajectory loss
+ * (the squared-error counterpart of Sec. IV-A, Eq. 4).  Observation j is step
+ * obs_first + j*obs_stride (must be <= n_steps) for every vehicle;
+ * target[j*N + i] is the observed absolute position (m), FP32.
+ * L = 1/(n_obs*N) * sum_j sum_i (p0_i + d_k(i) - target[j*N+i])^2, summed in FP64. */
+typedef struct {
+    const float *target;
+    int32_t n_obs;
+    int32_t obs_first;
+    int32_t obs_stride;
+} idm_obs;
+
+typedef struct idm_plan idm_plan;
+
+/* Plan: validates the problem, packs lanes into work-group bundles and uploads
+ * that small table to device memory owned by the plan (the only allocation
+ * the library makes; freed by idm_plan_destroy).  `tuning` may be NULL. */
+idm_status idm_plan_create(const idm_problem *problem, const idm_tuning *tuning, idm_plan **out);
+idm_status idm_plan_destroy(idm_plan *plan);
+
+/* Bytes of device workspace the caller must pass to the compute calls:
+ * checkpoints ceil(S/K) * 2 * N * 4 B, per-bundle loss partials, and the
+ * FP64 gradient buffer used by idm_fit_step.  256-byte aligned. */
+size_t idm_workspace_bytes(const idm_plan *plan);
+
+/* Chosen launch shape and packing statistics. */
+typedef struct {
+    int32_t threads, per_thread, ckpt_every, grid;
+    int32_t n_bundles;      /* work-group bundles */
+    int32_t max_lane;       /* longest lane (vehicles) */
+    int64_t n_slots;        /* bundles * threads * per_thread */
+    double fill;            /* N / n_slots */
+} idm_plan_info;
+idm_status idm_plan_get_info(const idm_plan *plan, idm_plan_info *out);
+
+/* Host-only checks (no device needed, nothing allocated): validate a problem
+ * and tuning exactly as idm_plan_create does, and report the launch shape,
+ * bundle statistics and workspace size it would get (info and
+ * workspace_bytes are nullable). */
+idm_status idm_problem_check(const idm_problem *problem, const idm_tuning *tuning,
+                             idm_plan_info *info, size_t *workspace_bytes);
+
+/* Host-only: the bundle layout idm_plan_create would upload.  Slot s of
+ * bundle b is element b*threads*per_thread + s; slot_vehicle_host receives the
+ * vehicle index (-1 = padding) and slot_flags_host bit 0 = lane head, bit 1 =
+ * lane tail, bit 2 = occupied.  Both arrays must hold `capacity` >= n_slots
+ * entries (see idm_problem_check), else IDM_ERR_INVALID_ARG. */
+idm_status idm_problem_layout(const idm_problem *problem, const idm_tuning *tuning,
+                              int32_t *slot_vehicle_host, uint8_t *slot_flags_host,
+                              int64_t capacity);
+
+/* Forward simulation (Eqs. 1-3 with the chosen bound, Sec. III-B update
+ * order), all n_steps in one launch.
+ *   p0      [N] FP64 initial positions;  v_init [N] FP32 initial speeds.
+ *   traj_d  [(S+1)*N] FP32 displacement p_k - p0 (nullable: not written).
+ *   traj_v  [(S+1)*N] FP32 speeds (nullable).
+ *   workspace: receives the checkpoints the backward pass needs (may be NULL
+ *   when no backward will follow). */
+idm_status idm_sim_forward(idm_plan *plan, const idm_params *prm, const double *p0,
+                           const float *v_init, float *traj_d, float *traj_v, void *workspace,
+                           void *stream);
+
+/* Reverse-mode gradient of a scalar loss L with respect to the five
+ * parameters and the initial state (the paper differentiates the same
+ * simulation, Sec. III-B).  Must follow idm_sim_forward with the same inputs
+ * and workspace (it recomputes each K-step block from the checkpoints).
+ * Upstream gradient = any combination of:
+ *   grad_traj_d [(S+1)*N] FP32 dL/dd_k (= dL/dp_k), nullable;
+ *   grad_traj_v [(S+1)*N] FP32 dL/dv_k, nullable;
+ *   obs: fused mean-squared trajectory loss (see idm_obs), nullable.
+ * Outputs (overwritten, FP64): grad_params [5*N] (v0, T, a, b, s0 blocks),
+ * grad_p0 [N] = dL/dp(0), grad_v0 [N] = dL/dv(0).  loss_out (device FP64
+ * scalar, nullable) receives the fused loss (0 if obs is NULL).  Per-vehicle
+ * gradients are summed over time in FP64 in a fixed order; no atomics, so
+ * results are bitwise reproducible. */
+idm_status idm_sim_backward(idm_plan *plan, const idm_params *prm, const double *p0,
+                            const float *v_init, const float *grad_traj_d,
+                            const float *grad_traj_v, const idm_obs *obs, double *grad_params,
+                            double *grad_p0, double *grad_v0, double *loss_out, void *workspace,
+                            void *stream);
+
+/* One gradient step of the trajectory fit (Sec. IV-A): forward (checkpoints
+ * only), fused MSE loss and backward, then Adam on NORMALISED parameters
+ * u = (theta - lo) / (hi - lo) followed by projection of u onto [0, 1] (the
+ * paper's box constraints).  The physical parameters params[5*N] are
+ * rewritten from u after the step and are what the simulation reads.
+ * All state lives in device memory, so a call can be captured in a HIP graph
+ * and replayed (see idm_fit_run). */
+typedef struct {
+    float *u;              /* [5*N] normalised parameters, updated */
+    float *m;              /* [5*N] Adam first moment, updated */
+    float *v;              /* [5*N] Adam second moment, updated */
+    float *params;         /* [5*N] physical parameters (v0, T, a, b, s0 blocks), rewritten */
+    const float *length;   /* [N] vehicle lengths */
+    int32_t *step;         /* device int32: Adam step counter t (0 before the first step), updated */
+    double *loss_hist;     /* device [hist_len] FP64: loss of step t goes to min(t, hist_len-1) */
+    int32_t hist_len;      /* >= 1 */
+    float lo[5], hi[5];    /* box per parameter kind, hi > lo */
+    float lr0, lr1;        /* learning rate, linear from lr0 (t=0) to lr1 (t >= lr_steps) */
+    int32_t lr_steps;      /* >= 1 */
+    float beta1, beta2, eps;
+} idm_fit_state;
+
+idm_status idm_fit_step(idm_plan *plan, const idm_fit_state *st, const double *p0,
+                        const float *v_init, const idm_obs *obs, void *workspace, void *stream);
+
+/* n_iters fit steps: the first call for a given argument set captures one
+ * step in a HIP graph owned by the plan; every iteration is a graph replay. */
+idm_status idm_fit_run(idm_plan *plan, const idm_fit_state *st, const double *p0,
+                       const float *v_init, const idm_obs *obs, int32_t n_iters,
+                       void *workspace, void *stream);
+
+/* Forward + backward as one HIP graph (captured on first use for a given
+ * argument set, then replayed): the batched launch for many independent
+ * lanes.  Arguments as in idm_sim_forward / idm_sim_backward. */
+typedef struct {
+    idm_params prm;
+    const double *p0;
+    const float *v_init;
+    float *traj_d, *traj_v;
+    const float *grad_traj_d, *grad_traj_v;
+    const float *obs_target; /* NULL: no fused loss */
+    int32_t n_obs, obs_first, obs_stride;
+    double *grad_params, *grad_p0, *grad_v0, *loss_out;
+    void *workspace;
+} idm_step_args;
+idm_status idm_step_graph_launch(idm_plan *plan, const idm_step_args *args, void *stream);
+
+/* Autotuner: times forward + backward of every candidate launch shape
+ * (threads x per_thread x K) whose lanes fit and whose workspace fits in
+ * `workspace_bytes`, `reps` times each, on the real inputs, and switches the
+ * plan to the fastest.  Synchronises `stream`.  Results of the timed runs are
+ * discarded (they overwrite the output buffers).  Any graph captured by the
+ * plan is dropped. */
+idm_status idm_plan_autotune(idm_plan *plan, const idm_step_args *args, size_t workspace_bytes,
+                             int32_t reps, void *stream);
+
+/* Thread-local description of the last error (never NULL). */
+const char *idm_last_error(void);
+
+/* Library version string. */
+const char *idm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IDM_H */

@@ -1,0 +1,725 @@
+// Host runtime behind the C ABI declared in include/idm.h: validation, lane
+// packing into work-group bundles, workspace layout, kernel dispatch, HIP
+// graph capture/replay of the step and fit sequences, and the autotuner.
+#include "idm.h"
+#include "idm_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace idmx;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+idm_status fail(idm_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+idm_status hip_fail(hipError_t e, const char *what) {
+    return fail(IDM_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Shape {
+    int threads = 0, per_thread = 0, K = 0, grid = 0;
+};
+
+bool valid_threads(int t) { return t == 64 || t == 128 || t == 256 || t == 512 || t == 1024; }
+bool valid_per_thread(int r) { return r == 1 || r == 2 || r == 4; }
+
+// Backward block lengths instantiated for each vehicles-per-thread count.
+std::vector<int> ks_for(int r) {
+    if (r == 1) return {8, 16, 32};
+    if (r == 2) return {8, 16};
+    return {4, 8};
+}
+
+bool k_ok(int r, int K) {
+    auto v = ks_for(r);
+    return std::find(v.begin(), v.end(), K) != v.end();
+}
+
+}  // namespace
+
+struct idm_plan {
+    idm_problem pb{};
+    std::vector<int32_t> offsets;
+    int32_t max_lane = 0;
+    Shape sh;
+    // bundle layout
+    int32_t n_bundles = 0;
+    int64_t n_slots = 0;
+    int32_t *d_gidx = nullptr;
+    uint8_t *d_flags = nullptr;
+    // graphs
+    hipGraphExec_t step_exec = nullptr;
+    idm_step_args step_key{};
+    hipGraphExec_t fit_exec = nullptr;
+    std::vector<unsigned char> fit_key;
+};
+
+namespace {
+
+int32_t nblk_of(const idm_plan *p) {
+    return p->pb.n_steps == 0 ? 0 : (p->pb.n_steps + p->sh.K - 1) / p->sh.K;
+}
+
+// Workspace layout: [loss partials: n_lanes doubles][fit: 7N doubles][checkpoints]
+size_t ws_loss_off(const idm_plan *) { return 0; }
+size_t ws_fit_off(const idm_plan *p) { return align_up(sizeof(double) * (size_t)p->pb.n_lanes); }
+size_t ws_ckpt_off(const idm_plan *p) {
+    return ws_fit_off(p) + align_up(sizeof(double) * 7 * (size_t)p->pb.n_vehicles);
+}
+size_t ckpt_bytes(const idm_plan *p, int K) {
+    size_t nb = p->pb.n_steps == 0 ? 0 : (size_t)(p->pb.n_steps + K - 1) / K;
+    return align_up(nb * 2 * sizeof(float) * (size_t)p->pb.n_vehicles);
+}
+size_t ws_total(const idm_plan *p, int K) { return ws_ckpt_off(p) + ckpt_bytes(p, K); }
+
+void drop_graphs(idm_plan *p) {
+    if (p->step_exec) hipGraphExecDestroy(p->step_exec);
+    if (p->fit_exec) hipGraphExecDestroy(p->fit_exec);
+    p->step_exec = nullptr;
+    p->fit_exec = nullptr;
+    p->fit_key.clear();
+    memset(&p->step_key, 0, sizeof p->step_key);
+}
+
+// Pack lanes into bundles of `cap` slots: best-fit decreasing on lane size,
+// deterministic (ties keep lane order), then bundles sorted by fill (largest
+// first) so that a persistent grid starts with the most work.  Host only.
+struct Layout {
+    int64_t n_bundles = 0, cap = 0;
+    std::vector<int32_t> gidx;
+    std::vector<uint8_t> flags;
+};
+
+idm_status compute_layout(const std::vector<int32_t> &offsets, int L, const Shape &sh, Layout &out) {
+    const int64_t cap = (int64_t)sh.threads * sh.per_thread;
+    std::vector<int> order;
+    order.reserve(L);
+    for (int l = 0; l < L; ++l)
+        if (offsets[l + 1] > offsets[l]) order.push_back(l);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return (offsets[x + 1] - offsets[x]) > (offsets[y + 1] - offsets[y]);
+    });
+    std::vector<std::vector<int>> bundles;
+    std::vector<int64_t> fill;
+    std::multimap<int64_t, int> room;  // remaining capacity -> bundle
+    for (int l : order) {
+        int64_t sz = offsets[l + 1] - offsets[l];
+        if (sz > cap) return fail(IDM_ERR_LAYOUT, "lane %d has %lld vehicles > bundle capacity %lld", l,
+                                  (long long)sz, (long long)cap);
+        auto it = room.lower_bound(sz);
+        int b;
+        if (it == room.end()) {
+            b = (int)bundles.size();
+            bundles.emplace_back();
+            fill.push_back(0);
+        } else {
+            b = it->second;
+            room.erase(it);
+        }
+        bundles[b].push_back(l);
+        fill[b] += sz;
+        if (cap - fill[b] > 0) room.emplace(cap - fill[b], b);
+    }
+    std::vector<int> border(bundles.size());
+    for (size_t i = 0; i < border.size(); ++i) border[i] = (int)i;
+    std::stable_sort(border.begin(), border.end(), [&](int x, int y) { return fill[x] > fill[y]; });
+    const int64_t nb = (int64_t)bundles.size();
+    if (nb * cap >= ((int64_t)1 << 40) || nb >= ((int64_t)1 << 31))
+        return fail(IDM_ERR_LAYOUT, "layout too large");
+    out.n_bundles = nb;
+    out.cap = cap;
+    out.gidx.assign((size_t)(nb * cap), -1);
+    out.flags.assign((size_t)(nb * cap), 0);
+    for (int64_t bi = 0; bi < nb; ++bi) {
+        int64_t s = bi * cap;
+        for (int l : bundles[border[bi]]) {
+            int32_t lo = offsets[l], hi = offsets[l + 1];
+            for (int32_t i = lo; i < hi; ++i, ++s) {
+                out.gidx[s] = i;
+                uint8_t f = SLOT_VALID;
+                if (i == lo) f |= SLOT_HEAD;
+                if (i == hi - 1) f |= SLOT_TAIL;
+                out.flags[s] = f;
+            }
+        }
+    }
+    return IDM_OK;
+}
+
+idm_status build_layout(idm_plan *p, const Shape &sh) {
+    Layout lay;
+    idm_status r = compute_layout(p->offsets, p->pb.n_lanes, sh, lay);
+    if (r != IDM_OK) return r;
+    int32_t *dg = nullptr;
+    uint8_t *df = nullptr;
+    size_t n = lay.gidx.size() ? lay.gidx.size() : 1;
+    hipError_t e = hipMalloc(&dg, n * sizeof(int32_t));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(slot table)");
+    e = hipMalloc(&df, n);
+    if (e != hipSuccess) {
+        hipFree(dg);
+        return hip_fail(e, "hipMalloc(slot flags)");
+    }
+    if (!lay.gidx.empty()) {
+        e = hipMemcpy(dg, lay.gidx.data(), lay.gidx.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(df, lay.flags.data(), lay.flags.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hipFree(dg);
+            hipFree(df);
+            return hip_fail(e, "hipMemcpy(slot table)");
+        }
+    }
+    if (p->d_gidx) hipFree(p->d_gidx);
+    if (p->d_flags) hipFree(p->d_flags);
+    p->d_gidx = dg;
+    p->d_flags = df;
+    p->n_bundles = (int32_t)lay.n_bundles;
+    p->n_slots = lay.n_bundles * lay.cap;
+    p->sh = sh;
+    if (p->sh.grid > p->n_bundles) p->sh.grid = p->n_bundles;
+    drop_graphs(p);
+    return IDM_OK;
+}
+
+// Default launch shape: the smallest bundle that holds the longest lane, one
+// vehicle per thread when possible (most work-groups), K from the problem.
+idm_status choose_shape(const idm_plan *p, const idm_tuning *tu, Shape &sh) {
+    int K = p->pb.ckpt_every;
+    if (tu && tu->ckpt_every > 0) K = tu->ckpt_every;
+    const bool k_given = K > 0;
+    if (tu && (tu->threads || tu->per_thread)) {
+        if (!valid_threads(tu->threads) || !valid_per_thread(tu->per_thread))
+            return fail(IDM_ERR_UNSUPPORTED, "tuning threads=%d per_thread=%d not supported",
+                        tu->threads, tu->per_thread);
+        sh.threads = tu->threads;
+        sh.per_thread = tu->per_thread;
+        if (!k_given) K = ks_for(sh.per_thread).back();
+    } else {
+        const int64_t need = std::max<int64_t>(p->max_lane, 1);
+        bool found = false;
+        for (int r : {1, 2, 4}) {
+            if (k_given && !k_ok(r, K)) continue;
+            for (int t : {64, 128, 256, 512, 1024}) {
+                if ((int64_t)t * r >= need) {
+                    sh.threads = t;
+                    sh.per_thread = r;
+                    found = true;
+                    break;
+                }
+            }
+            if (found) break;
+        }
+        if (!found)
+            return fail(k_given ? IDM_ERR_UNSUPPORTED : IDM_ERR_LAYOUT,
+                        "no launch shape holds a %d-vehicle lane with K=%d", p->max_lane, K);
+        if (!k_given) K = std::min(16, ks_for(sh.per_thread).back());
+    }
+    if (!k_ok(sh.per_thread, K))
+        return fail(IDM_ERR_UNSUPPORTED, "K=%d not instantiated for per_thread=%d", K, sh.per_thread);
+    sh.K = K;
+    sh.grid = (tu && tu->grid > 0) ? tu->grid : 0;
+    return IDM_OK;
+}
+
+SimArgs base_args(const idm_plan *p) {
+    SimArgs a;
+    memset(&a, 0, sizeof a);
+    a.n = p->pb.n_vehicles;
+    a.n_steps = p->pb.n_steps;
+    a.K = p->sh.K;
+    a.dt = p->pb.dt;
+    a.inv_dt = 1.0f / p->pb.dt;
+    a.a_min = p->pb.a_min;
+    a.gap_floor = p->pb.gap_floor;
+    a.slot_gidx = p->d_gidx;
+    a.slot_flags = p->d_flags;
+    a.n_bundles = p->n_bundles;
+    return a;
+}
+
+idm_status check_params(const idm_params *prm) {
+    if (!prm || !prm->v0 || !prm->T || !prm->a || !prm->b || !prm->s0 || !prm->length)
+        return fail(IDM_ERR_INVALID_ARG, "params: null pointer");
+    return IDM_OK;
+}
+
+idm_status check_obs(const idm_plan *p, const idm_obs *obs) {
+    if (!obs) return IDM_OK;
+    if (!obs->target) return fail(IDM_ERR_INVALID_ARG, "obs.target is null");
+    if (obs->n_obs < 1 || obs->obs_first < 0 || obs->obs_stride < 1)
+        return fail(IDM_ERR_INVALID_ARG, "obs: n_obs=%d first=%d stride=%d invalid", obs->n_obs,
+                    obs->obs_first, obs->obs_stride);
+    int64_t last = (int64_t)obs->obs_first + (int64_t)(obs->n_obs - 1) * obs->obs_stride;
+    if (last > p->pb.n_steps)
+        return fail(IDM_ERR_INVALID_ARG, "obs: last observed step %lld > n_steps %d", (long long)last,
+                    p->pb.n_steps);
+    return IDM_OK;
+}
+
+int grid_of(const idm_plan *p) { return p->sh.grid > 0 ? std::min(p->sh.grid, p->n_bundles) : p->n_bundles; }
+
+idm_status run_forward(idm_plan *p, const idm_params *prm, const double *p0, const float *v_init,
+                       float *traj_d, float *traj_v, void *ws, hipStream_t s) {
+    SimArgs a = base_args(p);
+    a.v0 = prm->v0; a.T = prm->T; a.a = prm->a; a.b = prm->b; a.s0 = prm->s0; a.len = prm->length;
+    a.p0 = p0;
+    a.v_init = v_init;
+    a.traj_d = traj_d;
+    a.traj_v = traj_v;
+    a.ckpt = ws ? (float *)((char *)ws + ws_ckpt_off(p)) : nullptr;
+    if (p->pb.n_steps == 0 && a.ckpt) a.ckpt = nullptr;
+    KernelFn fn = forward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads);
+    if (!fn) return fail(IDM_ERR_UNSUPPORTED, "no forward kernel for this shape");
+    if (p->n_bundles == 0) return IDM_OK;
+    hipError_t e = launch_sim(fn, grid_of(p), p->sh.threads, a, s);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return IDM_OK;
+}
+
+idm_status run_backward(idm_plan *p, const idm_params *prm, const double *p0, const float *v_init,
+                        const float *gd, const float *gv, const idm_obs *obs, double *g_prm,
+                        double *g_p0, double *g_v0, double *loss_out, void *ws, hipStream_t s) {
+    SimArgs a = base_args(p);
+    a.v0 = prm->v0; a.T = prm->T; a.a = prm->a; a.b = prm->b; a.s0 = prm->s0; a.len = prm->length;
+    a.p0 = p0;
+    a.v_init = v_init;
+    a.ckpt = (float *)((char *)ws + ws_ckpt_off(p));
+    a.gd = gd;
+    a.gv = gv;
+    if (obs) {
+        a.target = obs->target;
+        a.n_obs = obs->n_obs;
+        a.obs_first = obs->obs_first;
+        a.obs_stride = obs->obs_stride;
+        a.inv_count = 1.0 / ((double)obs->n_obs * (double)p->pb.n_vehicles);
+    } else {
+        a.obs_stride = 1;
+    }
+    a.g_prm = g_prm;
+    a.g_p0 = g_p0;
+    a.g_v0 = g_v0;
+    a.loss_part = (double *)((char *)ws + ws_loss_off(p));
+    KernelFn fn = backward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, p->sh.K);
+    if (!fn) return fail(IDM_ERR_UNSUPPORTED, "no backward kernel for this shape");
+    if (p->n_bundles > 0) {
+        hipError_t e = launch_sim(fn, grid_of(p), p->sh.threads, a, s);
+        if (e != hipSuccess) return hip_fail(e, "backward launch");
+    }
+    if (loss_out) {
+        hipError_t e = launch_loss_finalize(a.loss_part, p->n_bundles, obs ? a.inv_count : 0.0,
+                                            loss_out, s);
+        if (e != hipSuccess) return hip_fail(e, "loss finalize launch");
+    }
+    return IDM_OK;
+}
+
+AdamArgs adam_args(const idm_plan *p, const idm_fit_state *st, const double *grad) {
+    AdamArgs a;
+    memset(&a, 0, sizeof a);
+    a.n = p->pb.n_vehicles;
+    a.u = st->u;
+    a.m = st->m;
+    a.v = st->v;
+    a.params = st->params;
+    a.grad = grad;
+    a.step = st->step;
+    for (int i = 0; i < 5; ++i) {
+        a.lo[i] = st->lo[i];
+        a.hi[i] = st->hi[i];
+    }
+    a.lr0 = st->lr0;
+    a.lr1 = st->lr1;
+    a.lr_steps = st->lr_steps;
+    a.beta1 = st->beta1;
+    a.beta2 = st->beta2;
+    a.eps = st->eps;
+    return a;
+}
+
+idm_status check_fit(const idm_plan *p, const idm_fit_state *st, const double *p0,
+                     const float *v_init, const idm_obs *obs, void *ws) {
+    if (!st || !st->u || !st->m || !st->v || !st->params || !st->length || !st->step ||
+        !st->loss_hist)
+        return fail(IDM_ERR_INVALID_ARG, "fit state: null pointer");
+    if (st->hist_len < 1 || st->lr_steps < 1)
+        return fail(IDM_ERR_INVALID_ARG, "fit state: hist_len and lr_steps must be >= 1");
+    for (int i = 0; i < 5; ++i)
+        if (!(st->hi[i] > st->lo[i]) || !std::isfinite(st->lo[i]) || !std::isfinite(st->hi[i]))
+            return fail(IDM_ERR_INVALID_ARG, "fit state: box %d invalid", i);
+    if (!(st->beta1 >= 0 && st->beta1 < 1 && st->beta2 >= 0 && st->beta2 < 1 && st->eps > 0) ||
+        !std::isfinite(st->lr0) || !std::isfinite(st->lr1))
+        return fail(IDM_ERR_INVALID_ARG, "fit state: Adam hyper-parameters invalid");
+    if (!p0 || !v_init) return fail(IDM_ERR_INVALID_ARG, "p0 / v_init null");
+    if (!obs) return fail(IDM_ERR_INVALID_ARG, "fit needs observations");
+    if (!ws) return fail(IDM_ERR_WORKSPACE, "workspace is null");
+    return check_obs(p, obs);
+}
+
+idm_status run_fit_step(idm_plan *p, const idm_fit_state *st, const double *p0, const float *v_init,
+                        const idm_obs *obs, void *ws, hipStream_t s) {
+    const int64_t N = p->pb.n_vehicles;
+    idm_params prm;
+    prm.v0 = st->params;
+    prm.T = st->params + N;
+    prm.a = st->params + 2 * N;
+    prm.b = st->params + 3 * N;
+    prm.s0 = st->params + 4 * N;
+    prm.length = st->length;
+    double *grad = (double *)((char *)ws + ws_fit_off(p));
+    double *gp0 = grad + 5 * N, *gv0 = grad + 6 * N;
+    idm_status r = run_forward(p, &prm, p0, v_init, nullptr, nullptr, ws, s);
+    if (r != IDM_OK) return r;
+    r = run_backward(p, &prm, p0, v_init, nullptr, nullptr, obs, grad, gp0, gv0, nullptr, ws, s);
+    if (r != IDM_OK) return r;
+    double scale = 1.0 / ((double)obs->n_obs * (double)N);
+    hipError_t e = launch_fit_finalize((double *)((char *)ws + ws_loss_off(p)), p->n_bundles, scale,
+                                       st->step, st->loss_hist, st->hist_len, s);
+    if (e != hipSuccess) return hip_fail(e, "fit finalize launch");
+    AdamArgs aa = adam_args(p, st, grad);
+    e = launch_adam(aa, s);
+    if (e != hipSuccess) return hip_fail(e, "adam launch");
+    return IDM_OK;
+}
+
+idm_status run_step(idm_plan *p, const idm_step_args *a, hipStream_t s) {
+    idm_status r = run_forward(p, &a->prm, a->p0, a->v_init, a->traj_d, a->traj_v, a->workspace, s);
+    if (r != IDM_OK) return r;
+    idm_obs obs{a->obs_target, a->n_obs, a->obs_first, a->obs_stride};
+    return run_backward(p, &a->prm, a->p0, a->v_init, a->grad_traj_d, a->grad_traj_v,
+                        a->obs_target ? &obs : nullptr, a->grad_params, a->grad_p0, a->grad_v0,
+                        a->loss_out, a->workspace, s);
+}
+
+idm_status check_step(const idm_plan *p, const idm_step_args *a) {
+    if (!a) return fail(IDM_ERR_INVALID_ARG, "args is null");
+    idm_status r = check_params(&a->prm);
+    if (r != IDM_OK) return r;
+    if (!a->p0 || !a->v_init) return fail(IDM_ERR_INVALID_ARG, "p0 / v_init null");
+    if (!a->grad_params || !a->grad_p0 || !a->grad_v0)
+        return fail(IDM_ERR_INVALID_ARG, "gradient outputs null");
+    if (!a->workspace) return fail(IDM_ERR_WORKSPACE, "workspace is null");
+    if (a->obs_target) {
+        idm_obs obs{a->obs_target, a->n_obs, a->obs_first, a->obs_stride};
+        return check_obs(p, &obs);
+    }
+    return IDM_OK;
+}
+
+// Capture `fn` (which launches on the given stream) into a graph.
+template <class F>
+idm_status capture(hipStream_t s, hipGraphExec_t *out, F fn) {
+    if (!s) return fail(IDM_ERR_INVALID_ARG, "graph capture needs a non-default stream");
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    idm_status r = fn();
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (r != IDM_OK) {
+        if (g) hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    *out = ex;
+    return IDM_OK;
+}
+
+// Validation of the problem and choice of the launch shape (host only).
+idm_status host_plan(const idm_problem *pb, const idm_tuning *tu, idm_plan *p, Shape &sh) {
+    if (!pb) return fail(IDM_ERR_INVALID_ARG, "null argument");
+    if (pb->n_vehicles < 1 || pb->n_lanes < 1 || pb->n_steps < 0)
+        return fail(IDM_ERR_INVALID_ARG, "sizes: N=%d L=%d S=%d", pb->n_vehicles, pb->n_lanes,
+                    pb->n_steps);
+    if (!(pb->dt > 0.0f) || !std::isfinite(pb->dt))
+        return fail(IDM_ERR_INVALID_ARG, "dt must be positive and finite");
+    if (!std::isfinite(pb->a_min) || !(pb->a_min < 0.0f))
+        return fail(IDM_ERR_INVALID_ARG, "a_min must be negative and finite");
+    if (!(pb->gap_floor >= 0.0f) || !std::isfinite(pb->gap_floor))
+        return fail(IDM_ERR_INVALID_ARG, "gap_floor must be >= 0");
+    if (pb->delta != 4.0f)
+        return fail(IDM_ERR_UNSUPPORTED, "delta=%g: only delta = 4 is implemented", pb->delta);
+    if (pb->bound != IDM_BOUND_SOFTPLUS && pb->bound != IDM_BOUND_CLAMP)
+        return fail(IDM_ERR_INVALID_ARG, "bound must be IDM_BOUND_SOFTPLUS or IDM_BOUND_CLAMP");
+    if (pb->ckpt_every < 0) return fail(IDM_ERR_INVALID_ARG, "ckpt_every < 0");
+    if (!pb->lane_offsets_host) return fail(IDM_ERR_INVALID_ARG, "lane_offsets_host is null");
+    const int32_t *off = pb->lane_offsets_host;
+    if (off[0] != 0 || off[pb->n_lanes] != pb->n_vehicles)
+        return fail(IDM_ERR_LAYOUT, "lane offsets must start at 0 and end at N");
+    int32_t max_lane = 0;
+    for (int l = 0; l < pb->n_lanes; ++l) {
+        if (off[l + 1] < off[l]) return fail(IDM_ERR_LAYOUT, "lane offsets decrease at lane %d", l);
+        max_lane = std::max(max_lane, off[l + 1] - off[l]);
+    }
+    if (max_lane > 4096)
+        return fail(IDM_ERR_LAYOUT, "longest lane (%d vehicles) exceeds 4096", max_lane);
+    if (tu && (tu->grid < 0 || tu->ckpt_every < 0))
+        return fail(IDM_ERR_INVALID_ARG, "tuning: negative grid or ckpt_every");
+    p->pb = *pb;
+    p->offsets.assign(off, off + pb->n_lanes + 1);
+    p->pb.lane_offsets_host = nullptr;
+    p->max_lane = max_lane;
+    return choose_shape(p, tu, sh);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *idm_last_error(void) { return g_err.c_str(); }
+
+const char *idm_version(void) { return "idmx 0.1 gfx950"; }
+
+idm_status idm_plan_create(const idm_problem *pb, const idm_tuning *tu, idm_plan **out) {
+    if (!out) return fail(IDM_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    idm_plan *p = new idm_plan();
+    Shape sh;
+    idm_status r = host_plan(pb, tu, p, sh);
+    if (r == IDM_OK) r = build_layout(p, sh);
+    if (r != IDM_OK) {
+        idm_plan_destroy(p);
+        return r;
+    }
+    *out = p;
+    return IDM_OK;
+}
+
+idm_status idm_problem_check(const idm_problem *pb, const idm_tuning *tu, idm_plan_info *info,
+                             size_t *workspace_bytes) {
+    idm_plan p;
+    Shape sh;
+    idm_status r = host_plan(pb, tu, &p, sh);
+    if (r != IDM_OK) return r;
+    Layout lay;
+    r = compute_layout(p.offsets, p.pb.n_lanes, sh, lay);
+    if (r != IDM_OK) return r;
+    p.sh = sh;
+    p.n_bundles = (int32_t)lay.n_bundles;
+    p.n_slots = lay.n_bundles * lay.cap;
+    if (p.sh.grid > p.n_bundles) p.sh.grid = p.n_bundles;
+    if (workspace_bytes) *workspace_bytes = ws_total(&p, sh.K);
+    if (info) return idm_plan_get_info(&p, info);
+    return IDM_OK;
+}
+
+idm_status idm_problem_layout(const idm_problem *pb, const idm_tuning *tu, int32_t *slot_vehicle_host,
+                              uint8_t *slot_flags_host, int64_t capacity) {
+    if (!slot_vehicle_host || !slot_flags_host) return fail(IDM_ERR_INVALID_ARG, "null output");
+    idm_plan p;
+    Shape sh;
+    idm_status r = host_plan(pb, tu, &p, sh);
+    if (r != IDM_OK) return r;
+    Layout lay;
+    r = compute_layout(p.offsets, p.pb.n_lanes, sh, lay);
+    if (r != IDM_OK) return r;
+    if ((int64_t)lay.gidx.size() > capacity)
+        return fail(IDM_ERR_INVALID_ARG, "capacity %lld < %lld slots", (long long)capacity,
+                    (long long)lay.gidx.size());
+    std::copy(lay.gidx.begin(), lay.gidx.end(), slot_vehicle_host);
+    std::copy(lay.flags.begin(), lay.flags.end(), slot_flags_host);
+    return IDM_OK;
+}
+
+idm_status idm_plan_destroy(idm_plan *p) {
+    if (!p) return IDM_OK;
+    drop_graphs(p);
+    if (p->d_gidx) hipFree(p->d_gidx);
+    if (p->d_flags) hipFree(p->d_flags);
+    delete p;
+    return IDM_OK;
+}
+
+size_t idm_workspace_bytes(const idm_plan *p) { return p ? ws_total(p, p->sh.K) : 0; }
+
+idm_status idm_plan_get_info(const idm_plan *p, idm_plan_info *o) {
+    if (!p || !o) return fail(IDM_ERR_INVALID_ARG, "null argument");
+    o->threads = p->sh.threads;
+    o->per_thread = p->sh.per_thread;
+    o->ckpt_every = p->sh.K;
+    o->grid = grid_of(p);
+    o->n_bundles = p->n_bundles;
+    o->max_lane = p->max_lane;
+    o->n_slots = p->n_slots;
+    o->fill = p->n_slots ? (double)p->pb.n_vehicles / (double)p->n_slots : 0.0;
+    return IDM_OK;
+}
+
+idm_status idm_sim_forward(idm_plan *p, const idm_params *prm, const double *p0, const float *v_init,
+                           float *traj_d, float *traj_v, void *ws, void *stream) {
+    if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
+    idm_status r = check_params(prm);
+    if (r != IDM_OK) return r;
+    if (!p0 || !v_init) return fail(IDM_ERR_INVALID_ARG, "p0 / v_init null");
+    return run_forward(p, prm, p0, v_init, traj_d, traj_v, ws, (hipStream_t)stream);
+}
+
+idm_status idm_sim_backward(idm_plan *p, const idm_params *prm, const double *p0,
+                            const float *v_init, const float *gd, const float *gv,
+                            const idm_obs *obs, double *g_prm, double *g_p0, double *g_v0,
+                            double *loss_out, void *ws, void *stream) {
+    if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
+    idm_status r = check_params(prm);
+    if (r != IDM_OK) return r;
+    if (!p0 || !v_init) return fail(IDM_ERR_INVALID_ARG, "p0 / v_init null");
+    if (!g_prm || !g_p0 || !g_v0) return fail(IDM_ERR_INVALID_ARG, "gradient outputs null");
+    if (!ws) return fail(IDM_ERR_WORKSPACE, "workspace is null");
+    r = check_obs(p, obs);
+    if (r != IDM_OK) return r;
+    return run_backward(p, prm, p0, v_init, gd, gv, obs, g_prm, g_p0, g_v0, loss_out, ws,
+                        (hipStream_t)stream);
+}
+
+idm_status idm_fit_step(idm_plan *p, const idm_fit_state *st, const double *p0, const float *v_init,
+                        const idm_obs *obs, void *ws, void *stream) {
+    if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
+    idm_status r = check_fit(p, st, p0, v_init, obs, ws);
+    if (r != IDM_OK) return r;
+    return run_fit_step(p, st, p0, v_init, obs, ws, (hipStream_t)stream);
+}
+
+idm_status idm_fit_run(idm_plan *p, const idm_fit_state *st, const double *p0, const float *v_init,
+                       const idm_obs *obs, int32_t n_iters, void *ws, void *stream) {
+    if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
+    if (n_iters < 0) return fail(IDM_ERR_INVALID_ARG, "n_iters < 0");
+    idm_status r = check_fit(p, st, p0, v_init, obs, ws);
+    if (r != IDM_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<unsigned char> key(sizeof(idm_fit_state) + sizeof(idm_obs) + 3 * sizeof(void *));
+    unsigned char *k = key.data();
+    memcpy(k, st, sizeof(idm_fit_state));
+    memcpy(k + sizeof(idm_fit_state), obs, sizeof(idm_obs));
+    const void *ptrs[3] = {p0, v_init, ws};
+    memcpy(k + sizeof(idm_fit_state) + sizeof(idm_obs), ptrs, sizeof ptrs);
+    if (!p->fit_exec || p->fit_key != key) {
+        if (p->fit_exec) hipGraphExecDestroy(p->fit_exec);
+        p->fit_exec = nullptr;
+        r = capture(s, &p->fit_exec, [&]() { return run_fit_step(p, st, p0, v_init, obs, ws, s); });
+        if (r != IDM_OK) return r;
+        p->fit_key = key;
+    }
+    for (int32_t i = 0; i < n_iters; ++i) {
+        hipError_t e = hipGraphLaunch(p->fit_exec, s);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch(fit)");
+    }
+    return IDM_OK;
+}
+
+idm_status idm_step_graph_launch(idm_plan *p, const idm_step_args *a, void *stream) {
+    if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
+    idm_status r = check_step(p, a);
+    if (r != IDM_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    if (!p->step_exec || memcmp(&p->step_key, a, sizeof *a) != 0) {
+        if (p->step_exec) hipGraphExecDestroy(p->step_exec);
+        p->step_exec = nullptr;
+        r = capture(s, &p->step_exec, [&]() { return run_step(p, a, s); });
+        if (r != IDM_OK) return r;
+        p->step_key = *a;
+    }
+    hipError_t e = hipGraphLaunch(p->step_exec, s);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch(step)");
+    return IDM_OK;
+}
+
+idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_bytes, int32_t reps,
+                             void *stream) {
+    if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
+    idm_status r = check_step(p, a);
+    if (r != IDM_OK) return r;
+    if (reps < 1) return fail(IDM_ERR_INVALID_ARG, "reps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0, cus = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus <= 0) cus = 256;
+    std::vector<Shape> cands;
+    for (int t : {64, 128, 256, 512, 1024})
+        for (int rr : {1, 2, 4}) {
+            if ((int64_t)t * rr < p->max_lane) continue;
+            if ((int64_t)t * rr > 8 * std::max<int64_t>(p->max_lane, 64)) continue;
+            for (int K : ks_for(rr)) {
+                if (ws_total(p, K) > ws_bytes) continue;
+                Shape sh;
+                sh.threads = t;
+                sh.per_thread = rr;
+                sh.K = K;
+                sh.grid = 0;
+                cands.push_back(sh);
+            }
+        }
+    if (cands.empty()) return fail(IDM_ERR_WORKSPACE, "no launch shape fits the workspace");
+    const Shape orig = p->sh;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best = INFINITY;
+    Shape best_sh = orig;
+    for (Shape sh : cands) {
+        for (int persistent = 0; persistent < 2; ++persistent) {
+            Shape s2 = sh;
+            if (persistent) {
+                KernelFn fb = backward_kernel(p->pb.bound, sh.per_thread, sh.threads, sh.K);
+                int occ = 0;
+                if (!fb || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fb, sh.threads, 0) !=
+                               hipSuccess || occ < 1)
+                    continue;
+                s2.grid = cus * occ;
+            }
+            r = build_layout(p, s2);
+            if (r != IDM_OK) continue;
+            if (persistent && p->n_bundles <= s2.grid) continue;  // same as non-persistent
+            r = run_step(p, a, s);  // warm-up
+            if (r != IDM_OK) break;
+            hipEventRecord(e0, s);
+            for (int i = 0; i < reps; ++i) {
+                r = run_step(p, a, s);
+                if (r != IDM_OK) break;
+            }
+            hipEventRecord(e1, s);
+            hipError_t he = hipEventSynchronize(e1);
+            if (r != IDM_OK || he != hipSuccess) {
+                if (he != hipSuccess) r = hip_fail(he, "autotune timing");
+                break;
+            }
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                best_sh = s2;
+            }
+        }
+        if (r != IDM_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    idm_status r2 = build_layout(p, r == IDM_OK ? best_sh : orig);
+    if (r != IDM_OK) return r;
+    return r2;
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Internal interface between the host runtime (idm_api.hip) and the kernels
+// (idm_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace idmx {
+
+// Slot flags: a bundle is threads*per_thread consecutive slots holding whole
+// lanes (head -> tail) followed by padding.
+enum : uint8_t { SLOT_HEAD = 1u, SLOT_TAIL = 2u, SLOT_VALID = 4u };
+
+// Everything a simulation kernel reads, passed by value as the kernel argument.
+struct SimArgs {
+    int64_t n;          // vehicles N
+    int32_t n_steps;    // S
+    int32_t K;          // checkpoint interval / backward block length
+    float dt, inv_dt, a_min, gap_floor;
+
+    // bundle layout (device, owned by the plan)
+    const int32_t *slot_gidx;   // [n_bundles * C], -1 = padding
+    const uint8_t *slot_flags;  // [n_bundles * C]
+    int32_t n_bundles;
+
+    // inputs
+    const float *v0, *T, *a, *b, *s0, *len;
+    const double *p0;
+    const float *v_init;
+
+    // forward outputs
+    float *traj_d, *traj_v;   // nullable
+    float *ckpt;              // [nblk][2][N], nullable in forward
+
+    // backward upstream
+    const float *gd, *gv;     // nullable, [(S+1)*N]
+    const float *target;      // nullable, [n_obs][N]
+    int32_t n_obs, obs_first, obs_stride;
+    double inv_count;         // 1 / (n_obs * N)
+
+    // backward outputs
+    double *g_prm;            // [5][N]
+    double *g_p0, *g_v0;      // [N]
+    double *loss_part;        // [n_bundles]
+};
+
+struct AdamArgs {
+    int64_t n;
+    float *u, *m, *v, *params;
+    const double *grad;   // [5][N]
+    const int32_t *step;  // device counter (already incremented for this step)
+    float lo[5], hi[5];
+    float lr0, lr1;
+    int32_t lr_steps;
+    float beta1, beta2, eps;
+};
+
+using KernelFn = const void *;
+
+// Lookup of compiled kernel instantiations; nullptr when not instantiated.
+KernelFn forward_kernel(int mode, int per_thread, int threads);
+KernelFn backward_kernel(int mode, int per_thread, int threads, int K);
+
+// Launch helpers (return the HIP error of the launch).
+hipError_t launch_sim(KernelFn fn, int grid, int threads, const SimArgs &a, hipStream_t s);
+hipError_t launch_loss_finalize(const double *part, int32_t n_part, double scale, double *out,
+                                hipStream_t s);
+hipError_t launch_fit_finalize(const double *part, int32_t n_part, double scale,
+                               int32_t *step, double *hist, int32_t hist_len, hipStream_t s);
+hipError_t launch_adam(const AdamArgs &a, hipStream_t s);
+hipError_t launch_params_from_u(const AdamArgs &a, hipStream_t s);
+
+}  // namespace idmx

@@ -1,0 +1,619 @@
+// HIP kernels of the differentiable IDM simulator for gfx950 (MI355X).
+//
+// Method (arXiv 2412.16750): Sec. III-A Eqs. 1-3 (IDM acceleration from the
+// gap and speed difference to the leader, explicit Euler), Sec. III-B
+// (synchronous per-frame update), Sec. III-C (softplus lower bounds).  The
+// reverse pass is a hand-derived adjoint of the same discrete equations.
+//
+// Design:
+//   * A work-group owns a "bundle": threads*R consecutive slots holding whole
+//     lanes (head -> tail).  Thread t owns slots t*R .. t*R+R-1, so the
+//     leader of every vehicle but the thread's first one is in registers; the
+//     first vehicle reads its leader (the previous thread's last vehicle)
+//     from LDS.  Lanes never interact, so a work-group runs ALL time steps of
+//     its bundle in one launch, with one work-group barrier per step
+//     (ping-pong LDS buffers remove the second barrier).
+//   * State is FP32 displacement d = p - p0 plus speed; the initial gap to the
+//     leader g0 = p0_h - p0 - len_h is formed in FP64 once and rounded, so the
+//     gap at step k is g0 + (d_h - d) without cancellation of large positions.
+//   * Forward writes the trajectory (coalesced, step-major) and a checkpoint of
+//     (d, v) every K steps.  Backward walks K-step blocks from last to first:
+//     it reloads the block's checkpoint, recomputes the K states into
+//     registers, then sweeps them in reverse.  The follower -> leader part of
+//     the adjoint is a GATHER: every vehicle publishes its contribution to
+//     its leader and each vehicle reads the one of its follower (slot + 1).
+//     No atomics anywhere, so results are bitwise reproducible.
+//   * Per-vehicle parameter gradients are summed in FP32 within a block and in
+//     FP64 across blocks; the fused MSE loss is summed in FP64 per bundle and
+//     reduced in a fixed order by a second kernel.
+#include "idm_internal.h"
+
+#include <math.h>
+
+namespace idmx {
+namespace {
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float log2_fast(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// softplus(x) = log(1 + e^x) = max(x, 0) + log(1 + e^-|x|)   (Sec. III-C)
+__device__ __forceinline__ float softplus(float x) {
+    float e = exp2_fast(-fabsf(x) * kLog2e);
+    return fmaf(kLn2, log2_fast(1.0f + e), fmaxf(x, 0.0f));
+}
+
+// softplus(x) and its derivative, the logistic function.
+__device__ __forceinline__ float softplus_d(float x, float &sig) {
+    float e = exp2_fast(-fabsf(x) * kLog2e);
+    float onep = 1.0f + e;
+    float r = rcp_fast(onep);
+    sig = x >= 0.0f ? r : e * r;
+    return fmaf(kLn2, log2_fast(onep), fmaxf(x, 0.0f));
+}
+
+// Work-group barrier that orders only LDS traffic.  __syncthreads() also
+// waits for every outstanding global store of the wave, which would stall each
+// time step on the trajectory writes; nothing here reads another thread's
+// global writes inside a launch, so only the LDS ("local") fence is needed.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ float logistic(float x) {
+    float e = exp2_fast(-fabsf(x) * kLog2e);
+    float r = rcp_fast(1.0f + e);
+    return x >= 0.0f ? r : e * r;
+}
+
+// Per-vehicle constants, computed once per launch.
+struct Veh {
+    float inv_v0, T, a, s0;
+    float c;    // 1 / (2 sqrt(a b))   (Eq. 1)
+    float g0;   // initial gap to the leader (FP64 difference, rounded); +inf for a lane head
+    int32_t g;  // global vehicle index, -1 for padding
+    bool head, tail;
+};
+
+template <int R>
+__device__ __forceinline__ void load_vehicles(const SimArgs &A, int64_t slot0, Veh (&q)[R],
+                                              float (&i2a)[R], float (&i2b)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int32_t g = A.slot_gidx[slot0 + r];
+        uint8_t f = A.slot_flags[slot0 + r];
+        q[r].g = g;
+        q[r].head = (f & SLOT_HEAD) || g < 0;
+        q[r].tail = (f & SLOT_TAIL) || g < 0;
+        if (g >= 0) {
+            float v0 = A.v0[g], a = A.a[g], b = A.b[g];
+            q[r].inv_v0 = 1.0f / v0;
+            q[r].T = A.T[g];
+            q[r].a = a;
+            q[r].s0 = A.s0[g];
+            q[r].c = 0.5f / sqrtf(a * b);
+            i2a[r] = 0.5f / a;
+            i2b[r] = 0.5f / b;
+            if (!q[r].head) {
+                double gap0 = A.p0[g - 1] - A.p0[g] - (double)A.len[g - 1];
+                q[r].g0 = (float)gap0;
+            } else {
+                q[r].g0 = INFINITY;
+            }
+        } else {
+            q[r].inv_v0 = 0.0f;
+            q[r].T = 0.0f;
+            q[r].a = 0.0f;
+            q[r].s0 = 0.0f;
+            q[r].c = 0.0f;
+            q[r].g0 = INFINITY;
+            i2a[r] = 0.0f;
+            i2b[r] = 0.0f;
+        }
+    }
+}
+
+// Acceleration entering the speed update: a* (SOFTPLUS) or ahat (CLAMP).
+// A lane head has g0 = +inf, so its interaction term is exactly zero.
+template <int MODE>
+__device__ __forceinline__ float accel(const Veh &q, float d, float v, float dh, float vh,
+                                       float inv_dt, float a_min, float gap_floor) {
+    float x = v * q.inv_v0;
+    float x2 = x * x;
+    float gap = q.g0 + (dh - d);                      // Sec. III-A: p_h - p - len_h
+    float sg = fmaxf(gap, gap_floor);
+    float dv = v - vh;                                // Sec. III-A: v - v_h
+    float s_opt = fmaf(v * dv, q.c, fmaf(v, q.T, q.s0));  // Eq. 1
+    float s = (MODE == 0) ? softplus(s_opt) : s_opt;  // Sec. III-C floor on s_opt
+    float qq = s * rcp_fast(sg);
+    float ahat = q.a * (1.0f - fmaf(x2, x2, qq * qq));   // Eq. 2, delta = 4
+    if (MODE == 0) {
+        float lb = fmaxf(-v * inv_dt, a_min);           // Sec. III-C a_lb
+        return lb + softplus(ahat - lb);
+    }
+    return ahat;
+}
+
+template <int MODE>
+__device__ __forceinline__ void euler(float &d, float &v, float acc, float dt) {
+    float dn = fmaf(dt, v, d);                        // Eq. 3, old speed
+    float vn = fmaf(dt, acc, v);
+    if (MODE == 1) vn = fmaxf(vn, 0.0f);
+    d = dn;
+    v = vn;
+}
+
+// Local partial derivatives of the acceleration at one (vehicle, step).
+struct Part {
+    float Ad, Av, Adh, Avh;           // w.r.t. own d, own v, leader d, leader v
+    float Ap[5];                      // v0, T, a, b, s0
+    float gate;                       // d v' / d (v + dt acc): 1, or the clamp indicator
+};
+
+template <int MODE>
+__device__ __forceinline__ void partials(const Veh &q, float i2a, float i2b, float d, float v,
+                                         float dh, float vh, float dt, float inv_dt, float a_min,
+                                         float gap_floor, Part &P) {
+    float x = v * q.inv_v0;
+    float x2 = x * x;
+    float gap = q.g0 + (dh - d);
+    bool floored = !(gap > gap_floor);
+    float sg = fmaxf(gap, gap_floor);
+    float inv_sg = rcp_fast(sg);
+    float dv = v - vh;
+    float vdv = v * dv;
+    float s_opt = fmaf(vdv, q.c, fmaf(v, q.T, q.s0));
+    float sig_s = 1.0f, s = s_opt;
+    if (MODE == 0) s = softplus_d(s_opt, sig_s);
+    float qq = s * inv_sg;
+    float inter = qq * qq;
+    float rest = 1.0f - fmaf(x2, x2, inter);          // 1 - x^4 - (s/gap)^2
+    float ahat = q.a * rest;
+    // d ahat / d s_opt
+    float As = -2.0f * q.a * qq * inv_sg * sig_s;
+    // d ahat / d gap (zero while the floor is active)
+    float hg = floored ? 0.0f : 2.0f * q.a * inter * inv_sg;
+    float x3 = x2 * x;
+    float hv = fmaf(As, fmaf(dv + v, q.c, q.T), -4.0f * q.a * x3 * q.inv_v0);
+    float hvh = -As * v * q.c;
+    float vdvc = vdv * q.c;
+    float w = 1.0f, dlb = 0.0f, gate = 1.0f;
+    if (MODE == 0) {
+        float nv = -v * inv_dt;
+        bool on_v = nv > a_min;                       // tie -> a_min branch
+        float lb = on_v ? nv : a_min;
+        w = logistic(ahat - lb);
+        dlb = on_v ? (w - 1.0f) * inv_dt : 0.0f;
+    } else {
+        gate = (fmaf(dt, ahat, v) > 0.0f) ? 1.0f : 0.0f;
+    }
+    P.Ad = -w * hg;
+    P.Adh = w * hg;
+    P.Av = fmaf(w, hv, dlb);
+    P.Avh = w * hvh;
+    P.Ap[0] = w * (4.0f * q.a * x2 * x2 * q.inv_v0);  // v0
+    P.Ap[1] = w * (As * v);                           // T
+    P.Ap[2] = w * (rest - As * vdvc * i2a);           // a
+    P.Ap[3] = w * (-As * vdvc * i2b);                 // b
+    P.Ap[4] = w * As;                                 // s0
+    P.gate = gate;
+}
+
+__device__ __forceinline__ double block_sum(double x, double *red) {
+    // fixed-order reduction: wave shuffles, then waves in index order
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = x;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) s += red[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------- forward
+
+template <int MODE, int R, int NT>
+__global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
+    __shared__ float2 sbuf[2][NT];
+    const int t = threadIdx.x;
+    const int64_t N = A.n;
+    const int S = A.n_steps;
+    for (int bidx = blockIdx.x; bidx < A.n_bundles; bidx += gridDim.x) {
+        Veh q[R];
+        float i2a[R], i2b[R];
+        load_vehicles<R>(A, (int64_t)bidx * (NT * R) + t * R, q, i2a, i2b);
+        float d[R], v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            d[r] = 0.0f;
+            v[r] = q[r].g >= 0 ? A.v_init[q[r].g] : 0.0f;
+            if (q[r].g >= 0) {
+                if (A.traj_d) A.traj_d[q[r].g] = 0.0f;
+                if (A.traj_v) A.traj_v[q[r].g] = v[r];
+                if (A.ckpt) {
+                    A.ckpt[q[r].g] = 0.0f;
+                    A.ckpt[N + q[r].g] = v[r];
+                }
+            }
+        }
+        sbuf[0][t] = make_float2(d[R - 1], v[R - 1]);
+        lds_barrier();
+        for (int k = 0; k < S; ++k) {
+            float2 L = t > 0 ? sbuf[k & 1][t - 1] : make_float2(0.0f, 0.0f);
+            float acc[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float dh = r ? d[r - 1] : L.x;
+                float vh = r ? v[r - 1] : L.y;
+                if (q[r].head) {
+                    dh = d[r];
+                    vh = v[r];
+                }
+                acc[r] = accel<MODE>(q[r], d[r], v[r], dh, vh, A.inv_dt, A.a_min, A.gap_floor);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) euler<MODE>(d[r], v[r], acc[r], A.dt);
+            sbuf[(k + 1) & 1][t] = make_float2(d[R - 1], v[R - 1]);
+            const int64_t row = (int64_t)(k + 1) * N;
+            const bool ck = A.ckpt && ((k + 1) % A.K == 0) && (k + 1 < S);
+            const int64_t crow = (int64_t)((k + 1) / A.K) * 2 * N;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                int32_t g = q[r].g;
+                if (g >= 0) {
+                    if (A.traj_d) A.traj_d[row + g] = d[r];
+                    if (A.traj_v) A.traj_v[row + g] = v[r];
+                    if (ck) {
+                        A.ckpt[crow + g] = d[r];
+                        A.ckpt[crow + N + g] = v[r];
+                    }
+                }
+            }
+            lds_barrier();
+        }
+    }
+}
+
+// ---------------------------------------------------------------- backward
+
+template <int R>
+__device__ __forceinline__ float upstream(const SimArgs &A, int k, int32_t g, float d,
+                                          double p0g, int jo, double &loss) {
+    float u = 0.0f;
+    if (g < 0) return u;
+    if (A.gd) u = A.gd[(int64_t)k * A.n + g];
+    if (jo >= 0) {
+        double r = (p0g + (double)d) - (double)A.target[(int64_t)jo * A.n + g];
+        loss = fma(r, r, loss);
+        u += (float)(2.0 * r * A.inv_count);
+    }
+    return u;
+}
+
+__device__ __forceinline__ int obs_index(const SimArgs &A, int k) {
+    if (!A.target || k < A.obs_first) return -1;
+    int rel = k - A.obs_first;
+    if (rel % A.obs_stride) return -1;
+    int j = rel / A.obs_stride;
+    return j < A.n_obs ? j : -1;
+}
+
+template <int MODE, int R, int NT, int K>
+__global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
+    __shared__ float2 sbuf[2][NT];
+    __shared__ float2 cbuf[2][NT];
+    __shared__ double red[NT / 64 + 1];
+    const int t = threadIdx.x;
+    const int64_t N = A.n;
+    const int S = A.n_steps;
+    const float dt = A.dt;
+    const int nblk = (S + K - 1) / K;
+    for (int bidx = blockIdx.x; bidx < A.n_bundles; bidx += gridDim.x) {
+        Veh q[R];
+        float i2a[R], i2b[R];
+        load_vehicles<R>(A, (int64_t)bidx * (NT * R) + t * R, q, i2a, i2b);
+        double p0g[R];
+        float ld[R], lv[R];
+        double gacc[5][R];
+        double loss = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            p0g[r] = q[r].g >= 0 ? A.p0[q[r].g] : 0.0;
+            ld[r] = 0.0f;
+            lv[r] = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) gacc[j][r] = 0.0;
+        }
+        if (S == 0) {
+            const int jo = obs_index(A, 0);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                ld[r] = upstream<R>(A, 0, q[r].g, 0.0f, p0g[r], jo, loss);
+                if (A.gv && q[r].g >= 0) lv[r] = A.gv[q[r].g];
+            }
+        }
+        for (int blk = nblk - 1; blk >= 0; --blk) {
+            const int k0 = blk * K;
+            const int len = min(K, S - k0);
+            float d[R], v[R];
+            const int64_t crow = (int64_t)blk * 2 * N;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                int32_t g = q[r].g;
+                d[r] = g >= 0 ? A.ckpt[crow + g] : 0.0f;
+                v[r] = g >= 0 ? A.ckpt[crow + N + g] : 0.0f;
+            }
+            // recompute the block's states into registers
+            float hd[K][R], hv[K][R];
+            sbuf[0][t] = make_float2(d[R - 1], v[R - 1]);
+            lds_barrier();
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                if (j < len) {
+                    float2 L = t > 0 ? sbuf[j & 1][t - 1] : make_float2(0.0f, 0.0f);
+                    float acc[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        hd[j][r] = d[r];
+                        hv[j][r] = v[r];
+                        float dh = r ? d[r - 1] : L.x;
+                        float vh = r ? v[r - 1] : L.y;
+                        if (q[r].head) {
+                            dh = d[r];
+                            vh = v[r];
+                        }
+                        acc[r] = accel<MODE>(q[r], d[r], v[r], dh, vh, A.inv_dt, A.a_min,
+                                             A.gap_floor);
+                    }
+#pragma unroll
+                    for (int r = 0; r < R; ++r) euler<MODE>(d[r], v[r], acc[r], dt);
+                    sbuf[(j + 1) & 1][t] = make_float2(d[R - 1], v[R - 1]);
+                    lds_barrier();
+                }
+            }
+            if (blk == nblk - 1) {
+                // seed: upstream gradient at the last step S
+                const int jo = obs_index(A, S);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    ld[r] += upstream<R>(A, S, q[r].g, d[r], p0g[r], jo, loss);
+                    if (A.gv && q[r].g >= 0) lv[r] += A.gv[(int64_t)S * N + q[r].g];
+                }
+            }
+            float gblk[5][R];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int j = 0; j < 5; ++j) gblk[j][r] = 0.0f;
+            // reverse sweep over the block
+#pragma unroll
+            for (int j = K - 1; j >= 0; --j) {
+                if (j < len) {
+                    const int k = k0 + j;
+                    float2 L = t > 0 ? sbuf[j & 1][t - 1] : make_float2(0.0f, 0.0f);
+                    Part P[R];
+                    float mu[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        float dh = r ? hd[j][r - 1] : L.x;
+                        float vh = r ? hv[j][r - 1] : L.y;
+                        if (q[r].head) {
+                            dh = hd[j][r];
+                            vh = hv[j][r];
+                        }
+                        partials<MODE>(q[r], i2a[r], i2b[r], hd[j][r], hv[j][r], dh, vh, dt,
+                                       A.inv_dt, A.a_min, A.gap_floor, P[r]);
+                        mu[r] = P[r].gate * dt * lv[r];
+                    }
+                    // contribution of my first vehicle to its leader (previous thread)
+                    cbuf[j & 1][t] = make_float2(mu[0] * P[0].Adh, mu[0] * P[0].Avh);
+                    if (j > 0) sbuf[(j - 1) & 1][t] = make_float2(hd[j - 1][R - 1], hv[j - 1][R - 1]);
+                    lds_barrier();
+                    float2 F = (t + 1 < NT) ? cbuf[j & 1][t + 1] : make_float2(0.0f, 0.0f);
+                    const int jo = obs_index(A, k);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        float fd, fv;  // gathered from the follower
+                        if (r + 1 < R) {
+                            fd = mu[r + 1] * P[r + 1].Adh;
+                            fv = mu[r + 1] * P[r + 1].Avh;
+                        } else {
+                            fd = F.x;
+                            fv = F.y;
+                        }
+                        if (q[r].tail) {
+                            fd = 0.0f;
+                            fv = 0.0f;
+                        }
+                        float nld = fmaf(mu[r], P[r].Ad, ld[r]) + fd;
+                        float nlv = fmaf(dt, ld[r], fmaf(P[r].gate, lv[r], fmaf(mu[r], P[r].Av, fv)));
+#pragma unroll
+                        for (int p = 0; p < 5; ++p) gblk[p][r] = fmaf(mu[r], P[r].Ap[p], gblk[p][r]);
+                        ld[r] = nld + upstream<R>(A, k, q[r].g, hd[j][r], p0g[r], jo, loss);
+                        lv[r] = nlv;
+                        if (A.gv && q[r].g >= 0) lv[r] += A.gv[(int64_t)k * N + q[r].g];
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int p = 0; p < 5; ++p) gacc[p][r] += (double)gblk[p][r];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int32_t g = q[r].g;
+            if (g >= 0) {
+#pragma unroll
+                for (int p = 0; p < 5; ++p) A.g_prm[(int64_t)p * N + g] = gacc[p][r];
+                A.g_p0[g] = (double)ld[r];
+                A.g_v0[g] = (double)lv[r];
+            }
+        }
+        double tot = block_sum(loss, red);
+        if (t == 0 && A.loss_part) A.loss_part[bidx] = tot;
+    }
+}
+
+// ---------------------------------------------------------------- small kernels
+
+__global__ __launch_bounds__(256) void k_loss_finalize(const double *part, int32_t n, double scale,
+                                                       double *out) {
+    __shared__ double red[5];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    double tot = block_sum(s, red);
+    if (threadIdx.x == 0) *out = tot * scale;
+}
+
+__global__ __launch_bounds__(256) void k_fit_finalize(const double *part, int32_t n, double scale,
+                                                      int32_t *step, double *hist,
+                                                      int32_t hist_len) {
+    __shared__ double red[5];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    double tot = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        int32_t st = *step;
+        hist[st < hist_len ? st : hist_len - 1] = tot * scale;
+        *step = st + 1;
+    }
+}
+
+// Adam (Kingma & Ba) on normalised parameters u in [0, 1], then projection
+// onto the box and rewrite of the physical parameters lo + u (hi - lo).
+__global__ __launch_bounds__(256) void k_adam(AdamArgs A) {
+    const int64_t total = 5 * A.n;
+    const int32_t t = *A.step;  // 1-based step number after the finalize kernel
+    const float frac = fminf((float)(t - 1) / (float)A.lr_steps, 1.0f);
+    const float lr = A.lr0 + (A.lr1 - A.lr0) * frac;
+    const float bc1 = 1.0f - powf(A.beta1, (float)t);
+    const float bc2 = 1.0f - powf(A.beta2, (float)t);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int p = (int)(i / A.n);
+        float span = A.hi[p] - A.lo[p];
+        float g = (float)(A.grad[i] * (double)span);
+        float m = A.beta1 * A.m[i] + (1.0f - A.beta1) * g;
+        float v = A.beta2 * A.v[i] + (1.0f - A.beta2) * g * g;
+        A.m[i] = m;
+        A.v[i] = v;
+        float mh = m / bc1, vh = v / bc2;
+        float u = A.u[i] - lr * mh / (sqrtf(vh) + A.eps);
+        u = fminf(fmaxf(u, 0.0f), 1.0f);
+        A.u[i] = u;
+        A.params[i] = A.lo[p] + u * span;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_params_from_u(AdamArgs A) {
+    const int64_t total = 5 * A.n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int p = (int)(i / A.n);
+        float u = fminf(fmaxf(A.u[i], 0.0f), 1.0f);
+        A.u[i] = u;
+        A.params[i] = A.lo[p] + u * (A.hi[p] - A.lo[p]);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- dispatch
+//
+// The file is compiled three times (IDM_PART = 0, 1, 2) so the backward
+// instantiations of the two bound modes build in parallel.
+#ifndef IDM_PART
+#define IDM_PART 0
+#endif
+
+#define IDM_FWD_CASE(M, R, NT) \
+    if (mode == M && per_thread == R && threads == NT) return (KernelFn)&k_forward<M, R, NT>;
+#define IDM_FWD_R(M, R) \
+    IDM_FWD_CASE(M, R, 64) IDM_FWD_CASE(M, R, 128) IDM_FWD_CASE(M, R, 256) \
+    IDM_FWD_CASE(M, R, 512) IDM_FWD_CASE(M, R, 1024)
+
+#if IDM_PART == 0
+KernelFn forward_kernel(int mode, int per_thread, int threads) {
+    IDM_FWD_R(0, 1) IDM_FWD_R(0, 2) IDM_FWD_R(0, 4)
+    IDM_FWD_R(1, 1) IDM_FWD_R(1, 2) IDM_FWD_R(1, 4)
+    return nullptr;
+}
+#endif
+
+#define IDM_BWD_CASE(M, R, NT, KK)                                            \
+    if (mode == M && per_thread == R && threads == NT && K == KK)             \
+        return (KernelFn)&k_backward<M, R, NT, KK>;
+#define IDM_BWD_NT(M, R, KK)                                                  \
+    IDM_BWD_CASE(M, R, 64, KK) IDM_BWD_CASE(M, R, 128, KK) IDM_BWD_CASE(M, R, 256, KK) \
+    IDM_BWD_CASE(M, R, 512, KK) IDM_BWD_CASE(M, R, 1024, KK)
+#define IDM_BWD_M(M)                                                          \
+    IDM_BWD_NT(M, 1, 8) IDM_BWD_NT(M, 1, 16) IDM_BWD_NT(M, 1, 32)             \
+    IDM_BWD_NT(M, 2, 8) IDM_BWD_NT(M, 2, 16) IDM_BWD_NT(M, 4, 4) IDM_BWD_NT(M, 4, 8)
+
+#if IDM_PART == 1
+KernelFn backward_kernel_softplus(int mode, int per_thread, int threads, int K) {
+    IDM_BWD_M(0)
+    return nullptr;
+}
+#endif
+#if IDM_PART == 2
+KernelFn backward_kernel_clamp(int mode, int per_thread, int threads, int K) {
+    IDM_BWD_M(1)
+    return nullptr;
+}
+#endif
+#if IDM_PART == 0
+KernelFn backward_kernel_softplus(int, int, int, int);
+KernelFn backward_kernel_clamp(int, int, int, int);
+KernelFn backward_kernel(int mode, int per_thread, int threads, int K) {
+    return mode == 0 ? backward_kernel_softplus(mode, per_thread, threads, K)
+                     : backward_kernel_clamp(mode, per_thread, threads, K);
+}
+
+hipError_t launch_sim(KernelFn fn, int grid, int threads, const SimArgs &a, hipStream_t s) {
+    void *args[] = {(void *)&a};
+    return hipLaunchKernel(fn, dim3(grid), dim3(threads), args, 0, s);
+}
+
+hipError_t launch_loss_finalize(const double *part, int32_t n_part, double scale, double *out,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_loss_finalize, dim3(1), dim3(256), 0, s, part, n_part, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit_finalize(const double *part, int32_t n_part, double scale, int32_t *step,
+                               double *hist, int32_t hist_len, hipStream_t s) {
+    hipLaunchKernelGGL(k_fit_finalize, dim3(1), dim3(256), 0, s, part, n_part, scale, step, hist,
+                       hist_len);
+    return hipGetLastError();
+}
+
+static int elementwise_grid(int64_t total) {
+    int64_t g = (total + 255) / 256;
+    return (int)(g < 4096 ? (g < 1 ? 1 : g) : 4096);
+}
+
+hipError_t launch_adam(const AdamArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3(elementwise_grid(5 * a.n)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_params_from_u(const AdamArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_params_from_u, dim3(elementwise_grid(5 * a.n)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+#endif  // IDM_PART == 0
+
+}  // namespace idmx

@@ -1,0 +1,155 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/idm.h declares, validates problems, sizes workspaces
+and packs lanes into work-group bundles correctly."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2412_16750_amd import _lib
+    return _lib.load()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "idm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(idm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    from paper_2412_16750_amd import _lib
+    assert sorted(_lib.EXPORTS) == names
+
+
+def _problem(offsets, S=100, K=16, delta=4.0, dt=0.1, bound=0, a_min=-10.0, gap_floor=1e-3):
+    from paper_2412_16750_amd._lib import IdmProblem
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32))
+    pb = IdmProblem(int(off[-1]), len(off) - 1, S, K, dt, delta, a_min, gap_floor, bound,
+                    off.ctypes.data_as(ctypes.c_void_p))
+    return pb, off
+
+
+def _check(L, offsets, tuning=None, **kw):
+    from paper_2412_16750_amd._lib import IdmPlanInfo, IdmTuning
+    pb, off = _problem(offsets, **kw)
+    info = IdmPlanInfo()
+    ws = ctypes.c_size_t()
+    tu = IdmTuning(*tuning) if tuning else None
+    st = L.idm_problem_check(ctypes.byref(pb), ctypes.byref(tu) if tu else None, ctypes.byref(info),
+                             ctypes.byref(ws))
+    return st, info, ws.value
+
+
+def test_valid_problem_shape_and_workspace(L):
+    off = np.arange(0, 2000 * 1000 + 1, 1000)
+    st, info, ws = _check(L, off, S=100, K=32)
+    assert st == 0
+    assert (info.threads, info.per_thread, info.ckpt_every) == (1024, 1, 32)
+    assert info.n_bundles == 2000 and info.max_lane == 1000
+    assert abs(info.fill - 1000 / 1024) < 1e-12
+    N, S, K = 2_000_000, 100, 32
+    align = lambda x: (x + 255) // 256 * 256
+    expect = align(8 * 2000) + align(8 * 7 * N) + align(((S + K - 1) // K) * 2 * 4 * N)
+    assert ws == expect
+
+
+@pytest.mark.parametrize("case, status", [
+    (dict(offsets=[0, 5, 3, 10]), -2),            # decreasing
+    (dict(offsets=[1, 5]), -2),                   # does not start at 0
+    (dict(offsets=[0, 5000]), -2),                # lane > 4096
+    (dict(offsets=[0, 10], delta=2.0), -3),       # only delta = 4
+    (dict(offsets=[0, 10], dt=0.0), -1),
+    (dict(offsets=[0, 10], dt=float("nan")), -1),
+    (dict(offsets=[0, 10], a_min=1.0), -1),
+    (dict(offsets=[0, 10], gap_floor=-1.0), -1),
+    (dict(offsets=[0, 10], bound=7), -1),
+    (dict(offsets=[0, 10], S=-1), -1),
+    (dict(offsets=[0, 10], K=-3), -1),
+    (dict(offsets=[0, 10], K=12), -3),            # K not instantiated
+])
+def test_invalid_problems_are_rejected(L, case, status):
+    st, _, _ = _check(L, **case)
+    assert st == status
+    assert len(L.idm_last_error()) > 0
+
+
+def test_invalid_tuning(L):
+    assert _check(L, [0, 100], tuning=(100, 1, 0, 0))[0] == -3
+    assert _check(L, [0, 100], tuning=(64, 3, 0, 0))[0] == -3
+    assert _check(L, [0, 100], tuning=(64, 1, 0, 0))[0] == -2   # 100 > 64 slots
+    assert _check(L, [0, 100], tuning=(128, 1, 0, -1))[0] == -1
+    assert _check(L, [0, 100], tuning=(64, 4, 32, 0))[0] == -3  # K=32 not for R=4
+    st, info, _ = _check(L, [0, 100], tuning=(64, 2, 8, 0))
+    assert st == 0 and (info.threads, info.per_thread, info.ckpt_every) == (64, 2, 8)
+
+
+def _layout(L, offsets, tuning):
+    from paper_2412_16750_amd._lib import IdmTuning
+    st, info, _ = _check(L, offsets, tuning=tuning)
+    assert st == 0
+    pb, off = _problem(offsets)
+    tu = IdmTuning(*tuning)
+    n = info.n_slots
+    gidx = np.empty(n, dtype=np.int32)
+    flags = np.empty(n, dtype=np.uint8)
+    assert L.idm_problem_layout(ctypes.byref(pb), ctypes.byref(tu), gidx.ctypes.data_as(ctypes.c_void_p),
+                                flags.ctypes.data_as(ctypes.c_void_p), n - 1) == -1
+    assert L.idm_problem_layout(ctypes.byref(pb), ctypes.byref(tu), gidx.ctypes.data_as(ctypes.c_void_p),
+                                flags.ctypes.data_as(ctypes.c_void_p), n) == 0
+    return info, gidx, flags
+
+
+@pytest.mark.parametrize("tuning", [(64, 1, 8, 0), (64, 2, 8, 0), (256, 4, 4, 0), (1024, 4, 8, 0)])
+def test_layout_packs_whole_lanes(L, tuning):
+    import scenarios
+    sizes = scenarios.lognormal_lane_sizes(3000, 3.0, 1.2, 1, tuning[0] * tuning[1], 99)
+    sizes[::97] = 0
+    off = scenarios.offsets_from_sizes(sizes)
+    info, gidx, flags = _layout(L, off, tuning)
+    cap = tuning[0] * tuning[1]
+    N = int(off[-1])
+    valid = gidx >= 0
+    # every vehicle exactly once
+    assert np.array_equal(np.sort(gidx[valid]), np.arange(N))
+    assert np.all((flags[valid] & 4) == 4) and np.all(flags[~valid] == 0)
+    lane_of = np.repeat(np.arange(len(sizes)), sizes)
+    fills = []
+    for b in range(info.n_bundles):
+        g = gidx[b * cap:(b + 1) * cap]
+        f = flags[b * cap:(b + 1) * cap]
+        k = int(np.sum(g >= 0))
+        fills.append(k)
+        assert np.all(g[k:] == -1)          # padding only at the end
+        seg = g[:k]
+        # lanes are contiguous, head -> tail, flags mark heads and tails
+        heads = np.flatnonzero(f[:k] & 1)
+        tails = np.flatnonzero(f[:k] & 2)
+        assert heads[0] == 0 and len(heads) == len(tails)
+        for h, t in zip(heads, tails):
+            lane = lane_of[seg[h]]
+            assert seg[h] == off[lane] and seg[t] == off[lane + 1] - 1
+            assert np.array_equal(seg[h:t + 1], np.arange(off[lane], off[lane + 1]))
+    assert fills == sorted(fills, reverse=True)
+    # best-fit decreasing: no two bundles could be merged
+    assert sum(1 for f in fills if f <= cap // 2) <= 1
+
+
+def test_python_binding_rejects_bad_tensors():
+    """The Python binding validates shapes, dtypes and devices before calling."""
+    import torch
+    from paper_2412_16750_amd import sim
+    with pytest.raises(ValueError):
+        sim._need(torch.zeros(3), "x", torch.float32, 3)   # CPU tensor
+    with pytest.raises(TypeError):
+        sim._need(np.zeros(3), "x", torch.float32, 3)         # not a tensor
