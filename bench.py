@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput of the differentiable IDM simulator on one MI355X.
+
+Workload (the paper's 2-million-vehicle scale point, Sec. V-A / Fig. 1):
+2000 lanes x 1000 vehicles = 2,000,000 vehicles, 100 Euler steps of 0.1 s,
+softplus bounds (Sec. III-C), checkpoints every 32 steps.  One timed step is
+the whole hot path on that batch:
+  idm_sim_forward   all 100 steps in one launch, writes the FP32 trajectory
+                    [101 x 2M] and the checkpoints;
+  idm_sim_backward  recompute-from-checkpoint adjoint with the fused
+                    mean-squared trajectory loss against dense synthetic targets
+                    [100 x 2M] (FP64 loss, FP64 per-vehicle gradients of
+                    v0, T, a, b, s0, p0 and v_init).
+Inputs are seeded synthetic draws (scenarios.scale) already resident in HBM.
+value = N * S / (seconds per step): forward+backward vehicle-steps per second.
+
+Prints ONE JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic FP32 operations per vehicle-step (FMA = 2, every other add, sub,
+# mul, max, exp2, log2, rcp = 1), counted from the kernels' formulas; derived
+# term by term in the design doc.
+FLOP_FWD = 40
+FLOP_BWD = 147
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA) with non-packed FP32.
+PEAK_FP32_VECTOR_TFLOPS = 78.6
+PEAK_HBM_GBPS = 8000.0
+# Paper, Fig. 1 / Sec. V-A: < 30 ms per step for 2M vehicles in each of the
+# forward and backward passes (Xeon W-2255 x16 threads or RTX A5000).
+PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_inputs(sc, dev):
+    import numpy as np
+    import torch
+    import scenarios
+    from paper_2412_16750_amd import sim
+    steps = np.arange(1, sc.n_steps + 1, dtype=np.int32)
+    # dense synthetic targets: constant-speed extrapolation + N(0, 0.5 m) noise,
+    # generated in chunks of steps to bound host memory
+    tgt = torch.empty(len(steps), sc.n, dtype=torch.float32, device=dev)
+    for s0 in range(0, len(steps), 10):
+        blk = scenarios.constant_speed_targets(sc, steps[s0:s0 + 10], 2 + 100 * s0)
+        tgt[s0:s0 + len(blk)] = torch.from_numpy(blk).to(dev)
+    x = dict(prm=sim.params_tensor(sc.params, dev),
+             length=torch.from_numpy(np.ascontiguousarray(sc.params["length"])).to(dev),
+             p0=torch.from_numpy(np.ascontiguousarray(sc.p0)).to(dev),
+             v=torch.from_numpy(np.ascontiguousarray(sc.v_init)).to(dev))
+    return x, sim.Obs(tgt, 1, 1)
+
+
+def cpu_baseline(sc, lanes: int):
+    """The FP64 oracle (single-threaded C) on the first `lanes` lanes:
+    forward + MSE + adjoint, timed on this host."""
+    import numpy as np
+    import oracle
+    import scenarios
+    sub = scenarios.subset_lanes(sc, list(range(lanes)))
+    idx = sub.extra["vehicle_index"]
+    steps = np.arange(1, sc.n_steps + 1)
+    tgt = scenarios.constant_speed_targets(sub, steps, 2)
+    pb = oracle.Problem.from_scenario(sub)
+    t0 = time.perf_counter()
+    P, V, _, _ = oracle.forward(pb)
+    loss, gP = oracle.mse(P, steps, tgt)
+    oracle.adjoint(pb, P, V, gP)
+    dt = time.perf_counter() - t0
+    vs = sub.n * sc.n_steps
+    return {"value": vs / dt, "unit": "vehicle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d of %d lanes (%d vehicles) x %d steps, forward + MSE + adjoint, "
+                      "FP64 sequential C, %.2f s" % (lanes, sc.n_lanes, len(idx), sc.n_steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-lanes", type=int, default=400,
+                    help="lanes of the workload the CPU oracle baseline times")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only run the streaming copy kernel (byte-counter calibration)")
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--per-thread", type=int, default=0)
+    ap.add_argument("--ckpt", type=int, default=32)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only (lanes shard across GPUs with no "
+              "exchange; the multi-GPU layout is described in DESIGN.md). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import scenarios
+    from paper_2412_16750_amd import sim
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a HIP device")
+    dev = "cuda"
+    torch.cuda.init()
+
+    if args.copy_only:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(3):
+            sim.idm_copy_bytes(b, a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            sim.idm_copy_bytes(b, a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"copy_bytes": nbytes, "copy_ms": ms,
+                          "copy_GBps_read_plus_write": 2 * nbytes / ms / 1e6}))
+        return
+
+    sc = scenarios.scale(ckpt_every=args.ckpt)
+    N, S = sc.n, sc.n_steps
+    log("bench: building inputs N=%d S=%d" % (N, S))
+    x, obs = build_inputs(sc, dev)
+    plan = sim.Plan.for_scenario(sc, threads=args.threads, per_thread=args.per_thread)
+    info = plan.info()
+    traj_d = torch.empty(S + 1, N, dtype=torch.float32, device=dev)
+    ws = plan.workspace(dev)
+    gp = torch.empty(5, N, dtype=torch.float64, device=dev)
+    gp0 = torch.empty(N, dtype=torch.float64, device=dev)
+    gv0 = torch.empty(N, dtype=torch.float64, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def fwd():
+        sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj_d, None, ws, stream)
+
+    def bwd():
+        sim.idm_sim_backward(plan, x["prm"], x["length"], x["p0"], x["v"], gp, gp0, gv0, ws,
+                             obs=obs, loss_out=loss, stream=stream)
+
+    log("bench: plan %s" % info)
+    for _ in range(args.warmup):
+        fwd()
+        bwd()
+    torch.cuda.synchronize()
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        ev[i][0].record(stream)
+        fwd()
+        ev[i][1].record(stream)
+        bwd()
+        ev[i][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd_ms = float(np.mean([ev[i][0].elapsed_time(ev[i][1]) for i in range(K)]))
+    bwd_ms = float(np.mean([ev[i][1].elapsed_time(ev[i][2]) for i in range(K)]))
+    ms_per_step = wall * 1e3 / K
+    vsteps = float(N) * S
+    value = vsteps / (ms_per_step / 1e3)
+    log("bench: fwd %.3f ms, bwd %.3f ms, step %.3f ms, loss %.6e" % (fwd_ms, bwd_ms, ms_per_step,
+                                                                    loss.item()))
+
+    # dominant kernel: the backward (recompute + adjoint + fused loss)
+    bwd_flops = FLOP_BWD * vsteps
+    achieved = bwd_flops / (bwd_ms / 1e3) / 1e12
+    # algorithmic HBM bytes of one backward launch: checkpoints (2 x 4 B x N per
+    # block), params 5 x 4 B, length, p0 (8 B) x N, targets 4 B x N x S,
+    # FP64 gradients 7 x 8 B x N
+    nblk = -(-S // info["ckpt_every"])
+    bwd_bytes = N * (nblk * 8 + 20 + 4 + 16 + 4 * S + 56)
+    fwd_bytes = N * (20 + 4 + 16 + 4 + 4 * (S + 1) + nblk * 8)
+    roofline = {
+        "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+        "kernel": "k_backward<softplus,R=%d,threads=%d,K=%d>" % (info["per_thread"], info["threads"],
+                                                                  info["ckpt_every"]),
+        "kernel_ms": round(bwd_ms, 4), "flop_per_vehicle_step": FLOP_BWD,
+        "hbm_algorithmic_GBps": round(bwd_bytes / (bwd_ms / 1e3) / 1e9, 1),
+        "hbm_frac": round(bwd_bytes / (bwd_ms / 1e3) / 1e9 / PEAK_HBM_GBPS, 4),
+        "forward": {"kernel_ms": round(fwd_ms, 4),
+                    "achieved_TFLOPs": round(FLOP_FWD * vsteps / (fwd_ms / 1e3) / 1e12, 3),
+                    "hbm_algorithmic_GBps": round(fwd_bytes / (fwd_ms / 1e3) / 1e9, 1),
+                    "vehicle_steps_per_s": vsteps / (fwd_ms / 1e3)},
+    }
+    out = {
+        "metric": "fwd+bwd vehicle-steps/s @2M vehicles",
+        "value": value, "unit": "vehicle-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": value / PAPER_FWD_BWD_VEH_STEPS_PER_S,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "scale: 2000 lanes x 1000 vehicles = 2M, 100 steps of 0.1 s, "
+                               "softplus bounds, checkpoints every %d, fused MSE vs dense targets"
+                               % info["ckpt_every"],
+                   "n_vehicles": N, "n_steps": S, "ckpt_every": info["ckpt_every"],
+                   "threads": info["threads"], "per_thread": info["per_thread"]},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline on %d lanes" % args.cpu_lanes)
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_lanes)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -231,6 +231,11 @@ idm_status idm_step_graph_launch(idm_plan *plan, const idm_step_args *args, void
 idm_status idm_plan_autotune(idm_plan *plan, const idm_step_args *args, size_t workspace_bytes,
                              int32_t reps, void *stream);
 
+/* Plain device-to-device copy of `bytes` (multiple of 16, 16-byte aligned
+ * pointers) by a streaming kernel: the measured HBM bandwidth ceiling and the
+ * byte-counter calibration reference of the benchmark.  Asynchronous. */
+idm_status idm_copy_bytes(void *dst, const void *src, size_t bytes, void *stream);
+
 /* Thread-local description of the last error (never NULL). */
 const char *idm_last_error(void);
 

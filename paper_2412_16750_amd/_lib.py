@@ -71,7 +71,8 @@ class IdmStepArgs(ctypes.Structure):
 EXPORTS = ("idm_plan_create", "idm_plan_destroy", "idm_workspace_bytes", "idm_plan_get_info",
            "idm_problem_check", "idm_problem_layout",
            "idm_sim_forward", "idm_sim_backward", "idm_fit_step", "idm_fit_run",
-           "idm_step_graph_launch", "idm_plan_autotune", "idm_last_error", "idm_version")
+           "idm_step_graph_launch", "idm_plan_autotune", "idm_copy_bytes", "idm_last_error",
+           "idm_version")
 
 _lib = None
 
@@ -110,6 +111,8 @@ def load() -> ctypes.CDLL:
                               c_void_p, c_void_p]
     L.idm_step_graph_launch.argtypes = [c_void_p, P(IdmStepArgs), c_void_p]
     L.idm_plan_autotune.argtypes = [c_void_p, P(IdmStepArgs), c_size_t, c_int32, c_void_p]
+    L.idm_copy_bytes.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
+    L.idm_copy_bytes.restype = c_int32
     L.idm_last_error.restype = ctypes.c_char_p
     L.idm_version.restype = ctypes.c_char_p
     for name in ("idm_problem_check", "idm_problem_layout", "idm_plan_create", "idm_plan_destroy", "idm_plan_get_info", "idm_sim_forward",

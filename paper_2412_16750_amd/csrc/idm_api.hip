@@ -494,6 +494,19 @@ const char *idm_last_error(void) { return g_err.c_str(); }
 
 const char *idm_version(void) { return "idmx 0.1 gfx950"; }
 
+idm_status idm_copy_bytes(void *dst, const void *src, size_t bytes, void *stream) {
+    if (!dst || !src) return fail(IDM_ERR_INVALID_ARG, "null pointer");
+    if (bytes % 16 || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16))
+        return fail(IDM_ERR_INVALID_ARG, "copy needs 16-byte aligned pointers and sizes");
+    if (bytes == 0) return IDM_OK;
+    int64_t n16 = (int64_t)(bytes / 16);
+    int64_t g = (n16 + 255) / 256;
+    int grid = (int)std::min<int64_t>(g, 256 * 32);
+    hipError_t e = launch_copy(src, dst, n16, grid, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "copy launch");
+    return IDM_OK;
+}
+
 idm_status idm_plan_create(const idm_problem *pb, const idm_tuning *tu, idm_plan **out) {
     if (!out) return fail(IDM_ERR_INVALID_ARG, "null argument");
     *out = nullptr;

@@ -69,6 +69,7 @@ hipError_t launch_loss_finalize(const double *part, int32_t n_part, double scale
 hipError_t launch_fit_finalize(const double *part, int32_t n_part, double scale,
                                int32_t *step, double *hist, int32_t hist_len, hipStream_t s);
 hipError_t launch_adam(const AdamArgs &a, hipStream_t s);
+hipError_t launch_copy(const void *src, void *dst, int64_t n16, int grid, hipStream_t s);
 hipError_t launch_params_from_u(const AdamArgs &a, hipStream_t s);
 
 }  // namespace idmx

@@ -527,6 +527,15 @@ __global__ __launch_bounds__(256) void k_params_from_u(AdamArgs A) {
     }
 }
 
+// Plain streaming copy (16-byte vectors, grid-stride): the measured HBM ceiling
+// and the calibration reference of the hardware byte counters.
+__global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                              int64_t n16) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- dispatch
@@ -602,6 +611,11 @@ hipError_t launch_fit_finalize(const double *part, int32_t n_part, double scale,
 static int elementwise_grid(int64_t total) {
     int64_t g = (total + 255) / 256;
     return (int)(g < 4096 ? (g < 1 ? 1 : g) : 4096);
+}
+
+hipError_t launch_copy(const void *src, void *dst, int64_t n16, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n16);
+    return hipGetLastError();
 }
 
 hipError_t launch_adam(const AdamArgs &a, hipStream_t s) {

@@ -263,3 +263,13 @@ def idm_plan_autotune(bufs: StepBuffers, reps: int = 3, stream=None) -> dict:
 def params_tensor(params: dict, device="cuda") -> torch.Tensor:
     """Stack (v0, T, a, b, s0) float32 arrays into a [5, N] device tensor."""
     return torch.from_numpy(np.stack([np.asarray(params[k], dtype=np.float32) for k in PARAM_NAMES])).to(device)
+
+
+def idm_copy_bytes(dst: torch.Tensor, src: torch.Tensor, stream=None) -> None:
+    """Streaming device copy of src into dst (same byte size, 16-byte multiple)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb or src.device.type != "cuda" or dst.device.type != "cuda":
+        raise ValueError("idm_copy_bytes: device tensors of equal byte size required")
+    if not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("idm_copy_bytes: contiguous tensors required")
+    check(_lib.load().idm_copy_bytes(_ptr(dst), _ptr(src), nb, _stream(stream)), "idm_copy_bytes")

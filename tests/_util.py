@@ -47,17 +47,23 @@ def pos_close(p_gpu, p_ref, rtol=1e-4, floor=1.0):
     return bool(np.all(err <= lim)), float(err.max()), float((err / lim).max())
 
 
-def grad_close(g_gpu, g_ref, rtol=1e-3, rel_floor=1e-2):
-    """|g_gpu - g_ref| <= rtol * max(|g_ref|, rel_floor * max|g_ref|), per row."""
+def grad_close(g_gpu, g_ref, rtol=1e-3, rel_floor=1e-2, where=None):
+    """|g_gpu - g_ref| <= rtol * max(|g_ref|, rel_floor * max|g_ref|), per row.
+    Returns (ok, worst error / limit); `where` (a list) receives the worst
+    element as (row, index, g_gpu, g_ref, limit)."""
     g_gpu = np.atleast_2d(g_gpu)
     g_ref = np.atleast_2d(g_ref)
     worst = 0.0
     ok = True
-    for a, b in zip(g_gpu, g_ref):
+    for row, (a, b) in enumerate(zip(g_gpu, g_ref)):
         scale = np.max(np.abs(b)) if b.size else 0.0
         lim = rtol * np.maximum(np.abs(b), rel_floor * scale)
         lim = np.where(lim > 0, lim, 1e-30)
         r = np.abs(a - b) / lim
-        worst = max(worst, float(r.max()) if r.size else 0.0)
+        if r.size and float(r.max()) > worst:
+            worst = float(r.max())
+            if where is not None:
+                i = int(r.argmax())
+                where[:] = [(row, i, float(a[i]), float(b[i]), float(lim[i]))]
         ok = ok and bool(np.all(np.abs(a - b) <= lim))
     return ok, worst

@@ -26,10 +26,12 @@ def _check(sc, ref, out, what, pos_rtol=1e-4, grad_rtol=1e-3, check_v=True):
         log("%s: speeds max|err| = %.3e m/s" % (what, maxv))
         assert okv, (what, maxv, worstv)
     if "g" in out:
-        okg, wg = grad_close(out["g"], ref["g"], rtol=grad_rtol)
+        where = []
+        okg, wg = grad_close(out["g"], ref["g"], rtol=grad_rtol, where=where)
         ok0, w0 = grad_close(out["gp0"], ref["gp0"], rtol=grad_rtol)
         ok1, w1 = grad_close(out["gv0"], ref["gv0"], rtol=grad_rtol)
-        log("%s: gradient worst/limit params %.3f p0 %.3f v0 %.3f" % (what, wg, w0, w1))
+        log("%s: gradient worst/limit params %.3f p0 %.3f v0 %.3f (worst param element "
+            "(kind, vehicle, gpu, oracle, limit) = %s)" % (what, wg, w0, w1, where))
         assert okg and ok0 and ok1, (what, wg, w0, w1)
 
 
@@ -73,7 +75,8 @@ def test_forward_bitwise_independent_of_launch_shape():
     """The per-vehicle arithmetic does not depend on where the leader's state
     comes from (register or LDS), so trajectories are bitwise identical for
     every launch shape and checkpoint interval; gradients are bitwise identical
-    across shapes with the same K."""
+    across shapes with the same K.  Only the FP64 loss sum depends on how lanes
+    are grouped into bundles (summation order).""" 
     sizes = [50, 64, 1, 120, 33, 7, 128]
     sc = ragged_scenario(sizes, 150, ckpt_every=8)
     steps = np.arange(1, 151)
@@ -84,7 +87,8 @@ def test_forward_bitwise_independent_of_launch_shape():
         assert np.array_equal(o["d"], base["d"]) and np.array_equal(o["V"], base["V"]), shape
         assert np.array_equal(o["g"], base["g"]), shape
         assert np.array_equal(o["gp0"], base["gp0"]) and np.array_equal(o["gv0"], base["gv0"])
-        assert o["loss"] == base["loss"]
+        # the loss is summed per bundle, and bundles differ between shapes
+        assert abs(o["loss"] - base["loss"]) <= 1e-13 * base["loss"]
     for K in (16, 32):
         o = gpu_run(sc, steps, tgt, threads=128, per_thread=1, tuning_k=K)
         assert np.array_equal(o["d"], base["d"])
