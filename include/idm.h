@@ -62,9 +62,10 @@ typedef struct {
     int32_t n_vehicles;               /* N >= 1 */
     int32_t n_lanes;                  /* L >= 1 */
     int32_t n_steps;                  /* S >= 0 Euler steps of length dt */
-    int32_t ckpt_every;               /* K: checkpoint interval of the forward and block
-                                         length of the backward recompute; 0 = let the
-                                         library choose */
+    int32_t ckpt_every;               /* K: checkpoint interval of the forward; the backward
+                                         sweeps each K-step block from its last register
+                                         sub-block (see idm_tuning.block) to its first;
+                                         0 = let the library choose */
     float dt;                         /* > 0, seconds */
     float delta;                      /* free-road exponent; only 4 is implemented */
     float a_min;                      /* maximum deceleration bound (< 0), e.g. -10 */
@@ -79,9 +80,11 @@ typedef struct {
 typedef struct {
     int32_t threads;    /* 64, 128, 256, 512 or 1024 */
     int32_t per_thread; /* vehicles per thread: 1, 2 or 4 */
-    int32_t ckpt_every; /* K in {4, 8, 16, 32}; overrides the problem's K when > 0 */
+    int32_t ckpt_every; /* K, overrides the problem's K when > 0 */
     int32_t grid;       /* >0: persistent grid of that many work-groups walking the bundle
                            list; 0: one work-group per bundle */
+    int32_t block;      /* backward register block KB: 8, 16 or 32 with 1 vehicle per thread,
+                           8 or 16 with 2, 4 or 8 with 4; must divide K; 0 = choose */
 } idm_tuning;
 
 /* Per-vehicle IDM parameters (Sec. III-A), FP32 [N] each, all > 0. */
@@ -122,6 +125,7 @@ size_t idm_workspace_bytes(const idm_plan *plan);
 /* Chosen launch shape and packing statistics. */
 typedef struct {
     int32_t threads, per_thread, ckpt_every, grid;
+    int32_t block;          /* backward register block KB */
     int32_t n_bundles;      /* work-group bundles */
     int32_t max_lane;       /* longest lane (vehicles) */
     int64_t n_slots;        /* bundles * threads * per_thread */

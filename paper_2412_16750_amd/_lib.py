@@ -30,7 +30,7 @@ class IdmProblem(ctypes.Structure):
 
 class IdmTuning(ctypes.Structure):
     _fields_ = [("threads", c_int32), ("per_thread", c_int32), ("ckpt_every", c_int32),
-                ("grid", c_int32)]
+                ("grid", c_int32), ("block", c_int32)]
 
 
 class IdmParams(ctypes.Structure):
@@ -45,7 +45,7 @@ class IdmObs(ctypes.Structure):
 
 class IdmPlanInfo(ctypes.Structure):
     _fields_ = [("threads", c_int32), ("per_thread", c_int32), ("ckpt_every", c_int32),
-                ("grid", c_int32), ("n_bundles", c_int32), ("max_lane", c_int32),
+                ("grid", c_int32), ("block", c_int32), ("n_bundles", c_int32), ("max_lane", c_int32),
                 ("n_slots", c_int64), ("fill", c_double)]
 
 

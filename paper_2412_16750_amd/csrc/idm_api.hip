@@ -39,22 +39,36 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Shape {
-    int threads = 0, per_thread = 0, K = 0, grid = 0;
+    int threads = 0, per_thread = 0;
+    int K = 0;   // checkpoint interval
+    int KB = 0;  // backward register block (divides K)
+    int grid = 0;
 };
 
 bool valid_threads(int t) { return t == 64 || t == 128 || t == 256 || t == 512 || t == 1024; }
 bool valid_per_thread(int r) { return r == 1 || r == 2 || r == 4; }
 
-// Backward block lengths instantiated for each vehicles-per-thread count.
-std::vector<int> ks_for(int r) {
+// Backward register blocks instantiated for each vehicles-per-thread count.
+std::vector<int> kbs_for(int r) {
     if (r == 1) return {8, 16, 32};
     if (r == 2) return {8, 16};
     return {4, 8};
 }
 
-bool k_ok(int r, int K) {
-    auto v = ks_for(r);
-    return std::find(v.begin(), v.end(), K) != v.end();
+bool kb_ok(int r, int KB) {
+    auto v = kbs_for(r);
+    return std::find(v.begin(), v.end(), KB) != v.end();
+}
+
+// Default register block for a checkpoint interval: the largest instantiated
+// block that divides K and keeps the kernel free of register spills (16 for
+// one or two vehicles per thread, 8 for four); 0 if none divides K.
+int default_kb(int r, int K) {
+    const int cap = r == 4 ? 8 : 16;
+    int best = 0;
+    for (int kb : kbs_for(r))
+        if (kb <= cap && K % kb == 0) best = kb;
+    return best;
 }
 
 }  // namespace
@@ -69,6 +83,7 @@ struct idm_plan {
     int64_t n_slots = 0;
     int32_t *d_gidx = nullptr;
     uint8_t *d_flags = nullptr;
+    float *d_zero = nullptr;  // 64 zero floats read in place of absent upstream inputs
     // graphs
     hipGraphExec_t step_exec = nullptr;
     idm_step_args step_key{};
@@ -191,6 +206,15 @@ idm_status build_layout(idm_plan *p, const Shape &sh) {
             return hip_fail(e, "hipMemcpy(slot table)");
         }
     }
+    if (!p->d_zero) {
+        e = hipMalloc(&p->d_zero, 64 * sizeof(float));
+        if (e == hipSuccess) e = hipMemset(p->d_zero, 0, 64 * sizeof(float));
+        if (e != hipSuccess) {
+            hipFree(dg);
+            hipFree(df);
+            return hip_fail(e, "hipMalloc(zero word)");
+        }
+    }
     if (p->d_gidx) hipFree(p->d_gidx);
     if (p->d_flags) hipFree(p->d_flags);
     p->d_gidx = dg;
@@ -208,19 +232,19 @@ idm_status build_layout(idm_plan *p, const Shape &sh) {
 idm_status choose_shape(const idm_plan *p, const idm_tuning *tu, Shape &sh) {
     int K = p->pb.ckpt_every;
     if (tu && tu->ckpt_every > 0) K = tu->ckpt_every;
-    const bool k_given = K > 0;
+    const int KB_req = tu ? tu->block : 0;
+    if (K <= 0) K = KB_req > 0 ? KB_req : 32;
     if (tu && (tu->threads || tu->per_thread)) {
         if (!valid_threads(tu->threads) || !valid_per_thread(tu->per_thread))
             return fail(IDM_ERR_UNSUPPORTED, "tuning threads=%d per_thread=%d not supported",
                         tu->threads, tu->per_thread);
         sh.threads = tu->threads;
         sh.per_thread = tu->per_thread;
-        if (!k_given) K = ks_for(sh.per_thread).back();
     } else {
         const int64_t need = std::max<int64_t>(p->max_lane, 1);
         bool found = false;
         for (int r : {1, 2, 4}) {
-            if (k_given && !k_ok(r, K)) continue;
+            if (KB_req > 0 ? !(kb_ok(r, KB_req) && K % KB_req == 0) : default_kb(r, K) == 0) continue;
             for (int t : {64, 128, 256, 512, 1024}) {
                 if ((int64_t)t * r >= need) {
                     sh.threads = t;
@@ -232,13 +256,17 @@ idm_status choose_shape(const idm_plan *p, const idm_tuning *tu, Shape &sh) {
             if (found) break;
         }
         if (!found)
-            return fail(k_given ? IDM_ERR_UNSUPPORTED : IDM_ERR_LAYOUT,
-                        "no launch shape holds a %d-vehicle lane with K=%d", p->max_lane, K);
-        if (!k_given) K = std::min(16, ks_for(sh.per_thread).back());
+            return fail(IDM_ERR_UNSUPPORTED, "no launch shape holds a %d-vehicle lane with K=%d",
+                        p->max_lane, K);
     }
-    if (!k_ok(sh.per_thread, K))
-        return fail(IDM_ERR_UNSUPPORTED, "K=%d not instantiated for per_thread=%d", K, sh.per_thread);
+    const int KB = KB_req > 0 ? KB_req : default_kb(sh.per_thread, K);
+    if (KB <= 0 || !kb_ok(sh.per_thread, KB) || K % KB != 0)
+        return fail(IDM_ERR_UNSUPPORTED,
+                    "checkpoint interval K=%d needs a backward block (8/16/32 for 1-2 vehicles per "
+                    "thread, 4/8 for 4) that divides it; got block %d, per_thread %d",
+                    K, KB_req, sh.per_thread);
     sh.K = K;
+    sh.KB = KB;
     sh.grid = (tu && tu->grid > 0) ? tu->grid : 0;
     return IDM_OK;
 }
@@ -256,6 +284,7 @@ SimArgs base_args(const idm_plan *p) {
     a.slot_gidx = p->d_gidx;
     a.slot_flags = p->d_flags;
     a.n_bundles = p->n_bundles;
+    a.zero = p->d_zero;
     return a;
 }
 
@@ -314,6 +343,7 @@ idm_status run_backward(idm_plan *p, const idm_params *prm, const double *p0, co
         a.obs_first = obs->obs_first;
         a.obs_stride = obs->obs_stride;
         a.inv_count = 1.0 / ((double)obs->n_obs * (double)p->pb.n_vehicles);
+        a.two_inv_count = 2.0 * a.inv_count;
     } else {
         a.obs_stride = 1;
     }
@@ -321,7 +351,7 @@ idm_status run_backward(idm_plan *p, const idm_params *prm, const double *p0, co
     a.g_p0 = g_p0;
     a.g_v0 = g_v0;
     a.loss_part = (double *)((char *)ws + ws_loss_off(p));
-    KernelFn fn = backward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, p->sh.K);
+    KernelFn fn = backward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, p->sh.KB);
     if (!fn) return fail(IDM_ERR_UNSUPPORTED, "no backward kernel for this shape");
     if (p->n_bundles > 0) {
         hipError_t e = launch_sim(fn, grid_of(p), p->sh.threads, a, s);
@@ -477,8 +507,8 @@ idm_status host_plan(const idm_problem *pb, const idm_tuning *tu, idm_plan *p, S
     }
     if (max_lane > 4096)
         return fail(IDM_ERR_LAYOUT, "longest lane (%d vehicles) exceeds 4096", max_lane);
-    if (tu && (tu->grid < 0 || tu->ckpt_every < 0))
-        return fail(IDM_ERR_INVALID_ARG, "tuning: negative grid or ckpt_every");
+    if (tu && (tu->grid < 0 || tu->ckpt_every < 0 || tu->block < 0))
+        return fail(IDM_ERR_INVALID_ARG, "tuning: negative grid, ckpt_every or block");
     p->pb = *pb;
     p->offsets.assign(off, off + pb->n_lanes + 1);
     p->pb.lane_offsets_host = nullptr;
@@ -563,6 +593,7 @@ idm_status idm_plan_destroy(idm_plan *p) {
     drop_graphs(p);
     if (p->d_gidx) hipFree(p->d_gidx);
     if (p->d_flags) hipFree(p->d_flags);
+    if (p->d_zero) hipFree(p->d_zero);
     delete p;
     return IDM_OK;
 }
@@ -574,6 +605,7 @@ idm_status idm_plan_get_info(const idm_plan *p, idm_plan_info *o) {
     o->threads = p->sh.threads;
     o->per_thread = p->sh.per_thread;
     o->ckpt_every = p->sh.K;
+    o->block = p->sh.KB;
     o->grid = grid_of(p);
     o->n_bundles = p->n_bundles;
     o->max_lane = p->max_lane;
@@ -671,16 +703,24 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (cus <= 0) cus = 256;
     std::vector<Shape> cands;
+    // the checkpoint interval the caller fixed is kept; otherwise K = KB
+    const bool k_fixed = p->pb.ckpt_every > 0;
     for (int t : {64, 128, 256, 512, 1024})
         for (int rr : {1, 2, 4}) {
             if ((int64_t)t * rr < p->max_lane) continue;
             if ((int64_t)t * rr > 8 * std::max<int64_t>(p->max_lane, 64)) continue;
-            for (int K : ks_for(rr)) {
-                if (ws_total(p, K) > ws_bytes) continue;
+            for (int KB : kbs_for(rr)) {
+                const int K = k_fixed ? p->pb.ckpt_every : KB;
+                if (K % KB != 0 || ws_total(p, K) > ws_bytes) continue;
+                KernelFn fb = backward_kernel(p->pb.bound, rr, t, KB);
+                hipFuncAttributes fa;
+                if (!fb || hipFuncGetAttributes(&fa, fb) != hipSuccess || fa.localSizeBytes > 0)
+                    continue;  // skip shapes whose backward spills registers
                 Shape sh;
                 sh.threads = t;
                 sh.per_thread = rr;
                 sh.K = K;
+                sh.KB = KB;
                 sh.grid = 0;
                 cands.push_back(sh);
             }
@@ -696,7 +736,7 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
         for (int persistent = 0; persistent < 2; ++persistent) {
             Shape s2 = sh;
             if (persistent) {
-                KernelFn fb = backward_kernel(p->pb.bound, sh.per_thread, sh.threads, sh.K);
+                KernelFn fb = backward_kernel(p->pb.bound, sh.per_thread, sh.threads, sh.KB);
                 int occ = 0;
                 if (!fb || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fb, sh.threads, 0) !=
                                hipSuccess || occ < 1)

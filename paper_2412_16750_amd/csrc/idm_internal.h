@@ -35,9 +35,11 @@ struct SimArgs {
 
     // backward upstream
     const float *gd, *gv;     // nullable, [(S+1)*N]
+    const float *zero;        // >= 1 zero word (plan-owned), read in place of absent inputs
     const float *target;      // nullable, [n_obs][N]
     int32_t n_obs, obs_first, obs_stride;
     double inv_count;         // 1 / (n_obs * N)
+    double two_inv_count;     // 2 / (n_obs * N)
 
     // backward outputs
     double *g_prm;            // [5][N]

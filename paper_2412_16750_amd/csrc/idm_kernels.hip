@@ -74,22 +74,23 @@ __device__ __forceinline__ float logistic(float x) {
 // Per-vehicle constants, computed once per launch.
 struct Veh {
     float inv_v0, T, a, s0;
-    float c;    // 1 / (2 sqrt(a b))   (Eq. 1)
-    float g0;   // initial gap to the leader (FP64 difference, rounded); +inf for a lane head
-    int32_t g;  // global vehicle index, -1 for padding
-    bool head, tail;
+    float c;      // 1 / (2 sqrt(a b))   (Eq. 1)
+    float g0;     // initial gap to the leader (FP64 difference, rounded); +inf for a lane head
+    float two_a;  // 2 a
+    float fa_v0;  // 4 a / v0   (delta = 4)
+    float i2a, i2b;  // 1 / (2a), 1 / (2b)
+    int32_t g;    // global vehicle index, -1 for padding
+    bool head;
 };
 
 template <int R>
-__device__ __forceinline__ void load_vehicles(const SimArgs &A, int64_t slot0, Veh (&q)[R],
-                                              float (&i2a)[R], float (&i2b)[R]) {
+__device__ __forceinline__ void load_vehicles(const SimArgs &A, int64_t slot0, Veh (&q)[R]) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         int32_t g = A.slot_gidx[slot0 + r];
         uint8_t f = A.slot_flags[slot0 + r];
         q[r].g = g;
         q[r].head = (f & SLOT_HEAD) || g < 0;
-        q[r].tail = (f & SLOT_TAIL) || g < 0;
         if (g >= 0) {
             float v0 = A.v0[g], a = A.a[g], b = A.b[g];
             q[r].inv_v0 = 1.0f / v0;
@@ -97,8 +98,10 @@ __device__ __forceinline__ void load_vehicles(const SimArgs &A, int64_t slot0, V
             q[r].a = a;
             q[r].s0 = A.s0[g];
             q[r].c = 0.5f / sqrtf(a * b);
-            i2a[r] = 0.5f / a;
-            i2b[r] = 0.5f / b;
+            q[r].two_a = 2.0f * a;
+            q[r].fa_v0 = 4.0f * a / v0;
+            q[r].i2a = 0.5f / a;
+            q[r].i2b = 0.5f / b;
             if (!q[r].head) {
                 double gap0 = A.p0[g - 1] - A.p0[g] - (double)A.len[g - 1];
                 q[r].g0 = (float)gap0;
@@ -111,9 +114,11 @@ __device__ __forceinline__ void load_vehicles(const SimArgs &A, int64_t slot0, V
             q[r].a = 0.0f;
             q[r].s0 = 0.0f;
             q[r].c = 0.0f;
+            q[r].two_a = 0.0f;
+            q[r].fa_v0 = 0.0f;
+            q[r].i2a = 0.0f;
+            q[r].i2b = 0.0f;
             q[r].g0 = INFINITY;
-            i2a[r] = 0.0f;
-            i2b[r] = 0.0f;
         }
     }
 }
@@ -131,7 +136,7 @@ __device__ __forceinline__ float accel(const Veh &q, float d, float v, float dh,
     float s_opt = fmaf(v * dv, q.c, fmaf(v, q.T, q.s0));  // Eq. 1
     float s = (MODE == 0) ? softplus(s_opt) : s_opt;  // Sec. III-C floor on s_opt
     float qq = s * rcp_fast(sg);
-    float ahat = q.a * (1.0f - fmaf(x2, x2, qq * qq));   // Eq. 2, delta = 4
+    float ahat = q.a * (1.0f - fmaf(qq, qq, x2 * x2));   // Eq. 2, delta = 4
     if (MODE == 0) {
         float lb = fmaxf(-v * inv_dt, a_min);           // Sec. III-C a_lb
         return lb + softplus(ahat - lb);
@@ -148,17 +153,32 @@ __device__ __forceinline__ void euler(float &d, float &v, float acc, float dt) {
     v = vn;
 }
 
-// Local partial derivatives of the acceleration at one (vehicle, step).
+// Local partial derivatives at one (vehicle, step).  With ahat the IDM
+// acceleration of Eq. 2, a* the bounded one that enters the speed update,
+// gap = g0 + d_h - d and s_opt of Eq. 1:
+//   d a*/d gap  = w hg
+//   d a*/d v    = w (As (T + (dv + v) c) - (4a/v0) x^3) + lbv
+//   d a*/d v_h  = -w As v c
+//   d a*/d v0   = w (4a/v0) x^4,   d a*/d T = w As v,   d a*/d s0 = w As,
+//   d a*/d a    = w (rest - As v dv c / (2a)),   d a*/d b = -w As v dv c / (2b)
+// with As = d ahat / d s_opt and rest = 1 - x^4 - (s*/gap)^2.
 struct Part {
-    float Ad, Av, Adh, Avh;           // w.r.t. own d, own v, leader d, leader v
-    float Ap[5];                      // v0, T, a, b, s0
-    float gate;                       // d v' / d (v + dt acc): 1, or the clamp indicator
+    float hg;      // d ahat / d gap (0 while the gap floor is active)
+    float As;      // d ahat / d s_opt
+    float u1;      // T + (dv + v) c  = d s_opt / d v
+    float x3, x4;  // (v/v0)^3, (v/v0)^4
+    float vc;      // v c
+    float vdvc;    // v dv c
+    float rest;    // 1 - x^4 - (s*/gap)^2
+    float w;       // d a* / d ahat (1 in CLAMP mode)
+    float lbv;     // contribution of a_lb = max(-v/dt, a_min) to d a*/d v
+    float gate;    // d v' / d (v + dt a*): 1, or the clamp indicator
 };
 
 template <int MODE>
-__device__ __forceinline__ void partials(const Veh &q, float i2a, float i2b, float d, float v,
-                                         float dh, float vh, float dt, float inv_dt, float a_min,
-                                         float gap_floor, Part &P) {
+__device__ __forceinline__ void partials(const Veh &q, float d, float v, float dh, float vh,
+                                         float dt, float inv_dt, float a_min, float gap_floor,
+                                         Part &P) {
     float x = v * q.inv_v0;
     float x2 = x * x;
     float gap = q.g0 + (dh - d);
@@ -171,37 +191,28 @@ __device__ __forceinline__ void partials(const Veh &q, float i2a, float i2b, flo
     float sig_s = 1.0f, s = s_opt;
     if (MODE == 0) s = softplus_d(s_opt, sig_s);
     float qq = s * inv_sg;
-    float inter = qq * qq;
-    float rest = 1.0f - fmaf(x2, x2, inter);          // 1 - x^4 - (s/gap)^2
-    float ahat = q.a * rest;
-    // d ahat / d s_opt
-    float As = -2.0f * q.a * qq * inv_sg * sig_s;
-    // d ahat / d gap (zero while the floor is active)
-    float hg = floored ? 0.0f : 2.0f * q.a * inter * inv_sg;
-    float x3 = x2 * x;
-    float hv = fmaf(As, fmaf(dv + v, q.c, q.T), -4.0f * q.a * x3 * q.inv_v0);
-    float hvh = -As * v * q.c;
-    float vdvc = vdv * q.c;
-    float w = 1.0f, dlb = 0.0f, gate = 1.0f;
+    P.x4 = x2 * x2;
+    P.rest = 1.0f - fmaf(qq, qq, P.x4);
+    float ahat = q.a * P.rest;
+    float tq = q.two_a * qq * inv_sg;                 // 2 a q / gap
+    P.As = -tq * sig_s;
+    P.hg = floored ? 0.0f : tq * qq;                  // 2 a q^2 / gap
+    P.u1 = fmaf(dv + v, q.c, q.T);
+    P.x3 = x2 * x;
+    P.vc = v * q.c;
+    P.vdvc = vdv * q.c;
     if (MODE == 0) {
         float nv = -v * inv_dt;
         bool on_v = nv > a_min;                       // tie -> a_min branch
         float lb = on_v ? nv : a_min;
-        w = logistic(ahat - lb);
-        dlb = on_v ? (w - 1.0f) * inv_dt : 0.0f;
+        P.w = logistic(ahat - lb);
+        P.lbv = on_v ? (P.w - 1.0f) * inv_dt : 0.0f;
+        P.gate = 1.0f;
     } else {
-        gate = (fmaf(dt, ahat, v) > 0.0f) ? 1.0f : 0.0f;
+        P.w = 1.0f;
+        P.lbv = 0.0f;
+        P.gate = (fmaf(dt, ahat, v) > 0.0f) ? 1.0f : 0.0f;
     }
-    P.Ad = -w * hg;
-    P.Adh = w * hg;
-    P.Av = fmaf(w, hv, dlb);
-    P.Avh = w * hvh;
-    P.Ap[0] = w * (4.0f * q.a * x2 * x2 * q.inv_v0);  // v0
-    P.Ap[1] = w * (As * v);                           // T
-    P.Ap[2] = w * (rest - As * vdvc * i2a);           // a
-    P.Ap[3] = w * (-As * vdvc * i2b);                 // b
-    P.Ap[4] = w * As;                                 // s0
-    P.gate = gate;
 }
 
 __device__ __forceinline__ double block_sum(double x, double *red) {
@@ -230,8 +241,7 @@ __global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
     const int S = A.n_steps;
     for (int bidx = blockIdx.x; bidx < A.n_bundles; bidx += gridDim.x) {
         Veh q[R];
-        float i2a[R], i2b[R];
-        load_vehicles<R>(A, (int64_t)bidx * (NT * R) + t * R, q, i2a, i2b);
+        load_vehicles<R>(A, (int64_t)bidx * (NT * R) + t * R, q);
         float d[R], v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -248,24 +258,24 @@ __global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
         }
         sbuf[0][t] = make_float2(d[R - 1], v[R - 1]);
         lds_barrier();
+        int to_ckpt = A.K;  // steps until the next checkpoint
         for (int k = 0; k < S; ++k) {
             float2 L = t > 0 ? sbuf[k & 1][t - 1] : make_float2(0.0f, 0.0f);
             float acc[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
+                // a lane head has g0 = +inf: any finite leader state gives a zero
+                // interaction term
                 float dh = r ? d[r - 1] : L.x;
                 float vh = r ? v[r - 1] : L.y;
-                if (q[r].head) {
-                    dh = d[r];
-                    vh = v[r];
-                }
                 acc[r] = accel<MODE>(q[r], d[r], v[r], dh, vh, A.inv_dt, A.a_min, A.gap_floor);
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) euler<MODE>(d[r], v[r], acc[r], A.dt);
             sbuf[(k + 1) & 1][t] = make_float2(d[R - 1], v[R - 1]);
             const int64_t row = (int64_t)(k + 1) * N;
-            const bool ck = A.ckpt && ((k + 1) % A.K == 0) && (k + 1 < S);
+            const bool ck = A.ckpt && (--to_ckpt == 0) && (k + 1 < S);
+            if (to_ckpt == 0) to_ckpt = A.K;
             const int64_t crow = (int64_t)((k + 1) / A.K) * 2 * N;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -286,19 +296,12 @@ __global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
 
 // ---------------------------------------------------------------- backward
 
-template <int R>
-__device__ __forceinline__ float upstream(const SimArgs &A, int k, int32_t g, float d,
-                                          double p0g, int jo, double &loss) {
-    float u = 0.0f;
-    if (g < 0) return u;
-    if (A.gd) u = A.gd[(int64_t)k * A.n + g];
-    if (jo >= 0) {
-        double r = (p0g + (double)d) - (double)A.target[(int64_t)jo * A.n + g];
-        loss = fma(r, r, loss);
-        u += (float)(2.0 * r * A.inv_count);
-    }
-    return u;
-}
+// Raw upstream inputs of one (vehicle, step): dense dL/dd, dense dL/dv and the
+// observed target.  Fetched one step ahead of their use so that the HBM
+// latency overlaps a whole step of arithmetic.
+struct Up {
+    float gd, gv, tg;
+};
 
 __device__ __forceinline__ int obs_index(const SimArgs &A, int k) {
     if (!A.target || k < A.obs_first) return -1;
@@ -308,7 +311,64 @@ __device__ __forceinline__ int obs_index(const SimArgs &A, int k) {
     return j < A.n_obs ? j : -1;
 }
 
-template <int MODE, int R, int NT, int K>
+// Branch-free loads (absent inputs read a zero word, padding slots read
+// vehicle 0), so the compiler can keep the prefetch in flight across a step.
+template <int R>
+__device__ __forceinline__ void fetch_up(const SimArgs &A, int k, int jo, const Veh (&q)[R],
+                                         Up (&u)[R]) {
+    const int64_t row = (int64_t)k * A.n;
+    const float *pgd = A.gd ? A.gd + row : A.zero;
+    const float *pgv = A.gv ? A.gv + row : A.zero;
+    const float *ptg = jo >= 0 ? A.target + (int64_t)jo * A.n : A.zero;
+    const int32_t mgd = A.gd ? -1 : 0, mgv = A.gv ? -1 : 0, mtg = jo >= 0 ? -1 : 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int32_t gl = q[r].g > 0 ? q[r].g : 0;
+        u[r].gd = pgd[gl & mgd];
+        u[r].gv = pgv[gl & mgv];
+        u[r].tg = ptg[gl & mtg];
+    }
+}
+
+// dL/dd at one step: dense part + 2 (p - target) / |O| (residual in FP64).
+__device__ __forceinline__ float apply_up(const SimArgs &A, bool observed, bool valid, const Up &u,
+                                          float d, double p0g, double &loss) {
+    float s = u.gd;  // padding slots carry a harmless, never-written adjoint
+    if (observed) {
+        double r = valid ? (p0g + (double)d) - (double)u.tg : 0.0;
+        loss = fma(r, r, loss);
+        s += (float)(r * A.two_inv_count);
+    }
+    return s;
+}
+
+// One simulation step of all vehicles of the bundle (leader of the first
+// vehicle from LDS, the others from registers), publishing the new state of
+// the last vehicle into LDS buffer `nb` and ending on a barrier.
+template <int MODE, int R, int NT>
+__device__ __forceinline__ void bundle_step(const SimArgs &A, const Veh (&q)[R], float (&d)[R],
+                                            float (&v)[R], float2 (*sbuf)[NT], int cb, int nb) {
+    const int t = threadIdx.x;
+    float2 L = t > 0 ? sbuf[cb][t - 1] : make_float2(0.0f, 0.0f);
+    float acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float dh = r ? d[r - 1] : L.x;
+        float vh = r ? v[r - 1] : L.y;
+        acc[r] = accel<MODE>(q[r], d[r], v[r], dh, vh, A.inv_dt, A.a_min, A.gap_floor);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) euler<MODE>(d[r], v[r], acc[r], A.dt);
+    sbuf[nb][t] = make_float2(d[R - 1], v[R - 1]);
+    lds_barrier();
+}
+
+// Backward pass.  The forward stored a checkpoint every A.K steps; each
+// checkpoint block is swept from its last KB-step sub-block to its first: the
+// sub-block's start state is re-advanced from the checkpoint, its KB states are
+// recomputed into registers, and the adjoint walks them backwards.  KB is a
+// compile-time size (register arrays), A.K a multiple of it.
+template <int MODE, int R, int NT, int KB>
 __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
     __shared__ float2 sbuf[2][NT];
     __shared__ float2 cbuf[2][NT];
@@ -316,139 +376,182 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
     const int t = threadIdx.x;
     const int64_t N = A.n;
     const int S = A.n_steps;
+    const int K = A.K;
     const float dt = A.dt;
     const int nblk = (S + K - 1) / K;
     for (int bidx = blockIdx.x; bidx < A.n_bundles; bidx += gridDim.x) {
         Veh q[R];
-        float i2a[R], i2b[R];
-        load_vehicles<R>(A, (int64_t)bidx * (NT * R) + t * R, q, i2a, i2b);
+        load_vehicles<R>(A, (int64_t)bidx * (NT * R) + t * R, q);
         double p0g[R];
         float ld[R], lv[R];
         double gacc[5][R];
         double loss = 0.0;
+        // upstream of the last step (the seed), and prefetch of step S-1
+        Up seed[R], nxt[R];
+        const int jo_S = obs_index(A, S);
+        fetch_up<R>(A, S, jo_S, q, seed);
+        int jo_nxt = S > 0 ? obs_index(A, S - 1) : -1;
+        if (S > 0) fetch_up<R>(A, S - 1, jo_nxt, q, nxt);
+        // checkpoint of the last block
+        float ckd[R], ckv[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            p0g[r] = q[r].g >= 0 ? A.p0[q[r].g] : 0.0;
+            const int32_t gl = q[r].g > 0 ? q[r].g : 0;
+            const int64_t crow = (int64_t)(nblk > 0 ? nblk - 1 : 0) * 2 * N;
+            p0g[r] = q[r].g >= 0 ? A.p0[gl] : 0.0;
+            ckd[r] = nblk > 0 ? A.ckpt[crow + gl] : 0.0f;
+            ckv[r] = nblk > 0 ? A.ckpt[crow + N + gl] : 0.0f;
             ld[r] = 0.0f;
             lv[r] = 0.0f;
 #pragma unroll
             for (int j = 0; j < 5; ++j) gacc[j][r] = 0.0;
         }
         if (S == 0) {
-            const int jo = obs_index(A, 0);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                ld[r] = upstream<R>(A, 0, q[r].g, 0.0f, p0g[r], jo, loss);
-                if (A.gv && q[r].g >= 0) lv[r] = A.gv[q[r].g];
+                ld[r] = apply_up(A, jo_S >= 0, q[r].g >= 0, seed[r], 0.0f, p0g[r], loss);
+                lv[r] = seed[r].gv;
             }
         }
         for (int blk = nblk - 1; blk >= 0; --blk) {
             const int k0 = blk * K;
             const int len = min(K, S - k0);
-            float d[R], v[R];
-            const int64_t crow = (int64_t)blk * 2 * N;
+            const int nsub = (len + KB - 1) / KB;
+            // this block's checkpoint, kept for re-advancing to every sub-block
+            float c0d[R], c0v[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                int32_t g = q[r].g;
-                d[r] = g >= 0 ? A.ckpt[crow + g] : 0.0f;
-                v[r] = g >= 0 ? A.ckpt[crow + N + g] : 0.0f;
+                c0d[r] = q[r].g >= 0 ? ckd[r] : 0.0f;
+                c0v[r] = q[r].g >= 0 ? ckv[r] : 0.0f;
             }
-            // recompute the block's states into registers
-            float hd[K][R], hv[K][R];
-            sbuf[0][t] = make_float2(d[R - 1], v[R - 1]);
-            lds_barrier();
+            float gs[5][R];
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                if (j < len) {
-                    float2 L = t > 0 ? sbuf[j & 1][t - 1] : make_float2(0.0f, 0.0f);
-                    float acc[R];
+            for (int r = 0; r < R; ++r)
 #pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        hd[j][r] = d[r];
-                        hv[j][r] = v[r];
-                        float dh = r ? d[r - 1] : L.x;
-                        float vh = r ? v[r - 1] : L.y;
-                        if (q[r].head) {
-                            dh = d[r];
-                            vh = v[r];
-                        }
-                        acc[r] = accel<MODE>(q[r], d[r], v[r], dh, vh, A.inv_dt, A.a_min,
-                                             A.gap_floor);
-                    }
-#pragma unroll
-                    for (int r = 0; r < R; ++r) euler<MODE>(d[r], v[r], acc[r], dt);
-                    sbuf[(j + 1) & 1][t] = make_float2(d[R - 1], v[R - 1]);
-                    lds_barrier();
-                }
-            }
-            if (blk == nblk - 1) {
-                // seed: upstream gradient at the last step S
-                const int jo = obs_index(A, S);
+                for (int j = 0; j < 5; ++j) gs[j][r] = 0.0f;
+            for (int sb = nsub - 1; sb >= 0; --sb) {
+                const int ks = k0 + sb * KB;
+                const int slen = min(KB, len - sb * KB);
+                float d[R], v[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    ld[r] += upstream<R>(A, S, q[r].g, d[r], p0g[r], jo, loss);
-                    if (A.gv && q[r].g >= 0) lv[r] += A.gv[(int64_t)S * N + q[r].g];
+                    d[r] = c0d[r];
+                    v[r] = c0v[r];
                 }
-            }
-            float gblk[5][R];
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int j = 0; j < 5; ++j) gblk[j][r] = 0.0f;
-            // reverse sweep over the block
-#pragma unroll
-            for (int j = K - 1; j >= 0; --j) {
-                if (j < len) {
-                    const int k = k0 + j;
-                    float2 L = t > 0 ? sbuf[j & 1][t - 1] : make_float2(0.0f, 0.0f);
-                    Part P[R];
-                    float mu[R];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        float dh = r ? hd[j][r - 1] : L.x;
-                        float vh = r ? hv[j][r - 1] : L.y;
-                        if (q[r].head) {
-                            dh = hd[j][r];
-                            vh = hv[j][r];
-                        }
-                        partials<MODE>(q[r], i2a[r], i2b[r], hd[j][r], hv[j][r], dh, vh, dt,
-                                       A.inv_dt, A.a_min, A.gap_floor, P[r]);
-                        mu[r] = P[r].gate * dt * lv[r];
-                    }
-                    // contribution of my first vehicle to its leader (previous thread)
-                    cbuf[j & 1][t] = make_float2(mu[0] * P[0].Adh, mu[0] * P[0].Avh);
-                    if (j > 0) sbuf[(j - 1) & 1][t] = make_float2(hd[j - 1][R - 1], hv[j - 1][R - 1]);
+                sbuf[0][t] = make_float2(d[R - 1], v[R - 1]);
+                lds_barrier();
+                // re-advance from the checkpoint to the sub-block start
+                for (int j = 0; j < sb * KB; ++j) bundle_step<MODE, R, NT>(A, q, d, v, sbuf, j & 1, (j + 1) & 1);
+                if (sb > 0) {
+                    // restart the LDS ping-pong at parity 0 (buffer (sb*KB)&1 was
+                    // written last and is not read again)
+                    sbuf[0][t] = make_float2(d[R - 1], v[R - 1]);
                     lds_barrier();
-                    float2 F = (t + 1 < NT) ? cbuf[j & 1][t + 1] : make_float2(0.0f, 0.0f);
-                    const int jo = obs_index(A, k);
+                }
+                // recompute the sub-block's states into registers
+                float hd[KB][R], hv[KB][R];
+#pragma unroll
+                for (int j = 0; j < KB; ++j) {
+                    if (j < slen) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            hd[j][r] = d[r];
+                            hv[j][r] = v[r];
+                        }
+                        bundle_step<MODE, R, NT>(A, q, d, v, sbuf, j & 1, (j + 1) & 1);
+                    }
+                }
+                if (blk == nblk - 1 && sb == nsub - 1) {
+                    // seed: upstream gradient at the last step S (d, v are now step S)
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        float fd, fv;  // gathered from the follower
-                        if (r + 1 < R) {
-                            fd = mu[r + 1] * P[r + 1].Adh;
-                            fv = mu[r + 1] * P[r + 1].Avh;
-                        } else {
-                            fd = F.x;
-                            fv = F.y;
-                        }
-                        if (q[r].tail) {
-                            fd = 0.0f;
-                            fv = 0.0f;
-                        }
-                        float nld = fmaf(mu[r], P[r].Ad, ld[r]) + fd;
-                        float nlv = fmaf(dt, ld[r], fmaf(P[r].gate, lv[r], fmaf(mu[r], P[r].Av, fv)));
+                        ld[r] += apply_up(A, jo_S >= 0, q[r].g >= 0, seed[r], d[r], p0g[r], loss);
+                        lv[r] += seed[r].gv;
+                    }
+                }
+                if (sb == 0) {
+                    // prefetch the previous block's checkpoint (block 0 reloads itself)
+                    const int64_t crow = (int64_t)(blk > 0 ? blk - 1 : 0) * 2 * N;
 #pragma unroll
-                        for (int p = 0; p < 5; ++p) gblk[p][r] = fmaf(mu[r], P[r].Ap[p], gblk[p][r]);
-                        ld[r] = nld + upstream<R>(A, k, q[r].g, hd[j][r], p0g[r], jo, loss);
-                        lv[r] = nlv;
-                        if (A.gv && q[r].g >= 0) lv[r] += A.gv[(int64_t)k * N + q[r].g];
+                    for (int r = 0; r < R; ++r) {
+                        const int32_t gl = q[r].g > 0 ? q[r].g : 0;
+                        ckd[r] = A.ckpt[crow + gl];
+                        ckv[r] = A.ckpt[crow + N + gl];
+                    }
+                }
+                // reverse sweep over the sub-block
+#pragma unroll
+                for (int j = KB - 1; j >= 0; --j) {
+                    if (j < slen) {
+                        const int k = ks + j;
+                        Up cur[R];
+#pragma unroll
+                        for (int r = 0; r < R; ++r) cur[r] = nxt[r];
+                        const int jo_cur = jo_nxt;
+                        if (k > 0) {
+                            jo_nxt = obs_index(A, k - 1);
+                            fetch_up<R>(A, k - 1, jo_nxt, q, nxt);
+                        }
+                        float2 L = t > 0 ? sbuf[j & 1][t - 1] : make_float2(0.0f, 0.0f);
+                        Part P[R];
+                        float mu[R], mw[R], mwAs[R];
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            float dh = r ? hd[j][r - 1] : L.x;
+                            float vh = r ? hv[j][r - 1] : L.y;
+                            partials<MODE>(q[r], hd[j][r], hv[j][r], dh, vh, dt, A.inv_dt, A.a_min,
+                                           A.gap_floor, P[r]);
+                            mu[r] = (MODE == 0) ? dt * lv[r] : P[r].gate * dt * lv[r];
+                            mw[r] = mu[r] * P[r].w;
+                            mwAs[r] = mw[r] * P[r].As;
+                        }
+                        // contribution of my first vehicle to its leader (previous
+                        // thread): (mu d a*/d d_h, mu d a*/d v_h).  A lane head
+                        // contributes exactly 0 (its hg and As vanish), so a lane
+                        // tail needs no mask.
+                        cbuf[j & 1][t] = make_float2(mw[0] * P[0].hg, -mwAs[0] * P[0].vc);
+                        if (j > 0)
+                            sbuf[(j - 1) & 1][t] = make_float2(hd[j - 1][R - 1], hv[j - 1][R - 1]);
+                        lds_barrier();
+                        float2 F = (t + 1 < NT) ? cbuf[j & 1][t + 1] : make_float2(0.0f, 0.0f);
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            float fd, fv;  // gathered from the follower
+                            if (r + 1 < R) {
+                                fd = mw[r + 1] * P[r + 1].hg;
+                                fv = -mwAs[r + 1] * P[r + 1].vc;
+                            } else {
+                                fd = F.x;
+                                fv = F.y;
+                            }
+                            float nld = fmaf(-mw[r], P[r].hg, ld[r]) + fd;
+                            float keep = (MODE == 0) ? lv[r] : P[r].gate * lv[r];
+                            float nlv = fmaf(dt, ld[r], keep);
+                            nlv = fmaf(mwAs[r], P[r].u1, nlv);
+                            nlv = fmaf(-mw[r] * q[r].fa_v0, P[r].x3, nlv);
+                            if (MODE == 0) nlv = fmaf(mu[r], P[r].lbv, nlv);
+                            nlv += fv;
+                            // sufficient statistics of the five parameter gradients
+                            gs[0][r] = fmaf(mw[r], P[r].x4, gs[0][r]);      // v0 (times 4a/v0)
+                            gs[1][r] = fmaf(mwAs[r], hv[j][r], gs[1][r]);   // T
+                            gs[2][r] = fmaf(mw[r], P[r].rest, gs[2][r]);    // a, direct part
+                            gs[3][r] = fmaf(mwAs[r], P[r].vdvc, gs[3][r]);  // a and b, through c
+                            gs[4][r] += mwAs[r];                           // s0
+                            ld[r] = nld + apply_up(A, jo_cur >= 0, q[r].g >= 0, cur[r], hd[j][r],
+                                                   p0g[r], loss);
+                            lv[r] = nlv + cur[r].gv;
+                        }
                     }
                 }
             }
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int p = 0; p < 5; ++p) gacc[p][r] += (double)gblk[p][r];
+            for (int r = 0; r < R; ++r) {
+                gacc[0][r] += (double)q[r].fa_v0 * (double)gs[0][r];
+                gacc[1][r] += (double)gs[1][r];
+                gacc[2][r] += (double)gs[2][r] - (double)q[r].i2a * (double)gs[3][r];
+                gacc[3][r] -= (double)q[r].i2b * (double)gs[3][r];
+                gacc[4][r] += (double)gs[4][r];
+            }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {

@@ -55,7 +55,7 @@ def test_valid_problem_shape_and_workspace(L):
     off = np.arange(0, 2000 * 1000 + 1, 1000)
     st, info, ws = _check(L, off, S=100, K=32)
     assert st == 0
-    assert (info.threads, info.per_thread, info.ckpt_every) == (1024, 1, 32)
+    assert (info.threads, info.per_thread, info.ckpt_every, info.block) == (1024, 1, 32, 16)
     assert info.n_bundles == 2000 and info.max_lane == 1000
     assert abs(info.fill - 1000 / 1024) < 1e-12
     N, S, K = 2_000_000, 100, 32
@@ -76,7 +76,7 @@ def test_valid_problem_shape_and_workspace(L):
     (dict(offsets=[0, 10], bound=7), -1),
     (dict(offsets=[0, 10], S=-1), -1),
     (dict(offsets=[0, 10], K=-3), -1),
-    (dict(offsets=[0, 10], K=12), -3),            # K not instantiated
+    (dict(offsets=[0, 10], K=6), -3),             # no backward block divides K
 ])
 def test_invalid_problems_are_rejected(L, case, status):
     st, _, _ = _check(L, **case)
@@ -89,9 +89,18 @@ def test_invalid_tuning(L):
     assert _check(L, [0, 100], tuning=(64, 3, 0, 0))[0] == -3
     assert _check(L, [0, 100], tuning=(64, 1, 0, 0))[0] == -2   # 100 > 64 slots
     assert _check(L, [0, 100], tuning=(128, 1, 0, -1))[0] == -1
-    assert _check(L, [0, 100], tuning=(64, 4, 32, 0))[0] == -3  # K=32 not for R=4
+    assert _check(L, [0, 100], tuning=(64, 4, 32, 0, 16))[0] == -3  # block 16 not for R=4
+    assert _check(L, [0, 100], tuning=(128, 1, 24, 0, 16))[0] == -3  # 16 does not divide 24
+    assert _check(L, [0, 100], tuning=(128, 1, 0, 0, -1))[0] == -1
+    st, info, _ = _check(L, [0, 100], tuning=(64, 4, 32, 0))
+    assert st == 0 and (info.per_thread, info.ckpt_every, info.block) == (4, 32, 8)
     st, info, _ = _check(L, [0, 100], tuning=(64, 2, 8, 0))
-    assert st == 0 and (info.threads, info.per_thread, info.ckpt_every) == (64, 2, 8)
+    assert st == 0 and (info.threads, info.per_thread, info.ckpt_every, info.block) == (64, 2, 8, 8)
+    # K = 12: only 4 vehicles per thread (block 4) divides it
+    st, info, _ = _check(L, [0, 10], K=12)
+    assert st == 0 and (info.per_thread, info.block) == (4, 4)
+    st, info, _ = _check(L, [0, 10], K=48)
+    assert st == 0 and (info.per_thread, info.block) == (1, 16)
 
 
 def _layout(L, offsets, tuning):
@@ -110,7 +119,8 @@ def _layout(L, offsets, tuning):
     return info, gidx, flags
 
 
-@pytest.mark.parametrize("tuning", [(64, 1, 8, 0), (64, 2, 8, 0), (256, 4, 4, 0), (1024, 4, 8, 0)])
+@pytest.mark.parametrize("tuning", [(64, 1, 8, 0, 0), (64, 2, 8, 0, 0), (256, 4, 4, 0, 0),
+                                    (1024, 4, 8, 0, 0)])
 def test_layout_packs_whole_lanes(L, tuning):
     import scenarios
     sizes = scenarios.lognormal_lane_sizes(3000, 3.0, 1.2, 1, tuning[0] * tuning[1], 99)

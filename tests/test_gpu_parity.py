@@ -50,12 +50,15 @@ def test_single_lane_1000_steps(mode):
 
 
 @pytest.mark.parametrize("mode", [MODE_SOFTPLUS, MODE_CLAMP])
-@pytest.mark.parametrize("shape", [(64, 1, 8), (128, 2, 8), (64, 4, 4), (256, 1, 32), (128, 2, 16),
-                                   (64, 4, 8)])
+@pytest.mark.parametrize("shape", [(64, 1, 8, 8), (128, 2, 8, 8), (64, 4, 4, 4), (256, 1, 32, 32),
+                                   (256, 1, 32, 16), (128, 1, 32, 8), (128, 2, 16, 16),
+                                   (64, 4, 8, 8), (64, 4, 24, 4)])
 def test_ragged_lanes_several_tiles(mode, shape):
     """Lanes of 1..256 vehicles (several work-group tiles, ragged bundle tails),
-    S = 203 (ragged last K-block), dense upstream gradient + fused MSE."""
-    threads, per, K = shape
+    S = 203 (ragged last checkpoint block and sub-block), checkpoint interval K
+    with a backward register block KB dividing it (1 to 6 sub-blocks per
+    checkpoint block), dense upstream gradient + fused MSE."""
+    threads, per, K, KB = shape
     sizes = [1, 2, 3, 63, 64, 65, 100, 127, 31, 256, 0, 17, 200, 5, 90]
     cap = threads * per
     sizes = [s for s in sizes if s <= cap]
@@ -65,9 +68,9 @@ def test_ragged_lanes_several_tiles(mode, shape):
     tgt = oracle_targets(sc, steps, c=3)
     dense = rng.normal(0, 1e-3, size=(sc.n_steps + 1, sc.n)).astype(np.float32)
     ref = oracle_reference(sc, steps, tgt, dense)
-    out = gpu_run(sc, steps, tgt, dense, threads=threads, per_thread=per, tuning_k=K)
+    out = gpu_run(sc, steps, tgt, dense, threads=threads, per_thread=per, tuning_k=K, block=KB)
     assert out["info"]["threads"] == threads and out["info"]["per_thread"] == per
-    assert out["info"]["ckpt_every"] == K
+    assert out["info"]["ckpt_every"] == K and out["info"]["block"] == KB
     _check(sc, ref, out, "ragged mode=%d shape=%s" % (mode, shape))
 
 
@@ -89,11 +92,17 @@ def test_forward_bitwise_independent_of_launch_shape():
         assert np.array_equal(o["gp0"], base["gp0"]) and np.array_equal(o["gv0"], base["gv0"])
         # the loss is summed per bundle, and bundles differ between shapes
         assert abs(o["loss"] - base["loss"]) <= 1e-13 * base["loss"]
-    for K in (16, 32):
-        o = gpu_run(sc, steps, tgt, threads=128, per_thread=1, tuning_k=K)
-        assert np.array_equal(o["d"], base["d"])
+    for K, KB in ((16, 16), (32, 32), (32, 8), (24, 8)):
+        o = gpu_run(sc, steps, tgt, threads=128, per_thread=1, tuning_k=K, block=KB)
+        assert np.array_equal(o["d"], base["d"]) and np.array_equal(o["V"], base["V"])
         okg, w = grad_close(o["g"], base["g"], rtol=1e-5)
-        assert okg, (K, w)
+        assert okg, (K, KB, w)
+    # with K fixed, the register block only changes where states are recomputed:
+    # the arithmetic of every step is the same, so gradients are bitwise equal
+    a32 = gpu_run(sc, steps, tgt, threads=128, per_thread=1, tuning_k=32, block=32)
+    b32 = gpu_run(sc, steps, tgt, threads=128, per_thread=1, tuning_k=32, block=8)
+    for k in ("g", "gp0", "gv0"):
+        assert np.array_equal(a32[k], b32[k]), k
 
 
 def test_persistent_grid_matches_one_group_per_bundle():
@@ -137,7 +146,7 @@ def test_zero_steps_and_single_vehicle():
 
 def test_full_capacity_lanes():
     """Lanes that fill a bundle exactly (1024 = 1024 x 1 and 256 x 4)."""
-    for threads, per, K in [(1024, 1, 8), (256, 4, 4)]:
+    for threads, per, K in [(1024, 1, 32), (256, 4, 4)]:
         sc = ragged_scenario([1024, 1023], 120, ckpt_every=K)
         steps = np.arange(1, 121)
         tgt = oracle_targets(sc, steps, c=8)
