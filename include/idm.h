@@ -169,7 +169,10 @@ idm_status idm_sim_forward(idm_plan *plan, const idm_params *prm, const double *
  *   grad_traj_v [(S+1)*N] FP32 dL/dv_k, nullable;
  *   obs: fused mean-squared trajectory loss (see idm_obs), nullable.
  * Outputs (overwritten, FP64): grad_params [5*N] (v0, T, a, b, s0 blocks),
- * grad_p0 [N] = dL/dp(0), grad_v0 [N] = dL/dv(0).  loss_out (device FP64
+ * grad_p0 [N] = dL/dp0 and grad_v0 [N] = dL/dv(0).  grad_p0 treats the dense
+ * upstream grad_traj_d as acting on the displacements at fixed p0 (so it
+ * reaches p0 only through the gaps), and the fused loss as acting on the
+ * absolute positions p0 + d_k (gap terms plus its direct term).  loss_out (device FP64
  * scalar, nullable) receives the fused loss (0 if obs is NULL).  Per-vehicle
  * gradients are summed over time in FP64 in a fixed order; no atomics, so
  * results are bitwise reproducible. */
@@ -200,6 +203,12 @@ typedef struct {
     int32_t lr_steps;      /* >= 1 */
     float beta1, beta2, eps;
 } idm_fit_state;
+
+/* Start a fit from physical parameters init_params [5*N] (device FP32):
+ * u = clamp((theta - lo)/(hi - lo), 0, 1), Adam moments 0, step counter 0,
+ * params rewritten from u.  One kernel; graph-capturable. */
+idm_status idm_fit_init(idm_plan *plan, const idm_fit_state *st, const float *init_params,
+                        void *stream);
 
 idm_status idm_fit_step(idm_plan *plan, const idm_fit_state *st, const double *p0,
                         const float *v_init, const idm_obs *obs, void *workspace, void *stream);

@@ -89,6 +89,10 @@ struct idm_plan {
     idm_step_args step_key{};
     hipGraphExec_t fit_exec = nullptr;
     std::vector<unsigned char> fit_key;
+    // graphs cannot be captured on the legacy null stream: null-stream callers
+    // get a plan-owned side stream (default priority), joined by events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
 namespace {
@@ -375,6 +379,7 @@ AdamArgs adam_args(const idm_plan *p, const idm_fit_state *st, const double *gra
     a.params = st->params;
     a.grad = grad;
     a.step = st->step;
+    a.step_rw = st->step;
     for (int i = 0; i < 5; ++i) {
         a.lo[i] = st->lo[i];
         a.hi[i] = st->hi[i];
@@ -516,6 +521,36 @@ idm_status host_plan(const idm_problem *pb, const idm_tuning *tu, idm_plan *p, S
     return choose_shape(p, tu, sh);
 }
 
+// The stream graph work runs on: the caller's, or the side stream for the
+// null stream (made to wait for the null stream's prior work).
+idm_status graph_stream_enter(idm_plan *p, hipStream_t caller, hipStream_t *out) {
+    if (caller) {
+        *out = caller;
+        return IDM_OK;
+    }
+    hipError_t e = hipSuccess;
+    if (!p->side) {
+        e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "side stream creation");
+    }
+    e = hipEventRecord(p->ev_in, nullptr);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_in, 0);
+    if (e != hipSuccess) return hip_fail(e, "side stream join");
+    *out = p->side;
+    return IDM_OK;
+}
+
+// Make the null stream wait for the side stream's graph work.
+idm_status graph_stream_leave(idm_plan *p, hipStream_t caller) {
+    if (caller) return IDM_OK;
+    hipError_t e = hipEventRecord(p->ev_out, p->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(nullptr, p->ev_out, 0);
+    if (e != hipSuccess) return hip_fail(e, "side stream join");
+    return IDM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -594,6 +629,9 @@ idm_status idm_plan_destroy(idm_plan *p) {
     if (p->d_gidx) hipFree(p->d_gidx);
     if (p->d_flags) hipFree(p->d_flags);
     if (p->d_zero) hipFree(p->d_zero);
+    if (p->side) hipStreamDestroy(p->side);
+    if (p->ev_in) hipEventDestroy(p->ev_in);
+    if (p->ev_out) hipEventDestroy(p->ev_out);
     delete p;
     return IDM_OK;
 }
@@ -639,6 +677,21 @@ idm_status idm_sim_backward(idm_plan *p, const idm_params *prm, const double *p0
                         (hipStream_t)stream);
 }
 
+idm_status idm_fit_init(idm_plan *p, const idm_fit_state *st, const float *init_params,
+                        void *stream) {
+    if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
+    if (!init_params) return fail(IDM_ERR_INVALID_ARG, "init_params is null");
+    if (!st || !st->u || !st->m || !st->v || !st->params || !st->step)
+        return fail(IDM_ERR_INVALID_ARG, "fit state: null pointer");
+    for (int i = 0; i < 5; ++i)
+        if (!(st->hi[i] > st->lo[i]) || !std::isfinite(st->lo[i]) || !std::isfinite(st->hi[i]))
+            return fail(IDM_ERR_INVALID_ARG, "fit state: box %d invalid", i);
+    AdamArgs aa = adam_args(p, st, nullptr);
+    hipError_t e = launch_fit_init(aa, init_params, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fit init launch");
+    return IDM_OK;
+}
+
 idm_status idm_fit_step(idm_plan *p, const idm_fit_state *st, const double *p0, const float *v_init,
                         const idm_obs *obs, void *ws, void *stream) {
     if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
@@ -653,7 +706,9 @@ idm_status idm_fit_run(idm_plan *p, const idm_fit_state *st, const double *p0, c
     if (n_iters < 0) return fail(IDM_ERR_INVALID_ARG, "n_iters < 0");
     idm_status r = check_fit(p, st, p0, v_init, obs, ws);
     if (r != IDM_OK) return r;
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t s = nullptr;
+    r = graph_stream_enter(p, (hipStream_t)stream, &s);
+    if (r != IDM_OK) return r;
     std::vector<unsigned char> key(sizeof(idm_fit_state) + sizeof(idm_obs) + 3 * sizeof(void *));
     unsigned char *k = key.data();
     memcpy(k, st, sizeof(idm_fit_state));
@@ -671,14 +726,16 @@ idm_status idm_fit_run(idm_plan *p, const idm_fit_state *st, const double *p0, c
         hipError_t e = hipGraphLaunch(p->fit_exec, s);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch(fit)");
     }
-    return IDM_OK;
+    return graph_stream_leave(p, (hipStream_t)stream);
 }
 
 idm_status idm_step_graph_launch(idm_plan *p, const idm_step_args *a, void *stream) {
     if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
     idm_status r = check_step(p, a);
     if (r != IDM_OK) return r;
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t s = nullptr;
+    r = graph_stream_enter(p, (hipStream_t)stream, &s);
+    if (r != IDM_OK) return r;
     if (!p->step_exec || memcmp(&p->step_key, a, sizeof *a) != 0) {
         if (p->step_exec) hipGraphExecDestroy(p->step_exec);
         p->step_exec = nullptr;
@@ -688,7 +745,7 @@ idm_status idm_step_graph_launch(idm_plan *p, const idm_step_args *a, void *stre
     }
     hipError_t e = hipGraphLaunch(p->step_exec, s);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch(step)");
-    return IDM_OK;
+    return graph_stream_leave(p, (hipStream_t)stream);
 }
 
 idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_bytes, int32_t reps,

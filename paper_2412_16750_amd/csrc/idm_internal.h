@@ -52,6 +52,7 @@ struct AdamArgs {
     float *u, *m, *v, *params;
     const double *grad;   // [5][N]
     const int32_t *step;  // device counter (already incremented for this step)
+    int32_t *step_rw;     // same counter, written by the initialisation kernel
     float lo[5], hi[5];
     float lr0, lr1;
     int32_t lr_steps;
@@ -73,5 +74,6 @@ hipError_t launch_fit_finalize(const double *part, int32_t n_part, double scale,
 hipError_t launch_adam(const AdamArgs &a, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, int64_t n16, int grid, hipStream_t s);
 hipError_t launch_params_from_u(const AdamArgs &a, hipStream_t s);
+hipError_t launch_fit_init(const AdamArgs &a, const float *init, hipStream_t s);
 
 }  // namespace idmx

@@ -330,14 +330,15 @@ __device__ __forceinline__ void fetch_up(const SimArgs &A, int k, int jo, const 
     }
 }
 
-// dL/dd at one step: dense part + 2 (p - target) / |O| (residual in FP64).
-__device__ __forceinline__ float apply_up(const SimArgs &A, bool observed, bool valid, const Up &u,
-                                          float d, double p0g, double &loss) {
-    float s = u.gd;  // padding slots carry a harmless, never-written adjoint
+// Fused loss at one step: returns 2 (p - target) / |O| (residual in FP64) and
+// accumulates the squared residual; 0 when the step is not observed.
+__device__ __forceinline__ float mse_up(const SimArgs &A, bool observed, bool valid, const Up &u,
+                                        float d, double p0g, double &loss) {
+    float s = 0.0f;
     if (observed) {
         double r = valid ? (p0g + (double)d) - (double)u.tg : 0.0;
         loss = fma(r, r, loss);
-        s += (float)(r * A.two_inv_count);
+        s = (float)(r * A.two_inv_count);
     }
     return s;
 }
@@ -384,6 +385,9 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
         load_vehicles<R>(A, (int64_t)bidx * (NT * R) + t * R, q);
         double p0g[R];
         float ld[R], lv[R];
+        // dL/dp0: the gap terms plus the fused loss's direct term (p = p0 + d);
+        // a dense upstream dL/dd acts at fixed p0 and reaches p0 only via gaps
+        float gp0[R];
         double gacc[5][R];
         double loss = 0.0;
         // upstream of the last step (the seed), and prefetch of step S-1
@@ -403,13 +407,15 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
             ckv[r] = nblk > 0 ? A.ckpt[crow + N + gl] : 0.0f;
             ld[r] = 0.0f;
             lv[r] = 0.0f;
+            gp0[r] = 0.0f;
 #pragma unroll
             for (int j = 0; j < 5; ++j) gacc[j][r] = 0.0;
         }
         if (S == 0) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                ld[r] = apply_up(A, jo_S >= 0, q[r].g >= 0, seed[r], 0.0f, p0g[r], loss);
+                gp0[r] = mse_up(A, jo_S >= 0, q[r].g >= 0, seed[r], 0.0f, p0g[r], loss);
+                ld[r] = seed[r].gd + gp0[r];
                 lv[r] = seed[r].gv;
             }
         }
@@ -465,7 +471,9 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                     // seed: upstream gradient at the last step S (d, v are now step S)
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        ld[r] += apply_up(A, jo_S >= 0, q[r].g >= 0, seed[r], d[r], p0g[r], loss);
+                        const float um = mse_up(A, jo_S >= 0, q[r].g >= 0, seed[r], d[r], p0g[r], loss);
+                        gp0[r] += um;
+                        ld[r] += seed[r].gd + um;
                         lv[r] += seed[r].gv;
                     }
                 }
@@ -524,7 +532,8 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                                 fd = F.x;
                                 fv = F.y;
                             }
-                            float nld = fmaf(-mw[r], P[r].hg, ld[r]) + fd;
+                            const float gterm = fmaf(-mw[r], P[r].hg, fd);  // gap terms
+                            float nld = ld[r] + gterm;
                             float keep = (MODE == 0) ? lv[r] : P[r].gate * lv[r];
                             float nlv = fmaf(dt, ld[r], keep);
                             nlv = fmaf(mwAs[r], P[r].u1, nlv);
@@ -537,8 +546,10 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                             gs[2][r] = fmaf(mw[r], P[r].rest, gs[2][r]);    // a, direct part
                             gs[3][r] = fmaf(mwAs[r], P[r].vdvc, gs[3][r]);  // a and b, through c
                             gs[4][r] += mwAs[r];                           // s0
-                            ld[r] = nld + apply_up(A, jo_cur >= 0, q[r].g >= 0, cur[r], hd[j][r],
-                                                   p0g[r], loss);
+                            const float um = mse_up(A, jo_cur >= 0, q[r].g >= 0, cur[r], hd[j][r],
+                                                    p0g[r], loss);
+                            gp0[r] += gterm + um;
+                            ld[r] = nld + (cur[r].gd + um);
                             lv[r] = nlv + cur[r].gv;
                         }
                     }
@@ -559,7 +570,7 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
             if (g >= 0) {
 #pragma unroll
                 for (int p = 0; p < 5; ++p) A.g_prm[(int64_t)p * N + g] = gacc[p][r];
-                A.g_p0[g] = (double)ld[r];
+                A.g_p0[g] = (double)gp0[r];
                 A.g_v0[g] = (double)lv[r];
             }
         }
@@ -617,6 +628,23 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs A) {
         A.u[i] = u;
         A.params[i] = A.lo[p] + u * span;
     }
+}
+
+// Fit initialisation: u = clamp((theta - lo) / (hi - lo), 0, 1), zero Adam
+// moments, step counter 0, physical parameters rewritten from u.
+__global__ __launch_bounds__(256) void k_fit_init(AdamArgs A, const float *init) {
+    const int64_t total = 5 * A.n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int p = (int)(i / A.n);
+        float span = A.hi[p] - A.lo[p];
+        float u = fminf(fmaxf((init[i] - A.lo[p]) / span, 0.0f), 1.0f);
+        A.u[i] = u;
+        A.m[i] = 0.0f;
+        A.v[i] = 0.0f;
+        A.params[i] = A.lo[p] + u * span;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *A.step_rw = 0;
 }
 
 __global__ __launch_bounds__(256) void k_params_from_u(AdamArgs A) {
@@ -723,6 +751,11 @@ hipError_t launch_copy(const void *src, void *dst, int64_t n16, int grid, hipStr
 
 hipError_t launch_adam(const AdamArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_adam, dim3(elementwise_grid(5 * a.n)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit_init(const AdamArgs &a, const float *init, hipStream_t s) {
+    hipLaunchKernelGGL(k_fit_init, dim3(elementwise_grid(5 * a.n)), dim3(256), 0, s, a, init);
     return hipGetLastError();
 }
 

@@ -37,6 +37,10 @@ def oracle_reference(sc, steps=None, target=None, dense=None):
     if dense is not None:
         gP += dense.astype(np.float64).reshape(gP.shape)
     g, gp0, gv0 = oracle.adjoint(pb, P, V, gP)
+    if dense is not None:
+        # a dense upstream acts on the displacements d = P - p0 at fixed p0:
+        # L(d) = L(P - p0), so dL/dp0 loses the direct term sum_k dL/dd_k
+        gp0 = gp0 - dense.astype(np.float64).reshape(gP.shape).sum(axis=0)
     return dict(P=P, V=V, loss=loss, g=g, gp0=gp0, gv0=gv0, floor_hits=hits)
 
 

@@ -1,0 +1,115 @@
+"""The device-side trajectory fit (idm_fit_init / idm_fit_step / idm_fit_run)
+against the oracle's gradient + Adam step, graph replay against eager steps,
+and convergence on a small problem."""
+import numpy as np
+import pytest
+
+import oracle
+import scenarios
+from oracle.fit import adam_box_step
+from _util import grad_close, ragged_scenario
+from gpu_run import device_inputs, log
+
+pytestmark = pytest.mark.gpu
+
+BOX_LO = np.array([15.0, 0.5, 0.5, 0.5, 0.5])
+BOX_HI = np.array([45.0, 3.0, 3.0, 4.0, 5.0])
+MID = (BOX_LO + BOX_HI) / 2  # exactly representable, u = 0.5 exactly
+
+
+def _problem(sizes=(30, 20, 1, 12), S=200, every=10, seed_c=4):
+    sc = ragged_scenario(list(sizes), S, ckpt_every=16, seed_c=seed_c)
+    steps = np.arange(every, S + 1, every)
+    P, _, _, _ = oracle.forward(oracle.Problem.from_scenario(sc))  # hidden parameters
+    tgt = (P[steps] + scenarios.noise((len(steps), sc.n), seed_c)).astype(np.float32)
+    return sc, steps, tgt
+
+
+def _fitter(sc, steps, tgt, lr=1e-2, **kw):
+    import torch
+    from paper_2412_16750_amd import sim
+    from paper_2412_16750_amd.fit import Fitter
+    plan = sim.Plan.for_scenario(sc)
+    x = device_inputs(sc)
+    obs = sim.Obs(torch.from_numpy(tgt).cuda(), int(steps[0]), int(steps[1] - steps[0]))
+    f = Fitter(plan, x["length"], x["p0"], x["v"], obs, lr0=lr, **kw)
+    return f, x
+
+
+def _cold(n, values):
+    import torch
+    return torch.from_numpy(np.repeat(np.asarray(values, np.float32)[:, None], n, axis=1)).cuda()
+
+
+def test_first_fit_step_matches_oracle_gradient_and_adam():
+    sc, steps, tgt = _problem()
+    f, x = _fitter(sc, steps, tgt)
+    f.init(_cold(sc.n, MID))
+    f.step()
+    import torch
+    torch.cuda.synchronize()
+    # oracle: loss and gradient at the box midpoints, then one Adam step
+    prm = {k: np.full(sc.n, MID[i], np.float32) for i, k in enumerate(oracle.PARAM_NAMES)}
+    prm["length"] = sc.params["length"]
+    pb = oracle.Problem.from_scenario(sc, params=prm)
+    P, V, _, _ = oracle.forward(pb)
+    loss, gP = oracle.mse(P, steps, tgt.astype(np.float64))
+    g, _, _ = oracle.adjoint(pb, P, V, gP)
+    u0 = np.full((5, sc.n), 0.5)
+    u1, m1, v1, th1 = adam_box_step(u0, np.zeros_like(u0), np.zeros_like(u0), g,
+                                    BOX_LO[:, None], BOX_HI[:, None], 1, 1e-2)
+    l_gpu = f.losses()[0]
+    log("fit step 1: loss gpu %.9e oracle %.9e" % (l_gpu, loss))
+    assert abs(l_gpu - loss) <= 1e-4 * loss
+    ok, w = grad_close(f.m.double().cpu().numpy(), m1)
+    log("fit step 1: Adam first moment worst/limit %.3f" % w)
+    assert ok
+    assert np.max(np.abs(f.u.double().cpu().numpy() - u1)) < 1e-5
+    assert np.max(np.abs(f.params.double().cpu().numpy() - th1) / (BOX_HI - BOX_LO)[:, None]) < 1e-5
+    assert f.steps_done() == 1
+
+
+def test_fit_graph_replay_matches_eager_steps():
+    """Each replay of the captured fit step is checked against the eager step,
+    with eager work and synchronisations between the replays."""
+    import torch
+    sc, steps, tgt = _problem(seed_c=5)
+    f, x = _fitter(sc, steps, tgt)
+    cold = _cold(sc.n, [scenarios.COLD_START[k] for k in oracle.PARAM_NAMES])
+    f.init(cold)
+    eager = []
+    for _ in range(6):
+        f.step()
+        torch.cuda.synchronize()
+        eager.append([t.clone() for t in (f.u, f.m, f.v, f.params)] + [f.losses().copy()])
+    f.init(cold)
+    for i in range(6):
+        f.run(1)
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device="cuda").sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        got = [f.u, f.m, f.v, f.params]
+        for a, b in zip(got, eager[i][:4]):
+            assert torch.equal(a, b), i
+        assert np.array_equal(f.losses(), eager[i][4]), i
+        del junk
+    f.init(cold)
+    f.run(6)
+    torch.cuda.synchronize()
+    assert torch.equal(f.u, eager[-1][0]) and f.steps_done() == 6
+
+
+def test_fit_reduces_the_loss_within_the_boxes():
+    import torch
+    sc, steps, tgt = _problem(sizes=(60, 40), S=300, seed_c=6)
+    f, x = _fitter(sc, steps, tgt)
+    f.init(_cold(sc.n, [scenarios.COLD_START[k] for k in oracle.PARAM_NAMES]))
+    f.run(150)
+    torch.cuda.synchronize()
+    L = f.losses()
+    log("fit: loss %.4e -> %.4e over %d steps" % (L[0], L[-1], len(L)))
+    assert len(L) == 150 and L[-1] < 0.3 * L[0]
+    prm = f.params.double().cpu().numpy()
+    assert np.all(prm >= BOX_LO[:, None] - 1e-6) and np.all(prm <= BOX_HI[:, None] + 1e-6)
+    u = f.u.cpu().numpy()
+    assert u.min() >= 0.0 and u.max() <= 1.0

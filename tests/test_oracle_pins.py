@@ -416,3 +416,48 @@ def test_mse_and_gradient():
     assert loss0 == 0.0
     s, g = oracle.mae_sum(P, steps, tgt)
     assert abs(s - 0.25 * 15) < 1e-12 and np.all(g[steps] == -1.0)
+
+
+# ---------------------------------------------------------------- fit (Adam + box)
+
+def test_adam_first_step_is_signed_learning_rate():
+    """With zero moments the bias-corrected first Adam step is
+    -lr * g / (|g| + eps): a step of (almost exactly) lr against the sign of
+    the gradient, whatever its scale."""
+    from oracle.fit import adam_box_step
+    u = np.full((5, 4), 0.5)
+    g = np.array([[3.0, -2e-3, 1e5, -7.0]] * 5)
+    lo = np.zeros((5, 1)); hi = np.ones((5, 1))
+    u1, m, v, th = adam_box_step(u, np.zeros_like(u), np.zeros_like(u), g, lo, hi, 1, 0.01)
+    np.testing.assert_allclose(u1, 0.5 - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(th, u1)
+
+
+def test_adam_projection_and_chain_rule():
+    """The box is enforced after every step, and a box of width w scales the
+    gradient seen by u by w (theta = lo + u w)."""
+    from oracle.fit import adam_box_step, lr_at
+    lo = np.array([[15.0]]); hi = np.array([[45.0]])
+    u = np.array([[0.995]]); m = np.zeros((1, 1)); v = np.zeros((1, 1))
+    for t in range(1, 50):
+        u, m, v, th = adam_box_step(u, m, v, np.array([[-1.0]]), lo, hi, t, 0.01)
+        assert 0.0 <= u[0, 0] <= 1.0
+    assert u[0, 0] == 1.0 and th[0, 0] == 45.0
+    _, m1, _, _ = adam_box_step(np.array([[0.5]]), np.zeros((1, 1)), np.zeros((1, 1)),
+                                np.array([[2.0]]), lo, hi, 1, 0.1)
+    assert abs(m1[0, 0] - 0.1 * 2.0 * 30.0) < 1e-12
+    assert lr_at(1, 0.1, 0.01, 500) == 0.1 and abs(lr_at(501, 0.1, 0.01, 500) - 0.01) < 1e-15
+    assert abs(lr_at(251, 0.1, 0.01, 500) - 0.055) < 1e-15
+
+
+def test_adam_minimises_a_box_constrained_quadratic():
+    """Adam on f(theta) = (theta - c)^2 reaches c inside the box and the
+    nearest bound when c is outside."""
+    from oracle.fit import adam_box_step
+    lo = np.array([[0.5], [0.5]]); hi = np.array([[3.0], [3.0]])
+    c = np.array([[1.7], [5.0]])
+    u = np.array([[0.9], [0.1]]); m = np.zeros_like(u); v = np.zeros_like(u)
+    th = lo + u * (hi - lo)
+    for t in range(1, 3000):
+        u, m, v, th = adam_box_step(u, m, v, 2 * (th - c), lo, hi, t, 0.01)
+    assert abs(th[0, 0] - 1.7) < 5e-3 and th[1, 0] == 3.0
