@@ -210,6 +210,12 @@ typedef struct {
 idm_status idm_fit_init(idm_plan *plan, const idm_fit_state *st, const float *init_params,
                         void *stream);
 
+/* Start a fit from normalised parameters given as rows: u of vehicle i and
+ * kind p at u_rows[i*ld + p] (ld >= 5; e.g. the MLP output with ld =
+ * IDM_MLP_OUT_PAD), clamped to [0, 1]; moments and step counter reset. */
+idm_status idm_fit_init_normalized(idm_plan *plan, const idm_fit_state *st, const float *u_rows,
+                                   int32_t ld, void *stream);
+
 idm_status idm_fit_step(idm_plan *plan, const idm_fit_state *st, const double *p0,
                         const float *v_init, const idm_obs *obs, void *workspace, void *stream);
 
@@ -244,10 +250,88 @@ idm_status idm_step_graph_launch(idm_plan *plan, const idm_step_args *args, void
 idm_status idm_plan_autotune(idm_plan *plan, const idm_step_args *args, size_t workspace_bytes,
                              int32_t reps, void *stream);
 
+/* Observations from a simulated trajectory (synthetic data generation):
+ * target_out[j*N + i] = p0[i] + traj_d[(obs_first + j*obs_stride)*N + i]
+ * + noise[j*N + i] (noise nullable), FP32; observed steps must be <= n_steps. */
+idm_status idm_observe(idm_plan *plan, const float *traj_d, const double *p0, const float *noise,
+                       int32_t n_obs, int32_t obs_first, int32_t obs_stride, float *target_out,
+                       void *stream);
+
+/* Per-lane observed squared error of a trajectory: lane_loss[l] = sum over the
+ * lane's vehicles and the observed steps of (p0 + d_k - target)^2, FP64,
+ * fixed summation order. */
+idm_status idm_lane_loss(idm_plan *plan, const float *traj_d, const double *p0, const idm_obs *obs,
+                         double *lane_loss, void *stream);
+
+/* Per-lane choice between two parameter sets [5*N]: every vehicle of lane l
+ * takes params_a if loss_a[l] <= loss_b[l], else params_b (the warm start's
+ * fallback to the cold start).  chose_a [N] (nullable) records the choice. */
+idm_status idm_select_by_lane(idm_plan *plan, const double *loss_a, const double *loss_b,
+                              const float *params_a, const float *params_b, float *params_out,
+                              int32_t *chose_a, void *stream);
+
 /* Plain device-to-device copy of `bytes` (multiple of 16, 16-byte aligned
  * pointers) by a streaming kernel: the measured HBM bandwidth ceiling and the
  * byte-counter calibration reference of the benchmark.  Asynchronous. */
 idm_status idm_copy_bytes(void *dst, const void *src, size_t bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start (not in the paper, whose fit starts from fixed values,
+ * Sec. IV-A): a 150 -> 256 -> 256 -> 5 ReLU MLP maps the observed trajectory
+ * window of a vehicle to normalised IDM parameters u in [0, 1]^5 (same boxes
+ * as the fit).  BF16 MFMA GEMMs with FP32 accumulation, FP32 master weights,
+ * Adam.  Feature rows are padded to IDM_MLP_IN_PAD BF16 values and outputs
+ * to IDM_MLP_OUT_PAD FP32 columns (the first IDM_MLP_OUT are meaningful).
+ *
+ * FP32 parameter buffer (idm_mlp_param_count() floats), row-major blocks:
+ *   W1 [IN_PAD x HIDDEN], b1 [HIDDEN], W2 [HIDDEN x HIDDEN], b2 [HIDDEN],
+ *   W3 [HIDDEN x OUT_PAD], b3 [OUT_PAD]
+ * BF16 weight copies (idm_mlp_weight_bf16_count() values): W1, W2, W3 in the
+ * same layouts, back to back.  idm_mlp_sync refreshes them from the FP32
+ * weights (and zeroes the Adam moments); idm_mlp_train_step keeps them in
+ * sync after every update.
+ * ------------------------------------------------------------------------- */
+#define IDM_MLP_IN 150
+#define IDM_MLP_IN_PAD 160
+#define IDM_MLP_HIDDEN 256
+#define IDM_MLP_OUT 5
+#define IDM_MLP_OUT_PAD 16
+
+typedef struct {
+    float *params;          /* FP32 master parameters (layout above), device */
+    uint16_t *weights_bf16; /* BF16 copies of W1, W2, W3, device */
+    float *adam_m, *adam_v; /* Adam moments [param_count], device (nullable for inference) */
+    float lr, beta1, beta2, eps;
+} idm_mlp_state;
+
+int64_t idm_mlp_param_count(void);
+int64_t idm_mlp_weight_bf16_count(void);
+/* Device workspace for forward / gradients / train step on a batch of B rows. */
+size_t idm_mlp_workspace_bytes(int64_t batch);
+/* FP32 -> BF16 weight copies; zero the Adam moments if present. */
+idm_status idm_mlp_sync(const idm_mlp_state *st, void *stream);
+/* Window features X [N x IN_PAD] BF16 of every vehicle of the plan from its
+ * observed absolute positions target [n_obs x N] (observation j at step
+ * obs_first + j*obs_stride >= 1), the initial positions p0 and the lengths:
+ * per observation the offset (p_j - p0)/1000 m, the finite-difference speed
+ * /30 m/s (the first one from p0 at t = 0), and the gap to the observed leader
+ * /50 m (200 m for a lane head); 3*n_obs <= IN_PAD, zero padded. */
+idm_status idm_mlp_features(idm_plan *plan, const float *target, int32_t n_obs, int32_t obs_first,
+                            int32_t obs_stride, const double *p0, const float *length,
+                            uint16_t *X, void *stream);
+/* Y [batch x OUT_PAD] FP32 = MLP(X). */
+idm_status idm_mlp_forward(const idm_mlp_state *st, const uint16_t *X, int64_t batch, float *Y,
+                           void *workspace, void *stream);
+/* Gradients of L = mean over batch and the 5 outputs of (Y - U)^2 (U [batch x 5]
+ * FP32 normalised targets) w.r.t. every FP32 parameter, into grad_out
+ * [param_count]; loss_out (device FP64, nullable) receives L. */
+idm_status idm_mlp_gradients(const idm_mlp_state *st, const uint16_t *X, const float *U,
+                             int64_t batch, float *grad_out, double *loss_out, void *workspace,
+                             void *stream);
+/* One Adam step (step number t >= 1) on the same loss; refreshes the BF16 copies. */
+idm_status idm_mlp_train_step(const idm_mlp_state *st, const uint16_t *X, const float *U,
+                              int64_t batch, int32_t t, double *loss_out, void *workspace,
+                              void *stream);
 
 /* Thread-local description of the last error (never NULL). */
 const char *idm_last_error(void);

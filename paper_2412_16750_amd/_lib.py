@@ -57,6 +57,15 @@ class IdmFitState(ctypes.Structure):
                 ("beta1", c_float), ("beta2", c_float), ("eps", c_float)]
 
 
+class IdmMlpState(ctypes.Structure):
+    _fields_ = [("params", c_void_p), ("weights_bf16", c_void_p), ("adam_m", c_void_p),
+                ("adam_v", c_void_p), ("lr", c_float), ("beta1", c_float), ("beta2", c_float),
+                ("eps", c_float)]
+
+
+MLP_IN, MLP_IN_PAD, MLP_HIDDEN, MLP_OUT, MLP_OUT_PAD = 150, 160, 256, 5, 16
+
+
 class IdmStepArgs(ctypes.Structure):
     _fields_ = [("prm", IdmParams), ("p0", c_void_p), ("v_init", c_void_p),
                 ("traj_d", c_void_p), ("traj_v", c_void_p),
@@ -72,7 +81,10 @@ EXPORTS = ("idm_plan_create", "idm_plan_destroy", "idm_workspace_bytes", "idm_pl
            "idm_problem_check", "idm_problem_layout",
            "idm_sim_forward", "idm_sim_backward", "idm_fit_init", "idm_fit_step", "idm_fit_run",
            "idm_step_graph_launch", "idm_plan_autotune", "idm_copy_bytes", "idm_last_error",
-           "idm_version")
+           "idm_version", "idm_mlp_param_count", "idm_mlp_weight_bf16_count",
+           "idm_mlp_workspace_bytes", "idm_mlp_sync", "idm_mlp_features", "idm_mlp_forward",
+           "idm_mlp_gradients", "idm_mlp_train_step", "idm_fit_init_normalized", "idm_observe",
+           "idm_lane_loss", "idm_select_by_lane")
 
 _lib = None
 
@@ -114,6 +126,28 @@ def load() -> ctypes.CDLL:
     L.idm_plan_autotune.argtypes = [c_void_p, P(IdmStepArgs), c_size_t, c_int32, c_void_p]
     L.idm_copy_bytes.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
     L.idm_copy_bytes.restype = c_int32
+    L.idm_mlp_param_count.restype = c_int64
+    L.idm_mlp_weight_bf16_count.restype = c_int64
+    L.idm_mlp_workspace_bytes.argtypes = [c_int64]
+    L.idm_mlp_workspace_bytes.restype = c_size_t
+    L.idm_mlp_sync.argtypes = [P(IdmMlpState), c_void_p]
+    L.idm_mlp_features.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                   c_void_p, c_void_p]
+    L.idm_mlp_forward.argtypes = [P(IdmMlpState), c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
+    L.idm_mlp_gradients.argtypes = [P(IdmMlpState), c_void_p, c_void_p, c_int64, c_void_p, c_void_p,
+                                    c_void_p, c_void_p]
+    L.idm_mlp_train_step.argtypes = [P(IdmMlpState), c_void_p, c_void_p, c_int64, c_int32, c_void_p,
+                                     c_void_p, c_void_p]
+    L.idm_fit_init_normalized.argtypes = [c_void_p, P(IdmFitState), c_void_p, c_int32, c_void_p]
+    L.idm_observe.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32,
+                              c_void_p, c_void_p]
+    L.idm_lane_loss.argtypes = [c_void_p, c_void_p, c_void_p, P(IdmObs), c_void_p, c_void_p]
+    L.idm_select_by_lane.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_void_p]
+    for name in ("idm_mlp_sync", "idm_mlp_features", "idm_mlp_forward", "idm_mlp_gradients",
+                 "idm_mlp_train_step", "idm_fit_init_normalized", "idm_observe", "idm_lane_loss",
+                 "idm_select_by_lane"):
+        getattr(L, name).restype = c_int32
     L.idm_last_error.restype = ctypes.c_char_p
     L.idm_version.restype = ctypes.c_char_p
     for name in ("idm_problem_check", "idm_problem_layout", "idm_plan_create", "idm_plan_destroy", "idm_plan_get_info", "idm_sim_forward",

@@ -84,6 +84,9 @@ struct idm_plan {
     int32_t *d_gidx = nullptr;
     uint8_t *d_flags = nullptr;
     float *d_zero = nullptr;  // 64 zero floats read in place of absent upstream inputs
+    uint8_t *d_head = nullptr;  // [N] 1 = first vehicle of its lane (feature kernel)
+    int32_t *d_lane_off = nullptr;  // [L+1] lane offsets on the device
+    int32_t *d_lane_of = nullptr;   // [N] lane of every vehicle
     // graphs
     hipGraphExec_t step_exec = nullptr;
     idm_step_args step_key{};
@@ -208,6 +211,36 @@ idm_status build_layout(idm_plan *p, const Shape &sh) {
             hipFree(dg);
             hipFree(df);
             return hip_fail(e, "hipMemcpy(slot table)");
+        }
+    }
+    if (!p->d_lane_off) {
+        std::vector<int32_t> lane_of((size_t)p->pb.n_vehicles, 0);
+        for (int l = 0; l < p->pb.n_lanes; ++l)
+            for (int32_t i = p->offsets[l]; i < p->offsets[l + 1]; ++i) lane_of[(size_t)i] = l;
+        e = hipMalloc(&p->d_lane_off, p->offsets.size() * sizeof(int32_t));
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_lane_off, p->offsets.data(), p->offsets.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc(&p->d_lane_of, lane_of.size() * sizeof(int32_t));
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_lane_of, lane_of.data(), lane_of.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hipFree(dg);
+            hipFree(df);
+            return hip_fail(e, "lane tables");
+        }
+    }
+    if (!p->d_head) {
+        std::vector<uint8_t> head((size_t)p->pb.n_vehicles, 0);
+        for (int l = 0; l < p->pb.n_lanes; ++l)
+            if (p->offsets[l + 1] > p->offsets[l]) head[(size_t)p->offsets[l]] = 1;
+        e = hipMalloc(&p->d_head, head.size());
+        if (e == hipSuccess) e = hipMemcpy(p->d_head, head.data(), head.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hipFree(dg);
+            hipFree(df);
+            return hip_fail(e, "head flags");
         }
     }
     if (!p->d_zero) {
@@ -553,6 +586,14 @@ idm_status graph_stream_leave(idm_plan *p, hipStream_t caller) {
 
 }  // namespace
 
+namespace idmx {
+idm_status set_error(idm_status st, const char *msg) { return fail(st, "%s", msg); }
+const uint8_t *plan_head_flags(const idm_plan *p) { return p ? p->d_head : nullptr; }
+int64_t plan_vehicles(const idm_plan *p) { return p ? p->pb.n_vehicles : 0; }
+int32_t plan_steps(const idm_plan *p) { return p ? p->pb.n_steps : 0; }
+float plan_dt(const idm_plan *p) { return p ? p->pb.dt : 0.0f; }
+}  // namespace idmx
+
 extern "C" {
 
 const char *idm_last_error(void) { return g_err.c_str(); }
@@ -629,6 +670,9 @@ idm_status idm_plan_destroy(idm_plan *p) {
     if (p->d_gidx) hipFree(p->d_gidx);
     if (p->d_flags) hipFree(p->d_flags);
     if (p->d_zero) hipFree(p->d_zero);
+    if (p->d_head) hipFree(p->d_head);
+    if (p->d_lane_off) hipFree(p->d_lane_off);
+    if (p->d_lane_of) hipFree(p->d_lane_of);
     if (p->side) hipStreamDestroy(p->side);
     if (p->ev_in) hipEventDestroy(p->ev_in);
     if (p->ev_out) hipEventDestroy(p->ev_out);
@@ -689,6 +733,58 @@ idm_status idm_fit_init(idm_plan *p, const idm_fit_state *st, const float *init_
     AdamArgs aa = adam_args(p, st, nullptr);
     hipError_t e = launch_fit_init(aa, init_params, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fit init launch");
+    return IDM_OK;
+}
+
+idm_status idm_fit_init_normalized(idm_plan *p, const idm_fit_state *st, const float *u_rows,
+                                   int32_t ld, void *stream) {
+    if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
+    if (!u_rows || ld < 5) return fail(IDM_ERR_INVALID_ARG, "u_rows null or ld < 5");
+    if (!st || !st->u || !st->m || !st->v || !st->params || !st->step)
+        return fail(IDM_ERR_INVALID_ARG, "fit state: null pointer");
+    for (int i = 0; i < 5; ++i)
+        if (!(st->hi[i] > st->lo[i]) || !std::isfinite(st->lo[i]) || !std::isfinite(st->hi[i]))
+            return fail(IDM_ERR_INVALID_ARG, "fit state: box %d invalid", i);
+    AdamArgs aa = adam_args(p, st, nullptr);
+    hipError_t e = launch_fit_init_u(aa, u_rows, ld, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fit init launch");
+    return IDM_OK;
+}
+
+idm_status idm_observe(idm_plan *p, const float *traj_d, const double *p0, const float *noise,
+                       int32_t n_obs, int32_t obs_first, int32_t obs_stride, float *target_out,
+                       void *stream) {
+    if (!p || !traj_d || !p0 || !target_out) return fail(IDM_ERR_INVALID_ARG, "null argument");
+    idm_obs o{target_out, n_obs, obs_first, obs_stride};
+    idm_status r = check_obs(p, &o);
+    if (r != IDM_OK) return r;
+    hipError_t e = launch_observe(traj_d, p0, noise, n_obs, obs_first, obs_stride,
+                                  p->pb.n_vehicles, target_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "observe launch");
+    return IDM_OK;
+}
+
+idm_status idm_lane_loss(idm_plan *p, const float *traj_d, const double *p0, const idm_obs *obs,
+                         double *lane_loss, void *stream) {
+    if (!p || !traj_d || !p0 || !lane_loss) return fail(IDM_ERR_INVALID_ARG, "null argument");
+    if (!obs) return fail(IDM_ERR_INVALID_ARG, "obs is null");
+    idm_status r = check_obs(p, obs);
+    if (r != IDM_OK) return r;
+    hipError_t e = launch_lane_loss(traj_d, p0, obs->target, obs->n_obs, obs->obs_first,
+                                    obs->obs_stride, p->pb.n_vehicles, p->d_lane_off,
+                                    p->pb.n_lanes, lane_loss, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lane loss launch");
+    return IDM_OK;
+}
+
+idm_status idm_select_by_lane(idm_plan *p, const double *loss_a, const double *loss_b,
+                              const float *params_a, const float *params_b, float *params_out,
+                              int32_t *chose_a, void *stream) {
+    if (!p || !loss_a || !loss_b || !params_a || !params_b || !params_out)
+        return fail(IDM_ERR_INVALID_ARG, "null argument");
+    hipError_t e = launch_select_by_lane(loss_a, loss_b, p->d_lane_of, params_a, params_b,
+                                         p->pb.n_vehicles, params_out, chose_a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "select launch");
     return IDM_OK;
 }
 

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
+
+#include "idm.h"
 #include <stdint.h>
 
 namespace idmx {
@@ -75,5 +77,21 @@ hipError_t launch_adam(const AdamArgs &a, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, int64_t n16, int grid, hipStream_t s);
 hipError_t launch_params_from_u(const AdamArgs &a, hipStream_t s);
 hipError_t launch_fit_init(const AdamArgs &a, const float *init, hipStream_t s);
+hipError_t launch_fit_init_u(const AdamArgs &a, const float *u_rows, int ld, hipStream_t s);
+hipError_t launch_observe(const float *traj_d, const double *p0, const float *noise, int n_obs,
+                          int obs_first, int obs_stride, int64_t N, float *out, hipStream_t s);
+hipError_t launch_lane_loss(const float *traj_d, const double *p0, const float *target, int n_obs,
+                            int obs_first, int obs_stride, int64_t N, const int32_t *lane_off,
+                            int n_lanes, double *out, hipStream_t s);
+hipError_t launch_select_by_lane(const double *la, const double *lb, const int32_t *lane_of,
+                                 const float *pa, const float *pb, int64_t N, float *out,
+                                 int32_t *chose_a, hipStream_t s);
+
+// Shared error reporting (idm_last_error) and plan accessors for the MLP code.
+idm_status set_error(idm_status st, const char *msg);
+const uint8_t *plan_head_flags(const idm_plan *p);  // device [N]: 1 = lane head
+int64_t plan_vehicles(const idm_plan *p);
+int32_t plan_steps(const idm_plan *p);
+float plan_dt(const idm_plan *p);
 
 }  // namespace idmx

@@ -667,6 +667,72 @@ __global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uin
         dst[i] = src[i];
 }
 
+// Observed positions from a displacement trajectory: out[j][i] =
+// p0[i] + d[obs_first + j*obs_stride][i] (+ noise[j][i]), FP32.
+__global__ __launch_bounds__(256) void k_observe(const float *traj_d, const double *p0,
+                                                 const float *noise, int n_obs, int obs_first,
+                                                 int obs_stride, int64_t N, float *out) {
+    const int64_t total = (int64_t)n_obs * N;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = idx / N, i = idx - j * N;
+        double p = p0[i] + (double)traj_d[(obs_first + j * obs_stride) * N + i];
+        if (noise) p += (double)noise[idx];
+        out[idx] = (float)p;
+    }
+}
+
+// Sum over the vehicles of one lane and the observed steps of
+// (p0 + d_k - target)^2, FP64, one work-group per lane, fixed order.
+__global__ __launch_bounds__(256) void k_lane_loss(const float *traj_d, const double *p0,
+                                                   const float *target, int n_obs, int obs_first,
+                                                   int obs_stride, int64_t N,
+                                                   const int32_t *lane_off, double *out) {
+    __shared__ double red[5];
+    const int l = blockIdx.x;
+    const int lo = lane_off[l], hi = lane_off[l + 1];
+    double s = 0.0;
+    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x)
+        for (int j = 0; j < n_obs; ++j) {
+            const int64_t k = obs_first + (int64_t)j * obs_stride;
+            double r = p0[i] + (double)traj_d[k * N + i] - (double)target[(int64_t)j * N + i];
+            s = fma(r, r, s);
+        }
+    double tot = block_sum(s, red);
+    if (threadIdx.x == 0) out[l] = tot;
+}
+
+// out = lane's loss under A <= under B ? A : B, per vehicle, all 5 parameter blocks.
+__global__ __launch_bounds__(256) void k_select_by_lane(const double *loss_a, const double *loss_b,
+                                                        const int32_t *lane_of, const float *pa,
+                                                        const float *pb, int64_t N, float *out,
+                                                        int32_t *chose_a) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = lane_of[i];
+        const bool a = loss_a[l] <= loss_b[l];
+        for (int p = 0; p < 5; ++p) out[p * N + i] = a ? pa[p * N + i] : pb[p * N + i];
+        if (chose_a) chose_a[i] = a ? 1 : 0;
+    }
+}
+
+// Normalised parameters from a row-major [N][ld] source (first 5 columns),
+// clamped to [0, 1], into the fit state (u, zero moments, step 0, params).
+__global__ __launch_bounds__(256) void k_fit_init_u(AdamArgs A, const float *u_rows, int ld) {
+    const int64_t total = 5 * A.n;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int p = (int)(idx / A.n);
+        const int64_t i = idx - (int64_t)p * A.n;
+        const float u = fminf(fmaxf(u_rows[i * ld + p], 0.0f), 1.0f);
+        A.u[idx] = u;
+        A.m[idx] = 0.0f;
+        A.v[idx] = 0.0f;
+        A.params[idx] = A.lo[p] + u * (A.hi[p] - A.lo[p]);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *A.step_rw = 0;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- dispatch
@@ -756,6 +822,34 @@ hipError_t launch_adam(const AdamArgs &a, hipStream_t s) {
 
 hipError_t launch_fit_init(const AdamArgs &a, const float *init, hipStream_t s) {
     hipLaunchKernelGGL(k_fit_init, dim3(elementwise_grid(5 * a.n)), dim3(256), 0, s, a, init);
+    return hipGetLastError();
+}
+
+hipError_t launch_observe(const float *traj_d, const double *p0, const float *noise, int n_obs,
+                          int obs_first, int obs_stride, int64_t N, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_observe, dim3(elementwise_grid((int64_t)n_obs * N)), dim3(256), 0, s, traj_d,
+                       p0, noise, n_obs, obs_first, obs_stride, N, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_lane_loss(const float *traj_d, const double *p0, const float *target, int n_obs,
+                            int obs_first, int obs_stride, int64_t N, const int32_t *lane_off,
+                            int n_lanes, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_lane_loss, dim3(n_lanes), dim3(256), 0, s, traj_d, p0, target, n_obs,
+                       obs_first, obs_stride, N, lane_off, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_by_lane(const double *la, const double *lb, const int32_t *lane_of,
+                                 const float *pa, const float *pb, int64_t N, float *out,
+                                 int32_t *chose_a, hipStream_t s) {
+    hipLaunchKernelGGL(k_select_by_lane, dim3(elementwise_grid(N)), dim3(256), 0, s, la, lb, lane_of,
+                       pa, pb, N, out, chose_a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fit_init_u(const AdamArgs &a, const float *u_rows, int ld, hipStream_t s) {
+    hipLaunchKernelGGL(k_fit_init_u, dim3(elementwise_grid(5 * a.n)), dim3(256), 0, s, a, u_rows, ld);
     return hipGetLastError();
 }
 

@@ -1,0 +1,499 @@
+// Learned warm start for the trajectory fit: a 150 -> 256 -> 256 -> 5 ReLU MLP
+// that maps an observed trajectory window to normalised IDM parameters.
+// Hand-written BF16 MFMA GEMMs (v_mfma_f32_16x16x16_bf16, FP32 accumulate)
+// for training and inference on gfx950, fused bias / ReLU / ReLU-mask
+// epilogues, deterministic split-K for the weight gradients, Adam on FP32
+// master weights with BF16 copies, and the window-feature kernel.
+//
+// BF16 rounding points (mirrored by the CPU reference): the features X, the
+// weight copies W1..W3, the hidden activations H1, H2 and the back-propagated
+// gradients dY, dH2, dH1 are rounded to nearest-even BF16; every product is
+// accumulated in FP32; biases, outputs Y and weight gradients stay FP32.
+#include "idm.h"
+#include "idm_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+namespace idmx {
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint16_t f2bf(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+struct Gemm {
+    // C[m][n] = sum_k A[m][k] B[k][n]; element strides allow transposed operands
+    const uint16_t *A;
+    int64_t a_rs, a_cs;
+    const uint16_t *B;
+    int64_t b_rs, b_cs;
+    int M, N, K;
+    int k_chunk;             // split-K: block z handles k in [z*k_chunk, (z+1)*k_chunk)
+    const float *bias;       // [N] or null
+    const uint16_t *mask;    // ReLU mask source (value > 0 keeps) or null
+    int64_t mask_rs;
+    int relu;
+    float *C32;              // FP32 output (split-K: partial slab z at C32 + z*M*c32_rs)
+    int64_t c32_rs;
+    uint16_t *C16;           // BF16 output or null
+    int64_t c16_rs;
+};
+
+// 256 threads = 4 waves; block tile 64 x 64; each wave 32 x 32 = 2 x 2 MFMA
+// 16x16x16 tiles.  MFMA operand layout (16x16x16 bf16): lane l holds
+// A[l % 16][4 (l / 16) + e] and B[4 (l / 16) + e][l % 16], e = 0..3, and the
+// result D[4 (l / 16) + e][l % 16].
+__global__ __launch_bounds__(256) void k_gemm_bf16(Gemm g) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int bm = blockIdx.y * 64 + (wave >> 1) * 32;
+    const int bn = blockIdx.x * 64 + (wave & 1) * 32;
+    const int kb = blockIdx.z * g.k_chunk;
+    const int ke = min(g.K, kb + g.k_chunk);
+    const int li = lane & 15, lq = lane >> 4;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = kb; k0 < ke; k0 += 16) {
+        bf16x4 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int m = bm + i * 16 + li;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = k0 + 4 * lq + e;
+                a[i][e] = (m < g.M && k < ke) ? (short)g.A[(int64_t)m * g.a_rs + (int64_t)k * g.a_cs] : (short)0;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = bn + j * 16 + li;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = k0 + 4 * lq + e;
+                b[j][e] = (n < g.N && k < ke) ? (short)g.B[(int64_t)k * g.b_rs + (int64_t)n * g.b_cs] : (short)0;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    float *C32 = g.C32 ? g.C32 + (int64_t)blockIdx.z * g.M * g.c32_rs : nullptr;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = bm + i * 16 + 4 * lq + e;
+                const int n = bn + j * 16 + li;
+                if (m >= g.M || n >= g.N) continue;
+                float v = acc[i][j][e];
+                if (g.bias) v += g.bias[n];
+                if (g.mask && !(bf2f(g.mask[(int64_t)m * g.mask_rs + n]) > 0.0f)) v = 0.0f;
+                if (g.relu) v = fmaxf(v, 0.0f);
+                if (C32) C32[(int64_t)m * g.c32_rs + n] = v;
+                if (g.C16) g.C16[(int64_t)m * g.c16_rs + n] = f2bf(v);
+            }
+}
+
+// Fixed-order sum of split-K partial slabs: out[i] = sum_z part[z][i].
+__global__ __launch_bounds__(256) void k_sum_slabs(const float *part, int slabs, int64_t n,
+                                                   float *out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int z = 0; z < slabs; ++z) s += part[(int64_t)z * n + i];
+        out[i] = s;
+    }
+}
+
+// Column sums of a BF16 [rows x cols] matrix (bias gradients), fixed order.
+__global__ __launch_bounds__(256) void k_colsum_bf16(const uint16_t *X, int rows, int cols,
+                                                     int64_t rs, float *out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    float s = 0.0f;
+    for (int r = 0; r < rows; ++r) s += bf2f(X[(int64_t)r * rs + c]);
+    out[c] = s;
+}
+
+// dY = 2 (Y - U) / (B * n_out) on the first n_out columns (BF16, padding 0),
+// and per-block FP64 partial sums of the squared error.
+__global__ __launch_bounds__(256) void k_mse_grad(const float *Y, int64_t y_rs, const float *U,
+                                                  int B, int n_out, int n_pad, uint16_t *dY,
+                                                  float *dYf, double *part) {
+    __shared__ double red[4];
+    const int64_t total = (int64_t)B * n_pad;
+    double se = 0.0;
+    const float scale = 2.0f / ((float)B * (float)n_out);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(i / n_pad), c = (int)(i % n_pad);
+        float d = 0.0f;
+        if (c < n_out) {
+            float r = Y[(int64_t)b * y_rs + c] - U[(int64_t)b * n_out + c];
+            se += (double)r * (double)r;
+            d = scale * r;
+        }
+        dY[i] = f2bf(d);
+        if (dYf) dYf[i] = d;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) se += __shfl_down(se, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = se;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(64) void k_sum_f64(const double *part, int n, double scale,
+                                                double *out) {
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += part[i];
+        *out = s * scale;
+    }
+}
+
+// Adam on the FP32 master parameters, then BF16 copies of the weights.
+struct MlpAdam {
+    float *p, *m, *v;
+    const float *g;
+    int64_t n;
+    int32_t t;        // step number of this update (1-based)
+    float lr, beta1, beta2, eps;
+    uint16_t *w16;    // BF16 copies of the weight blocks
+    int64_t w1_off, w1_n, w2_off, w2_n, w3_off, w3_n;  // ranges in p / w16 offsets
+    int64_t w16_w2, w16_w3;
+};
+
+__global__ __launch_bounds__(256) void k_mlp_adam(MlpAdam A) {
+    const float bc1 = 1.0f - powf(A.beta1, (float)A.t);
+    const float bc2 = 1.0f - powf(A.beta2, (float)A.t);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float g = A.g[i];
+        const float m = A.beta1 * A.m[i] + (1.0f - A.beta1) * g;
+        const float v = A.beta2 * A.v[i] + (1.0f - A.beta2) * g * g;
+        A.m[i] = m;
+        A.v[i] = v;
+        const float p = A.p[i] - A.lr * (m / bc1) / (sqrtf(v / bc2) + A.eps);
+        A.p[i] = p;
+        if (i >= A.w1_off && i < A.w1_off + A.w1_n) A.w16[i - A.w1_off] = f2bf(p);
+        else if (i >= A.w2_off && i < A.w2_off + A.w2_n) A.w16[A.w16_w2 + (i - A.w2_off)] = f2bf(p);
+        else if (i >= A.w3_off && i < A.w3_off + A.w3_n) A.w16[A.w16_w3 + (i - A.w3_off)] = f2bf(p);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_to_bf16(const float *x, int64_t n, uint16_t *y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = f2bf(x[i]);
+}
+
+__global__ __launch_bounds__(256) void k_fill_f32(float *x, int64_t n, float v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+// Window features of one vehicle from its observed positions (observation j
+// at time t_j = (obs_first + j*obs_stride)*dt), its leader's observations and
+// its initial state; row layout [n_feat_pad] BF16:
+//   [0, n_obs)         (p_j - p0) / 1000 m
+//   [n_obs, 2 n_obs)   (p_j - p_{j-1}) / (t_j - t_{j-1}) / 30 m/s  (p_{-1} = p0 at t = 0)
+//   [2 n_obs, 3 n_obs) (p_h,j - p_j - length_h) / 50 m, 200 m for a lane head
+//   rest               0
+__global__ __launch_bounds__(256) void k_features(const float *target, int n_obs, int obs_first,
+                                                  int obs_stride, float dt, const double *p0,
+                                                  const float *length, const uint8_t *is_head,
+                                                  int64_t N, int n_feat_pad, uint16_t *X) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const bool head = is_head[i] != 0;
+    const double p0i = p0[i];
+    const float lh = head ? 0.0f : length[i - 1];
+    uint16_t *row = X + i * n_feat_pad;
+    double prev = p0i;
+    float tprev = 0.0f;
+    for (int j = 0; j < n_obs; ++j) {
+        const double pj = (double)target[(int64_t)j * N + i];
+        const float tj = (float)(obs_first + j * obs_stride) * dt;
+        row[j] = f2bf((float)((pj - p0i) / 1000.0));
+        row[n_obs + j] = f2bf((float)((pj - prev) / (double)(tj - tprev)) / 30.0f);
+        float gap = 200.0f;
+        if (!head) gap = (float)((double)target[(int64_t)j * N + i - 1] - pj - (double)lh);
+        row[2 * n_obs + j] = f2bf(gap / 50.0f);
+        prev = pj;
+        tprev = tj;
+    }
+    for (int c = 3 * n_obs; c < n_feat_pad; ++c) row[c] = 0;
+}
+
+int grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const Gemm &g, int splits, hipStream_t s);
+
+}  // namespace idmx
+
+using namespace idmx;
+
+// ---------------------------------------------------------------- C ABI
+
+namespace {
+
+idm_status mfail(idm_status st, const char *msg) { return idmx::set_error(st, msg); }
+
+constexpr int H = IDM_MLP_HIDDEN, FIN = IDM_MLP_IN_PAD, FOUT = IDM_MLP_OUT_PAD;
+
+// FP32 parameter blocks: W1 [FIN x H], b1 [H], W2 [H x H], b2 [H], W3 [H x FOUT], b3 [FOUT]
+constexpr int64_t OFF_W1 = 0, N_W1 = (int64_t)FIN * H;
+constexpr int64_t OFF_B1 = OFF_W1 + N_W1, N_B1 = H;
+constexpr int64_t OFF_W2 = OFF_B1 + N_B1, N_W2 = (int64_t)H * H;
+constexpr int64_t OFF_B2 = OFF_W2 + N_W2, N_B2 = H;
+constexpr int64_t OFF_W3 = OFF_B2 + N_B2, N_W3 = (int64_t)H * FOUT;
+constexpr int64_t OFF_B3 = OFF_W3 + N_W3, N_B3 = FOUT;
+constexpr int64_t N_PARAMS = OFF_B3 + N_B3;
+// BF16 copies: W1, W2, W3 back to back
+constexpr int64_t H16_W1 = 0, H16_W2 = N_W1, H16_W3 = N_W1 + N_W2, N_W16 = N_W1 + N_W2 + N_W3;
+
+constexpr int SPLIT_ROWS = 512;  // batch rows per split-K slab of a weight gradient
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+struct MlpWs {
+    size_t h1, h2, y, dy, dyf, dh2, dh1, grad, part, lpart, total;
+};
+
+MlpWs mlp_ws(int64_t B) {
+    MlpWs w;
+    size_t o = 0;
+    w.h1 = o; o += al(2 * B * H);
+    w.h2 = o; o += al(2 * B * H);
+    w.y = o; o += al(4 * B * FOUT);
+    w.dy = o; o += al(2 * B * FOUT);
+    w.dyf = o; o += al(4 * B * FOUT);
+    w.dh2 = o; o += al(2 * B * H);
+    w.dh1 = o; o += al(2 * B * H);
+    w.grad = o; o += al(4 * N_PARAMS);
+    const int64_t slabs = (B + SPLIT_ROWS - 1) / SPLIT_ROWS;
+    w.part = o; o += al(4 * slabs * (int64_t)H * H);
+    w.lpart = o; o += al(8 * 8192);
+    w.total = o;
+    return w;
+}
+
+Gemm gemm(const uint16_t *A, int64_t a_rs, int64_t a_cs, const uint16_t *B, int64_t b_rs,
+          int64_t b_cs, int M, int N, int K) {
+    Gemm g;
+    memset(&g, 0, sizeof g);
+    g.A = A; g.a_rs = a_rs; g.a_cs = a_cs;
+    g.B = B; g.b_rs = b_rs; g.b_cs = b_cs;
+    g.M = M; g.N = N; g.K = K;
+    g.k_chunk = ((K + 15) / 16) * 16;
+    return g;
+}
+
+// Weight gradient dW = Act^T dZ over the batch: split-K slabs + fixed-order sum.
+hipError_t weight_grad(const uint16_t *act, int64_t act_rs, int rows, int in, const uint16_t *dz,
+                       int64_t dz_rs, int out, float *part, float *dst, hipStream_t s) {
+    Gemm g = gemm(act, 1, act_rs, dz, dz_rs, 1, in, out, rows);
+    g.k_chunk = SPLIT_ROWS;
+    const int slabs = (rows + SPLIT_ROWS - 1) / SPLIT_ROWS;
+    g.C32 = part;
+    g.c32_rs = out;
+    hipError_t e = launch_gemm(g, slabs, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_slabs, dim3(grid_for((int64_t)in * out)), dim3(256), 0, s, part, slabs,
+                       (int64_t)in * out, dst);
+    return hipGetLastError();
+}
+
+hipError_t mlp_forward(const idm_mlp_state *st, const uint16_t *X, int64_t B, const MlpWs &w,
+                       char *ws, float *Y, hipStream_t s) {
+    const float *P = st->params;
+    const uint16_t *W16 = st->weights_bf16;
+    uint16_t *H1 = (uint16_t *)(ws + w.h1), *H2 = (uint16_t *)(ws + w.h2);
+    Gemm g1 = gemm(X, FIN, 1, W16 + H16_W1, H, 1, (int)B, H, FIN);
+    g1.bias = P + OFF_B1; g1.relu = 1; g1.C16 = H1; g1.c16_rs = H;
+    hipError_t e = launch_gemm(g1, 1, s);
+    if (e != hipSuccess) return e;
+    Gemm g2 = gemm(H1, H, 1, W16 + H16_W2, H, 1, (int)B, H, H);
+    g2.bias = P + OFF_B2; g2.relu = 1; g2.C16 = H2; g2.c16_rs = H;
+    e = launch_gemm(g2, 1, s);
+    if (e != hipSuccess) return e;
+    Gemm g3 = gemm(H2, H, 1, W16 + H16_W3, FOUT, 1, (int)B, FOUT, H);
+    g3.bias = P + OFF_B3; g3.C32 = Y; g3.c32_rs = FOUT;
+    return launch_gemm(g3, 1, s);
+}
+
+// Forward + MSE + backward: gradients of every FP32 parameter into G.
+hipError_t mlp_backward(const idm_mlp_state *st, const uint16_t *X, const float *U, int64_t batch,
+                        char *ws, float *G, double *loss_out, hipStream_t s) {
+    const MlpWs w = mlp_ws(batch);
+    const int B = (int)batch;
+    float *Y = (float *)(ws + w.y);
+    hipError_t e = mlp_forward(st, X, batch, w, ws, Y, s);
+    if (e != hipSuccess) return e;
+    uint16_t *H1 = (uint16_t *)(ws + w.h1), *H2 = (uint16_t *)(ws + w.h2);
+    uint16_t *dY = (uint16_t *)(ws + w.dy), *dH2 = (uint16_t *)(ws + w.dh2);
+    uint16_t *dH1 = (uint16_t *)(ws + w.dh1);
+    float *part = (float *)(ws + w.part);
+    double *lpart = (double *)(ws + w.lpart);
+    const int lgrid = std::min(1024, grid_for((int64_t)B * FOUT));
+    hipLaunchKernelGGL(k_mse_grad, dim3(lgrid), dim3(256), 0, s, Y, (int64_t)FOUT, U, B,
+                       IDM_MLP_OUT, FOUT, dY, (float *)(ws + w.dyf), lpart);
+    if (loss_out)
+        hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(64), 0, s, lpart, lgrid,
+                           1.0 / ((double)B * IDM_MLP_OUT), loss_out);
+    const uint16_t *W16 = st->weights_bf16;
+    // layer 3: dW3 = H2^T dY, db3 = colsum(dY), dH2 = (dY W3^T) * [H2 > 0]
+    e = weight_grad(H2, H, B, H, dY, FOUT, FOUT, part, G + OFF_W3, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_colsum_bf16, dim3(1), dim3(256), 0, s, dY, B, FOUT, (int64_t)FOUT, G + OFF_B3);
+    Gemm g3 = gemm(dY, FOUT, 1, W16 + H16_W3, 1, FOUT, B, H, FOUT);
+    g3.mask = H2; g3.mask_rs = H; g3.C16 = dH2; g3.c16_rs = H;
+    e = launch_gemm(g3, 1, s);
+    if (e != hipSuccess) return e;
+    // layer 2: dW2 = H1^T dH2, db2, dH1 = (dH2 W2^T) * [H1 > 0]
+    e = weight_grad(H1, H, B, H, dH2, H, H, part, G + OFF_W2, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_colsum_bf16, dim3(1), dim3(256), 0, s, dH2, B, H, (int64_t)H, G + OFF_B2);
+    Gemm g2 = gemm(dH2, H, 1, W16 + H16_W2, 1, H, B, H, H);
+    g2.mask = H1; g2.mask_rs = H; g2.C16 = dH1; g2.c16_rs = H;
+    e = launch_gemm(g2, 1, s);
+    if (e != hipSuccess) return e;
+    // layer 1: dW1 = X^T dH1, db1
+    e = weight_grad(X, FIN, B, FIN, dH1, H, H, part, G + OFF_W1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_colsum_bf16, dim3(1), dim3(256), 0, s, dH1, B, H, (int64_t)H, G + OFF_B1);
+    return hipGetLastError();
+}
+
+idm_status check_state(const idm_mlp_state *st) {
+    if (!st || !st->params || !st->weights_bf16) return mfail(IDM_ERR_INVALID_ARG, "mlp state: null pointer");
+    return IDM_OK;
+}
+
+}  // namespace
+
+namespace idmx {
+hipError_t launch_gemm(const Gemm &g, int splits, hipStream_t s) {
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, splits);
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+}  // namespace idmx
+
+extern "C" {
+
+int64_t idm_mlp_param_count(void) { return N_PARAMS; }
+int64_t idm_mlp_weight_bf16_count(void) { return N_W16; }
+
+size_t idm_mlp_workspace_bytes(int64_t batch) { return batch > 0 ? mlp_ws(batch).total : 0; }
+
+idm_status idm_mlp_sync(const idm_mlp_state *st, void *stream) {
+    idm_status r = check_state(st);
+    if (r != IDM_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(N_W1)), dim3(256), 0, s, st->params + OFF_W1, N_W1,
+                       st->weights_bf16 + H16_W1);
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(N_W2)), dim3(256), 0, s, st->params + OFF_W2, N_W2,
+                       st->weights_bf16 + H16_W2);
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(N_W3)), dim3(256), 0, s, st->params + OFF_W3, N_W3,
+                       st->weights_bf16 + H16_W3);
+    if (st->adam_m && st->adam_v) {
+        hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(N_PARAMS)), dim3(256), 0, s, st->adam_m, N_PARAMS, 0.0f);
+        hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(N_PARAMS)), dim3(256), 0, s, st->adam_v, N_PARAMS, 0.0f);
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? IDM_OK : mfail(IDM_ERR_HIP, hipGetErrorString(e));
+}
+
+idm_status idm_mlp_features(idm_plan *plan, const float *target, int32_t n_obs, int32_t obs_first,
+                            int32_t obs_stride, const double *p0, const float *length,
+                            uint16_t *X, void *stream) {
+    if (!plan || !target || !p0 || !length || !X) return mfail(IDM_ERR_INVALID_ARG, "null argument");
+    if (n_obs < 1 || 3 * n_obs > FIN || obs_first < 1 || obs_stride < 1)
+        return mfail(IDM_ERR_INVALID_ARG, "features: need 1 <= n_obs <= 53, obs_first >= 1, obs_stride >= 1");
+    const uint8_t *head = idmx::plan_head_flags(plan);
+    const int64_t N = idmx::plan_vehicles(plan);
+    if (!head) return mfail(IDM_ERR_INVALID_ARG, "plan has no head flags");
+    if ((int64_t)obs_first + (int64_t)(n_obs - 1) * obs_stride > idmx::plan_steps(plan))
+        return mfail(IDM_ERR_INVALID_ARG, "features: last observed step beyond n_steps");
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       target, n_obs, obs_first, obs_stride, idmx::plan_dt(plan), p0, length, head, N,
+                       FIN, X);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? IDM_OK : mfail(IDM_ERR_HIP, hipGetErrorString(e));
+}
+
+idm_status idm_mlp_forward(const idm_mlp_state *st, const uint16_t *X, int64_t batch, float *Y,
+                           void *workspace, void *stream) {
+    idm_status r = check_state(st);
+    if (r != IDM_OK) return r;
+    if (!X || !Y || !workspace || batch < 1 || batch > (1 << 30))
+        return mfail(IDM_ERR_INVALID_ARG, "mlp forward: bad arguments");
+    MlpWs w = mlp_ws(batch);
+    hipError_t e = mlp_forward(st, X, batch, w, (char *)workspace, Y, (hipStream_t)stream);
+    return e == hipSuccess ? IDM_OK : mfail(IDM_ERR_HIP, hipGetErrorString(e));
+}
+
+idm_status idm_mlp_gradients(const idm_mlp_state *st, const uint16_t *X, const float *U,
+                             int64_t batch, float *grad_out, double *loss_out, void *workspace,
+                             void *stream) {
+    idm_status r = check_state(st);
+    if (r != IDM_OK) return r;
+    if (!X || !U || !workspace || !grad_out || batch < 1 || batch > (1 << 30))
+        return mfail(IDM_ERR_INVALID_ARG, "mlp gradients: bad arguments");
+    hipError_t e = mlp_backward(st, X, U, batch, (char *)workspace, grad_out, loss_out,
+                                (hipStream_t)stream);
+    return e == hipSuccess ? IDM_OK : mfail(IDM_ERR_HIP, hipGetErrorString(e));
+}
+
+idm_status idm_mlp_train_step(const idm_mlp_state *st, const uint16_t *X, const float *U,
+                              int64_t batch, int32_t t, double *loss_out, void *workspace,
+                              void *stream) {
+    idm_status r = check_state(st);
+    if (r != IDM_OK) return r;
+    if (!st->adam_m || !st->adam_v) return mfail(IDM_ERR_INVALID_ARG, "mlp state: no Adam moments");
+    if (!X || !U || !workspace || batch < 1 || batch > (1 << 30) || t < 1)
+        return mfail(IDM_ERR_INVALID_ARG, "mlp train step: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    float *G = (float *)(ws + mlp_ws(batch).grad);
+    hipError_t e = mlp_backward(st, X, U, batch, ws, G, loss_out, s);
+    if (e == hipSuccess) {
+        MlpAdam A;
+        A.p = st->params; A.m = st->adam_m; A.v = st->adam_v; A.g = G; A.n = N_PARAMS;
+        A.t = t;
+        A.lr = st->lr; A.beta1 = st->beta1; A.beta2 = st->beta2; A.eps = st->eps;
+        A.w16 = st->weights_bf16;
+        A.w1_off = OFF_W1; A.w1_n = N_W1; A.w2_off = OFF_W2; A.w2_n = N_W2; A.w3_off = OFF_W3; A.w3_n = N_W3;
+        A.w16_w2 = H16_W2; A.w16_w3 = H16_W3;
+        hipLaunchKernelGGL(k_mlp_adam, dim3(grid_for(N_PARAMS)), dim3(256), 0, s, A);
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? IDM_OK : mfail(IDM_ERR_HIP, hipGetErrorString(e));
+}
+
+}  // extern "C"

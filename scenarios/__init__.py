@@ -241,3 +241,39 @@ def subset_lanes(sc: Scenario, lanes) -> Scenario:
                     n_steps=sc.n_steps, dt=sc.dt, delta=sc.delta, a_min=sc.a_min,
                     gap_floor=sc.gap_floor, mode=sc.mode, ckpt_every=sc.ckpt_every,
                     extra=dict(sc.extra, vehicle_index=idx))
+
+
+# ---------------------------------------------------------------- warm-start MLP
+
+MLP_IN, MLP_IN_PAD, MLP_HIDDEN, MLP_OUT, MLP_OUT_PAD = 150, 160, 256, 5, 16
+
+
+def mlp_init_params(seed: int) -> np.ndarray:
+    """Seeded Kaiming-uniform draw (bound sqrt(6 / fan_in)) of the MLP's FP32
+    parameter vector in the layout W1 [160 x 256], b1 [256], W2 [256 x 256],
+    b2 [256], W3 [256 x 16], b3 [16]; padding rows/columns and biases are 0."""
+    rng = np.random.default_rng(seed)
+    W1 = np.zeros((MLP_IN_PAD, MLP_HIDDEN))
+    W1[:MLP_IN] = rng.uniform(-1, 1, (MLP_IN, MLP_HIDDEN)) * np.sqrt(6.0 / MLP_IN)
+    W2 = rng.uniform(-1, 1, (MLP_HIDDEN, MLP_HIDDEN)) * np.sqrt(6.0 / MLP_HIDDEN)
+    W3 = np.zeros((MLP_HIDDEN, MLP_OUT_PAD))
+    W3[:, :MLP_OUT] = rng.uniform(-1, 1, (MLP_HIDDEN, MLP_OUT)) * np.sqrt(6.0 / MLP_HIDDEN)
+    parts = [W1, np.zeros(MLP_HIDDEN), W2, np.zeros(MLP_HIDDEN), W3, np.zeros(MLP_OUT_PAD)]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def normalized_params(params: Dict[str, np.ndarray]) -> np.ndarray:
+    """[N, 5] FP32 targets u = (theta - lo) / (hi - lo) in the fit boxes."""
+    cols = [(np.asarray(params[k], np.float64) - FIT_BOXES[k][0]) / (FIT_BOXES[k][1] - FIT_BOXES[k][0])
+            for k in PARAM_NAMES]
+    return np.ascontiguousarray(np.stack(cols, axis=1).astype(np.float32))
+
+
+def warm_training(n_lanes: int = 1000, lane_len: int = 1000, n_steps: int = 500,
+                  obs_every: int = 10, **kw) -> Scenario:
+    """Workload 5: training pairs for the warm start, drawn like workload 4 from
+    independent seeds (1000 lanes x 1000 vehicles = 1M pairs by default)."""
+    sc = make_scenario("warm", uniform_lanes(n_lanes, lane_len), n_steps, 5, **kw)
+    sc.extra["obs_first"] = obs_every
+    sc.extra["obs_stride"] = obs_every
+    return sc

@@ -461,3 +461,52 @@ def test_adam_minimises_a_box_constrained_quadratic():
     for t in range(1, 3000):
         u, m, v, th = adam_box_step(u, m, v, 2 * (th - c), lo, hi, t, 0.01)
     assert abs(th[0, 0] - 1.7) < 5e-3 and th[1, 0] == 3.0
+
+
+# ---------------------------------------------------------------- warm-start MLP
+
+def test_bf16_rounding_matches_torch():
+    """The oracle's BF16 rounding (nearest, ties to even) equals torch's
+    float32 -> bfloat16 conversion, including exact ties."""
+    import torch
+    from oracle.mlp import bf16
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.normal(0, 10, 20000), rng.normal(0, 1e-3, 1000),
+                        np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -(1.0 + 2 ** -8), 0.0, -0.0])])
+    x32 = x.astype(np.float32)
+    ref = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(bf16(x32), ref)
+
+
+def test_mlp_gradient_matches_central_differences():
+    """FP64 network (no BF16 rounding): the hand-written backward against
+    central differences on 60 random parameters, every block included."""
+    from oracle import mlp
+    import scenarios
+    rng = np.random.default_rng(1)
+    theta = scenarios.mlp_init_params(3).astype(np.float64)
+    theta += rng.normal(0, 0.05, theta.shape)  # non-zero biases and padding
+    X = rng.normal(0, 1, (12, mlp.IN_PAD))
+    U = rng.uniform(0, 1, (12, mlp.OUT))
+    L, g = mlp.loss_and_grad(theta, X, U, mirror=False)
+    sizes = np.cumsum([0] + [int(np.prod(s)) for _, s in mlp.SHAPES])
+    idx = np.concatenate([rng.integers(sizes[b], sizes[b + 1], 10) for b in range(6)])
+    for i in idx:
+        h = 1e-6
+        tp = theta.copy(); tp[i] += h
+        tm = theta.copy(); tm[i] -= h
+        fd = (mlp.loss_and_grad(tp, X, U, False)[0] - mlp.loss_and_grad(tm, X, U, False)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_mlp_bf16_mirror_is_close_to_fp64():
+    from oracle import mlp
+    import scenarios
+    rng = np.random.default_rng(2)
+    theta = scenarios.mlp_init_params(4).astype(np.float64)
+    X = rng.normal(0, 1, (64, mlp.IN_PAD)); X[:, mlp.IN:] = 0
+    U = rng.uniform(0, 1, (64, mlp.OUT))
+    La, ga = mlp.loss_and_grad(theta, X, U, mirror=True)
+    Lb, gb = mlp.loss_and_grad(theta, X, U, mirror=False)
+    assert abs(La - Lb) < 2e-2 * Lb
+    assert np.linalg.norm(ga - gb) < 5e-2 * np.linalg.norm(gb)
