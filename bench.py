@@ -32,13 +32,18 @@ if ROOT not in sys.path:
 # mul, max, exp2, log2, rcp = 1), counted from the kernels' formulas; derived
 # term by term in the design doc.
 FLOP_FWD = 40
-FLOP_BWD = 147
+FLOP_BWD = 130
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA) with non-packed FP32.
 PEAK_FP32_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBPS = 8000.0
 # Paper, Fig. 1 / Sec. V-A: < 30 ms per step for 2M vehicles in each of the
 # forward and backward passes (Xeon W-2255 x16 threads or RTX A5000).
 PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
+# HBM bytes of one backward launch on this workload from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE (scaled by the copy-kernel calibration, 2.000 and 1.000), valid
+# only for the kernel source they were taken with (sha256 of idm_kernels.hip).
+TRAFFIC_BWD_BYTES = 1.2170e9
+TRAFFIC_KERNEL_SHA256 = "e39910b3b24ccb333a682a34f4e736f3d1f4d6e77770598055c684d88a2e7d0d"
 
 
 def log(*a):
@@ -86,6 +91,96 @@ def cpu_baseline(sc, lanes: int):
                       "FP64 sequential C, %.2f s" % (lanes, sc.n_lanes, len(idx), sc.n_steps, dt)}
 
 
+def fit_report(dev, log_fn, cap: int = 2000) -> dict:
+    """Trajectory fitting workload (100 lanes x 1000 vehicles, 500 steps,
+    observed every 10th step with N(0, 0.5 m) noise) and the learned warm start:
+    time to 0.5 m RMSE against the hidden trajectory, warm vs cold, on the same
+    GPU, plus the 200-iteration cold fit's per-iteration time, RMSE and
+    parameter errors."""
+    import numpy as np
+    import torch
+    import scenarios
+    from paper_2412_16750_amd import sim
+    from paper_2412_16750_amd import warmstart as ws
+    from paper_2412_16750_amd.fit import Fitter
+
+    # warm-start network: 1M simulated (window, parameters) pairs, batch 4096
+    t0 = time.perf_counter()
+    data = ws.make_pairs(scenarios.warm_training())
+    gen_s = time.perf_counter() - t0
+    net = ws.MLP(scenarios.mlp_init_params(5), lr=1e-3)
+    rep = ws.train(net, data, batch=4096, epochs=10, log=log_fn)
+    n_pairs = int(data.X.shape[0])
+    del data
+    # the fitting problem, hidden parameters = the scenario's draw
+    sc = scenarios.fit()
+    plan = sim.Plan.for_scenario(sc)
+    prm = sim.params_tensor(sc.params, dev)
+    length = torch.from_numpy(np.ascontiguousarray(sc.params["length"])).to(dev)
+    p0 = torch.from_numpy(np.ascontiguousarray(sc.p0)).to(dev)
+    v = torch.from_numpy(np.ascontiguousarray(sc.v_init)).to(dev)
+    hidden = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device=dev)
+    sim.idm_sim_forward(plan, prm, length, p0, v, hidden, None, None)
+    n_obs = sc.n_steps // 10
+    noise = torch.from_numpy(scenarios.noise((n_obs, sc.n), 4).astype(np.float32)).to(dev)
+    obs = sim.Obs(ws.observe(plan, hidden, p0, noise, 10, 10, n_obs), 10, 10)
+    cold = sim.params_tensor(scenarios.cold_params(sc), dev)
+    X = ws.features(plan, obs, p0, length)
+    Uh = torch.from_numpy(scenarios.normalized_params(sc.params)).to(dev)
+    heldout_mse = ws.evaluate(net, ws.Dataset(X, Uh))
+    out = {"workload": "100 lanes x 1000 vehicles, 500 steps, observed every 10th step, "
+                       "N(0, 0.5 m) noise; Adam lr 1e-2 on normalised parameters",
+           "mlp": {"pairs": n_pairs, "batch": 4096, "epochs": 10, "steps": rep["steps"],
+                   "data_seconds": round(gen_s, 3), "train_seconds": round(rep["seconds"], 3),
+                   "train_mse": rep["history"][-1]["train_mse"], "heldout_mse": heldout_mse}}
+    # cold start, 200 iterations: per-iteration time, RMSE, parameter errors
+    f = Fitter(plan, length, p0, v, obs, lr0=1e-2)
+    f.init(cold)
+    f.run(5)
+    f.init(cold)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    f.run(200)
+    e1.record()
+    torch.cuda.synchronize()
+    traj = torch.empty_like(hidden)
+    rmse200 = ws.trajectory_rmse(plan, f.params, length, p0, v, hidden, traj)
+    fitted = f.params.double().cpu().numpy()
+    true = np.stack([sc.params[k].astype(np.float64) for k in scenarios.PARAM_NAMES])
+    rel = np.abs(fitted - true) / true
+    heads = np.zeros(sc.n, bool)
+    heads[sc.lane_offsets[:-1]] = True
+    perr = {}
+    for i, k in enumerate(scenarios.PARAM_NAMES):
+        mask = ~heads if k in ("T", "b", "s0") else np.ones(sc.n, bool)
+        perr[k] = float(np.median(rel[i, mask]))
+    out["cold_200"] = {"ms_per_iteration": e0.elapsed_time(e1) / 200, "rmse_m": rmse200,
+                       "median_rel_param_error": perr,
+                       "loss_first_last": [float(f.losses()[0]), float(f.losses()[-1])]}
+    # time to 0.5 m RMSE, cold and warm
+    f = Fitter(plan, length, p0, v, obs, lr0=1e-2)
+    f.init(cold)
+    rc = ws.fit_until(f, plan, length, p0, v, hidden, 0.5, chunk=10, cap=cap)
+    f = Fitter(plan, length, p0, v, obs, lr0=1e-2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = ws.warm_init(f, net, plan, obs, p0, v, length, cold)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    rw = ws.fit_until(f, plan, length, p0, v, hidden, 0.5, chunk=10, cap=cap)
+    out["cold"] = {"iterations": rc["iterations"], "seconds": rc["fit_seconds"],
+                   "start_rmse_m": rc["curve"][0][1], "final_rmse_m": rc["rmse"],
+                   "reached": rc["reached"]}
+    out["warm"] = {"iterations": rw["iterations"], "seconds": init_s + rw["fit_seconds"],
+                   "init_seconds": init_s, "start_rmse_m": rw["curve"][0][1],
+                   "final_rmse_m": rw["rmse"], "reached": rw["reached"],
+                   "fallback_lanes": info["fallback_lanes"]}
+    if rc["reached"] and rw["reached"]:
+        out["warm_speedup"] = out["cold"]["seconds"] / max(out["warm"]["seconds"], 1e-12)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +194,8 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--per-thread", type=int, default=0)
     ap.add_argument("--ckpt", type=int, default=32)
+    ap.add_argument("--no-fit", action="store_true",
+                    help="skip the fitting / warm-start time-to-RMSE section")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -193,11 +290,16 @@ def main():
     nblk = -(-S // info["ckpt_every"])
     bwd_bytes = N * (nblk * 8 + 20 + 4 + 16 + 4 * S + 56)
     fwd_bytes = N * (20 + 4 + 16 + 4 + 4 * (S + 1) + nblk * 8)
+    import hashlib
+    src = os.path.join(ROOT, "paper_2412_16750_amd", "csrc", "idm_kernels.hip")
+    same_kernel = hashlib.sha256(open(src, "rb").read()).hexdigest() == TRAFFIC_KERNEL_SHA256
+    traffic = TRAFFIC_BWD_BYTES if (same_kernel and info["ckpt_every"] == 32 and info["block"] == 16
+                                    and info["threads"] == 1024 and info["per_thread"] == 1) else None
     roofline = {
         "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
-        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
-        "kernel": "k_backward<softplus,R=%d,threads=%d,K=%d>" % (info["per_thread"], info["threads"],
-                                                                  info["ckpt_every"]),
+        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
+        "kernel": "k_backward<softplus,R=%d,threads=%d,KB=%d> (K=%d)"
+                  % (info["per_thread"], info["threads"], info["block"], info["ckpt_every"]),
         "kernel_ms": round(bwd_ms, 4), "flop_per_vehicle_step": FLOP_BWD,
         "hbm_algorithmic_GBps": round(bwd_bytes / (bwd_ms / 1e3) / 1e9, 1),
         "hbm_frac": round(bwd_bytes / (bwd_ms / 1e3) / 1e9 / PEAK_HBM_GBPS, 4),
@@ -220,6 +322,11 @@ def main():
                    "threads": info["threads"], "per_thread": info["per_thread"]},
         "roofline": roofline,
     }
+    if not args.no_fit:
+        log("bench: fitting and warm start")
+        del x, obs, traj_d, ws, gp, gp0, gv0
+        torch.cuda.empty_cache()
+        out["fit"] = fit_report(dev, log)
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline on %d lanes" % args.cpu_lanes)
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_lanes)

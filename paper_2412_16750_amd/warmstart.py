@@ -1,0 +1,246 @@
+"""Learned warm start for the trajectory fit.
+
+A 150 -> 256 -> 256 -> 5 MLP (BF16 MFMA kernels, FP32 accumulation, FP32
+master weights) maps a vehicle's observed trajectory window to normalised
+IDM parameters.  It is trained on (window, parameters) pairs that the
+simulator generates, and its predictions initialise the Adam fit of
+Sec. IV-A; per lane the fit falls back to the cold start when that gives the
+lower observed loss.  Every numeric step (simulation, observation, features,
+MLP, per-lane losses and choice, fit) runs in libidmx.so's kernels; torch
+holds the buffers and the stream, and shuffles the training rows.
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib, sim
+from ._lib import MLP_IN_PAD, MLP_OUT, MLP_OUT_PAD, IdmMlpState, IdmObs, check
+from .fit import DEFAULT_BOXES, Fitter
+
+
+class MLP:
+    """Device state of the warm-start network (idm_mlp_state)."""
+
+    def __init__(self, init_params: np.ndarray, lr: float = 1e-3, betas=(0.9, 0.999),
+                 eps: float = 1e-8, device="cuda"):
+        L = _lib.load()
+        n_p, n_w = int(L.idm_mlp_param_count()), int(L.idm_mlp_weight_bf16_count())
+        init_params = np.ascontiguousarray(np.asarray(init_params, dtype=np.float32))
+        if init_params.size != n_p:
+            raise ValueError("init_params has %d values, expected %d" % (init_params.size, n_p))
+        self.params = torch.from_numpy(init_params).to(device)
+        self.w16 = torch.empty(n_w, dtype=torch.bfloat16, device=device)
+        self.m = torch.zeros(n_p, dtype=torch.float32, device=device)
+        self.v = torch.zeros(n_p, dtype=torch.float32, device=device)
+        st = IdmMlpState()
+        st.params, st.weights_bf16 = self.params.data_ptr(), self.w16.data_ptr()
+        st.adam_m, st.adam_v = self.m.data_ptr(), self.v.data_ptr()
+        st.lr, st.beta1, st.beta2, st.eps = float(lr), float(betas[0]), float(betas[1]), float(eps)
+        self._st = st
+        self.t = 0
+        self._ws = {}
+        check(L.idm_mlp_sync(ctypes.byref(st), sim._stream()), "idm_mlp_sync")
+
+    def workspace(self, batch: int) -> torch.Tensor:
+        if batch not in self._ws:
+            nb = int(_lib.load().idm_mlp_workspace_bytes(int(batch)))
+            self._ws = {batch: torch.empty(nb, dtype=torch.uint8, device=self.params.device)}
+        return self._ws[batch]
+
+    @staticmethod
+    def _rows(X, U=None):
+        B = X.shape[0]
+        sim._need(X, "X", torch.bfloat16, B * MLP_IN_PAD)
+        if U is not None:
+            sim._need(U, "U", torch.float32, B * MLP_OUT)
+        return B
+
+    def forward(self, X: torch.Tensor, Y: Optional[torch.Tensor] = None) -> torch.Tensor:
+        B = self._rows(X)
+        if Y is None:
+            Y = torch.empty(B, MLP_OUT_PAD, dtype=torch.float32, device=X.device)
+        sim._need(Y, "Y", torch.float32, B * MLP_OUT_PAD)
+        check(_lib.load().idm_mlp_forward(ctypes.byref(self._st), sim._ptr(X), B, sim._ptr(Y),
+                                          sim._ptr(self.workspace(B)), sim._stream()),
+              "idm_mlp_forward")
+        return Y
+
+    def gradients(self, X, U, grad_out, loss_out=None):
+        B = self._rows(X, U)
+        sim._need(grad_out, "grad_out", torch.float32, self.params.numel())
+        check(_lib.load().idm_mlp_gradients(ctypes.byref(self._st), sim._ptr(X), sim._ptr(U), B,
+                                            sim._ptr(grad_out), sim._ptr(loss_out),
+                                            sim._ptr(self.workspace(B)), sim._stream()),
+              "idm_mlp_gradients")
+
+    def train_step(self, X, U, loss_out=None):
+        B = self._rows(X, U)
+        self.t += 1
+        check(_lib.load().idm_mlp_train_step(ctypes.byref(self._st), sim._ptr(X), sim._ptr(U), B,
+                                             self.t, sim._ptr(loss_out),
+                                             sim._ptr(self.workspace(B)), sim._stream()),
+              "idm_mlp_train_step")
+
+
+def observe(plan, traj_d, p0, noise, obs_first, obs_stride, n_obs) -> torch.Tensor:
+    """Observed absolute positions [n_obs, N] from a simulated trajectory."""
+    n = plan.n
+    sim._need(traj_d, "traj_d", torch.float32, (plan.n_steps + 1) * n)
+    sim._need(p0, "p0", torch.float64, n)
+    if noise is not None:
+        sim._need(noise, "noise", torch.float32, n_obs * n)
+    out = torch.empty(n_obs, n, dtype=torch.float32, device=p0.device)
+    check(_lib.load().idm_observe(plan.handle, sim._ptr(traj_d), sim._ptr(p0), sim._ptr(noise),
+                                  int(n_obs), int(obs_first), int(obs_stride), sim._ptr(out),
+                                  sim._stream()), "idm_observe")
+    return out
+
+
+def features(plan, obs: "sim.Obs", p0, length) -> torch.Tensor:
+    """Window features [N, 160] (BF16) of every vehicle."""
+    n = plan.n
+    sim._need(obs.target, "obs.target", torch.float32, obs.n_obs * n)
+    X = torch.empty(n, MLP_IN_PAD, dtype=torch.bfloat16, device=p0.device)
+    check(_lib.load().idm_mlp_features(plan.handle, sim._ptr(obs.target), obs.n_obs, obs.obs_first,
+                                       obs.obs_stride, sim._ptr(p0), sim._ptr(length), sim._ptr(X),
+                                       sim._stream()), "idm_mlp_features")
+    return X
+
+
+def lane_loss(plan, traj_d, p0, obs: "sim.Obs") -> torch.Tensor:
+    out = torch.empty(plan.n_lanes, dtype=torch.float64, device=p0.device)
+    oc = obs.c()
+    check(_lib.load().idm_lane_loss(plan.handle, sim._ptr(traj_d), sim._ptr(p0), ctypes.byref(oc),
+                                    sim._ptr(out), sim._stream()), "idm_lane_loss")
+    return out
+
+
+def select_by_lane(plan, loss_a, loss_b, params_a, params_b):
+    out = torch.empty_like(params_a)
+    chose = torch.empty(plan.n, dtype=torch.int32, device=params_a.device)
+    check(_lib.load().idm_select_by_lane(plan.handle, sim._ptr(loss_a), sim._ptr(loss_b),
+                                         sim._ptr(params_a), sim._ptr(params_b), sim._ptr(out),
+                                         sim._ptr(chose), sim._stream()), "idm_select_by_lane")
+    return out, chose
+
+
+@dataclass
+class Dataset:
+    X: torch.Tensor   # [N, 160] BF16 features
+    U: torch.Tensor   # [N, 5] FP32 normalised true parameters
+
+
+def make_pairs(sc, dev="cuda") -> Dataset:
+    """Simulate the scenario with its own (true) parameters, observe every
+    obs_stride-th step with N(0, 0.5 m) noise, and return (features, u) pairs."""
+    import scenarios
+    plan = sim.Plan.for_scenario(sc)
+    prm = sim.params_tensor(sc.params, dev)
+    length = torch.from_numpy(np.ascontiguousarray(sc.params["length"])).to(dev)
+    p0 = torch.from_numpy(np.ascontiguousarray(sc.p0)).to(dev)
+    v = torch.from_numpy(np.ascontiguousarray(sc.v_init)).to(dev)
+    traj = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device=dev)
+    sim.idm_sim_forward(plan, prm, length, p0, v, traj, None, None)
+    first, stride = int(sc.extra["obs_first"]), int(sc.extra["obs_stride"])
+    n_obs = (sc.n_steps - first) // stride + 1
+    noise = torch.from_numpy(scenarios.noise((n_obs, sc.n), 5).astype(np.float32)).to(dev)
+    tgt = observe(plan, traj, p0, noise, first, stride, n_obs)
+    del traj
+    X = features(plan, sim.Obs(tgt, first, stride), p0, length)
+    U = torch.from_numpy(scenarios.normalized_params(sc.params)).to(dev)
+    torch.cuda.synchronize()
+    return Dataset(X, U)
+
+
+def train(mlp: MLP, data: Dataset, batch: int = 4096, epochs: int = 10, seed: int = 0,
+          val: Optional[Dataset] = None, log=None) -> dict:
+    """Minibatch Adam over shuffled rows; returns per-epoch losses and time."""
+    n = data.X.shape[0]
+    nb = n // batch
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    loss = torch.zeros(1, dtype=torch.float64, device=data.X.device)
+    hist = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(data.X.device)
+        Xs, Us = data.X.index_select(0, perm), data.U.index_select(0, perm)
+        acc = torch.zeros(1, dtype=torch.float64, device=data.X.device)
+        for b in range(nb):
+            mlp.train_step(Xs[b * batch:(b + 1) * batch], Us[b * batch:(b + 1) * batch], loss)
+            acc += loss
+        torch.cuda.synchronize()
+        ep_loss = float(acc.item()) / max(nb, 1)
+        rec = {"epoch": ep, "train_mse": ep_loss}
+        if val is not None:
+            rec["val_mse"] = evaluate(mlp, val)
+        hist.append(rec)
+        if log:
+            log("mlp epoch %d: %s" % (ep, rec))
+    torch.cuda.synchronize()
+    return {"history": hist, "seconds": time.perf_counter() - t0, "steps": epochs * nb}
+
+
+def evaluate(mlp: MLP, data: Dataset) -> float:
+    """Mean squared error of the predicted normalised parameters."""
+    Y = mlp.forward(data.X)
+    return float(((Y[:, :MLP_OUT] - data.U) ** 2).mean().item())
+
+
+def warm_init(fitter: Fitter, mlp: MLP, plan, obs, p0, v_init, length, cold_params,
+              fallback: bool = True) -> dict:
+    """Initialise the fit from the MLP's predictions; with the fallback, lanes
+    whose observed loss is lower at the cold start keep the cold start."""
+    X = features(plan, obs, p0, length)
+    Y = mlp.forward(X)
+    check(_lib.load().idm_fit_init_normalized(plan.handle, ctypes.byref(fitter._st), sim._ptr(Y),
+                                              MLP_OUT_PAD, sim._stream()), "idm_fit_init_normalized")
+    info = {"fallback_lanes": 0}
+    if fallback:
+        warm = fitter.params.clone()
+        traj = torch.empty(plan.n_steps + 1, plan.n, dtype=torch.float32, device=p0.device)
+        sim.idm_sim_forward(plan, warm, length, p0, v_init, traj, None, None)
+        la = lane_loss(plan, traj, p0, obs)
+        sim.idm_sim_forward(plan, cold_params, length, p0, v_init, traj, None, None)
+        lb = lane_loss(plan, traj, p0, obs)
+        chosen, chose_a = select_by_lane(plan, la, lb, warm, cold_params)
+        fitter.init(chosen)
+        info["fallback_lanes"] = int((la > lb).sum().item())
+    return info
+
+
+def trajectory_rmse(plan, params, length, p0, v_init, hidden_traj, traj_buf) -> float:
+    """RMSE (m) of the simulated trajectory under `params` against the hidden
+    trajectory, over every vehicle and steps 1..S (evaluation only)."""
+    sim.idm_sim_forward(plan, params, length, p0, v_init, traj_buf, None, None)
+    d = (traj_buf[1:] - hidden_traj[1:]).double()
+    return float(torch.sqrt((d * d).mean()).item())
+
+
+def fit_until(fitter: Fitter, plan, length, p0, v_init, hidden_traj, target_rmse: float = 0.5,
+              chunk: int = 10, cap: int = 2000) -> dict:
+    """Run the fit in graph replays of `chunk` iterations until the RMSE
+    against the hidden trajectory reaches `target_rmse` (or `cap`
+    iterations).  Only the fitting is timed (HIP events), not the checks."""
+    traj = torch.empty_like(hidden_traj)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fit_ms, it = 0.0, 0
+    rmse = trajectory_rmse(plan, fitter.params, length, p0, v_init, hidden_traj, traj)
+    curve = [(0, rmse)]
+    while rmse > target_rmse and it < cap:
+        e0.record()
+        fitter.run(chunk)
+        e1.record()
+        torch.cuda.synchronize()
+        fit_ms += e0.elapsed_time(e1)
+        it += chunk
+        rmse = trajectory_rmse(plan, fitter.params, length, p0, v_init, hidden_traj, traj)
+        curve.append((it, rmse))
+    return {"iterations": it, "fit_seconds": fit_ms / 1e3, "rmse": rmse,
+            "reached": rmse <= target_rmse, "curve": curve}

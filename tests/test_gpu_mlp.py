@@ -1,0 +1,175 @@
+"""The warm-start MLP kernels (BF16 MFMA, FP32 accumulation) against the FP64
+oracle with BF16 rounding mirrored, the feature / lane-loss / lane-select
+kernels, and a small end-to-end warm start."""
+import numpy as np
+import pytest
+
+import oracle
+import scenarios
+from oracle import mlp as omlp
+from gpu_run import device_inputs, log
+
+pytestmark = pytest.mark.gpu
+
+
+def _net(seed=3, bias_scale=0.1):
+    rng = np.random.default_rng(seed)
+    theta = scenarios.mlp_init_params(seed).astype(np.float64)
+    p = omlp.unpack(theta)
+    p["b1"] = rng.normal(0, bias_scale, p["b1"].shape)
+    p["b2"] = rng.normal(0, bias_scale, p["b2"].shape)
+    p["b3"][:5] = rng.normal(0, bias_scale, 5)
+    return omlp.pack(p).astype(np.float32)
+
+
+def _batch(B, seed=0):
+    import torch
+    rng = np.random.default_rng(seed)
+    X = np.zeros((B, omlp.IN_PAD), np.float32)
+    X[:, :omlp.IN] = rng.normal(0, 1, (B, omlp.IN))
+    U = rng.uniform(0, 1, (B, omlp.OUT)).astype(np.float32)
+    Xt = torch.from_numpy(X).to(torch.bfloat16).cuda()
+    return X, U, Xt, torch.from_numpy(U).cuda()
+
+
+@pytest.mark.parametrize("B", [4096, 777])
+def test_mlp_forward_and_gradients_match_oracle(B):
+    import torch
+    from paper_2412_16750_amd.warmstart import MLP
+    theta = _net()
+    X, U, Xt, Ut = _batch(B)
+    net = MLP(theta)
+    Y = net.forward(Xt)
+    G = torch.empty(theta.size, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    net.gradients(Xt, Ut, G, loss)
+    torch.cuda.synchronize()
+    Yr, _ = omlp.forward(theta.astype(np.float64), X, mirror=True)
+    Lr, Gr = omlp.loss_and_grad(theta.astype(np.float64), X, U, mirror=True)
+    Yg = Y.double().cpu().numpy()
+    err = np.abs(Yg[:, :5] - Yr[:, :5]).max()
+    log("mlp B=%d: max |Y - Y_oracle| = %.3e (|Y| max %.3f), loss %.6e vs %.6e"
+        % (B, err, np.abs(Yr[:, :5]).max(), loss.item(), Lr))
+    assert err <= 1e-2 * max(1.0, np.abs(Yr[:, :5]).max())
+    assert abs(loss.item() - Lr) <= 1e-2 * Lr
+    g = G.double().cpu().numpy()
+    sizes = np.cumsum([0] + [int(np.prod(s)) for _, s in omlp.SHAPES])
+    for b, (name, _) in enumerate(omlp.SHAPES):
+        a, r = g[sizes[b]:sizes[b + 1]], Gr[sizes[b]:sizes[b + 1]]
+        nr = np.linalg.norm(r)
+        rel = np.linalg.norm(a - r) / max(nr, 1e-30)
+        log("mlp B=%d: grad %s norm %.3e rel err %.3e" % (B, name, nr, rel))
+        if nr > 0:
+            assert rel <= 2e-2, name
+        else:
+            assert np.all(a == 0.0), name
+
+
+def test_mlp_training_reduces_loss():
+    """Adam steps on a learnable target (u = sigmoid of a fixed projection of X)."""
+    import torch
+    from paper_2412_16750_amd.warmstart import MLP
+    rng = np.random.default_rng(5)
+    B = 4096
+    X = np.zeros((B, omlp.IN_PAD), np.float32)
+    X[:, :omlp.IN] = rng.normal(0, 1, (B, omlp.IN))
+    A = rng.normal(0, 0.15, (omlp.IN_PAD, 5))
+    U = (1 / (1 + np.exp(-(X @ A)))).astype(np.float32)
+    Xt = torch.from_numpy(X).to(torch.bfloat16).cuda()
+    Ut = torch.from_numpy(U).cuda()
+    net = MLP(scenarios.mlp_init_params(7), lr=1e-3)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    losses = []
+    for _ in range(200):
+        net.train_step(Xt, Ut, loss)
+        losses.append(loss.item())
+    log("mlp training: loss %.4e -> %.4e" % (losses[0], losses[-1]))
+    assert losses[-1] < 0.2 * losses[0]
+    # the BF16 copies track the FP32 masters
+    w16 = net.w16.float().cpu().numpy()
+    p = net.params.cpu().numpy()
+    n1 = omlp.IN_PAD * omlp.HID
+    np.testing.assert_array_equal(w16[:n1], torch.from_numpy(p[:n1]).to(torch.bfloat16).float().numpy())
+
+
+def test_features_lane_loss_and_selection():
+    import torch
+    from paper_2412_16750_amd import sim
+    from paper_2412_16750_amd import warmstart as ws
+    sizes = [40, 1, 25, 0, 70]
+    sc = scenarios.make_scenario("feat", scenarios.offsets_from_sizes(sizes), 100, 9, ckpt_every=16)
+    plan = sim.Plan.for_scenario(sc)
+    x = device_inputs(sc)
+    traj = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device="cuda")
+    sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj, None, None)
+    noise = torch.from_numpy(scenarios.noise((10, sc.n), 9).astype(np.float32)).cuda()
+    tgt = ws.observe(plan, traj, x["p0"], noise, 10, 10, 10)
+    d = traj.double().cpu().numpy()
+    exp_tgt = (sc.p0[None, :] + d[10::10] + noise.double().cpu().numpy()).astype(np.float32)
+    np.testing.assert_array_equal(tgt.cpu().numpy(), exp_tgt)
+    obs = sim.Obs(tgt, 10, 10)
+    X = ws.features(plan, obs, x["p0"], x["length"])
+    F = oracle.mlp.features(tgt.cpu().numpy(), 10, 10, sc.dt, sc.p0, sc.params["length"],
+                            sc.lane_offsets)
+    ref = omlp.bf16(F.astype(np.float32))
+    got = X.float().double().cpu().numpy()
+    bad = np.abs(got - ref) > np.abs(ref) * 2 ** -7  # at most one BF16 ulp apart
+    log("features: %d of %d values differ by more than one BF16 ulp" % (bad.sum(), bad.size))
+    assert not bad.any()
+    assert np.mean(got == ref) > 0.99
+    # per-lane observed squared error
+    ll = ws.lane_loss(plan, traj, x["p0"], obs).cpu().numpy()
+    P = sc.p0[None, :] + d
+    r = P[10::10] - tgt.double().cpu().numpy()
+    per_vehicle = (r * r).sum(axis=0)
+    off = sc.lane_offsets
+    expect = np.array([per_vehicle[off[l]:off[l + 1]].sum() for l in range(len(sizes))])
+    np.testing.assert_allclose(ll, expect, rtol=1e-12, atol=1e-12)
+    # per-lane choice
+    la = torch.tensor([1.0, 5.0, 2.0, 0.0, 9.0], dtype=torch.float64, device="cuda")
+    lb = torch.tensor([2.0, 4.0, 2.0, 1.0, 1.0], dtype=torch.float64, device="cuda")
+    pa = torch.full((5, sc.n), 1.0, device="cuda")
+    pb = torch.full((5, sc.n), 2.0, device="cuda")
+    out, chose = ws.select_by_lane(plan, la, lb, pa, pb)
+    lane_of = np.repeat(np.arange(len(sizes)), sizes)
+    want_a = (la.cpu().numpy() <= lb.cpu().numpy())[lane_of]
+    assert np.array_equal(chose.cpu().numpy().astype(bool), want_a)
+    assert np.array_equal(out.cpu().numpy(), np.where(want_a[None, :], 1.0, 2.0).repeat(1, 0) * np.ones((5, 1)))
+
+
+def test_warm_start_end_to_end_small():
+    """Train on 200k simulated pairs, then warm vs cold fit on a held-out
+    4-lane problem: the warm start begins closer to the hidden trajectory and
+    reaches 0.5 m RMSE in fewer iterations."""
+    import torch
+    from paper_2412_16750_amd import sim
+    from paper_2412_16750_amd import warmstart as ws
+    from paper_2412_16750_amd.fit import Fitter
+    train_sc = scenarios.warm_training(n_lanes=200, lane_len=1000)
+    data = ws.make_pairs(train_sc)
+    net = ws.MLP(scenarios.mlp_init_params(11), lr=1e-3)
+    rep = ws.train(net, data, batch=4096, epochs=4, log=log)
+    assert rep["history"][-1]["train_mse"] < 0.5 * rep["history"][0]["train_mse"]
+    sc = scenarios.fit(n_lanes=4, lane_len=1000)
+    plan = sim.Plan.for_scenario(sc)
+    x = device_inputs(sc)
+    hidden = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device="cuda")
+    sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], hidden, None, None)
+    noise = torch.from_numpy(scenarios.noise((50, sc.n), 4).astype(np.float32)).cuda()
+    tgt = ws.observe(plan, hidden, x["p0"], noise, 10, 10, 50)
+    obs = sim.Obs(tgt, 10, 10)
+    cold = sim.params_tensor(scenarios.cold_params(sc))
+    res = {}
+    for mode in ("cold", "warm"):
+        f = Fitter(plan, x["length"], x["p0"], x["v"], obs, lr0=1e-2)
+        if mode == "cold":
+            f.init(cold)
+        else:
+            info = ws.warm_init(f, net, plan, obs, x["p0"], x["v"], x["length"], cold)
+            log("warm start: %s" % info)
+        res[mode] = ws.fit_until(f, plan, x["length"], x["p0"], x["v"], hidden, 0.5, chunk=10,
+                                 cap=600)
+        log("%s: start RMSE %.3f m, %d iterations, final %.3f m"
+            % (mode, res[mode]["curve"][0][1], res[mode]["iterations"], res[mode]["rmse"]))
+    assert res["warm"]["curve"][0][1] < res["cold"]["curve"][0][1]
+    assert res["warm"]["reached"] and res["warm"]["iterations"] < res["cold"]["iterations"]
