@@ -57,9 +57,12 @@ enum {
     IDM_BOUND_CLAMP = 1     /* textbook IDM, speed clamped: v' = max(v + dt*a, 0) */
 };
 
+/* Largest N: per-step rows of N floats are addressed with 32-bit byte offsets. */
+#define IDM_MAX_VEHICLES (1 << 29)
+
 /* The simulation problem (Sec. III-A): lanes, step count and constants. */
 typedef struct {
-    int32_t n_vehicles;               /* N >= 1 */
+    int32_t n_vehicles;               /* 1 <= N <= IDM_MAX_VEHICLES */
     int32_t n_lanes;                  /* L >= 1 */
     int32_t n_steps;                  /* S >= 0 Euler steps of length dt */
     int32_t ckpt_every;               /* K: checkpoint interval of the forward; the backward
@@ -83,8 +86,11 @@ typedef struct {
     int32_t ckpt_every; /* K, overrides the problem's K when > 0 */
     int32_t grid;       /* >0: persistent grid of that many work-groups walking the bundle
                            list; 0: one work-group per bundle */
-    int32_t block;      /* backward register block KB: 8, 16 or 32 with 1 vehicle per thread,
-                           8 or 16 with 2, 4 or 8 with 4; must divide K; 0 = choose */
+    int32_t block;      /* backward register block KB: 8, 16 or 32 with 1 or 2 vehicles per
+                           thread, 4 or 8 with 4; must divide K; 0 = choose.  With K = 2 KB
+                           on (512 or 1024 threads x 1, 512 x 2, 256 x 4 with KB = 8) the
+                           backward keeps the lower sub-block's states in LDS and computes
+                           every state of a block once */
 } idm_tuning;
 
 /* Per-vehicle IDM parameters (Sec. III-A), FP32 [N] each, all > 0. */
@@ -242,7 +248,8 @@ typedef struct {
 idm_status idm_step_graph_launch(idm_plan *plan, const idm_step_args *args, void *stream);
 
 /* Autotuner: times forward + backward of every candidate launch shape
- * (threads x per_thread x K) whose lanes fit and whose workspace fits in
+ * (threads x per_thread x KB, with K the problem's or, left free, KB and 2 KB
+ * where the LDS stash exists) whose lanes fit and whose workspace fits in
  * `workspace_bytes`, `reps` times each, on the real inputs, and switches the
  * plan to the fastest.  Synchronises `stream`.  Results of the timed runs are
  * discarded (they overwrite the output buffers).  Any graph captured by the

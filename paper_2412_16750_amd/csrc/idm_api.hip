@@ -51,7 +51,7 @@ bool valid_per_thread(int r) { return r == 1 || r == 2 || r == 4; }
 // Backward register blocks instantiated for each vehicles-per-thread count.
 std::vector<int> kbs_for(int r) {
     if (r == 1) return {8, 16, 32};
-    if (r == 2) return {8, 16};
+    if (r == 2) return {8, 16, 32};
     return {4, 8};
 }
 
@@ -388,7 +388,7 @@ idm_status run_backward(idm_plan *p, const idm_params *prm, const double *p0, co
     a.g_p0 = g_p0;
     a.g_v0 = g_v0;
     a.loss_part = (double *)((char *)ws + ws_loss_off(p));
-    KernelFn fn = backward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, p->sh.KB);
+    KernelFn fn = backward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, p->sh.KB, p->sh.K);
     if (!fn) return fail(IDM_ERR_UNSUPPORTED, "no backward kernel for this shape");
     if (p->n_bundles > 0) {
         hipError_t e = launch_sim(fn, grid_of(p), p->sh.threads, a, s);
@@ -523,6 +523,10 @@ idm_status host_plan(const idm_problem *pb, const idm_tuning *tu, idm_plan *p, S
     if (pb->n_vehicles < 1 || pb->n_lanes < 1 || pb->n_steps < 0)
         return fail(IDM_ERR_INVALID_ARG, "sizes: N=%d L=%d S=%d", pb->n_vehicles, pb->n_lanes,
                     pb->n_steps);
+    // a per-step row of N floats is addressed with 32-bit buffer offsets
+    if (pb->n_vehicles > IDM_MAX_VEHICLES)
+        return fail(IDM_ERR_INVALID_ARG, "N=%d exceeds %d vehicles", pb->n_vehicles,
+                    IDM_MAX_VEHICLES);
     if (!(pb->dt > 0.0f) || !std::isfinite(pb->dt))
         return fail(IDM_ERR_INVALID_ARG, "dt must be positive and finite");
     if (!std::isfinite(pb->a_min) || !(pb->a_min < 0.0f))
@@ -863,19 +867,27 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
             if ((int64_t)t * rr < p->max_lane) continue;
             if ((int64_t)t * rr > 8 * std::max<int64_t>(p->max_lane, 64)) continue;
             for (int KB : kbs_for(rr)) {
-                const int K = k_fixed ? p->pb.ckpt_every : KB;
-                if (K % KB != 0 || ws_total(p, K) > ws_bytes) continue;
-                KernelFn fb = backward_kernel(p->pb.bound, rr, t, KB);
-                hipFuncAttributes fa;
-                if (!fb || hipFuncGetAttributes(&fa, fb) != hipSuccess || fa.localSizeBytes > 0)
-                    continue;  // skip shapes whose backward spills registers
-                Shape sh;
-                sh.threads = t;
-                sh.per_thread = rr;
-                sh.K = K;
-                sh.KB = KB;
-                sh.grid = 0;
-                cands.push_back(sh);
+                // K = KB, and K = 2 KB where a stash variant exists for the shape
+                for (int twice = 0; twice < 2; ++twice) {
+                    const int K = k_fixed ? p->pb.ckpt_every : (twice ? 2 * KB : KB);
+                    if (k_fixed && twice) break;
+                    if (K % KB != 0 || ws_total(p, K) > ws_bytes) continue;
+                    KernelFn fb = backward_kernel(p->pb.bound, rr, t, KB, K);
+                    if (twice && fb == backward_kernel(p->pb.bound, rr, t, KB, KB)) continue;
+                    hipFuncAttributes fa;
+                    // skip shapes whose backward spills more than a few registers
+                    // (small spills sit outside the step loops)
+                    if (!fb || hipFuncGetAttributes(&fa, fb) != hipSuccess ||
+                        fa.localSizeBytes > 128)
+                        continue;
+                    Shape sh;
+                    sh.threads = t;
+                    sh.per_thread = rr;
+                    sh.K = K;
+                    sh.KB = KB;
+                    sh.grid = 0;
+                    cands.push_back(sh);
+                }
             }
         }
     if (cands.empty()) return fail(IDM_ERR_WORKSPACE, "no launch shape fits the workspace");
@@ -889,7 +901,7 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
         for (int persistent = 0; persistent < 2; ++persistent) {
             Shape s2 = sh;
             if (persistent) {
-                KernelFn fb = backward_kernel(p->pb.bound, sh.per_thread, sh.threads, sh.KB);
+                KernelFn fb = backward_kernel(p->pb.bound, sh.per_thread, sh.threads, sh.KB, sh.K);
                 int occ = 0;
                 if (!fb || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fb, sh.threads, 0) !=
                                hipSuccess || occ < 1)

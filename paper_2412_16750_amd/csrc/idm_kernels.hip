@@ -28,7 +28,10 @@
 //     reduced in a fixed order by a second kernel.
 #include "idm_internal.h"
 
+#include <limits.h>
 #include <math.h>
+
+#include <type_traits>
 
 namespace idmx {
 namespace {
@@ -131,14 +134,15 @@ __device__ __forceinline__ float accel(const Veh &q, float d, float v, float dh,
     float x = v * q.inv_v0;
     float x2 = x * x;
     float gap = q.g0 + (dh - d);                      // Sec. III-A: p_h - p - len_h
-    float sg = fmaxf(gap, gap_floor);
+    float sg = gap > gap_floor ? gap : gap_floor;     // max(gap, floor), no NaN inputs
     float dv = v - vh;                                // Sec. III-A: v - v_h
     float s_opt = fmaf(v * dv, q.c, fmaf(v, q.T, q.s0));  // Eq. 1
     float s = (MODE == 0) ? softplus(s_opt) : s_opt;  // Sec. III-C floor on s_opt
     float qq = s * rcp_fast(sg);
     float ahat = q.a * (1.0f - fmaf(qq, qq, x2 * x2));   // Eq. 2, delta = 4
     if (MODE == 0) {
-        float lb = fmaxf(-v * inv_dt, a_min);           // Sec. III-C a_lb
+        float nv = -v * inv_dt;
+        float lb = nv > a_min ? nv : a_min;             // Sec. III-C a_lb
         return lb + softplus(ahat - lb);
     }
     return ahat;
@@ -183,7 +187,7 @@ __device__ __forceinline__ void partials(const Veh &q, float d, float v, float d
     float x2 = x * x;
     float gap = q.g0 + (dh - d);
     bool floored = !(gap > gap_floor);
-    float sg = fmaxf(gap, gap_floor);
+    float sg = floored ? gap_floor : gap;
     float inv_sg = rcp_fast(sg);
     float dv = v - vh;
     float vdv = v * dv;
@@ -233,10 +237,24 @@ __device__ __forceinline__ double block_sum(double x, double *red) {
 
 // ---------------------------------------------------------------- forward
 
+// Exchange-slot indices without masks.  Thread 0's first vehicle always opens
+// a bundle, so it is a lane head (or padding, also flagged head): its gap is
+// +inf and every leader term it computes is exactly zero for any finite
+// leader state, so it reads its own slot instead of a missing leader.  The
+// last thread reads thread 0's follower contribution, which is exactly zero
+// for the same reason.
+__device__ __forceinline__ int lead_thread(int t) { return t > 0 ? t - 1 : 0; }
+template <int NT>
+__device__ __forceinline__ int follow_thread(int t) {
+    static_assert((NT & (NT - 1)) == 0, "power-of-two work-group");
+    return (t + 1) & (NT - 1);
+}
+
 template <int MODE, int R, int NT>
 __global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
     __shared__ float2 sbuf[2][NT];
     const int t = threadIdx.x;
+    const int tl = lead_thread(t);
     const int64_t N = A.n;
     const int S = A.n_steps;
     for (int bidx = blockIdx.x; bidx < A.n_bundles; bidx += gridDim.x) {
@@ -260,7 +278,7 @@ __global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
         lds_barrier();
         int to_ckpt = A.K;  // steps until the next checkpoint
         for (int k = 0; k < S; ++k) {
-            float2 L = t > 0 ? sbuf[k & 1][t - 1] : make_float2(0.0f, 0.0f);
+            float2 L = sbuf[k & 1][tl];
             float acc[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -303,30 +321,76 @@ struct Up {
     float gd, gv, tg;
 };
 
-__device__ __forceinline__ int obs_index(const SimArgs &A, int k) {
-    if (!A.target || k < A.obs_first) return -1;
-    int rel = k - A.obs_first;
-    if (rel % A.obs_stride) return -1;
-    int j = rel / A.obs_stride;
-    return j < A.n_obs ? j : -1;
+// Walks the upstream inputs backwards one step at a time with a few scalar
+// updates (no per-step multiply or division).  Loads go through buffer
+// resources: an absent input, or the target row of an unobserved step, is a
+// resource with zero records, whose loads return 0 without a memory access.
+struct UpCursor {
+    int64_t row;     // byte offset of step k's row in the dense inputs (k N 4)
+    int64_t tg_row;  // byte offset of the current observation row (jq N 4)
+    int gap;         // steps from k down to the next observed step; INT_MAX if none
+    int jq;          // index of that observation
+};
+
+__device__ __forceinline__ void cursor_init(const SimArgs &A, int k, UpCursor &c) {
+    const int64_t NB = A.n * 4;
+    c.row = (int64_t)k * NB;
+    c.gap = INT_MAX;
+    c.jq = -1;
+    c.tg_row = 0;
+    if (A.target && A.n_obs > 0 && k >= A.obs_first) {
+        const int last = A.obs_first + (A.n_obs - 1) * A.obs_stride;
+        if (k >= last) {
+            c.jq = A.n_obs - 1;
+            c.gap = k - last;
+        } else {
+            const int rel = k - A.obs_first;
+            c.jq = rel / A.obs_stride;
+            c.gap = rel - c.jq * A.obs_stride;
+        }
+        c.tg_row = (int64_t)c.jq * NB;
+    }
 }
 
-// Branch-free loads (absent inputs read a zero word, padding slots read
-// vehicle 0), so the compiler can keep the prefetch in flight across a step.
+__device__ __forceinline__ bool cursor_obs(const UpCursor &c) { return c.gap == 0; }
+
+__device__ __forceinline__ void cursor_dec(const SimArgs &A, UpCursor &c) {
+    const int64_t NB = A.n * 4;
+    c.row -= NB;
+    // leaving observation jq (gap 0): the previous one is a stride lower.  With
+    // no observation left, gap counts down from INT_MAX and cannot reach 0
+    // within a trajectory.
+    const bool at = c.gap == 0;
+    const bool more = c.jq > 0;
+    c.tg_row -= (at && more) ? NB : 0;
+    c.jq -= at ? 1 : 0;
+    c.gap = at ? (more ? A.obs_stride - 1 : INT_MAX) : c.gap - 1;
+}
+
+__device__ __forceinline__ float load_rec(const float *base, int64_t row, uint32_t bytes, int off) {
+    // dword 3 of a raw (unswizzled, stride 0) buffer resource on gfx9; the
+    // address is formed as an integer (the base may be null when bytes = 0)
+    const char *p = reinterpret_cast<const char *>(reinterpret_cast<uintptr_t>(base) + row);
+    __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)bytes, 0x00020000);
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+}
+
+// Loads of the cursor's step (padding slots read vehicle 0's word).
 template <int R>
-__device__ __forceinline__ void fetch_up(const SimArgs &A, int k, int jo, const Veh (&q)[R],
+__device__ __forceinline__ void fetch_up(const SimArgs &A, const UpCursor &c, const Veh (&q)[R],
                                          Up (&u)[R]) {
-    const int64_t row = (int64_t)k * A.n;
-    const float *pgd = A.gd ? A.gd + row : A.zero;
-    const float *pgv = A.gv ? A.gv + row : A.zero;
-    const float *ptg = jo >= 0 ? A.target + (int64_t)jo * A.n : A.zero;
-    const int32_t mgd = A.gd ? -1 : 0, mgv = A.gv ? -1 : 0, mtg = jo >= 0 ? -1 : 0;
+    // an absent input keeps its (null) base: with zero records the resource's
+    // address is never used
+    const uint32_t NB = (uint32_t)(A.n * 4);
+    const uint32_t bgd = A.gd ? NB : 0u, bgv = A.gv ? NB : 0u;
+    const uint32_t btg = cursor_obs(c) ? NB : 0u;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int32_t gl = q[r].g > 0 ? q[r].g : 0;
-        u[r].gd = pgd[gl & mgd];
-        u[r].gv = pgv[gl & mgv];
-        u[r].tg = ptg[gl & mtg];
+        const int off = (q[r].g > 0 ? q[r].g : 0) * 4;
+        u[r].gd = load_rec(A.gd, c.row, bgd, off);
+        u[r].gv = load_rec(A.gv, c.row, bgv, off);
+        u[r].tg = load_rec(A.target, c.tg_row, btg, off);
     }
 }
 
@@ -350,7 +414,7 @@ template <int MODE, int R, int NT>
 __device__ __forceinline__ void bundle_step(const SimArgs &A, const Veh (&q)[R], float (&d)[R],
                                             float (&v)[R], float2 (*sbuf)[NT], int cb, int nb) {
     const int t = threadIdx.x;
-    float2 L = t > 0 ? sbuf[cb][t - 1] : make_float2(0.0f, 0.0f);
+    float2 L = sbuf[cb][lead_thread(t)];
     float acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -369,12 +433,23 @@ __device__ __forceinline__ void bundle_step(const SimArgs &A, const Veh (&q)[R],
 // sub-block's start state is re-advanced from the checkpoint, its KB states are
 // recomputed into registers, and the adjoint walks them backwards.  KB is a
 // compile-time size (register arrays), A.K a multiple of it.
-template <int MODE, int R, int NT, int KB>
+//
+// ST (stash): when a block has exactly two sub-blocks, the re-advance to the
+// upper one passes through every state of the lower one; they are kept in LDS
+// (KB x NT*R float2) and the lower sub-block's reverse sweep reads them there
+// instead of recomputing them, so each state of the block is computed once.
+template <int MODE, int R, int NT, int KB, bool ST>
 __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
     __shared__ float2 sbuf[2][NT];
     __shared__ float2 cbuf[2][NT];
-    __shared__ double red[NT / 64 + 1];
+    __shared__ float2 stash[ST ? KB : 1][ST ? NT * R : 1];
+    // the final loss reduction reuses cbuf (after a barrier)
+    double *red = reinterpret_cast<double *>(&cbuf[0][0]);
+    static_assert((NT / 64 + 1) * sizeof(double) <= sizeof(cbuf), "reduction scratch");
     const int t = threadIdx.x;
+    const int tl = lead_thread(t);             // leader's exchange slot
+    const int tf = follow_thread<NT>(t);       // follower's contribution slot
+    const int tlv = t > 0 ? t * R - 1 : 0;     // leader vehicle's stash slot
     const int64_t N = A.n;
     const int S = A.n_steps;
     const int K = A.K;
@@ -392,10 +467,16 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
         double loss = 0.0;
         // upstream of the last step (the seed), and prefetch of step S-1
         Up seed[R], nxt[R];
-        const int jo_S = obs_index(A, S);
-        fetch_up<R>(A, S, jo_S, q, seed);
-        int jo_nxt = S > 0 ? obs_index(A, S - 1) : -1;
-        if (S > 0) fetch_up<R>(A, S - 1, jo_nxt, q, nxt);
+        UpCursor cur_k;
+        cursor_init(A, S, cur_k);
+        fetch_up<R>(A, cur_k, q, seed);
+        const bool obs_S = cursor_obs(cur_k);
+        bool obs_nxt = false;
+        if (S > 0) {
+            cursor_dec(A, cur_k);
+            fetch_up<R>(A, cur_k, q, nxt);
+            obs_nxt = cursor_obs(cur_k);
+        }
         // checkpoint of the last block
         float ckd[R], ckv[R];
 #pragma unroll
@@ -414,7 +495,7 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
         if (S == 0) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                gp0[r] = mse_up(A, jo_S >= 0, q[r].g >= 0, seed[r], 0.0f, p0g[r], loss);
+                gp0[r] = mse_up(A, obs_S, q[r].g >= 0, seed[r], 0.0f, p0g[r], loss);
                 ld[r] = seed[r].gd + gp0[r];
                 lv[r] = seed[r].gv;
             }
@@ -438,43 +519,77 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
             for (int sb = nsub - 1; sb >= 0; --sb) {
                 const int ks = k0 + sb * KB;
                 const int slen = min(KB, len - sb * KB);
-                float d[R], v[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    d[r] = c0d[r];
-                    v[r] = c0v[r];
-                }
-                sbuf[0][t] = make_float2(d[R - 1], v[R - 1]);
-                lds_barrier();
-                // re-advance from the checkpoint to the sub-block start
-                for (int j = 0; j < sb * KB; ++j) bundle_step<MODE, R, NT>(A, q, d, v, sbuf, j & 1, (j + 1) & 1);
-                if (sb > 0) {
-                    // restart the LDS ping-pong at parity 0 (buffer (sb*KB)&1 was
-                    // written last and is not read again)
-                    sbuf[0][t] = make_float2(d[R - 1], v[R - 1]);
-                    lds_barrier();
-                }
-                // recompute the sub-block's states into registers
+                const bool stash_fill = ST && nsub == 2 && sb == 1;
+                const bool stash_use = ST && nsub == 2 && sb == 0;
                 float hd[KB][R], hv[KB][R];
-#pragma unroll
-                for (int j = 0; j < KB; ++j) {
-                    if (j < slen) {
-#pragma unroll
-                        for (int r = 0; r < R; ++r) {
-                            hd[j][r] = d[r];
-                            hv[j][r] = v[r];
-                        }
-                        bundle_step<MODE, R, NT>(A, q, d, v, sbuf, j & 1, (j + 1) & 1);
-                    }
-                }
-                if (blk == nblk - 1 && sb == nsub - 1) {
-                    // seed: upstream gradient at the last step S (d, v are now step S)
+                if (!stash_use) {
+                    float d[R], v[R];
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        const float um = mse_up(A, jo_S >= 0, q[r].g >= 0, seed[r], d[r], p0g[r], loss);
-                        gp0[r] += um;
-                        ld[r] += seed[r].gd + um;
-                        lv[r] += seed[r].gv;
+                        d[r] = c0d[r];
+                        v[r] = c0v[r];
+                    }
+                    if (stash_fill) {
+                        // advance through the lower sub-block, keeping its states
+#pragma unroll
+                        for (int r = 0; r < R; ++r) stash[0][t * R + r] = make_float2(d[r], v[r]);
+                        lds_barrier();
+                        for (int j = 0; j < KB; ++j) {
+                            const float2 L = stash[j][tlv];
+                            float acc[R];
+#pragma unroll
+                            for (int r = 0; r < R; ++r) {
+                                const float dh = r ? d[r - 1] : L.x;
+                                const float vh = r ? v[r - 1] : L.y;
+                                acc[r] = accel<MODE>(q[r], d[r], v[r], dh, vh, A.inv_dt, A.a_min,
+                                                     A.gap_floor);
+                            }
+#pragma unroll
+                            for (int r = 0; r < R; ++r) euler<MODE>(d[r], v[r], acc[r], dt);
+                            if (j + 1 < KB) {
+#pragma unroll
+                                for (int r = 0; r < R; ++r)
+                                    stash[j + 1][t * R + r] = make_float2(d[r], v[r]);
+                            } else {
+                                sbuf[0][t] = make_float2(d[R - 1], v[R - 1]);
+                            }
+                            lds_barrier();
+                        }
+                    } else {
+                        sbuf[0][t] = make_float2(d[R - 1], v[R - 1]);
+                        lds_barrier();
+                        // re-advance from the checkpoint to the sub-block start
+                        for (int j = 0; j < sb * KB; ++j)
+                            bundle_step<MODE, R, NT>(A, q, d, v, sbuf, j & 1, (j + 1) & 1);
+                        if (sb > 0) {
+                            // restart the LDS ping-pong at parity 0 (buffer (sb*KB)&1
+                            // was written last and is not read again)
+                            sbuf[0][t] = make_float2(d[R - 1], v[R - 1]);
+                            lds_barrier();
+                        }
+                    }
+                    // recompute the sub-block's states into registers
+#pragma unroll
+                    for (int j = 0; j < KB; ++j) {
+                        if (j < slen) {
+#pragma unroll
+                            for (int r = 0; r < R; ++r) {
+                                hd[j][r] = d[r];
+                                hv[j][r] = v[r];
+                            }
+                            bundle_step<MODE, R, NT>(A, q, d, v, sbuf, j & 1, (j + 1) & 1);
+                        }
+                    }
+                    if (blk == nblk - 1 && sb == nsub - 1) {
+                        // seed: upstream gradient at the last step S (d, v are now step S)
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const float um =
+                                mse_up(A, obs_S, q[r].g >= 0, seed[r], d[r], p0g[r], loss);
+                            gp0[r] += um;
+                            ld[r] += seed[r].gd + um;
+                            lv[r] += seed[r].gv;
+                        }
                     }
                 }
                 if (sb == 0) {
@@ -487,72 +602,124 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                         ckv[r] = A.ckpt[crow + N + gl];
                     }
                 }
-                // reverse sweep over the sub-block
+                // reverse sweep over the sub-block; its states come from the
+                // registers or, for a stashed sub-block, from LDS.  The leader
+                // state of the next step is read right after the barrier, next
+                // to the follower's contribution, so a step waits on one LDS
+                // round trip; a stashed sub-block reads its states one step
+                // ahead, before the barrier (the stash is read-only here).
+                float2 Lc;      // leader state of the current step
+                float2 own[R];  // stashed sub-block: own states of the current step
+                if (stash_use) {
 #pragma unroll
-                for (int j = KB - 1; j >= 0; --j) {
-                    if (j < slen) {
-                        const int k = ks + j;
-                        Up cur[R];
+                    for (int r = 0; r < R; ++r) own[r] = stash[KB - 1][t * R + r];
+                    Lc = stash[KB - 1][tlv];
+                } else {
+                    Lc = sbuf[(slen - 1) & 1][tl];
+                }
+                // (one step; j is a compile-time index on the register path)
+                auto rstep = [&](const int j, auto from_stash) {
+                    constexpr bool FS = decltype(from_stash)::value;
+                    const int k = ks + j;
+                    Up cur[R];
 #pragma unroll
-                        for (int r = 0; r < R; ++r) cur[r] = nxt[r];
-                        const int jo_cur = jo_nxt;
-                        if (k > 0) {
-                            jo_nxt = obs_index(A, k - 1);
-                            fetch_up<R>(A, k - 1, jo_nxt, q, nxt);
-                        }
-                        float2 L = t > 0 ? sbuf[j & 1][t - 1] : make_float2(0.0f, 0.0f);
-                        Part P[R];
-                        float mu[R], mw[R], mwAs[R];
+                    for (int r = 0; r < R; ++r) cur[r] = nxt[r];
+                    const bool obs_cur = obs_nxt;
+                    if (k > 0) {
+                        cursor_dec(A, cur_k);
+                        fetch_up<R>(A, cur_k, q, nxt);
+                        obs_nxt = cursor_obs(cur_k);
+                    }
+                    float sd[R], sv[R];
 #pragma unroll
-                        for (int r = 0; r < R; ++r) {
-                            float dh = r ? hd[j][r - 1] : L.x;
-                            float vh = r ? hv[j][r - 1] : L.y;
-                            partials<MODE>(q[r], hd[j][r], hv[j][r], dh, vh, dt, A.inv_dt, A.a_min,
-                                           A.gap_floor, P[r]);
-                            mu[r] = (MODE == 0) ? dt * lv[r] : P[r].gate * dt * lv[r];
-                            mw[r] = mu[r] * P[r].w;
-                            mwAs[r] = mw[r] * P[r].As;
-                        }
-                        // contribution of my first vehicle to its leader (previous
-                        // thread): (mu d a*/d d_h, mu d a*/d v_h).  A lane head
-                        // contributes exactly 0 (its hg and As vanish), so a lane
-                        // tail needs no mask.
-                        cbuf[j & 1][t] = make_float2(mw[0] * P[0].hg, -mwAs[0] * P[0].vc);
-                        if (j > 0)
-                            sbuf[(j - 1) & 1][t] = make_float2(hd[j - 1][R - 1], hv[j - 1][R - 1]);
-                        lds_barrier();
-                        float2 F = (t + 1 < NT) ? cbuf[j & 1][t + 1] : make_float2(0.0f, 0.0f);
-#pragma unroll
-                        for (int r = 0; r < R; ++r) {
-                            float fd, fv;  // gathered from the follower
-                            if (r + 1 < R) {
-                                fd = mw[r + 1] * P[r + 1].hg;
-                                fv = -mwAs[r + 1] * P[r + 1].vc;
-                            } else {
-                                fd = F.x;
-                                fv = F.y;
-                            }
-                            const float gterm = fmaf(-mw[r], P[r].hg, fd);  // gap terms
-                            float nld = ld[r] + gterm;
-                            float keep = (MODE == 0) ? lv[r] : P[r].gate * lv[r];
-                            float nlv = fmaf(dt, ld[r], keep);
-                            nlv = fmaf(mwAs[r], P[r].u1, nlv);
-                            nlv = fmaf(-mw[r] * q[r].fa_v0, P[r].x3, nlv);
-                            if (MODE == 0) nlv = fmaf(mu[r], P[r].lbv, nlv);
-                            nlv += fv;
-                            // sufficient statistics of the five parameter gradients
-                            gs[0][r] = fmaf(mw[r], P[r].x4, gs[0][r]);      // v0 (times 4a/v0)
-                            gs[1][r] = fmaf(mwAs[r], hv[j][r], gs[1][r]);   // T
-                            gs[2][r] = fmaf(mw[r], P[r].rest, gs[2][r]);    // a, direct part
-                            gs[3][r] = fmaf(mwAs[r], P[r].vdvc, gs[3][r]);  // a and b, through c
-                            gs[4][r] += mwAs[r];                           // s0
-                            const float um = mse_up(A, jo_cur >= 0, q[r].g >= 0, cur[r], hd[j][r],
-                                                    p0g[r], loss);
-                            gp0[r] += gterm + um;
-                            ld[r] = nld + (cur[r].gd + um);
-                            lv[r] = nlv + cur[r].gv;
+                    for (int r = 0; r < R; ++r) {
+                        if constexpr (FS) {
+                            sd[r] = own[r].x;
+                            sv[r] = own[r].y;
+                        } else {
+                            sd[r] = hd[j][r];
+                            sv[r] = hv[j][r];
                         }
                     }
+                    Part P[R];
+                    float mu[R], mw[R], mwAs[R], um[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const float dh = r ? sd[r - 1] : Lc.x;
+                        const float vh = r ? sv[r - 1] : Lc.y;
+                        partials<MODE>(q[r], sd[r], sv[r], dh, vh, dt, A.inv_dt, A.a_min,
+                                       A.gap_floor, P[r]);
+                        mu[r] = (MODE == 0) ? dt * lv[r] : P[r].gate * dt * lv[r];
+                        mw[r] = mu[r] * P[r].w;
+                        mwAs[r] = mw[r] * P[r].As;
+                        um[r] = mse_up(A, obs_cur, q[r].g >= 0, cur[r], sd[r], p0g[r], loss);
+                    }
+                    // contribution of my first vehicle to its leader (previous
+                    // thread): (mu d a*/d d_h, mu d a*/d v_h).  A lane head
+                    // contributes exactly 0 (its hg and As vanish), so a lane
+                    // tail needs no mask.
+                    cbuf[j & 1][t] = make_float2(mw[0] * P[0].hg, -mwAs[0] * P[0].vc);
+                    if constexpr (!FS) {
+                        if (j > 0)
+                            sbuf[(j - 1) & 1][t] = make_float2(hd[j - 1][R - 1], hv[j - 1][R - 1]);
+                    } else {
+                        if (j > 0) {
+#pragma unroll
+                            for (int r = 0; r < R; ++r) own[r] = stash[j - 1][t * R + r];
+                            Lc = stash[j - 1][tlv];
+                        }
+                    }
+                    lds_barrier();
+                    const float2 F = cbuf[j & 1][tf];
+                    if constexpr (!FS) {
+                        if (j > 0) Lc = sbuf[(j - 1) & 1][tl];
+                    }
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        float fd, fv;  // gathered from the follower
+                        if (r + 1 < R) {
+                            fd = mw[r + 1] * P[r + 1].hg;
+                            fv = -mwAs[r + 1] * P[r + 1].vc;
+                        } else {
+                            fd = F.x;
+                            fv = F.y;
+                        }
+                        const float gterm = fmaf(-mw[r], P[r].hg, fd);  // gap terms
+                        const float nld = ld[r] + gterm;
+                        const float keep = (MODE == 0) ? lv[r] : P[r].gate * lv[r];
+                        float nlv = fmaf(dt, ld[r], keep);
+                        nlv = fmaf(mwAs[r], P[r].u1, nlv);
+                        nlv = fmaf(-mw[r] * q[r].fa_v0, P[r].x3, nlv);
+                        if (MODE == 0) nlv = fmaf(mu[r], P[r].lbv, nlv);
+                        nlv += fv;
+                        // sufficient statistics of the five parameter gradients
+                        gs[0][r] = fmaf(mw[r], P[r].x4, gs[0][r]);      // v0 (times 4a/v0)
+                        gs[1][r] = fmaf(mwAs[r], sv[r], gs[1][r]);      // T
+                        gs[2][r] = fmaf(mw[r], P[r].rest, gs[2][r]);    // a, direct part
+                        gs[3][r] = fmaf(mwAs[r], P[r].vdvc, gs[3][r]);  // a and b, through c
+                        gs[4][r] += mwAs[r];                           // s0
+                        gp0[r] += gterm + um[r];
+                        ld[r] = nld + (cur[r].gd + um[r]);
+                        lv[r] = nlv + cur[r].gv;
+                    }
+                };
+                auto sweep_registers = [&]() {
+#pragma unroll
+                    for (int j = KB - 1; j >= 0; --j)
+                        if (j < slen) rstep(j, std::false_type{});
+                };
+                if constexpr (ST) {
+                    if (stash_use) {
+                        // a stashed sub-block is always full; its states are
+                        // indexed at run time, so the loop stays rolled (half
+                        // the code of an unrolled copy)
+#pragma unroll 1
+                        for (int j = KB - 1; j >= 0; --j) rstep(j, std::true_type{});
+                    } else {
+                        sweep_registers();
+                    }
+                } else {
+                    sweep_registers();
                 }
             }
 #pragma unroll
@@ -574,6 +741,7 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                 A.g_v0[g] = (double)lv[r];
             }
         }
+        __syncthreads();  // every cbuf read is done before the reduction reuses it
         double tot = block_sum(loss, red);
         if (t == 0 && A.loss_part) A.loss_part[bidx] = tot;
     }
@@ -758,33 +926,41 @@ KernelFn forward_kernel(int mode, int per_thread, int threads) {
 #endif
 
 #define IDM_BWD_CASE(M, R, NT, KK)                                            \
-    if (mode == M && per_thread == R && threads == NT && K == KK)             \
-        return (KernelFn)&k_backward<M, R, NT, KK>;
+    if (mode == M && per_thread == R && threads == NT && KB == KK)            \
+        return (KernelFn)&k_backward<M, R, NT, KK, false>;
+// stash variants (checkpoint interval = two register blocks), for the shapes
+// whose stash fits next to the exchange buffers in the 160 KB of LDS
+#define IDM_BWD_ST(M, R, NT, KK)                                              \
+    if (mode == M && per_thread == R && threads == NT && KB == KK && K == 2 * KK) \
+        return (KernelFn)&k_backward<M, R, NT, KK, true>;
 #define IDM_BWD_NT(M, R, KK)                                                  \
     IDM_BWD_CASE(M, R, 64, KK) IDM_BWD_CASE(M, R, 128, KK) IDM_BWD_CASE(M, R, 256, KK) \
     IDM_BWD_CASE(M, R, 512, KK) IDM_BWD_CASE(M, R, 1024, KK)
 #define IDM_BWD_M(M)                                                          \
+    IDM_BWD_ST(M, 1, 1024, 16) IDM_BWD_ST(M, 1, 512, 16) IDM_BWD_ST(M, 2, 512, 16) \
+    IDM_BWD_ST(M, 4, 256, 8)                                                  \
     IDM_BWD_NT(M, 1, 8) IDM_BWD_NT(M, 1, 16) IDM_BWD_NT(M, 1, 32)             \
-    IDM_BWD_NT(M, 2, 8) IDM_BWD_NT(M, 2, 16) IDM_BWD_NT(M, 4, 4) IDM_BWD_NT(M, 4, 8)
+    IDM_BWD_NT(M, 2, 8) IDM_BWD_NT(M, 2, 16) IDM_BWD_NT(M, 2, 32)                \
+    IDM_BWD_NT(M, 4, 4) IDM_BWD_NT(M, 4, 8)
 
 #if IDM_PART == 1
-KernelFn backward_kernel_softplus(int mode, int per_thread, int threads, int K) {
+KernelFn backward_kernel_softplus(int mode, int per_thread, int threads, int KB, int K) {
     IDM_BWD_M(0)
     return nullptr;
 }
 #endif
 #if IDM_PART == 2
-KernelFn backward_kernel_clamp(int mode, int per_thread, int threads, int K) {
+KernelFn backward_kernel_clamp(int mode, int per_thread, int threads, int KB, int K) {
     IDM_BWD_M(1)
     return nullptr;
 }
 #endif
 #if IDM_PART == 0
-KernelFn backward_kernel_softplus(int, int, int, int);
-KernelFn backward_kernel_clamp(int, int, int, int);
-KernelFn backward_kernel(int mode, int per_thread, int threads, int K) {
-    return mode == 0 ? backward_kernel_softplus(mode, per_thread, threads, K)
-                     : backward_kernel_clamp(mode, per_thread, threads, K);
+KernelFn backward_kernel_softplus(int, int, int, int, int);
+KernelFn backward_kernel_clamp(int, int, int, int, int);
+KernelFn backward_kernel(int mode, int per_thread, int threads, int KB, int K) {
+    return mode == 0 ? backward_kernel_softplus(mode, per_thread, threads, KB, K)
+                     : backward_kernel_clamp(mode, per_thread, threads, KB, K);
 }
 
 hipError_t launch_sim(KernelFn fn, int grid, int threads, const SimArgs &a, hipStream_t s) {

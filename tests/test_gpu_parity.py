@@ -52,12 +52,14 @@ def test_single_lane_1000_steps(mode):
 @pytest.mark.parametrize("mode", [MODE_SOFTPLUS, MODE_CLAMP])
 @pytest.mark.parametrize("shape", [(64, 1, 8, 8), (128, 2, 8, 8), (64, 4, 4, 4), (256, 1, 32, 32),
                                    (256, 1, 32, 16), (128, 1, 32, 8), (128, 2, 16, 16),
-                                   (64, 4, 8, 8), (64, 4, 24, 4)])
+                                   (64, 4, 8, 8), (64, 4, 24, 4), (1024, 1, 32, 16),
+                                   (512, 1, 32, 16), (512, 2, 32, 16), (256, 4, 16, 8)])
 def test_ragged_lanes_several_tiles(mode, shape):
     """Lanes of 1..256 vehicles (several work-group tiles, ragged bundle tails),
     S = 203 (ragged last checkpoint block and sub-block), checkpoint interval K
     with a backward register block KB dividing it (1 to 6 sub-blocks per
-    checkpoint block), dense upstream gradient + fused MSE."""
+    checkpoint block; K = 2 KB on the shapes with an LDS stash of the lower
+    sub-block), dense upstream gradient + fused MSE."""
     threads, per, K, KB = shape
     sizes = [1, 2, 3, 63, 64, 65, 100, 127, 31, 256, 0, 17, 200, 5, 90]
     cap = threads * per
