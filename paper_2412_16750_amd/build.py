@@ -1,7 +1,7 @@
 """Compile the HIP library ``libidmx.so`` for gfx950, in-tree.
 
 hipcc cross-compiles, so this runs without a GPU.  The kernels file is built
-three times (IDM_PART = 0, 1, 2) in parallel to shorten the build.
+five times (IDM_PART = 0..4) in parallel to shorten the build.
 """
 from __future__ import annotations
 
@@ -45,13 +45,13 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 8) -> str:
     """Compile every HIP source and link libidmx.so next to this file."""
     bdir = os.path.join(ROOT, "_build")
     os.makedirs(bdir, exist_ok=True)
     cc = hipcc()
     units = []
-    for part in (0, 1, 2):
+    for part in (0, 1, 2, 3, 4):
         units.append((os.path.join(CSRC, "idm_kernels.hip"), os.path.join(bdir, "idm_kernels_%d.o" % part),
                       ["-DIDM_PART=%d" % part]))
     units.append((os.path.join(CSRC, "idm_api.hip"), os.path.join(bdir, "idm_api.o"), []))

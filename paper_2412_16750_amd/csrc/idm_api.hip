@@ -388,7 +388,8 @@ idm_status run_backward(idm_plan *p, const idm_params *prm, const double *p0, co
     a.g_p0 = g_p0;
     a.g_v0 = g_v0;
     a.loss_part = (double *)((char *)ws + ws_loss_off(p));
-    KernelFn fn = backward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, p->sh.KB, p->sh.K);
+    KernelFn fn = backward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, p->sh.KB, p->sh.K,
+                                  gd || gv);
     if (!fn) return fail(IDM_ERR_UNSUPPORTED, "no backward kernel for this shape");
     if (p->n_bundles > 0) {
         hipError_t e = launch_sim(fn, grid_of(p), p->sh.threads, a, s);
@@ -855,6 +856,7 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
     if (r != IDM_OK) return r;
     if (reps < 1) return fail(IDM_ERR_INVALID_ARG, "reps must be >= 1");
     hipStream_t s = (hipStream_t)stream;
+    const bool dense = a->grad_traj_d || a->grad_traj_v;
     int dev = 0, cus = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -872,8 +874,8 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
                     const int K = k_fixed ? p->pb.ckpt_every : (twice ? 2 * KB : KB);
                     if (k_fixed && twice) break;
                     if (K % KB != 0 || ws_total(p, K) > ws_bytes) continue;
-                    KernelFn fb = backward_kernel(p->pb.bound, rr, t, KB, K);
-                    if (twice && fb == backward_kernel(p->pb.bound, rr, t, KB, KB)) continue;
+                    KernelFn fb = backward_kernel(p->pb.bound, rr, t, KB, K, dense);
+                    if (twice && fb == backward_kernel(p->pb.bound, rr, t, KB, KB, dense)) continue;
                     hipFuncAttributes fa;
                     // skip shapes whose backward spills more than a few registers
                     // (small spills sit outside the step loops)
@@ -901,7 +903,8 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
         for (int persistent = 0; persistent < 2; ++persistent) {
             Shape s2 = sh;
             if (persistent) {
-                KernelFn fb = backward_kernel(p->pb.bound, sh.per_thread, sh.threads, sh.KB, sh.K);
+                KernelFn fb =
+                    backward_kernel(p->pb.bound, sh.per_thread, sh.threads, sh.KB, sh.K, dense);
                 int occ = 0;
                 if (!fb || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fb, sh.threads, 0) !=
                                hipSuccess || occ < 1)

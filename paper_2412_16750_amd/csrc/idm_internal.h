@@ -66,8 +66,9 @@ using KernelFn = const void *;
 // Lookup of compiled kernel instantiations; nullptr when not instantiated.
 KernelFn forward_kernel(int mode, int per_thread, int threads);
 // Backward kernel for a register block KB and checkpoint interval K (the
-// stash variant when K = 2 KB and one is instantiated for the shape).
-KernelFn backward_kernel(int mode, int per_thread, int threads, int KB, int K);
+// stash variant when K = 2 KB and one is instantiated for the shape); `dense`
+// selects the variant that reads dense upstream gradients.
+KernelFn backward_kernel(int mode, int per_thread, int threads, int KB, int K, bool dense);
 
 // Launch helpers (return the HIP error of the launch).
 hipError_t launch_sim(KernelFn fn, int grid, int threads, const SimArgs &a, hipStream_t s);

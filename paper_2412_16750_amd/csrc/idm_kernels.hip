@@ -327,44 +327,36 @@ struct Up {
 // resource with zero records, whose loads return 0 without a memory access.
 struct UpCursor {
     int64_t row;     // byte offset of step k's row in the dense inputs (k N 4)
-    int64_t tg_row;  // byte offset of the current observation row (jq N 4)
-    int gap;         // steps from k down to the next observed step; INT_MAX if none
-    int jq;          // index of that observation
+    int64_t tg_row;  // byte offset of observation row `nobs` in the targets
+    int k;           // step the cursor is on
+    int nobs;        // largest observed step <= k, or INT_MIN if none is left
 };
 
 __device__ __forceinline__ void cursor_init(const SimArgs &A, int k, UpCursor &c) {
     const int64_t NB = A.n * 4;
+    c.k = k;
     c.row = (int64_t)k * NB;
-    c.gap = INT_MAX;
-    c.jq = -1;
+    c.nobs = INT_MIN;
     c.tg_row = 0;
     if (A.target && A.n_obs > 0 && k >= A.obs_first) {
-        const int last = A.obs_first + (A.n_obs - 1) * A.obs_stride;
-        if (k >= last) {
-            c.jq = A.n_obs - 1;
-            c.gap = k - last;
-        } else {
-            const int rel = k - A.obs_first;
-            c.jq = rel / A.obs_stride;
-            c.gap = rel - c.jq * A.obs_stride;
-        }
-        c.tg_row = (int64_t)c.jq * NB;
+        const int jq = min((k - A.obs_first) / A.obs_stride, A.n_obs - 1);
+        c.nobs = A.obs_first + jq * A.obs_stride;
+        c.tg_row = (int64_t)jq * NB;
     }
 }
 
-__device__ __forceinline__ bool cursor_obs(const UpCursor &c) { return c.gap == 0; }
+__device__ __forceinline__ bool cursor_obs(const UpCursor &c) { return c.k == c.nobs; }
 
 __device__ __forceinline__ void cursor_dec(const SimArgs &A, UpCursor &c) {
     const int64_t NB = A.n * 4;
+    if (c.k == c.nobs) {
+        // leaving an observed step: the previous observation is a stride lower
+        const int prev = c.nobs - A.obs_stride;
+        c.nobs = prev >= A.obs_first ? prev : INT_MIN;
+        c.tg_row -= NB;
+    }
+    c.k -= 1;
     c.row -= NB;
-    // leaving observation jq (gap 0): the previous one is a stride lower.  With
-    // no observation left, gap counts down from INT_MAX and cannot reach 0
-    // within a trajectory.
-    const bool at = c.gap == 0;
-    const bool more = c.jq > 0;
-    c.tg_row -= (at && more) ? NB : 0;
-    c.jq -= at ? 1 : 0;
-    c.gap = at ? (more ? A.obs_stride - 1 : INT_MAX) : c.gap - 1;
 }
 
 __device__ __forceinline__ float load_rec(const float *base, int64_t row, uint32_t bytes, int off) {
@@ -376,33 +368,45 @@ __device__ __forceinline__ float load_rec(const float *base, int64_t row, uint32
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
 }
 
-// Loads of the cursor's step (padding slots read vehicle 0's word).
-template <int R>
+// Loads of the cursor's step (padding slots read vehicle 0's word).  DN: the
+// dense upstream inputs may be present; without them only the target is read.
+// `live` = false (the cursor has passed step 0) reads nothing and gives zeros.
+template <int R, bool DN>
 __device__ __forceinline__ void fetch_up(const SimArgs &A, const UpCursor &c, const Veh (&q)[R],
-                                         Up (&u)[R]) {
+                                         bool live, Up (&u)[R]) {
     // an absent input keeps its (null) base: with zero records the resource's
     // address is never used
-    const uint32_t NB = (uint32_t)(A.n * 4);
+    const uint32_t NB = live ? (uint32_t)(A.n * 4) : 0u;
     const uint32_t bgd = A.gd ? NB : 0u, bgv = A.gv ? NB : 0u;
     const uint32_t btg = cursor_obs(c) ? NB : 0u;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int off = (q[r].g > 0 ? q[r].g : 0) * 4;
-        u[r].gd = load_rec(A.gd, c.row, bgd, off);
-        u[r].gv = load_rec(A.gv, c.row, bgv, off);
+        if constexpr (DN) {
+            u[r].gd = load_rec(A.gd, c.row, bgd, off);
+            u[r].gv = load_rec(A.gv, c.row, bgv, off);
+        } else {
+            u[r].gd = 0.0f;
+            u[r].gv = 0.0f;
+        }
         u[r].tg = load_rec(A.target, c.tg_row, btg, off);
     }
 }
 
-// Fused loss at one step: returns 2 (p - target) / |O| (residual in FP64) and
-// accumulates the squared residual; 0 when the step is not observed.
-__device__ __forceinline__ float mse_up(const SimArgs &A, bool observed, bool valid, const Up &u,
-                                        float d, double p0g, double &loss) {
+// Fused loss at one step: returns 2 (p - target) / |O| and adds the squared
+// residual to `lossf`; 0 when the step is not observed.  p0 = p0h + p0l is
+// split into two floats, and the residual is formed as ((p0h - target) + d)
+// + p0l: the first difference cancels exactly when p0h and the target are
+// within a factor of two, so the FP32 residual carries an error of about one
+// unit in its own last place rather than in the position's.
+__device__ __forceinline__ float mse_up(bool observed, bool valid, const Up &u, float d, float p0h,
+                                        float p0l, float two_inv, float &lossf) {
     float s = 0.0f;
     if (observed) {
-        double r = valid ? (p0g + (double)d) - (double)u.tg : 0.0;
-        loss = fma(r, r, loss);
-        s = (float)(r * A.two_inv_count);
+        float r = ((p0h - u.tg) + d) + p0l;
+        r = valid ? r : 0.0f;
+        lossf = fmaf(r, r, lossf);
+        s = r * two_inv;
     }
     return s;
 }
@@ -438,7 +442,10 @@ __device__ __forceinline__ void bundle_step(const SimArgs &A, const Veh (&q)[R],
 // upper one passes through every state of the lower one; they are kept in LDS
 // (KB x NT*R float2) and the lower sub-block's reverse sweep reads them there
 // instead of recomputing them, so each state of the block is computed once.
-template <int MODE, int R, int NT, int KB, bool ST>
+//
+// DN: a dense upstream gradient (dL/dd or dL/dv) may be given; without it the
+// kernel reads only the observed targets.
+template <int MODE, int R, int NT, int KB, bool ST, bool DN>
 __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
     __shared__ float2 sbuf[2][NT];
     __shared__ float2 cbuf[2][NT];
@@ -454,36 +461,41 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
     const int S = A.n_steps;
     const int K = A.K;
     const float dt = A.dt;
+    const float two_inv = (float)A.two_inv_count;
     const int nblk = (S + K - 1) / K;
     for (int bidx = blockIdx.x; bidx < A.n_bundles; bidx += gridDim.x) {
         Veh q[R];
         load_vehicles<R>(A, (int64_t)bidx * (NT * R) + t * R, q);
-        double p0g[R];
+        float p0h[R], p0l[R];  // p0 = p0h + p0l
         float ld[R], lv[R];
         // dL/dp0: the gap terms plus the fused loss's direct term (p = p0 + d);
         // a dense upstream dL/dd acts at fixed p0 and reaches p0 only via gaps
         float gp0[R];
         double gacc[5][R];
+        // squared residuals: FP32 per vehicle within a checkpoint block (the same
+        // grouping for every launch shape), FP64 across blocks and vehicles
         double loss = 0.0;
+        float lossf[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) lossf[r] = 0.0f;
         // upstream of the last step (the seed), and prefetch of step S-1
         Up seed[R], nxt[R];
         UpCursor cur_k;
         cursor_init(A, S, cur_k);
-        fetch_up<R>(A, cur_k, q, seed);
+        fetch_up<R, DN>(A, cur_k, q, true, seed);
         const bool obs_S = cursor_obs(cur_k);
-        bool obs_nxt = false;
-        if (S > 0) {
-            cursor_dec(A, cur_k);
-            fetch_up<R>(A, cur_k, q, nxt);
-            obs_nxt = cursor_obs(cur_k);
-        }
+        cursor_dec(A, cur_k);
+        fetch_up<R, DN>(A, cur_k, q, S > 0, nxt);
+        bool obs_nxt = S > 0 && cursor_obs(cur_k);
         // checkpoint of the last block
         float ckd[R], ckv[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int32_t gl = q[r].g > 0 ? q[r].g : 0;
             const int64_t crow = (int64_t)(nblk > 0 ? nblk - 1 : 0) * 2 * N;
-            p0g[r] = q[r].g >= 0 ? A.p0[gl] : 0.0;
+            const double p0 = q[r].g >= 0 ? A.p0[gl] : 0.0;
+            p0h[r] = (float)p0;
+            p0l[r] = (float)(p0 - (double)p0h[r]);
             ckd[r] = nblk > 0 ? A.ckpt[crow + gl] : 0.0f;
             ckv[r] = nblk > 0 ? A.ckpt[crow + N + gl] : 0.0f;
             ld[r] = 0.0f;
@@ -495,7 +507,7 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
         if (S == 0) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                gp0[r] = mse_up(A, obs_S, q[r].g >= 0, seed[r], 0.0f, p0g[r], loss);
+                gp0[r] = mse_up(obs_S, q[r].g >= 0, seed[r], 0.0f, p0h[r], p0l[r], two_inv, lossf[r]);
                 ld[r] = seed[r].gd + gp0[r];
                 lv[r] = seed[r].gv;
             }
@@ -584,8 +596,8 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                         // seed: upstream gradient at the last step S (d, v are now step S)
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
-                            const float um =
-                                mse_up(A, obs_S, q[r].g >= 0, seed[r], d[r], p0g[r], loss);
+                            const float um = mse_up(obs_S, q[r].g >= 0, seed[r], d[r], p0h[r],
+                                                    p0l[r], two_inv, lossf[r]);
                             gp0[r] += um;
                             ld[r] += seed[r].gd + um;
                             lv[r] += seed[r].gv;
@@ -625,12 +637,12 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
 #pragma unroll
                     for (int r = 0; r < R; ++r) cur[r] = nxt[r];
                     const bool obs_cur = obs_nxt;
-                    if (k > 0) {
-                        cursor_dec(A, cur_k);
-                        fetch_up<R>(A, cur_k, q, nxt);
-                        obs_nxt = cursor_obs(cur_k);
-                    }
+                    // prefetch step k-1 (nothing is read past step 0)
+                    cursor_dec(A, cur_k);
+                    fetch_up<R, DN>(A, cur_k, q, k > 0, nxt);
+                    obs_nxt = k > 0 && cursor_obs(cur_k);
                     float sd[R], sv[R];
+                    const float2 Lk = Lc;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         if constexpr (FS) {
@@ -641,18 +653,28 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                             sv[r] = hv[j][r];
                         }
                     }
+                    if constexpr (FS) {
+                        // next step's states, read now so that the LDS latency
+                        // overlaps this step's arithmetic
+                        if (j > 0) {
+#pragma unroll
+                            for (int r = 0; r < R; ++r) own[r] = stash[j - 1][t * R + r];
+                            Lc = stash[j - 1][tlv];
+                        }
+                    }
                     Part P[R];
                     float mu[R], mw[R], mwAs[R], um[R];
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        const float dh = r ? sd[r - 1] : Lc.x;
-                        const float vh = r ? sv[r - 1] : Lc.y;
+                        const float dh = r ? sd[r - 1] : Lk.x;
+                        const float vh = r ? sv[r - 1] : Lk.y;
                         partials<MODE>(q[r], sd[r], sv[r], dh, vh, dt, A.inv_dt, A.a_min,
                                        A.gap_floor, P[r]);
                         mu[r] = (MODE == 0) ? dt * lv[r] : P[r].gate * dt * lv[r];
                         mw[r] = mu[r] * P[r].w;
                         mwAs[r] = mw[r] * P[r].As;
-                        um[r] = mse_up(A, obs_cur, q[r].g >= 0, cur[r], sd[r], p0g[r], loss);
+                        um[r] = mse_up(obs_cur, q[r].g >= 0, cur[r], sd[r], p0h[r], p0l[r],
+                                       two_inv, lossf[r]);
                     }
                     // contribution of my first vehicle to its leader (previous
                     // thread): (mu d a*/d d_h, mu d a*/d v_h).  A lane head
@@ -662,12 +684,6 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                     if constexpr (!FS) {
                         if (j > 0)
                             sbuf[(j - 1) & 1][t] = make_float2(hd[j - 1][R - 1], hv[j - 1][R - 1]);
-                    } else {
-                        if (j > 0) {
-#pragma unroll
-                            for (int r = 0; r < R; ++r) own[r] = stash[j - 1][t * R + r];
-                            Lc = stash[j - 1][tlv];
-                        }
                     }
                     lds_barrier();
                     const float2 F = cbuf[j & 1][tf];
@@ -699,8 +715,13 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                         gs[3][r] = fmaf(mwAs[r], P[r].vdvc, gs[3][r]);  // a and b, through c
                         gs[4][r] += mwAs[r];                           // s0
                         gp0[r] += gterm + um[r];
-                        ld[r] = nld + (cur[r].gd + um[r]);
-                        lv[r] = nlv + cur[r].gv;
+                        if constexpr (DN) {
+                            ld[r] = nld + (cur[r].gd + um[r]);
+                            lv[r] = nlv + cur[r].gv;
+                        } else {
+                            ld[r] = nld + um[r];
+                            lv[r] = nlv;
+                        }
                     }
                 };
                 auto sweep_registers = [&]() {
@@ -729,8 +750,12 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                 gacc[2][r] += (double)gs[2][r] - (double)q[r].i2a * (double)gs[3][r];
                 gacc[3][r] -= (double)q[r].i2b * (double)gs[3][r];
                 gacc[4][r] += (double)gs[4][r];
+                loss += (double)lossf[r];
+                lossf[r] = 0.0f;
             }
         }
+#pragma unroll
+        for (int r = 0; r < R; ++r) loss += (double)lossf[r];  // S = 0: the seed's residual
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             int32_t g = q[r].g;
@@ -905,8 +930,9 @@ __global__ __launch_bounds__(256) void k_fit_init_u(AdamArgs A, const float *u_r
 
 // ---------------------------------------------------------------- dispatch
 //
-// The file is compiled three times (IDM_PART = 0, 1, 2) so the backward
-// instantiations of the two bound modes build in parallel.
+// The file is compiled five times (IDM_PART = 0..4) so the backward
+// instantiations of the two bound modes, with and without dense upstream
+// gradients, build in parallel.
 #ifndef IDM_PART
 #define IDM_PART 0
 #endif
@@ -927,12 +953,12 @@ KernelFn forward_kernel(int mode, int per_thread, int threads) {
 
 #define IDM_BWD_CASE(M, R, NT, KK)                                            \
     if (mode == M && per_thread == R && threads == NT && KB == KK)            \
-        return (KernelFn)&k_backward<M, R, NT, KK, false>;
+        return (KernelFn)&k_backward<M, R, NT, KK, false, IDM_DN>;
 // stash variants (checkpoint interval = two register blocks), for the shapes
 // whose stash fits next to the exchange buffers in the 160 KB of LDS
 #define IDM_BWD_ST(M, R, NT, KK)                                              \
     if (mode == M && per_thread == R && threads == NT && KB == KK && K == 2 * KK) \
-        return (KernelFn)&k_backward<M, R, NT, KK, true>;
+        return (KernelFn)&k_backward<M, R, NT, KK, true, IDM_DN>;
 #define IDM_BWD_NT(M, R, KK)                                                  \
     IDM_BWD_CASE(M, R, 64, KK) IDM_BWD_CASE(M, R, 128, KK) IDM_BWD_CASE(M, R, 256, KK) \
     IDM_BWD_CASE(M, R, 512, KK) IDM_BWD_CASE(M, R, 1024, KK)
@@ -943,24 +969,37 @@ KernelFn forward_kernel(int mode, int per_thread, int threads) {
     IDM_BWD_NT(M, 2, 8) IDM_BWD_NT(M, 2, 16) IDM_BWD_NT(M, 2, 32)                \
     IDM_BWD_NT(M, 4, 4) IDM_BWD_NT(M, 4, 8)
 
+// parts 1-4: (softplus, clamp) x (targets only, dense upstream)
+#if IDM_PART >= 1 && IDM_PART <= 4
+#define IDM_DN (IDM_PART >= 3)
 #if IDM_PART == 1
-KernelFn backward_kernel_softplus(int mode, int per_thread, int threads, int KB, int K) {
-    IDM_BWD_M(0)
-    return nullptr;
-}
+KernelFn backward_kernel_sp_t(int mode, int per_thread, int threads, int KB, int K) {
+#elif IDM_PART == 2
+KernelFn backward_kernel_cl_t(int mode, int per_thread, int threads, int KB, int K) {
+#elif IDM_PART == 3
+KernelFn backward_kernel_sp_d(int mode, int per_thread, int threads, int KB, int K) {
+#else
+KernelFn backward_kernel_cl_d(int mode, int per_thread, int threads, int KB, int K) {
 #endif
-#if IDM_PART == 2
-KernelFn backward_kernel_clamp(int mode, int per_thread, int threads, int KB, int K) {
+#if IDM_PART == 1 || IDM_PART == 3
+    IDM_BWD_M(0)
+#else
     IDM_BWD_M(1)
+#endif
     return nullptr;
 }
 #endif
 #if IDM_PART == 0
-KernelFn backward_kernel_softplus(int, int, int, int, int);
-KernelFn backward_kernel_clamp(int, int, int, int, int);
-KernelFn backward_kernel(int mode, int per_thread, int threads, int KB, int K) {
-    return mode == 0 ? backward_kernel_softplus(mode, per_thread, threads, KB, K)
-                     : backward_kernel_clamp(mode, per_thread, threads, KB, K);
+KernelFn backward_kernel_sp_t(int, int, int, int, int);
+KernelFn backward_kernel_cl_t(int, int, int, int, int);
+KernelFn backward_kernel_sp_d(int, int, int, int, int);
+KernelFn backward_kernel_cl_d(int, int, int, int, int);
+KernelFn backward_kernel(int mode, int per_thread, int threads, int KB, int K, bool dense) {
+    if (dense)
+        return mode == 0 ? backward_kernel_sp_d(mode, per_thread, threads, KB, K)
+                         : backward_kernel_cl_d(mode, per_thread, threads, KB, K);
+    return mode == 0 ? backward_kernel_sp_t(mode, per_thread, threads, KB, K)
+                     : backward_kernel_cl_t(mode, per_thread, threads, KB, K);
 }
 
 hipError_t launch_sim(KernelFn fn, int grid, int threads, const SimArgs &a, hipStream_t s) {
