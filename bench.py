@@ -42,8 +42,8 @@ PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
 # HBM bytes of one backward launch on this workload from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled by the copy-kernel calibration, 2.000 and 1.000), valid
 # only for the kernel source they were taken with (sha256 of idm_kernels.hip).
-TRAFFIC_BWD_BYTES = 1.2170e9
-TRAFFIC_KERNEL_SHA256 = "e39910b3b24ccb333a682a34f4e736f3d1f4d6e77770598055c684d88a2e7d0d"
+TRAFFIC_BWD_BYTES = 1.2596e9
+TRAFFIC_KERNEL_SHA256 = "5458ca7ef10a6575bd9a81d686b78ca8b2e31ff2b0120f15e387051e881cf95d"
 
 
 def log(*a):
@@ -162,6 +162,9 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
     f = Fitter(plan, length, p0, v, obs, lr0=1e-2)
     f.init(cold)
     rc = ws.fit_until(f, plan, length, p0, v, hidden, 0.5, chunk=10, cap=cap)
+    # one untimed warm start first: kernel loading and allocator growth are
+    # one-time process costs, not part of a fit
+    ws.warm_init(Fitter(plan, length, p0, v, obs, lr0=1e-2), net, plan, obs, p0, v, length, cold)
     f = Fitter(plan, length, p0, v, obs, lr0=1e-2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

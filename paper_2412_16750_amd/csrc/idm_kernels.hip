@@ -134,15 +134,14 @@ __device__ __forceinline__ float accel(const Veh &q, float d, float v, float dh,
     float x = v * q.inv_v0;
     float x2 = x * x;
     float gap = q.g0 + (dh - d);                      // Sec. III-A: p_h - p - len_h
-    float sg = gap > gap_floor ? gap : gap_floor;     // max(gap, floor), no NaN inputs
+    float sg = fmaxf(gap, gap_floor);
     float dv = v - vh;                                // Sec. III-A: v - v_h
     float s_opt = fmaf(v * dv, q.c, fmaf(v, q.T, q.s0));  // Eq. 1
     float s = (MODE == 0) ? softplus(s_opt) : s_opt;  // Sec. III-C floor on s_opt
     float qq = s * rcp_fast(sg);
     float ahat = q.a * (1.0f - fmaf(qq, qq, x2 * x2));   // Eq. 2, delta = 4
     if (MODE == 0) {
-        float nv = -v * inv_dt;
-        float lb = nv > a_min ? nv : a_min;             // Sec. III-C a_lb
+        float lb = fmaxf(-v * inv_dt, a_min);           // Sec. III-C a_lb
         return lb + softplus(ahat - lb);
     }
     return ahat;
