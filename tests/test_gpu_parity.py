@@ -158,6 +158,22 @@ def test_full_capacity_lanes():
         _check(sc, ref, out, "full capacity %s" % ((threads, per, K),))
 
 
+def test_lanes_far_from_origin():
+    """Lanes 250 km from the origin (an FP32 position step there is 1.6 cm): the
+    residual p0 + d - target is formed from a two-float split of p0, so loss and
+    gradients keep the oracle's accuracy although positions alone could not."""
+    sizes = [100, 37, 64, 1]
+    sc = ragged_scenario(sizes, 300, ckpt_every=32)
+    sc.p0 = sc.p0 + 2.5e5
+    steps = np.arange(2, sc.n_steps + 1, 2)
+    tgt = oracle_targets(sc, steps, c=9)
+    ref = oracle_reference(sc, steps, tgt)
+    out = gpu_run(sc, steps, tgt, threads=128, per_thread=1, tuning_k=32, block=16)
+    log("far lanes: loss %.9e vs oracle %.9e" % (out["loss"], ref["loss"]))
+    assert abs(out["loss"] - ref["loss"]) <= 1e-4 * ref["loss"]
+    _check(sc, ref, out, "far from origin")
+
+
 @pytest.mark.parametrize("mode", [MODE_CLAMP, MODE_SOFTPLUS])
 def test_equilibrium_platoon_on_gpu(mode):
     """An open-lane platoon at its equilibrium gaps (Eqs. 1-2 with dv = 0)
