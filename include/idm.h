@@ -340,6 +340,106 @@ idm_status idm_mlp_train_step(const idm_mlp_state *st, const uint16_t *X, const 
                               int64_t batch, int32_t t, double *loss_out, void *workspace,
                               void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Ego-only reconstruction (Sec. IV-A, trajectory filtering and reconstruction).
+ * Every trajectory is one vehicle starting at p(0) = 0 whose leader is not
+ * simulated: its bumper-to-bumper gap G_k and speed difference D_k = v - v_h
+ * at every step k are free variables next to the five parameters.  The loss
+ * is the sum over trajectories and their observations of |observed position -
+ * simulated position at the nearest step|.  Step-indexed arrays are
+ * step-major [S][N] FP32 on the device; every pointer is device memory owned
+ * by the caller unless stated otherwise.
+ * ------------------------------------------------------------------------- */
+typedef struct idm_ego_plan idm_ego_plan;
+
+typedef struct {
+    int32_t n_traj;     /* N trajectories, 1 <= N <= IDM_MAX_VEHICLES */
+    int32_t n_steps;    /* S >= 0 steps of dt */
+    int32_t ckpt_every; /* K: 8, 16 or 32 (0 = 32); checkpoint interval of the forward and
+                           register block of the backward */
+    float dt;           /* > 0, seconds */
+    float delta;        /* only 4 is implemented */
+    float a_min;        /* < 0 */
+    float gap_floor;    /* >= 0 */
+    int32_t bound;      /* IDM_BOUND_* */
+} idm_ego_problem;
+
+/* The fit variables: parameters [N] each (as idm_params) and the per-step
+ * gap G and speed difference D [S][N] (null allowed when S = 0). */
+typedef struct {
+    const float *v0, *T, *a, *b, *s0;
+    const float *gap, *dv;
+} idm_ego_vars;
+
+/* Observations, CSR by trajectory: trajectory i owns entries offsets[i] ..
+ * offsets[i+1]-1 (offsets[0] = 0, offsets[N] = n_obs), each a simulation step
+ * in 0..S (non-decreasing within a trajectory; idm_ego_match_steps maps
+ * timestamps to steps) and an observed position in the p(0) = 0 frame. */
+typedef struct {
+    const int32_t *offsets; /* [N+1] */
+    const int32_t *step;    /* [n_obs] */
+    const float *pos;       /* [n_obs], m */
+    int32_t n_obs;
+} idm_ego_obs;
+
+/* Validates the problem (host only) and allocates the plan (host memory). */
+idm_status idm_ego_plan_create(const idm_ego_problem *pb, idm_ego_plan **out);
+idm_status idm_ego_plan_destroy(idm_ego_plan *plan);
+/* Caller-allocated device workspace: loss partials, fit gradients, checkpoints. */
+size_t idm_ego_workspace_bytes(const idm_ego_plan *plan);
+/* Nearest simulation step of each timestamp (Sec. IV-A): step_out[j] =
+ * rint(t[j] / dt) in FP64, clamped to [0, n_steps]; t [m] FP64 seconds from
+ * the trajectory's first observation. */
+idm_status idm_ego_match_steps(const double *t, int32_t m, double dt, int32_t n_steps,
+                               int32_t *step_out, void *stream);
+/* Initial speed v(0) = max((P_1 - P_0) / (T_1 - T_0), 0) from each trajectory's
+ * first two observations (0 with fewer than two); t FP64, pos FP32, CSR. */
+idm_status idm_ego_initial_speed(const int32_t *offsets, const double *t, const float *pos,
+                                 int32_t n, float *v_init_out, void *stream);
+/* Forward: all S steps in one launch, one thread per trajectory; writes the
+ * checkpoints into the workspace and, where non-null, positions traj_p and
+ * speeds traj_v [(S+1)][N] and the acceleration of each update traj_a [S][N]
+ * (CLAMP: (v' - v) / dt). */
+idm_status idm_ego_forward(idm_ego_plan *plan, const idm_ego_vars *x, const float *v_init,
+                           float *traj_p, float *traj_v, float *traj_a, void *workspace,
+                           void *stream);
+/* Backward (needs the forward's checkpoints in the workspace): gradients of
+ * the summed absolute error (subgradient sign(p - obs), 0 at equality) with
+ * respect to the parameters grad_params [5][N] FP64, the free variables
+ * grad_gap, grad_dv [S][N] FP32 and v(0) grad_v0 [N] FP64 (nullable);
+ * loss_out (FP64, nullable) receives the loss. */
+idm_status idm_ego_backward(idm_ego_plan *plan, const idm_ego_vars *x, const float *v_init,
+                            const idm_ego_obs *obs, double *grad_params, float *grad_gap,
+                            float *grad_dv, double *grad_v0, double *loss_out, void *workspace,
+                            void *stream);
+
+/* Adam fit of the reconstruction (Sec. V-B3): parameters projected onto their
+ * boxes after every step, G and D unconstrained, learning rate linear from
+ * lr0 to lr1 over lr_steps steps. */
+typedef struct {
+    float *params;     /* [5][N] (v0, T, a, b, s0), updated in place */
+    float *gap, *dv;   /* [S][N], updated in place */
+    float *m, *v;      /* [5N + 2SN] Adam moments */
+    int32_t *step;     /* device step counter */
+    double *loss_hist; /* [hist_len] loss before each step (FP64) */
+    int32_t hist_len;
+    float lo[5], hi[5];
+    float lr0, lr1;
+    int32_t lr_steps;
+    float beta1, beta2, eps;
+} idm_ego_fit_state;
+
+/* Every trajectory's parameters = init_params (v0, T, a, b, s0), every G =
+ * gap0, every D = dv0, zero moments, step 0. */
+idm_status idm_ego_fit_init(idm_ego_plan *plan, const idm_ego_fit_state *st,
+                            const float init_params[5], float gap0, float dv0, void *stream);
+/* One fit step: forward, loss + gradients, loss history, Adam. */
+idm_status idm_ego_fit_step(idm_ego_plan *plan, const idm_ego_fit_state *st, const float *v_init,
+                            const idm_ego_obs *obs, void *workspace, void *stream);
+/* n_iters fit steps replayed from a HIP graph captured on first use. */
+idm_status idm_ego_fit_run(idm_ego_plan *plan, const idm_ego_fit_state *st, const float *v_init,
+                           const idm_ego_obs *obs, int32_t n_iters, void *workspace, void *stream);
+
 /* Thread-local description of the last error (never NULL). */
 const char *idm_last_error(void);
 

@@ -61,6 +61,15 @@ def lib():
         L.oracle_mse.argtypes = [i, i, pd, i, pi, pd, pd]
         L.oracle_mae_sum.restype = ctypes.c_double
         L.oracle_mae_sum.argtypes = [i, i, pd, i, pi, pd, pd]
+        ego = [i, d, d, d, d, i, i] + [pd] * 7
+        L.oracle_ego_forward.restype = ctypes.c_long
+        L.oracle_ego_forward.argtypes = ego + [pd, pd, pd, pd]
+        L.oracle_ego_adjoint.restype = ctypes.c_int
+        L.oracle_ego_adjoint.argtypes = ego + [pd] * 7
+        L.oracle_ego_tangent.restype = ctypes.c_int
+        L.oracle_ego_tangent.argtypes = ego + [pd] * 7
+        L.oracle_ego_mae.restype = ctypes.c_double
+        L.oracle_ego_mae.argtypes = [i, i, pd, pi, pi, pd, pd]
         _lib = L
     return _lib
 
@@ -170,3 +179,82 @@ def loss_and_grads(pb: Problem, steps, target, dense_grad=None):
         gP = gP + _d(dense_grad).reshape(gP.shape)
     g, gp0, gv0 = adjoint(pb, P, V, gP)
     return dict(P=P, V=V, loss=loss, g=g, gp0=gp0, gv0=gv0, floor_hits=hits)
+
+
+# --------------------------------------------------------------------------
+# Ego-only reconstruction (Sec. IV-A): one vehicle per trajectory, per-step
+# free gap G and speed difference D to an unsimulated leader, p(0) = 0, loss =
+# summed absolute error at the observed steps.
+
+
+class EgoProblem:
+    """n trajectories over n_steps steps; params [N] each, G and D [S, N]."""
+
+    def __init__(self, params: Dict[str, np.ndarray], G, D, v_init, n_steps: int,
+                 dt: float = 1.0, delta: float = 4.0, a_min: float = -10.0,
+                 gap_floor: float = 1e-3, mode: int = MODE_SOFTPLUS):
+        self.params = {k: _d(params[k]) for k in PARAM_NAMES}
+        self.n = len(self.params["v0"])
+        self.n_steps = int(n_steps)
+        self.G = _d(G).reshape(self.n_steps, self.n)
+        self.D = _d(D).reshape(self.n_steps, self.n)
+        self.v_init = _d(v_init)
+        self.dt, self.delta, self.a_min, self.gap_floor = float(dt), float(delta), float(a_min), float(gap_floor)
+        self.mode = int(mode)
+
+    def _head(self):
+        pr = self.params
+        return [self.mode, self.dt, self.delta, self.a_min, self.gap_floor, self.n, self.n_steps,
+                _p(pr["v0"]), _p(pr["T"]), _p(pr["a"]), _p(pr["b"]), _p(pr["s0"]), _p(self.G),
+                _p(self.D)]
+
+
+def ego_forward(pb: EgoProblem, want_acc: bool = False):
+    """Returns (P, V, A or None, floor_hits); P, V [(S+1), N], P(0) = 0."""
+    S, n = pb.n_steps, pb.n
+    P = np.empty((S + 1, n), dtype=np.float64)
+    V = np.empty((S + 1, n), dtype=np.float64)
+    A = np.empty((S, n), dtype=np.float64) if want_acc else None
+    hits = lib().oracle_ego_forward(*pb._head(), _p(pb.v_init), _p(P), _p(V), _p(A))
+    if hits < 0:
+        raise ValueError("oracle_ego_forward: invalid arguments")
+    return P, V, A, int(hits)
+
+
+def ego_adjoint(pb: EgoProblem, P, V, gP):
+    """Returns (g_params [5, N], g_G [S, N], g_D [S, N], g_v0 [N])."""
+    S, n = pb.n_steps, pb.n
+    g = np.empty((5, n), dtype=np.float64)
+    gG = np.empty((S, n), dtype=np.float64)
+    gD = np.empty((S, n), dtype=np.float64)
+    gv0 = np.empty(n, dtype=np.float64)
+    rc = lib().oracle_ego_adjoint(*pb._head(), _p(_d(P)), _p(_d(V)), _p(_d(gP).reshape(S + 1, n)),
+                                  _p(g), _p(gG), _p(gD), _p(gv0))
+    if rc != 0:
+        raise ValueError("oracle_ego_adjoint: invalid arguments")
+    return g, gG, gD, gv0
+
+
+def ego_tangent(pb: EgoProblem, V, dprm, dG, dD, dv0):
+    S, n = pb.n_steps, pb.n
+    dP = np.empty((S + 1, n), dtype=np.float64)
+    dV = np.empty((S + 1, n), dtype=np.float64)
+    rc = lib().oracle_ego_tangent(*pb._head(), _p(_d(V)), _p(_d(dprm).reshape(5, n)),
+                                  _p(_d(dG).reshape(S, n)), _p(_d(dD).reshape(S, n)), _p(_d(dv0)),
+                                  _p(dP), _p(dV))
+    if rc != 0:
+        raise ValueError("oracle_ego_tangent: invalid arguments")
+    return dP, dV
+
+
+def ego_mae(P, obs_off, obs_step, obs_pos, want_grad: bool = True):
+    """Summed absolute error over each trajectory's observations (CSR by
+    trajectory); returns (loss, dL/dP or None)."""
+    P = _d(P)
+    S1, n = P.shape
+    off = np.ascontiguousarray(np.asarray(obs_off, dtype=np.int32))
+    st = np.ascontiguousarray(np.asarray(obs_step, dtype=np.int32))
+    pos = _d(obs_pos)
+    gP = np.zeros_like(P) if want_grad else None
+    loss = lib().oracle_ego_mae(n, S1 - 1, _p(P), _p(off), _p(st), _p(pos), _p(gP))
+    return float(loss), gP

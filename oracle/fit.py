@@ -32,3 +32,15 @@ def adam_box_step(u, m, v, grad_theta, lo, hi, t, lr, beta1=0.9, beta2=0.999, ep
     u = u - lr * mh / (np.sqrt(vh) + eps)
     u = np.clip(u, 0.0, 1.0)                   # projection onto the box
     return u, m, v, lo + u * span
+
+
+def adam_raw_step(x, m, v, grad, lo, hi, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step directly on the variables x (the reconstruction fit of
+    Sec. IV-A / V-B3), then projection onto [lo, hi] (use -inf / inf for an
+    unconstrained variable); returns (x, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * grad
+    v = beta2 * v + (1.0 - beta2) * grad * grad
+    mh = m / (1.0 - beta1 ** t)
+    vh = v / (1.0 - beta2 ** t)
+    x = np.clip(x - lr * mh / (np.sqrt(vh) + eps), lo, hi)
+    return x, m, v

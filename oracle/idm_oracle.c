@@ -399,3 +399,151 @@ double oracle_mae_sum(int n, int n_steps, const double *P, int n_obs, const int 
     }
     return sum;
 }
+
+/* ------------------------------------------------------------------------
+ * Ego-only reconstruction (Sec. IV-A, trajectory filtering / reconstruction).
+ * Every trajectory i is one vehicle whose leader is not simulated: at each
+ * step k its bumper-to-bumper gap G[k*n+i] and its speed difference
+ * D[k*n+i] = v - v_h to the (unobserved) leader are free variables of the
+ * fit, and p(0) = 0.  The loss is the paper's summed absolute error between
+ * the observed positions and the simulated position at the nearest step.
+ *
+ * The leader relation enters Eqs. 1-2 only through (gap, v - v_h), so one ego
+ * step is the lane step of idm_local with a virtual leader of length 0 at
+ * p_h = gap (own position 0) and speed v_h = v - D.  Its partials map as
+ *   d acc / d G = d acc / d p_h,   d acc / d D = -d acc / d v_h,
+ *   d acc / d v (D fixed) = d acc / d v + d acc / d v_h,
+ * and the own position does not enter (the gap is given, not p_h - p).
+ * ------------------------------------------------------------------------ */
+static local_t ego_local(const cfg_t *c, double v, double gap, double dv, double v0, double T,
+                         double a, double b, double s0, int want)
+{
+    return idm_local(c, 1, 0.0, v, gap, v - dv, 0.0, v0, T, a, b, s0, want);
+}
+
+static int ego_check(const cfg_t *c, int n, int n_steps)
+{
+    if (n < 0 || n_steps < 0) return -1;
+    if (!(c->dt > 0.0) || !(c->gap_floor >= 0.0)) return -1;
+    if (c->mode != MODE_SOFTPLUS && c->mode != MODE_CLAMP) return -1;
+    return 0;
+}
+
+/*
+ * Ego forward: P, V [(n_steps+1)*n] (P(0) = 0, V(0) = v_init), A (nullable)
+ * [n_steps*n] the acceleration of each update (CLAMP: (v'-v)/dt).  Returns the
+ * number of steps with the gap floor active, or -1 on invalid arguments.
+ */
+long oracle_ego_forward(int mode, double dt, double delta, double a_min, double gap_floor,
+                        int n, int n_steps, const double *v0, const double *T, const double *a,
+                        const double *b, const double *s0, const double *G, const double *D,
+                        const double *v_init, double *P, double *V, double *A)
+{
+    cfg_t c = {mode, dt, delta, a_min, gap_floor};
+    if (ego_check(&c, n, n_steps)) return -1;
+    long hits = 0;
+    for (int i = 0; i < n; ++i) {
+        P[i] = 0.0;
+        V[i] = v_init[i];
+        for (int k = 0; k < n_steps; ++k) {
+            size_t at = (size_t)k * n + i, nx = (size_t)(k + 1) * n + i;
+            local_t r = ego_local(&c, V[at], G[at], D[at], v0[i], T[i], a[i], b[i], s0[i], 0);
+            double gate;
+            hits += r.floor_active;
+            P[nx] = P[at] + dt * V[at];                      /* Eq. 3, old speed */
+            V[nx] = speed_update(&c, V[at], r.acc, &gate);
+            if (A) A[at] = (mode == MODE_CLAMP) ? (V[nx] - V[at]) / dt : r.acc;
+        }
+    }
+    return hits;
+}
+
+/*
+ * Ego adjoint for the upstream gP = dL/dP [(n_steps+1)*n].  Outputs
+ * (overwritten): g_prm [5*n] (v0, T, a, b, s0), gG, gD [n_steps*n] (the
+ * per-step free variables), g_v0 [n] = dL/dv(0).
+ */
+int oracle_ego_adjoint(int mode, double dt, double delta, double a_min, double gap_floor,
+                       int n, int n_steps, const double *v0, const double *T, const double *a,
+                       const double *b, const double *s0, const double *G, const double *D,
+                       const double *P, const double *V, const double *gP, double *g_prm,
+                       double *gG, double *gD, double *g_v0)
+{
+    cfg_t c = {mode, dt, delta, a_min, gap_floor};
+    if (ego_check(&c, n, n_steps)) return -1;
+    (void)P;
+    for (int i = 0; i < n; ++i) {
+        double lp = gP[(size_t)n_steps * n + i], lv = 0.0;
+        double g[5] = {0, 0, 0, 0, 0};
+        for (int k = n_steps - 1; k >= 0; --k) {
+            size_t at = (size_t)k * n + i;
+            local_t r = ego_local(&c, V[at], G[at], D[at], v0[i], T[i], a[i], b[i], s0[i], 1);
+            double gate;
+            (void)speed_update(&c, V[at], r.acc, &gate);
+            double mu = gate * dt * lv;
+            gG[at] = mu * r.d_ph;
+            gD[at] = -mu * r.d_vh;
+            for (int j = 0; j < 5; ++j) g[j] += mu * r.d_prm[j];
+            double nlv = dt * lp + gate * lv + mu * (r.d_v + r.d_vh);
+            lp = gP[at] + lp;
+            lv = nlv;
+        }
+        for (int j = 0; j < 5; ++j) g_prm[(size_t)j * n + i] = g[j];
+        g_v0[i] = lv;
+    }
+    return 0;
+}
+
+/*
+ * Ego tangent-linear model: directions dprm [5*n], dG, dD [n_steps*n],
+ * dv0 [n] -> dP, dV [(n_steps+1)*n] (dP(0) = 0).  The adjoint is its exact
+ * transpose (dot-product test).
+ */
+int oracle_ego_tangent(int mode, double dt, double delta, double a_min, double gap_floor,
+                       int n, int n_steps, const double *v0, const double *T, const double *a,
+                       const double *b, const double *s0, const double *G, const double *D,
+                       const double *V, const double *dprm, const double *dG,
+                       const double *dD, const double *dv0, double *dP, double *dV)
+{
+    cfg_t c = {mode, dt, delta, a_min, gap_floor};
+    if (ego_check(&c, n, n_steps)) return -1;
+    for (int i = 0; i < n; ++i) {
+        dP[i] = 0.0;
+        dV[i] = dv0[i];
+        for (int k = 0; k < n_steps; ++k) {
+            size_t at = (size_t)k * n + i, nx = (size_t)(k + 1) * n + i;
+            local_t r = ego_local(&c, V[at], G[at], D[at], v0[i], T[i], a[i], b[i], s0[i], 1);
+            double gate;
+            (void)speed_update(&c, V[at], r.acc, &gate);
+            double dacc = (r.d_v + r.d_vh) * dV[at] + r.d_ph * dG[at] - r.d_vh * dD[at];
+            for (int j = 0; j < 5; ++j) dacc += r.d_prm[j] * dprm[(size_t)j * n + i];
+            dP[nx] = dP[at] + dt * dV[at];
+            dV[nx] = gate * (dV[at] + dt * dacc);
+        }
+    }
+    return 0;
+}
+
+/*
+ * The reconstruction loss (Sec. IV-A): for trajectory i with observations
+ * j = obs_off[i] .. obs_off[i+1]-1 at steps obs_step[j] (the nearest
+ * simulation step of each timestamp) and positions obs_pos[j],
+ *   L = sum_i sum_j |obs_pos[j] - P[obs_step[j]*n + i]|.
+ * Subgradient sign(P - obs) (0 at equality) is ADDED into gP.  Returns NAN
+ * for a step outside 0..n_steps.
+ */
+double oracle_ego_mae(int n, int n_steps, const double *P, const int *obs_off,
+                      const int *obs_step, const double *obs_pos, double *gP)
+{
+    double sum = 0.0;
+    for (int i = 0; i < n; ++i) {
+        for (int j = obs_off[i]; j < obs_off[i + 1]; ++j) {
+            int k = obs_step[j];
+            if (k < 0 || k > n_steps) return NAN;
+            double r = P[(size_t)k * n + i] - obs_pos[j];
+            sum += fabs(r);
+            if (gP) gP[(size_t)k * n + i] += (r > 0.0) - (r < 0.0);
+        }
+    }
+    return sum;
+}

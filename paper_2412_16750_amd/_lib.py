@@ -66,6 +66,29 @@ class IdmMlpState(ctypes.Structure):
 MLP_IN, MLP_IN_PAD, MLP_HIDDEN, MLP_OUT, MLP_OUT_PAD = 150, 160, 256, 5, 16
 
 
+class IdmEgoProblem(ctypes.Structure):
+    _fields_ = [("n_traj", c_int32), ("n_steps", c_int32), ("ckpt_every", c_int32),
+                ("dt", c_float), ("delta", c_float), ("a_min", c_float), ("gap_floor", c_float),
+                ("bound", c_int32)]
+
+
+class IdmEgoVars(ctypes.Structure):
+    _fields_ = [("v0", c_void_p), ("T", c_void_p), ("a", c_void_p), ("b", c_void_p),
+                ("s0", c_void_p), ("gap", c_void_p), ("dv", c_void_p)]
+
+
+class IdmEgoObs(ctypes.Structure):
+    _fields_ = [("offsets", c_void_p), ("step", c_void_p), ("pos", c_void_p), ("n_obs", c_int32)]
+
+
+class IdmEgoFitState(ctypes.Structure):
+    _fields_ = [("params", c_void_p), ("gap", c_void_p), ("dv", c_void_p), ("m", c_void_p),
+                ("v", c_void_p), ("step", c_void_p), ("loss_hist", c_void_p),
+                ("hist_len", c_int32), ("lo", c_float * 5), ("hi", c_float * 5),
+                ("lr0", c_float), ("lr1", c_float), ("lr_steps", c_int32),
+                ("beta1", c_float), ("beta2", c_float), ("eps", c_float)]
+
+
 class IdmStepArgs(ctypes.Structure):
     _fields_ = [("prm", IdmParams), ("p0", c_void_p), ("v_init", c_void_p),
                 ("traj_d", c_void_p), ("traj_v", c_void_p),
@@ -84,7 +107,10 @@ EXPORTS = ("idm_plan_create", "idm_plan_destroy", "idm_workspace_bytes", "idm_pl
            "idm_version", "idm_mlp_param_count", "idm_mlp_weight_bf16_count",
            "idm_mlp_workspace_bytes", "idm_mlp_sync", "idm_mlp_features", "idm_mlp_forward",
            "idm_mlp_gradients", "idm_mlp_train_step", "idm_fit_init_normalized", "idm_observe",
-           "idm_lane_loss", "idm_select_by_lane")
+           "idm_lane_loss", "idm_select_by_lane",
+           "idm_ego_plan_create", "idm_ego_plan_destroy", "idm_ego_workspace_bytes",
+           "idm_ego_match_steps", "idm_ego_initial_speed", "idm_ego_forward", "idm_ego_backward",
+           "idm_ego_fit_init", "idm_ego_fit_step", "idm_ego_fit_run")
 
 _lib = None
 
@@ -147,6 +173,26 @@ def load() -> ctypes.CDLL:
     for name in ("idm_mlp_sync", "idm_mlp_features", "idm_mlp_forward", "idm_mlp_gradients",
                  "idm_mlp_train_step", "idm_fit_init_normalized", "idm_observe", "idm_lane_loss",
                  "idm_select_by_lane"):
+        getattr(L, name).restype = c_int32
+    L.idm_ego_plan_create.argtypes = [P(IdmEgoProblem), P(c_void_p)]
+    L.idm_ego_plan_destroy.argtypes = [c_void_p]
+    L.idm_ego_workspace_bytes.argtypes = [c_void_p]
+    L.idm_ego_workspace_bytes.restype = c_size_t
+    L.idm_ego_match_steps.argtypes = [c_void_p, c_int32, c_double, c_int32, c_void_p, c_void_p]
+    L.idm_ego_initial_speed.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p]
+    L.idm_ego_forward.argtypes = [c_void_p, P(IdmEgoVars), c_void_p, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p]
+    L.idm_ego_backward.argtypes = [c_void_p, P(IdmEgoVars), c_void_p, P(IdmEgoObs), c_void_p,
+                                   c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.idm_ego_fit_init.argtypes = [c_void_p, P(IdmEgoFitState), P(c_float * 5), c_float, c_float,
+                                   c_void_p]
+    L.idm_ego_fit_step.argtypes = [c_void_p, P(IdmEgoFitState), c_void_p, P(IdmEgoObs), c_void_p,
+                                   c_void_p]
+    L.idm_ego_fit_run.argtypes = [c_void_p, P(IdmEgoFitState), c_void_p, P(IdmEgoObs), c_int32,
+                                  c_void_p, c_void_p]
+    for name in ("idm_ego_plan_create", "idm_ego_plan_destroy", "idm_ego_match_steps",
+                 "idm_ego_initial_speed", "idm_ego_forward", "idm_ego_backward", "idm_ego_fit_init",
+                 "idm_ego_fit_step", "idm_ego_fit_run"):
         getattr(L, name).restype = c_int32
     L.idm_last_error.restype = ctypes.c_char_p
     L.idm_version.restype = ctypes.c_char_p

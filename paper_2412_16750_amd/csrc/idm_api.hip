@@ -561,7 +561,8 @@ idm_status host_plan(const idm_problem *pb, const idm_tuning *tu, idm_plan *p, S
 
 // The stream graph work runs on: the caller's, or the side stream for the
 // null stream (made to wait for the null stream's prior work).
-idm_status graph_stream_enter(idm_plan *p, hipStream_t caller, hipStream_t *out) {
+template <class PL>
+idm_status graph_stream_enter(PL *p, hipStream_t caller, hipStream_t *out) {
     if (caller) {
         *out = caller;
         return IDM_OK;
@@ -581,7 +582,8 @@ idm_status graph_stream_enter(idm_plan *p, hipStream_t caller, hipStream_t *out)
 }
 
 // Make the null stream wait for the side stream's graph work.
-idm_status graph_stream_leave(idm_plan *p, hipStream_t caller) {
+template <class PL>
+idm_status graph_stream_leave(PL *p, hipStream_t caller) {
     if (caller) return IDM_OK;
     hipError_t e = hipEventRecord(p->ev_out, p->side);
     if (e == hipSuccess) e = hipStreamWaitEvent(nullptr, p->ev_out, 0);
@@ -941,6 +943,290 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
     idm_status r2 = build_layout(p, r == IDM_OK ? best_sh : orig);
     if (r != IDM_OK) return r;
     return r2;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- ego-only reconstruction
+
+struct idm_ego_plan {
+    idm_ego_problem pb{};
+    int32_t K = 32;
+    hipGraphExec_t fit_exec = nullptr;
+    std::vector<unsigned char> fit_key;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+namespace {
+
+int32_t ego_nblk(const idm_ego_plan *p) {
+    return p->pb.n_steps == 0 ? 0 : (p->pb.n_steps + p->K - 1) / p->K;
+}
+size_t ego_sn(const idm_ego_plan *p) { return (size_t)p->pb.n_steps * (size_t)p->pb.n_traj; }
+// Workspace: [loss parts N doubles][dL/dparams 5N doubles][dL/dG SN floats]
+//            [dL/dD SN floats][checkpoints nblk x 2 x N floats]
+size_t ego_ws_grad_prm(const idm_ego_plan *p) { return align_up(sizeof(double) * (size_t)p->pb.n_traj); }
+size_t ego_ws_grad_gap(const idm_ego_plan *p) {
+    return ego_ws_grad_prm(p) + align_up(sizeof(double) * 5 * (size_t)p->pb.n_traj);
+}
+size_t ego_ws_grad_dv(const idm_ego_plan *p) {
+    return ego_ws_grad_gap(p) + align_up(sizeof(float) * ego_sn(p));
+}
+size_t ego_ws_ckpt(const idm_ego_plan *p) { return ego_ws_grad_dv(p) + align_up(sizeof(float) * ego_sn(p)); }
+size_t ego_ws_total(const idm_ego_plan *p) {
+    return ego_ws_ckpt(p) + align_up(sizeof(float) * 2 * (size_t)ego_nblk(p) * (size_t)p->pb.n_traj);
+}
+
+idm_status ego_check_vars(const idm_ego_plan *p, const idm_ego_vars *x, const float *v_init,
+                          const void *ws) {
+    if (!x || !v_init || !ws) return fail(IDM_ERR_INVALID_ARG, "null argument");
+    if (!x->v0 || !x->T || !x->a || !x->b || !x->s0)
+        return fail(IDM_ERR_INVALID_ARG, "null parameter array");
+    if (p->pb.n_steps > 0 && (!x->gap || !x->dv))
+        return fail(IDM_ERR_INVALID_ARG, "null gap or speed-difference array");
+    return IDM_OK;
+}
+
+EgoArgs ego_args(const idm_ego_plan *p, const idm_ego_vars *x, const float *v_init, void *ws) {
+    EgoArgs a{};
+    a.n = p->pb.n_traj;
+    a.n_steps = p->pb.n_steps;
+    a.K = p->K;
+    a.dt = p->pb.dt;
+    a.inv_dt = 1.0f / p->pb.dt;
+    a.a_min = p->pb.a_min;
+    a.gap_floor = p->pb.gap_floor;
+    a.v0 = x->v0; a.T = x->T; a.a = x->a; a.b = x->b; a.s0 = x->s0;
+    a.gap = x->gap;
+    a.dv = x->dv;
+    a.v_init = v_init;
+    // no checkpoint is kept without steps (the region is empty)
+    a.ckpt = p->pb.n_steps > 0 ? (float *)((char *)ws + ego_ws_ckpt(p)) : nullptr;
+    return a;
+}
+
+idm_status ego_run_forward(idm_ego_plan *p, const EgoArgs &a, hipStream_t s) {
+    hipError_t e = launch_ego_forward(p->pb.bound, a, s);
+    return e == hipSuccess ? IDM_OK : hip_fail(e, "ego forward launch");
+}
+
+idm_status ego_run_backward(idm_ego_plan *p, EgoArgs a, const idm_ego_obs *obs, double *g_prm,
+                            float *g_gap, float *g_dv, double *g_v0, void *ws, hipStream_t s) {
+    a.obs_off = obs->offsets;
+    a.obs_step = obs->step;
+    a.obs_pos = obs->pos;
+    a.g_prm = g_prm;
+    a.g_gap = g_gap;
+    a.g_dv = g_dv;
+    a.g_v0 = g_v0;
+    a.loss_part = (double *)ws;
+    hipError_t e = launch_ego_backward(p->pb.bound, a, s);
+    return e == hipSuccess ? IDM_OK : hip_fail(e, "ego backward launch");
+}
+
+idm_status ego_check_obs(const idm_ego_obs *obs) {
+    if (!obs || !obs->offsets || obs->n_obs < 0 || (obs->n_obs > 0 && (!obs->step || !obs->pos)))
+        return fail(IDM_ERR_INVALID_ARG, "observations: null arrays or negative count");
+    return IDM_OK;
+}
+
+EgoAdamArgs ego_adam_args(const idm_ego_plan *p, const idm_ego_fit_state *st, void *ws) {
+    EgoAdamArgs a{};
+    a.n = p->pb.n_traj;
+    a.sn = (int64_t)ego_sn(p);
+    a.params = st->params;
+    a.gap = st->gap;
+    a.dv = st->dv;
+    a.m = st->m;
+    a.v = st->v;
+    if (ws) {
+        a.g_prm = (const double *)((char *)ws + ego_ws_grad_prm(p));
+        a.g_gap = (const float *)((char *)ws + ego_ws_grad_gap(p));
+        a.g_dv = (const float *)((char *)ws + ego_ws_grad_dv(p));
+    }
+    a.step = st->step;
+    a.step_rw = st->step;
+    for (int j = 0; j < 5; ++j) {
+        a.lo[j] = st->lo[j];
+        a.hi[j] = st->hi[j];
+    }
+    a.lr0 = st->lr0;
+    a.lr1 = st->lr1;
+    a.lr_steps = st->lr_steps;
+    a.beta1 = st->beta1;
+    a.beta2 = st->beta2;
+    a.eps = st->eps;
+    return a;
+}
+
+idm_status ego_check_fit(const idm_ego_plan *p, const idm_ego_fit_state *st, const float *v_init,
+                         const idm_ego_obs *obs, const void *ws) {
+    if (!p || !st || !v_init || !ws) return fail(IDM_ERR_INVALID_ARG, "null argument");
+    if (!st->params || !st->gap || !st->dv || !st->m || !st->v || !st->step || !st->loss_hist ||
+        st->hist_len < 1)
+        return fail(IDM_ERR_INVALID_ARG, "fit state: null arrays or hist_len < 1");
+    if (st->lr_steps < 1) return fail(IDM_ERR_INVALID_ARG, "fit state: lr_steps < 1");
+    for (int j = 0; j < 5; ++j)
+        if (!(st->lo[j] <= st->hi[j])) return fail(IDM_ERR_INVALID_ARG, "fit state: box %d empty", j);
+    return ego_check_obs(obs);
+}
+
+// forward (checkpoints only) -> backward into the workspace gradients ->
+// loss history + step counter -> Adam
+idm_status ego_run_fit_step(idm_ego_plan *p, const idm_ego_fit_state *st, const float *v_init,
+                            const idm_ego_obs *obs, void *ws, hipStream_t s) {
+    idm_ego_vars x{st->params, st->params + p->pb.n_traj, st->params + 2 * (size_t)p->pb.n_traj,
+                   st->params + 3 * (size_t)p->pb.n_traj, st->params + 4 * (size_t)p->pb.n_traj,
+                   st->gap, st->dv};
+    EgoArgs a = ego_args(p, &x, v_init, ws);
+    idm_status r = ego_run_forward(p, a, s);
+    if (r != IDM_OK) return r;
+    r = ego_run_backward(p, a, obs, (double *)((char *)ws + ego_ws_grad_prm(p)),
+                         (float *)((char *)ws + ego_ws_grad_gap(p)),
+                         (float *)((char *)ws + ego_ws_grad_dv(p)), nullptr, ws, s);
+    if (r != IDM_OK) return r;
+    hipError_t e = launch_fit_finalize((const double *)ws, p->pb.n_traj, 1.0, st->step,
+                                       st->loss_hist, st->hist_len, s);
+    if (e != hipSuccess) return hip_fail(e, "ego fit finalize launch");
+    e = launch_ego_adam(ego_adam_args(p, st, ws), s);
+    return e == hipSuccess ? IDM_OK : hip_fail(e, "ego Adam launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+idm_status idm_ego_plan_create(const idm_ego_problem *pb, idm_ego_plan **out) {
+    if (!pb || !out) return fail(IDM_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (pb->n_traj < 1 || pb->n_traj > IDM_MAX_VEHICLES || pb->n_steps < 0)
+        return fail(IDM_ERR_INVALID_ARG, "sizes: N=%d S=%d", pb->n_traj, pb->n_steps);
+    if (!(pb->dt > 0.0f) || !std::isfinite(pb->dt))
+        return fail(IDM_ERR_INVALID_ARG, "dt must be positive and finite");
+    if (!std::isfinite(pb->a_min) || !(pb->a_min < 0.0f))
+        return fail(IDM_ERR_INVALID_ARG, "a_min must be negative and finite");
+    if (!(pb->gap_floor >= 0.0f) || !std::isfinite(pb->gap_floor))
+        return fail(IDM_ERR_INVALID_ARG, "gap_floor must be >= 0");
+    if (pb->delta != 4.0f)
+        return fail(IDM_ERR_UNSUPPORTED, "delta=%g: only delta = 4 is implemented", pb->delta);
+    if (pb->bound != IDM_BOUND_SOFTPLUS && pb->bound != IDM_BOUND_CLAMP)
+        return fail(IDM_ERR_INVALID_ARG, "bound must be IDM_BOUND_SOFTPLUS or IDM_BOUND_CLAMP");
+    const int32_t K = pb->ckpt_every == 0 ? 32 : pb->ckpt_every;
+    if (K != 8 && K != 16 && K != 32)
+        return fail(IDM_ERR_UNSUPPORTED, "ego checkpoint interval %d: 8, 16 or 32", pb->ckpt_every);
+    idm_ego_plan *p = new idm_ego_plan();
+    p->pb = *pb;
+    p->K = K;
+    *out = p;
+    return IDM_OK;
+}
+
+idm_status idm_ego_plan_destroy(idm_ego_plan *p) {
+    if (!p) return IDM_OK;
+    if (p->fit_exec) hipGraphExecDestroy(p->fit_exec);
+    if (p->side) hipStreamDestroy(p->side);
+    if (p->ev_in) hipEventDestroy(p->ev_in);
+    if (p->ev_out) hipEventDestroy(p->ev_out);
+    delete p;
+    return IDM_OK;
+}
+
+size_t idm_ego_workspace_bytes(const idm_ego_plan *p) { return p ? ego_ws_total(p) : 0; }
+
+idm_status idm_ego_match_steps(const double *t, int32_t m, double dt, int32_t n_steps,
+                               int32_t *step_out, void *stream) {
+    if (m < 0 || (m > 0 && (!t || !step_out)) || !(dt > 0.0) || n_steps < 0)
+        return fail(IDM_ERR_INVALID_ARG, "match_steps: bad arguments");
+    if (m == 0) return IDM_OK;
+    hipError_t e = launch_ego_match_steps(t, m, dt, n_steps, step_out, (hipStream_t)stream);
+    return e == hipSuccess ? IDM_OK : hip_fail(e, "match_steps launch");
+}
+
+idm_status idm_ego_initial_speed(const int32_t *offsets, const double *t, const float *pos,
+                                 int32_t n, float *v_init_out, void *stream) {
+    if (n < 1 || !offsets || !t || !pos || !v_init_out)
+        return fail(IDM_ERR_INVALID_ARG, "initial_speed: bad arguments");
+    hipError_t e = launch_ego_initial_speed(offsets, t, pos, n, v_init_out, (hipStream_t)stream);
+    return e == hipSuccess ? IDM_OK : hip_fail(e, "initial_speed launch");
+}
+
+idm_status idm_ego_forward(idm_ego_plan *p, const idm_ego_vars *x, const float *v_init,
+                           float *traj_p, float *traj_v, float *traj_a, void *ws, void *stream) {
+    if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
+    idm_status r = ego_check_vars(p, x, v_init, ws);
+    if (r != IDM_OK) return r;
+    EgoArgs a = ego_args(p, x, v_init, ws);
+    a.traj_p = traj_p;
+    a.traj_v = traj_v;
+    a.traj_a = traj_a;
+    return ego_run_forward(p, a, (hipStream_t)stream);
+}
+
+idm_status idm_ego_backward(idm_ego_plan *p, const idm_ego_vars *x, const float *v_init,
+                            const idm_ego_obs *obs, double *grad_params, float *grad_gap,
+                            float *grad_dv, double *grad_v0, double *loss_out, void *ws,
+                            void *stream) {
+    if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
+    idm_status r = ego_check_vars(p, x, v_init, ws);
+    if (r != IDM_OK) return r;
+    r = ego_check_obs(obs);
+    if (r != IDM_OK) return r;
+    if (!grad_params || (p->pb.n_steps > 0 && (!grad_gap || !grad_dv)))
+        return fail(IDM_ERR_INVALID_ARG, "null gradient output");
+    hipStream_t s = (hipStream_t)stream;
+    EgoArgs a = ego_args(p, x, v_init, ws);
+    r = ego_run_backward(p, a, obs, grad_params, grad_gap, grad_dv, grad_v0, ws, s);
+    if (r != IDM_OK) return r;
+    if (loss_out) {
+        hipError_t e = launch_loss_finalize((const double *)ws, p->pb.n_traj, 1.0, loss_out, s);
+        if (e != hipSuccess) return hip_fail(e, "ego loss finalize launch");
+    }
+    return IDM_OK;
+}
+
+idm_status idm_ego_fit_init(idm_ego_plan *p, const idm_ego_fit_state *st, const float init_params[5],
+                            float gap0, float dv0, void *stream) {
+    if (!p || !st || !init_params || !st->params || !st->gap || !st->dv || !st->m || !st->v ||
+        !st->step)
+        return fail(IDM_ERR_INVALID_ARG, "null argument");
+    hipError_t e = launch_ego_fit_init(ego_adam_args(p, st, nullptr), init_params, gap0, dv0,
+                                       (hipStream_t)stream);
+    return e == hipSuccess ? IDM_OK : hip_fail(e, "ego fit init launch");
+}
+
+idm_status idm_ego_fit_step(idm_ego_plan *p, const idm_ego_fit_state *st, const float *v_init,
+                            const idm_ego_obs *obs, void *ws, void *stream) {
+    idm_status r = ego_check_fit(p, st, v_init, obs, ws);
+    if (r != IDM_OK) return r;
+    return ego_run_fit_step(p, st, v_init, obs, ws, (hipStream_t)stream);
+}
+
+idm_status idm_ego_fit_run(idm_ego_plan *p, const idm_ego_fit_state *st, const float *v_init,
+                           const idm_ego_obs *obs, int32_t n_iters, void *ws, void *stream) {
+    idm_status r = ego_check_fit(p, st, v_init, obs, ws);
+    if (r != IDM_OK) return r;
+    if (n_iters < 0) return fail(IDM_ERR_INVALID_ARG, "n_iters < 0");
+    hipStream_t s = nullptr;
+    r = graph_stream_enter(p, (hipStream_t)stream, &s);
+    if (r != IDM_OK) return r;
+    std::vector<unsigned char> key(sizeof(idm_ego_fit_state) + sizeof(idm_ego_obs) + 2 * sizeof(void *));
+    memcpy(key.data(), st, sizeof(idm_ego_fit_state));
+    memcpy(key.data() + sizeof(idm_ego_fit_state), obs, sizeof(idm_ego_obs));
+    const void *ptrs[2] = {v_init, ws};
+    memcpy(key.data() + sizeof(idm_ego_fit_state) + sizeof(idm_ego_obs), ptrs, sizeof ptrs);
+    if (!p->fit_exec || p->fit_key != key) {
+        if (p->fit_exec) hipGraphExecDestroy(p->fit_exec);
+        p->fit_exec = nullptr;
+        r = capture(s, &p->fit_exec, [&]() { return ego_run_fit_step(p, st, v_init, obs, ws, s); });
+        if (r != IDM_OK) return r;
+        p->fit_key = key;
+    }
+    for (int32_t i = 0; i < n_iters; ++i) {
+        hipError_t e = hipGraphLaunch(p->fit_exec, s);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch(ego fit)");
+    }
+    return graph_stream_leave(p, (hipStream_t)stream);
 }
 
 }  // extern "C"

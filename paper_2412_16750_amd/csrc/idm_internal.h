@@ -61,6 +61,43 @@ struct AdamArgs {
     float beta1, beta2, eps;
 };
 
+// Ego-only reconstruction (one vehicle per trajectory, per-step free gap and
+// speed difference to an unsimulated leader).
+struct EgoArgs {
+    int64_t n;          // trajectories N
+    int32_t n_steps;    // S
+    int32_t K;          // checkpoint interval
+    float dt, inv_dt, a_min, gap_floor;
+    const float *v0, *T, *a, *b, *s0;  // [N]
+    const float *gap, *dv;             // [S][N]
+    const float *v_init;               // [N]
+    float *traj_p, *traj_v, *traj_a;   // nullable: [(S+1)][N], [(S+1)][N], [S][N]
+    float *ckpt;                       // [nblk][2][N]
+    // backward
+    const int32_t *obs_off;            // [N+1]
+    const int32_t *obs_step;           // [M], non-decreasing within a trajectory
+    const float *obs_pos;              // [M]
+    double *g_prm;                     // [5][N]
+    float *g_gap, *g_dv;               // [S][N]
+    double *g_v0;                      // [N], nullable
+    double *loss_part;                 // [N] summed absolute error per trajectory
+};
+
+struct EgoAdamArgs {
+    int64_t n, sn;                     // N, S*N
+    float *params;                     // [5][N] physical parameters
+    float *gap, *dv;                   // [S][N]
+    float *m, *v;                      // [5N + 2SN] moments
+    const double *g_prm;               // [5][N]
+    const float *g_gap, *g_dv;         // [S][N]
+    const int32_t *step;               // 1-based step after the finalize kernel
+    int32_t *step_rw;
+    float lo[5], hi[5];
+    float lr0, lr1;
+    int32_t lr_steps;
+    float beta1, beta2, eps;
+};
+
 using KernelFn = const void *;
 
 // Lookup of compiled kernel instantiations; nullptr when not instantiated.
@@ -77,6 +114,17 @@ hipError_t launch_loss_finalize(const double *part, int32_t n_part, double scale
 hipError_t launch_fit_finalize(const double *part, int32_t n_part, double scale,
                                int32_t *step, double *hist, int32_t hist_len, hipStream_t s);
 hipError_t launch_adam(const AdamArgs &a, hipStream_t s);
+// Ego-only reconstruction kernels (block = one checkpoint interval K for the
+// backward; K must be 8, 16 or 32).
+hipError_t launch_ego_forward(int mode, const EgoArgs &a, hipStream_t s);
+hipError_t launch_ego_backward(int mode, const EgoArgs &a, hipStream_t s);
+hipError_t launch_ego_adam(const EgoAdamArgs &a, hipStream_t s);
+hipError_t launch_ego_fit_init(const EgoAdamArgs &a, const float *init5, float gap0, float dv0,
+                               hipStream_t s);
+hipError_t launch_ego_match_steps(const double *t, int32_t m, double dt, int32_t n_steps,
+                                  int32_t *step_out, hipStream_t s);
+hipError_t launch_ego_initial_speed(const int32_t *off, const double *t, const float *pos,
+                                    int64_t n, float *v_out, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, int64_t n16, int grid, hipStream_t s);
 hipError_t launch_params_from_u(const AdamArgs &a, hipStream_t s);
 hipError_t launch_fit_init(const AdamArgs &a, const float *init, hipStream_t s);

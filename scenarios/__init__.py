@@ -277,3 +277,89 @@ def warm_training(n_lanes: int = 1000, lane_len: int = 1000, n_steps: int = 500,
     sc.extra["obs_first"] = obs_every
     sc.extra["obs_stride"] = obs_every
     return sc
+
+
+# ---------------------------------------------------------------------------
+# Sparse observed trajectories for the ego-only reconstruction (Sec. IV-A /
+# V-B): stand-ins for the paper's trajectory sets (NGSIM at 10 Hz for filtering,
+# a non-public set of 21,750 trajectories sampled at >= 1 s and up to 20 min
+# long for reconstruction), which are not available here.  A trajectory is a
+# smooth random speed profile (a mean plus three sinusoids of 30-300 s period
+# whose slopes stay within 0.5 m/s^2 each, floored at 0), integrated on a
+# 0.1 s grid and sampled at irregular times, with N(0, sigma) position noise;
+# times and positions are taken relative to the first sample (p(0) = 0).  No
+# traffic model is involved.
+
+@dataclass
+class EgoData:
+    """CSR by trajectory: t [M] (s, FP64), pos [M] (m, FP64), offsets [N+1]."""
+    offsets: np.ndarray
+    t: np.ndarray
+    pos: np.ndarray
+    duration: np.ndarray  # [N] time of the last sample (s)
+    dt: float             # simulation step of the reconstruction
+    n_steps: int          # steps that cover the longest trajectory
+
+    @property
+    def n(self) -> int:
+        return len(self.offsets) - 1
+
+
+def ego_trajectories(n_traj: int, c: int, dt: float = 1.0, min_s: float = 120.0,
+                     max_s: float = 1200.0, min_gap: float = 1.0, mean_extra_gap: float = 4.0,
+                     sigma: float = 0.5, dense: bool = False) -> EgoData:
+    """n_traj synthetic observed trajectories (seeds 6000 + c).  Sparse
+    sampling: intervals min_gap + Exp(mean_extra_gap) s; dense (filtering):
+    every dt."""
+    rng = np.random.default_rng(6000 + c)
+    dur = rng.uniform(min_s, max_s, n_traj)
+    ts, ps, counts = [], [], []
+    for i in range(n_traj):
+        if dense:
+            t = np.arange(0.0, dur[i] + 1e-9, dt)
+        else:
+            gaps = min_gap + rng.exponential(mean_extra_gap, int(dur[i] / min_gap) + 2)
+            t = np.concatenate([[0.0], np.cumsum(gaps)])
+            t = t[t <= dur[i]]
+        grid = np.arange(0.0, t[-1] + 0.1 + 1e-9, 0.1)
+        vbar = rng.uniform(8.0, 25.0)
+        per = rng.uniform(30.0, 300.0, 3)
+        amp = rng.uniform(0.0, 0.5, 3) * per / (2 * np.pi)
+        ph = rng.uniform(0.0, 2 * np.pi, 3)
+        v = vbar + np.sum(amp[:, None] * np.sin(2 * np.pi * grid[None, :] / per[:, None] + ph[:, None]),
+                          axis=0)
+        v = np.maximum(v, 0.0)
+        x = np.concatenate([[0.0], np.cumsum(0.5 * (v[1:] + v[:-1]) * 0.1)])
+        p = np.interp(t, grid, x) + rng.normal(0.0, sigma, len(t))
+        ts.append(t - t[0])
+        ps.append(p - p[0])
+        counts.append(len(t))
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    t_all = np.concatenate(ts)
+    dur_obs = np.array([t[-1] for t in ts])
+    return EgoData(off, t_all, np.concatenate(ps), dur_obs, float(dt),
+                   int(np.ceil(dur_obs.max() / dt)) + 1)
+
+
+def reconstruction(n_traj: int = 21750, c: int = 6) -> EgoData:
+    """The reconstruction workload: 21,750 trajectories, >= 1 s sampling, up to
+    20 minutes, simulated with dt = 1 s."""
+    return ego_trajectories(n_traj, c, dt=1.0)
+
+
+def filtering(n_traj: int = 6101, c: int = 7) -> EgoData:
+    """The filtering workload: 6,101 trajectories observed every 0.1 s (NGSIM
+    rate), 30 s to 3 min long, simulated with dt = 0.1 s."""
+    return ego_trajectories(n_traj, c, dt=0.1, min_s=30.0, max_s=180.0, sigma=0.3, dense=True)
+
+
+def ego_free_variables(n_traj: int, n_steps: int, c: int):
+    """Random parameters [5, N] (config ranges), gap G [S, N] in [8, 40] m and
+    speed difference D [S, N] ~ N(0, 1.5) for parity tests (seeds 7000 + c)."""
+    rng = np.random.default_rng(7000 + c)
+    prm = draw_params(rng, n_traj)
+    P = np.stack([prm[k] for k in PARAM_NAMES]).astype(np.float32)
+    G = rng.uniform(8.0, 40.0, (n_steps, n_traj)).astype(np.float32)
+    D = rng.normal(0.0, 1.5, (n_steps, n_traj)).astype(np.float32)
+    v = rng.uniform(8.0, 25.0, n_traj).astype(np.float32)
+    return P, G, D, v

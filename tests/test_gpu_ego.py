@@ -1,0 +1,186 @@
+"""Ego-only reconstruction (Sec. IV-A) on the GPU against the FP64 oracle:
+forward trajectories, the summed absolute error and its gradients with respect
+to the parameters, the per-step gap and speed difference and v(0); the step
+matching and initial speed kernels; the Adam fit (eager steps vs graph
+replays, loss history vs the oracle's Adam)."""
+import numpy as np
+import pytest
+
+import oracle
+import scenarios
+from oracle.fit import adam_raw_step, lr_at
+from _util import grad_close, pos_close
+from gpu_run import log
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(n=150, mode=scenarios.MODE_SOFTPLUS, c=1, min_s=60.0, max_s=200.0, K=0):
+    import torch
+    from paper_2412_16750_amd import ego
+    data = scenarios.ego_trajectories(n, c, dt=1.0, min_s=min_s, max_s=max_s)
+    S = data.n_steps
+    P, G, D, v = scenarios.ego_free_variables(n, S, c)
+    steps = np.clip(np.rint(data.t / data.dt), 0, S).astype(np.int32)
+    pos32 = data.pos.astype(np.float32)
+    dev = "cuda"
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    plan = ego.EgoPlan(n, S, dt=data.dt, bound=mode, ckpt_every=K)
+    x = dict(params=T(P), gap=T(G), dv=T(D), v=T(v),
+             obs=ego.EgoObs(T(data.offsets), T(steps), T(pos32)), ws=plan.workspace(dev))
+    pb = oracle.EgoProblem(dict(zip(oracle.PARAM_NAMES, P.astype(np.float64))), G, D, v, S,
+                           dt=data.dt, mode=mode)
+    return data, plan, x, pb, steps, pos32
+
+
+def _gpu_all(plan, x):
+    import torch
+    from paper_2412_16750_amd import ego
+    n, S = plan.n, plan.n_steps
+    Pt = torch.empty(S + 1, n, dtype=torch.float32, device="cuda")
+    Vt = torch.empty_like(Pt)
+    At = torch.empty(S, n, dtype=torch.float32, device="cuda")
+    ego.idm_ego_forward(plan, x["params"], x["gap"], x["dv"], x["v"], x["ws"], Pt, Vt, At)
+    g = torch.empty(5, n, dtype=torch.float64, device="cuda")
+    gG = torch.empty(S, n, dtype=torch.float32, device="cuda")
+    gD = torch.empty_like(gG)
+    gv0 = torch.empty(n, dtype=torch.float64, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ego.idm_ego_backward(plan, x["params"], x["gap"], x["dv"], x["v"], x["obs"], g, gG, gD, x["ws"],
+                         gv0, loss)
+    torch.cuda.synchronize()
+    return dict(P=Pt.double().cpu().numpy(), V=Vt.double().cpu().numpy(), A=At.double().cpu().numpy(),
+                g=g.cpu().numpy(), gG=gG.double().cpu().numpy(), gD=gD.double().cpu().numpy(),
+                gv0=gv0.cpu().numpy(), loss=float(loss.item()))
+
+
+@pytest.mark.parametrize("mode", [scenarios.MODE_SOFTPLUS, scenarios.MODE_CLAMP])
+@pytest.mark.parametrize("K", [0, 16, 8])
+def test_ego_forward_backward_match_oracle(mode, K):
+    data, plan, x, pb, steps, pos32 = _setup(mode=mode, K=K)
+    out = _gpu_all(plan, x)
+    P, V, A, hits = oracle.ego_forward(pb, want_acc=True)
+    loss, gP = oracle.ego_mae(P, data.offsets, steps, pos32.astype(np.float64))
+    g, gG, gD, gv0 = oracle.ego_adjoint(pb, P, V, gP)
+    # every residual after step 0 is far from 0, so FP32 and FP64 take the same
+    # signs; at step 0 both sides hold p = 0 and the observation 0 exactly
+    r = P[steps, np.repeat(np.arange(plan.n), np.diff(data.offsets))] - pos32
+    later = steps > 0
+    log("ego mode=%d K=%d: S=%d, %d obs, min |residual| after step 0 %.3f m, floor hits %d"
+        % (mode, K, plan.n_steps, len(steps), np.abs(r[later]).min(), hits))
+    assert np.abs(r[later]).min() > 1e-2 and np.all(r[~later] == 0) and hits == 0
+    ok, maxerr, worst = pos_close(out["P"], P, rtol=1e-4)
+    log("ego positions max err %.3e m (worst/limit %.3f)" % (maxerr, worst))
+    assert ok
+    assert np.allclose(out["V"], V, rtol=1e-4, atol=1e-3)
+    assert np.allclose(out["A"], A, rtol=1e-3, atol=1e-3)
+    assert abs(out["loss"] - loss) <= 1e-4 * loss
+    where = []
+    okg, wg = grad_close(out["g"], g, rtol=1e-3, where=where)
+    okG, wG = grad_close(out["gG"].T, gG.T, rtol=1e-3)
+    okD, wD = grad_close(out["gD"].T, gD.T, rtol=1e-3)
+    okv, wv = grad_close(out["gv0"], gv0, rtol=1e-3)
+    log("ego gradients worst/limit: params %.3f G %.3f D %.3f v0 %.3f %s" % (wg, wG, wD, wv, where))
+    assert okg and okG and okD and okv
+
+
+def test_ego_edge_cases():
+    """A trajectory without observations gets zero gradients and zero loss; S = 0."""
+    import torch
+    from paper_2412_16750_amd import ego
+    data, plan, x, pb, steps, pos32 = _setup(n=70, c=2)
+    off = data.offsets.copy()
+    # drop every observation of trajectories 3 and 40
+    keep = np.ones(len(steps), bool)
+    for i in (3, 40):
+        keep[off[i]:off[i + 1]] = False
+    counts = np.diff(off)
+    counts[[3, 40]] = 0
+    off2 = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    x["obs"] = ego.EgoObs(T(off2), T(steps[keep]), T(pos32[keep]))
+    out = _gpu_all(plan, x)
+    for i in (3, 40):
+        assert np.all(out["g"][:, i] == 0) and np.all(out["gG"][:, i] == 0) and out["gv0"][i] == 0
+    P, V, _, _ = oracle.ego_forward(pb)
+    loss, gP = oracle.ego_mae(P, off2, steps[keep], pos32[keep].astype(np.float64))
+    assert abs(out["loss"] - loss) <= 1e-4 * loss
+    # zero steps: positions stay 0, the loss is the sum of |obs| at step 0
+    plan0 = ego.EgoPlan(3, 0, dt=1.0)
+    ws0 = plan0.workspace()
+    prm = torch.full((5, 3), 2.0, device="cuda")
+    e = torch.empty(0, device="cuda")
+    v = torch.full((3,), 10.0, device="cuda")
+    Pt = torch.empty(1, 3, device="cuda")
+    ego.idm_ego_forward(plan0, prm, e, e, v, ws0, Pt)
+    obs0 = ego.EgoObs(T(np.array([0, 1, 1, 3], np.int32)), T(np.zeros(3, np.int32)),
+                      T(np.array([1.5, -2.0, 0.5], np.float32)))
+    g = torch.empty(5, 3, dtype=torch.float64, device="cuda")
+    gv0 = torch.empty(3, dtype=torch.float64, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ego.idm_ego_backward(plan0, prm, e, e, v, obs0, g, e, e, ws0, gv0, loss)
+    assert float(loss.item()) == pytest.approx(4.0) and np.all(Pt.cpu().numpy() == 0)
+    assert np.all(g.cpu().numpy() == 0) and np.all(gv0.cpu().numpy() == 0)
+
+
+def test_ego_match_steps_and_initial_speed():
+    import torch
+    from paper_2412_16750_amd import ego
+    data = scenarios.ego_trajectories(300, 3, dt=1.0)
+    t = torch.from_numpy(data.t).cuda()
+    st = ego.match_steps(t, data.dt, data.n_steps).cpu().numpy()
+    assert np.array_equal(st, np.clip(np.rint(data.t / data.dt), 0, data.n_steps).astype(np.int32))
+    pos = torch.from_numpy(data.pos.astype(np.float32)).cuda()
+    off = torch.from_numpy(data.offsets).cuda()
+    v = ego.initial_speed(off, t, pos).cpu().numpy()
+    o = data.offsets
+    p32 = data.pos.astype(np.float32).astype(np.float64)
+    expect = np.maximum((p32[o[:-1] + 1] - p32[o[:-1]]) / (data.t[o[:-1] + 1] - data.t[o[:-1]]), 0)
+    assert np.allclose(v, expect, rtol=1e-6, atol=1e-6)
+
+
+def test_ego_fit_graph_matches_eager_and_oracle_adam():
+    """Eight fit steps: eager steps and graph replays give bitwise equal
+    variables; the GPU's loss history follows the oracle's Adam on the same
+    problem (paper initialisation, lr 0.1 -> 0.01)."""
+    import torch
+    from paper_2412_16750_amd import ego
+    data, plan, x, pb, steps, pos32 = _setup(n=60, c=4)
+    n, S = plan.n, plan.n_steps
+    v_init = ego.initial_speed(x["obs"].offsets, torch.from_numpy(data.t).cuda(), x["obs"].pos)
+    fa = ego.EgoFitter(plan, v_init, x["obs"])
+    fb = ego.EgoFitter(plan, v_init, x["obs"])
+    fa.init()
+    fb.init()
+    iters = 8
+    for _ in range(iters):
+        fa.step()
+    fb.run(iters)
+    torch.cuda.synchronize()
+    for k in ("params", "gap", "dv", "m", "v"):
+        assert torch.equal(getattr(fa, k), getattr(fb, k)), k
+    la = fa.losses().numpy()
+    assert np.array_equal(la, fb.losses().numpy()) and len(la) == iters
+    # the oracle's Adam on the same problem
+    lo = np.array([b[0] for b in ego.PAPER_BOXES])[:, None]
+    hi = np.array([b[1] for b in ego.PAPER_BOXES])[:, None]
+    prm = np.tile(np.array(ego.PAPER_INIT, np.float64)[:, None], (1, n))
+    G = np.full((S, n), ego.PAPER_GAP0)
+    D = np.full((S, n), ego.PAPER_DV0)
+    mp, vp, mG, vG, mD, vD = (np.zeros_like(a) for a in (prm, prm, G, G, D, D))
+    vi = v_init.double().cpu().numpy()
+    ref = []
+    for t in range(1, iters + 1):
+        q = oracle.EgoProblem(dict(zip(oracle.PARAM_NAMES, prm)), G, D, vi, S, dt=data.dt)
+        P, V, _, _ = oracle.ego_forward(q)
+        loss, gP = oracle.ego_mae(P, data.offsets, steps, pos32.astype(np.float64))
+        ref.append(loss)
+        g, gG, gD, _ = oracle.ego_adjoint(q, P, V, gP)
+        lr = lr_at(t, 0.1, 0.01, 500)
+        prm, mp, vp = adam_raw_step(prm, mp, vp, g, lo, hi, t, lr)
+        G, mG, vG = adam_raw_step(G, mG, vG, gG, -np.inf, np.inf, t, lr)
+        D, mD, vD = adam_raw_step(D, mD, vD, gD, -np.inf, np.inf, t, lr)
+    log("ego fit loss: gpu %s oracle %s" % (np.array2string(la, precision=1),
+                                             np.array2string(np.array(ref), precision=1)))
+    assert la[-1] < la[0]
+    assert np.allclose(la, ref, rtol=2e-3)
