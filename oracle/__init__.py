@@ -258,3 +258,29 @@ def ego_mae(P, obs_off, obs_step, obs_pos, want_grad: bool = True):
     gP = np.zeros_like(P) if want_grad else None
     loss = lib().oracle_ego_mae(n, S1 - 1, _p(P), _p(off), _p(st), _p(pos), _p(gP))
     return float(loss), gP
+
+
+def reconstruction_metrics(P, A, obs_off, obs_step, obs_pos) -> dict:
+    """Plain loops over the paper's evaluation criteria (Sec. V-B4): mean over
+    observations of |obs - P[step]| / (last - first observed position of the
+    trajectory, at least 1 m); mean and standard deviation of |a| over the
+    steps before each trajectory's last observed step; fraction of
+    trajectories with |a| > 10 at any of those steps."""
+    P, A = _d(P), _d(A)
+    n = len(obs_off) - 1
+    rel, accs, bad = [], [], 0
+    for i in range(n):
+        lo, hi = int(obs_off[i]), int(obs_off[i + 1])
+        if hi == lo:
+            continue
+        length = max(abs(float(obs_pos[hi - 1]) - float(obs_pos[lo])), 1.0)
+        for j in range(lo, hi):
+            rel.append(abs(float(obs_pos[j]) - P[int(obs_step[j]), i]) / length)
+        a = np.abs(A[:int(obs_step[hi - 1]), i])
+        accs.append(a)
+        bad += int(np.any(a > 10.0))
+    acc = np.concatenate(accs) if accs else np.zeros(0)
+    return {"pos_error": float(np.mean(rel)) if rel else 0.0,
+            "acc_mean": float(acc.mean()) if acc.size else 0.0,
+            "acc_std": float(acc.std()) if acc.size else 0.0,
+            "implausible": bad / n}

@@ -191,3 +191,38 @@ class EgoFitter:
     def losses(self) -> torch.Tensor:
         k = int(self.step_ctr.item())
         return self.loss_hist[:min(k, self.loss_hist.numel())].cpu()
+
+
+def reconstruction_metrics(traj_p: torch.Tensor, traj_a: torch.Tensor, obs: EgoObs) -> dict:
+    """The paper's evaluation criteria of a reconstruction (Sec. V-B4),
+    evaluated on the device from the forward's positions [(S+1), N] and
+    accelerations [S, N]:
+      pos_error: mean over observations of |observed - simulated position at the
+        nearest step| / the trajectory's length (last minus first observation);
+      acc_mean / acc_std: mean and standard deviation of |a| over every step
+        inside each trajectory's observed span;
+      implausible: fraction of trajectories with |a| > 10 m/s^2 at any such step.
+    Evaluation only (not part of the fitted path)."""
+    off = obs.offsets.long()
+    n = off.numel() - 1
+    counts = off[1:] - off[:-1]
+    traj = torch.repeat_interleave(torch.arange(n, device=off.device), counts)
+    step = obs.step.long()
+    sim_p = traj_p[step, traj]
+    first = obs.pos[off[:-1].clamp(max=max(obs.n_obs - 1, 0))]
+    last = obs.pos[(off[1:] - 1).clamp(min=0)]
+    length = (last - first).abs().clamp(min=1.0)
+    rel = ((sim_p - obs.pos).abs() / length[traj]).double()
+    # steps inside each trajectory's span: k < last observed step
+    last_step = torch.zeros(n, dtype=torch.long, device=off.device)
+    has = counts > 0
+    last_step[has] = step[off[1:][has] - 1]
+    S = traj_a.shape[0]
+    inside = torch.arange(S, device=off.device)[:, None] < last_step[None, :]
+    aa = traj_a.abs().double()
+    sel = aa[inside]
+    bad = ((aa > 10.0) & inside).any(dim=0)
+    return {"pos_error": float(rel.mean().item()) if rel.numel() else 0.0,
+            "acc_mean": float(sel.mean().item()) if sel.numel() else 0.0,
+            "acc_std": float(sel.std(unbiased=False).item()) if sel.numel() else 0.0,
+            "implausible": float(bad.double().mean().item())}

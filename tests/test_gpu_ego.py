@@ -82,6 +82,16 @@ def test_ego_forward_backward_match_oracle(mode, K):
     okv, wv = grad_close(out["gv0"], gv0, rtol=1e-3)
     log("ego gradients worst/limit: params %.3f G %.3f D %.3f v0 %.3f %s" % (wg, wG, wD, wv, where))
     assert okg and okG and okD and okv
+    if mode == scenarios.MODE_SOFTPLUS and K == 0:
+        # the paper's criteria, on the device and by plain loops on the oracle
+        import torch
+        from paper_2412_16750_amd import ego
+        md = ego.reconstruction_metrics(torch.from_numpy(out["P"]).float().cuda(),
+                                        torch.from_numpy(out["A"]).float().cuda(), x["obs"])
+        mo = oracle.reconstruction_metrics(P, A, data.offsets, steps, pos32)
+        log("metrics gpu %s oracle %s" % (md, mo))
+        for k in mo:
+            assert abs(md[k] - mo[k]) <= 1e-3 * max(abs(mo[k]), 1e-3), k
 
 
 def test_ego_edge_cases():

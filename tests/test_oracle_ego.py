@@ -198,3 +198,23 @@ def test_raw_adam_first_step_projection_and_quadratic():
     for t in range(1, 3001):
         x, m, v = adam_raw_step(x, m, v, 2 * (x - 3.0), 0.0, 2.0, t, lr_at(t, 0.1, 0.01, 500))
     assert x[0] == 2.0
+
+
+def test_reconstruction_metrics_hand_example():
+    # two trajectories, S = 4; trajectory 1 has no observation
+    P = np.zeros((5, 2))
+    P[:, 0] = [0.0, 10.0, 20.0, 30.0, 40.0]
+    A = np.zeros((4, 2))
+    A[:, 0] = [1.0, -3.0, 11.0, 2.0]
+    A[:, 1] = [50.0, 50.0, 50.0, 50.0]
+    off = [0, 3, 3]
+    steps = [0, 2, 3]
+    pos = [0.0, 21.0, 28.0]
+    m = oracle.reconstruction_metrics(P, A, off, steps, pos)
+    # length 28 - 0 = 28 m; errors 0, 1, 2 -> mean 3 / (3 * 28)
+    assert m["pos_error"] == pytest.approx(3.0 / 84.0)
+    # steps before the last observed step (3): |a| = 1, 3, 11
+    assert m["acc_mean"] == pytest.approx(5.0)
+    assert m["acc_std"] == pytest.approx(np.std([1.0, 3.0, 11.0]))
+    # trajectory 0 exceeds 10 m/s^2 once; trajectory 1 has no observed span
+    assert m["implausible"] == pytest.approx(0.5)
