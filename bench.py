@@ -41,9 +41,10 @@ PEAK_HBM_GBPS = 8000.0
 PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
 # HBM bytes of one backward launch on this workload from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (scaled by the copy-kernel calibration, 2.000 and 1.000), valid
-# only for the kernel source they were taken with (sha256 of idm_kernels.hip).
+# only for the kernel source they were taken with (sha256 of idm_kernels.hip
+# followed by idm_device.h).
 TRAFFIC_BWD_BYTES = 1.2596e9
-TRAFFIC_KERNEL_SHA256 = "5458ca7ef10a6575bd9a81d686b78ca8b2e31ff2b0120f15e387051e881cf95d"
+TRAFFIC_KERNEL_SHA256 = "e448f5a332ed7d76a5f726ebed95ac85d65b2803b4fd44cd475ab50bcffecb7c"
 
 
 def log(*a):
@@ -397,8 +398,11 @@ def main():
     bwd_bytes = N * (nblk * 8 + 20 + 4 + 16 + 4 * S + 56)
     fwd_bytes = N * (20 + 4 + 16 + 4 + 4 * (S + 1) + nblk * 8)
     import hashlib
-    src = os.path.join(ROOT, "paper_2412_16750_amd", "csrc", "idm_kernels.hip")
-    same_kernel = hashlib.sha256(open(src, "rb").read()).hexdigest() == TRAFFIC_KERNEL_SHA256
+    csrc = os.path.join(ROOT, "paper_2412_16750_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("idm_kernels.hip", "idm_device.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    same_kernel = h.hexdigest() == TRAFFIC_KERNEL_SHA256
     traffic = TRAFFIC_BWD_BYTES if (same_kernel and info["ckpt_every"] == 32 and info["block"] == 16
                                     and info["threads"] == 1024 and info["per_thread"] == 1) else None
     roofline = {

@@ -55,7 +55,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         units.append((os.path.join(CSRC, "idm_kernels.hip"), os.path.join(bdir, "idm_kernels_%d.o" % part),
                       ["-DIDM_PART=%d" % part]))
     units.append((os.path.join(CSRC, "idm_api.hip"), os.path.join(bdir, "idm_api.o"), []))
-    for extra in ("mlp_kernels.hip",):
+    for extra in ("ego_kernels.hip", "mlp_kernels.hip"):
         src = os.path.join(CSRC, extra)
         if os.path.exists(src):
             units.append((src, os.path.join(bdir, extra.replace(".hip", ".o")), []))

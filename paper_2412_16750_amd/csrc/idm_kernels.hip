@@ -26,7 +26,7 @@
 //   * Per-vehicle parameter gradients are summed in FP32 within a block and in
 //     FP64 across blocks; the fused MSE loss is summed in FP64 per bundle and
 //     reduced in a fixed order by a second kernel.
-#include "idm_internal.h"
+#include "idm_device.h"
 
 #include <limits.h>
 #include <math.h>
@@ -35,56 +35,6 @@
 
 namespace idmx {
 namespace {
-
-constexpr float kLog2e = 1.4426950408889634f;
-constexpr float kLn2 = 0.6931471805599453f;
-
-__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
-__device__ __forceinline__ float log2_fast(float x) { return __builtin_amdgcn_logf(x); }
-__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// softplus(x) = log(1 + e^x) = max(x, 0) + log(1 + e^-|x|)   (Sec. III-C)
-__device__ __forceinline__ float softplus(float x) {
-    float e = exp2_fast(-fabsf(x) * kLog2e);
-    return fmaf(kLn2, log2_fast(1.0f + e), fmaxf(x, 0.0f));
-}
-
-// softplus(x) and its derivative, the logistic function.
-__device__ __forceinline__ float softplus_d(float x, float &sig) {
-    float e = exp2_fast(-fabsf(x) * kLog2e);
-    float onep = 1.0f + e;
-    float r = rcp_fast(onep);
-    sig = x >= 0.0f ? r : e * r;
-    return fmaf(kLn2, log2_fast(onep), fmaxf(x, 0.0f));
-}
-
-// Work-group barrier that orders only LDS traffic.  __syncthreads() also
-// waits for every outstanding global store of the wave, which would stall each
-// time step on the trajectory writes; nothing here reads another thread's
-// global writes inside a launch, so only the LDS ("local") fence is needed.
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-__device__ __forceinline__ float logistic(float x) {
-    float e = exp2_fast(-fabsf(x) * kLog2e);
-    float r = rcp_fast(1.0f + e);
-    return x >= 0.0f ? r : e * r;
-}
-
-// Per-vehicle constants, computed once per launch.
-struct Veh {
-    float inv_v0, T, a, s0;
-    float c;      // 1 / (2 sqrt(a b))   (Eq. 1)
-    float g0;     // initial gap to the leader (FP64 difference, rounded); +inf for a lane head
-    float two_a;  // 2 a
-    float fa_v0;  // 4 a / v0   (delta = 4)
-    float i2a, i2b;  // 1 / (2a), 1 / (2b)
-    int32_t g;    // global vehicle index, -1 for padding
-    bool head;
-};
 
 template <int R>
 __device__ __forceinline__ void load_vehicles(const SimArgs &A, int64_t slot0, Veh (&q)[R]) {
@@ -124,128 +74,6 @@ __device__ __forceinline__ void load_vehicles(const SimArgs &A, int64_t slot0, V
             q[r].g0 = INFINITY;
         }
     }
-}
-
-// Acceleration entering the speed update: a* (SOFTPLUS) or ahat (CLAMP), for
-// a bumper-to-bumper gap and speed difference v - v_h to the leader.
-template <int MODE>
-__device__ __forceinline__ float accel_gd(const Veh &q, float v, float gap, float dv,
-                                          float inv_dt, float a_min, float gap_floor) {
-    float x = v * q.inv_v0;
-    float x2 = x * x;
-    float sg = fmaxf(gap, gap_floor);
-    float s_opt = fmaf(v * dv, q.c, fmaf(v, q.T, q.s0));  // Eq. 1
-    float s = (MODE == 0) ? softplus(s_opt) : s_opt;  // Sec. III-C floor on s_opt
-    float qq = s * rcp_fast(sg);
-    float ahat = q.a * (1.0f - fmaf(qq, qq, x2 * x2));   // Eq. 2, delta = 4
-    if (MODE == 0) {
-        float lb = fmaxf(-v * inv_dt, a_min);           // Sec. III-C a_lb
-        return lb + softplus(ahat - lb);
-    }
-    return ahat;
-}
-
-// The lane model: gap = p_h - p - len_h = g0 + (d_h - d), dv = v - v_h
-// (Sec. III-A).  A lane head has g0 = +inf, so its interaction term is
-// exactly zero.
-template <int MODE>
-__device__ __forceinline__ float accel(const Veh &q, float d, float v, float dh, float vh,
-                                       float inv_dt, float a_min, float gap_floor) {
-    return accel_gd<MODE>(q, v, q.g0 + (dh - d), v - vh, inv_dt, a_min, gap_floor);
-}
-
-template <int MODE>
-__device__ __forceinline__ void euler(float &d, float &v, float acc, float dt) {
-    float dn = fmaf(dt, v, d);                        // Eq. 3, old speed
-    float vn = fmaf(dt, acc, v);
-    if (MODE == 1) vn = fmaxf(vn, 0.0f);
-    d = dn;
-    v = vn;
-}
-
-// Local partial derivatives at one (vehicle, step).  With ahat the IDM
-// acceleration of Eq. 2, a* the bounded one that enters the speed update,
-// gap = g0 + d_h - d and s_opt of Eq. 1:
-//   d a*/d gap  = w hg
-//   d a*/d v    = w (As (T + (dv + v) c) - (4a/v0) x^3) + lbv
-//   d a*/d v_h  = -w As v c
-//   d a*/d v0   = w (4a/v0) x^4,   d a*/d T = w As v,   d a*/d s0 = w As,
-//   d a*/d a    = w (rest - As v dv c / (2a)),   d a*/d b = -w As v dv c / (2b)
-// with As = d ahat / d s_opt and rest = 1 - x^4 - (s*/gap)^2.
-struct Part {
-    float hg;      // d ahat / d gap (0 while the gap floor is active)
-    float As;      // d ahat / d s_opt
-    float u1;      // T + (dv + v) c  = d s_opt / d v
-    float x3, x4;  // (v/v0)^3, (v/v0)^4
-    float vc;      // v c
-    float vdvc;    // v dv c
-    float rest;    // 1 - x^4 - (s*/gap)^2
-    float w;       // d a* / d ahat (1 in CLAMP mode)
-    float lbv;     // contribution of a_lb = max(-v/dt, a_min) to d a*/d v
-    float gate;    // d v' / d (v + dt a*): 1, or the clamp indicator
-};
-
-// EGO: the speed difference is a free input (the ego-only reconstruction
-// model), so d s_opt / d v = T + dv c instead of T + (dv + v) c.
-template <int MODE, bool EGO = false>
-__device__ __forceinline__ void partials_gd(const Veh &q, float v, float gap, float dv, float dt,
-                                            float inv_dt, float a_min, float gap_floor, Part &P) {
-    float x = v * q.inv_v0;
-    float x2 = x * x;
-    bool floored = !(gap > gap_floor);
-    float sg = floored ? gap_floor : gap;
-    float inv_sg = rcp_fast(sg);
-    float vdv = v * dv;
-    float s_opt = fmaf(vdv, q.c, fmaf(v, q.T, q.s0));
-    float sig_s = 1.0f, s = s_opt;
-    if (MODE == 0) s = softplus_d(s_opt, sig_s);
-    float qq = s * inv_sg;
-    P.x4 = x2 * x2;
-    P.rest = 1.0f - fmaf(qq, qq, P.x4);
-    float ahat = q.a * P.rest;
-    float tq = q.two_a * qq * inv_sg;                 // 2 a q / gap
-    P.As = -tq * sig_s;
-    P.hg = floored ? 0.0f : tq * qq;                  // 2 a q^2 / gap
-    P.u1 = EGO ? fmaf(dv, q.c, q.T) : fmaf(dv + v, q.c, q.T);
-    P.x3 = x2 * x;
-    P.vc = v * q.c;
-    P.vdvc = vdv * q.c;
-    if (MODE == 0) {
-        float nv = -v * inv_dt;
-        bool on_v = nv > a_min;                       // tie -> a_min branch
-        float lb = on_v ? nv : a_min;
-        P.w = logistic(ahat - lb);
-        P.lbv = on_v ? (P.w - 1.0f) * inv_dt : 0.0f;
-        P.gate = 1.0f;
-    } else {
-        P.w = 1.0f;
-        P.lbv = 0.0f;
-        P.gate = (fmaf(dt, ahat, v) > 0.0f) ? 1.0f : 0.0f;
-    }
-}
-
-// The lane model's partials (gap = g0 + d_h - d, dv = v - v_h).
-template <int MODE>
-__device__ __forceinline__ void partials(const Veh &q, float d, float v, float dh, float vh,
-                                         float dt, float inv_dt, float a_min, float gap_floor,
-                                         Part &P) {
-    partials_gd<MODE>(q, v, q.g0 + (dh - d), v - vh, dt, inv_dt, a_min, gap_floor, P);
-}
-
-__device__ __forceinline__ double block_sum(double x, double *red) {
-    // fixed-order reduction: wave shuffles, then waves in index order
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) red[wave] = x;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0) {
-        int nw = (blockDim.x + 63) >> 6;
-        for (int i = 0; i < nw; ++i) s += red[i];
-    }
-    __syncthreads();
-    return s;
 }
 
 // ---------------------------------------------------------------- forward
@@ -939,306 +767,6 @@ __global__ __launch_bounds__(256) void k_fit_init_u(AdamArgs A, const float *u_r
     if (blockIdx.x == 0 && threadIdx.x == 0) *A.step_rw = 0;
 }
 
-#if IDM_PART == 0
-// ---------------------------------------------------------------- ego-only reconstruction
-//
-// One thread per trajectory (Sec. IV-A): the ego vehicle starts at p(0) = 0
-// and its leader is not simulated; the gap and speed difference of every step
-// are inputs ([S][N], step-major, so a wave's loads are coalesced).  No data
-// is shared between threads, so these kernels have no LDS and no barrier.
-
-constexpr int EGO_THREADS = 64;
-constexpr int EGO_CHUNK = 8;  // steps whose free variables are loaded ahead
-
-__device__ __forceinline__ void load_ego(const EgoArgs &A, int64_t i, Veh &q) {
-    const float v0 = A.v0[i], a = A.a[i], b = A.b[i];
-    q.inv_v0 = 1.0f / v0;
-    q.T = A.T[i];
-    q.a = a;
-    q.s0 = A.s0[i];
-    q.c = 0.5f / sqrtf(a * b);
-    q.two_a = 2.0f * a;
-    q.fa_v0 = 4.0f * a / v0;
-    q.i2a = 0.5f / a;
-    q.i2b = 0.5f / b;
-    q.g0 = 0.0f;
-    q.g = (int32_t)i;
-    q.head = false;
-}
-
-template <int MODE>
-__global__ __launch_bounds__(EGO_THREADS) void k_ego_forward(EgoArgs A) {
-    const int64_t i = (int64_t)blockIdx.x * EGO_THREADS + threadIdx.x;
-    if (i >= A.n) return;
-    const int64_t N = A.n;
-    const int S = A.n_steps;
-    Veh q;
-    load_ego(A, i, q);
-    float d = 0.0f, v = A.v_init[i];
-    if (A.traj_p) A.traj_p[i] = 0.0f;
-    if (A.traj_v) A.traj_v[i] = v;
-    if (A.ckpt) {
-        A.ckpt[i] = 0.0f;
-        A.ckpt[N + i] = v;
-    }
-    // free variables of the current and the next chunk of steps (indices
-    // clamped into [0, S-1]; S = 0 reads nothing)
-    float gc[EGO_CHUNK], dc[EGO_CHUNK];
-#pragma unroll
-    for (int u = 0; u < EGO_CHUNK; ++u) {
-        const int64_t kk = min(u, S - 1);
-        gc[u] = S > 0 ? A.gap[kk * N + i] : 0.0f;
-        dc[u] = S > 0 ? A.dv[kk * N + i] : 0.0f;
-    }
-    int to_ckpt = A.K;
-    for (int k0 = 0; k0 < S; k0 += EGO_CHUNK) {
-        float gn[EGO_CHUNK], dn[EGO_CHUNK];
-#pragma unroll
-        for (int u = 0; u < EGO_CHUNK; ++u) {
-            const int64_t kk = min(k0 + EGO_CHUNK + u, S - 1);
-            gn[u] = A.gap[kk * N + i];
-            dn[u] = A.dv[kk * N + i];
-        }
-#pragma unroll
-        for (int u = 0; u < EGO_CHUNK; ++u) {
-            const int k = k0 + u;
-            if (k < S) {
-                const float acc =
-                    accel_gd<MODE>(q, v, gc[u], dc[u], A.inv_dt, A.a_min, A.gap_floor);
-                const float vk = v;
-                euler<MODE>(d, v, acc, A.dt);
-                const int64_t row = (int64_t)(k + 1) * N + i;
-                if (A.traj_p) A.traj_p[row] = d;
-                if (A.traj_v) A.traj_v[row] = v;
-                if (A.traj_a) A.traj_a[(int64_t)k * N + i] = MODE == 1 ? (v - vk) * A.inv_dt : acc;
-                if (--to_ckpt == 0) {
-                    to_ckpt = A.K;
-                    if (A.ckpt && k + 1 < S) {
-                        const int64_t c = (int64_t)((k + 1) / A.K) * 2 * N + i;
-                        A.ckpt[c] = d;
-                        A.ckpt[c + N] = v;
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < EGO_CHUNK; ++u) {
-            gc[u] = gn[u];
-            dc[u] = dn[u];
-        }
-    }
-}
-
-// The trajectory's next observations, walked from the last one backwards.
-struct ObsRing {
-    static constexpr int D = 4;
-    int st[D];
-    float pos[D];
-    int j;     // index of the observation D places ahead of st[0]
-    int lo;    // first observation of the trajectory
-};
-
-__device__ __forceinline__ void ring_fill(const EgoArgs &A, ObsRing &R, int lo, int hi) {
-    R.lo = lo;
-#pragma unroll
-    for (int u = 0; u < ObsRing::D; ++u) {
-        const int j = hi - 1 - u;
-        R.st[u] = j >= lo ? A.obs_step[j] : -1;
-        R.pos[u] = j >= lo ? A.obs_pos[j] : 0.0f;
-    }
-    R.j = hi - 1 - ObsRing::D;
-}
-
-// Upstream dL/dp at step k from the observations matched to k (summed
-// absolute error: sign(p - obs), 0 at equality); their |p - obs| go to `loss`.
-__device__ __forceinline__ float ring_take(const EgoArgs &A, ObsRing &R, int k, float p,
-                                           double &loss) {
-    float up = 0.0f;
-    while (R.st[0] == k) {
-        const float r = p - R.pos[0];
-        up += (r > 0.0f ? 1.0f : 0.0f) - (r < 0.0f ? 1.0f : 0.0f);
-        loss += (double)fabsf(r);
-#pragma unroll
-        for (int u = 0; u + 1 < ObsRing::D; ++u) {
-            R.st[u] = R.st[u + 1];
-            R.pos[u] = R.pos[u + 1];
-        }
-        const int j = R.j;
-        R.st[ObsRing::D - 1] = j >= R.lo ? A.obs_step[j] : -1;
-        R.pos[ObsRing::D - 1] = j >= R.lo ? A.obs_pos[j] : 0.0f;
-        R.j = j - 1;
-    }
-    return up;
-}
-
-// Ego backward: checkpoint blocks of K = KB steps from the last; each block's
-// states and free variables are recomputed into registers, then the adjoint
-// walks them backwards.  Per step it writes dL/dG and dL/dD; the parameter
-// gradients accumulate as the five sufficient statistics of the lane kernel.
-template <int MODE, int KB>
-__global__ __launch_bounds__(EGO_THREADS) void k_ego_backward(EgoArgs A) {
-    const int64_t i = (int64_t)blockIdx.x * EGO_THREADS + threadIdx.x;
-    if (i >= A.n) return;
-    const int64_t N = A.n;
-    const int S = A.n_steps;
-    const float dt = A.dt;
-    const int nblk = (S + KB - 1) / KB;
-    Veh q;
-    load_ego(A, i, q);
-    ObsRing R;
-    ring_fill(A, R, A.obs_off[i], A.obs_off[i + 1]);
-    double loss = 0.0;
-    double gacc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    float lp = 0.0f, lv = 0.0f;
-    if (S == 0) lp = ring_take(A, R, 0, 0.0f, loss);
-    for (int blk = nblk - 1; blk >= 0; --blk) {
-        const int k0 = blk * KB;
-        const int len = min(KB, S - k0);
-        const int64_t c = (int64_t)blk * 2 * N + i;
-        float d = A.ckpt[c], v = A.ckpt[c + N];
-        float hd[KB], hv[KB], hg[KB], hq[KB];
-#pragma unroll
-        for (int j = 0; j < KB; ++j) {
-            const int64_t kk = (int64_t)min(k0 + j, S - 1) * N + i;
-            hg[j] = A.gap[kk];
-            hq[j] = A.dv[kk];
-        }
-#pragma unroll
-        for (int j = 0; j < KB; ++j) {
-            if (j < len) {
-                hd[j] = d;
-                hv[j] = v;
-                const float acc = accel_gd<MODE>(q, v, hg[j], hq[j], A.inv_dt, A.a_min, A.gap_floor);
-                euler<MODE>(d, v, acc, dt);
-            }
-        }
-        if (blk == nblk - 1) lp = ring_take(A, R, S, d, loss);  // seed: step S
-        float gs[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int j = KB - 1; j >= 0; --j) {
-            if (j < len) {
-                const int k = k0 + j;
-                Part P;
-                partials_gd<MODE, true>(q, hv[j], hg[j], hq[j], dt, A.inv_dt, A.a_min,
-                                        A.gap_floor, P);
-                const float mu = (MODE == 0) ? dt * lv : P.gate * dt * lv;
-                const float mw = mu * P.w;
-                const float mwAs = mw * P.As;
-                A.g_gap[(int64_t)k * N + i] = mw * P.hg;
-                A.g_dv[(int64_t)k * N + i] = mwAs * P.vc;
-                const float keep = (MODE == 0) ? lv : P.gate * lv;
-                float nlv = fmaf(dt, lp, keep);
-                nlv = fmaf(mwAs, P.u1, nlv);
-                nlv = fmaf(-mw * q.fa_v0, P.x3, nlv);
-                if (MODE == 0) nlv = fmaf(mu, P.lbv, nlv);
-                gs[0] = fmaf(mw, P.x4, gs[0]);
-                gs[1] = fmaf(mwAs, hv[j], gs[1]);
-                gs[2] = fmaf(mw, P.rest, gs[2]);
-                gs[3] = fmaf(mwAs, P.vdvc, gs[3]);
-                gs[4] += mwAs;
-                lp += ring_take(A, R, k, hd[j], loss);
-                lv = nlv;
-            }
-        }
-        gacc[0] += (double)q.fa_v0 * (double)gs[0];
-        gacc[1] += (double)gs[1];
-        gacc[2] += (double)gs[2] - (double)q.i2a * (double)gs[3];
-        gacc[3] -= (double)q.i2b * (double)gs[3];
-        gacc[4] += (double)gs[4];
-    }
-#pragma unroll
-    for (int p = 0; p < 5; ++p) A.g_prm[(int64_t)p * N + i] = gacc[p];
-    if (A.g_v0) A.g_v0[i] = (double)lv;
-    A.loss_part[i] = loss;
-}
-
-// Adam (Kingma & Ba) on the physical parameters, projected onto their boxes,
-// and on the unconstrained per-step gap and speed difference; learning rate
-// linear from lr0 to lr1 over lr_steps.
-__global__ __launch_bounds__(256) void k_ego_adam(EgoAdamArgs A) {
-    const int64_t n5 = 5 * A.n, total = n5 + 2 * A.sn;
-    const int32_t t = *A.step;
-    const float frac = fminf((float)(t - 1) / (float)A.lr_steps, 1.0f);
-    const float lr = A.lr0 + (A.lr1 - A.lr0) * frac;
-    const float bc1 = 1.0f - powf(A.beta1, (float)t);
-    const float bc2 = 1.0f - powf(A.beta2, (float)t);
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        float x, g;
-        if (idx < n5) {
-            x = A.params[idx];
-            g = (float)A.g_prm[idx];
-        } else if (idx < n5 + A.sn) {
-            x = A.gap[idx - n5];
-            g = A.g_gap[idx - n5];
-        } else {
-            x = A.dv[idx - n5 - A.sn];
-            g = A.g_dv[idx - n5 - A.sn];
-        }
-        const float m = A.beta1 * A.m[idx] + (1.0f - A.beta1) * g;
-        const float v = A.beta2 * A.v[idx] + (1.0f - A.beta2) * g * g;
-        A.m[idx] = m;
-        A.v[idx] = v;
-        x -= lr * (m / bc1) / (sqrtf(v / bc2) + A.eps);
-        if (idx < n5) {
-            const int p = (int)(idx / A.n);
-            A.params[idx] = fminf(fmaxf(x, A.lo[p]), A.hi[p]);
-        } else if (idx < n5 + A.sn) {
-            A.gap[idx - n5] = x;
-        } else {
-            A.dv[idx - n5 - A.sn] = x;
-        }
-    }
-}
-
-// Initial values of the fit: parameters init5[p] for every trajectory, gap
-// gap0 and speed difference dv0 at every step, zero moments, step 0.
-__global__ __launch_bounds__(256) void k_ego_fit_init(EgoAdamArgs A, float i0, float i1, float i2,
-                                                      float i3, float i4, float gap0, float dv0) {
-    const int64_t n5 = 5 * A.n, total = n5 + 2 * A.sn;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        if (idx < n5) {
-            const int p = (int)(idx / A.n);
-            A.params[idx] = p == 0 ? i0 : p == 1 ? i1 : p == 2 ? i2 : p == 3 ? i3 : i4;
-        } else if (idx < n5 + A.sn) {
-            A.gap[idx - n5] = gap0;
-        } else {
-            A.dv[idx - n5 - A.sn] = dv0;
-        }
-        A.m[idx] = 0.0f;
-        A.v[idx] = 0.0f;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *A.step_rw = 0;
-}
-
-// Nearest simulation step of each timestamp (Sec. IV-A), clamped to [0, S].
-__global__ __launch_bounds__(256) void k_ego_match_steps(const double *t, int32_t m, double dt,
-                                                         int32_t n_steps, int32_t *out) {
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        double k = rint(t[j] / dt);
-        k = k < 0.0 ? 0.0 : (k > (double)n_steps ? (double)n_steps : k);
-        out[j] = (int32_t)k;
-    }
-}
-
-// Initial speed of each trajectory from its first two observations (Sec. V-B3):
-// max((P_1 - P_0) / (T_1 - T_0), 0); 0 with fewer than two observations.
-__global__ __launch_bounds__(256) void k_ego_initial_speed(const int32_t *off, const double *t,
-                                                           const float *pos, int64_t n, float *v) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int lo = off[i], hi = off[i + 1];
-        float s = 0.0f;
-        if (hi - lo >= 2) {
-            const double dtj = t[lo + 1] - t[lo];
-            if (dtj > 0.0) s = (float)(((double)pos[lo + 1] - (double)pos[lo]) / dtj);
-        }
-        v[i] = fmaxf(s, 0.0f);
-    }
-}
-#endif  // IDM_PART == 0 (ego kernels)
 
 }  // namespace
 
@@ -1387,50 +915,6 @@ hipError_t launch_params_from_u(const AdamArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_ego_forward(int mode, const EgoArgs &a, hipStream_t s) {
-    const dim3 grid((unsigned)((a.n + EGO_THREADS - 1) / EGO_THREADS));
-    if (mode == 0)
-        hipLaunchKernelGGL(k_ego_forward<0>, grid, dim3(EGO_THREADS), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_ego_forward<1>, grid, dim3(EGO_THREADS), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_ego_backward(int mode, const EgoArgs &a, hipStream_t s) {
-    const dim3 grid((unsigned)((a.n + EGO_THREADS - 1) / EGO_THREADS)), blk(EGO_THREADS);
-#define IDM_EGO_BWD(M, KK) \
-    if (mode == M && a.K == KK) { hipLaunchKernelGGL((k_ego_backward<M, KK>), grid, blk, 0, s, a); return hipGetLastError(); }
-    IDM_EGO_BWD(0, 8) IDM_EGO_BWD(0, 16) IDM_EGO_BWD(0, 32)
-    IDM_EGO_BWD(1, 8) IDM_EGO_BWD(1, 16) IDM_EGO_BWD(1, 32)
-#undef IDM_EGO_BWD
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_ego_adam(const EgoAdamArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_ego_adam, dim3(elementwise_grid(5 * a.n + 2 * a.sn)), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_ego_fit_init(const EgoAdamArgs &a, const float *init5, float gap0, float dv0,
-                               hipStream_t s) {
-    hipLaunchKernelGGL(k_ego_fit_init, dim3(elementwise_grid(5 * a.n + 2 * a.sn)), dim3(256), 0, s,
-                       a, init5[0], init5[1], init5[2], init5[3], init5[4], gap0, dv0);
-    return hipGetLastError();
-}
-
-hipError_t launch_ego_match_steps(const double *t, int32_t m, double dt, int32_t n_steps,
-                                  int32_t *step_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_ego_match_steps, dim3(elementwise_grid(m)), dim3(256), 0, s, t, m, dt,
-                       n_steps, step_out);
-    return hipGetLastError();
-}
-
-hipError_t launch_ego_initial_speed(const int32_t *off, const double *t, const float *pos,
-                                    int64_t n, float *v_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_ego_initial_speed, dim3(elementwise_grid(n)), dim3(256), 0, s, off, t, pos,
-                       n, v_out);
-    return hipGetLastError();
-}
 #endif  // IDM_PART == 0
 
 }  // namespace idmx
