@@ -363,3 +363,15 @@ def ego_free_variables(n_traj: int, n_steps: int, c: int):
     D = rng.normal(0.0, 1.5, (n_steps, n_traj)).astype(np.float32)
     v = rng.uniform(8.0, 25.0, n_traj).astype(np.float32)
     return P, G, D, v
+
+
+def forecast(n_lanes: int = 10000, lane_len: int = 8, history: int = 10, future: int = 80,
+             **kw) -> Scenario:
+    """Forecasting workload (stand-in for the paper's WOMD rollouts, Sec. V-C):
+    short lanes of a few vehicles with hidden parameters = the usual draw,
+    observed over a 1 s history (10 steps of 0.1 s) and rolled out 8 s (80
+    steps) further; n_steps = history + future."""
+    sc = make_scenario("forecast", uniform_lanes(n_lanes, lane_len), history + future, 8, **kw)
+    sc.extra["history"] = history
+    sc.extra["future"] = future
+    return sc
