@@ -268,6 +268,19 @@ def recon_report(dev, log_fn, which: str, iters: int = 500) -> dict:
     ego.idm_ego_forward(plan, p, f.gap, f.dv, v_init, f.workspace, P, None, A)
     m = ego.reconstruction_metrics(P, A, obs)
     log_fn("bench: %s %d trajectories, %d iterations in %.3f s" % (which, data.n, iters, ms / 1e3))
+    frozen = None
+    if which == "reconstruction":
+        # ablation (Sec. V-B5): the five parameters held at their initial values
+        # (box collapsed onto them), only the per-step gap and speed difference fitted
+        fz = ego.EgoFitter(plan, v_init, obs, boxes=[(x, x) for x in ego.PAPER_INIT],
+                           lr_steps=iters)
+        fz.init()
+        fz.run(iters)
+        ego.idm_ego_forward(plan, fz.params, fz.gap, fz.dv, v_init, fz.workspace, P, None, A)
+        mf = ego.reconstruction_metrics(P, A, obs)
+        frozen = {"pos_error_pct": 100 * mf["pos_error"], "acc_mean": mf["acc_mean"],
+                  "acc_std": mf["acc_std"], "implausible_pct": 100 * mf["implausible"],
+                  "paper": {"pos_error_pct": 0.22, "acc_mean": 0.5, "acc_std": 1.7}}
     return {"workload": "%d synthetic trajectories, %s, %d observations, dt %.1f s, %d steps"
                         % (data.n, "observed every 0.1 s" if which == "filtering" else
                            ">= 1 s sampling, 2-20 min", len(data.t), data.dt, data.n_steps),
@@ -276,7 +289,46 @@ def recon_report(dev, log_fn, which: str, iters: int = 500) -> dict:
             "loss_first_last": [float(losses[0]), float(losses[-1])],
             "pos_error_pct": 100 * m["pos_error"], "acc_mean": m["acc_mean"],
             "acc_std": m["acc_std"], "implausible_pct": 100 * m["implausible"],
-            "paper_table1_context": PAPER_TABLE1[which]}
+            "paper_table1_context": PAPER_TABLE1[which],
+            **({"frozen_parameters": frozen} if frozen else {})}
+
+
+def size_sweep(dev, log_fn, sizes=(1000, 10000, 100000, 1000000, 2000000), reps: int = 10) -> list:
+    """Forward and backward time per simulated step against the number of
+    vehicles (lanes of 1000, 100 steps, K = 32), as in the paper's Fig. 1."""
+    import numpy as np
+    import torch
+    import scenarios
+    from paper_2412_16750_amd import sim
+    out = []
+    for n in sizes:
+        sc = scenarios.make_scenario("sweep", scenarios.uniform_lanes(max(1, n // 1000), min(n, 1000)),
+                                     100, 2, ckpt_every=32)
+        x, obs = build_inputs(sc, dev)
+        plan = sim.Plan.for_scenario(sc)
+        ws = plan.workspace(dev)
+        traj = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device=dev)
+        gp = torch.empty(5, sc.n, dtype=torch.float64, device=dev)
+        g0 = torch.empty(sc.n, dtype=torch.float64, device=dev)
+        g1 = torch.empty_like(g0)
+        fwd = lambda: sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj, None, ws)
+        bwd = lambda: sim.idm_sim_backward(plan, x["prm"], x["length"], x["p0"], x["v"], gp, g0, g1,
+                                           ws, obs=obs)
+        fwd(); bwd()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        tf = tb = 0.0
+        for _ in range(reps):
+            ev[0].record(); fwd(); ev[1].record(); bwd(); ev[2].record()
+            torch.cuda.synchronize()
+            tf += ev[0].elapsed_time(ev[1])
+            tb += ev[1].elapsed_time(ev[2])
+        out.append({"vehicles": sc.n, "fwd_us_per_step": 1e3 * tf / reps / sc.n_steps,
+                    "bwd_us_per_step": 1e3 * tb / reps / sc.n_steps})
+        log_fn("bench: sweep %d vehicles fwd %.2f us/step bwd %.2f us/step"
+               % (sc.n, out[-1]["fwd_us_per_step"], out[-1]["bwd_us_per_step"]))
+        del plan, ws, traj, gp, g0, g1, x, obs
+    return out
 
 
 def forecast_report(dev, log_fn, iters: int = 500) -> dict:
@@ -347,6 +399,8 @@ def main():
                     help="skip the ego-only reconstruction / filtering section")
     ap.add_argument("--no-forecast", action="store_true",
                     help="skip the fit-then-rollout forecasting section")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the time-per-step against vehicle-count sweep")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -494,6 +548,9 @@ def main():
         out["filtering"] = recon_report(dev, log, "filtering")
     if not args.no_forecast:
         out["forecast"] = forecast_report(dev, log)
+    if not args.no_sweep:
+        torch.cuda.empty_cache()
+        out["size_sweep"] = size_sweep(dev, log)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
