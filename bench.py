@@ -331,6 +331,57 @@ def size_sweep(dev, log_fn, sizes=(1000, 10000, 100000, 1000000, 2000000), reps:
     return out
 
 
+def batched_report(dev, log_fn, reps: int = 10) -> dict:
+    """Many independent lanes of uneven length in one launch: 10,000 lanes of
+    lognormal(5, 1.2) size clipped to [10, 4096] (about 3.0M vehicles), 300
+    steps, dense constant-speed targets; forward + backward replayed as one HIP
+    graph, first in the default launch shape, then in the shape the autotuner
+    picks on these inputs."""
+    import numpy as np
+    import torch
+    import scenarios
+    from paper_2412_16750_amd import sim
+    sc = scenarios.uneven(ckpt_every=32)
+    x, obs = build_inputs(sc, dev)
+    plan = sim.Plan.for_scenario(sc)
+    traj = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device=dev)
+    b = sim.StepBuffers(plan, x["prm"], x["length"], x["p0"], x["v"], traj_d=traj, obs=obs)
+    vsteps = float(sc.n) * sc.n_steps
+
+    def timed():
+        sim.idm_step_graph_launch(b)          # capture (first use) + warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            sim.idm_step_graph_launch(b)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    keep = ("threads", "per_thread", "ckpt_every", "block", "n_bundles", "grid", "fill")
+    default_info = {k: plan.info()[k] for k in keep}
+    ms_default = timed()
+    loss_default = b.loss.item()
+    t0 = time.perf_counter()
+    tuned = sim.idm_plan_autotune(b, reps=2)
+    tune_s = time.perf_counter() - t0
+    tuned_info = {k: tuned[k] for k in keep}
+    ms_tuned = timed()
+    sizes = np.diff(sc.lane_offsets)
+    log_fn("bench: uneven %d lanes, %d vehicles: default %s %.3f ms, autotuned %s %.3f ms"
+           % (sc.n_lanes, sc.n, default_info, ms_default, tuned_info, ms_tuned))
+    return {"workload": "%d lanes of lognormal(5, 1.2) size in [10, 4096] (max %d, mean %.0f), "
+                        "%d vehicles, %d steps of %.1f s, dense targets, fwd+bwd as one graph"
+                        % (sc.n_lanes, int(sizes.max()), float(sizes.mean()), sc.n, sc.n_steps, sc.dt),
+            "default_shape": default_info, "default_ms": ms_default,
+            "default_vehicle_steps_per_s": vsteps / (ms_default / 1e3),
+            "autotuned_shape": tuned_info, "autotuned_ms": ms_tuned,
+            "autotuned_vehicle_steps_per_s": vsteps / (ms_tuned / 1e3),
+            "autotune_seconds": tune_s, "loss": loss_default,
+            "loss_after_autotune": b.loss.item()}
+
+
 def forecast_report(dev, log_fn, iters: int = 500) -> dict:
     """Training-free forecasting (Sec. V-C) on synthetic lanes: per-vehicle IDM
     parameters fitted to a 1 s history (10 steps of 0.1 s, N(0, 0.1 m) noise)
@@ -401,6 +452,8 @@ def main():
                     help="skip the fit-then-rollout forecasting section")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the time-per-step against vehicle-count sweep")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the many-uneven-lanes graph replay and autotuner section")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -542,6 +595,9 @@ def main():
         del x, obs, traj_d, ws, gp, gp0, gv0
         torch.cuda.empty_cache()
         out["fit"] = fit_report(dev, log)
+    if not args.no_batched:
+        torch.cuda.empty_cache()
+        out["batched_uneven"] = batched_report(dev, log)
     if not args.no_recon:
         torch.cuda.empty_cache()
         out["reconstruction"] = recon_report(dev, log, "reconstruction")

@@ -78,8 +78,13 @@ typedef struct {
 } idm_problem;
 
 /* Launch shape.  Zero fields mean "choose".  A work-group of `threads`
- * threads owns `threads * per_thread` consecutive vehicle slots holding
- * whole lanes; a lane longer than that is rejected (IDM_ERR_LAYOUT). */
+ * threads owns a bundle of `threads * per_thread` consecutive vehicle slots
+ * holding whole lanes.  A lane longer than a bundle is cut into pieces of one
+ * bundle each (plus a remainder); piece j runs in launch level j, after piece
+ * j-1 in the forward and before it in the backward, and the two exchange the
+ * boundary vehicle's state and adjoint contribution at every step through the
+ * workspace.  Results do not depend on the cut (the same arithmetic in the
+ * same order).  The default is 1024 threads x 1 for lanes above 1024. */
 typedef struct {
     int32_t threads;    /* 64, 128, 256, 512 or 1024 */
     int32_t per_thread; /* vehicles per thread: 1, 2 or 4 */
@@ -124,8 +129,10 @@ idm_status idm_plan_create(const idm_problem *problem, const idm_tuning *tuning,
 idm_status idm_plan_destroy(idm_plan *plan);
 
 /* Bytes of device workspace the caller must pass to the compute calls:
- * checkpoints ceil(S/K) * 2 * N * 4 B, per-bundle loss partials, and the
- * FP64 gradient buffer used by idm_fit_step.  256-byte aligned. */
+ * checkpoints ceil(S/K) * 2 * N * 4 B, per-bundle loss partials, the FP64
+ * gradient buffer used by idm_fit_step and, with lanes longer than a bundle,
+ * (2 S + 1) * 8 B per piece boundary.  256-byte aligned.  With piece
+ * boundaries, idm_sim_forward needs the workspace too. */
 size_t idm_workspace_bytes(const idm_plan *plan);
 
 /* Chosen launch shape and packing statistics. */
@@ -136,6 +143,8 @@ typedef struct {
     int32_t max_lane;       /* longest lane (vehicles) */
     int64_t n_slots;        /* bundles * threads * per_thread */
     double fill;            /* N / n_slots */
+    int32_t n_levels;       /* launches per pass: 1 + most extra pieces of one lane */
+    int32_t n_boundaries;   /* piece boundaries of lanes longer than a bundle */
 } idm_plan_info;
 idm_status idm_plan_get_info(const idm_plan *plan, idm_plan_info *out);
 
@@ -154,6 +163,16 @@ idm_status idm_problem_check(const idm_problem *problem, const idm_tuning *tunin
 idm_status idm_problem_layout(const idm_problem *problem, const idm_tuning *tuning,
                               int32_t *slot_vehicle_host, uint8_t *slot_flags_host,
                               int64_t capacity);
+
+/* Host-only: per bundle (in the order of idm_problem_layout), the piece
+ * boundary whose leader state the bundle's first slot reads (bnd_in, -1 if
+ * its first slot is a lane head or padding), the boundary its last slot
+ * leads (bnd_out, -1 if none) and its launch level.  A piece's head slot
+ * carries no head flag; only a lane's first and last vehicles are flagged.
+ * Arrays hold `capacity` >= n_bundles entries, else IDM_ERR_INVALID_ARG. */
+idm_status idm_problem_bundles(const idm_problem *problem, const idm_tuning *tuning,
+                               int32_t *bnd_in_host, int32_t *bnd_out_host, int32_t *level_host,
+                               int64_t capacity);
 
 /* Forward simulation (Eqs. 1-3 with the chosen bound, Sec. III-B update
  * order), all n_steps in one launch.
@@ -251,7 +270,8 @@ idm_status idm_step_graph_launch(idm_plan *plan, const idm_step_args *args, void
  * (threads x per_thread x KB, with K the problem's or, left free, KB and 2 KB
  * where the LDS stash exists) whose lanes fit and whose workspace fits in
  * `workspace_bytes`, `reps` times each, on the real inputs, and switches the
- * plan to the fastest.  Synchronises `stream`.  Results of the timed runs are
+ * plan to the fastest.  Shapes whose backward spills registers are timed only
+ * when no other shape holds the longest lane (lanes above 2048 vehicles).  Synchronises `stream`.  Results of the timed runs are
  * discarded (they overwrite the output buffers).  Any graph captured by the
  * plan is dropped. */
 idm_status idm_plan_autotune(idm_plan *plan, const idm_step_args *args, size_t workspace_bytes,

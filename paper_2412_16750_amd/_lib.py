@@ -46,7 +46,8 @@ class IdmObs(ctypes.Structure):
 class IdmPlanInfo(ctypes.Structure):
     _fields_ = [("threads", c_int32), ("per_thread", c_int32), ("ckpt_every", c_int32),
                 ("grid", c_int32), ("block", c_int32), ("n_bundles", c_int32), ("max_lane", c_int32),
-                ("n_slots", c_int64), ("fill", c_double)]
+                ("n_slots", c_int64), ("fill", c_double), ("n_levels", c_int32),
+                ("n_boundaries", c_int32)]
 
 
 class IdmFitState(ctypes.Structure):
@@ -101,7 +102,7 @@ class IdmStepArgs(ctypes.Structure):
 
 # every symbol declared in include/idm.h
 EXPORTS = ("idm_plan_create", "idm_plan_destroy", "idm_workspace_bytes", "idm_plan_get_info",
-           "idm_problem_check", "idm_problem_layout",
+           "idm_problem_check", "idm_problem_layout", "idm_problem_bundles",
            "idm_sim_forward", "idm_sim_backward", "idm_fit_init", "idm_fit_step", "idm_fit_run",
            "idm_step_graph_launch", "idm_plan_autotune", "idm_copy_bytes", "idm_last_error",
            "idm_version", "idm_mlp_param_count", "idm_mlp_weight_bf16_count",
@@ -138,6 +139,8 @@ def load() -> ctypes.CDLL:
     L.idm_plan_get_info.argtypes = [c_void_p, P(IdmPlanInfo)]
     L.idm_problem_check.argtypes = [P(IdmProblem), P(IdmTuning), P(IdmPlanInfo), P(c_size_t)]
     L.idm_problem_layout.argtypes = [P(IdmProblem), P(IdmTuning), c_void_p, c_void_p, c_int64]
+    L.idm_problem_bundles.argtypes = [P(IdmProblem), P(IdmTuning), c_void_p, c_void_p, c_void_p,
+                                      c_int64]
     L.idm_sim_forward.argtypes = [c_void_p, P(IdmParams), c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p]
     L.idm_sim_backward.argtypes = [c_void_p, P(IdmParams), c_void_p, c_void_p, c_void_p, c_void_p,
@@ -196,7 +199,8 @@ def load() -> ctypes.CDLL:
         getattr(L, name).restype = c_int32
     L.idm_last_error.restype = ctypes.c_char_p
     L.idm_version.restype = ctypes.c_char_p
-    for name in ("idm_problem_check", "idm_problem_layout", "idm_plan_create", "idm_plan_destroy", "idm_plan_get_info", "idm_sim_forward",
+    for name in ("idm_problem_check", "idm_problem_layout", "idm_problem_bundles", "idm_plan_create",
+                 "idm_plan_destroy", "idm_plan_get_info", "idm_sim_forward",
                  "idm_sim_backward", "idm_fit_init", "idm_fit_step", "idm_fit_run",
                  "idm_step_graph_launch",
                  "idm_plan_autotune"):

@@ -81,8 +81,11 @@ struct idm_plan {
     // bundle layout
     int32_t n_bundles = 0;
     int64_t n_slots = 0;
+    int32_t n_bnd = 0;                  // piece boundaries of lanes longer than a bundle
+    std::vector<int32_t> level_start;   // bundles of launch level l: [start[l], start[l+1])
     int32_t *d_gidx = nullptr;
     uint8_t *d_flags = nullptr;
+    int32_t *d_bnd = nullptr;           // [2][n_bundles]: bnd_in, bnd_out (null if n_bnd = 0)
     float *d_zero = nullptr;  // 64 zero floats read in place of absent upstream inputs
     uint8_t *d_head = nullptr;  // [N] 1 = first vehicle of its lane (feature kernel)
     int32_t *d_lane_off = nullptr;  // [L+1] lane offsets on the device
@@ -104,17 +107,43 @@ int32_t nblk_of(const idm_plan *p) {
     return p->pb.n_steps == 0 ? 0 : (p->pb.n_steps + p->sh.K - 1) / p->sh.K;
 }
 
-// Workspace layout: [loss partials: n_lanes doubles][fit: 7N doubles][checkpoints]
+// Piece boundaries when lanes are cut into bundles of `cap` slots: a lane of
+// n > cap vehicles has ceil(n / cap) pieces.
+int64_t count_boundaries(const std::vector<int32_t> &offsets, int L, int64_t cap) {
+    int64_t n = 0;
+    for (int l = 0; l < L; ++l) {
+        const int64_t sz = offsets[l + 1] - offsets[l];
+        if (sz > cap) n += (sz + cap - 1) / cap - 1;
+    }
+    return n;
+}
+
+// Workspace layout: [loss partials: one double per bundle (at most one per
+// lane piece)][fit: 7N doubles][checkpoints][boundary states: n_bnd x (S+1)
+// float2][boundary adjoint contributions: n_bnd x S float2]
 size_t ws_loss_off(const idm_plan *) { return 0; }
-size_t ws_fit_off(const idm_plan *p) { return align_up(sizeof(double) * (size_t)p->pb.n_lanes); }
-size_t ws_ckpt_off(const idm_plan *p) {
-    return ws_fit_off(p) + align_up(sizeof(double) * 7 * (size_t)p->pb.n_vehicles);
+size_t ws_fit_off(const idm_plan *p, int64_t nbnd) {
+    return align_up(sizeof(double) * ((size_t)p->pb.n_lanes + (size_t)nbnd));
+}
+size_t ws_ckpt_off(const idm_plan *p, int64_t nbnd) {
+    return ws_fit_off(p, nbnd) + align_up(sizeof(double) * 7 * (size_t)p->pb.n_vehicles);
 }
 size_t ckpt_bytes(const idm_plan *p, int K) {
     size_t nb = p->pb.n_steps == 0 ? 0 : (size_t)(p->pb.n_steps + K - 1) / K;
     return align_up(nb * 2 * sizeof(float) * (size_t)p->pb.n_vehicles);
 }
-size_t ws_total(const idm_plan *p, int K) { return ws_ckpt_off(p) + ckpt_bytes(p, K); }
+size_t ws_ext_off(const idm_plan *p, int K, int64_t nbnd) {
+    return ws_ckpt_off(p, nbnd) + ckpt_bytes(p, K);
+}
+size_t ext_state_bytes(const idm_plan *p, int64_t nbnd) {
+    return align_up((size_t)nbnd * ((size_t)p->pb.n_steps + 1) * 2 * sizeof(float));
+}
+size_t ws_total(const idm_plan *p, int K, int64_t nbnd) {
+    return ws_ext_off(p, K, nbnd) + ext_state_bytes(p, nbnd) +
+           align_up((size_t)nbnd * (size_t)p->pb.n_steps * 2 * sizeof(float));
+}
+size_t ws_fit_off(const idm_plan *p) { return ws_fit_off(p, p->n_bnd); }
+size_t ws_ckpt_off(const idm_plan *p) { return ws_ckpt_off(p, p->n_bnd); }
 
 void drop_graphs(idm_plan *p) {
     if (p->step_exec) hipGraphExecDestroy(p->step_exec);
@@ -125,68 +154,144 @@ void drop_graphs(idm_plan *p) {
     memset(&p->step_key, 0, sizeof p->step_key);
 }
 
-// Pack lanes into bundles of `cap` slots: best-fit decreasing on lane size,
-// deterministic (ties keep lane order), then bundles sorted by fill (largest
-// first) so that a persistent grid starts with the most work.  Host only.
+// Pack lanes into bundles of `cap` slots.  A lane longer than `cap` is cut
+// into pieces of exactly `cap` vehicles and a remainder; piece j opens its own
+// bundle and runs in launch level j (the forward walks the levels upwards, the
+// backward downwards), the boundary between pieces j-1 and j getting one row of
+// the boundary buffers.  Whole lanes then go best-fit decreasing (ties keep
+// lane order) into the room left by remainders or into new bundles, and the
+// bundles of whole lanes only are spread over the levels so that every level
+// launches about as many work-groups.  Within a level, bundles are sorted by
+// fill (largest first), so a persistent grid starts with the most work.
+// Deterministic; host only.
 struct Layout {
     int64_t n_bundles = 0, cap = 0;
+    int32_t n_bnd = 0;
     std::vector<int32_t> gidx;
     std::vector<uint8_t> flags;
+    std::vector<int32_t> bnd_in, bnd_out;  // per bundle, -1 = none
+    std::vector<int32_t> level, level_start;
 };
 
 idm_status compute_layout(const std::vector<int32_t> &offsets, int L, const Shape &sh, Layout &out) {
     const int64_t cap = (int64_t)sh.threads * sh.per_thread;
+    struct Item {
+        int32_t lo, hi;
+        bool lane_head, lane_tail;
+    };
+    std::vector<std::vector<Item>> bundles;
+    std::vector<int64_t> fill;
+    std::vector<int32_t> level, bin, bout;
+    std::multimap<int64_t, int> room;  // remaining capacity -> bundle
+    auto open = [&](int32_t lv, int32_t in) {
+        bundles.emplace_back();
+        fill.push_back(0);
+        level.push_back(lv);
+        bin.push_back(in);
+        bout.push_back(-1);
+        return (int)bundles.size() - 1;
+    };
+    int64_t nbnd = 0;
+    int32_t n_levels = 1;
+    for (int l = 0; l < L; ++l) {
+        const int64_t sz = offsets[l + 1] - offsets[l];
+        if (sz <= cap) continue;
+        const int64_t np = (sz + cap - 1) / cap;
+        if (np >= ((int64_t)1 << 20) || nbnd + np >= ((int64_t)1 << 30))
+            return fail(IDM_ERR_LAYOUT, "lane %d: too many pieces", l);
+        n_levels = std::max<int32_t>(n_levels, (int32_t)np);
+        int prev = -1;
+        for (int64_t j = 0; j < np; ++j) {
+            const int32_t lo = (int32_t)(offsets[l] + j * cap);
+            const int32_t hi = (int32_t)std::min<int64_t>(lo + cap, offsets[l + 1]);
+            int32_t in = -1;
+            if (j > 0) {
+                in = (int32_t)nbnd++;
+                bout[prev] = in;
+            }
+            const int b = open((int32_t)j, in);
+            bundles[b].push_back({lo, hi, j == 0, j == np - 1});
+            fill[b] = hi - lo;
+            if (cap - fill[b] > 0) room.emplace(cap - fill[b], b);
+            prev = b;
+        }
+    }
     std::vector<int> order;
     order.reserve(L);
-    for (int l = 0; l < L; ++l)
-        if (offsets[l + 1] > offsets[l]) order.push_back(l);
+    for (int l = 0; l < L; ++l) {
+        const int64_t sz = offsets[l + 1] - offsets[l];
+        if (sz > 0 && sz <= cap) order.push_back(l);
+    }
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         return (offsets[x + 1] - offsets[x]) > (offsets[y + 1] - offsets[y]);
     });
-    std::vector<std::vector<int>> bundles;
-    std::vector<int64_t> fill;
-    std::multimap<int64_t, int> room;  // remaining capacity -> bundle
     for (int l : order) {
-        int64_t sz = offsets[l + 1] - offsets[l];
-        if (sz > cap) return fail(IDM_ERR_LAYOUT, "lane %d has %lld vehicles > bundle capacity %lld", l,
-                                  (long long)sz, (long long)cap);
+        const int64_t sz = offsets[l + 1] - offsets[l];
         auto it = room.lower_bound(sz);
         int b;
         if (it == room.end()) {
-            b = (int)bundles.size();
-            bundles.emplace_back();
-            fill.push_back(0);
+            b = open(-1, -1);
         } else {
             b = it->second;
             room.erase(it);
         }
-        bundles[b].push_back(l);
+        bundles[b].push_back({offsets[l], offsets[l + 1], true, true});
         fill[b] += sz;
         if (cap - fill[b] > 0) room.emplace(cap - fill[b], b);
     }
-    std::vector<int> border(bundles.size());
-    for (size_t i = 0; i < border.size(); ++i) border[i] = (int)i;
-    std::stable_sort(border.begin(), border.end(), [&](int x, int y) { return fill[x] > fill[y]; });
     const int64_t nb = (int64_t)bundles.size();
     if (nb * cap >= ((int64_t)1 << 40) || nb >= ((int64_t)1 << 31))
         return fail(IDM_ERR_LAYOUT, "layout too large");
+    // bundles of whole lanes only: fullest first, each to the level with the
+    // fewest bundles so far (lowest level on ties)
+    std::vector<int64_t> count((size_t)n_levels, 0);
+    std::vector<int> free_b;
+    for (int64_t b = 0; b < nb; ++b) {
+        if (level[b] >= 0)
+            ++count[level[b]];
+        else
+            free_b.push_back((int)b);
+    }
+    std::stable_sort(free_b.begin(), free_b.end(), [&](int x, int y) { return fill[x] > fill[y]; });
+    for (int b : free_b) {
+        int best = 0;
+        for (int lv = 1; lv < n_levels; ++lv)
+            if (count[lv] < count[best]) best = lv;
+        level[b] = best;
+        ++count[best];
+    }
+    std::vector<int> border((size_t)nb);
+    for (int64_t i = 0; i < nb; ++i) border[i] = (int)i;
+    std::stable_sort(border.begin(), border.end(), [&](int x, int y) {
+        return level[x] != level[y] ? level[x] < level[y] : fill[x] > fill[y];
+    });
     out.n_bundles = nb;
     out.cap = cap;
+    out.n_bnd = (int32_t)nbnd;
     out.gidx.assign((size_t)(nb * cap), -1);
     out.flags.assign((size_t)(nb * cap), 0);
+    out.bnd_in.assign((size_t)nb, -1);
+    out.bnd_out.assign((size_t)nb, -1);
+    out.level.assign((size_t)nb, 0);
+    out.level_start.assign((size_t)n_levels + 1, 0);
     for (int64_t bi = 0; bi < nb; ++bi) {
+        const int b = border[bi];
+        out.bnd_in[bi] = bin[b];
+        out.bnd_out[bi] = bout[b];
+        out.level[bi] = level[b];
+        ++out.level_start[level[b] + 1];
         int64_t s = bi * cap;
-        for (int l : bundles[border[bi]]) {
-            int32_t lo = offsets[l], hi = offsets[l + 1];
-            for (int32_t i = lo; i < hi; ++i, ++s) {
+        for (const Item &it : bundles[b]) {
+            for (int32_t i = it.lo; i < it.hi; ++i, ++s) {
                 out.gidx[s] = i;
                 uint8_t f = SLOT_VALID;
-                if (i == lo) f |= SLOT_HEAD;
-                if (i == hi - 1) f |= SLOT_TAIL;
+                if (i == it.lo && it.lane_head) f |= SLOT_HEAD;
+                if (i == it.hi - 1 && it.lane_tail) f |= SLOT_TAIL;
                 out.flags[s] = f;
             }
         }
     }
+    for (int32_t lv = 0; lv < n_levels; ++lv) out.level_start[lv + 1] += out.level_start[lv];
     return IDM_OK;
 }
 
@@ -213,6 +318,28 @@ idm_status build_layout(idm_plan *p, const Shape &sh) {
             return hip_fail(e, "hipMemcpy(slot table)");
         }
     }
+    int32_t *db = nullptr;
+    if (lay.n_bnd > 0) {
+        const size_t nb = (size_t)lay.n_bundles;
+        e = hipMalloc(&db, 2 * nb * sizeof(int32_t));
+        if (e == hipSuccess)
+            e = hipMemcpy(db, lay.bnd_in.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(db + nb, lay.bnd_out.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hipFree(dg);
+            hipFree(df);
+            if (db) hipFree(db);
+            return hip_fail(e, "boundary table");
+        }
+    }
+    // the tables below are made once per plan; a failure frees this layout
+    auto fail_tables = [&](hipError_t err, const char *what) {
+        hipFree(dg);
+        hipFree(df);
+        if (db) hipFree(db);
+        return hip_fail(err, what);
+    };
     if (!p->d_lane_off) {
         std::vector<int32_t> lane_of((size_t)p->pb.n_vehicles, 0);
         for (int l = 0; l < p->pb.n_lanes; ++l)
@@ -225,11 +352,7 @@ idm_status build_layout(idm_plan *p, const Shape &sh) {
         if (e == hipSuccess)
             e = hipMemcpy(p->d_lane_of, lane_of.data(), lane_of.size() * sizeof(int32_t),
                           hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            hipFree(dg);
-            hipFree(df);
-            return hip_fail(e, "lane tables");
-        }
+        if (e != hipSuccess) return fail_tables(e, "lane tables");
     }
     if (!p->d_head) {
         std::vector<uint8_t> head((size_t)p->pb.n_vehicles, 0);
@@ -237,35 +360,32 @@ idm_status build_layout(idm_plan *p, const Shape &sh) {
             if (p->offsets[l + 1] > p->offsets[l]) head[(size_t)p->offsets[l]] = 1;
         e = hipMalloc(&p->d_head, head.size());
         if (e == hipSuccess) e = hipMemcpy(p->d_head, head.data(), head.size(), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            hipFree(dg);
-            hipFree(df);
-            return hip_fail(e, "head flags");
-        }
+        if (e != hipSuccess) return fail_tables(e, "head flags");
     }
     if (!p->d_zero) {
         e = hipMalloc(&p->d_zero, 64 * sizeof(float));
         if (e == hipSuccess) e = hipMemset(p->d_zero, 0, 64 * sizeof(float));
-        if (e != hipSuccess) {
-            hipFree(dg);
-            hipFree(df);
-            return hip_fail(e, "hipMalloc(zero word)");
-        }
+        if (e != hipSuccess) return fail_tables(e, "hipMalloc(zero word)");
     }
     if (p->d_gidx) hipFree(p->d_gidx);
     if (p->d_flags) hipFree(p->d_flags);
+    if (p->d_bnd) hipFree(p->d_bnd);
     p->d_gidx = dg;
     p->d_flags = df;
+    p->d_bnd = db;
     p->n_bundles = (int32_t)lay.n_bundles;
     p->n_slots = lay.n_bundles * lay.cap;
+    p->n_bnd = lay.n_bnd;
+    p->level_start = lay.level_start;
     p->sh = sh;
     if (p->sh.grid > p->n_bundles) p->sh.grid = p->n_bundles;
     drop_graphs(p);
     return IDM_OK;
 }
 
-// Default launch shape: the smallest bundle that holds the longest lane, one
-// vehicle per thread when possible (most work-groups), K from the problem.
+// Default launch shape: one vehicle per thread when K allows it (most
+// work-groups), the smallest bundle that holds the longest lane, or 1024
+// threads with longer lanes cut into pieces; K from the problem.
 idm_status choose_shape(const idm_plan *p, const idm_tuning *tu, Shape &sh) {
     int K = p->pb.ckpt_every;
     if (tu && tu->ckpt_every > 0) K = tu->ckpt_every;
@@ -277,24 +397,34 @@ idm_status choose_shape(const idm_plan *p, const idm_tuning *tu, Shape &sh) {
                         tu->threads, tu->per_thread);
         sh.threads = tu->threads;
         sh.per_thread = tu->per_thread;
+        if ((int64_t)sh.threads * sh.per_thread < p->max_lane && sh.per_thread != 1)
+            return fail(IDM_ERR_UNSUPPORTED,
+                        "a %d-vehicle lane does not fit %d x %d slots: lanes cut into pieces "
+                        "need one vehicle per thread",
+                        p->max_lane, sh.threads, sh.per_thread);
     } else {
         const int64_t need = std::max<int64_t>(p->max_lane, 1);
         bool found = false;
         for (int r : {1, 2, 4}) {
             if (KB_req > 0 ? !(kb_ok(r, KB_req) && K % KB_req == 0) : default_kb(r, K) == 0) continue;
+            // lanes cut into pieces need one vehicle per thread
+            if (r > 1 && need > 1024 * r) continue;
+            sh.threads = 1024;
+            sh.per_thread = r;
             for (int t : {64, 128, 256, 512, 1024}) {
                 if ((int64_t)t * r >= need) {
                     sh.threads = t;
-                    sh.per_thread = r;
-                    found = true;
                     break;
                 }
             }
-            if (found) break;
+            found = true;
+            break;
         }
         if (!found)
-            return fail(IDM_ERR_UNSUPPORTED, "no launch shape holds a %d-vehicle lane with K=%d",
-                        p->max_lane, K);
+            return fail(IDM_ERR_UNSUPPORTED,
+                        "no launch shape for K=%d and a %d-vehicle lane: K needs a backward block "
+                        "that divides it (8, 16 or 32 for lanes cut into pieces)",
+                        K, p->max_lane);
     }
     const int KB = KB_req > 0 ? KB_req : default_kb(sh.per_thread, K);
     if (KB <= 0 || !kb_ok(sh.per_thread, KB) || K % KB != 0)
@@ -344,7 +474,33 @@ idm_status check_obs(const idm_plan *p, const idm_obs *obs) {
     return IDM_OK;
 }
 
-int grid_of(const idm_plan *p) { return p->sh.grid > 0 ? std::min(p->sh.grid, p->n_bundles) : p->n_bundles; }
+int grid_of(const idm_plan *p, int32_t n) { return p->sh.grid > 0 ? std::min(p->sh.grid, n) : n; }
+int grid_of(const idm_plan *p) { return grid_of(p, p->n_bundles); }
+
+int32_t n_levels(const idm_plan *p) { return (int32_t)p->level_start.size() - 1; }
+
+// Launch level `lv`: its bundle tables (and the first of its loss partials);
+// returns its bundle count.
+int32_t level_args(const idm_plan *p, int32_t lv, SimArgs &a, double *loss_base) {
+    const int32_t b0 = p->level_start[lv], b1 = p->level_start[lv + 1];
+    const int64_t cap = (int64_t)p->sh.threads * p->sh.per_thread;
+    a.slot_gidx = p->d_gidx + b0 * cap;
+    a.slot_flags = p->d_flags + b0 * cap;
+    a.n_bundles = b1 - b0;
+    if (p->d_bnd) {
+        a.bnd_in = p->d_bnd + b0;
+        a.bnd_out = p->d_bnd + p->n_bundles + b0;
+    }
+    if (loss_base) a.loss_part = loss_base + b0;
+    return b1 - b0;
+}
+
+void ext_args(const idm_plan *p, void *ws, SimArgs &a) {
+    if (p->n_bnd == 0) return;
+    char *base = (char *)ws + ws_ext_off(p, p->sh.K, p->n_bnd);
+    a.ext_state = (float2 *)base;
+    a.ext_adj = (float2 *)(base + ext_state_bytes(p, p->n_bnd));
+}
 
 idm_status run_forward(idm_plan *p, const idm_params *prm, const double *p0, const float *v_init,
                        float *traj_d, float *traj_v, void *ws, hipStream_t s) {
@@ -356,11 +512,22 @@ idm_status run_forward(idm_plan *p, const idm_params *prm, const double *p0, con
     a.traj_v = traj_v;
     a.ckpt = ws ? (float *)((char *)ws + ws_ckpt_off(p)) : nullptr;
     if (p->pb.n_steps == 0 && a.ckpt) a.ckpt = nullptr;
-    KernelFn fn = forward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads);
+    if (p->n_bnd > 0) {
+        if (!ws)
+            return fail(IDM_ERR_WORKSPACE,
+                        "lanes longer than a bundle exchange boundary states through the "
+                        "workspace; the forward needs it");
+        ext_args(p, ws, a);
+    }
+    KernelFn fn = forward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, p->n_bnd > 0);
     if (!fn) return fail(IDM_ERR_UNSUPPORTED, "no forward kernel for this shape");
-    if (p->n_bundles == 0) return IDM_OK;
-    hipError_t e = launch_sim(fn, grid_of(p), p->sh.threads, a, s);
-    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    // pieces of long lanes: level l reads the boundary states level l-1 wrote
+    for (int32_t lv = 0; lv < n_levels(p); ++lv) {
+        const int32_t nb = level_args(p, lv, a, nullptr);
+        if (nb == 0) continue;
+        hipError_t e = launch_sim(fn, grid_of(p, nb), p->sh.threads, a, s);
+        if (e != hipSuccess) return hip_fail(e, "forward launch");
+    }
     return IDM_OK;
 }
 
@@ -387,16 +554,20 @@ idm_status run_backward(idm_plan *p, const idm_params *prm, const double *p0, co
     a.g_prm = g_prm;
     a.g_p0 = g_p0;
     a.g_v0 = g_v0;
-    a.loss_part = (double *)((char *)ws + ws_loss_off(p));
+    double *loss_base = (double *)((char *)ws + ws_loss_off(p));
+    ext_args(p, ws, a);
     KernelFn fn = backward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, p->sh.KB, p->sh.K,
-                                  gd || gv);
+                                  gd || gv, p->n_bnd > 0);
     if (!fn) return fail(IDM_ERR_UNSUPPORTED, "no backward kernel for this shape");
-    if (p->n_bundles > 0) {
-        hipError_t e = launch_sim(fn, grid_of(p), p->sh.threads, a, s);
+    // pieces of long lanes: level l reads the adjoint contributions level l+1 wrote
+    for (int32_t lv = n_levels(p) - 1; lv >= 0; --lv) {
+        const int32_t nb = level_args(p, lv, a, loss_base);
+        if (nb == 0) continue;
+        hipError_t e = launch_sim(fn, grid_of(p, nb), p->sh.threads, a, s);
         if (e != hipSuccess) return hip_fail(e, "backward launch");
     }
     if (loss_out) {
-        hipError_t e = launch_loss_finalize(a.loss_part, p->n_bundles, obs ? a.inv_count : 0.0,
+        hipError_t e = launch_loss_finalize(loss_base, p->n_bundles, obs ? a.inv_count : 0.0,
                                             loss_out, s);
         if (e != hipSuccess) return hip_fail(e, "loss finalize launch");
     }
@@ -548,8 +719,6 @@ idm_status host_plan(const idm_problem *pb, const idm_tuning *tu, idm_plan *p, S
         if (off[l + 1] < off[l]) return fail(IDM_ERR_LAYOUT, "lane offsets decrease at lane %d", l);
         max_lane = std::max(max_lane, off[l + 1] - off[l]);
     }
-    if (max_lane > 4096)
-        return fail(IDM_ERR_LAYOUT, "longest lane (%d vehicles) exceeds 4096", max_lane);
     if (tu && (tu->grid < 0 || tu->ckpt_every < 0 || tu->block < 0))
         return fail(IDM_ERR_INVALID_ARG, "tuning: negative grid, ckpt_every or block");
     p->pb = *pb;
@@ -647,8 +816,10 @@ idm_status idm_problem_check(const idm_problem *pb, const idm_tuning *tu, idm_pl
     p.sh = sh;
     p.n_bundles = (int32_t)lay.n_bundles;
     p.n_slots = lay.n_bundles * lay.cap;
+    p.n_bnd = lay.n_bnd;
+    p.level_start = lay.level_start;
     if (p.sh.grid > p.n_bundles) p.sh.grid = p.n_bundles;
-    if (workspace_bytes) *workspace_bytes = ws_total(&p, sh.K);
+    if (workspace_bytes) *workspace_bytes = ws_total(&p, sh.K, p.n_bnd);
     if (info) return idm_plan_get_info(&p, info);
     return IDM_OK;
 }
@@ -671,11 +842,32 @@ idm_status idm_problem_layout(const idm_problem *pb, const idm_tuning *tu, int32
     return IDM_OK;
 }
 
+idm_status idm_problem_bundles(const idm_problem *pb, const idm_tuning *tu, int32_t *bnd_in_host,
+                               int32_t *bnd_out_host, int32_t *level_host, int64_t capacity) {
+    if (!bnd_in_host || !bnd_out_host || !level_host)
+        return fail(IDM_ERR_INVALID_ARG, "null output");
+    idm_plan p;
+    Shape sh;
+    idm_status r = host_plan(pb, tu, &p, sh);
+    if (r != IDM_OK) return r;
+    Layout lay;
+    r = compute_layout(p.offsets, p.pb.n_lanes, sh, lay);
+    if (r != IDM_OK) return r;
+    if (lay.n_bundles > capacity)
+        return fail(IDM_ERR_INVALID_ARG, "capacity %lld < %lld bundles", (long long)capacity,
+                    (long long)lay.n_bundles);
+    std::copy(lay.bnd_in.begin(), lay.bnd_in.end(), bnd_in_host);
+    std::copy(lay.bnd_out.begin(), lay.bnd_out.end(), bnd_out_host);
+    std::copy(lay.level.begin(), lay.level.end(), level_host);
+    return IDM_OK;
+}
+
 idm_status idm_plan_destroy(idm_plan *p) {
     if (!p) return IDM_OK;
     drop_graphs(p);
     if (p->d_gidx) hipFree(p->d_gidx);
     if (p->d_flags) hipFree(p->d_flags);
+    if (p->d_bnd) hipFree(p->d_bnd);
     if (p->d_zero) hipFree(p->d_zero);
     if (p->d_head) hipFree(p->d_head);
     if (p->d_lane_off) hipFree(p->d_lane_off);
@@ -687,7 +879,7 @@ idm_status idm_plan_destroy(idm_plan *p) {
     return IDM_OK;
 }
 
-size_t idm_workspace_bytes(const idm_plan *p) { return p ? ws_total(p, p->sh.K) : 0; }
+size_t idm_workspace_bytes(const idm_plan *p) { return p ? ws_total(p, p->sh.K, p->n_bnd) : 0; }
 
 idm_status idm_plan_get_info(const idm_plan *p, idm_plan_info *o) {
     if (!p || !o) return fail(IDM_ERR_INVALID_ARG, "null argument");
@@ -700,6 +892,8 @@ idm_status idm_plan_get_info(const idm_plan *p, idm_plan_info *o) {
     o->max_lane = p->max_lane;
     o->n_slots = p->n_slots;
     o->fill = p->n_slots ? (double)p->pb.n_vehicles / (double)p->n_slots : 0.0;
+    o->n_levels = n_levels(p);
+    o->n_boundaries = p->n_bnd;
     return IDM_OK;
 }
 
@@ -863,37 +1057,43 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (cus <= 0) cus = 256;
-    std::vector<Shape> cands;
+    std::vector<Shape> cands, spilling;
     // the checkpoint interval the caller fixed is kept; otherwise K = KB
     const bool k_fixed = p->pb.ckpt_every > 0;
     for (int t : {64, 128, 256, 512, 1024})
         for (int rr : {1, 2, 4}) {
-            if ((int64_t)t * rr < p->max_lane) continue;
-            if ((int64_t)t * rr > 8 * std::max<int64_t>(p->max_lane, 64)) continue;
+            // bundles up to 8 times the longest lane; a shorter bundle cuts lanes
+            // into pieces (one vehicle per thread, at most 8 pieces below 1024
+            // threads)
+            const int64_t cap = (int64_t)t * rr;
+            if (cap < p->max_lane && (rr != 1 || (cap * 8 < p->max_lane && t < 1024))) continue;
+            if (cap > 8 * std::max<int64_t>(p->max_lane, 64)) continue;
+            const int64_t nbnd = count_boundaries(p->offsets, p->pb.n_lanes, cap);
             for (int KB : kbs_for(rr)) {
                 // K = KB, and K = 2 KB where a stash variant exists for the shape
                 for (int twice = 0; twice < 2; ++twice) {
                     const int K = k_fixed ? p->pb.ckpt_every : (twice ? 2 * KB : KB);
                     if (k_fixed && twice) break;
-                    if (K % KB != 0 || ws_total(p, K) > ws_bytes) continue;
-                    KernelFn fb = backward_kernel(p->pb.bound, rr, t, KB, K, dense);
-                    if (twice && fb == backward_kernel(p->pb.bound, rr, t, KB, KB, dense)) continue;
-                    hipFuncAttributes fa;
-                    // skip shapes whose backward spills more than a few registers
-                    // (small spills sit outside the step loops)
-                    if (!fb || hipFuncGetAttributes(&fa, fb) != hipSuccess ||
-                        fa.localSizeBytes > 128)
+                    if (K % KB != 0 || ws_total(p, K, nbnd) > ws_bytes) continue;
+                    KernelFn fb = backward_kernel(p->pb.bound, rr, t, KB, K, dense, nbnd > 0);
+                    if (twice && fb == backward_kernel(p->pb.bound, rr, t, KB, KB, dense, nbnd > 0))
                         continue;
+                    hipFuncAttributes fa;
+                    if (!fb || hipFuncGetAttributes(&fa, fb) != hipSuccess) continue;
                     Shape sh;
                     sh.threads = t;
                     sh.per_thread = rr;
                     sh.K = K;
                     sh.KB = KB;
                     sh.grid = 0;
-                    cands.push_back(sh);
+                    // shapes whose backward spills more than a few registers (small
+                    // spills sit outside the step loops) are timed only when no other
+                    // shape holds the longest lane
+                    (fa.localSizeBytes > 128 ? spilling : cands).push_back(sh);
                 }
             }
         }
+    if (cands.empty()) cands.swap(spilling);
     if (cands.empty()) return fail(IDM_ERR_WORKSPACE, "no launch shape fits the workspace");
     const Shape orig = p->sh;
     hipEvent_t e0, e1;
@@ -906,7 +1106,9 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
             Shape s2 = sh;
             if (persistent) {
                 KernelFn fb =
-                    backward_kernel(p->pb.bound, sh.per_thread, sh.threads, sh.KB, sh.K, dense);
+                    backward_kernel(p->pb.bound, sh.per_thread, sh.threads, sh.KB, sh.K, dense,
+                                    count_boundaries(p->offsets, p->pb.n_lanes,
+                                                     (int64_t)sh.threads * sh.per_thread) > 0);
                 int occ = 0;
                 if (!fb || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fb, sh.threads, 0) !=
                                hipSuccess || occ < 1)

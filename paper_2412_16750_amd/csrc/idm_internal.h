@@ -11,7 +11,8 @@
 namespace idmx {
 
 // Slot flags: a bundle is threads*per_thread consecutive slots holding whole
-// lanes (head -> tail) followed by padding.
+// lanes (head -> tail) followed by padding; a lane longer than a bundle is cut
+// into pieces, a piece after the first opening its bundle without a head flag.
 enum : uint8_t { SLOT_HEAD = 1u, SLOT_TAIL = 2u, SLOT_VALID = 4u };
 
 // Everything a simulation kernel reads, passed by value as the kernel argument.
@@ -47,6 +48,16 @@ struct SimArgs {
     double *g_prm;            // [5][N]
     double *g_p0, *g_v0;      // [N]
     double *loss_part;        // [n_bundles]
+
+    // pieces of lanes longer than a bundle (null when there are none).  A
+    // bundle with bnd_in[b] = j >= 0 starts with a piece whose leader is the
+    // last vehicle of the previous piece: that leader's state at step k is
+    // ext_state[j*(S+1) + k], and the piece head's adjoint contribution to it
+    // goes to ext_adj[j*S + k].  A bundle with bnd_out[b] = j >= 0 ends with
+    // that leader: it writes ext_state and reads ext_adj of boundary j.
+    const int32_t *bnd_in, *bnd_out;  // [n_bundles], -1 = none
+    float2 *ext_state;                // [n_boundaries][S+1]
+    float2 *ext_adj;                  // [n_boundaries][S]
 };
 
 struct AdamArgs {
@@ -101,11 +112,12 @@ struct EgoAdamArgs {
 using KernelFn = const void *;
 
 // Lookup of compiled kernel instantiations; nullptr when not instantiated.
-KernelFn forward_kernel(int mode, int per_thread, int threads);
+KernelFn forward_kernel(int mode, int per_thread, int threads, bool pieces);
 // Backward kernel for a register block KB and checkpoint interval K (the
 // stash variant when K = 2 KB and one is instantiated for the shape); `dense`
 // selects the variant that reads dense upstream gradients.
-KernelFn backward_kernel(int mode, int per_thread, int threads, int KB, int K, bool dense);
+KernelFn backward_kernel(int mode, int per_thread, int threads, int KB, int K, bool dense,
+                         bool pieces);
 
 // Launch helpers (return the HIP error of the launch).
 hipError_t launch_sim(KernelFn fn, int grid, int threads, const SimArgs &a, hipStream_t s);

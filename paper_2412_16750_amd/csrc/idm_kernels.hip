@@ -13,6 +13,13 @@
 //     from LDS.  Lanes never interact, so a work-group runs ALL time steps of
 //     its bundle in one launch, with one work-group barrier per step
 //     (ping-pong LDS buffers remove the second barrier).
+//   * A lane longer than a bundle is cut into pieces of a whole bundle each
+//     (plus a remainder).  Piece j runs in a later launch than piece j-1 in
+//     the forward and an earlier one in the backward: the last vehicle of
+//     piece j-1 publishes its state at every step to a boundary buffer that
+//     the head of piece j reads as its leader, and the head of piece j
+//     publishes its adjoint contribution to that leader at every step.  The
+//     leader never depends on its follower, so each launch is complete.
 //   * State is FP32 displacement d = p - p0 plus speed; the initial gap to the
 //     leader g0 = p0_h - p0 - len_h is formed in FP64 once and rounded, so the
 //     gap at step k is g0 + (d_h - d) without cancellation of large positions.
@@ -83,7 +90,9 @@ __device__ __forceinline__ void load_vehicles(const SimArgs &A, int64_t slot0, V
 // +inf and every leader term it computes is exactly zero for any finite
 // leader state, so it reads its own slot instead of a missing leader.  The
 // last thread reads thread 0's follower contribution, which is exactly zero
-// for the same reason.
+// for the same reason.  The one exception, a bundle opened by a later piece of
+// a long lane, replaces both reads with the boundary buffers (ext_lead, and
+// the last thread's gather in the backward).
 __device__ __forceinline__ int lead_thread(int t) { return t > 0 ? t - 1 : 0; }
 template <int NT>
 __device__ __forceinline__ int follow_thread(int t) {
@@ -91,7 +100,44 @@ __device__ __forceinline__ int follow_thread(int t) {
     return (t + 1) & (NT - 1);
 }
 
-template <int MODE, int R, int NT>
+// Boundary rows of bundle `bidx` (uniform): the external leader's states and
+// the adjoint contributions to it (bnd_in), and the same rows of the boundary
+// this bundle's last vehicle leads (bnd_out).  Null when absent.
+struct Ext {
+    const float2 *lead;  // [S+1] leader state of the first vehicle
+    float2 *lead_adj;    // [S]   its contribution to that leader
+    float2 *tail;        // [S+1] state of the last vehicle, for the next piece
+    const float2 *tail_adj;  // [S] the next piece head's contribution to it
+};
+
+template <bool CH>
+__device__ __forceinline__ Ext ext_rows(const SimArgs &A, int bidx) {
+    Ext x{nullptr, nullptr, nullptr, nullptr};
+    if (CH && A.bnd_in) {
+        const int64_t S = A.n_steps;
+        const int32_t bi = A.bnd_in[bidx], bo = A.bnd_out[bidx];
+        if (bi >= 0) {
+            x.lead = A.ext_state + bi * (S + 1);
+            x.lead_adj = A.ext_adj + bi * S;
+        }
+        if (bo >= 0) {
+            x.tail = A.ext_state + bo * (S + 1);
+            x.tail_adj = A.ext_adj + bo * S;
+        }
+    }
+    return x;
+}
+
+// Thread 0's leader at step k when the bundle opens with a later piece.
+__device__ __forceinline__ void ext_lead(const Ext &x, int k, float2 &L) {
+    if (x.lead) {
+        const float2 X = x.lead[k];
+        if (threadIdx.x == 0) L = X;
+    }
+}
+
+// CH: bundles may hold lane pieces (see k_backward).
+template <int MODE, int R, int NT, bool CH>
 __global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
     __shared__ float2 sbuf[2][NT];
     const int t = threadIdx.x;
@@ -101,6 +147,7 @@ __global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
     for (int bidx = blockIdx.x; bidx < A.n_bundles; bidx += gridDim.x) {
         Veh q[R];
         load_vehicles<R>(A, (int64_t)bidx * (NT * R) + t * R, q);
+        const Ext x = ext_rows<CH>(A, bidx);
         float d[R], v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -116,10 +163,13 @@ __global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
             }
         }
         sbuf[0][t] = make_float2(d[R - 1], v[R - 1]);
+        if constexpr (CH)
+            if (x.tail && t == NT - 1) x.tail[0] = make_float2(d[R - 1], v[R - 1]);
         lds_barrier();
         int to_ckpt = A.K;  // steps until the next checkpoint
         for (int k = 0; k < S; ++k) {
             float2 L = sbuf[k & 1][tl];
+            if constexpr (CH) ext_lead(x, k, L);
             float acc[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -132,6 +182,8 @@ __global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
 #pragma unroll
             for (int r = 0; r < R; ++r) euler<MODE>(d[r], v[r], acc[r], A.dt);
             sbuf[(k + 1) & 1][t] = make_float2(d[R - 1], v[R - 1]);
+            if constexpr (CH)
+                if (x.tail && t == NT - 1) x.tail[k + 1] = make_float2(d[R - 1], v[R - 1]);
             const int64_t row = (int64_t)(k + 1) * N;
             const bool ck = A.ckpt && (--to_ckpt == 0) && (k + 1 < S);
             if (to_ckpt == 0) to_ckpt = A.K;
@@ -252,14 +304,17 @@ __device__ __forceinline__ float mse_up(bool observed, bool valid, const Up &u, 
     return s;
 }
 
-// One simulation step of all vehicles of the bundle (leader of the first
-// vehicle from LDS, the others from registers), publishing the new state of
-// the last vehicle into LDS buffer `nb` and ending on a barrier.
-template <int MODE, int R, int NT>
+// One simulation step (step k) of all vehicles of the bundle (leader of the
+// first vehicle from LDS or the boundary buffer, the others from registers),
+// publishing the new state of the last vehicle into LDS buffer `nb` and ending
+// on a barrier.
+template <int MODE, int R, int NT, bool CH>
 __device__ __forceinline__ void bundle_step(const SimArgs &A, const Veh (&q)[R], float (&d)[R],
-                                            float (&v)[R], float2 (*sbuf)[NT], int cb, int nb) {
+                                            float (&v)[R], float2 (*sbuf)[NT], int cb, int nb,
+                                            const Ext &x, int k) {
     const int t = threadIdx.x;
     float2 L = sbuf[cb][lead_thread(t)];
+    if constexpr (CH) ext_lead(x, k, L);
     float acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -286,7 +341,11 @@ __device__ __forceinline__ void bundle_step(const SimArgs &A, const Veh (&q)[R],
 //
 // DN: a dense upstream gradient (dL/dd or dL/dv) may be given; without it the
 // kernel reads only the observed targets.
-template <int MODE, int R, int NT, int KB, bool ST, bool DN>
+//
+// CH: bundles may hold pieces of lanes longer than a bundle (boundary rows);
+// without it that code is compiled out, keeping the register budget of the
+// whole-lane kernels.
+template <int MODE, int R, int NT, int KB, bool ST, bool DN, bool CH>
 __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
     __shared__ float2 sbuf[2][NT];
     __shared__ float2 cbuf[2][NT];
@@ -307,6 +366,7 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
     for (int bidx = blockIdx.x; bidx < A.n_bundles; bidx += gridDim.x) {
         Veh q[R];
         load_vehicles<R>(A, (int64_t)bidx * (NT * R) + t * R, q);
+        const Ext x = ext_rows<CH>(A, bidx);
         float p0h[R], p0l[R];  // p0 = p0h + p0l
         float ld[R], lv[R];
         // dL/dp0: the gap terms plus the fused loss's direct term (p = p0 + d);
@@ -388,7 +448,8 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                         for (int r = 0; r < R; ++r) stash[0][t * R + r] = make_float2(d[r], v[r]);
                         lds_barrier();
                         for (int j = 0; j < KB; ++j) {
-                            const float2 L = stash[j][tlv];
+                            float2 L = stash[j][tlv];
+                            if constexpr (CH) ext_lead(x, k0 + j, L);
                             float acc[R];
 #pragma unroll
                             for (int r = 0; r < R; ++r) {
@@ -413,7 +474,8 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                         lds_barrier();
                         // re-advance from the checkpoint to the sub-block start
                         for (int j = 0; j < sb * KB; ++j)
-                            bundle_step<MODE, R, NT>(A, q, d, v, sbuf, j & 1, (j + 1) & 1);
+                            bundle_step<MODE, R, NT, CH>(A, q, d, v, sbuf, j & 1, (j + 1) & 1,
+                                                         x, k0 + j);
                         if (sb > 0) {
                             // restart the LDS ping-pong at parity 0 (buffer (sb*KB)&1
                             // was written last and is not read again)
@@ -430,7 +492,8 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                                 hd[j][r] = d[r];
                                 hv[j][r] = v[r];
                             }
-                            bundle_step<MODE, R, NT>(A, q, d, v, sbuf, j & 1, (j + 1) & 1);
+                            bundle_step<MODE, R, NT, CH>(A, q, d, v, sbuf, j & 1, (j + 1) & 1,
+                                                         x, ks + j);
                         }
                     }
                     if (blk == nblk - 1 && sb == nsub - 1) {
@@ -470,6 +533,7 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                 } else {
                     Lc = sbuf[(slen - 1) & 1][tl];
                 }
+                if constexpr (CH) ext_lead(x, ks + slen - 1, Lc);
                 // (one step; j is a compile-time index on the register path)
                 auto rstep = [&](const int j, auto from_stash) {
                     constexpr bool FS = decltype(from_stash)::value;
@@ -482,6 +546,13 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                     cursor_dec(A, cur_k);
                     fetch_up<R, DN>(A, cur_k, q, k > 0, nxt);
                     obs_nxt = k > 0 && cursor_obs(cur_k);
+                    // boundary rows of this step: the leader state of step k-1
+                    // and the next piece head's contribution at step k
+                    float2 Xl = make_float2(0.0f, 0.0f), Xf = make_float2(0.0f, 0.0f);
+                    if constexpr (CH) {
+                        if (x.lead && j > 0) Xl = x.lead[k - 1];
+                        if (x.tail_adj) Xf = x.tail_adj[k];
+                    }
                     float sd[R], sv[R];
                     const float2 Lk = Lc;
 #pragma unroll
@@ -501,6 +572,8 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
 #pragma unroll
                             for (int r = 0; r < R; ++r) own[r] = stash[j - 1][t * R + r];
                             Lc = stash[j - 1][tlv];
+                            if constexpr (CH)
+                                if (x.lead && t == 0) Lc = Xl;
                         }
                     }
                     Part P[R];
@@ -521,15 +594,26 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                     // thread): (mu d a*/d d_h, mu d a*/d v_h).  A lane head
                     // contributes exactly 0 (its hg and As vanish), so a lane
                     // tail needs no mask.
-                    cbuf[j & 1][t] = make_float2(mw[0] * P[0].hg, -mwAs[0] * P[0].vc);
+                    const float2 mine = make_float2(mw[0] * P[0].hg, -mwAs[0] * P[0].vc);
+                    cbuf[j & 1][t] = mine;
+                    if constexpr (CH)
+                        if (x.lead_adj && t == 0) x.lead_adj[k] = mine;
                     if constexpr (!FS) {
                         if (j > 0)
                             sbuf[(j - 1) & 1][t] = make_float2(hd[j - 1][R - 1], hv[j - 1][R - 1]);
                     }
                     lds_barrier();
-                    const float2 F = cbuf[j & 1][tf];
+                    float2 F = cbuf[j & 1][tf];
+                    // the last thread's follower is thread 0 (exactly zero for a
+                    // lane head) unless a boundary gives the next piece's head
+                    if constexpr (CH)
+                        if ((x.lead || x.tail_adj) && t == NT - 1) F = Xf;
                     if constexpr (!FS) {
-                        if (j > 0) Lc = sbuf[(j - 1) & 1][tl];
+                        if (j > 0) {
+                            Lc = sbuf[(j - 1) & 1][tl];
+                            if constexpr (CH)
+                                if (x.lead && t == 0) Lc = Xl;
+                        }
                     }
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
@@ -772,21 +856,22 @@ __global__ __launch_bounds__(256) void k_fit_init_u(AdamArgs A, const float *u_r
 
 // ---------------------------------------------------------------- dispatch
 //
-// The file is compiled five times (IDM_PART = 0..4) so the backward
+// The file is compiled nine times (IDM_PART = 0..8) so the backward
 // instantiations of the two bound modes, with and without dense upstream
-// gradients, build in parallel.
+// gradients, with and without lane pieces, build in parallel.
 #ifndef IDM_PART
 #define IDM_PART 0
 #endif
 
-#define IDM_FWD_CASE(M, R, NT) \
-    if (mode == M && per_thread == R && threads == NT) return (KernelFn)&k_forward<M, R, NT>;
+#define IDM_FWD_CASE(M, R, NT)                                                \
+    if (mode == M && per_thread == R && threads == NT)                        \
+        return pieces ? (KernelFn)&k_forward<M, R, NT, true> : (KernelFn)&k_forward<M, R, NT, false>;
 #define IDM_FWD_R(M, R) \
     IDM_FWD_CASE(M, R, 64) IDM_FWD_CASE(M, R, 128) IDM_FWD_CASE(M, R, 256) \
     IDM_FWD_CASE(M, R, 512) IDM_FWD_CASE(M, R, 1024)
 
 #if IDM_PART == 0
-KernelFn forward_kernel(int mode, int per_thread, int threads) {
+KernelFn forward_kernel(int mode, int per_thread, int threads, bool pieces) {
     IDM_FWD_R(0, 1) IDM_FWD_R(0, 2) IDM_FWD_R(0, 4)
     IDM_FWD_R(1, 1) IDM_FWD_R(1, 2) IDM_FWD_R(1, 4)
     return nullptr;
@@ -795,12 +880,12 @@ KernelFn forward_kernel(int mode, int per_thread, int threads) {
 
 #define IDM_BWD_CASE(M, R, NT, KK)                                            \
     if (mode == M && per_thread == R && threads == NT && KB == KK)            \
-        return (KernelFn)&k_backward<M, R, NT, KK, false, IDM_DN>;
+        return (KernelFn)&k_backward<M, R, NT, KK, false, IDM_DN, IDM_CH>;
 // stash variants (checkpoint interval = two register blocks), for the shapes
 // whose stash fits next to the exchange buffers in the 160 KB of LDS
 #define IDM_BWD_ST(M, R, NT, KK)                                              \
     if (mode == M && per_thread == R && threads == NT && KB == KK && K == 2 * KK) \
-        return (KernelFn)&k_backward<M, R, NT, KK, true, IDM_DN>;
+        return (KernelFn)&k_backward<M, R, NT, KK, true, IDM_DN, IDM_CH>;
 #define IDM_BWD_NT(M, R, KK)                                                  \
     IDM_BWD_CASE(M, R, 64, KK) IDM_BWD_CASE(M, R, 128, KK) IDM_BWD_CASE(M, R, 256, KK) \
     IDM_BWD_CASE(M, R, 512, KK) IDM_BWD_CASE(M, R, 1024, KK)
@@ -810,23 +895,38 @@ KernelFn forward_kernel(int mode, int per_thread, int threads) {
     IDM_BWD_NT(M, 1, 8) IDM_BWD_NT(M, 1, 16) IDM_BWD_NT(M, 1, 32)             \
     IDM_BWD_NT(M, 2, 8) IDM_BWD_NT(M, 2, 16) IDM_BWD_NT(M, 2, 32)                \
     IDM_BWD_NT(M, 4, 4) IDM_BWD_NT(M, 4, 8)
+// lane pieces: one vehicle per thread only
+#define IDM_BWD_M_CH(M)                                                       \
+    IDM_BWD_ST(M, 1, 1024, 16) IDM_BWD_ST(M, 1, 512, 16)                      \
+    IDM_BWD_NT(M, 1, 8) IDM_BWD_NT(M, 1, 16) IDM_BWD_NT(M, 1, 32)
 
-// parts 1-4: (softplus, clamp) x (targets only, dense upstream)
-#if IDM_PART >= 1 && IDM_PART <= 4
-#define IDM_DN (IDM_PART >= 3)
+// parts 1-4: (softplus, clamp) x (targets only, dense upstream), whole lanes;
+// parts 5-8: the same with lane pieces
+#if IDM_PART >= 1 && IDM_PART <= 8
+#define IDM_DN (IDM_PART == 3 || IDM_PART == 4 || IDM_PART == 7 || IDM_PART == 8)
+#define IDM_CH (IDM_PART >= 5)
+#define IDM_SP (IDM_PART == 1 || IDM_PART == 3 || IDM_PART == 5 || IDM_PART == 7)
 #if IDM_PART == 1
 KernelFn backward_kernel_sp_t(int mode, int per_thread, int threads, int KB, int K) {
 #elif IDM_PART == 2
 KernelFn backward_kernel_cl_t(int mode, int per_thread, int threads, int KB, int K) {
 #elif IDM_PART == 3
 KernelFn backward_kernel_sp_d(int mode, int per_thread, int threads, int KB, int K) {
-#else
+#elif IDM_PART == 4
 KernelFn backward_kernel_cl_d(int mode, int per_thread, int threads, int KB, int K) {
-#endif
-#if IDM_PART == 1 || IDM_PART == 3
-    IDM_BWD_M(0)
+#elif IDM_PART == 5
+KernelFn backward_kernel_sp_t_ch(int mode, int per_thread, int threads, int KB, int K) {
+#elif IDM_PART == 6
+KernelFn backward_kernel_cl_t_ch(int mode, int per_thread, int threads, int KB, int K) {
+#elif IDM_PART == 7
+KernelFn backward_kernel_sp_d_ch(int mode, int per_thread, int threads, int KB, int K) {
 #else
-    IDM_BWD_M(1)
+KernelFn backward_kernel_cl_d_ch(int mode, int per_thread, int threads, int KB, int K) {
+#endif
+#if IDM_CH
+    IDM_BWD_M_CH(IDM_SP ? 0 : 1)
+#else
+    IDM_BWD_M(IDM_SP ? 0 : 1)
 #endif
     return nullptr;
 }
@@ -836,7 +936,19 @@ KernelFn backward_kernel_sp_t(int, int, int, int, int);
 KernelFn backward_kernel_cl_t(int, int, int, int, int);
 KernelFn backward_kernel_sp_d(int, int, int, int, int);
 KernelFn backward_kernel_cl_d(int, int, int, int, int);
-KernelFn backward_kernel(int mode, int per_thread, int threads, int KB, int K, bool dense) {
+KernelFn backward_kernel_sp_t_ch(int, int, int, int, int);
+KernelFn backward_kernel_cl_t_ch(int, int, int, int, int);
+KernelFn backward_kernel_sp_d_ch(int, int, int, int, int);
+KernelFn backward_kernel_cl_d_ch(int, int, int, int, int);
+KernelFn backward_kernel(int mode, int per_thread, int threads, int KB, int K, bool dense,
+                         bool pieces) {
+    if (pieces) {
+        if (dense)
+            return mode == 0 ? backward_kernel_sp_d_ch(mode, per_thread, threads, KB, K)
+                             : backward_kernel_cl_d_ch(mode, per_thread, threads, KB, K);
+        return mode == 0 ? backward_kernel_sp_t_ch(mode, per_thread, threads, KB, K)
+                         : backward_kernel_cl_t_ch(mode, per_thread, threads, KB, K);
+    }
     if (dense)
         return mode == 0 ? backward_kernel_sp_d(mode, per_thread, threads, KB, K)
                          : backward_kernel_cl_d(mode, per_thread, threads, KB, K);

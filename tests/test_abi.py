@@ -67,7 +67,7 @@ def test_valid_problem_shape_and_workspace(L):
 @pytest.mark.parametrize("case, status", [
     (dict(offsets=[0, 5, 3, 10]), -2),            # decreasing
     (dict(offsets=[1, 5]), -2),                   # does not start at 0
-    (dict(offsets=[0, 5000]), -2),                # lane > 4096
+    (dict(offsets=[0, 5000], K=12), -3),          # pieces need 1 vehicle/thread; K=12 needs 4
     (dict(offsets=[0, 10], delta=2.0), -3),       # only delta = 4
     (dict(offsets=[0, 10], dt=0.0), -1),
     (dict(offsets=[0, 10], dt=float("nan")), -1),
@@ -88,7 +88,9 @@ def test_invalid_problems_are_rejected(L, case, status):
 def test_invalid_tuning(L):
     assert _check(L, [0, 100], tuning=(100, 1, 0, 0))[0] == -3
     assert _check(L, [0, 100], tuning=(64, 3, 0, 0))[0] == -3
-    assert _check(L, [0, 100], tuning=(64, 1, 0, 0))[0] == -2   # 100 > 64 slots
+    st, info, _ = _check(L, [0, 100], tuning=(64, 1, 0, 0))    # 100 > 64 slots: two pieces
+    assert st == 0 and (info.n_levels, info.n_boundaries, info.n_bundles) == (2, 1, 2)
+    assert _check(L, [0, 200], tuning=(64, 2, 0, 0))[0] == -3   # pieces need 1 vehicle/thread
     assert _check(L, [0, 100], tuning=(128, 1, 0, -1))[0] == -1
     assert _check(L, [0, 100], tuning=(64, 4, 32, 0, 16))[0] == -3  # block 16 not for R=4
     assert _check(L, [0, 100], tuning=(128, 1, 24, 0, 16))[0] == -3  # 16 does not divide 24
@@ -164,3 +166,87 @@ def test_python_binding_rejects_bad_tensors():
         sim._need(torch.zeros(3), "x", torch.float32, 3)   # CPU tensor
     with pytest.raises(TypeError):
         sim._need(np.zeros(3), "x", torch.float32, 3)         # not a tensor
+
+
+def _bundles(L, offsets, tuning):
+    from paper_2412_16750_amd._lib import IdmTuning
+    st, info, ws = _check(L, offsets, tuning=tuning)
+    assert st == 0
+    pb, off = _problem(offsets)
+    tu = IdmTuning(*tuning) if tuning else None
+    nb = info.n_bundles
+    bin_, bout, lvl = (np.empty(nb, dtype=np.int32) for _ in range(3))
+    args = [ctypes.byref(pb), ctypes.byref(tu) if tu else None] + \
+        [a.ctypes.data_as(ctypes.c_void_p) for a in (bin_, bout, lvl)]
+    assert L.idm_problem_bundles(*args, nb - 1) == -1
+    assert L.idm_problem_bundles(*args, nb) == 0
+    return info, ws, bin_, bout, lvl
+
+
+@pytest.mark.parametrize("tuning", [(64, 1, 8, 0, 0), (256, 1, 16, 0, 0), None])
+def test_long_lanes_are_cut_into_pieces(L, tuning):
+    """Lanes longer than a bundle: pieces of a whole bundle each plus a
+    remainder, piece j in launch level j, every boundary linking the last
+    slot of piece j-1 to the first slot of piece j; short lanes fill the
+    remainders' room and spread over the levels."""
+    import scenarios
+    cap = tuning[0] * tuning[1] if tuning else 1024
+    sizes = scenarios.lognormal_lane_sizes(400, np.log(cap) - 0.5, 1.0, 1, 5 * cap, 77)
+    sizes[[3, 50]] = [4 * cap, cap + 1]
+    sizes[::53] = 0
+    off = scenarios.offsets_from_sizes(sizes)
+    info, gidx, flags = _layout(L, off, tuning) if tuning else (None, None, None)
+    if tuning is None:
+        from paper_2412_16750_amd._lib import IdmTuning
+        st, info, _ = _check(L, off)
+        assert st == 0 and (info.threads, info.per_thread) == (1024, 1)
+        tuning = (1024, 1, 0, 0, 0)
+        info, gidx, flags = _layout(L, off, tuning)
+    info, ws, bin_, bout, lvl = _bundles(L, off, tuning)
+    N = int(off[-1])
+    pieces = np.where(sizes > cap, -(-sizes // cap), 1)
+    assert info.n_levels == pieces.max() == 5
+    assert info.n_boundaries == int(np.sum(pieces[sizes > 0] - 1))
+    valid = gidx >= 0
+    assert np.array_equal(np.sort(gidx[valid]), np.arange(N))
+    # only a lane's own first and last vehicles carry head / tail flags
+    heads = np.zeros(N, dtype=bool)
+    tails = np.zeros(N, dtype=bool)
+    heads[gidx[valid & ((flags & 1) == 1)]] = True
+    tails[gidx[valid & ((flags & 2) == 2)]] = True
+    ne = sizes > 0
+    assert np.array_equal(np.flatnonzero(heads), off[:-1][ne])
+    assert np.array_equal(np.flatnonzero(tails), off[1:][ne] - 1)
+    g = gidx.reshape(-1, cap)
+    # levels ascend through the bundle list
+    assert np.all(np.diff(lvl) >= 0) and lvl[0] == 0 and lvl[-1] == info.n_levels - 1
+    seen = set()
+    for b in range(info.n_bundles):
+        if bin_[b] >= 0:
+            j = bin_[b]
+            src = np.flatnonzero(bout == j)
+            assert len(src) == 1 and j not in seen
+            seen.add(j)
+            a = src[0]
+            # the leader bundle is a full piece whose last slot leads slot 0 here
+            assert np.all(g[a] >= 0) and g[a, -1] + 1 == g[b, 0]
+            assert not heads[g[b, 0]] and lvl[b] == lvl[a] + 1
+        if bout[b] >= 0:
+            assert np.all(g[b] >= 0) and not tails[g[b, -1]]
+    assert seen == set(range(info.n_boundaries))
+    # bundles of whole lanes only even out the level sizes
+    counts = np.bincount(lvl, minlength=info.n_levels)
+    fixed = np.zeros(info.n_levels, dtype=int)
+    for b in range(info.n_bundles):
+        if bin_[b] >= 0 or bout[b] >= 0:
+            fixed[lvl[b]] += 1
+    free = counts - fixed
+    assert np.all((free == 0) | (counts <= counts.min() + 1))
+    # workspace: loss partials per lane and piece, fit buffer, checkpoints,
+    # boundary rows (S + 1 states and S adjoint contributions of 8 B)
+    S, K = 100, info.ckpt_every
+    align = lambda x: (x + 255) // 256 * 256
+    nbnd = info.n_boundaries
+    expect = (align(8 * (len(sizes) + nbnd)) + align(8 * 7 * N) + align(-(-S // K) * 8 * N)
+              + align(nbnd * (S + 1) * 8) + align(nbnd * S * 8))
+    assert ws == expect
