@@ -36,6 +36,10 @@ idm_status hip_fail(hipError_t e, const char *what) {
 }
 
 constexpr size_t kAlign = 256;
+// Resident work-group model used to size launch levels: MI355X has 256 compute
+// units of at most 2048 resident threads (the forward kernels reach it).
+constexpr int64_t kRoundCUs = 256;
+constexpr int kThreadsPerCU = 2048;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Shape {
@@ -160,9 +164,9 @@ void drop_graphs(idm_plan *p) {
 // backward downwards), the boundary between pieces j-1 and j getting one row of
 // the boundary buffers.  Whole lanes then go best-fit decreasing (ties keep
 // lane order) into the room left by remainders or into new bundles, and the
-// bundles of whole lanes only are spread over the levels so that every level
-// launches about as many work-groups.  Within a level, bundles are sorted by
-// fill (largest first), so a persistent grid starts with the most work.
+// bundles of whole lanes only fill up each level's last round of resident
+// work-groups.  Within a level, bundles are sorted by fill (largest first), so
+// a persistent grid starts with the most work.
 // Deterministic; host only.
 struct Layout {
     int64_t n_bundles = 0, cap = 0;
@@ -242,8 +246,11 @@ idm_status compute_layout(const std::vector<int32_t> &offsets, int L, const Shap
     const int64_t nb = (int64_t)bundles.size();
     if (nb * cap >= ((int64_t)1 << 40) || nb >= ((int64_t)1 << 31))
         return fail(IDM_ERR_LAYOUT, "layout too large");
-    // bundles of whole lanes only: fullest first, each to the level with the
-    // fewest bundles so far (lowest level on ties)
+    // bundles of whole lanes only, fullest first: into the room left in the
+    // last round of resident work-groups of each level (level 0 first), the
+    // rest into level 0, so that the levels take as few rounds as one launch
+    // of all bundles would
+    const int64_t q = kRoundCUs * std::max(1, kThreadsPerCU / sh.threads);
     std::vector<int64_t> count((size_t)n_levels, 0);
     std::vector<int> free_b;
     for (int64_t b = 0; b < nb; ++b) {
@@ -253,13 +260,15 @@ idm_status compute_layout(const std::vector<int32_t> &offsets, int L, const Shap
             free_b.push_back((int)b);
     }
     std::stable_sort(free_b.begin(), free_b.end(), [&](int x, int y) { return fill[x] > fill[y]; });
-    for (int b : free_b) {
-        int best = 0;
-        for (int lv = 1; lv < n_levels; ++lv)
-            if (count[lv] < count[best]) best = lv;
-        level[b] = best;
-        ++count[best];
+    size_t next = 0;
+    for (int32_t lv = 0; lv < n_levels && next < free_b.size(); ++lv) {
+        const int64_t room_lv = (count[lv] + q - 1) / q * q - count[lv];
+        for (int64_t i = 0; i < room_lv && next < free_b.size(); ++i) {
+            level[free_b[next++]] = lv;
+            ++count[lv];
+        }
     }
+    for (; next < free_b.size(); ++next) level[free_b[next]] = 0;
     std::vector<int> border((size_t)nb);
     for (int64_t i = 0; i < nb; ++i) border[i] = (int)i;
     std::stable_sort(border.begin(), border.end(), [&](int x, int y) {

@@ -128,17 +128,68 @@ __device__ __forceinline__ Ext ext_rows(const SimArgs &A, int bidx) {
     return x;
 }
 
-// Thread 0's leader at step k when the bundle opens with a later piece.
-__device__ __forceinline__ void ext_lead(const Ext &x, int k, float2 &L) {
-    if (x.lead) {
-        const float2 X = x.lead[k];
-        if (threadIdx.x == 0) L = X;
-    }
+// The boundary leader's states, staged 64 steps at a time through LDS by wave
+// 0: lane l loads step k0 + l of the chunk after next while the current chunk
+// is read from LDS, so a step never waits on memory (a wait for a register
+// load would also wait for every trajectory store before it).
+__device__ __forceinline__ float2 lead_row(const Ext &x, int k, int S) {
+    const int kk = k + (int)(threadIdx.x & 63);
+    return kk <= S ? x.lead[kk] : make_float2(0.0f, 0.0f);
+}
+
+// The backward reads and writes the boundary rows through raw buffer
+// resources: an absent row has zero records, so its loads return 0 and its
+// stores are dropped without a memory access.  Every step then issues the
+// same loads and stores, and the compiler can count the outstanding memory
+// operations exactly instead of waiting for all of them.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+struct ExtRs {
+    __amdgpu_buffer_rsrc_t lead, lead_adj, tail_adj;
+    bool has_lead;
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float2 *p, int n) {
+    const char *c = reinterpret_cast<const char *>(reinterpret_cast<uintptr_t>(p));
+    return __builtin_amdgcn_make_buffer_rsrc((void *)c, (short)0, p ? n * 8 : 0, 0x00020000);
+}
+
+__device__ __forceinline__ ExtRs ext_rsrc(const Ext &x, int S) {
+    ExtRs r;
+    r.lead = row_rsrc(x.lead, S + 1);
+    r.lead_adj = row_rsrc(x.lead_adj, S);
+    r.tail_adj = row_rsrc(x.tail_adj, S);
+    r.has_lead = x.lead != nullptr;
+    return r;
+}
+
+// Row entry k (k < 0 reads as 0).
+__device__ __forceinline__ float2 row_load(__amdgpu_buffer_rsrc_t rs, int k) {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, k >= 0 ? k * 8 : 0x7ffffff0, 0, 0);
+    return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+}
+
+// Thread 0 writes row entry k; every other lane's store falls outside the row.
+__device__ __forceinline__ void row_store_t0(__amdgpu_buffer_rsrc_t rs, int k, float2 v) {
+    const u32x2 d = {__float_as_uint(v.x), __float_as_uint(v.y)};
+    __builtin_amdgcn_raw_buffer_store_b64(d, rs, threadIdx.x == 0 ? k * 8 : 0x7ffffff0, 0, 0);
+}
+
+// Leader states of thread 0 streamed one step ahead: `next` holds step k when
+// step k starts; the step fetches k + 1 and keeps the value it used in `used`.
+struct LeadPipe {
+    float2 next, used;
+};
+
+__device__ __forceinline__ void lead_pipe_step(const ExtRs &xr, LeadPipe &lp, int k, float2 &L) {
+    lp.used = lp.next;
+    lp.next = row_load(xr.lead, k + 1);
+    if (threadIdx.x == 0 && xr.has_lead) L = lp.used;
 }
 
 // CH: bundles may hold lane pieces (see k_backward).
 template <int MODE, int R, int NT, bool CH>
-__global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
+__device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf)[64]) {
     __shared__ float2 sbuf[2][NT];
     const int t = threadIdx.x;
     const int tl = lead_thread(t);
@@ -163,13 +214,30 @@ __global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
             }
         }
         sbuf[0][t] = make_float2(d[R - 1], v[R - 1]);
-        if constexpr (CH)
+        float2 lead_next = make_float2(0.0f, 0.0f);  // wave 0: the next 64-step chunk
+        if constexpr (CH) {
             if (x.tail && t == NT - 1) x.tail[0] = make_float2(d[R - 1], v[R - 1]);
+            if (x.lead && t < 64) {
+                lead_buf[0][t] = lead_row(x, 0, S);
+                lead_next = lead_row(x, 64, S);
+            }
+        }
         lds_barrier();
         int to_ckpt = A.K;  // steps until the next checkpoint
         for (int k = 0; k < S; ++k) {
             float2 L = sbuf[k & 1][tl];
-            if constexpr (CH) ext_lead(x, k, L);
+            if constexpr (CH) {
+                if (x.lead) {
+                    const float2 X = lead_buf[(k >> 6) & 1][k & 63];
+                    if (t == 0) L = X;
+                    // last step of a chunk: stage the next one (read after this
+                    // step's barrier) and fetch the one after
+                    if ((k & 63) == 63 && t < 64) {
+                        lead_buf[((k >> 6) + 1) & 1][t] = lead_next;
+                        lead_next = lead_row(x, k + 65, S);
+                    }
+                }
+            }
             float acc[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -203,6 +271,21 @@ __global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
             lds_barrier();
         }
     }
+}
+
+
+template <int MODE, int R, int NT>
+__global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
+    forward_body<MODE, R, NT, false>(A, nullptr);
+}
+
+// Lane pieces (one vehicle per thread), with the register budget of 8 waves
+// per SIMD: two 1024-thread work-groups per compute unit.
+template <int MODE, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_forward_pieces(
+    SimArgs A) {
+    __shared__ float2 lead_buf[2][64];
+    forward_body<MODE, 1, NT, true>(A, lead_buf);
 }
 
 // ---------------------------------------------------------------- backward
@@ -311,10 +394,10 @@ __device__ __forceinline__ float mse_up(bool observed, bool valid, const Up &u, 
 template <int MODE, int R, int NT, bool CH>
 __device__ __forceinline__ void bundle_step(const SimArgs &A, const Veh (&q)[R], float (&d)[R],
                                             float (&v)[R], float2 (*sbuf)[NT], int cb, int nb,
-                                            const Ext &x, int k) {
+                                            const ExtRs &xr, LeadPipe &lp, int k) {
     const int t = threadIdx.x;
     float2 L = sbuf[cb][lead_thread(t)];
-    if constexpr (CH) ext_lead(x, k, L);
+    if constexpr (CH) lead_pipe_step(xr, lp, k, L);
     float acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -366,7 +449,9 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
     for (int bidx = blockIdx.x; bidx < A.n_bundles; bidx += gridDim.x) {
         Veh q[R];
         load_vehicles<R>(A, (int64_t)bidx * (NT * R) + t * R, q);
-        const Ext x = ext_rows<CH>(A, bidx);
+        ExtRs xr{};
+        if constexpr (CH) xr = ext_rsrc(ext_rows<CH>(A, bidx), S);
+        LeadPipe lp{};
         float p0h[R], p0l[R];  // p0 = p0h + p0l
         float ld[R], lv[R];
         // dL/dp0: the gap terms plus the fused loss's direct term (p = p0 + d);
@@ -446,10 +531,11 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                         // advance through the lower sub-block, keeping its states
 #pragma unroll
                         for (int r = 0; r < R; ++r) stash[0][t * R + r] = make_float2(d[r], v[r]);
+                        if constexpr (CH) lp.next = row_load(xr.lead, k0);
                         lds_barrier();
                         for (int j = 0; j < KB; ++j) {
                             float2 L = stash[j][tlv];
-                            if constexpr (CH) ext_lead(x, k0 + j, L);
+                            if constexpr (CH) lead_pipe_step(xr, lp, k0 + j, L);
                             float acc[R];
 #pragma unroll
                             for (int r = 0; r < R; ++r) {
@@ -471,11 +557,12 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                         }
                     } else {
                         sbuf[0][t] = make_float2(d[R - 1], v[R - 1]);
+                        if constexpr (CH) lp.next = row_load(xr.lead, k0);
                         lds_barrier();
                         // re-advance from the checkpoint to the sub-block start
                         for (int j = 0; j < sb * KB; ++j)
                             bundle_step<MODE, R, NT, CH>(A, q, d, v, sbuf, j & 1, (j + 1) & 1,
-                                                         x, k0 + j);
+                                                         xr, lp, k0 + j);
                         if (sb > 0) {
                             // restart the LDS ping-pong at parity 0 (buffer (sb*KB)&1
                             // was written last and is not read again)
@@ -493,7 +580,7 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                                 hv[j][r] = v[r];
                             }
                             bundle_step<MODE, R, NT, CH>(A, q, d, v, sbuf, j & 1, (j + 1) & 1,
-                                                         x, ks + j);
+                                                         xr, lp, ks + j);
                         }
                     }
                     if (blk == nblk - 1 && sb == nsub - 1) {
@@ -533,7 +620,18 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                 } else {
                     Lc = sbuf[(slen - 1) & 1][tl];
                 }
-                if constexpr (CH) ext_lead(x, ks + slen - 1, Lc);
+                // boundary rows of the sweep, one step ahead: the leader state of
+                // step k-1 and the next piece head's contribution at step k
+                float2 Xl_n = make_float2(0.0f, 0.0f), Xf_n = make_float2(0.0f, 0.0f);
+                if constexpr (CH) {
+                    // the last recomputed step used the leader state of step
+                    // ks + slen - 1; a stashed sub-block recomputed nothing
+                    const float2 Xlast =
+                        stash_use ? row_load(xr.lead, ks + slen - 1) : lp.used;
+                    if (t == 0 && xr.has_lead) Lc = Xlast;
+                    Xl_n = row_load(xr.lead, ks + slen - 2);
+                    Xf_n = row_load(xr.tail_adj, ks + slen - 1);
+                }
                 // (one step; j is a compile-time index on the register path)
                 auto rstep = [&](const int j, auto from_stash) {
                     constexpr bool FS = decltype(from_stash)::value;
@@ -550,8 +648,10 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                     // and the next piece head's contribution at step k
                     float2 Xl = make_float2(0.0f, 0.0f), Xf = make_float2(0.0f, 0.0f);
                     if constexpr (CH) {
-                        if (x.lead && j > 0) Xl = x.lead[k - 1];
-                        if (x.tail_adj) Xf = x.tail_adj[k];
+                        Xl = Xl_n;
+                        Xf = Xf_n;
+                        Xl_n = row_load(xr.lead, k - 2);
+                        Xf_n = row_load(xr.tail_adj, k - 1);
                     }
                     float sd[R], sv[R];
                     const float2 Lk = Lc;
@@ -573,7 +673,7 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                             for (int r = 0; r < R; ++r) own[r] = stash[j - 1][t * R + r];
                             Lc = stash[j - 1][tlv];
                             if constexpr (CH)
-                                if (x.lead && t == 0) Lc = Xl;
+                                if (t == 0 && xr.has_lead) Lc = Xl;
                         }
                     }
                     Part P[R];
@@ -596,8 +696,7 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                     // tail needs no mask.
                     const float2 mine = make_float2(mw[0] * P[0].hg, -mwAs[0] * P[0].vc);
                     cbuf[j & 1][t] = mine;
-                    if constexpr (CH)
-                        if (x.lead_adj && t == 0) x.lead_adj[k] = mine;
+                    if constexpr (CH) row_store_t0(xr.lead_adj, k, mine);
                     if constexpr (!FS) {
                         if (j > 0)
                             sbuf[(j - 1) & 1][t] = make_float2(hd[j - 1][R - 1], hv[j - 1][R - 1]);
@@ -607,12 +706,12 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                     // the last thread's follower is thread 0 (exactly zero for a
                     // lane head) unless a boundary gives the next piece's head
                     if constexpr (CH)
-                        if ((x.lead || x.tail_adj) && t == NT - 1) F = Xf;
+                        if (t == NT - 1) F = Xf;
                     if constexpr (!FS) {
                         if (j > 0) {
                             Lc = sbuf[(j - 1) & 1][tl];
                             if constexpr (CH)
-                                if (x.lead && t == 0) Lc = Xl;
+                                if (t == 0 && xr.has_lead) Lc = Xl;
                         }
                     }
 #pragma unroll
@@ -865,7 +964,8 @@ __global__ __launch_bounds__(256) void k_fit_init_u(AdamArgs A, const float *u_r
 
 #define IDM_FWD_CASE(M, R, NT)                                                \
     if (mode == M && per_thread == R && threads == NT)                        \
-        return pieces ? (KernelFn)&k_forward<M, R, NT, true> : (KernelFn)&k_forward<M, R, NT, false>;
+        return pieces ? (R == 1 ? (KernelFn)&k_forward_pieces<M, NT> : nullptr)  \
+                      : (KernelFn)&k_forward<M, R, NT>;
 #define IDM_FWD_R(M, R) \
     IDM_FWD_CASE(M, R, 64) IDM_FWD_CASE(M, R, 128) IDM_FWD_CASE(M, R, 256) \
     IDM_FWD_CASE(M, R, 512) IDM_FWD_CASE(M, R, 1024)

@@ -234,14 +234,16 @@ def test_long_lanes_are_cut_into_pieces(L, tuning):
         if bout[b] >= 0:
             assert np.all(g[b] >= 0) and not tails[g[b, -1]]
     assert seen == set(range(info.n_boundaries))
-    # bundles of whole lanes only even out the level sizes
+    # bundles of whole lanes only fill the levels' last rounds of resident
+    # work-groups (256 CUs x 2048 threads): as few rounds as possible
     counts = np.bincount(lvl, minlength=info.n_levels)
     fixed = np.zeros(info.n_levels, dtype=int)
     for b in range(info.n_bundles):
         if bin_[b] >= 0 or bout[b] >= 0:
             fixed[lvl[b]] += 1
-    free = counts - fixed
-    assert np.all((free == 0) | (counts <= counts.min() + 1))
+    q = 256 * max(1, 2048 // tuning[0])
+    rounds = lambda c: int(np.sum(-(-c // q)))
+    assert rounds(counts) == max(rounds(fixed), -(-info.n_bundles // q))
     # workspace: loss partials per lane and piece, fit buffer, checkpoints,
     # boundary rows (S + 1 states and S adjoint contributions of 8 B)
     S, K = 100, info.ckpt_every
@@ -250,3 +252,15 @@ def test_long_lanes_are_cut_into_pieces(L, tuning):
     expect = (align(8 * (len(sizes) + nbnd)) + align(8 * 7 * N) + align(-(-S // K) * 8 * N)
               + align(nbnd * (S + 1) * 8) + align(nbnd * S * 8))
     assert ws == expect
+
+
+def test_level_rounds_on_the_uneven_workload(L):
+    """The 10,000-lane uneven workload at 1024 x 1: 4 levels whose sizes are
+    whole rounds of 512 resident forward work-groups but for one."""
+    import scenarios
+    sc = scenarios.uneven()
+    info, ws, bin_, bout, lvl = _bundles(L, sc.lane_offsets, (1024, 1, 32, 0, 16))
+    counts = np.bincount(lvl)
+    assert info.n_levels == 4 and len(counts) == 4
+    assert np.sum(counts % 512 != 0) <= 1
+    assert int(np.sum(-(-counts // 512))) == -(-info.n_bundles // 512)
