@@ -44,7 +44,7 @@ PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
 # only for the kernel source they were taken with (sha256 of idm_kernels.hip
 # followed by idm_device.h).
 TRAFFIC_BWD_BYTES = 1.2596e9
-TRAFFIC_KERNEL_SHA256 = "e448f5a332ed7d76a5f726ebed95ac85d65b2803b4fd44cd475ab50bcffecb7c"
+TRAFFIC_KERNEL_SHA256 = "50cbff338af0efd5de07425cdf5f8d8c62e19ff6bf81cedd9f479d4b30b618c8"
 
 
 def log(*a):
