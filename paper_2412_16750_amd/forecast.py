@@ -28,7 +28,8 @@ def fit_and_rollout(plan_history: "sim.Plan", plan_rollout: "sim.Plan", length: 
     f.run(iters)
     traj = torch.empty(plan_rollout.n_steps + 1, plan_rollout.n, dtype=torch.float32,
                        device=p0.device)
-    sim.idm_sim_forward(plan_rollout, f.params, length, p0, v_init, traj, None, None)
+    sim.idm_sim_forward(plan_rollout, f.params, length, p0, v_init, traj, None,
+                        plan_rollout.forward_workspace(p0.device))
     return f.params, traj, f
 
 

@@ -107,6 +107,17 @@ class Plan:
     def workspace(self, device="cuda") -> torch.Tensor:
         return torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=device)
 
+    def forward_workspace(self, device="cuda") -> Optional[torch.Tensor]:
+        """A workspace for forward-only calls: None unless lanes longer than a
+        bundle exchange boundary states through it (then one buffer, kept by
+        the plan and reused)."""
+        if self.info()["n_boundaries"] == 0:
+            return None
+        ws = getattr(self, "_fws", None)
+        if ws is None or ws.device != torch.device(device):
+            ws = self._fws = self.workspace(device)
+        return ws
+
     def info(self) -> dict:
         o = IdmPlanInfo()
         check(self._L.idm_plan_get_info(self.handle, ctypes.byref(o)), "idm_plan_get_info")

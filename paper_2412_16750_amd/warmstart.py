@@ -146,7 +146,7 @@ def make_pairs(sc, dev="cuda") -> Dataset:
     p0 = torch.from_numpy(np.ascontiguousarray(sc.p0)).to(dev)
     v = torch.from_numpy(np.ascontiguousarray(sc.v_init)).to(dev)
     traj = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device=dev)
-    sim.idm_sim_forward(plan, prm, length, p0, v, traj, None, None)
+    sim.idm_sim_forward(plan, prm, length, p0, v, traj, None, plan.forward_workspace(dev))
     first, stride = int(sc.extra["obs_first"]), int(sc.extra["obs_stride"])
     n_obs = (sc.n_steps - first) // stride + 1
     noise = torch.from_numpy(scenarios.noise((n_obs, sc.n), 5).astype(np.float32)).to(dev)
@@ -205,9 +205,9 @@ def warm_init(fitter: Fitter, mlp: MLP, plan, obs, p0, v_init, length, cold_para
     if fallback:
         warm = fitter.params.clone()
         traj = torch.empty(plan.n_steps + 1, plan.n, dtype=torch.float32, device=p0.device)
-        sim.idm_sim_forward(plan, warm, length, p0, v_init, traj, None, None)
+        sim.idm_sim_forward(plan, warm, length, p0, v_init, traj, None, fitter.workspace)
         la = lane_loss(plan, traj, p0, obs)
-        sim.idm_sim_forward(plan, cold_params, length, p0, v_init, traj, None, None)
+        sim.idm_sim_forward(plan, cold_params, length, p0, v_init, traj, None, fitter.workspace)
         lb = lane_loss(plan, traj, p0, obs)
         chosen, chose_a = select_by_lane(plan, la, lb, warm, cold_params)
         fitter.init(chosen)
@@ -218,7 +218,8 @@ def warm_init(fitter: Fitter, mlp: MLP, plan, obs, p0, v_init, length, cold_para
 def trajectory_rmse(plan, params, length, p0, v_init, hidden_traj, traj_buf) -> float:
     """RMSE (m) of the simulated trajectory under `params` against the hidden
     trajectory, over every vehicle and steps 1..S (evaluation only)."""
-    sim.idm_sim_forward(plan, params, length, p0, v_init, traj_buf, None, None)
+    sim.idm_sim_forward(plan, params, length, p0, v_init, traj_buf, None,
+                        plan.forward_workspace(p0.device))
     d = (traj_buf[1:] - hidden_traj[1:]).double()
     return float(torch.sqrt((d * d).mean()).item())
 
