@@ -185,3 +185,33 @@ def test_autograd_with_pieces():
     assert grads[0][2] == 8 and grads[1][2] == 1
     # FP64 gradients rounded to FP32 by the wrapper: bitwise equal across the cut
     assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+
+
+def test_autotuner_with_pieces():
+    """The autotuner on lanes up to 2500 vehicles (K fixed at 32): it may pick
+    any shape whose workspace fits; trajectories and gradients stay bitwise
+    those of the default plan."""
+    import torch
+    from paper_2412_16750_amd import sim
+    from gpu_run import device_inputs
+    sizes = _sizes(60, 400, 49, extra=(2500, 1500, 700))
+    sc = ragged_scenario(sizes, 40, seed_c=49, ckpt_every=32)
+    steps = np.arange(1, sc.n_steps + 1)
+    tgt = oracle_targets(sc, steps, c=49)
+    x = device_inputs(sc)
+    obs = sim.Obs(torch.from_numpy(tgt).cuda(), 1, 1)
+    plan = sim.Plan.for_scenario(sc)
+    traj = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device="cuda")
+    b = sim.StepBuffers(plan, x["prm"], x["length"], x["p0"], x["v"], traj_d=traj, obs=obs)
+    # room for the shapes that cut lanes into more pieces
+    b.workspace = torch.empty(4 * plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    b.run_eager()
+    torch.cuda.synchronize()
+    before = [t.clone() for t in (b.traj_d, b.grad_params, b.grad_p0, b.grad_v0)]
+    info = sim.idm_plan_autotune(b, reps=1)
+    log("autotune with pieces chose %s" % info)
+    assert info["ckpt_every"] == 32 and info["per_thread"] == 1
+    b.run_eager()
+    torch.cuda.synchronize()
+    for a, e in zip((b.traj_d, b.grad_params, b.grad_p0, b.grad_v0), before):
+        assert torch.equal(a, e)
