@@ -12,6 +12,7 @@ holds the buffers and the stream, and shuffles the training rows.
 from __future__ import annotations
 
 import ctypes
+import math
 import time
 from dataclasses import dataclass
 from typing import Optional
@@ -159,13 +160,16 @@ def make_pairs(sc, dev="cuda") -> Dataset:
 
 
 def train(mlp: MLP, data: Dataset, batch: int = 4096, epochs: int = 10, seed: int = 0,
-          val: Optional[Dataset] = None, log=None) -> dict:
-    """Minibatch Adam over shuffled rows; returns per-epoch losses and time."""
+          val: Optional[Dataset] = None, log=None, lr_final: Optional[float] = None) -> dict:
+    """Minibatch Adam over shuffled rows; returns per-epoch losses and time.
+    With `lr_final`, the learning rate follows a cosine from the network's
+    initial rate to `lr_final` over all steps; otherwise it stays constant."""
     n = data.X.shape[0]
     nb = n // batch
     g = torch.Generator(device="cpu").manual_seed(seed)
     loss = torch.zeros(1, dtype=torch.float64, device=data.X.device)
     hist = []
+    lr0, total, step = mlp._st.lr, max(epochs * nb, 1), 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for ep in range(epochs):
@@ -173,6 +177,9 @@ def train(mlp: MLP, data: Dataset, batch: int = 4096, epochs: int = 10, seed: in
         Xs, Us = data.X.index_select(0, perm), data.U.index_select(0, perm)
         acc = torch.zeros(1, dtype=torch.float64, device=data.X.device)
         for b in range(nb):
+            if lr_final is not None:
+                mlp._st.lr = lr_final + 0.5 * (lr0 - lr_final) * (1.0 + math.cos(math.pi * step / total))
+            step += 1
             mlp.train_step(Xs[b * batch:(b + 1) * batch], Us[b * batch:(b + 1) * batch], loss)
             acc += loss
         torch.cuda.synchronize()
