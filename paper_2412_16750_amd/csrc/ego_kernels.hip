@@ -197,11 +197,9 @@ __global__ __launch_bounds__(EGO_THREADS) void k_ego_backward(EgoArgs A) {
                 const float mwAs = mw * P.As;
                 A.g_gap[(int64_t)k * N + i] = mw * P.hg;
                 A.g_dv[(int64_t)k * N + i] = mwAs * P.vc;
-                const float keep = (MODE == 0) ? lv : P.gate * lv;
-                float nlv = fmaf(dt, lp, keep);
+                float nlv = fmaf(dt, lp, P.carry * lv);
                 nlv = fmaf(mwAs, P.u1, nlv);
                 nlv = fmaf(-mw * q.fa_v0, P.x3, nlv);
-                if (MODE == 0) nlv = fmaf(mu, P.lbv, nlv);
                 gs[0] = fmaf(mw, P.x4, gs[0]);
                 gs[1] = fmaf(mwAs, hv[j], gs[1]);
                 gs[2] = fmaf(mw, P.rest, gs[2]);

@@ -44,10 +44,10 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// 1 / (1 + e^-x).  For x << 0 the exponential overflows to +inf and the
+// reciprocal gives the limit 0; no NaN for any finite x.
 __device__ __forceinline__ float logistic(float x) {
-    float e = exp2_fast(-fabsf(x) * kLog2e);
-    float r = rcp_fast(1.0f + e);
-    return x >= 0.0f ? r : e * r;
+    return rcp_fast(1.0f + exp2_fast(-x * kLog2e));
 }
 
 // Per-vehicle constants, computed once per launch.
@@ -73,12 +73,14 @@ __device__ __forceinline__ float accel_gd(const Veh &q, float v, float gap, floa
     float s_opt = fmaf(v * dv, q.c, fmaf(v, q.T, q.s0));  // Eq. 1
     float s = (MODE == 0) ? softplus(s_opt) : s_opt;  // Sec. III-C floor on s_opt
     float qq = s * rcp_fast(sg);
-    float ahat = q.a * (1.0f - fmaf(qq, qq, x2 * x2));   // Eq. 2, delta = 4
+    float rest = 1.0f - fmaf(qq, qq, x2 * x2);          // Eq. 2, delta = 4: ahat = a rest
     if (MODE == 0) {
-        float lb = fmaxf(-v * inv_dt, a_min);           // Sec. III-C a_lb
-        return lb + softplus(ahat - lb);
+        // Sec. III-C: a* = a_lb + softplus(ahat - a_lb), a_lb = max(-v/dt, a_min),
+        // carried as -a_lb = min(v/dt, -a_min)
+        float mlb = fminf(v * inv_dt, -a_min);
+        return softplus(fmaf(q.a, rest, mlb)) - mlb;
     }
-    return ahat;
+    return q.a * rest;
 }
 
 // The lane model: gap = p_h - p - len_h = g0 + (d_h - d), dv = v - v_h
@@ -103,7 +105,7 @@ __device__ __forceinline__ void euler(float &d, float &v, float acc, float dt) {
 // acceleration of Eq. 2, a* the bounded one that enters the speed update,
 // gap = g0 + d_h - d and s_opt of Eq. 1:
 //   d a*/d gap  = w hg
-//   d a*/d v    = w (As (T + (dv + v) c) - (4a/v0) x^3) + lbv
+//   d a*/d v    = w (As (T + (dv + v) c) - (4a/v0) x^3) + (d a_lb/d v)(1 - w)
 //   d a*/d v_h  = -w As v c
 //   d a*/d v0   = w (4a/v0) x^4,   d a*/d T = w As v,   d a*/d s0 = w As,
 //   d a*/d a    = w (rest - As v dv c / (2a)),   d a*/d b = -w As v dv c / (2b)
@@ -117,8 +119,11 @@ struct Part {
     float vdvc;    // v dv c
     float rest;    // 1 - x^4 - (s*/gap)^2
     float w;       // d a* / d ahat (1 in CLAMP mode)
-    float lbv;     // contribution of a_lb = max(-v/dt, a_min) to d a*/d v
     float gate;    // d v' / d (v + dt a*): 1, or the clamp indicator
+    float carry;   // d v' / d v apart from the ahat terms: with the bound on
+                   // a_lb = -v/dt its -1/dt (1 - w) cancels all but w of the
+                   // Euler update's 1 (w then, 1 on a_min); the clamp
+                   // indicator in CLAMP mode
 };
 
 // EGO: the speed difference is a free input (the ego-only reconstruction
@@ -138,7 +143,6 @@ __device__ __forceinline__ void partials_gd(const Veh &q, float v, float gap, fl
     float qq = s * inv_sg;
     P.x4 = x2 * x2;
     P.rest = 1.0f - fmaf(qq, qq, P.x4);
-    float ahat = q.a * P.rest;
     float tq = q.two_a * qq * inv_sg;                 // 2 a q / gap
     P.As = -tq * sig_s;
     P.hg = floored ? 0.0f : tq * qq;                  // 2 a q^2 / gap
@@ -147,16 +151,18 @@ __device__ __forceinline__ void partials_gd(const Veh &q, float v, float gap, fl
     P.vc = v * q.c;
     P.vdvc = vdv * q.c;
     if (MODE == 0) {
-        float nv = -v * inv_dt;
-        bool on_v = nv > a_min;                       // tie -> a_min branch
-        float lb = on_v ? nv : a_min;
-        P.w = logistic(ahat - lb);
-        P.lbv = on_v ? (P.w - 1.0f) * inv_dt : 0.0f;
+        // a_lb = max(-v/dt, a_min) (tie -> a_min branch), entering as -a_lb
+        float pv = v * inv_dt;
+        bool on_v = pv < -a_min;
+        float mlb = on_v ? pv : -a_min;
+        P.w = logistic(fmaf(q.a, P.rest, mlb));       // ahat - a_lb
         P.gate = 1.0f;
+        P.carry = on_v ? P.w : 1.0f;
     } else {
+        float ahat = q.a * P.rest;
         P.w = 1.0f;
-        P.lbv = 0.0f;
         P.gate = (fmaf(dt, ahat, v) > 0.0f) ? 1.0f : 0.0f;
+        P.carry = P.gate;
     }
 }
 

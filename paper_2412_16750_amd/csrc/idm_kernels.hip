@@ -725,12 +725,10 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                             fv = F.y;
                         }
                         const float gterm = fmaf(-mw[r], P[r].hg, fd);  // gap terms
-                        const float nld = ld[r] + gterm;
-                        const float keep = (MODE == 0) ? lv[r] : P[r].gate * lv[r];
-                        float nlv = fmaf(dt, ld[r], keep);
+                        const float gu = gterm + um[r];
+                        float nlv = fmaf(dt, ld[r], P[r].carry * lv[r]);
                         nlv = fmaf(mwAs[r], P[r].u1, nlv);
                         nlv = fmaf(-mw[r] * q[r].fa_v0, P[r].x3, nlv);
-                        if (MODE == 0) nlv = fmaf(mu[r], P[r].lbv, nlv);
                         nlv += fv;
                         // sufficient statistics of the five parameter gradients
                         gs[0][r] = fmaf(mw[r], P[r].x4, gs[0][r]);      // v0 (times 4a/v0)
@@ -738,12 +736,12 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                         gs[2][r] = fmaf(mw[r], P[r].rest, gs[2][r]);    // a, direct part
                         gs[3][r] = fmaf(mwAs[r], P[r].vdvc, gs[3][r]);  // a and b, through c
                         gs[4][r] += mwAs[r];                           // s0
-                        gp0[r] += gterm + um[r];
+                        gp0[r] += gu;
                         if constexpr (DN) {
-                            ld[r] = nld + (cur[r].gd + um[r]);
+                            ld[r] = (ld[r] + gu) + cur[r].gd;
                             lv[r] = nlv + cur[r].gv;
                         } else {
-                            ld[r] = nld + um[r];
+                            ld[r] += gu;
                             lv[r] = nlv;
                         }
                     }
