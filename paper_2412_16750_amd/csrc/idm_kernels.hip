@@ -754,9 +754,9 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                 if constexpr (ST) {
                     if (stash_use) {
                         // a stashed sub-block is always full; its states are
-                        // indexed at run time, so the loop stays rolled (half
-                        // the code of an unrolled copy)
-#pragma unroll 1
+                        // indexed at run time.  Two steps per iteration remove
+                        // most loop-carried register copies; a full unroll spills
+#pragma unroll 2
                         for (int j = KB - 1; j >= 0; --j) rstep(j, std::true_type{});
                     } else {
                         sweep_registers();
