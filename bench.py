@@ -43,8 +43,8 @@ PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
 # WRITE_SIZE (scaled by the copy-kernel calibration, 2.000 and 1.000), valid
 # only for the kernel source they were taken with (sha256 of idm_kernels.hip
 # followed by idm_device.h).
-TRAFFIC_BWD_BYTES = 1.2269e9
-TRAFFIC_KERNEL_SHA256 = "56d81a9a6dea48ea0d3a8c0fd9dc47ec25621b0049ce455f8776ef9038c50c4e"
+TRAFFIC_BWD_BYTES = 1.1980e9
+TRAFFIC_KERNEL_SHA256 = "84a2538cd00164a67d01da53eb7f24783c61a761c4537d3e4a91c3a5cb035854"
 
 
 # Warm-start network training: Adam over 1M pairs, batch 4096, learning rate
