@@ -49,7 +49,7 @@ TRAFFIC_KERNEL_SHA256 = "84a2538cd00164a67d01da53eb7f24783c61a761c4537d3e4a91c3a
 
 # Warm-start network training: Adam over 1M pairs, batch 4096, learning rate
 # on a cosine from MLP_LR to MLP_LR_FINAL over MLP_EPOCHS epochs.
-MLP_EPOCHS = 30
+MLP_EPOCHS = 60
 MLP_LR = 2e-3
 MLP_LR_FINAL = 1e-5
 

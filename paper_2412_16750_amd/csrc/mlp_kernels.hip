@@ -122,14 +122,22 @@ __global__ __launch_bounds__(256) void k_sum_slabs(const float *part, int slabs,
     }
 }
 
-// Column sums of a BF16 [rows x cols] matrix (bias gradients), fixed order.
+// Column sums of a BF16 [rows x cols] matrix (bias gradients) in a fixed
+// order: each slab of `slab` rows in row order (one thread per column and
+// slab, rows read coalesced across the columns), then the slabs in order
+// (k_sum_slabs).
+constexpr int COLSUM_ROWS = 64;      // rows per slab, at least
+constexpr int COLSUM_SLABS = 32768;  // slabs, at most (grid y)
+
 __global__ __launch_bounds__(256) void k_colsum_bf16(const uint16_t *X, int rows, int cols,
-                                                     int64_t rs, float *out) {
+                                                     int64_t rs, int slab, float *part) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cols) return;
+    const int r0 = blockIdx.y * slab;
+    const int r1 = min(r0 + slab, rows);
     float s = 0.0f;
-    for (int r = 0; r < rows; ++r) s += bf2f(X[(int64_t)r * rs + c]);
-    out[c] = s;
+    for (int r = r0; r < r1; ++r) s += bf2f(X[(int64_t)r * rs + c]);
+    part[(int64_t)blockIdx.y * cols + c] = s;
 }
 
 // dY = 2 (Y - U) / (B * n_out) on the first n_out columns (BF16, padding 0),
@@ -328,6 +336,20 @@ hipError_t weight_grad(const uint16_t *act, int64_t act_rs, int rows, int in, co
     return hipGetLastError();
 }
 
+// out[c] = column sum c of X, through `part` (>= min(ceil(rows / 64), 32768) *
+// cols floats; the weight-gradient slab buffer always holds that).
+hipError_t colsum(const uint16_t *X, int rows, int cols, int64_t rs, float *part, float *dst,
+                  hipStream_t s) {
+    const int slab = std::max(COLSUM_ROWS, (rows + COLSUM_SLABS - 1) / COLSUM_SLABS);
+    const int slabs = (rows + slab - 1) / slab;
+    if (slabs > 0)
+        hipLaunchKernelGGL(k_colsum_bf16, dim3((cols + 255) / 256, slabs), dim3(256), 0, s, X, rows,
+                           cols, rs, slab, part);
+    hipLaunchKernelGGL(k_sum_slabs, dim3(grid_for(cols)), dim3(256), 0, s, part, slabs,
+                       (int64_t)cols, dst);
+    return hipGetLastError();
+}
+
 hipError_t mlp_forward(const idm_mlp_state *st, const uint16_t *X, int64_t B, const MlpWs &w,
                        char *ws, float *Y, hipStream_t s) {
     const float *P = st->params;
@@ -369,7 +391,8 @@ hipError_t mlp_backward(const idm_mlp_state *st, const uint16_t *X, const float 
     // layer 3: dW3 = H2^T dY, db3 = colsum(dY), dH2 = (dY W3^T) * [H2 > 0]
     e = weight_grad(H2, H, B, H, dY, FOUT, FOUT, part, G + OFF_W3, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_colsum_bf16, dim3(1), dim3(256), 0, s, dY, B, FOUT, (int64_t)FOUT, G + OFF_B3);
+    e = colsum(dY, B, FOUT, FOUT, part, G + OFF_B3, s);
+    if (e != hipSuccess) return e;
     Gemm g3 = gemm(dY, FOUT, 1, W16 + H16_W3, 1, FOUT, B, H, FOUT);
     g3.mask = H2; g3.mask_rs = H; g3.C16 = dH2; g3.c16_rs = H;
     e = launch_gemm(g3, 1, s);
@@ -377,7 +400,8 @@ hipError_t mlp_backward(const idm_mlp_state *st, const uint16_t *X, const float 
     // layer 2: dW2 = H1^T dH2, db2, dH1 = (dH2 W2^T) * [H1 > 0]
     e = weight_grad(H1, H, B, H, dH2, H, H, part, G + OFF_W2, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_colsum_bf16, dim3(1), dim3(256), 0, s, dH2, B, H, (int64_t)H, G + OFF_B2);
+    e = colsum(dH2, B, H, H, part, G + OFF_B2, s);
+    if (e != hipSuccess) return e;
     Gemm g2 = gemm(dH2, H, 1, W16 + H16_W2, 1, H, B, H, H);
     g2.mask = H1; g2.mask_rs = H; g2.C16 = dH1; g2.c16_rs = H;
     e = launch_gemm(g2, 1, s);
@@ -385,8 +409,7 @@ hipError_t mlp_backward(const idm_mlp_state *st, const uint16_t *X, const float 
     // layer 1: dW1 = X^T dH1, db1
     e = weight_grad(X, FIN, B, FIN, dH1, H, H, part, G + OFF_W1, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_colsum_bf16, dim3(1), dim3(256), 0, s, dH1, B, H, (int64_t)H, G + OFF_B1);
-    return hipGetLastError();
+    return colsum(dH1, B, H, H, part, G + OFF_B1, s);
 }
 
 idm_status check_state(const idm_mlp_state *st) {
