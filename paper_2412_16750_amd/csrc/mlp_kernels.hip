@@ -48,16 +48,116 @@ struct Gemm {
     int64_t c32_rs;
     uint16_t *C16;           // BF16 output or null
     int64_t c16_rs;
+    int ones_row;            // A's row that reads as all ones (not in memory), or -1
 };
 
 // 256 threads = 4 waves; block tile 64 x 64; each wave 32 x 32 = 2 x 2 MFMA
 // 16x16x16 tiles.  MFMA operand layout (16x16x16 bf16): lane l holds
 // A[l % 16][4 (l / 16) + e] and B[4 (l / 16) + e][l % 16], e = 0..3, and the
 // result D[4 (l / 16) + e][l % 16].
+//
+// K advances in stages of 32: the block stages A (64 x 32) and B (32 x 64)
+// in LDS, both stored k-contiguous (As[m][k], Bs[n][k], row pitch 36 so the
+// 16 rows one operand read touches fall in distinct banks), so each MFMA
+// operand is one 8-byte LDS read.  (Stages of 128 were no faster: these
+// GEMMs are small and latency-bound, and the larger tile halves occupancy.)  Global loads are 16-byte vectors of 8
+// elements along whichever of the operand's dimensions is contiguous in
+// memory (k for activations, m for a transposed activation, n or k for the
+// weights); partial or misaligned vectors fall back to element loads, and
+// elements outside the matrix or the block's k range read as 0.
+constexpr int GK = 32;       // k per stage
+constexpr int GPITCH = 36;   // LDS row pitch (elements): 16 consecutive rows hit distinct banks
+
+typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+
+constexpr uint16_t BF16_ONE = 0x3f80;
+
+// Element (r, c) of a strided matrix, 0 outside [0, R) x [c_lo, c_hi); row
+// `ones` reads as 1 without touching memory.
+__device__ __forceinline__ uint16_t elem(const uint16_t *P, int64_t rs, int64_t cs, int r, int c,
+                                         int R, int c_lo, int c_hi, int ones) {
+    if (r >= R || c < c_lo || c >= c_hi) return 0;
+    return r == ones ? BF16_ONE : P[(int64_t)r * rs + (int64_t)c * cs];
+}
+
+__device__ __forceinline__ void unpack8(const u32x4v &w, uint16_t (&v)[8]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        v[2 * i] = (uint16_t)(w[i] & 0xffffu);
+        v[2 * i + 1] = (uint16_t)(w[i] >> 16);
+    }
+}
+
+// Stage one 64 x GK operand tile into T[row][k] (row = m for A, n for B).
+// s_row / s_k: element strides along the tile's row index and along k.  Each
+// thread moves GK / 4 elements as GK / 32 vectors of 8; all of a thread's
+// global loads are issued before its LDS stores.
+__device__ __forceinline__ void stage_tile(const uint16_t *P, int64_t s_row, int64_t s_k,
+                                           int row0, int rows, int k0, int k_lo, int k_hi,
+                                           int ones, uint16_t (*T)[GPITCH]) {
+    constexpr int NV = GK / 32;
+    const int t = threadIdx.x;
+    uint16_t v[NV][8];
+    if (s_k == 1) {
+        // k contiguous: thread -> (row, NV runs of 8 consecutive k)
+        const int r = t >> 2, gr = row0 + r;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            const int gk = k0 + c * 32 + (t & 3) * 8;
+            const uint16_t *src = P + (int64_t)gr * s_row + gk;
+            if (gr < rows && gr != ones && gk >= k_lo && gk + 8 <= k_hi &&
+                ((uintptr_t)src & 15) == 0) {
+                unpack8(*reinterpret_cast<const u32x4v *>(src), v[c]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    v[c][i] = elem(P, s_row, 1, gr, gk + i, rows, k_lo, k_hi, ones);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NV; ++c)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) T[r][c * 32 + (t & 3) * 8 + i] = v[c][i];
+    } else if (s_row == 1) {
+        // row contiguous: thread -> (NV values of k, 8 consecutive rows)
+        const int rq = (t & 7) * 8, gr = row0 + rq;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            const int gk = k0 + c * 32 + (t >> 3);
+            const uint16_t *src = P + (int64_t)gk * s_k + gr;
+            if (gr + 8 <= rows && (ones < gr || ones >= gr + 8) && gk >= k_lo && gk < k_hi &&
+                ((uintptr_t)src & 15) == 0) {
+                unpack8(*reinterpret_cast<const u32x4v *>(src), v[c]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    v[c][i] = elem(P, 1, s_k, gr + i, gk, rows, k_lo, k_hi, ones);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NV; ++c)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) T[rq + i][c * 32 + (t >> 3)] = v[c][i];
+    } else {
+        // general strides: element loads
+        const int r = t >> 2;
+#pragma unroll
+        for (int c = 0; c < NV; ++c)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int kk = c * 32 + (t & 3) * 8 + i;
+                T[r][kk] = elem(P, s_row, s_k, row0 + r, k0 + kk, rows, k_lo, k_hi, ones);
+            }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_gemm_bf16(Gemm g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[64][GPITCH];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[64][GPITCH];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int bm = blockIdx.y * 64 + (wave >> 1) * 32;
-    const int bn = blockIdx.x * 64 + (wave & 1) * 32;
+    const int tm = blockIdx.y * 64, tn = blockIdx.x * 64;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int bm = tm + wm, bn = tn + wn;
     const int kb = blockIdx.z * g.k_chunk;
     const int ke = min(g.K, kb + g.k_chunk);
     const int li = lane & 15, lq = lane >> 4;
@@ -66,31 +166,27 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(Gemm g) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = kb; k0 < ke; k0 += 16) {
-        bf16x4 a[2], b[2];
+    for (int k0 = kb; k0 < ke; k0 += GK) {
+        __syncthreads();  // the previous stage's reads are done
+        stage_tile(g.A, g.a_rs, g.a_cs, tm, g.M, k0, kb, ke, g.ones_row, As);
+        stage_tile(g.B, g.b_cs, g.b_rs, tn, g.N, k0, kb, ke, -1, Bs);
+        __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int m = bm + i * 16 + li;
+        for (int kk = 0; kk < GK; kk += 16) {
+            if (k0 + kk >= ke) break;  // the rest of the stage is zero fill
+            bf16x4 a[2], b[2];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = k0 + 4 * lq + e;
-                a[i][e] = (m < g.M && k < ke) ? (short)g.A[(int64_t)m * g.a_rs + (int64_t)k * g.a_cs] : (short)0;
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int n = bn + j * 16 + li;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = k0 + 4 * lq + e;
-                b[j][e] = (n < g.N && k < ke) ? (short)g.B[(int64_t)k * g.b_rs + (int64_t)n * g.b_cs] : (short)0;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
+                a[i] = *reinterpret_cast<const bf16x4 *>(&As[wm + i * 16 + li][kk + 4 * lq]);
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                b[j] = *reinterpret_cast<const bf16x4 *>(&Bs[wn + j * 16 + li][kk + 4 * lq]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
     }
     float *C32 = g.C32 ? g.C32 + (int64_t)blockIdx.z * g.M * g.c32_rs : nullptr;
 #pragma unroll
@@ -120,24 +216,6 @@ __global__ __launch_bounds__(256) void k_sum_slabs(const float *part, int slabs,
         for (int z = 0; z < slabs; ++z) s += part[(int64_t)z * n + i];
         out[i] = s;
     }
-}
-
-// Column sums of a BF16 [rows x cols] matrix (bias gradients) in a fixed
-// order: each slab of `slab` rows in row order (one thread per column and
-// slab, rows read coalesced across the columns), then the slabs in order
-// (k_sum_slabs).
-constexpr int COLSUM_ROWS = 64;      // rows per slab, at least
-constexpr int COLSUM_SLABS = 32768;  // slabs, at most (grid y)
-
-__global__ __launch_bounds__(256) void k_colsum_bf16(const uint16_t *X, int rows, int cols,
-                                                     int64_t rs, int slab, float *part) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
-    const int r0 = blockIdx.y * slab;
-    const int r1 = min(r0 + slab, rows);
-    float s = 0.0f;
-    for (int r = r0; r < r1; ++r) s += bf2f(X[(int64_t)r * rs + c]);
-    part[(int64_t)blockIdx.y * cols + c] = s;
 }
 
 // dY = 2 (Y - U) / (B * n_out) on the first n_out columns (BF16, padding 0),
@@ -281,6 +359,9 @@ constexpr int64_t OFF_B2 = OFF_W2 + N_W2, N_B2 = H;
 constexpr int64_t OFF_W3 = OFF_B2 + N_B2, N_W3 = (int64_t)H * FOUT;
 constexpr int64_t OFF_B3 = OFF_W3 + N_W3, N_B3 = FOUT;
 constexpr int64_t N_PARAMS = OFF_B3 + N_B3;
+// weight_grad writes a layer's weight and bias gradients as one block
+static_assert(OFF_B1 == OFF_W1 + N_W1 && OFF_B2 == OFF_W2 + N_W2 && OFF_B3 == OFF_W3 + N_W3,
+              "each bias follows its weights");
 // BF16 copies: W1, W2, W3 back to back
 constexpr int64_t H16_W1 = 0, H16_W2 = N_W1, H16_W3 = N_W1 + N_W2, N_W16 = N_W1 + N_W2 + N_W3;
 
@@ -304,7 +385,7 @@ MlpWs mlp_ws(int64_t B) {
     w.dh1 = o; o += al(2 * B * H);
     w.grad = o; o += al(4 * N_PARAMS);
     const int64_t slabs = (B + SPLIT_ROWS - 1) / SPLIT_ROWS;
-    w.part = o; o += al(4 * slabs * (int64_t)H * H);
+    w.part = o; o += al(4 * slabs * (int64_t)(std::max(H, FIN) + 1) * H);
     w.lpart = o; o += al(8 * 8192);
     w.total = o;
     return w;
@@ -318,35 +399,27 @@ Gemm gemm(const uint16_t *A, int64_t a_rs, int64_t a_cs, const uint16_t *B, int6
     g.B = B; g.b_rs = b_rs; g.b_cs = b_cs;
     g.M = M; g.N = N; g.K = K;
     g.k_chunk = ((K + 15) / 16) * 16;
+    g.ones_row = -1;
     return g;
 }
 
 // Weight gradient dW = Act^T dZ over the batch: split-K slabs + fixed-order sum.
+// Weight and bias gradients of one layer into dst = [in + 1][out] (the
+// weights, then the bias, as the parameters are laid out): [act^T; 1] dz, the
+// all-ones row giving the bias gradient (column sums of dz), split-K over
+// 512-row slabs summed in slab order.
 hipError_t weight_grad(const uint16_t *act, int64_t act_rs, int rows, int in, const uint16_t *dz,
                        int64_t dz_rs, int out, float *part, float *dst, hipStream_t s) {
-    Gemm g = gemm(act, 1, act_rs, dz, dz_rs, 1, in, out, rows);
+    Gemm g = gemm(act, 1, act_rs, dz, dz_rs, 1, in + 1, out, rows);
+    g.ones_row = in;
     g.k_chunk = SPLIT_ROWS;
     const int slabs = (rows + SPLIT_ROWS - 1) / SPLIT_ROWS;
     g.C32 = part;
     g.c32_rs = out;
     hipError_t e = launch_gemm(g, slabs, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_slabs, dim3(grid_for((int64_t)in * out)), dim3(256), 0, s, part, slabs,
-                       (int64_t)in * out, dst);
-    return hipGetLastError();
-}
-
-// out[c] = column sum c of X, through `part` (>= min(ceil(rows / 64), 32768) *
-// cols floats; the weight-gradient slab buffer always holds that).
-hipError_t colsum(const uint16_t *X, int rows, int cols, int64_t rs, float *part, float *dst,
-                  hipStream_t s) {
-    const int slab = std::max(COLSUM_ROWS, (rows + COLSUM_SLABS - 1) / COLSUM_SLABS);
-    const int slabs = (rows + slab - 1) / slab;
-    if (slabs > 0)
-        hipLaunchKernelGGL(k_colsum_bf16, dim3((cols + 255) / 256, slabs), dim3(256), 0, s, X, rows,
-                           cols, rs, slab, part);
-    hipLaunchKernelGGL(k_sum_slabs, dim3(grid_for(cols)), dim3(256), 0, s, part, slabs,
-                       (int64_t)cols, dst);
+    const int64_t n = (int64_t)(in + 1) * out;
+    hipLaunchKernelGGL(k_sum_slabs, dim3(grid_for(n)), dim3(256), 0, s, part, slabs, n, dst);
     return hipGetLastError();
 }
 
@@ -388,28 +461,22 @@ hipError_t mlp_backward(const idm_mlp_state *st, const uint16_t *X, const float 
         hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(64), 0, s, lpart, lgrid,
                            1.0 / ((double)B * IDM_MLP_OUT), loss_out);
     const uint16_t *W16 = st->weights_bf16;
-    // layer 3: dW3 = H2^T dY, db3 = colsum(dY), dH2 = (dY W3^T) * [H2 > 0]
-    e = weight_grad(H2, H, B, H, dY, FOUT, FOUT, part, G + OFF_W3, s);
-    if (e != hipSuccess) return e;
-    e = colsum(dY, B, FOUT, FOUT, part, G + OFF_B3, s);
+    // layer 3: [dW3; db3] = [H2^T; 1] dY, dH2 = (dY W3^T) * [H2 > 0]
+    e = weight_grad(H2, H, B, H, dY, FOUT, FOUT, part, G + OFF_W3, s);  // and db3
     if (e != hipSuccess) return e;
     Gemm g3 = gemm(dY, FOUT, 1, W16 + H16_W3, 1, FOUT, B, H, FOUT);
     g3.mask = H2; g3.mask_rs = H; g3.C16 = dH2; g3.c16_rs = H;
     e = launch_gemm(g3, 1, s);
     if (e != hipSuccess) return e;
-    // layer 2: dW2 = H1^T dH2, db2, dH1 = (dH2 W2^T) * [H1 > 0]
-    e = weight_grad(H1, H, B, H, dH2, H, H, part, G + OFF_W2, s);
-    if (e != hipSuccess) return e;
-    e = colsum(dH2, B, H, H, part, G + OFF_B2, s);
+    // layer 2: [dW2; db2] = [H1^T; 1] dH2, dH1 = (dH2 W2^T) * [H1 > 0]
+    e = weight_grad(H1, H, B, H, dH2, H, H, part, G + OFF_W2, s);  // and db2
     if (e != hipSuccess) return e;
     Gemm g2 = gemm(dH2, H, 1, W16 + H16_W2, 1, H, B, H, H);
     g2.mask = H1; g2.mask_rs = H; g2.C16 = dH1; g2.c16_rs = H;
     e = launch_gemm(g2, 1, s);
     if (e != hipSuccess) return e;
-    // layer 1: dW1 = X^T dH1, db1
-    e = weight_grad(X, FIN, B, FIN, dH1, H, H, part, G + OFF_W1, s);
-    if (e != hipSuccess) return e;
-    return colsum(dH1, B, H, H, part, G + OFF_B1, s);
+    // layer 1: [dW1; db1] = [X^T; 1] dH1
+    return weight_grad(X, FIN, B, FIN, dH1, H, H, part, G + OFF_W1, s);  // and db1
 }
 
 idm_status check_state(const idm_mlp_state *st) {
