@@ -45,7 +45,7 @@ extern "C" {
 typedef enum {
     IDM_OK = 0,
     IDM_ERR_INVALID_ARG = -1, /* null pointer, non-positive size, NaN, ... */
-    IDM_ERR_LAYOUT = -2,      /* lane offsets not monotone / not covering N, lane too long */
+    IDM_ERR_LAYOUT = -2,      /* lane offsets not monotone / not covering N, layout too large */
     IDM_ERR_UNSUPPORTED = -3, /* a value the kernels do not implement (e.g. delta != 4) */
     IDM_ERR_WORKSPACE = -4,   /* workspace missing or too small */
     IDM_ERR_HIP = -5          /* a HIP runtime call failed; message has the HIP error */
@@ -175,12 +175,14 @@ idm_status idm_problem_bundles(const idm_problem *problem, const idm_tuning *tun
                                int64_t capacity);
 
 /* Forward simulation (Eqs. 1-3 with the chosen bound, Sec. III-B update
- * order), all n_steps in one launch.
+ * order), all n_steps in one launch per launch level (one level unless lanes
+ * are longer than a bundle).
  *   p0      [N] FP64 initial positions;  v_init [N] FP32 initial speeds.
  *   traj_d  [(S+1)*N] FP32 displacement p_k - p0 (nullable: not written).
  *   traj_v  [(S+1)*N] FP32 speeds (nullable).
  *   workspace: receives the checkpoints the backward pass needs (may be NULL
- *   when no backward will follow). */
+ *   when no backward will follow and no lane is cut into pieces; with pieces
+ *   a NULL workspace is IDM_ERR_WORKSPACE). */
 idm_status idm_sim_forward(idm_plan *plan, const idm_params *prm, const double *p0,
                            const float *v_init, float *traj_d, float *traj_v, void *workspace,
                            void *stream);
