@@ -224,8 +224,21 @@ __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf
         }
         lds_barrier();
         int to_ckpt = A.K;  // steps until the next checkpoint
-        for (int k = 0; k < S; ++k) {
-            float2 L = sbuf[k & 1][tl];
+        // trajectory rows through raw buffer resources: the row address is
+        // advanced by scalar adds, each lane stores at its loop-invariant byte
+        // offset, and a padding slot's out-of-range offset drops its store
+        const uint32_t NB = (uint32_t)(N * 4);
+        int32_t voff[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) voff[r] = q[r].g >= 0 ? q[r].g * 4 : 0x7ffffff0;
+        const char *trow_d = reinterpret_cast<const char *>(A.traj_d);
+        const char *trow_v = reinterpret_cast<const char *>(A.traj_v);
+        // one step; P = k & 1 is a compile-time parity (the loop below runs
+        // two steps per iteration: a barrier in the loop keeps the compiler
+        // from unrolling it, and a run-time parity costs two address ops)
+        auto fstep = [&](const int k, auto parity) {
+            constexpr int P = decltype(parity)::value;
+            float2 L = sbuf[P][tl];
             if constexpr (CH) {
                 if (x.lead) {
                     const float2 X = lead_buf[(k >> 6) & 1][k & 63];
@@ -249,27 +262,46 @@ __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) euler<MODE>(d[r], v[r], acc[r], A.dt);
-            sbuf[(k + 1) & 1][t] = make_float2(d[R - 1], v[R - 1]);
+            sbuf[P ^ 1][t] = make_float2(d[R - 1], v[R - 1]);
             if constexpr (CH)
                 if (x.tail && t == NT - 1) x.tail[k + 1] = make_float2(d[R - 1], v[R - 1]);
-            const int64_t row = (int64_t)(k + 1) * N;
             const bool ck = A.ckpt && (--to_ckpt == 0) && (k + 1 < S);
             if (to_ckpt == 0) to_ckpt = A.K;
             const int64_t crow = (int64_t)((k + 1) / A.K) * 2 * N;
+            if (A.traj_d) {
+                trow_d += NB;
+                const __amdgpu_buffer_rsrc_t rs =
+                    __builtin_amdgcn_make_buffer_rsrc((void *)trow_d, (short)0, (int)NB, 0x00020000);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                int32_t g = q[r].g;
-                if (g >= 0) {
-                    if (A.traj_d) A.traj_d[row + g] = d[r];
-                    if (A.traj_v) A.traj_v[row + g] = v[r];
-                    if (ck) {
+                for (int r = 0; r < R; ++r)
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(d[r]), rs, voff[r], 0, 0);
+            }
+            if (A.traj_v) {
+                trow_v += NB;
+                const __amdgpu_buffer_rsrc_t rs =
+                    __builtin_amdgcn_make_buffer_rsrc((void *)trow_v, (short)0, (int)NB, 0x00020000);
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[r]), rs, voff[r], 0, 0);
+            }
+            if (ck) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int32_t g = q[r].g;
+                    if (g >= 0) {
                         A.ckpt[crow + g] = d[r];
                         A.ckpt[crow + N + g] = v[r];
                     }
                 }
             }
             lds_barrier();
+        };
+        int k = 0;
+        for (; k + 1 < S; k += 2) {
+            fstep(k, std::integral_constant<int, 0>{});
+            fstep(k + 1, std::integral_constant<int, 1>{});
         }
+        if (k < S) fstep(k, std::integral_constant<int, 0>{});
     }
 }
 
