@@ -44,7 +44,7 @@ PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
 # only for the kernel source they were taken with (sha256 of idm_kernels.hip
 # followed by idm_device.h).
 TRAFFIC_BWD_BYTES = 1.1980e9
-TRAFFIC_KERNEL_SHA256 = "84a2538cd00164a67d01da53eb7f24783c61a761c4537d3e4a91c3a5cb035854"
+TRAFFIC_KERNEL_SHA256 = "236b5e57ede1d6b8129cd1b0da955e73722de7d3768d2e8d3e27c2d7eadf37c4"
 
 
 # Warm-start network training: Adam over 1M pairs, batch 4096, learning rate
