@@ -59,12 +59,14 @@ enum {
 
 /* Largest N: per-step rows of N floats are addressed with 32-bit byte offsets. */
 #define IDM_MAX_VEHICLES (1 << 29)
+/* Largest S: per-boundary rows of S + 1 steps are addressed with 32-bit byte offsets. */
+#define IDM_MAX_STEPS (1 << 27)
 
 /* The simulation problem (Sec. III-A): lanes, step count and constants. */
 typedef struct {
     int32_t n_vehicles;               /* 1 <= N <= IDM_MAX_VEHICLES */
     int32_t n_lanes;                  /* L >= 1 */
-    int32_t n_steps;                  /* S >= 0 Euler steps of length dt */
+    int32_t n_steps;                  /* 0 <= S <= IDM_MAX_STEPS Euler steps of length dt */
     int32_t ckpt_every;               /* K: checkpoint interval of the forward; the backward
                                          sweeps each K-step block from its last register
                                          sub-block (see idm_tuning.block) to its first;

@@ -701,9 +701,9 @@ idm_status capture(hipStream_t s, hipGraphExec_t *out, F fn) {
 // Validation of the problem and choice of the launch shape (host only).
 idm_status host_plan(const idm_problem *pb, const idm_tuning *tu, idm_plan *p, Shape &sh) {
     if (!pb) return fail(IDM_ERR_INVALID_ARG, "null argument");
-    if (pb->n_vehicles < 1 || pb->n_lanes < 1 || pb->n_steps < 0)
-        return fail(IDM_ERR_INVALID_ARG, "sizes: N=%d L=%d S=%d", pb->n_vehicles, pb->n_lanes,
-                    pb->n_steps);
+    if (pb->n_vehicles < 1 || pb->n_lanes < 1 || pb->n_steps < 0 || pb->n_steps > IDM_MAX_STEPS)
+        return fail(IDM_ERR_INVALID_ARG, "sizes: N=%d L=%d S=%d (S <= %d)", pb->n_vehicles,
+                    pb->n_lanes, pb->n_steps, IDM_MAX_STEPS);
     // a per-step row of N floats is addressed with 32-bit buffer offsets
     if (pb->n_vehicles > IDM_MAX_VEHICLES)
         return fail(IDM_ERR_INVALID_ARG, "N=%d exceeds %d vehicles", pb->n_vehicles,

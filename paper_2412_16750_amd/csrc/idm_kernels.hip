@@ -163,7 +163,8 @@ __device__ __forceinline__ ExtRs ext_rsrc(const Ext &x, int S) {
     return r;
 }
 
-// Row entry k (k < 0 reads as 0).
+// Row entry k (k < 0 reads as 0; rows hold at most (2^27 + 1) entries of 8 B,
+// so the offset 0x7ffffff0 is always outside them).
 __device__ __forceinline__ float2 row_load(__amdgpu_buffer_rsrc_t rs, int k) {
     const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, k >= 0 ? k * 8 : 0x7ffffff0, 0, 0);
     return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
@@ -230,7 +231,8 @@ __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf
         const uint32_t NB = (uint32_t)(N * 4);
         int32_t voff[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) voff[r] = q[r].g >= 0 ? q[r].g * 4 : 0x7ffffff0;
+        for (int r = 0; r < R; ++r)  // a padding slot's offset is the row size: always outside
+            voff[r] = (int32_t)(q[r].g >= 0 ? (uint32_t)q[r].g * 4u : NB);
         const char *trow_d = reinterpret_cast<const char *>(A.traj_d);
         const char *trow_v = reinterpret_cast<const char *>(A.traj_v);
         // one step; P = k & 1 is a compile-time parity (the loop below runs

@@ -78,6 +78,7 @@ def test_valid_problem_shape_and_workspace(L):
     (dict(offsets=[0, 10], K=-3), -1),
     (dict(offsets=[0, 10], K=6), -3),             # no backward block divides K
     (dict(offsets=[0, (1 << 29) + 1]), -1),       # N above IDM_MAX_VEHICLES
+    (dict(offsets=[0, 10], S=(1 << 27) + 1), -1),  # S above IDM_MAX_STEPS
 ])
 def test_invalid_problems_are_rejected(L, case, status):
     st, _, _ = _check(L, **case)
