@@ -265,3 +265,56 @@ def test_level_rounds_on_the_uneven_workload(L):
     assert info.n_levels == 4 and len(counts) == 4
     assert np.sum(counts % 512 != 0) <= 1
     assert int(np.sum(-(-counts // 512))) == -(-info.n_bundles // 512)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_layouts_keep_every_invariant(L, seed):
+    """Random lane-size mixes (empty lanes, singletons, exact multiples of the
+    bundle, long lanes) and random one-vehicle-per-thread shapes: every
+    vehicle in exactly one slot, lanes contiguous head -> tail across their
+    pieces, each boundary joining a full bundle's last slot to the next
+    piece's first slot one level up, and levels ascending."""
+    rng = np.random.default_rng(seed)
+    threads = int(rng.choice([64, 128, 256, 512, 1024]))
+    cap = threads
+    n_lanes = int(rng.integers(1, 120))
+    kind = rng.integers(0, 4, n_lanes)
+    sizes = np.where(kind == 0, rng.integers(0, 3, n_lanes),                 # empty / tiny
+             np.where(kind == 1, rng.integers(1, cap + 1, n_lanes),          # fits
+             np.where(kind == 2, cap * rng.integers(1, 4, n_lanes),          # exact multiples
+                      rng.integers(cap + 1, 5 * cap, n_lanes)))).astype(np.int64)
+    if sizes.sum() == 0:
+        sizes[0] = 1
+    off = scenarios_offsets(sizes)
+    tuning = (threads, 1, 8, 0, 0)
+    info, gidx, flags = _layout(L, off, tuning)
+    info, ws, bin_, bout, lvl = _bundles(L, off, tuning)
+    N = int(off[-1])
+    valid = gidx >= 0
+    assert np.array_equal(np.sort(gidx[valid]), np.arange(N))
+    g = gidx.reshape(-1, cap)
+    assert np.all(np.diff(lvl) >= 0)
+    pieces = np.where(sizes > cap, -(-sizes // cap), 1)
+    assert info.n_levels == max(1, int(pieces[sizes > 0].max()))
+    assert info.n_boundaries == int(np.sum(pieces[sizes > 0] - 1))
+    # within a bundle, occupied slots come first; consecutive slots of one
+    # lane hold consecutive vehicles
+    lane_of = np.repeat(np.arange(len(sizes)), sizes)
+    for b in range(info.n_bundles):
+        row = g[b]
+        k = int(np.sum(row >= 0))
+        assert np.all(row[k:] == -1)
+        seg = row[:k]
+        same = lane_of[seg[1:]] == lane_of[seg[:-1]]
+        assert np.all(seg[1:][same] == seg[:-1][same] + 1)
+        if bin_[b] >= 0:
+            a = int(np.flatnonzero(bout == bin_[b])[0])
+            assert np.all(g[a] >= 0) and g[a, -1] + 1 == g[b, 0] and lvl[b] == lvl[a] + 1
+        elif k:
+            # a bundle without an incoming boundary starts with a lane head
+            assert seg[0] == off[lane_of[seg[0]]]
+
+
+def scenarios_offsets(sizes):
+    import scenarios
+    return scenarios.offsets_from_sizes(np.asarray(sizes, dtype=np.int64))
