@@ -215,3 +215,27 @@ def test_autotuner_with_pieces():
     torch.cuda.synchronize()
     for a, e in zip((b.traj_d, b.grad_params, b.grad_p0, b.grad_v0), before):
         assert torch.equal(a, e)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_cuts_bitwise(seed):
+    """Random lane mixes, bundle sizes, step counts, checkpoint intervals and
+    bound modes: lanes cut into pieces give the trajectories and gradients of
+    the same lanes held whole by 1024-slot bundles, bit for bit."""
+    rng = np.random.default_rng(100 + seed)
+    cap = int(rng.choice([64, 128, 256]))
+    n = int(rng.integers(5, 40))
+    sizes = rng.integers(1, 3 * cap + 1, n)
+    sizes[rng.integers(0, n)] = 3 * cap            # at least three pieces somewhere
+    S = int(rng.integers(1, 41))
+    K = int(rng.choice([8, 16]))
+    mode = int(rng.integers(0, 2))
+    sc = ragged_scenario(sizes, S, mode=mode, seed_c=60 + seed, ckpt_every=K)
+    steps = np.arange(1, S + 1)
+    tgt = oracle_targets(sc, steps, c=60 + seed)
+    whole = gpu_run(sc, steps, tgt, threads=1024, per_thread=1, block=8)
+    cut = gpu_run(sc, steps, tgt, threads=cap, per_thread=1, block=8)
+    log("random cut seed %d: cap %d, S %d, K %d, mode %d, levels %d" %
+        (seed, cap, S, K, mode, cut["info"]["n_levels"]))
+    assert cut["info"]["n_levels"] >= 3
+    _same(cut, whole, "seed %d" % seed)
