@@ -138,6 +138,50 @@ def cpu_baseline(sc, lanes: int) -> dict:
             "single_core": single, "cpu_model": cpu_model(), "host_cpus": ncpu}
 
 
+# MLP matrix-product flops per sample (150 -> 256 -> 256 -> 5): the forward's
+# three products; a training step adds the three weight gradients and the
+# input gradients of layers 3 and 2 (layer 1 needs none).
+MLP_FWD_FLOP = 2 * (150 * 256 + 256 * 256 + 256 * 5)
+MLP_TRAIN_FLOP = 2 * MLP_FWD_FLOP + 2 * (5 * 256 + 256 * 256)
+BF16_DENSE_PEAK_TFLOPS = 2500.0
+
+
+def mlp_rates(ws, data, batch: int = 4096, steps: int = 100, reps: int = 5) -> dict:
+    """Training-step and inference times of the warm-start network with the
+    matrix-product rate they reach (HIP events on the library's stream).  The
+    training steps run on a fresh network so the trained one is untouched."""
+    import torch
+    import scenarios
+    net = ws.MLP(scenarios.mlp_init_params(6), lr=MLP_LR)
+    X, U = data.X[:batch].contiguous(), data.U[:batch].contiguous()
+    for _ in range(5):
+        net.train_step(X, U)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        net.train_step(X, U)
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1) / steps
+    n = int(data.X.shape[0])
+    Y = net.forward(data.X)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        net.forward(data.X, Y)
+    e1.record()
+    torch.cuda.synchronize()
+    infer_ms = e0.elapsed_time(e1) / reps
+    tr = MLP_TRAIN_FLOP * batch / (train_ms * 1e-3) / 1e12
+    inf = MLP_FWD_FLOP * n / (infer_ms * 1e-3) / 1e12
+    return {"train_step_ms": round(train_ms, 4), "train_tflops": round(tr, 2),
+            "infer_rows": n, "infer_ms": round(infer_ms, 3), "infer_tflops": round(inf, 2),
+            "mfma_frac_train": round(tr / BF16_DENSE_PEAK_TFLOPS, 4),
+            "mfma_frac_infer": round(inf / BF16_DENSE_PEAK_TFLOPS, 4),
+            "flop_per_sample": {"forward": MLP_FWD_FLOP, "train": MLP_TRAIN_FLOP}}
+
+
 def fit_report(dev, log_fn, cap: int = 2000) -> dict:
     """Trajectory fitting workload (100 lanes x 1000 vehicles, 500 steps,
     observed every 10th step with N(0, 0.5 m) noise) and the learned warm start:
@@ -158,6 +202,7 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
     net = ws.MLP(scenarios.mlp_init_params(5), lr=MLP_LR)
     rep = ws.train(net, data, batch=4096, epochs=MLP_EPOCHS, log=log_fn, lr_final=MLP_LR_FINAL)
     n_pairs = int(data.X.shape[0])
+    rates = mlp_rates(ws, data)
     del data
     # the fitting problem, hidden parameters = the scenario's draw
     sc = scenarios.fit()
@@ -180,7 +225,8 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
            "mlp": {"pairs": n_pairs, "batch": 4096, "epochs": MLP_EPOCHS,
                    "lr": "cosine %.0e -> %.0e" % (MLP_LR, MLP_LR_FINAL), "steps": rep["steps"],
                    "data_seconds": round(gen_s, 3), "train_seconds": round(rep["seconds"], 3),
-                   "train_mse": rep["history"][-1]["train_mse"], "heldout_mse": heldout_mse}}
+                   "train_mse": rep["history"][-1]["train_mse"], "heldout_mse": heldout_mse,
+                   **rates}}
     # cold start, 200 iterations: per-iteration time, RMSE, parameter errors
     f = Fitter(plan, length, p0, v, obs, lr0=1e-2)
     f.init(cold)
