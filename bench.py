@@ -182,6 +182,25 @@ def mlp_rates(ws, data, batch: int = 4096, steps: int = 100, reps: int = 5) -> d
             "flop_per_sample": {"forward": MLP_FWD_FLOP, "train": MLP_TRAIN_FLOP}}
 
 
+def copy_ms(dev, nbytes: int, reps: int) -> float:
+    """Mean time of the library's streaming copy kernel over `nbytes` bytes."""
+    import torch
+    from paper_2412_16750_amd import sim
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(3):
+        sim.idm_copy_bytes(b, a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        sim.idm_copy_bytes(b, a)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def fit_report(dev, log_fn, cap: int = 2000) -> dict:
     """Trajectory fitting workload (100 lanes x 1000 vehicles, 500 steps,
     observed every 10th step with N(0, 0.5 m) noise) and the learned warm start:
@@ -493,6 +512,9 @@ def main():
     ap.add_argument("--cpu-lanes", type=int, default=400,
                     help="lanes of the workload the single-core CPU oracle baseline times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mlp-only", action="store_true",
+                    help="only time the warm-start network's training step and inference on "
+                         "the 1M simulated pairs (no training run)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the streaming copy kernel (byte-counter calibration)")
     ap.add_argument("--threads", type=int, default=0)
@@ -520,7 +542,7 @@ def main():
     import scenarios
 
     cpu = None
-    if not args.copy_only and not args.no_cpu_baseline:
+    if not args.copy_only and not args.mlp_only and not args.no_cpu_baseline:
         # before anything loads the HIP runtime: the baseline forks workers
         log("bench: CPU oracle baseline")
         cpu = cpu_baseline(scenarios.scale(ckpt_every=args.ckpt), args.cpu_lanes)
@@ -534,22 +556,15 @@ def main():
     dev = "cuda"
     torch.cuda.init()
 
+    if args.mlp_only:
+        from paper_2412_16750_amd import warmstart as ws
+        data = ws.make_pairs(scenarios.warm_training())
+        print(json.dumps({"pairs": int(data.X.shape[0]), **mlp_rates(ws, data)}))
+        return
+
     if args.copy_only:
         nbytes = 1 << 30
-        a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        a.fill_(1)
-        for _ in range(3):
-            sim.idm_copy_bytes(b, a)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 20
-        e0.record()
-        for _ in range(reps):
-            sim.idm_copy_bytes(b, a)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        ms = copy_ms(dev, nbytes, 20)
         print(json.dumps({"copy_bytes": nbytes, "copy_ms": ms,
                           "copy_GBps_read_plus_write": 2 * nbytes / ms / 1e6}))
         return
@@ -617,17 +632,25 @@ def main():
     same_kernel = h.hexdigest() == TRAFFIC_KERNEL_SHA256
     traffic = TRAFFIC_BWD_BYTES if (same_kernel and info["ckpt_every"] == 32 and info["block"] == 16
                                     and info["threads"] == 1024 and info["per_thread"] == 1) else None
+    # measured HBM ceiling: read + write rate of a 1 GiB streaming copy
+    copy_gbps = 2 * (1 << 30) / (copy_ms(dev, 1 << 30, 10) / 1e3) / 1e9
+    bwd_gbps = bwd_bytes / (bwd_ms / 1e3) / 1e9
+    fwd_gbps = fwd_bytes / (fwd_ms / 1e3) / 1e9
     roofline = {
         "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
         "kernel": "k_backward<softplus,R=%d,threads=%d,KB=%d> (K=%d)"
                   % (info["per_thread"], info["threads"], info["block"], info["ckpt_every"]),
         "kernel_ms": round(bwd_ms, 4), "flop_per_vehicle_step": FLOP_BWD,
-        "hbm_algorithmic_GBps": round(bwd_bytes / (bwd_ms / 1e3) / 1e9, 1),
-        "hbm_frac": round(bwd_bytes / (bwd_ms / 1e3) / 1e9 / PEAK_HBM_GBPS, 4),
+        "hbm_algorithmic_GBps": round(bwd_gbps, 1),
+        "hbm_frac": round(bwd_gbps / PEAK_HBM_GBPS, 4),
+        "copy_ceiling_GBps": round(copy_gbps, 1),
+        "hbm_frac_of_copy": round(bwd_gbps / copy_gbps, 4),
         "forward": {"kernel_ms": round(fwd_ms, 4),
                     "achieved_TFLOPs": round(FLOP_FWD * vsteps / (fwd_ms / 1e3) / 1e12, 3),
-                    "hbm_algorithmic_GBps": round(fwd_bytes / (fwd_ms / 1e3) / 1e9, 1),
+                    "hbm_algorithmic_GBps": round(fwd_gbps, 1),
+                    "hbm_frac": round(fwd_gbps / PEAK_HBM_GBPS, 4),
+                    "hbm_frac_of_copy": round(fwd_gbps / copy_gbps, 4),
                     "vehicle_steps_per_s": vsteps / (fwd_ms / 1e3)},
     }
     out = {

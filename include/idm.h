@@ -317,10 +317,12 @@ idm_status idm_copy_bytes(void *dst, const void *src, size_t bytes, void *stream
  * FP32 parameter buffer (idm_mlp_param_count() floats), row-major blocks:
  *   W1 [IN_PAD x HIDDEN], b1 [HIDDEN], W2 [HIDDEN x HIDDEN], b2 [HIDDEN],
  *   W3 [HIDDEN x OUT_PAD], b3 [OUT_PAD]
- * BF16 weight copies (idm_mlp_weight_bf16_count() values): W1, W2, W3 in the
- * same layouts, back to back.  idm_mlp_sync refreshes them from the FP32
- * weights (and zeroes the Adam moments); idm_mlp_train_step keeps them in
- * sync after every update.
+ * BF16 weight copies (idm_mlp_weight_bf16_count() values, 16-byte aligned
+ * buffer): W1, W2, W3 in the same layouts, back to back, then their
+ * transposes W1^T [HIDDEN x IN_PAD], W2^T [HIDDEN x HIDDEN], W3^T
+ * [OUT_PAD x HIDDEN] (the forward's operands).  idm_mlp_sync refreshes all of
+ * them from the FP32 weights (and zeroes the Adam moments);
+ * idm_mlp_train_step keeps them in sync after every update.
  * ------------------------------------------------------------------------- */
 #define IDM_MLP_IN 150
 #define IDM_MLP_IN_PAD 160
@@ -330,14 +332,15 @@ idm_status idm_copy_bytes(void *dst, const void *src, size_t bytes, void *stream
 
 typedef struct {
     float *params;          /* FP32 master parameters (layout above), device */
-    uint16_t *weights_bf16; /* BF16 copies of W1, W2, W3, device */
+    uint16_t *weights_bf16; /* BF16 copies of W1, W2, W3 and their transposes, device,
+                               16-byte aligned (else IDM_ERR_INVALID_ARG) */
     float *adam_m, *adam_v; /* Adam moments [param_count], device (nullable for inference) */
     float lr, beta1, beta2, eps;
 } idm_mlp_state;
 
 int64_t idm_mlp_param_count(void);
 int64_t idm_mlp_weight_bf16_count(void);
-/* Device workspace for forward / gradients / train step on a batch of B rows. */
+/* Device workspace (16-byte aligned) for gradients / train step on a batch of B rows. */
 size_t idm_mlp_workspace_bytes(int64_t batch);
 /* FP32 -> BF16 weight copies; zero the Adam moments if present. */
 idm_status idm_mlp_sync(const idm_mlp_state *st, void *stream);
@@ -350,7 +353,9 @@ idm_status idm_mlp_sync(const idm_mlp_state *st, void *stream);
 idm_status idm_mlp_features(idm_plan *plan, const float *target, int32_t n_obs, int32_t obs_first,
                             int32_t obs_stride, const double *p0, const float *length,
                             uint16_t *X, void *stream);
-/* Y [batch x OUT_PAD] FP32 = MLP(X). */
+/* Y [batch x OUT_PAD] FP32 = MLP(X), one fused launch (64 rows per
+ * work-group, hidden activations kept in LDS).  X may have any alignment;
+ * `workspace` is not used by the forward and may be null. */
 idm_status idm_mlp_forward(const idm_mlp_state *st, const uint16_t *X, int64_t batch, float *Y,
                            void *workspace, void *stream);
 /* Gradients of L = mean over batch and the 5 outputs of (Y - U)^2 (U [batch x 5]

@@ -1,9 +1,10 @@
 // Learned warm start for the trajectory fit: a 150 -> 256 -> 256 -> 5 ReLU MLP
 // that maps an observed trajectory window to normalised IDM parameters.
-// Hand-written BF16 MFMA GEMMs (v_mfma_f32_16x16x16_bf16, FP32 accumulate)
-// for training and inference on gfx950, fused bias / ReLU / ReLU-mask
-// epilogues, deterministic split-K for the weight gradients, Adam on FP32
-// master weights with BF16 copies, and the window-feature kernel.
+// Hand-written BF16 MFMA kernels for gfx950 (FP32 accumulate): the whole
+// forward fused into one launch (v_mfma_f32_16x16x32_bf16), backward GEMMs
+// (v_mfma_f32_16x16x16_bf16) with a ReLU-mask epilogue, deterministic
+// split-K for the weight gradients, Adam on FP32 master weights with BF16
+// copies, and the window-feature kernel.
 //
 // BF16 rounding points (mirrored by the CPU reference): the features X, the
 // weight copies W1..W3, the hidden activations H1, H2 and the back-propagated
@@ -40,10 +41,8 @@ struct Gemm {
     int64_t b_rs, b_cs;
     int M, N, K;
     int k_chunk;             // split-K: block z handles k in [z*k_chunk, (z+1)*k_chunk)
-    const float *bias;       // [N] or null
     const uint16_t *mask;    // ReLU mask source (value > 0 keeps) or null
     int64_t mask_rs;
-    int relu;
     float *C32;              // FP32 output (split-K: partial slab z at C32 + z*M*c32_rs)
     int64_t c32_rs;
     uint16_t *C16;           // BF16 output or null
@@ -199,12 +198,166 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(Gemm g) {
                 const int n = bn + j * 16 + li;
                 if (m >= g.M || n >= g.N) continue;
                 float v = acc[i][j][e];
-                if (g.bias) v += g.bias[n];
                 if (g.mask && !(bf2f(g.mask[(int64_t)m * g.mask_rs + n]) > 0.0f)) v = 0.0f;
-                if (g.relu) v = fmaxf(v, 0.0f);
                 if (C32) C32[(int64_t)m * g.c32_rs + n] = v;
                 if (g.C16) g.C16[(int64_t)m * g.c16_rs + n] = f2bf(v);
             }
+}
+
+// ---------------------------------------------------------------- fused forward
+// Y = MLP(X) for 64 rows per work-group in one launch.  The row tile of X is
+// staged in LDS once; H1 and then H2 replace it there (a layer accumulates in
+// registers, and its BF16 outputs overwrite the tile after a barrier that
+// ends every wave's reads).  Weights come from their transposed BF16 copies
+// (k contiguous, read through L2) straight into MFMA operands.  Each of the
+// 4 waves owns 64 output columns of a hidden layer (4 x 4 tiles of 16 x 16)
+// and 16 rows of the output layer.
+//
+// v_mfma_f32_16x16x32_bf16: lane l holds A[l % 16][k] and B[k][l % 16] for
+// the 8 values of k of its lane group l / 16, and the result
+// D[4 (l / 16) + e][l % 16].  The k-assignment is the same for both
+// operands, so any fixed map of the 32 k of a chunk onto (group, element)
+// gives the same sum; here group q holds k = 8 q .. 8 q + 7 (16-byte reads).
+// Rounding points as in the oracle: H = bf16(relu(acc + b)), Y = acc + b in
+// FP32.
+constexpr int FT = 64;          // rows per work-group
+constexpr int FPITCH = 264;     // LDS row pitch (elements): 132 dwords, so the 16 rows one
+                                // operand read touches start 4 banks apart
+constexpr int MH = IDM_MLP_HIDDEN, MIN = IDM_MLP_IN_PAD, MOUT = IDM_MLP_OUT_PAD;
+static_assert(MIN % 32 == 0 && MH % 32 == 0, "k in chunks of 32");
+static_assert(MH == 4 * 64 && MOUT == 16 && FT == 4 * 16, "4 waves: 64 columns / 16 rows each");
+static_assert(MIN <= FPITCH && MH <= FPITCH && (FPITCH * 2) % 16 == 0, "tile rows");
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Work-group barrier that orders LDS accesses only: the global weight loads
+// in flight (the next chunk's operands) need not drain at it.
+__device__ __forceinline__ void tile_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// B operands of one 32-k chunk: Wt rows n0 + 16 j + l % 16, k0 + 8 (l / 16) ..
+// (Wt is [N][K], k contiguous, 16-byte aligned rows).
+template <int K, int NJ>
+__device__ __forceinline__ void load_b(const uint16_t *Wt, int n0, int k0, bf16x8 (&b)[NJ]) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+        b[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4v *>(
+                                              Wt + (int64_t)(n0 + 16 * j + li) * K + k0 + 8 * lq));
+}
+
+// acc[i][j] = tile rows m0 + 16 i .. (all K) times Wt rows n0 + 16 j .. .
+// `b` holds chunk 0 on entry (the caller issues it early); each chunk's
+// products run while the next chunk's operands are in flight.
+template <int K, int NI, int NJ>
+__device__ __forceinline__ void tile_product(const uint16_t *tile, int m0, const uint16_t *Wt,
+                                             int n0, bf16x8 (&b)[NJ], f32x4 (&acc)[NI][NJ]) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 a[NI], bc[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) bc[j] = b[j];
+        if (k0 + 32 < K) load_b<K, NJ>(Wt, n0, k0 + 32, b);
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+            a[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4v *>(
+                                                  tile + (m0 + 16 * i + li) * FPITCH + k0 + 8 * lq));
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bc[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+// Hidden-layer epilogue: bf16(relu(acc + b)) into the wave's 64 columns of the tile.
+__device__ __forceinline__ void hidden_out(const f32x4 (&acc)[4][4], const float *bias, int n0,
+                                           uint16_t *tile) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = n0 + 16 * j + li;
+        const float bj = bias[col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                tile[(16 * i + 4 * lq + e) * FPITCH + col] = f2bf(fmaxf(acc[i][j][e] + bj, 0.0f));
+    }
+}
+
+// The tile's first `rows` hidden rows to Hg [.][MH] (16-byte stores).
+__device__ __forceinline__ void tile_to_global(const uint16_t *tile, int rows, int64_t r0,
+                                               uint16_t *Hg) {
+    for (int v = threadIdx.x; v < FT * (MH / 8); v += blockDim.x) {
+        const int r = v / (MH / 8), c = (v % (MH / 8)) * 8;
+        if (r < rows)
+            *reinterpret_cast<u32x4v *>(Hg + (r0 + r) * MH + c) =
+                *reinterpret_cast<const u32x4v *>(tile + r * FPITCH + c);
+    }
+}
+
+// X [B][MIN] BF16 (any alignment), W1t [MH][MIN], W2t [MH][MH], W3t [MOUT][MH]
+// (16-byte aligned), biases FP32; Y [B][MOUT] FP32; H1g, H2g [B][MH] BF16
+// (16-byte aligned) or null.
+__global__ __launch_bounds__(256) void k_mlp_forward(const uint16_t *X, int64_t B,
+                                                     const uint16_t *W1t, const uint16_t *W2t,
+                                                     const uint16_t *W3t, const float *b1,
+                                                     const float *b2, const float *b3, float *Y,
+                                                     uint16_t *H1g, uint16_t *H2g) {
+    __shared__ __attribute__((aligned(16))) uint16_t tile[FT * FPITCH];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63, li = lane & 15, lq = lane >> 4;
+    const int64_t r0 = (int64_t)blockIdx.x * FT;
+    const int rows = (int)min((int64_t)FT, B - r0);
+    bf16x8 b[4];
+    load_b<MIN, 4>(W1t, 64 * wave, 0, b);
+    // stage the X rows (zero beyond the batch)
+    const bool vec = ((uintptr_t)X & 15) == 0;
+    for (int v = t; v < FT * (MIN / 8); v += blockDim.x) {
+        const int r = v / (MIN / 8), c = (v % (MIN / 8)) * 8;
+        u32x4v w = {0u, 0u, 0u, 0u};
+        if (r < rows) {
+            const uint16_t *src = X + (r0 + r) * MIN + c;
+            if (vec) {
+                w = *reinterpret_cast<const u32x4v *>(src);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w[i] = (uint32_t)src[2 * i] | ((uint32_t)src[2 * i + 1] << 16);
+            }
+        }
+        *reinterpret_cast<u32x4v *>(tile + r * FPITCH + c) = w;
+    }
+    tile_barrier();
+    f32x4 acc[4][4];
+    tile_product<MIN, 4, 4>(tile, 0, W1t, 64 * wave, b, acc);
+    load_b<MH, 4>(W2t, 64 * wave, 0, b);
+    tile_barrier();  // every wave has read X
+    hidden_out(acc, b1, 64 * wave, tile);
+    tile_barrier();
+    if (H1g) tile_to_global(tile, rows, r0, H1g);
+    tile_product<MH, 4, 4>(tile, 0, W2t, 64 * wave, b, acc);
+    bf16x8 b3c[1];
+    load_b<MH, 1>(W3t, 0, 0, b3c);
+    tile_barrier();  // every wave has read H1
+    hidden_out(acc, b2, 64 * wave, tile);
+    tile_barrier();
+    if (H2g) tile_to_global(tile, rows, r0, H2g);
+    f32x4 y[1][1];
+    tile_product<MH, 1, 1>(tile, 16 * wave, W3t, 0, b3c, y);
+    const float bo = b3[li];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = 16 * wave + 4 * lq + e;
+        if (r < rows) Y[(r0 + r) * MOUT + li] = y[0][0][e] + bo;
+    }
 }
 
 // Fixed-order sum of split-K partial slabs: out[i] = sum_z part[z][i].
@@ -265,7 +418,16 @@ struct MlpAdam {
     uint16_t *w16;    // BF16 copies of the weight blocks
     int64_t w1_off, w1_n, w2_off, w2_n, w3_off, w3_n;  // ranges in p / w16 offsets
     int64_t w16_w2, w16_w3;
+    int64_t t16_w1, t16_w2, t16_w3;  // transposed copies in w16
 };
+
+// BF16 value of weight element j (row-major [rows][cols]) into both copies.
+__device__ __forceinline__ void put_w16(uint16_t *w16, int64_t plain, int64_t trans, int64_t j,
+                                        int rows, int cols, uint16_t b) {
+    w16[plain + j] = b;
+    const int64_t r = j / cols, c = j % cols;
+    w16[trans + c * rows + r] = b;
+}
 
 __global__ __launch_bounds__(256) void k_mlp_adam(MlpAdam A) {
     const float bc1 = 1.0f - powf(A.beta1, (float)A.t);
@@ -279,16 +441,25 @@ __global__ __launch_bounds__(256) void k_mlp_adam(MlpAdam A) {
         A.v[i] = v;
         const float p = A.p[i] - A.lr * (m / bc1) / (sqrtf(v / bc2) + A.eps);
         A.p[i] = p;
-        if (i >= A.w1_off && i < A.w1_off + A.w1_n) A.w16[i - A.w1_off] = f2bf(p);
-        else if (i >= A.w2_off && i < A.w2_off + A.w2_n) A.w16[A.w16_w2 + (i - A.w2_off)] = f2bf(p);
-        else if (i >= A.w3_off && i < A.w3_off + A.w3_n) A.w16[A.w16_w3 + (i - A.w3_off)] = f2bf(p);
+        if (i >= A.w1_off && i < A.w1_off + A.w1_n)
+            put_w16(A.w16, 0, A.t16_w1, i - A.w1_off, MIN, MH, f2bf(p));
+        else if (i >= A.w2_off && i < A.w2_off + A.w2_n)
+            put_w16(A.w16, A.w16_w2, A.t16_w2, i - A.w2_off, MH, MH, f2bf(p));
+        else if (i >= A.w3_off && i < A.w3_off + A.w3_n)
+            put_w16(A.w16, A.w16_w3, A.t16_w3, i - A.w3_off, MH, MOUT, f2bf(p));
     }
 }
 
-__global__ __launch_bounds__(256) void k_to_bf16(const float *x, int64_t n, uint16_t *y) {
+// BF16 copies of a row-major [rows][cols] weight block: y = x, yt = x^T.
+__global__ __launch_bounds__(256) void k_to_bf16(const float *x, int rows, int cols, uint16_t *y,
+                                                 uint16_t *yt) {
+    const int64_t n = (int64_t)rows * cols;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        y[i] = f2bf(x[i]);
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint16_t b = f2bf(x[i]);
+        y[i] = b;
+        yt[(i % cols) * rows + i / cols] = b;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_fill_f32(float *x, int64_t n, float v) {
@@ -362,8 +533,12 @@ constexpr int64_t N_PARAMS = OFF_B3 + N_B3;
 // weight_grad writes a layer's weight and bias gradients as one block
 static_assert(OFF_B1 == OFF_W1 + N_W1 && OFF_B2 == OFF_W2 + N_W2 && OFF_B3 == OFF_W3 + N_W3,
               "each bias follows its weights");
-// BF16 copies: W1, W2, W3 back to back
-constexpr int64_t H16_W1 = 0, H16_W2 = N_W1, H16_W3 = N_W1 + N_W2, N_W16 = N_W1 + N_W2 + N_W3;
+// BF16 copies: W1, W2, W3 back to back, then their transposes W1^T [H x FIN],
+// W2^T [H x H], W3^T [FOUT x H] (the fused forward's k-contiguous operands)
+constexpr int64_t H16_W1 = 0, H16_W2 = N_W1, H16_W3 = N_W1 + N_W2;
+constexpr int64_t T16_W1 = N_W1 + N_W2 + N_W3, T16_W2 = T16_W1 + N_W1, T16_W3 = T16_W2 + N_W2;
+constexpr int64_t N_W16 = T16_W3 + N_W3;
+static_assert(T16_W1 % 8 == 0 && T16_W2 % 8 == 0 && T16_W3 % 8 == 0, "16-byte aligned blocks");
 
 constexpr int SPLIT_ROWS = 512;  // batch rows per split-K slab of a weight gradient
 
@@ -423,22 +598,15 @@ hipError_t weight_grad(const uint16_t *act, int64_t act_rs, int rows, int in, co
     return hipGetLastError();
 }
 
-hipError_t mlp_forward(const idm_mlp_state *st, const uint16_t *X, int64_t B, const MlpWs &w,
-                       char *ws, float *Y, hipStream_t s) {
+// Y = MLP(X) in one launch; H1 and H2 are kept only when the backward needs them.
+hipError_t mlp_forward(const idm_mlp_state *st, const uint16_t *X, int64_t B, uint16_t *H1,
+                       uint16_t *H2, float *Y, hipStream_t s) {
     const float *P = st->params;
     const uint16_t *W16 = st->weights_bf16;
-    uint16_t *H1 = (uint16_t *)(ws + w.h1), *H2 = (uint16_t *)(ws + w.h2);
-    Gemm g1 = gemm(X, FIN, 1, W16 + H16_W1, H, 1, (int)B, H, FIN);
-    g1.bias = P + OFF_B1; g1.relu = 1; g1.C16 = H1; g1.c16_rs = H;
-    hipError_t e = launch_gemm(g1, 1, s);
-    if (e != hipSuccess) return e;
-    Gemm g2 = gemm(H1, H, 1, W16 + H16_W2, H, 1, (int)B, H, H);
-    g2.bias = P + OFF_B2; g2.relu = 1; g2.C16 = H2; g2.c16_rs = H;
-    e = launch_gemm(g2, 1, s);
-    if (e != hipSuccess) return e;
-    Gemm g3 = gemm(H2, H, 1, W16 + H16_W3, FOUT, 1, (int)B, FOUT, H);
-    g3.bias = P + OFF_B3; g3.C32 = Y; g3.c32_rs = FOUT;
-    return launch_gemm(g3, 1, s);
+    const int64_t tiles = (B + FT - 1) / FT;
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)tiles), dim3(256), 0, s, X, B, W16 + T16_W1,
+                       W16 + T16_W2, W16 + T16_W3, P + OFF_B1, P + OFF_B2, P + OFF_B3, Y, H1, H2);
+    return hipGetLastError();
 }
 
 // Forward + MSE + backward: gradients of every FP32 parameter into G.
@@ -447,9 +615,9 @@ hipError_t mlp_backward(const idm_mlp_state *st, const uint16_t *X, const float 
     const MlpWs w = mlp_ws(batch);
     const int B = (int)batch;
     float *Y = (float *)(ws + w.y);
-    hipError_t e = mlp_forward(st, X, batch, w, ws, Y, s);
-    if (e != hipSuccess) return e;
     uint16_t *H1 = (uint16_t *)(ws + w.h1), *H2 = (uint16_t *)(ws + w.h2);
+    hipError_t e = mlp_forward(st, X, batch, H1, H2, Y, s);
+    if (e != hipSuccess) return e;
     uint16_t *dY = (uint16_t *)(ws + w.dy), *dH2 = (uint16_t *)(ws + w.dh2);
     uint16_t *dH1 = (uint16_t *)(ws + w.dh1);
     float *part = (float *)(ws + w.part);
@@ -481,6 +649,8 @@ hipError_t mlp_backward(const idm_mlp_state *st, const uint16_t *X, const float 
 
 idm_status check_state(const idm_mlp_state *st) {
     if (!st || !st->params || !st->weights_bf16) return mfail(IDM_ERR_INVALID_ARG, "mlp state: null pointer");
+    if (((uintptr_t)st->weights_bf16 & 15) != 0)
+        return mfail(IDM_ERR_INVALID_ARG, "mlp state: weights_bf16 is not 16-byte aligned");
     return IDM_OK;
 }
 
@@ -505,12 +675,13 @@ idm_status idm_mlp_sync(const idm_mlp_state *st, void *stream) {
     idm_status r = check_state(st);
     if (r != IDM_OK) return r;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(N_W1)), dim3(256), 0, s, st->params + OFF_W1, N_W1,
-                       st->weights_bf16 + H16_W1);
-    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(N_W2)), dim3(256), 0, s, st->params + OFF_W2, N_W2,
-                       st->weights_bf16 + H16_W2);
-    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(N_W3)), dim3(256), 0, s, st->params + OFF_W3, N_W3,
-                       st->weights_bf16 + H16_W3);
+    uint16_t *w = st->weights_bf16;
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(N_W1)), dim3(256), 0, s, st->params + OFF_W1, FIN, H,
+                       w + H16_W1, w + T16_W1);
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(N_W2)), dim3(256), 0, s, st->params + OFF_W2, H, H,
+                       w + H16_W2, w + T16_W2);
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(N_W3)), dim3(256), 0, s, st->params + OFF_W3, H, FOUT,
+                       w + H16_W3, w + T16_W3);
     if (st->adam_m && st->adam_v) {
         hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(N_PARAMS)), dim3(256), 0, s, st->adam_m, N_PARAMS, 0.0f);
         hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(N_PARAMS)), dim3(256), 0, s, st->adam_v, N_PARAMS, 0.0f);
@@ -541,10 +712,10 @@ idm_status idm_mlp_forward(const idm_mlp_state *st, const uint16_t *X, int64_t b
                            void *workspace, void *stream) {
     idm_status r = check_state(st);
     if (r != IDM_OK) return r;
-    if (!X || !Y || !workspace || batch < 1 || batch > (1 << 30))
+    (void)workspace;  // the fused forward keeps its activations on chip
+    if (!X || !Y || batch < 1 || batch > (1 << 30))
         return mfail(IDM_ERR_INVALID_ARG, "mlp forward: bad arguments");
-    MlpWs w = mlp_ws(batch);
-    hipError_t e = mlp_forward(st, X, batch, w, (char *)workspace, Y, (hipStream_t)stream);
+    hipError_t e = mlp_forward(st, X, batch, nullptr, nullptr, Y, (hipStream_t)stream);
     return e == hipSuccess ? IDM_OK : mfail(IDM_ERR_HIP, hipGetErrorString(e));
 }
 
@@ -555,6 +726,8 @@ idm_status idm_mlp_gradients(const idm_mlp_state *st, const uint16_t *X, const f
     if (r != IDM_OK) return r;
     if (!X || !U || !workspace || !grad_out || batch < 1 || batch > (1 << 30))
         return mfail(IDM_ERR_INVALID_ARG, "mlp gradients: bad arguments");
+    if (((uintptr_t)workspace & 15) != 0)
+        return mfail(IDM_ERR_INVALID_ARG, "mlp gradients: workspace is not 16-byte aligned");
     hipError_t e = mlp_backward(st, X, U, batch, (char *)workspace, grad_out, loss_out,
                                 (hipStream_t)stream);
     return e == hipSuccess ? IDM_OK : mfail(IDM_ERR_HIP, hipGetErrorString(e));
@@ -568,6 +741,8 @@ idm_status idm_mlp_train_step(const idm_mlp_state *st, const uint16_t *X, const 
     if (!st->adam_m || !st->adam_v) return mfail(IDM_ERR_INVALID_ARG, "mlp state: no Adam moments");
     if (!X || !U || !workspace || batch < 1 || batch > (1 << 30) || t < 1)
         return mfail(IDM_ERR_INVALID_ARG, "mlp train step: bad arguments");
+    if (((uintptr_t)workspace & 15) != 0)
+        return mfail(IDM_ERR_INVALID_ARG, "mlp train step: workspace is not 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)workspace;
     float *G = (float *)(ws + mlp_ws(batch).grad);
@@ -580,6 +755,7 @@ idm_status idm_mlp_train_step(const idm_mlp_state *st, const uint16_t *X, const 
         A.w16 = st->weights_bf16;
         A.w1_off = OFF_W1; A.w1_n = N_W1; A.w2_off = OFF_W2; A.w2_n = N_W2; A.w3_off = OFF_W3; A.w3_n = N_W3;
         A.w16_w2 = H16_W2; A.w16_w3 = H16_W3;
+        A.t16_w1 = T16_W1; A.t16_w2 = T16_W2; A.t16_w3 = T16_W3;
         hipLaunchKernelGGL(k_mlp_adam, dim3(grid_for(N_PARAMS)), dim3(256), 0, s, A);
         e = hipGetLastError();
     }

@@ -68,7 +68,7 @@ class MLP:
             Y = torch.empty(B, MLP_OUT_PAD, dtype=torch.float32, device=X.device)
         sim._need(Y, "Y", torch.float32, B * MLP_OUT_PAD)
         check(_lib.load().idm_mlp_forward(ctypes.byref(self._st), sim._ptr(X), B, sim._ptr(Y),
-                                          sim._ptr(self.workspace(B)), sim._stream()),
+                                          None, sim._stream()),
               "idm_mlp_forward")
         return Y
 

@@ -32,7 +32,7 @@ def _batch(B, seed=0):
     return X, U, Xt, torch.from_numpy(U).cuda()
 
 
-@pytest.mark.parametrize("B", [4096, 777])
+@pytest.mark.parametrize("B", [4096, 777, 64, 1])
 def test_mlp_forward_and_gradients_match_oracle(B):
     import torch
     from paper_2412_16750_amd.warmstart import MLP
@@ -65,6 +65,32 @@ def test_mlp_forward_and_gradients_match_oracle(B):
             assert np.all(a == 0.0), name
 
 
+def test_mlp_forward_any_alignment_and_large_batch():
+    """The forward stages X rows with 16-byte loads when X is 16-byte aligned
+    and element loads otherwise: both give the same bits.  At 100,000 rows
+    (1563 row tiles, ragged last tile) sampled rows match the oracle."""
+    import torch
+    from paper_2412_16750_amd.warmstart import MLP
+    theta = _net(seed=11)
+    net = MLP(theta)
+    B = 100_000
+    X, _, Xt, _ = _batch(B, seed=9)
+    Y = net.forward(Xt)
+    buf = torch.zeros(B * omlp.IN_PAD + 1, dtype=torch.bfloat16, device="cuda")
+    Xo = buf[1:].view(B, omlp.IN_PAD)
+    Xo.copy_(Xt)
+    assert Xo.data_ptr() % 16 != 0
+    Yo = net.forward(Xo)
+    torch.cuda.synchronize()
+    assert torch.equal(Y, Yo)
+    rows = np.r_[0, 1, 63, 64, 65, np.random.default_rng(2).integers(0, B, 200), B - 1]
+    Yr, _ = omlp.forward(theta.astype(np.float64), X[rows], mirror=True)
+    Yg = Y[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+    err = np.abs(Yg[:, :5] - Yr[:, :5]).max()
+    log("mlp B=%d: sampled rows max |Y - Y_oracle| = %.3e" % (B, err))
+    assert err <= 1e-2 * max(1.0, np.abs(Yr[:, :5]).max())
+
+
 def test_mlp_training_reduces_loss():
     """Adam steps on a learnable target (u = sigmoid of a fixed projection of X)."""
     import torch
@@ -89,7 +115,12 @@ def test_mlp_training_reduces_loss():
     w16 = net.w16.float().cpu().numpy()
     p = net.params.cpu().numpy()
     n1 = omlp.IN_PAD * omlp.HID
-    np.testing.assert_array_equal(w16[:n1], torch.from_numpy(p[:n1]).to(torch.bfloat16).float().numpy())
+    w1 = torch.from_numpy(p[:n1]).to(torch.bfloat16).float().numpy()
+    np.testing.assert_array_equal(w16[:n1], w1)
+    # and the transposed copy of W1 that follows the three plain copies
+    t1 = n1 + omlp.HID * omlp.HID + omlp.HID * omlp.OUT_PAD
+    np.testing.assert_array_equal(w16[t1:t1 + n1].reshape(omlp.HID, omlp.IN_PAD),
+                                  w1.reshape(omlp.IN_PAD, omlp.HID).T)
 
 
 def test_features_lane_loss_and_selection():
