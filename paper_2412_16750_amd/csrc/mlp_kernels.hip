@@ -24,12 +24,13 @@ namespace {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// FP32 -> BF16, round to nearest even (NaN kept quiet).
+// FP32 -> BF16, round to nearest even (NaN kept quiet); a select, not a
+// branch, so a wave converting many values stays on one path.
 __device__ __forceinline__ uint16_t f2bf(float x) {
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const uint32_t u = __float_as_uint(x);
+    const uint32_t rounded = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t quiet = (u >> 16) | 0x40u;
+    return (uint16_t)((u & 0x7fffffffu) > 0x7f800000u ? quiet : rounded);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(Gemm g) {
     __shared__ __attribute__((aligned(16))) uint16_t As[64][GPITCH];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[64][GPITCH];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tm = blockIdx.y * 64, tn = blockIdx.x * 64;
+    const int tm = blockIdx.x * 64, tn = blockIdx.y * 64;  // batch-sized M on x (no 65535 cap)
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int bm = tm + wm, bn = tn + wn;
     const int kb = blockIdx.z * g.k_chunk;
@@ -221,55 +222,64 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(Gemm g) {
 // Rounding points as in the oracle: H = bf16(relu(acc + b)), Y = acc + b in
 // FP32.
 constexpr int FT = 64;          // rows per work-group
+constexpr int FPD = 2;          // hidden layers: weight chunks in flight ahead of the products
 constexpr int FPITCH = 264;     // LDS row pitch (elements): 132 dwords, so the 16 rows one
                                 // operand read touches start 4 banks apart
 constexpr int MH = IDM_MLP_HIDDEN, MIN = IDM_MLP_IN_PAD, MOUT = IDM_MLP_OUT_PAD;
 static_assert(MIN % 32 == 0 && MH % 32 == 0, "k in chunks of 32");
-static_assert(MH == 4 * 64 && MOUT == 16 && FT == 4 * 16, "4 waves: 64 columns / 16 rows each");
+static_assert(MH == 4 * 64 && MOUT == 16 && FT % 64 == 0, "4 waves: 64 columns / FT/4 rows each");
 static_assert(MIN <= FPITCH && MH <= FPITCH && (FPITCH * 2) % 16 == 0, "tile rows");
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // Work-group barrier that orders LDS accesses only: the global weight loads
-// in flight (the next chunk's operands) need not drain at it.
+// in flight (the next chunks' operands) need not drain at it.
 __device__ __forceinline__ void tile_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// B operands of one 32-k chunk: Wt rows n0 + 16 j + l % 16, k0 + 8 (l / 16) ..
+// B operands of 32-k chunk c: Wt rows n0 + 16 j + l % 16, k = 32 c + 8 (l / 16) ..
 // (Wt is [N][K], k contiguous, 16-byte aligned rows).
 template <int K, int NJ>
-__device__ __forceinline__ void load_b(const uint16_t *Wt, int n0, int k0, bf16x8 (&b)[NJ]) {
+__device__ __forceinline__ void load_b(const uint16_t *Wt, int n0, int c, bf16x8 (&b)[NJ]) {
     const int lane = threadIdx.x & 63, li = lane & 15, lq = lane >> 4;
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
         b[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4v *>(
-                                              Wt + (int64_t)(n0 + 16 * j + li) * K + k0 + 8 * lq));
+                                              Wt + (int64_t)(n0 + 16 * j + li) * K + 32 * c + 8 * lq));
+}
+
+// The first PD chunks of a layer's B operands (issued ahead of its products).
+template <int K, int NJ, int PD>
+__device__ __forceinline__ void load_b_head(const uint16_t *Wt, int n0, bf16x8 (&b)[PD][NJ]) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d)
+        if (d < K / 32) load_b<K, NJ>(Wt, n0, d, b[d]);
 }
 
 // acc[i][j] = tile rows m0 + 16 i .. (all K) times Wt rows n0 + 16 j .. .
-// `b` holds chunk 0 on entry (the caller issues it early); each chunk's
-// products run while the next chunk's operands are in flight.
-template <int K, int NI, int NJ>
+// On entry b[d] holds chunk d; chunk c's products run while chunks
+// c + 1 .. c + PD are in flight.
+template <int K, int NI, int NJ, int PD>
 __device__ __forceinline__ void tile_product(const uint16_t *tile, int m0, const uint16_t *Wt,
-                                             int n0, bf16x8 (&b)[NJ], f32x4 (&acc)[NI][NJ]) {
+                                             int n0, bf16x8 (&b)[PD][NJ], f32x4 (&acc)[NI][NJ]) {
     const int lane = threadIdx.x & 63, li = lane & 15, lq = lane >> 4;
 #pragma unroll
     for (int i = 0; i < NI; ++i)
 #pragma unroll
         for (int j = 0; j < NJ; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int k0 = 0; k0 < K; k0 += 32) {
+    for (int c = 0; c < K / 32; ++c) {
         bf16x8 a[NI], bc[NJ];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) bc[j] = b[j];
-        if (k0 + 32 < K) load_b<K, NJ>(Wt, n0, k0 + 32, b);
+        for (int j = 0; j < NJ; ++j) bc[j] = b[c % PD][j];
+        if (c + PD < K / 32) load_b<K, NJ>(Wt, n0, c + PD, b[c % PD]);
 #pragma unroll
         for (int i = 0; i < NI; ++i)
             a[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4v *>(
-                                                  tile + (m0 + 16 * i + li) * FPITCH + k0 + 8 * lq));
+                                                  tile + (m0 + 16 * i + li) * FPITCH + 32 * c + 8 * lq));
 #pragma unroll
         for (int i = 0; i < NI; ++i)
 #pragma unroll
@@ -279,7 +289,8 @@ __device__ __forceinline__ void tile_product(const uint16_t *tile, int m0, const
 }
 
 // Hidden-layer epilogue: bf16(relu(acc + b)) into the wave's 64 columns of the tile.
-__device__ __forceinline__ void hidden_out(const f32x4 (&acc)[4][4], const float *bias, int n0,
+template <int NI>
+__device__ __forceinline__ void hidden_out(const f32x4 (&acc)[NI][4], const float *bias, int n0,
                                            uint16_t *tile) {
     const int lane = threadIdx.x & 63, li = lane & 15, lq = lane >> 4;
 #pragma unroll
@@ -287,7 +298,7 @@ __device__ __forceinline__ void hidden_out(const f32x4 (&acc)[4][4], const float
         const int col = n0 + 16 * j + li;
         const float bj = bias[col];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NI; ++i)
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 tile[(16 * i + 4 * lq + e) * FPITCH + col] = f2bf(fmaxf(acc[i][j][e] + bj, 0.0f));
@@ -297,28 +308,27 @@ __device__ __forceinline__ void hidden_out(const f32x4 (&acc)[4][4], const float
 // The tile's first `rows` hidden rows to Hg [.][MH] (16-byte stores).
 __device__ __forceinline__ void tile_to_global(const uint16_t *tile, int rows, int64_t r0,
                                                uint16_t *Hg) {
-    for (int v = threadIdx.x; v < FT * (MH / 8); v += blockDim.x) {
+    for (int v = threadIdx.x; v < rows * (MH / 8); v += blockDim.x) {
         const int r = v / (MH / 8), c = (v % (MH / 8)) * 8;
-        if (r < rows)
-            *reinterpret_cast<u32x4v *>(Hg + (r0 + r) * MH + c) =
-                *reinterpret_cast<const u32x4v *>(tile + r * FPITCH + c);
+        *reinterpret_cast<u32x4v *>(Hg + (r0 + r) * MH + c) =
+            *reinterpret_cast<const u32x4v *>(tile + r * FPITCH + c);
     }
 }
 
 // X [B][MIN] BF16 (any alignment), W1t [MH][MIN], W2t [MH][MH], W3t [MOUT][MH]
 // (16-byte aligned), biases FP32; Y [B][MOUT] FP32; H1g, H2g [B][MH] BF16
 // (16-byte aligned) or null.
-__global__ __launch_bounds__(256) void k_mlp_forward(const uint16_t *X, int64_t B,
-                                                     const uint16_t *W1t, const uint16_t *W2t,
-                                                     const uint16_t *W3t, const float *b1,
-                                                     const float *b2, const float *b3, float *Y,
-                                                     uint16_t *H1g, uint16_t *H2g) {
+// Three waves per SIMD: the register budget that keeps 3 work-groups per CU.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_forward(
+    const uint16_t *X, int64_t B, const uint16_t *W1t, const uint16_t *W2t, const uint16_t *W3t,
+    const float *b1, const float *b2, const float *b3, float *Y, uint16_t *H1g, uint16_t *H2g) {
+    constexpr int NI = FT / 16, NO = FT / 64;  // m-tiles per wave: hidden layers, output layer
     __shared__ __attribute__((aligned(16))) uint16_t tile[FT * FPITCH];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63, li = lane & 15, lq = lane >> 4;
     const int64_t r0 = (int64_t)blockIdx.x * FT;
     const int rows = (int)min((int64_t)FT, B - r0);
-    bf16x8 b[4];
-    load_b<MIN, 4>(W1t, 64 * wave, 0, b);
+    bf16x8 b[FPD][4];
+    load_b_head<MIN, 4, FPD>(W1t, 64 * wave, b);
     // stage the X rows (zero beyond the batch)
     const bool vec = ((uintptr_t)X & 15) == 0;
     for (int v = t; v < FT * (MIN / 8); v += blockDim.x) {
@@ -336,28 +346,32 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const uint16_t *X, int64_t 
         *reinterpret_cast<u32x4v *>(tile + r * FPITCH + c) = w;
     }
     tile_barrier();
-    f32x4 acc[4][4];
-    tile_product<MIN, 4, 4>(tile, 0, W1t, 64 * wave, b, acc);
-    load_b<MH, 4>(W2t, 64 * wave, 0, b);
+    f32x4 acc[NI][4];
+    tile_product<MIN, NI, 4, FPD>(tile, 0, W1t, 64 * wave, b, acc);
+    load_b_head<MH, 4, FPD>(W2t, 64 * wave, b);
     tile_barrier();  // every wave has read X
-    hidden_out(acc, b1, 64 * wave, tile);
+    hidden_out<NI>(acc, b1, 64 * wave, tile);
     tile_barrier();
     if (H1g) tile_to_global(tile, rows, r0, H1g);
-    tile_product<MH, 4, 4>(tile, 0, W2t, 64 * wave, b, acc);
-    bf16x8 b3c[1];
-    load_b<MH, 1>(W3t, 0, 0, b3c);
+    tile_product<MH, NI, 4, FPD>(tile, 0, W2t, 64 * wave, b, acc);
+    // the output layer's weights (8 KB, the same for every wave): all of a
+    // wave's chunks issued at once, since each feeds only NO products
+    bf16x8 b3c[MH / 32][1];
+    load_b_head<MH, 1, MH / 32>(W3t, 0, b3c);
     tile_barrier();  // every wave has read H1
-    hidden_out(acc, b2, 64 * wave, tile);
+    hidden_out<NI>(acc, b2, 64 * wave, tile);
     tile_barrier();
     if (H2g) tile_to_global(tile, rows, r0, H2g);
-    f32x4 y[1][1];
-    tile_product<MH, 1, 1>(tile, 16 * wave, W3t, 0, b3c, y);
+    f32x4 y[NO][1];
+    tile_product<MH, NO, 1, MH / 32>(tile, 16 * NO * wave, W3t, 0, b3c, y);
     const float bo = b3[li];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int r = 16 * wave + 4 * lq + e;
-        if (r < rows) Y[(r0 + r) * MOUT + li] = y[0][0][e] + bo;
-    }
+    for (int i = 0; i < NO; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = 16 * (NO * wave + i) + 4 * lq + e;
+            if (r < rows) Y[(r0 + r) * MOUT + li] = y[i][0][e] + bo;
+        }
 }
 
 // Fixed-order sum of split-K partial slabs: out[i] = sum_z part[z][i].
@@ -540,7 +554,16 @@ constexpr int64_t T16_W1 = N_W1 + N_W2 + N_W3, T16_W2 = T16_W1 + N_W1, T16_W3 = 
 constexpr int64_t N_W16 = T16_W3 + N_W3;
 static_assert(T16_W1 % 8 == 0 && T16_W2 % 8 == 0 && T16_W3 % 8 == 0, "16-byte aligned blocks");
 
-constexpr int SPLIT_ROWS = 512;  // batch rows per split-K slab of a weight gradient
+constexpr int SPLIT_ROWS = 256;  // batch rows per split-K slab of a weight gradient
+constexpr int MAX_SLABS = 64;    // larger batches get longer slabs (bounded workspace, grid z)
+
+// Rows per split-K slab for a batch of B rows: SPLIT_ROWS, or longer (a
+// multiple of the GEMM's k stage) so that at most MAX_SLABS slabs cover B.
+int64_t slab_rows(int64_t B) {
+    const int64_t slabs = std::max<int64_t>(1, std::min<int64_t>((B + SPLIT_ROWS - 1) / SPLIT_ROWS, MAX_SLABS));
+    const int64_t rows = (B + slabs - 1) / slabs;
+    return (rows + GK - 1) / GK * GK;
+}
 
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -559,7 +582,7 @@ MlpWs mlp_ws(int64_t B) {
     w.dh2 = o; o += al(2 * B * H);
     w.dh1 = o; o += al(2 * B * H);
     w.grad = o; o += al(4 * N_PARAMS);
-    const int64_t slabs = (B + SPLIT_ROWS - 1) / SPLIT_ROWS;
+    const int64_t slabs = (B + slab_rows(B) - 1) / slab_rows(B);
     w.part = o; o += al(4 * slabs * (int64_t)(std::max(H, FIN) + 1) * H);
     w.lpart = o; o += al(8 * 8192);
     w.total = o;
@@ -582,13 +605,14 @@ Gemm gemm(const uint16_t *A, int64_t a_rs, int64_t a_cs, const uint16_t *B, int6
 // Weight and bias gradients of one layer into dst = [in + 1][out] (the
 // weights, then the bias, as the parameters are laid out): [act^T; 1] dz, the
 // all-ones row giving the bias gradient (column sums of dz), split-K over
-// 512-row slabs summed in slab order.
+// slabs of slab_rows(rows) rows summed in slab order.
 hipError_t weight_grad(const uint16_t *act, int64_t act_rs, int rows, int in, const uint16_t *dz,
                        int64_t dz_rs, int out, float *part, float *dst, hipStream_t s) {
     Gemm g = gemm(act, 1, act_rs, dz, dz_rs, 1, in + 1, out, rows);
     g.ones_row = in;
-    g.k_chunk = SPLIT_ROWS;
-    const int slabs = (rows + SPLIT_ROWS - 1) / SPLIT_ROWS;
+    const int64_t sr = slab_rows(rows);
+    g.k_chunk = (int)sr;
+    const int slabs = (int)((rows + sr - 1) / sr);
     g.C32 = part;
     g.c32_rs = out;
     hipError_t e = launch_gemm(g, slabs, s);
@@ -658,7 +682,7 @@ idm_status check_state(const idm_mlp_state *st) {
 
 namespace idmx {
 hipError_t launch_gemm(const Gemm &g, int splits, hipStream_t s) {
-    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, splits);
+    dim3 grid((g.M + 63) / 64, (g.N + 63) / 64, splits);
     hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }
