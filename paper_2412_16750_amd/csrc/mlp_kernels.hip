@@ -425,7 +425,9 @@ __global__ __launch_bounds__(64) void k_sum_f64(const double *part, int n, doubl
 // Adam on the FP32 master parameters, then BF16 copies of the weights.
 struct MlpAdam {
     float *p, *m, *v;
-    const float *g;
+    const float *g;   // gradients, or null: then sums of the split-K slabs in `part`
+    const float *part;
+    int slabs;
     int64_t n;
     int32_t t;        // step number of this update (1-based)
     float lr, beta1, beta2, eps;
@@ -443,12 +445,25 @@ __device__ __forceinline__ void put_w16(uint16_t *w16, int64_t plain, int64_t tr
     w16[trans + c * rows + r] = b;
 }
 
+// Gradient of parameter i from the weight-gradient GEMMs' split-K slabs:
+// layer block [b0, b1) (weights then bias) has its slabs at part + slabs * b0,
+// [slab][b1 - b0]; summed in slab order, as k_sum_slabs does.
+__device__ __forceinline__ float slab_grad(const MlpAdam &A, int64_t i) {
+    const int64_t b0 = i >= A.w3_off ? A.w3_off : (i >= A.w2_off ? A.w2_off : A.w1_off);
+    const int64_t b1 = i >= A.w3_off ? A.n : (i >= A.w2_off ? A.w3_off : A.w2_off);
+    const int64_t nb = b1 - b0;
+    const float *q = A.part + (int64_t)A.slabs * b0 + (i - b0);
+    float s = 0.0f;
+    for (int z = 0; z < A.slabs; ++z) s += q[(int64_t)z * nb];
+    return s;
+}
+
 __global__ __launch_bounds__(256) void k_mlp_adam(MlpAdam A) {
     const float bc1 = 1.0f - powf(A.beta1, (float)A.t);
     const float bc2 = 1.0f - powf(A.beta2, (float)A.t);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const float g = A.g[i];
+        const float g = A.g ? A.g[i] : slab_grad(A, i);
         const float m = A.beta1 * A.m[i] + (1.0f - A.beta1) * g;
         const float v = A.beta2 * A.v[i] + (1.0f - A.beta2) * g * g;
         A.m[i] = m;
@@ -568,7 +583,7 @@ int64_t slab_rows(int64_t B) {
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
 struct MlpWs {
-    size_t h1, h2, y, dy, dyf, dh2, dh1, grad, part, lpart, total;
+    size_t h1, h2, y, dy, dyf, dh2, dh1, part, lpart, total;
 };
 
 MlpWs mlp_ws(int64_t B) {
@@ -581,9 +596,10 @@ MlpWs mlp_ws(int64_t B) {
     w.dyf = o; o += al(4 * B * FOUT);
     w.dh2 = o; o += al(2 * B * H);
     w.dh1 = o; o += al(2 * B * H);
-    w.grad = o; o += al(4 * N_PARAMS);
     const int64_t slabs = (B + slab_rows(B) - 1) / slab_rows(B);
-    w.part = o; o += al(4 * slabs * (int64_t)(std::max(H, FIN) + 1) * H);
+    // split-K slabs of the three weight gradients, one region per layer:
+    // layer block [OFF_Wl, OFF_Wl + n_l) at part + slabs * OFF_Wl, [slab][n_l]
+    w.part = o; o += al(4 * slabs * N_PARAMS);
     w.lpart = o; o += al(8 * 8192);
     w.total = o;
     return w;
@@ -605,7 +621,8 @@ Gemm gemm(const uint16_t *A, int64_t a_rs, int64_t a_cs, const uint16_t *B, int6
 // Weight and bias gradients of one layer into dst = [in + 1][out] (the
 // weights, then the bias, as the parameters are laid out): [act^T; 1] dz, the
 // all-ones row giving the bias gradient (column sums of dz), split-K over
-// slabs of slab_rows(rows) rows summed in slab order.
+// slabs of slab_rows(rows) rows summed in slab order (into dst; with dst
+// null the slabs stay in `part` for the Adam kernel to sum).
 hipError_t weight_grad(const uint16_t *act, int64_t act_rs, int rows, int in, const uint16_t *dz,
                        int64_t dz_rs, int out, float *part, float *dst, hipStream_t s) {
     Gemm g = gemm(act, 1, act_rs, dz, dz_rs, 1, in + 1, out, rows);
@@ -616,7 +633,7 @@ hipError_t weight_grad(const uint16_t *act, int64_t act_rs, int rows, int in, co
     g.C32 = part;
     g.c32_rs = out;
     hipError_t e = launch_gemm(g, slabs, s);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !dst) return e;
     const int64_t n = (int64_t)(in + 1) * out;
     hipLaunchKernelGGL(k_sum_slabs, dim3(grid_for(n)), dim3(256), 0, s, part, slabs, n, dst);
     return hipGetLastError();
@@ -633,7 +650,8 @@ hipError_t mlp_forward(const idm_mlp_state *st, const uint16_t *X, int64_t B, ui
     return hipGetLastError();
 }
 
-// Forward + MSE + backward: gradients of every FP32 parameter into G.
+// Forward + MSE + backward: gradients of every FP32 parameter into G, or
+// (G null) left as per-layer split-K slabs in the workspace's `part`.
 hipError_t mlp_backward(const idm_mlp_state *st, const uint16_t *X, const float *U, int64_t batch,
                         char *ws, float *G, double *loss_out, hipStream_t s) {
     const MlpWs w = mlp_ws(batch);
@@ -645,6 +663,8 @@ hipError_t mlp_backward(const idm_mlp_state *st, const uint16_t *X, const float 
     uint16_t *dY = (uint16_t *)(ws + w.dy), *dH2 = (uint16_t *)(ws + w.dh2);
     uint16_t *dH1 = (uint16_t *)(ws + w.dh1);
     float *part = (float *)(ws + w.part);
+    const int64_t slabs = (B + slab_rows(B) - 1) / slab_rows(B);
+    float *part1 = part + slabs * OFF_W1, *part2 = part + slabs * OFF_W2, *part3 = part + slabs * OFF_W3;
     double *lpart = (double *)(ws + w.lpart);
     const int lgrid = std::min(1024, grid_for((int64_t)B * FOUT));
     hipLaunchKernelGGL(k_mse_grad, dim3(lgrid), dim3(256), 0, s, Y, (int64_t)FOUT, U, B,
@@ -654,21 +674,21 @@ hipError_t mlp_backward(const idm_mlp_state *st, const uint16_t *X, const float 
                            1.0 / ((double)B * IDM_MLP_OUT), loss_out);
     const uint16_t *W16 = st->weights_bf16;
     // layer 3: [dW3; db3] = [H2^T; 1] dY, dH2 = (dY W3^T) * [H2 > 0]
-    e = weight_grad(H2, H, B, H, dY, FOUT, FOUT, part, G + OFF_W3, s);  // and db3
+    e = weight_grad(H2, H, B, H, dY, FOUT, FOUT, part3, G ? G + OFF_W3 : nullptr, s);  // and db3
     if (e != hipSuccess) return e;
     Gemm g3 = gemm(dY, FOUT, 1, W16 + H16_W3, 1, FOUT, B, H, FOUT);
     g3.mask = H2; g3.mask_rs = H; g3.C16 = dH2; g3.c16_rs = H;
     e = launch_gemm(g3, 1, s);
     if (e != hipSuccess) return e;
     // layer 2: [dW2; db2] = [H1^T; 1] dH2, dH1 = (dH2 W2^T) * [H1 > 0]
-    e = weight_grad(H1, H, B, H, dH2, H, H, part, G + OFF_W2, s);  // and db2
+    e = weight_grad(H1, H, B, H, dH2, H, H, part2, G ? G + OFF_W2 : nullptr, s);  // and db2
     if (e != hipSuccess) return e;
     Gemm g2 = gemm(dH2, H, 1, W16 + H16_W2, 1, H, B, H, H);
     g2.mask = H1; g2.mask_rs = H; g2.C16 = dH1; g2.c16_rs = H;
     e = launch_gemm(g2, 1, s);
     if (e != hipSuccess) return e;
     // layer 1: [dW1; db1] = [X^T; 1] dH1
-    return weight_grad(X, FIN, B, FIN, dH1, H, H, part, G + OFF_W1, s);  // and db1
+    return weight_grad(X, FIN, B, FIN, dH1, H, H, part1, G ? G + OFF_W1 : nullptr, s);  // and db1
 }
 
 idm_status check_state(const idm_mlp_state *st) {
@@ -769,11 +789,12 @@ idm_status idm_mlp_train_step(const idm_mlp_state *st, const uint16_t *X, const 
         return mfail(IDM_ERR_INVALID_ARG, "mlp train step: workspace is not 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)workspace;
-    float *G = (float *)(ws + mlp_ws(batch).grad);
-    hipError_t e = mlp_backward(st, X, U, batch, ws, G, loss_out, s);
+    hipError_t e = mlp_backward(st, X, U, batch, ws, nullptr, loss_out, s);
     if (e == hipSuccess) {
         MlpAdam A;
-        A.p = st->params; A.m = st->adam_m; A.v = st->adam_v; A.g = G; A.n = N_PARAMS;
+        A.p = st->params; A.m = st->adam_m; A.v = st->adam_v; A.g = nullptr; A.n = N_PARAMS;
+        A.part = (const float *)(ws + mlp_ws(batch).part);
+        A.slabs = (int)((batch + slab_rows(batch) - 1) / slab_rows(batch));
         A.t = t;
         A.lr = st->lr; A.beta1 = st->beta1; A.beta2 = st->beta2; A.eps = st->eps;
         A.w16 = st->weights_bf16;

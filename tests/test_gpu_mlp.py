@@ -91,6 +91,31 @@ def test_mlp_forward_any_alignment_and_large_batch():
     assert err <= 1e-2 * max(1.0, np.abs(Yr[:, :5]).max())
 
 
+@pytest.mark.parametrize("B", [3000, 4096])
+def test_train_step_is_adam_on_the_gradients(B):
+    """The training step sums the weight gradients' split-K slabs inside its
+    Adam kernel; the gradients entry point sums them in a kernel of its own.
+    After one step the first moment is exactly (1 - beta1) g, the second
+    (1 - beta2) g^2, for the g that idm_mlp_gradients returns (B = 3000 ends
+    in a partial slab)."""
+    import torch
+    from paper_2412_16750_amd.warmstart import MLP
+    theta = _net(seed=4)
+    _, _, Xt, Ut = _batch(B, seed=4)
+    a, b = MLP(theta, lr=1e-3), MLP(theta, lr=1e-3)
+    G = torch.empty(theta.size, dtype=torch.float32, device="cuda")
+    a.gradients(Xt, Ut, G)
+    b.train_step(Xt, Ut)
+    torch.cuda.synchronize()
+    one = torch.tensor(1.0, dtype=torch.float32)
+    c1 = (one - torch.tensor(0.9, dtype=torch.float32)).item()
+    c2 = (one - torch.tensor(0.999, dtype=torch.float32)).item()
+    assert torch.count_nonzero(G) > 0.9 * G.numel()
+    assert torch.equal(b.m, G * c1)
+    assert torch.equal(b.v, (G * c2) * G)
+    log("mlp B=%d: train step moments match the gradients entry point" % B)
+
+
 def test_mlp_training_reduces_loss():
     """Adam steps on a learnable target (u = sigmoid of a fixed projection of X)."""
     import torch
