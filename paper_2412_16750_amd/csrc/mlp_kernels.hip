@@ -49,6 +49,17 @@ struct Gemm {
     uint16_t *C16;           // BF16 output or null
     int64_t c16_rs;
     int ones_row;            // A's row that reads as all ones (not in memory), or -1
+    int splits;              // k slabs (blocks along k)
+};
+
+// Up to three independent GEMMs in one launch: the blocks of problem p are
+// the linear block indices [start[p], start[p + 1]), each problem's blocks
+// ordered m-tile fastest, then n-tile, then k slab.
+constexpr int MAX_GROUP = 3;
+struct GemmGroup {
+    Gemm g[MAX_GROUP];
+    int n;
+    int start[MAX_GROUP + 1];
 };
 
 // 256 threads = 4 waves; block tile 64 x 64; each wave 32 x 32 = 2 x 2 MFMA
@@ -151,14 +162,20 @@ __device__ __forceinline__ void stage_tile(const uint16_t *P, int64_t s_row, int
     }
 }
 
-__global__ __launch_bounds__(256) void k_gemm_bf16(Gemm g) {
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmGroup G) {
     __shared__ __attribute__((aligned(16))) uint16_t As[64][GPITCH];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[64][GPITCH];
+    int p = 0;
+    while (p + 1 < G.n && (int)blockIdx.x >= G.start[p + 1]) ++p;
+    const Gemm &g = G.g[p];
+    const int local = (int)blockIdx.x - G.start[p];
+    const int mt = (g.M + 63) / 64, nt = (g.N + 63) / 64;
+    const int bz = local / (mt * nt);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tm = blockIdx.x * 64, tn = blockIdx.y * 64;  // batch-sized M on x (no 65535 cap)
+    const int tm = (local % mt) * 64, tn = ((local / mt) % nt) * 64;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int bm = tm + wm, bn = tn + wn;
-    const int kb = blockIdx.z * g.k_chunk;
+    const int kb = bz * g.k_chunk;
     const int ke = min(g.K, kb + g.k_chunk);
     const int li = lane & 15, lq = lane >> 4;
     f32x4 acc[2][2];
@@ -188,7 +205,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(Gemm g) {
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
         }
     }
-    float *C32 = g.C32 ? g.C32 + (int64_t)blockIdx.z * g.M * g.c32_rs : nullptr;
+    float *C32 = g.C32 ? g.C32 + (int64_t)bz * g.M * g.c32_rs : nullptr;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -385,32 +402,57 @@ __global__ __launch_bounds__(256) void k_sum_slabs(const float *part, int slabs,
     }
 }
 
-// dY = 2 (Y - U) / (B * n_out) on the first n_out columns (BF16, padding 0),
-// and per-block FP64 partial sums of the squared error.
-__global__ __launch_bounds__(256) void k_mse_grad(const float *Y, int64_t y_rs, const float *U,
-                                                  int B, int n_out, int n_pad, uint16_t *dY,
-                                                  float *dYf, double *part) {
+// Output layer's backward, 16 rows per step of a grid-stride loop:
+// dY = 2 (Y - U) / (B n_out) on the first n_out columns (BF16, padding
+// columns 0), the squared errors summed per work-group in FP64, and
+// dH2 = (dY W3^T) * [H2 > 0] in BF16.  dY has only n_out nonzero columns, so
+// dH2 is n_out FP32 products per element (exact: BF16 x BF16), accumulated
+// in column order, one thread per hidden column.
+constexpr int OG_ROWS = 256 / MOUT;  // rows per step: one thread per dY element
+__global__ __launch_bounds__(256) void k_out_grad(const float *Y, const float *U, int B,
+                                                  const uint16_t *W3, const uint16_t *H2,
+                                                  uint16_t *dY, uint16_t *dH2, double *part) {
+    constexpr int NOUT = IDM_MLP_OUT;
+    static_assert(MH == 256 && OG_ROWS * MOUT == 256, "one thread per dY element and per column");
+    __shared__ float sdy[OG_ROWS][NOUT];
     __shared__ double red[4];
-    const int64_t total = (int64_t)B * n_pad;
+    const int t = threadIdx.x;
+    const float scale = 2.0f / ((float)B * (float)NOUT);
+    float w[NOUT];  // column t of W3^T
+#pragma unroll
+    for (int c = 0; c < NOUT; ++c) w[c] = bf2f(W3[t * MOUT + c]);
     double se = 0.0;
-    const float scale = 2.0f / ((float)B * (float)n_out);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int b = (int)(i / n_pad), c = (int)(i % n_pad);
-        float d = 0.0f;
-        if (c < n_out) {
-            float r = Y[(int64_t)b * y_rs + c] - U[(int64_t)b * n_out + c];
-            se += (double)r * (double)r;
-            d = scale * r;
+    const int64_t groups = ((int64_t)B + OG_ROWS - 1) / OG_ROWS;
+    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int64_t r0 = g * OG_ROWS;
+        const int rows = (int)min((int64_t)OG_ROWS, (int64_t)B - r0);
+        {
+            const int r = t / MOUT, c = t % MOUT;
+            float d = 0.0f;
+            if (r < rows && c < NOUT) {
+                const float res = Y[(r0 + r) * MOUT + c] - U[(r0 + r) * NOUT + c];
+                se += (double)res * (double)res;
+                d = scale * res;
+            }
+            const uint16_t h = f2bf(d);
+            if (r < rows) dY[(r0 + r) * MOUT + c] = h;
+            if (c < NOUT) sdy[r][c] = bf2f(h);
         }
-        dY[i] = f2bf(d);
-        if (dYf) dYf[i] = d;
+        __syncthreads();
+        for (int r = 0; r < rows; ++r) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int c = 0; c < NOUT; ++c) acc = fmaf(sdy[r][c], w[c], acc);
+            const int64_t o = (r0 + r) * MH + t;
+            dH2[o] = f2bf(bf2f(H2[o]) > 0.0f ? acc : 0.0f);
+        }
+        __syncthreads();  // sdy is rewritten by the next step
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) se += __shfl_down(se, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = se;
+    if ((t & 63) == 0) red[t >> 6] = se;
     __syncthreads();
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (t == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 __global__ __launch_bounds__(64) void k_sum_f64(const double *part, int n, double scale,
@@ -537,7 +579,7 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
-hipError_t launch_gemm(const Gemm &g, int splits, hipStream_t s);
+hipError_t launch_gemms(const Gemm *gs, int n, hipStream_t s);
 
 }  // namespace idmx
 
@@ -583,7 +625,7 @@ int64_t slab_rows(int64_t B) {
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
 struct MlpWs {
-    size_t h1, h2, y, dy, dyf, dh2, dh1, part, lpart, total;
+    size_t h1, h2, y, dy, dh2, dh1, part, lpart, total;
 };
 
 MlpWs mlp_ws(int64_t B) {
@@ -593,7 +635,6 @@ MlpWs mlp_ws(int64_t B) {
     w.h2 = o; o += al(2 * B * H);
     w.y = o; o += al(4 * B * FOUT);
     w.dy = o; o += al(2 * B * FOUT);
-    w.dyf = o; o += al(4 * B * FOUT);
     w.dh2 = o; o += al(2 * B * H);
     w.dh1 = o; o += al(2 * B * H);
     const int64_t slabs = (B + slab_rows(B) - 1) / slab_rows(B);
@@ -614,28 +655,31 @@ Gemm gemm(const uint16_t *A, int64_t a_rs, int64_t a_cs, const uint16_t *B, int6
     g.M = M; g.N = N; g.K = K;
     g.k_chunk = ((K + 15) / 16) * 16;
     g.ones_row = -1;
+    g.splits = 1;
     return g;
 }
 
-// Weight gradient dW = Act^T dZ over the batch: split-K slabs + fixed-order sum.
-// Weight and bias gradients of one layer into dst = [in + 1][out] (the
-// weights, then the bias, as the parameters are laid out): [act^T; 1] dz, the
-// all-ones row giving the bias gradient (column sums of dz), split-K over
-// slabs of slab_rows(rows) rows summed in slab order (into dst; with dst
-// null the slabs stay in `part` for the Adam kernel to sum).
-hipError_t weight_grad(const uint16_t *act, int64_t act_rs, int rows, int in, const uint16_t *dz,
-                       int64_t dz_rs, int out, float *part, float *dst, hipStream_t s) {
+// Weight and bias gradients of one layer as one GEMM, [act^T; 1] dz, with
+// split-K over slabs of slab_rows(rows) rows: slab z of the [in + 1][out]
+// result (the weights, then the bias, as the parameters are laid out) at
+// part + z (in + 1) out.  The all-ones row gives the bias gradient (column
+// sums of dz).
+Gemm weight_grad(const uint16_t *act, int64_t act_rs, int rows, int in, const uint16_t *dz,
+                 int64_t dz_rs, int out, float *part) {
     Gemm g = gemm(act, 1, act_rs, dz, dz_rs, 1, in + 1, out, rows);
     g.ones_row = in;
     const int64_t sr = slab_rows(rows);
     g.k_chunk = (int)sr;
-    const int slabs = (int)((rows + sr - 1) / sr);
+    g.splits = (int)((rows + sr - 1) / sr);
     g.C32 = part;
     g.c32_rs = out;
-    hipError_t e = launch_gemm(g, slabs, s);
-    if (e != hipSuccess || !dst) return e;
-    const int64_t n = (int64_t)(in + 1) * out;
-    hipLaunchKernelGGL(k_sum_slabs, dim3(grid_for(n)), dim3(256), 0, s, part, slabs, n, dst);
+    return g;
+}
+
+// Fixed-order sum of a weight gradient's slabs into dst.
+hipError_t sum_slabs(const Gemm &wg, float *dst, hipStream_t s) {
+    const int64_t n = (int64_t)wg.M * wg.N;
+    hipLaunchKernelGGL(k_sum_slabs, dim3(grid_for(n)), dim3(256), 0, s, wg.C32, wg.splits, n, dst);
     return hipGetLastError();
 }
 
@@ -666,29 +710,30 @@ hipError_t mlp_backward(const idm_mlp_state *st, const uint16_t *X, const float 
     const int64_t slabs = (B + slab_rows(B) - 1) / slab_rows(B);
     float *part1 = part + slabs * OFF_W1, *part2 = part + slabs * OFF_W2, *part3 = part + slabs * OFF_W3;
     double *lpart = (double *)(ws + w.lpart);
-    const int lgrid = std::min(1024, grid_for((int64_t)B * FOUT));
-    hipLaunchKernelGGL(k_mse_grad, dim3(lgrid), dim3(256), 0, s, Y, (int64_t)FOUT, U, B,
-                       IDM_MLP_OUT, FOUT, dY, (float *)(ws + w.dyf), lpart);
+    const uint16_t *W16 = st->weights_bf16;
+    // output layer: dY, the loss partials and dH2 = (dY W3^T) * [H2 > 0]
+    const int lgrid = (int)std::min<int64_t>(8192, ((int64_t)B + OG_ROWS - 1) / OG_ROWS);
+    hipLaunchKernelGGL(k_out_grad, dim3(lgrid), dim3(256), 0, s, Y, U, B, W16 + H16_W3, H2, dY,
+                       dH2, lpart);
     if (loss_out)
         hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(64), 0, s, lpart, lgrid,
                            1.0 / ((double)B * IDM_MLP_OUT), loss_out);
-    const uint16_t *W16 = st->weights_bf16;
-    // layer 3: [dW3; db3] = [H2^T; 1] dY, dH2 = (dY W3^T) * [H2 > 0]
-    e = weight_grad(H2, H, B, H, dY, FOUT, FOUT, part3, G ? G + OFF_W3 : nullptr, s);  // and db3
+    // one launch: [dW3; db3] = [H2^T; 1] dY, [dW2; db2] = [H1^T; 1] dH2 and
+    // dH1 = (dH2 W2^T) * [H1 > 0]
+    Gemm grp[3];
+    grp[0] = weight_grad(H2, H, B, H, dY, FOUT, FOUT, part3);
+    grp[1] = weight_grad(H1, H, B, H, dH2, H, H, part2);
+    grp[2] = gemm(dH2, H, 1, W16 + H16_W2, 1, H, B, H, H);
+    grp[2].mask = H1; grp[2].mask_rs = H; grp[2].C16 = dH1; grp[2].c16_rs = H;
+    e = launch_gemms(grp, 3, s);
     if (e != hipSuccess) return e;
-    Gemm g3 = gemm(dY, FOUT, 1, W16 + H16_W3, 1, FOUT, B, H, FOUT);
-    g3.mask = H2; g3.mask_rs = H; g3.C16 = dH2; g3.c16_rs = H;
-    e = launch_gemm(g3, 1, s);
-    if (e != hipSuccess) return e;
-    // layer 2: [dW2; db2] = [H1^T; 1] dH2, dH1 = (dH2 W2^T) * [H1 > 0]
-    e = weight_grad(H1, H, B, H, dH2, H, H, part2, G ? G + OFF_W2 : nullptr, s);  // and db2
-    if (e != hipSuccess) return e;
-    Gemm g2 = gemm(dH2, H, 1, W16 + H16_W2, 1, H, B, H, H);
-    g2.mask = H1; g2.mask_rs = H; g2.C16 = dH1; g2.c16_rs = H;
-    e = launch_gemm(g2, 1, s);
-    if (e != hipSuccess) return e;
-    // layer 1: [dW1; db1] = [X^T; 1] dH1
-    return weight_grad(X, FIN, B, FIN, dH1, H, H, part1, G ? G + OFF_W1 : nullptr, s);  // and db1
+    // [dW1; db1] = [X^T; 1] dH1
+    const Gemm w1 = weight_grad(X, FIN, B, FIN, dH1, H, H, part1);
+    e = launch_gemms(&w1, 1, s);
+    if (e != hipSuccess || !G) return e;
+    if ((e = sum_slabs(grp[0], G + OFF_W3, s)) != hipSuccess) return e;
+    if ((e = sum_slabs(grp[1], G + OFF_W2, s)) != hipSuccess) return e;
+    return sum_slabs(w1, G + OFF_W1, s);
 }
 
 idm_status check_state(const idm_mlp_state *st) {
@@ -701,9 +746,20 @@ idm_status check_state(const idm_mlp_state *st) {
 }  // namespace
 
 namespace idmx {
-hipError_t launch_gemm(const Gemm &g, int splits, hipStream_t s) {
-    dim3 grid((g.M + 63) / 64, (g.N + 63) / 64, splits);
-    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
+hipError_t launch_gemms(const Gemm *gs, int n, hipStream_t s) {
+    GemmGroup G;
+    memset(&G, 0, sizeof G);
+    if (n < 1 || n > MAX_GROUP) return hipErrorInvalidValue;
+    int64_t total = 0;
+    for (int p = 0; p < n; ++p) {
+        G.g[p] = gs[p];
+        G.start[p] = (int)total;
+        total += (int64_t)((gs[p].M + 63) / 64) * ((gs[p].N + 63) / 64) * gs[p].splits;
+    }
+    if (total > INT32_MAX) return hipErrorInvalidValue;
+    G.n = n;
+    G.start[n] = (int)total;
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)total), dim3(256), 0, s, G);
     return hipGetLastError();
 }
 }  // namespace idmx
