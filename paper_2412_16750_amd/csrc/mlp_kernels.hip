@@ -2,9 +2,11 @@
 // that maps an observed trajectory window to normalised IDM parameters.
 // Hand-written BF16 MFMA kernels for gfx950 (FP32 accumulate): the whole
 // forward fused into one launch (v_mfma_f32_16x16x32_bf16), backward GEMMs
-// (v_mfma_f32_16x16x16_bf16) with a ReLU-mask epilogue, deterministic
-// split-K for the weight gradients, Adam on FP32 master weights with BF16
-// copies, and the window-feature kernel.
+// (v_mfma_f32_16x16x16_bf16, up to three problems per launch) with a
+// ReLU-mask epilogue and deterministic split-K for the weight gradients, the
+// output layer's gradient on the VALU (5 nonzero columns), Adam on FP32
+// master weights with BF16 copies (summing the split-K slabs), and the
+// window-feature kernel.
 //
 // BF16 rounding points (mirrored by the CPU reference): the features X, the
 // weight copies W1..W3, the hidden activations H1, H2 and the back-propagated
