@@ -337,17 +337,19 @@ __device__ __forceinline__ void tile_to_global(const uint16_t *tile, int rows, i
 // X [B][MIN] BF16 (any alignment), W1t [MH][MIN], W2t [MH][MH], W3t [MOUT][MH]
 // (16-byte aligned), biases FP32; Y [B][MOUT] FP32; H1g, H2g [B][MH] BF16
 // (16-byte aligned) or null.
-// Three waves per SIMD: the register budget that keeps 3 work-groups per CU.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_forward(
-    const uint16_t *X, int64_t B, const uint16_t *W1t, const uint16_t *W2t, const uint16_t *W3t,
-    const float *b1, const float *b2, const float *b3, float *Y, uint16_t *H1g, uint16_t *H2g) {
+// One row tile; PD weight chunks of a hidden layer in flight ahead of its products.
+template <int PD>
+__device__ __forceinline__ void mlp_forward_tile(const uint16_t *X, int64_t B, const uint16_t *W1t,
+                                                 const uint16_t *W2t, const uint16_t *W3t,
+                                                 const float *b1, const float *b2, const float *b3,
+                                                 float *Y, uint16_t *H1g, uint16_t *H2g) {
     constexpr int NI = FT / 16, NO = FT / 64;  // m-tiles per wave: hidden layers, output layer
     __shared__ __attribute__((aligned(16))) uint16_t tile[FT * FPITCH];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63, li = lane & 15, lq = lane >> 4;
     const int64_t r0 = (int64_t)blockIdx.x * FT;
     const int rows = (int)min((int64_t)FT, B - r0);
-    bf16x8 b[FPD][4];
-    load_b_head<MIN, 4, FPD>(W1t, 64 * wave, b);
+    bf16x8 b[PD][4];
+    load_b_head<MIN, 4, PD>(W1t, 64 * wave, b);
     // stage the X rows (zero beyond the batch)
     const bool vec = ((uintptr_t)X & 15) == 0;
     for (int v = t; v < FT * (MIN / 8); v += blockDim.x) {
@@ -366,13 +368,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
     tile_barrier();
     f32x4 acc[NI][4];
-    tile_product<MIN, NI, 4, FPD>(tile, 0, W1t, 64 * wave, b, acc);
-    load_b_head<MH, 4, FPD>(W2t, 64 * wave, b);
+    tile_product<MIN, NI, 4, PD>(tile, 0, W1t, 64 * wave, b, acc);
+    load_b_head<MH, 4, PD>(W2t, 64 * wave, b);
     tile_barrier();  // every wave has read X
     hidden_out<NI>(acc, b1, 64 * wave, tile);
     tile_barrier();
     if (H1g) tile_to_global(tile, rows, r0, H1g);
-    tile_product<MH, NI, 4, FPD>(tile, 0, W2t, 64 * wave, b, acc);
+    tile_product<MH, NI, 4, PD>(tile, 0, W2t, 64 * wave, b, acc);
     // the output layer's weights (8 KB, the same for every wave): all of a
     // wave's chunks issued at once, since each feeds only NO products
     bf16x8 b3c[MH / 32][1];
@@ -391,6 +393,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             const int r = 16 * (NO * wave + i) + 4 * lq + e;
             if (r < rows) Y[(r0 + r) * MOUT + li] = y[i][0][e] + bo;
         }
+}
+
+// Many row tiles: three waves per SIMD, the register budget that keeps 3
+// work-groups per CU resident to overlap each other's latencies.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_forward(
+    const uint16_t *X, int64_t B, const uint16_t *W1t, const uint16_t *W2t, const uint16_t *W3t,
+    const float *b1, const float *b2, const float *b3, float *Y, uint16_t *H1g, uint16_t *H2g) {
+    mlp_forward_tile<FPD>(X, B, W1t, W2t, W3t, b1, b2, b3, Y, H1g, H2g);
+}
+
+// At most one work-group per CU (a training batch): nothing overlaps a
+// work-group's latencies but itself, so every chunk of a hidden layer's
+// weights is in flight at once.
+constexpr int FT_SMALL_TILES = 256;
+__global__ __launch_bounds__(256) void k_mlp_forward_small(
+    const uint16_t *X, int64_t B, const uint16_t *W1t, const uint16_t *W2t, const uint16_t *W3t,
+    const float *b1, const float *b2, const float *b3, float *Y, uint16_t *H1g, uint16_t *H2g) {
+    mlp_forward_tile<MH / 32>(X, B, W1t, W2t, W3t, b1, b2, b3, Y, H1g, H2g);
 }
 
 // Fixed-order sum of split-K partial slabs: out[i] = sum_z part[z][i].
@@ -691,8 +711,9 @@ hipError_t mlp_forward(const idm_mlp_state *st, const uint16_t *X, int64_t B, ui
     const float *P = st->params;
     const uint16_t *W16 = st->weights_bf16;
     const int64_t tiles = (B + FT - 1) / FT;
-    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)tiles), dim3(256), 0, s, X, B, W16 + T16_W1,
-                       W16 + T16_W2, W16 + T16_W3, P + OFF_B1, P + OFF_B2, P + OFF_B3, Y, H1, H2);
+    hipLaunchKernelGGL(tiles <= FT_SMALL_TILES ? k_mlp_forward_small : k_mlp_forward,
+                       dim3((unsigned)tiles), dim3(256), 0, s, X, B, W16 + T16_W1, W16 + T16_W2,
+                       W16 + T16_W3, P + OFF_B1, P + OFF_B2, P + OFF_B3, Y, H1, H2);
     return hipGetLastError();
 }
 

@@ -91,6 +91,22 @@ def test_mlp_forward_any_alignment_and_large_batch():
     assert err <= 1e-2 * max(1.0, np.abs(Yr[:, :5]).max())
 
 
+def test_mlp_forward_small_and_large_launches_agree():
+    """Batches of at most 256 row tiles take the launch that keeps every
+    weight chunk of a layer in flight; larger ones the 3-waves-per-SIMD
+    launch.  Same products in the same order: the same bits."""
+    import torch
+    from paper_2412_16750_amd.warmstart import MLP
+    net = MLP(_net(seed=8))
+    _, _, Xt, _ = _batch(20000, seed=8)
+    Y_large = net.forward(Xt)                   # 313 tiles
+    Y_small = net.forward(Xt[:4096].contiguous())  # 64 tiles
+    Y_edge = net.forward(Xt[:16384].contiguous())  # 256 tiles
+    torch.cuda.synchronize()
+    assert torch.equal(Y_large[:4096], Y_small)
+    assert torch.equal(Y_large[:16384], Y_edge)
+
+
 @pytest.mark.parametrize("B", [3000, 4096])
 def test_train_step_is_adam_on_the_gradients(B):
     """The training step sums the weight gradients' split-K slabs inside its
