@@ -331,7 +331,7 @@ idm_status idm_copy_bytes(void *dst, const void *src, size_t bytes, void *stream
 #define IDM_MLP_OUT_PAD 16
 
 typedef struct {
-    float *params;          /* FP32 master parameters (layout above), device */
+    float *params;          /* FP32 master parameters (layout above), device, 16-byte aligned */
     uint16_t *weights_bf16; /* BF16 copies of W1, W2, W3 and their transposes, device,
                                16-byte aligned (else IDM_ERR_INVALID_ARG) */
     float *adam_m, *adam_v; /* Adam moments [param_count], device (nullable for inference) */

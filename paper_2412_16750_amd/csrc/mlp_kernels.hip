@@ -26,13 +26,13 @@ namespace {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// FP32 -> BF16, round to nearest even (NaN kept quiet); a select, not a
-// branch, so a wave converting many values stays on one path.
-__device__ __forceinline__ uint16_t f2bf(float x) {
-    const uint32_t u = __float_as_uint(x);
-    const uint32_t rounded = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-    const uint32_t quiet = (u >> 16) | 0x40u;
-    return (uint16_t)((u & 0x7fffffffu) > 0x7f800000u ? quiet : rounded);
+// FP32 -> BF16, round to nearest even, NaN quiet: gfx950's
+// v_cvt_pk_bf16_f32 (one instruction converts two values).
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint16_t f2bf(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+__device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){lo, hi}, bf16x2));
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -238,6 +238,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmGroup G) {
 // D[4 (l / 16) + e][l % 16].  The k-assignment is the same for both
 // operands, so any fixed map of the 32 k of a chunk onto (group, element)
 // gives the same sum; here group q holds k = 8 q .. 8 q + 7 (16-byte reads).
+// The product is computed transposed, D = W^T-tile x act^T-tile (A = the
+// weight rows, B = the activation rows: the same register contents as for
+// act x W), so a lane's 4 results are 4 consecutive output columns of one
+// row: one 8-byte LDS store of 4 BF16 values (or 4 adjacent FP32 outputs).
 // Rounding points as in the oracle: H = bf16(relu(acc + b)), Y = acc + b in
 // FP32.
 constexpr int FT = 64;          // rows per work-group
@@ -303,24 +307,26 @@ __device__ __forceinline__ void tile_product(const uint16_t *tile, int m0, const
         for (int i = 0; i < NI; ++i)
 #pragma unroll
             for (int j = 0; j < NJ; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bc[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bc[j], a[i], acc[i][j], 0, 0, 0);
     }
 }
 
-// Hidden-layer epilogue: bf16(relu(acc + b)) into the wave's 64 columns of the tile.
+// Hidden-layer epilogue: bf16(relu(acc + b)) into the wave's 64 columns of
+// the tile; acc[i][j][e] is row 16 i + l % 16, column n0 + 16 j + 4 (l / 16) + e.
 template <int NI>
 __device__ __forceinline__ void hidden_out(const f32x4 (&acc)[NI][4], const float *bias, int n0,
                                            uint16_t *tile) {
     const int lane = threadIdx.x & 63, li = lane & 15, lq = lane >> 4;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int col = n0 + 16 * j + li;
-        const float bj = bias[col];
+        const int col = n0 + 16 * j + 4 * lq;
+        const f32x4 bj = *reinterpret_cast<const f32x4 *>(bias + col);
 #pragma unroll
-        for (int i = 0; i < NI; ++i)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                tile[(16 * i + 4 * lq + e) * FPITCH + col] = f2bf(fmaxf(acc[i][j][e] + bj, 0.0f));
+        for (int i = 0; i < NI; ++i) {
+            const uint2 h = make_uint2(f2bf2(fmaxf(acc[i][j][0] + bj[0], 0.0f), fmaxf(acc[i][j][1] + bj[1], 0.0f)),
+                                       f2bf2(fmaxf(acc[i][j][2] + bj[2], 0.0f), fmaxf(acc[i][j][3] + bj[3], 0.0f)));
+            *reinterpret_cast<uint2 *>(tile + (16 * i + li) * FPITCH + col) = h;
+        }
     }
 }
 
@@ -385,14 +391,13 @@ __device__ __forceinline__ void mlp_forward_tile(const uint16_t *X, int64_t B, c
     if (H2g) tile_to_global(tile, rows, r0, H2g);
     f32x4 y[NO][1];
     tile_product<MH, NO, 1, MH / 32>(tile, 16 * NO * wave, W3t, 0, b3c, y);
-    const float bo = b3[li];
 #pragma unroll
-    for (int i = 0; i < NO; ++i)
+    for (int i = 0; i < NO; ++i) {
+        const int r = 16 * (NO * wave + i) + li;
+        if (r < rows)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int r = 16 * (NO * wave + i) + 4 * lq + e;
-            if (r < rows) Y[(r0 + r) * MOUT + li] = y[i][0][e] + bo;
-        }
+            for (int e = 0; e < 4; ++e) Y[(r0 + r) * MOUT + 4 * lq + e] = y[i][0][e] + b3[4 * lq + e];
+    }
 }
 
 // Many row tiles: three waves per SIMD, the register budget that keeps 3
@@ -761,8 +766,8 @@ hipError_t mlp_backward(const idm_mlp_state *st, const uint16_t *X, const float 
 
 idm_status check_state(const idm_mlp_state *st) {
     if (!st || !st->params || !st->weights_bf16) return mfail(IDM_ERR_INVALID_ARG, "mlp state: null pointer");
-    if (((uintptr_t)st->weights_bf16 & 15) != 0)
-        return mfail(IDM_ERR_INVALID_ARG, "mlp state: weights_bf16 is not 16-byte aligned");
+    if (((uintptr_t)st->weights_bf16 & 15) != 0 || ((uintptr_t)st->params & 15) != 0)
+        return mfail(IDM_ERR_INVALID_ARG, "mlp state: params or weights_bf16 not 16-byte aligned");
     return IDM_OK;
 }
 
