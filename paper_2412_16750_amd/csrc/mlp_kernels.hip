@@ -568,35 +568,56 @@ __global__ __launch_bounds__(256) void k_fill_f32(float *x, int64_t n, float v) 
 
 // Window features of one vehicle from its observed positions (observation j
 // at time t_j = (obs_first + j*obs_stride)*dt), its leader's observations and
-// its initial state; row layout [n_feat_pad] BF16:
+// its initial state; row layout [IN_PAD] BF16:
 //   [0, n_obs)         (p_j - p0) / 1000 m
 //   [n_obs, 2 n_obs)   (p_j - p_{j-1}) / (t_j - t_{j-1}) / 30 m/s  (p_{-1} = p0 at t = 0)
 //   [2 n_obs, 3 n_obs) (p_h,j - p_j - length_h) / 50 m, 200 m for a lane head
 //   rest               0
-__global__ __launch_bounds__(256) void k_features(const float *target, int n_obs, int obs_first,
-                                                  int obs_stride, float dt, const double *p0,
-                                                  const float *length, const uint8_t *is_head,
-                                                  int64_t N, int n_feat_pad, uint16_t *X) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const bool head = is_head[i] != 0;
-    const double p0i = p0[i];
-    const float lh = head ? 0.0f : length[i - 1];
-    uint16_t *row = X + i * n_feat_pad;
-    double prev = p0i;
-    float tprev = 0.0f;
-    for (int j = 0; j < n_obs; ++j) {
-        const double pj = (double)target[(int64_t)j * N + i];
-        const float tj = (float)(obs_first + j * obs_stride) * dt;
-        row[j] = f2bf((float)((pj - p0i) / 1000.0));
-        row[n_obs + j] = f2bf((float)((pj - prev) / (double)(tj - tprev)) / 30.0f);
-        float gap = 200.0f;
-        if (!head) gap = (float)((double)target[(int64_t)j * N + i - 1] - pj - (double)lh);
-        row[2 * n_obs + j] = f2bf(gap / 50.0f);
-        prev = pj;
-        tprev = tj;
+//
+// 64 vehicles per work-group: each thread builds its row in LDS, then the
+// work-group writes the 64 rows out as consecutive 4-byte words (2-byte
+// elements if X is not 4-byte aligned), so the stores are coalesced.
+constexpr int FEAT_ROWS = 64;
+constexpr int FEAT_PITCH = MIN + 2;  // 81 words: the 64 threads' rows start in distinct banks
+__global__ __launch_bounds__(FEAT_ROWS) void k_features(const float *target, int n_obs,
+                                                        int obs_first, int obs_stride, float dt,
+                                                        const double *p0, const float *length,
+                                                        const uint8_t *is_head, int64_t N,
+                                                        uint16_t *X) {
+    __shared__ __attribute__((aligned(4))) uint16_t rowbuf[FEAT_ROWS * FEAT_PITCH];
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * FEAT_ROWS, i = i0 + t;
+    const int rows = (int)min((int64_t)FEAT_ROWS, N - i0);
+    uint16_t *row = rowbuf + t * FEAT_PITCH;
+    if (i < N) {
+        const bool head = is_head[i] != 0;
+        const double p0i = p0[i];
+        const float lh = head ? 0.0f : length[i - 1];
+        double prev = p0i;
+        float tprev = 0.0f;
+        for (int j = 0; j < n_obs; ++j) {
+            const double pj = (double)target[(int64_t)j * N + i];
+            const float tj = (float)(obs_first + j * obs_stride) * dt;
+            row[j] = f2bf((float)((pj - p0i) / 1000.0));
+            row[n_obs + j] = f2bf((float)((pj - prev) / (double)(tj - tprev)) / 30.0f);
+            float gap = 200.0f;
+            if (!head) gap = (float)((double)target[(int64_t)j * N + i - 1] - pj - (double)lh);
+            row[2 * n_obs + j] = f2bf(gap / 50.0f);
+            prev = pj;
+            tprev = tj;
+        }
+        for (int c = 3 * n_obs; c < MIN; ++c) row[c] = 0;
     }
-    for (int c = 3 * n_obs; c < n_feat_pad; ++c) row[c] = 0;
+    __syncthreads();
+    if (((uintptr_t)X & 3) == 0) {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(rowbuf);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(X + i0 * MIN);
+        for (int w = t; w < rows * (MIN / 2); w += FEAT_ROWS)
+            dst[w] = src[(w / (MIN / 2)) * (FEAT_PITCH / 2) + w % (MIN / 2)];
+    } else {
+        for (int e = t; e < rows * MIN; e += FEAT_ROWS)
+            X[i0 * MIN + e] = rowbuf[(e / MIN) * FEAT_PITCH + e % MIN];
+    }
 }
 
 int grid_for(int64_t n) {
@@ -829,9 +850,10 @@ idm_status idm_mlp_features(idm_plan *plan, const float *target, int32_t n_obs, 
     if (!head) return mfail(IDM_ERR_INVALID_ARG, "plan has no head flags");
     if ((int64_t)obs_first + (int64_t)(n_obs - 1) * obs_stride > idmx::plan_steps(plan))
         return mfail(IDM_ERR_INVALID_ARG, "features: last observed step beyond n_steps");
-    hipLaunchKernelGGL(k_features, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((N + FEAT_ROWS - 1) / FEAT_ROWS)), dim3(FEAT_ROWS), 0,
+                       (hipStream_t)stream,
                        target, n_obs, obs_first, obs_stride, idmx::plan_dt(plan), p0, length, head, N,
-                       FIN, X);
+                       X);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? IDM_OK : mfail(IDM_ERR_HIP, hipGetErrorString(e));
 }

@@ -103,11 +103,13 @@ def observe(plan, traj_d, p0, noise, obs_first, obs_stride, n_obs) -> torch.Tens
     return out
 
 
-def features(plan, obs: "sim.Obs", p0, length) -> torch.Tensor:
-    """Window features [N, 160] (BF16) of every vehicle."""
+def features(plan, obs: "sim.Obs", p0, length, X: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Window features [N, 160] (BF16) of every vehicle (into X if given)."""
     n = plan.n
     sim._need(obs.target, "obs.target", torch.float32, obs.n_obs * n)
-    X = torch.empty(n, MLP_IN_PAD, dtype=torch.bfloat16, device=p0.device)
+    if X is None:
+        X = torch.empty(n, MLP_IN_PAD, dtype=torch.bfloat16, device=p0.device)
+    sim._need(X, "X", torch.bfloat16, n * MLP_IN_PAD)
     check(_lib.load().idm_mlp_features(plan.handle, sim._ptr(obs.target), obs.n_obs, obs.obs_first,
                                        obs.obs_stride, sim._ptr(p0), sim._ptr(length), sim._ptr(X),
                                        sim._stream()), "idm_mlp_features")

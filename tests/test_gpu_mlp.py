@@ -189,6 +189,11 @@ def test_features_lane_loss_and_selection():
     log("features: %d of %d values differ by more than one BF16 ulp" % (bad.sum(), bad.size))
     assert not bad.any()
     assert np.mean(got == ref) > 0.99
+    # rows written through 2-byte stores when X is not 4-byte aligned: same bits
+    buf = torch.zeros(sc.n * omlp.IN_PAD + 1, dtype=torch.bfloat16, device="cuda")
+    Xo = ws.features(plan, obs, x["p0"], x["length"], X=buf[1:].view(sc.n, omlp.IN_PAD))
+    assert Xo.data_ptr() % 4 != 0
+    assert torch.equal(Xo, X)
     # per-lane observed squared error
     ll = ws.lane_loss(plan, traj, x["p0"], obs).cpu().numpy()
     P = sc.p0[None, :] + d
