@@ -32,7 +32,8 @@ def _batch(B, seed=0):
     return X, U, Xt, torch.from_numpy(U).cuda()
 
 
-@pytest.mark.parametrize("B", [4096, 777, 64, 1])
+# 20000 rows: more than 64 slabs of 256 rows, so the slabs lengthen to 320
+@pytest.mark.parametrize("B", [4096, 777, 64, 1, 20000])
 def test_mlp_forward_and_gradients_match_oracle(B):
     import torch
     from paper_2412_16750_amd.warmstart import MLP
@@ -107,7 +108,7 @@ def test_mlp_forward_small_and_large_launches_agree():
     assert torch.equal(Y_large[:16384], Y_edge)
 
 
-@pytest.mark.parametrize("B", [3000, 4096])
+@pytest.mark.parametrize("B", [3000, 4096, 20000])
 def test_train_step_is_adam_on_the_gradients(B):
     """The training step sums the weight gradients' split-K slabs inside its
     Adam kernel; the gradients entry point sums them in a kernel of its own.
