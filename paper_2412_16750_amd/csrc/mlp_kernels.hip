@@ -282,9 +282,10 @@ __device__ __forceinline__ void load_b_head(const uint16_t *Wt, int n0, bf16x8 (
         if (d < K / 32) load_b<K, NJ>(Wt, n0, d, b[d]);
 }
 
-// acc[i][j] = tile rows m0 + 16 i .. (all K) times Wt rows n0 + 16 j .. .
-// On entry b[d] holds chunk d; chunk c's products run while chunks
-// c + 1 .. c + PD are in flight.
+// Output rows m0 + 16 i .. 16 i + 15 (tile rows) times columns n0 + 16 j ..
+// (Wt rows), over all K: lane l's acc[i][j][e] is row m0 + 16 i + l % 16,
+// column n0 + 16 j + 4 (l / 16) + e.  On entry b[d] holds chunk d; chunk
+// c's products run while chunks c + 1 .. c + PD are in flight.
 template <int K, int NI, int NJ, int PD>
 __device__ __forceinline__ void tile_product(const uint16_t *tile, int m0, const uint16_t *Wt,
                                              int n0, bf16x8 (&b)[PD][NJ], f32x4 (&acc)[NI][NJ]) {
