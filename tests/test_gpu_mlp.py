@@ -165,6 +165,41 @@ def test_mlp_training_reduces_loss():
                                   w1.reshape(omlp.IN_PAD, omlp.HID).T)
 
 
+def test_bf16_copies_round_like_torch_at_special_values():
+    """The BF16 weight copies (hardware conversion) equal torch's float32 ->
+    bfloat16 rounding: halfway cases to even, values next to them, subnormals,
+    signed zeros, the largest finite value, infinities; NaN stays NaN."""
+    import torch
+    from paper_2412_16750_amd.warmstart import MLP
+    n1 = omlp.IN_PAD * omlp.HID
+    theta = _net(seed=2)
+    one = np.float32(1.0)
+    ulp = np.float32(2.0 ** -7)
+    special = np.array([
+        one + ulp / 2,                      # tie, rounds down to even (1.0)
+        one + 3 * ulp / 2,                  # tie, rounds up to even
+        np.nextafter(one + ulp / 2, np.float32(2)),   # just above the tie
+        np.nextafter(one + ulp / 2, np.float32(0)),   # just below the tie
+        -(one + 3 * ulp / 2),
+        np.float32(1e-40), np.float32(-3e-39), np.float32(1.5e-45),  # subnormals
+        np.float32(0.0), np.float32(-0.0),
+        np.finfo(np.float32).max,           # rounds up to infinity
+        np.float32(np.inf), np.float32(-np.inf),
+        np.float32(3.3895314e38),           # the largest finite BF16 value
+        np.float32(np.nan),
+    ], dtype=np.float32)
+    theta[:special.size] = special
+    net = MLP(theta)
+    torch.cuda.synchronize()
+    got = net.w16[:n1].cpu()
+    want = torch.from_numpy(theta[:n1].copy()).to(torch.bfloat16)
+    nan = torch.isnan(want.float())
+    assert torch.equal(torch.isnan(got.float()), nan)
+    gb, wb = got.view(torch.int16)[~nan], want.view(torch.int16)[~nan]
+    bad = (gb != wb).nonzero().flatten()[:5].tolist()
+    assert not bad, [(float(theta[:n1][~nan.numpy()][j]), int(gb[j]), int(wb[j])) for j in bad]
+
+
 def test_features_lane_loss_and_selection():
     import torch
     from paper_2412_16750_amd import sim
