@@ -318,3 +318,39 @@ def test_random_layouts_keep_every_invariant(L, seed):
 def scenarios_offsets(sizes):
     import scenarios
     return scenarios.offsets_from_sizes(np.asarray(sizes, dtype=np.int64))
+
+
+def test_mlp_entry_points_validate_before_touching_the_device(L):
+    """The warm-start network's entry points check their pointers, sizes and
+    alignments on the host and return IDM_ERR_INVALID_ARG (nothing launched)."""
+    from paper_2412_16750_amd._lib import IdmMlpState
+    assert L.idm_mlp_param_count() == 160 * 256 + 256 + 256 * 256 + 256 + 256 * 16 + 16
+    # plain copies of W1, W2, W3 and their transposes
+    assert L.idm_mlp_weight_bf16_count() == 2 * (160 * 256 + 256 * 256 + 256 * 16)
+    assert L.idm_mlp_workspace_bytes(0) == 0
+    assert L.idm_mlp_workspace_bytes(4096) > 0
+
+    def state(params, w16, m=0, v=0):
+        st = IdmMlpState()
+        st.params, st.weights_bf16, st.adam_m, st.adam_v = params, w16, m, v
+        st.lr, st.beta1, st.beta2, st.eps = 1e-3, 0.9, 0.999, 1e-8
+        return st
+
+    good = state(0x10000, 0x20000, 0x30000, 0x40000)
+    X, U, Y, ws = 0x50000, 0x60000, 0x70000, 0x80000
+    cases = [
+        (L.idm_mlp_forward, (ctypes.byref(state(0, 0x20000)), X, 1, Y, None, None)),
+        (L.idm_mlp_forward, (ctypes.byref(state(0x10000, 0x20002)), X, 1, Y, None, None)),
+        (L.idm_mlp_forward, (ctypes.byref(state(0x10004, 0x20000)), X, 1, Y, None, None)),
+        (L.idm_mlp_forward, (ctypes.byref(good), X, 0, Y, None, None)),
+        (L.idm_mlp_forward, (ctypes.byref(good), None, 1, Y, None, None)),
+        (L.idm_mlp_gradients, (ctypes.byref(good), X, U, 1, 0x90000, None, ws + 8, None)),
+        (L.idm_mlp_gradients, (ctypes.byref(good), X, U, 1, None, None, ws, None)),
+        (L.idm_mlp_train_step, (ctypes.byref(state(0x10000, 0x20000)), X, U, 1, 1, None, ws, None)),
+        (L.idm_mlp_train_step, (ctypes.byref(good), X, U, 1, 0, None, ws, None)),
+        (L.idm_mlp_train_step, (ctypes.byref(good), X, U, 1, 1, None, ws + 4, None)),
+        (L.idm_mlp_train_step, (ctypes.byref(good), X, U, (1 << 30) + 1, 1, None, ws, None)),
+    ]
+    for fn, args in cases:
+        assert fn(*args) == -1, (fn.__name__, args)
+        assert len(L.idm_last_error()) > 0
