@@ -43,8 +43,8 @@ PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
 # WRITE_SIZE (scaled by the copy-kernel calibration, 2.000 and 1.000), valid
 # only for the kernel source they were taken with (sha256 of idm_kernels.hip
 # followed by idm_device.h).
-TRAFFIC_BWD_BYTES = 1.1979e9
-TRAFFIC_KERNEL_SHA256 = "b526322a98904b69bd87e6166c63bbb10c0a6e6cf40b7662553cc58e0d352852"
+TRAFFIC_BWD_BYTES = 1.1672e9
+TRAFFIC_KERNEL_SHA256 = "5413eabd14451bac2503bc4682d8607560fdc8971c561f13ded8f733592c1c44"
 
 
 # Warm-start network training: Adam over 1M pairs, batch 4096, learning rate
