@@ -43,8 +43,8 @@ PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
 # WRITE_SIZE (scaled by the copy-kernel calibration, 2.000 and 1.000), valid
 # only for the kernel source they were taken with (sha256 of idm_kernels.hip
 # followed by idm_device.h).
-TRAFFIC_BWD_BYTES = 1.1672e9
-TRAFFIC_KERNEL_SHA256 = "5413eabd14451bac2503bc4682d8607560fdc8971c561f13ded8f733592c1c44"
+TRAFFIC_BWD_BYTES = 1.1654e+09
+TRAFFIC_KERNEL_SHA256 = "663f54cd62894545f999e0cc70f8588c86e04864cd7c848336ba65adeb36149c"
 
 
 # Warm-start network training: Adam over 1M pairs, batch 4096, learning rate

@@ -146,11 +146,12 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // Cache policy of the streams touched once: non-temporal (the `nt` bit of
 // the gfx950 buffer instructions) for the forward's trajectory stores and the
-// backward's per-step upstream loads (targets, dense upstream gradients).
-// Neither is read again by the kernel that touches it, so streaming them
-// keeps L2 for the checkpoints and parameters: on the 2M-vehicle workload,
-// forward + backward 1.128 -> 1.098 ms with the stores alone and -> 1.070 ms
-// with the loads too (same-box A/Bs).
+// backward's per-step upstream loads (targets, dense upstream gradients);
+// the checkpoints, written by the forward and read once by the backward, are
+// non-temporal too.  Streaming them keeps L2 for the parameters and the
+// exchange: on the 2M-vehicle workload, forward + backward 1.128 -> 1.098 ms
+// with the trajectory stores, -> 1.070 ms with the upstream loads and ->
+// 1.060 ms with the checkpoints (same-box A/Bs).
 constexpr int kStreamNT = 2;
 
 struct ExtRs {
@@ -300,8 +301,8 @@ __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf
                 for (int r = 0; r < R; ++r) {
                     const int32_t g = q[r].g;
                     if (g >= 0) {
-                        A.ckpt[crow + g] = d[r];
-                        A.ckpt[crow + N + g] = v[r];
+                        __builtin_nontemporal_store(d[r], &A.ckpt[crow + g]);
+                        __builtin_nontemporal_store(v[r], &A.ckpt[crow + N + g]);
                     }
                 }
             }
@@ -525,8 +526,8 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
             const double p0 = q[r].g >= 0 ? A.p0[gl] : 0.0;
             p0h[r] = (float)p0;
             p0l[r] = (float)(p0 - (double)p0h[r]);
-            ckd[r] = nblk > 0 ? A.ckpt[crow + gl] : 0.0f;
-            ckv[r] = nblk > 0 ? A.ckpt[crow + N + gl] : 0.0f;
+            ckd[r] = nblk > 0 ? __builtin_nontemporal_load(&A.ckpt[crow + gl]) : 0.0f;
+            ckv[r] = nblk > 0 ? __builtin_nontemporal_load(&A.ckpt[crow + N + gl]) : 0.0f;
             ld[r] = 0.0f;
             lv[r] = 0.0f;
             gp0[r] = 0.0f;
@@ -644,8 +645,8 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const int32_t gl = q[r].g > 0 ? q[r].g : 0;
-                        ckd[r] = A.ckpt[crow + gl];
-                        ckv[r] = A.ckpt[crow + N + gl];
+                        ckd[r] = __builtin_nontemporal_load(&A.ckpt[crow + gl]);
+                        ckv[r] = __builtin_nontemporal_load(&A.ckpt[crow + N + gl]);
                     }
                 }
                 // reverse sweep over the sub-block; its states come from the
