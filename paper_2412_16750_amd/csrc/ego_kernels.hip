@@ -223,7 +223,11 @@ __global__ __launch_bounds__(EGO_THREADS) void k_ego_backward(EgoArgs A) {
 
 // Adam (Kingma & Ba) on the physical parameters, projected onto their boxes,
 // and on the unconstrained per-step gap and speed difference; learning rate
-// linear from lr0 to lr1 over lr_steps.
+// linear from lr0 to lr1 over lr_steps.  The per-step gradients and the
+// moments are touched once per fit step and dwarf the caches, so they stream
+// non-temporally (the reconstruction fit step 1.17 -> 1.11 ms, the filtering
+// one 1.38 -> 1.25 ms in a same-box A/B); the variables themselves, read again
+// by the next forward, keep the default policy.
 __global__ __launch_bounds__(256) void k_ego_adam(EgoAdamArgs A) {
     const int64_t n5 = 5 * A.n, total = n5 + 2 * A.sn;
     const int32_t t = *A.step;
@@ -239,15 +243,15 @@ __global__ __launch_bounds__(256) void k_ego_adam(EgoAdamArgs A) {
             g = (float)A.g_prm[idx];
         } else if (idx < n5 + A.sn) {
             x = A.gap[idx - n5];
-            g = A.g_gap[idx - n5];
+            g = __builtin_nontemporal_load(&A.g_gap[idx - n5]);
         } else {
             x = A.dv[idx - n5 - A.sn];
-            g = A.g_dv[idx - n5 - A.sn];
+            g = __builtin_nontemporal_load(&A.g_dv[idx - n5 - A.sn]);
         }
-        const float m = A.beta1 * A.m[idx] + (1.0f - A.beta1) * g;
-        const float v = A.beta2 * A.v[idx] + (1.0f - A.beta2) * g * g;
-        A.m[idx] = m;
-        A.v[idx] = v;
+        const float m = A.beta1 * __builtin_nontemporal_load(&A.m[idx]) + (1.0f - A.beta1) * g;
+        const float v = A.beta2 * __builtin_nontemporal_load(&A.v[idx]) + (1.0f - A.beta2) * g * g;
+        __builtin_nontemporal_store(m, &A.m[idx]);
+        __builtin_nontemporal_store(v, &A.v[idx]);
         x -= lr * (m / bc1) / (sqrtf(v / bc2) + A.eps);
         if (idx < n5) {
             const int p = (int)(idx / A.n);
