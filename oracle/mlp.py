@@ -73,28 +73,30 @@ def loss_and_grad(theta, X, U, mirror: bool = True):
 
 def features(target, obs_first: int, obs_stride: int, dt: float, p0, length, lane_offsets):
     """Window features [N, IN_PAD] (values before BF16 rounding, FP64), from the
-    observed absolute positions target [n_obs, N]: per observation j
-      (p_j - p0) / 1000, (p_j - p_{j-1}) / (t_j - t_{j-1}) / 30 with p_{-1} = p0 at t = 0,
-      (p_{h,j} - p_j - length_h) / 50, 200 / 50 for a lane head,
-    where observation j is at t_j = (obs_first + j obs_stride) dt (FP32 times,
-    as the kernel forms them)."""
-    target = np.asarray(target, dtype=np.float32).astype(np.float64)
+    observed absolute positions target [n_obs, N]: per observation j at time
+    t_j = (obs_first + j obs_stride) dt
+      (p_j - p0) / 1000,
+      (p_j - p_{j-1}) / (t_j - t_{j-1}) / 30 with p_{-1} = p0 at t_{-1} = 0,
+      (p_{h,j} - p_j - length_h) / 50 for the leader h (the vehicle ahead in
+      the lane), 200 / 50 for a lane head,
+    laid out as [offsets of all observations | speeds | gaps | zero padding].
+    Plain loops over vehicles and observations in FP64."""
+    target = np.asarray(target, dtype=np.float64)
     n_obs, N = target.shape
-    head = np.zeros(N, dtype=bool)
-    head[np.asarray(lane_offsets[:-1])[np.diff(lane_offsets) > 0]] = True
-    t = (np.arange(n_obs, dtype=np.float32) * np.float32(obs_stride) + np.float32(obs_first)) \
-        * np.float32(dt)
-    F = np.zeros((N, IN_PAD))
     p0 = np.asarray(p0, dtype=np.float64)
-    prev, tprev = p0.copy(), np.float32(0.0)
-    for j in range(n_obs):
-        pj = target[j]
-        F[:, j] = (pj - p0) / 1000.0
-        F[:, n_obs + j] = (pj - prev) / np.float64(np.float32(t[j] - tprev)) / 30.0
-        gap = np.full(N, 200.0)
-        lead = np.roll(pj, 1)
-        lh = np.roll(np.asarray(length, dtype=np.float64), 1)
-        gap[~head] = (lead - pj - lh)[~head]
-        F[:, 2 * n_obs + j] = gap / 50.0
-        prev, tprev = pj, t[j]
+    length = np.asarray(length, dtype=np.float64)
+    lane_offsets = np.asarray(lane_offsets)
+    F = np.zeros((N, IN_PAD))
+    for lane in range(len(lane_offsets) - 1):
+        for i in range(int(lane_offsets[lane]), int(lane_offsets[lane + 1])):
+            head = i == int(lane_offsets[lane])
+            prev, tprev = p0[i], 0.0
+            for j in range(n_obs):
+                tj = (obs_first + j * obs_stride) * float(dt)
+                pj = target[j, i]
+                F[i, j] = (pj - p0[i]) / 1000.0
+                F[i, n_obs + j] = (pj - prev) / (tj - tprev) / 30.0
+                gap = 200.0 if head else target[j, i - 1] - pj - length[i - 1]
+                F[i, 2 * n_obs + j] = gap / 50.0
+                prev, tprev = pj, tj
     return F

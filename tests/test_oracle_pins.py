@@ -510,3 +510,36 @@ def test_mlp_bf16_mirror_is_close_to_fp64():
     Lb, gb = mlp.loss_and_grad(theta, X, U, mirror=False)
     assert abs(La - Lb) < 2e-2 * Lb
     assert np.linalg.norm(ga - gb) < 5e-2 * np.linalg.norm(gb)
+
+
+def test_window_features_hand_computed():
+    """The warm-start window (per observation: offset from p0 / 1000 m,
+    finite-difference speed / 30 m/s from p0 at t = 0, gap to the observed
+    leader / 50 m with 200 m for a lane head) on a case small enough to work
+    out by hand: lane 0 = vehicles 0 (head) and 1, lane 1 = vehicle 2 (head),
+    an empty lane between them, observations at steps 5, 15, 25 of 0.2 s
+    (t = 1, 3, 5 s: a first interval of 1 s and then 2 s, so the time of the
+    first observation and the stride are told apart).  Vehicle 1's leader is 4 m
+    long and vehicle 1 itself 5 m, so using the follower's own length, the
+    follower as leader or a sign flip changes a gap value."""
+    from oracle import mlp
+    tgt = np.array([[110.0, 88.0, 30.0],
+                    [125.0, 101.0, 60.0],
+                    [145.0, 118.0, 90.0]])
+    p0 = np.array([100.0, 80.0, 0.0])
+    length = np.array([4.0, 5.0, 6.0])
+    F = mlp.features(tgt, 5, 10, 0.2, p0, length, np.array([0, 2, 2, 3]))
+    expect = np.zeros((3, mlp.IN_PAD))
+    # offsets (p_j - p0) / 1000
+    expect[0, 0:3] = [10 / 1000, 25 / 1000, 45 / 1000]
+    expect[1, 0:3] = [8 / 1000, 21 / 1000, 38 / 1000]
+    expect[2, 0:3] = [30 / 1000, 60 / 1000, 90 / 1000]
+    # speeds: (110 - 100) / 1 s, (125 - 110) / 2 s, (145 - 125) / 2 s, all / 30
+    expect[0, 3:6] = [10 / 30, 7.5 / 30, 10 / 30]
+    expect[1, 3:6] = [8 / 30, 6.5 / 30, 8.5 / 30]
+    expect[2, 3:6] = [30 / 30, 15 / 30, 15 / 30]
+    # gaps: heads 200 / 50; vehicle 1: 110 - 88 - 4, 125 - 101 - 4, 145 - 118 - 4
+    expect[0, 6:9] = [4.0, 4.0, 4.0]
+    expect[1, 6:9] = [18 / 50, 20 / 50, 23 / 50]
+    expect[2, 6:9] = [4.0, 4.0, 4.0]
+    np.testing.assert_allclose(F, expect, rtol=1e-15, atol=0)
