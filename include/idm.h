@@ -131,7 +131,8 @@ idm_status idm_plan_create(const idm_problem *problem, const idm_tuning *tuning,
 idm_status idm_plan_destroy(idm_plan *plan);
 
 /* Bytes of device workspace the caller must pass to the compute calls:
- * checkpoints ceil(S/K) * 2 * N * 4 B, per-bundle loss partials, the FP64
+ * checkpoints ceil(S/K) * 2 * N * 4 B, per-bundle loss partials and
+ * diagnostic counts (see idm_plan_diagnostics), the FP64
  * gradient buffer used by idm_fit_step and, with lanes longer than a bundle,
  * (2 S + 1) * 8 B per piece boundary.  256-byte aligned.  With piece
  * boundaries, idm_sim_forward needs the workspace too. */
@@ -188,6 +189,24 @@ idm_status idm_problem_bundles(const idm_problem *problem, const idm_tuning *tun
 idm_status idm_sim_forward(idm_plan *plan, const idm_params *prm, const double *p0,
                            const float *v_init, float *traj_d, float *traj_v, void *workspace,
                            void *stream);
+
+/* Runtime anomalies of the most recent forward pass that wrote `workspace`
+ * for this plan (idm_sim_forward with a workspace, idm_fit_step,
+ * idm_fit_run, idm_step_graph_launch).  The gap that enters (s* / gap)^2
+ * (Sec. III-A, Eq. 2) is max(gap, gap_floor) so that the interaction term
+ * stays finite when vehicles touch or overlap; the forward counts how often
+ * that floor was active.  counts_out (DEVICE int64[2]) receives
+ *   [0] the number of (vehicle, step) evaluations with gap <= gap_floor
+ *       (a lane head never counts: it drives on a free road),
+ *   [1] the number of vehicles whose state (displacement or speed) was not
+ *       finite at some step (a non-finite speed makes every later
+ *       displacement non-finite, so the final state decides).
+ * The forward writes per-bundle counts into the workspace with plain stores;
+ * this call sums them in a fixed order (one small kernel, asynchronous on
+ * `stream`, graph-capturable).  A workspace no forward has written gives
+ * meaningless counts; a forward called with a NULL workspace writes none. */
+idm_status idm_plan_diagnostics(idm_plan *plan, const void *workspace, int64_t *counts_out,
+                                void *stream);
 
 /* Reverse-mode gradient of a scalar loss L with respect to the five
  * parameters and the initial state (the paper differentiates the same

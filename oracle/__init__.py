@@ -55,6 +55,8 @@ def lib():
         L.oracle_forward.argtypes = common + [pd, pd, pd, pd, pd]
         L.oracle_adjoint.restype = ctypes.c_int
         L.oracle_adjoint.argtypes = common + [pd, pd, pd, pd, pd, pd, pd]
+        L.oracle_branch_terms.restype = ctypes.c_int
+        L.oracle_branch_terms.argtypes = common + [pd, pd, pd, pd]
         L.oracle_tangent.restype = ctypes.c_int
         L.oracle_tangent.argtypes = common + [pd, pd, pd, pd, pd, pd, pd]
         L.oracle_mse.restype = ctypes.c_double
@@ -136,6 +138,19 @@ def adjoint(pb: Problem, P, V, gP, gV=None):
     if rc != 0:
         raise ValueError("oracle_adjoint: invalid arguments")
     return g, gp0, gv0
+
+
+def branch_terms(pb: Problem, P, V):
+    """Per step k < S and vehicle: (AH, GAP) = the IDM acceleration of Eq. 2
+    before the Sec. III-C bound / the speed clamp, and the raw gap to the
+    leader (+inf for a lane head); [S, N] each."""
+    S, n = pb.n_steps, pb.n
+    AH = np.empty((S, n), dtype=np.float64)
+    GAP = np.empty((S, n), dtype=np.float64)
+    rc = lib().oracle_branch_terms(*pb._head(), _p(_d(P)), _p(_d(V)), _p(AH), _p(GAP))
+    if rc != 0:
+        raise ValueError("oracle_branch_terms: invalid arguments")
+    return AH, GAP
 
 
 def tangent(pb: Problem, P, V, dprm, dp0, dv0):

@@ -75,6 +75,8 @@ typedef struct {
     double d_p, d_v, d_ph, d_vh;
     double d_prm[5]; /* v0, T, a, b, s0 */
     int floor_active;
+    double ahat;     /* Eq. 2 before the Sec. III-C bound / the speed clamp */
+    double gap;      /* raw bumper-to-bumper gap; +inf without a leader */
 } local_t;
 
 static local_t idm_local(const cfg_t *c, int has_leader, double p, double v, double ph,
@@ -89,6 +91,7 @@ static local_t idm_local(const cfg_t *c, int has_leader, double p, double v, dou
     double xd = pow(fabs(x), c->delta);
     double dxd_dx = (c->delta == 0.0) ? 0.0 : c->delta * pow(fabs(x), c->delta - 1.0) * (x < 0 ? -1.0 : 1.0);
 
+    r.gap = INFINITY;
     double inter = 0.0;              /* (s* / gap)^2 */
     double dI_ds = 0.0, dI_dgap = 0.0; /* partials of inter w.r.t. s_opt and raw gap */
     double ds_dv = 0.0, ds_dvh = 0.0, ds_dT = 0.0, ds_da = 0.0, ds_db = 0.0, ds_ds0 = 0.0;
@@ -96,6 +99,7 @@ static local_t idm_local(const cfg_t *c, int has_leader, double p, double v, dou
         /* Sec. III-A: gap and speed difference */
         double gap = ph - p - len_h;
         double dv = v - vh;
+        r.gap = gap;
         double sg = gap > c->gap_floor ? gap : c->gap_floor;
         r.floor_active = !(gap > c->gap_floor);
         /* Eq. 1 */
@@ -123,6 +127,7 @@ static local_t idm_local(const cfg_t *c, int has_leader, double p, double v, dou
 
     /* Eq. 2 */
     double ahat = a * (1.0 - xd - inter);
+    r.ahat = ahat;
     /* partials of ahat */
     double h_v = a * (-dxd_dx / v0 - dI_ds * ds_dv);
     double h_vh = -a * dI_ds * ds_dvh;
@@ -239,6 +244,39 @@ long oracle_forward(int mode, double dt, double delta, double a_min, double gap_
     }
     free(acc);
     return floor_hits;
+}
+
+/*
+ * Test helper: for every step k < n_steps and vehicle i of a forward
+ * trajectory P, V, the quantities that decide the branches of the bounds:
+ * AH = the IDM acceleration of Eq. 2 before the Sec. III-C bound or the speed
+ * clamp, GAP = the raw bumper-to-bumper gap to the leader (+inf for a lane
+ * head).  Both [n_steps * n].  A test uses them to tell how far each
+ * evaluation is from a kink (a_lb switching branch, the clamp, the gap floor).
+ */
+int oracle_branch_terms(int mode, double dt, double delta, double a_min, double gap_floor,
+                        int n, int n_lanes, const int *lane_off, int n_steps,
+                        const double *v0, const double *T, const double *a, const double *b,
+                        const double *s0, const double *len, const double *P, const double *V,
+                        double *AH, double *GAP)
+{
+    cfg_t c = {mode, dt, delta, a_min, gap_floor};
+    if (check_common(&c, n, n_lanes, lane_off, n_steps)) return -1;
+    for (int l = 0; l < n_lanes; ++l) {
+        int lo = lane_off[l], hi = lane_off[l + 1];
+        for (int k = 0; k < n_steps; ++k) {
+            const double *Pk = P + (size_t)k * n, *Vk = V + (size_t)k * n;
+            for (int i = lo; i < hi; ++i) {
+                int has = i > lo;
+                int h = has ? i - 1 : i;
+                local_t r = idm_local(&c, has, Pk[i], Vk[i], Pk[h], Vk[h], len[h], v0[i], T[i],
+                                      a[i], b[i], s0[i], 0);
+                AH[(size_t)k * n + i] = r.ahat;
+                GAP[(size_t)k * n + i] = r.gap;
+            }
+        }
+    }
+    return 0;
 }
 
 /*

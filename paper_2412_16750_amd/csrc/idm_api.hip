@@ -123,11 +123,16 @@ int64_t count_boundaries(const std::vector<int32_t> &offsets, int L, int64_t cap
 }
 
 // Workspace layout: [loss partials: one double per bundle (at most one per
-// lane piece)][fit: 7N doubles][checkpoints][boundary states: n_bnd x (S+1)
-// float2][boundary adjoint contributions: n_bnd x S float2]
+// lane piece)][forward diagnostics: two uint64 per bundle][fit: 7N doubles]
+// [checkpoints][boundary states: n_bnd x (S+1) float2][boundary adjoint
+// contributions: n_bnd x S float2]
 size_t ws_loss_off(const idm_plan *) { return 0; }
-size_t ws_fit_off(const idm_plan *p, int64_t nbnd) {
+size_t ws_diag_off(const idm_plan *p, int64_t nbnd) {
     return align_up(sizeof(double) * ((size_t)p->pb.n_lanes + (size_t)nbnd));
+}
+size_t ws_fit_off(const idm_plan *p, int64_t nbnd) {
+    return ws_diag_off(p, nbnd) +
+           align_up(2 * sizeof(uint64_t) * ((size_t)p->pb.n_lanes + (size_t)nbnd));
 }
 size_t ws_ckpt_off(const idm_plan *p, int64_t nbnd) {
     return ws_fit_off(p, nbnd) + align_up(sizeof(double) * 7 * (size_t)p->pb.n_vehicles);
@@ -147,6 +152,7 @@ size_t ws_total(const idm_plan *p, int K, int64_t nbnd) {
            align_up((size_t)nbnd * (size_t)p->pb.n_steps * 2 * sizeof(float));
 }
 size_t ws_fit_off(const idm_plan *p) { return ws_fit_off(p, p->n_bnd); }
+size_t ws_diag_off(const idm_plan *p) { return ws_diag_off(p, p->n_bnd); }
 size_t ws_ckpt_off(const idm_plan *p) { return ws_ckpt_off(p, p->n_bnd); }
 
 void drop_graphs(idm_plan *p) {
@@ -488,9 +494,10 @@ int grid_of(const idm_plan *p) { return grid_of(p, p->n_bundles); }
 
 int32_t n_levels(const idm_plan *p) { return (int32_t)p->level_start.size() - 1; }
 
-// Launch level `lv`: its bundle tables (and the first of its loss partials);
-// returns its bundle count.
-int32_t level_args(const idm_plan *p, int32_t lv, SimArgs &a, double *loss_base) {
+// Launch level `lv`: its bundle tables (and the first of its loss partials
+// or diagnostic counts); returns its bundle count.
+int32_t level_args(const idm_plan *p, int32_t lv, SimArgs &a, double *loss_base,
+                   uint64_t *diag_base = nullptr) {
     const int32_t b0 = p->level_start[lv], b1 = p->level_start[lv + 1];
     const int64_t cap = (int64_t)p->sh.threads * p->sh.per_thread;
     a.slot_gidx = p->d_gidx + b0 * cap;
@@ -501,6 +508,7 @@ int32_t level_args(const idm_plan *p, int32_t lv, SimArgs &a, double *loss_base)
         a.bnd_out = p->d_bnd + p->n_bundles + b0;
     }
     if (loss_base) a.loss_part = loss_base + b0;
+    if (diag_base) a.diag = diag_base + 2 * (int64_t)b0;
     return b1 - b0;
 }
 
@@ -530,9 +538,10 @@ idm_status run_forward(idm_plan *p, const idm_params *prm, const double *p0, con
     }
     KernelFn fn = forward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, p->n_bnd > 0);
     if (!fn) return fail(IDM_ERR_UNSUPPORTED, "no forward kernel for this shape");
+    uint64_t *diag = ws ? (uint64_t *)((char *)ws + ws_diag_off(p)) : nullptr;
     // pieces of long lanes: level l reads the boundary states level l-1 wrote
     for (int32_t lv = 0; lv < n_levels(p); ++lv) {
-        const int32_t nb = level_args(p, lv, a, nullptr);
+        const int32_t nb = level_args(p, lv, a, nullptr, diag);
         if (nb == 0) continue;
         hipError_t e = launch_sim(fn, grid_of(p, nb), p->sh.threads, a, s);
         if (e != hipSuccess) return hip_fail(e, "forward launch");
@@ -913,6 +922,16 @@ idm_status idm_sim_forward(idm_plan *p, const idm_params *prm, const double *p0,
     if (r != IDM_OK) return r;
     if (!p0 || !v_init) return fail(IDM_ERR_INVALID_ARG, "p0 / v_init null");
     return run_forward(p, prm, p0, v_init, traj_d, traj_v, ws, (hipStream_t)stream);
+}
+
+idm_status idm_plan_diagnostics(idm_plan *p, const void *ws, int64_t *counts_out, void *stream) {
+    if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
+    if (!ws) return fail(IDM_ERR_WORKSPACE, "workspace is null");
+    if (!counts_out) return fail(IDM_ERR_INVALID_ARG, "counts_out is null");
+    hipError_t e = launch_diag_finalize((const uint64_t *)((const char *)ws + ws_diag_off(p)),
+                                        p->n_bundles, counts_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "diagnostics launch");
+    return IDM_OK;
 }
 
 idm_status idm_sim_backward(idm_plan *p, const idm_params *prm, const double *p0,

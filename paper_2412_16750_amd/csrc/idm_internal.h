@@ -49,6 +49,11 @@ struct SimArgs {
     double *g_p0, *g_v0;      // [N]
     double *loss_part;        // [n_bundles]
 
+    // forward diagnostics (nullable): per bundle, the number of (vehicle,
+    // step) evaluations whose gap was at or below gap_floor, and the number
+    // of vehicles whose final state is not finite
+    uint64_t *diag;           // [n_bundles][2]
+
     // pieces of lanes longer than a bundle (null when there are none).  A
     // bundle with bnd_in[b] = j >= 0 starts with a piece whose leader is the
     // last vehicle of the previous piece: that leader's state at step k is
@@ -123,6 +128,7 @@ KernelFn backward_kernel(int mode, int per_thread, int threads, int KB, int K, b
 hipError_t launch_sim(KernelFn fn, int grid, int threads, const SimArgs &a, hipStream_t s);
 hipError_t launch_loss_finalize(const double *part, int32_t n_part, double scale, double *out,
                                 hipStream_t s);
+hipError_t launch_diag_finalize(const uint64_t *part, int32_t n_part, int64_t *out, hipStream_t s);
 hipError_t launch_fit_finalize(const double *part, int32_t n_part, double scale,
                                int32_t *step, double *hist, int32_t hist_len, hipStream_t s);
 hipError_t launch_adam(const AdamArgs &a, hipStream_t s);

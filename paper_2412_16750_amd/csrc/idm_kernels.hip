@@ -202,6 +202,7 @@ __device__ __forceinline__ void lead_pipe_step(const ExtRs &xr, LeadPipe &lp, in
 template <int MODE, int R, int NT, bool CH>
 __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf)[64]) {
     __shared__ float2 sbuf[2][NT];
+    __shared__ uint64_t dred[2][NT / 64];  // per-wave diagnostic counts
     const int t = threadIdx.x;
     const int tl = lead_thread(t);
     const int64_t N = A.n;
@@ -234,6 +235,7 @@ __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf
             }
         }
         lds_barrier();
+        uint64_t n_floor = 0;  // this wave's gap-floor evaluations
         int to_ckpt = A.K;  // steps until the next checkpoint
         // trajectory rows through raw buffer resources: the row address is
         // advanced by scalar adds, each lane stores at its loop-invariant byte
@@ -270,7 +272,13 @@ __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf
                 // interaction term
                 float dh = r ? d[r - 1] : L.x;
                 float vh = r ? v[r - 1] : L.y;
-                acc[r] = accel<MODE>(q[r], d[r], v[r], dh, vh, A.inv_dt, A.a_min, A.gap_floor);
+                // the lane model's gap (as in accel), counted when the floor
+                // is active: one compare per vehicle-step, the wave's count
+                // kept in scalar registers
+                const float gap = q[r].g0 + (dh - d[r]);
+                n_floor += (uint64_t)__builtin_popcountll(__ballot(!(gap > A.gap_floor)));
+                acc[r] = accel_gd<MODE>(q[r], v[r], gap, v[r] - vh, A.inv_dt, A.a_min,
+                                        A.gap_floor);
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) euler<MODE>(d[r], v[r], acc[r], A.dt);
@@ -314,6 +322,30 @@ __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf
             fstep(k + 1, std::integral_constant<int, 1>{});
         }
         if (k < S) fstep(k, std::integral_constant<int, 0>{});
+        if (A.diag) {
+            // A non-finite speed at any step makes every later displacement
+            // non-finite (d' = d + dt v), so the final state shows whether the
+            // vehicle's state was ever non-finite.
+            uint64_t n_bad = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                n_bad += (uint64_t)__builtin_popcountll(
+                    __ballot(q[r].g >= 0 && !(isfinite(d[r]) && isfinite(v[r]))));
+            if ((t & 63) == 0) {
+                dred[0][t >> 6] = n_floor;
+                dred[1][t >> 6] = n_bad;
+            }
+            lds_barrier();
+            if (t == 0) {
+                uint64_t s0 = 0, s1 = 0;
+                for (int w = 0; w < NT / 64; ++w) {
+                    s0 += dred[0][w];
+                    s1 += dred[1][w];
+                }
+                A.diag[2 * (int64_t)bidx] = s0;
+                A.diag[2 * (int64_t)bidx + 1] = s1;
+            }
+        }
     }
 }
 
@@ -849,6 +881,20 @@ __global__ __launch_bounds__(256) void k_loss_finalize(const double *part, int32
     if (threadIdx.x == 0) *out = tot * scale;
 }
 
+// Fixed-order sum of the per-bundle diagnostic counts [n][2] (one thread:
+// the counts are small and integer sums need no tree).
+__global__ __launch_bounds__(64) void k_diag_finalize(const uint64_t *part, int32_t n,
+                                                      int64_t *out) {
+    if (threadIdx.x != 0) return;
+    uint64_t s0 = 0, s1 = 0;
+    for (int i = 0; i < n; ++i) {
+        s0 += part[2 * (int64_t)i];
+        s1 += part[2 * (int64_t)i + 1];
+    }
+    out[0] = (int64_t)s0;
+    out[1] = (int64_t)s1;
+}
+
 __global__ __launch_bounds__(256) void k_fit_finalize(const double *part, int32_t n, double scale,
                                                       int32_t *step, double *hist,
                                                       int32_t hist_len) {
@@ -1106,6 +1152,11 @@ hipError_t launch_sim(KernelFn fn, int grid, int threads, const SimArgs &a, hipS
 hipError_t launch_loss_finalize(const double *part, int32_t n_part, double scale, double *out,
                                 hipStream_t s) {
     hipLaunchKernelGGL(k_loss_finalize, dim3(1), dim3(256), 0, s, part, n_part, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_finalize(const uint64_t *part, int32_t n_part, int64_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_diag_finalize, dim3(1), dim3(64), 0, s, part, n_part, out);
     return hipGetLastError();
 }
 

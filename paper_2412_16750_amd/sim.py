@@ -187,6 +187,19 @@ def idm_sim_backward(plan: Plan, params: torch.Tensor, length: torch.Tensor, p0:
                                    _stream(stream)), "idm_sim_backward")
 
 
+def idm_plan_diagnostics(plan: Plan, workspace: torch.Tensor, out: Optional[torch.Tensor] = None,
+                         stream=None) -> torch.Tensor:
+    """Anomaly counts of the last forward that wrote `workspace`: a device int64
+    tensor [gap-floor evaluations, vehicles with a non-finite state]."""
+    _check_ws(plan, workspace, True)
+    if out is None:
+        out = torch.empty(2, dtype=torch.int64, device=workspace.device)
+    _need(out, "out", torch.int64, 2)
+    check(plan._L.idm_plan_diagnostics(plan.handle, _ptr(workspace), _ptr(out), _stream(stream)),
+          "idm_plan_diagnostics")
+    return out
+
+
 class StepBuffers:
     """Device buffers of one forward + backward pass (used by the graph launch,
     the autotuner and the benchmark)."""

@@ -51,6 +51,15 @@ def pos_close(p_gpu, p_ref, rtol=1e-4, floor=1.0):
     return bool(np.all(err <= lim)), float(err.max()), float((err / lim).max())
 
 
+def disp_close(d_gpu, p_ref, p0, rtol=1e-4, floor=1.0):
+    """The displacement d = p - p0 on its own scale:
+    |d_gpu - (p_ref - p0)| <= rtol * max(|p_ref - p0|, floor), elementwise
+    (the kernels advance displacements, so this does not loosen with the
+    distance of the lane from the origin as an absolute-position check does)."""
+    d_ref = np.asarray(p_ref, dtype=np.float64) - np.asarray(p0, dtype=np.float64)[None, :]
+    return pos_close(np.asarray(d_gpu, dtype=np.float64), d_ref, rtol, floor)
+
+
 def grad_close(g_gpu, g_ref, rtol=1e-3, rel_floor=1e-2, where=None):
     """|g_gpu - g_ref| <= rtol * max(|g_ref|, rel_floor * max|g_ref|), per row.
     Returns (ok, worst error / limit); `where` (a list) receives the worst
@@ -71,3 +80,48 @@ def grad_close(g_gpu, g_ref, rtol=1e-3, rel_floor=1e-2, where=None):
                 where[:] = [(row, i, float(a[i]), float(b[i]), float(lim[i]))]
         ok = ok and bool(np.all(np.abs(a - b) <= lim))
     return ok, worst
+
+
+def kink_margins(sc, ref, lb_tol=1e-2, clamp_rtol=1e-4, gap_min=0.05):
+    """Which vehicles' gradients a FP32 path can match in the bound regime of
+    Sec. III-C.  An evaluation is "near a kink" when the FP32 state could put
+    it on the other side of a branch: -v/dt within lb_tol m/s^2 of a_min while
+    the bound carries weight (1 - w > 1e-4, SOFTPLUS), v + dt * ahat within
+    clamp_rtol of its terms (CLAMP), or a gap below gap_min (the gap floor and
+    the stiff region above it).  A kink at vehicle i changes the adjoint of i
+    and of every vehicle ahead of it in the lane (the adjoint runs from
+    follower to leader), so the comparable vehicles of a lane are those behind
+    its last near-kink vehicle.  Returns (mask [N], counts) where counts has
+    the numbers of active bound evaluations ("lower_bound": a_lb = -v/dt with
+    1 - w > 1e-3, "clamp": v + dt * ahat <= 0) at comparable vehicles, and of
+    excluded vehicles."""
+    import oracle
+    pb = oracle.Problem.from_scenario(sc)
+    AH, GAP = oracle.branch_terms(pb, ref["P"], ref["V"])
+    Vk = ref["V"][:-1]
+    dt, a_min = sc.dt, sc.a_min
+    if sc.mode == scenarios.MODE_SOFTPLUS:
+        on_v = Vk / dt < -a_min
+        a_lb = np.where(on_v, -Vk / dt, a_min)
+        with np.errstate(over="ignore"):
+            w = 1.0 / (1.0 + np.exp(-(AH - a_lb)))
+        near = (np.abs(Vk / dt + a_min) < lb_tol) & ((1.0 - w) > 1e-4)
+        lower = on_v & ((1.0 - w) > 1e-3)
+        clamp = np.zeros_like(on_v)
+    else:
+        pre = Vk + dt * AH
+        near = np.abs(pre) < clamp_rtol * (np.abs(Vk) + dt * np.abs(AH)) + 1e-4
+        lower = np.zeros_like(near)
+        clamp = pre <= 0.0
+    near = near | (GAP < gap_min)
+    near_v = np.any(near, axis=0) if near.size else np.zeros(sc.n, bool)
+    mask = np.ones(sc.n, bool)
+    off = sc.lane_offsets
+    for l in range(sc.n_lanes):
+        lo, hi = int(off[l]), int(off[l + 1])
+        idx = np.nonzero(near_v[lo:hi])[0]
+        if idx.size:
+            mask[lo:lo + idx[-1] + 1] = False
+    counts = dict(lower_bound=int(lower[:, mask].sum()), clamp=int(clamp[:, mask].sum()),
+                  excluded=int((~mask).sum()), floor_hits=int(ref["floor_hits"]))
+    return mask, counts

@@ -34,7 +34,8 @@ def gpu_run(sc, steps=None, target=None, dense=None, want_traj=True, want_v=True
     traj_v = torch.empty(S + 1, n, dtype=torch.float32, device=dev) if want_v else None
     ws = plan.workspace(dev)
     sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj_d, traj_v, ws)
-    out = dict(info=plan.info())
+    diag = sim.idm_plan_diagnostics(plan, ws)
+    out = dict(info=plan.info(), diag=diag.cpu().numpy().tolist())
     if want_backward:
         obs = None
         if target is not None:

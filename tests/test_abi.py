@@ -60,7 +60,9 @@ def test_valid_problem_shape_and_workspace(L):
     assert abs(info.fill - 1000 / 1024) < 1e-12
     N, S, K = 2_000_000, 100, 32
     align = lambda x: (x + 255) // 256 * 256
-    expect = align(8 * 2000) + align(8 * 7 * N) + align(((S + K - 1) // K) * 2 * 4 * N)
+    # loss partials, diagnostic counts (two per bundle), fit gradients, checkpoints
+    expect = (align(8 * 2000) + align(16 * 2000) + align(8 * 7 * N)
+              + align(((S + K - 1) // K) * 2 * 4 * N))
     assert ws == expect
 
 
@@ -250,7 +252,8 @@ def test_long_lanes_are_cut_into_pieces(L, tuning):
     S, K = 100, info.ckpt_every
     align = lambda x: (x + 255) // 256 * 256
     nbnd = info.n_boundaries
-    expect = (align(8 * (len(sizes) + nbnd)) + align(8 * 7 * N) + align(-(-S // K) * 8 * N)
+    expect = (align(8 * (len(sizes) + nbnd)) + align(16 * (len(sizes) + nbnd)) + align(8 * 7 * N)
+              + align(-(-S // K) * 8 * N)
               + align(nbnd * (S + 1) * 8) + align(nbnd * S * 8))
     assert ws == expect
 

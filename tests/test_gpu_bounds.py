@@ -1,0 +1,183 @@
+"""Parity of the lane kernels with the oracle where the speed bounds of
+Sec. III-C decide the update: stop-and-go queues behind a creeping lane head,
+so speeds reach 0 and the lower bound a_lb = -v/dt of the acceleration
+(SOFTPLUS) or the speed clamp at 0 (CLAMP) is active at many (vehicle, step)
+evaluations; overlapping vehicles for the gap floor of the interaction term;
+and the anomaly counts of idm_plan_diagnostics against the oracle's.
+
+Positions and speeds are compared for every vehicle (they are continuous
+across the kinks).  Gradients are compared for the vehicles whose adjoint no
+evaluation near a kink reaches (tests/_util.kink_margins): an FP32 state can
+put such an evaluation on the other branch, where the derivative jumps.
+"""
+import numpy as np
+import pytest
+
+import scenarios
+from scenarios import MODE_CLAMP, MODE_SOFTPLUS
+
+from _util import (disp_close, grad_close, kink_margins, oracle_reference, oracle_targets,
+                   pos_close)
+from gpu_run import gpu_run, log
+
+pytestmark = pytest.mark.gpu
+
+# (mode, dt, top initial speed, initial gap range): queues that brake to a stop
+CASES = [(MODE_SOFTPLUS, 0.1, 15.0, (5.0, 15.0)), (MODE_SOFTPLUS, 0.5, 15.0, (5.0, 15.0)),
+         (MODE_CLAMP, 0.1, 30.0, (3.0, 12.0)), (MODE_CLAMP, 0.5, 15.0, (5.0, 15.0))]
+
+
+def _floor_ambiguous(sc, ref, tol=1e-3):
+    """Evaluations whose gap is within `tol` of the floor: the FP32 gap may
+    land on either side, so the two floor counts may differ by these."""
+    import oracle
+    _, GAP = oracle.branch_terms(oracle.Problem.from_scenario(sc), ref["P"], ref["V"])
+    return int(np.sum(np.abs(GAP - sc.gap_floor) < tol))
+
+
+def _compare(sc, ref, out, mask, what):
+    ok, maxerr, worst = pos_close(out["P"], ref["P"])
+    okd, maxd, worstd = disp_close(out["d"], ref["P"], sc.p0)
+    okv, maxv, worstv = pos_close(out["V"].astype(np.float64), ref["V"])
+    log("%s: positions max|err| %.3e m (worst/limit %.3f), displacements worst/limit %.3f, "
+        "speeds max|err| %.3e m/s (worst/limit %.3f)" % (what, maxerr, worst, worstd, maxv, worstv))
+    assert ok and okd and okv, what
+    where = []
+    okg, wg = grad_close(out["g"][:, mask], ref["g"][:, mask], where=where)
+    ok0, w0 = grad_close(out["gp0"][mask], ref["gp0"][mask])
+    ok1, w1 = grad_close(out["gv0"][mask], ref["gv0"][mask])
+    log("%s: gradient worst/limit params %.3f p0 %.3f v0 %.3f (%d of %d vehicles; worst %s)"
+        % (what, wg, w0, w1, int(mask.sum()), sc.n, where))
+    assert okg and ok0 and ok1, what
+    assert abs(out["loss"] - ref["loss"]) <= 1e-4 * ref["loss"], (out["loss"], ref["loss"])
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("shape", [(64, 1, 16, 16), (64, 4, 16, 8), (1024, 1, 32, 16)])
+def test_stop_and_go_lanes(case, shape):
+    """64 lanes x 12 vehicles, 200 steps; fused MSE every other step plus a
+    dense upstream gradient; whole lanes in one bundle (1024 x 1 with K = 32
+    takes the backward that keeps half a checkpoint block in LDS)."""
+    mode, dt, vmax, gaps = case
+    threads, per, K, KB = shape
+    sc = scenarios.congested(dt=dt, speed_max=vmax, gap_range=gaps, mode=mode, ckpt_every=K)
+    steps = np.arange(2, sc.n_steps + 1, 2)
+    tgt = oracle_targets(sc, steps, c=12)
+    dense = np.random.default_rng(12).normal(0, 1e-3, (sc.n_steps + 1, sc.n)).astype(np.float32)
+    ref = oracle_reference(sc, steps, tgt, dense)
+    mask, counts = kink_margins(sc, ref)
+    what = "stop-and-go mode=%d dt=%.1f shape=%s" % (mode, dt, shape)
+    log("%s: oracle %s" % (what, counts))
+    # the bound of Sec. III-C is what this test is about: it must be active
+    # at compared vehicles
+    assert counts["lower_bound" if mode == MODE_SOFTPLUS else "clamp"] > 0
+    assert mask.sum() >= 0.7 * sc.n
+    out = gpu_run(sc, steps, tgt, dense, threads=threads, per_thread=per, tuning_k=K, block=KB)
+    _compare(sc, ref, out, mask, what)
+    amb = _floor_ambiguous(sc, ref)
+    log("%s: diagnostics %s, oracle floor hits %d (%d within 1 mm of the floor)"
+        % (what, out["diag"], ref["floor_hits"], amb))
+    assert abs(out["diag"][0] - ref["floor_hits"]) <= amb and out["diag"][1] == 0
+
+
+@pytest.mark.parametrize("mode", [MODE_SOFTPLUS, MODE_CLAMP])
+@pytest.mark.parametrize("shape", [(64, 1, 16, 16), (128, 1, 32, 16)])
+def test_stop_and_go_lanes_cut_into_pieces(mode, shape):
+    """6 lanes x 150 vehicles on bundles of 64 or 128 slots: every lane is cut
+    into pieces that exchange boundary states and adjoint contributions at
+    every step while the bounds are active."""
+    threads, per, K, KB = shape
+    dt, vmax, gaps = (0.1, 15.0, (5.0, 15.0)) if mode == MODE_SOFTPLUS else (0.1, 30.0, (3.0, 12.0))
+    sc = scenarios.congested(n_lanes=6, lane_len=150, dt=dt, speed_max=vmax, gap_range=gaps,
+                             mode=mode, ckpt_every=K)
+    steps = np.arange(1, sc.n_steps + 1)
+    tgt = oracle_targets(sc, steps, c=13)
+    ref = oracle_reference(sc, steps, tgt)
+    mask, counts = kink_margins(sc, ref)
+    what = "stop-and-go pieces mode=%d shape=%s" % (mode, shape)
+    log("%s: oracle %s" % (what, counts))
+    assert counts["lower_bound" if mode == MODE_SOFTPLUS else "clamp"] > 0
+    out = gpu_run(sc, steps, tgt, threads=threads, per_thread=per, tuning_k=K, block=KB)
+    assert out["info"]["n_boundaries"] > 0
+    _compare(sc, ref, out, mask, what)
+    amb = _floor_ambiguous(sc, ref)
+    assert abs(out["diag"][0] - ref["floor_hits"]) <= amb and out["diag"][1] == 0
+
+
+def _overlap_scenario(mode, n_steps, c=14):
+    """40 lanes x 8 vehicles at 5-20 m/s; about a third of the followers start
+    overlapping their leader (bumper-to-bumper gap -3 .. -0.5 m), the others
+    0.5 .. 20 m behind it, so the gap floor is active from the first step for
+    the overlapping ones and far from it for the others."""
+    off = scenarios.uniform_lanes(40, 8)
+    n = int(off[-1])
+    params = scenarios.draw_params(np.random.default_rng(1000 + c), n)
+    rng = np.random.default_rng(3000 + c)
+    gaps = np.where(rng.uniform(size=n) < 0.35, rng.uniform(-3.0, -0.5, n), rng.uniform(0.5, 20.0, n))
+    v = rng.uniform(5.0, 20.0, n).astype(np.float32)
+    p0 = np.zeros(n)
+    for l in range(40):
+        lo, hi = int(off[l]), int(off[l + 1])
+        for i in range(hi - 2, lo - 1, -1):   # leaders ahead of the tail at 0
+            p0[i] = p0[i + 1] + params["length"][i] + gaps[i + 1]
+    return scenarios.Scenario("overlap", off, params, p0, v, n_steps, mode=mode, ckpt_every=8)
+
+
+@pytest.mark.parametrize("mode", [MODE_SOFTPLUS, MODE_CLAMP])
+@pytest.mark.parametrize("n_steps", [1, 3])
+def test_gap_floor_on_overlapping_vehicles(mode, n_steps):
+    """With the floor active the interaction term uses gap_floor and its gap
+    derivative is 0 (the reading of Sec. III-A used by both sides): speeds,
+    positions and gradients against the oracle, and the floor count of
+    idm_plan_diagnostics equal to the oracle's, evaluation for evaluation."""
+    sc = _overlap_scenario(mode, n_steps)
+    steps = np.arange(1, n_steps + 1)
+    tgt = oracle_targets(sc, steps, c=14)
+    dense = np.random.default_rng(14).normal(0, 1e-2, (n_steps + 1, sc.n)).astype(np.float32)
+    ref = oracle_reference(sc, steps, tgt, dense)
+    amb = _floor_ambiguous(sc, ref)
+    log("overlap mode=%d S=%d: oracle floor hits %d, %d within 1 mm of the floor"
+        % (mode, n_steps, ref["floor_hits"], amb))
+    assert ref["floor_hits"] >= 40 and amb == 0
+    mask, counts = kink_margins(sc, ref, gap_min=-np.inf)
+    out = gpu_run(sc, steps, tgt, dense, threads=64, per_thread=1, tuning_k=8)
+    _compare(sc, ref, out, mask, "overlap mode=%d S=%d" % (mode, n_steps))
+    log("overlap mode=%d S=%d: diagnostics %s" % (mode, n_steps, out["diag"]))
+    assert out["diag"] == [ref["floor_hits"], 0]
+
+
+def test_non_finite_states_are_counted():
+    """A NaN initial speed poisons that vehicle's state and, through the gap
+    and speed difference, every follower's: the count of vehicles with a
+    non-finite state and the floor count (a NaN gap counts as floored, as in
+    the oracle) equal the oracle's."""
+    sc = scenarios.single_lane(n_vehicles=50, n_steps=40, ckpt_every=8)
+    sc.v_init = sc.v_init.copy()
+    sc.v_init[30] = np.nan
+    ref = oracle_reference(sc)
+    bad = int(np.sum(~np.all(np.isfinite(ref["P"]) & np.isfinite(ref["V"]), axis=0)))
+    out = gpu_run(sc, want_backward=False)
+    log("non-finite: diagnostics %s, oracle (%d, %d)" % (out["diag"], ref["floor_hits"], bad))
+    assert bad == 20
+    assert out["diag"] == [ref["floor_hits"], bad]
+
+
+@pytest.mark.parametrize("mode", [MODE_SOFTPLUS, MODE_CLAMP])
+def test_diagnostics_after_a_fit_step(mode):
+    """idm_fit_step's forward writes the counts too (smooth lanes: none)."""
+    import torch
+    from paper_2412_16750_amd import sim
+    from paper_2412_16750_amd.fit import Fitter
+    from gpu_run import device_inputs
+    sc = scenarios.make_scenario("fitdiag", scenarios.uniform_lanes(4, 200), 100, 4, mode=mode,
+                                 ckpt_every=32)
+    steps = scenarios.obs_steps(sc.n_steps, 10, 10)
+    tgt = oracle_targets(sc, steps, c=4)
+    plan = sim.Plan.for_scenario(sc)
+    x = device_inputs(sc)
+    f = Fitter(plan, x["length"], x["p0"], x["v"], sim.Obs(torch.from_numpy(tgt).cuda(), 10, 10))
+    f.init(x["prm"])
+    f.step()
+    diag = sim.idm_plan_diagnostics(plan, f.workspace).cpu().numpy().tolist()
+    log("fit mode=%d: diagnostics %s" % (mode, diag))
+    assert diag == [0, 0]

@@ -11,7 +11,8 @@ import pytest
 import scenarios
 from scenarios import MODE_CLAMP, MODE_SOFTPLUS
 
-from _util import grad_close, oracle_reference, oracle_targets, pos_close, ragged_scenario
+from _util import (disp_close, grad_close, oracle_reference, oracle_targets, pos_close,
+                   ragged_scenario)
 from gpu_run import gpu_run, log
 
 pytestmark = pytest.mark.gpu
@@ -21,6 +22,11 @@ def _check(sc, ref, out, what, pos_rtol=1e-4, grad_rtol=1e-3, check_v=True):
     ok, maxerr, worst = pos_close(out["P"], ref["P"], rtol=pos_rtol)
     log("%s: positions max|err| = %.3e m, worst/limit = %.3f" % (what, maxerr, worst))
     assert ok, (what, maxerr, worst)
+    okd, maxd, worstd = disp_close(out["d"], ref["P"], sc.p0, rtol=pos_rtol)
+    log("%s: displacements max|err| = %.3e m, worst/limit = %.3f" % (what, maxd, worstd))
+    assert okd, (what, maxd, worstd)
+    # the gap floor never triggers on these lanes, and no state is non-finite
+    assert out["diag"] == [ref["floor_hits"], 0], (what, out["diag"], ref["floor_hits"])
     if check_v:
         okv, maxv, worstv = pos_close(out["V"].astype(np.float64), ref["V"], rtol=pos_rtol)
         log("%s: speeds max|err| = %.3e m/s" % (what, maxv))
@@ -243,6 +249,12 @@ def test_scale_config_sampled_lanes():
     ok, maxerr, worst = pos_close(sc.p0[idx][None, :] + d.astype(np.float64), ref["P"])
     log("scale sampled: positions max|err| %.3e worst/limit %.3f" % (maxerr, worst))
     assert ok
+    okd, maxd, worstd = disp_close(d, ref["P"], sc.p0[idx])
+    log("scale sampled: displacements max|err| %.3e worst/limit %.3f" % (maxd, worstd))
+    assert okd
+    diag = sim.idm_plan_diagnostics(plan, ws).cpu().numpy().tolist()
+    log("scale: diagnostics (gap-floor evaluations, non-finite vehicles) = %s" % diag)
+    assert diag == [0, 0]
     g = gp.cpu().numpy()[:, idx]
     okg, wg = grad_close(g, ref["g"] * fac)
     ok0, w0 = grad_close(gp0.cpu().numpy()[idx], ref["gp0"] * fac)

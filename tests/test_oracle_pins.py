@@ -543,3 +543,52 @@ def test_window_features_hand_computed():
     expect[1, 6:9] = [18 / 50, 20 / 50, 23 / 50]
     expect[2, 6:9] = [4.0, 4.0, 4.0]
     np.testing.assert_allclose(F, expect, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("mode", [MODE_SOFTPLUS, MODE_CLAMP])
+def test_branch_terms_agree_with_the_forward(mode):
+    """oracle.branch_terms (the test helper that measures distances to the
+    kinks) reports what the forward used: the raw gap is the leader's position
+    minus the own position minus the LEADER's length (+inf for a head); in
+    CLAMP mode an unclamped speed update is v + dt ahat; in SOFTPLUS mode the
+    acceleration is a_lb + softplus(ahat - a_lb) with a_lb = max(-v/dt, a_min)."""
+    import scenarios
+    sc = scenarios.congested(n_lanes=4, lane_len=12, n_steps=60, mode=mode)
+    pb = Problem.from_scenario(sc)
+    P, V, A, _ = oracle.forward(pb, want_acc=True)
+    AH, GAP = oracle.branch_terms(pb, P, V)
+    off = sc.lane_offsets
+    for l in range(sc.n_lanes):
+        lo, hi = int(off[l]), int(off[l + 1])
+        assert np.all(np.isinf(GAP[:, lo]))
+        want = P[:-1, lo:hi - 1] - P[:-1, lo + 1:hi] - sc.params["length"][lo:hi - 1].astype(np.float64)
+        np.testing.assert_allclose(GAP[:, lo + 1:hi], want, rtol=0, atol=1e-9)
+    if mode == MODE_CLAMP:
+        moving = V[1:] > 0
+        assert np.array_equal(V[1:][moving], (V[:-1] + sc.dt * AH)[moving])
+        assert np.all(V[:-1][~moving] + sc.dt * AH[~moving] <= 0)
+    else:
+        a_lb = np.maximum(-V[:-1] / sc.dt, sc.a_min)
+        x = AH - a_lb
+        sp = np.maximum(x, 0) + np.log1p(np.exp(-np.abs(x)))
+        np.testing.assert_allclose(A, a_lb + sp, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("mode", [MODE_SOFTPLUS, MODE_CLAMP])
+def test_stop_and_go_queues_reach_the_bounds(mode):
+    """The stop-and-go lanes used by the GPU bound tests stop vehicles: speeds
+    reach 0, the lower bound -v/dt of Sec. III-C (SOFTPLUS) or the clamp
+    (CLAMP) is active at vehicles whose gradients those tests compare, and
+    most vehicles are comparable."""
+    import sys, os
+    import scenarios
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from _util import kink_margins, oracle_reference
+    kw = dict(speed_max=15.0, gap_range=(5.0, 15.0)) if mode == MODE_SOFTPLUS else \
+        dict(speed_max=30.0, gap_range=(3.0, 12.0))
+    sc = scenarios.congested(mode=mode, **kw)
+    ref = oracle_reference(sc)
+    mask, counts = kink_margins(sc, ref)
+    assert ref["V"].min() <= (1e-3 if mode == MODE_SOFTPLUS else 0.0)
+    assert counts["lower_bound" if mode == MODE_SOFTPLUS else "clamp"] > 100
+    assert mask.sum() >= 0.7 * sc.n
