@@ -54,7 +54,7 @@ def lib():
         L.oracle_forward.restype = ctypes.c_long
         L.oracle_forward.argtypes = common + [pd, pd, pd, pd, pd]
         L.oracle_adjoint.restype = ctypes.c_int
-        L.oracle_adjoint.argtypes = common + [pd, pd, pd, pd, pd, pd, pd]
+        L.oracle_adjoint.argtypes = common + [pd, pd, pd, pd, pd, pd, pd, pd]
         L.oracle_branch_terms.restype = ctypes.c_int
         L.oracle_branch_terms.argtypes = common + [pd, pd, pd, pd]
         L.oracle_tangent.restype = ctypes.c_int
@@ -126,18 +126,22 @@ def forward(pb: Problem, want_acc: bool = False):
     return P, V, A, int(hits)
 
 
-def adjoint(pb: Problem, P, V, gP, gV=None):
-    """Returns (g_params [5, N] in (v0, T, a, b, s0) order, g_p0 [N], g_v0 [N])."""
+def adjoint(pb: Problem, P, V, gP, gV=None, magnitude: bool = False):
+    """Returns (g_params [5, N] in (v0, T, a, b, s0) order, g_p0 [N], g_v0 [N]),
+    plus, with magnitude=True, the [5, N] sums of the absolute per-step terms
+    of each parameter gradient."""
     S, n = pb.n_steps, pb.n
     gP = _d(gP).reshape(S + 1, n)
     gV = None if gV is None else _d(gV).reshape(S + 1, n)
     g = np.empty((5, n), dtype=np.float64)
     gp0 = np.empty(n, dtype=np.float64)
     gv0 = np.empty(n, dtype=np.float64)
-    rc = lib().oracle_adjoint(*pb._head(), _p(_d(P)), _p(_d(V)), _p(gP), _p(gV), _p(g), _p(gp0), _p(gv0))
+    gabs = np.empty((5, n), dtype=np.float64) if magnitude else None
+    rc = lib().oracle_adjoint(*pb._head(), _p(_d(P)), _p(_d(V)), _p(gP), _p(gV), _p(g), _p(gp0),
+                              _p(gv0), _p(gabs))
     if rc != 0:
         raise ValueError("oracle_adjoint: invalid arguments")
-    return g, gp0, gv0
+    return (g, gp0, gv0, gabs) if magnitude else (g, gp0, gv0)
 
 
 def branch_terms(pb: Problem, P, V):

@@ -283,7 +283,11 @@ int oracle_branch_terms(int mode, double dt, double delta, double a_min, double 
  * Reverse-mode gradient.  Inputs: the forward trajectory P, V, and the
  * upstream gradients gP = dL/dp_k ([(n_steps+1)*n]) and gV = dL/dv_k
  * (nullable, same shape).  Outputs (overwritten): g_prm [5*n] (v0, T, a, b,
- * s0 blocks of n), g_p0 [n] = dL/dp(0), g_v0 [n] = dL/dv(0).
+ * s0 blocks of n), g_p0 [n] = dL/dp(0), g_v0 [n] = dL/dv(0), and, if g_abs
+ * is non-null, g_abs [5*n] = the sum over steps of |mu_i d acc_i/d theta_i|,
+ * the magnitude of the terms each parameter gradient adds up (a gradient far
+ * smaller than it is a cancelling sum, which no FP32 trajectory determines to
+ * a fixed relative accuracy).
  *
  * Per step k (last to first), with lam_p, lam_v the adjoints of the step-(k+1)
  * state and acc = f(p_i, v_i, p_h, v_h, theta_i):
@@ -298,7 +302,7 @@ int oracle_adjoint(int mode, double dt, double delta, double a_min, double gap_f
                    const double *v0, const double *T, const double *a, const double *b,
                    const double *s0, const double *len, const double *P, const double *V,
                    const double *gP, const double *gV, double *g_prm, double *g_p0,
-                   double *g_v0)
+                   double *g_v0, double *g_abs)
 {
     cfg_t c = {mode, dt, delta, a_min, gap_floor};
     if (check_common(&c, n, n_lanes, lane_off, n_steps)) return -1;
@@ -310,6 +314,8 @@ int oracle_adjoint(int mode, double dt, double delta, double a_min, double gap_f
         return -1;
     }
     for (int j = 0; j < 5 * n; ++j) g_prm[j] = 0.0;
+    if (g_abs)
+        for (int j = 0; j < 5 * n; ++j) g_abs[j] = 0.0;
     for (int i = 0; i < n; ++i) {
         lp[i] = gP[(size_t)n_steps * n + i];
         lv[i] = gV ? gV[(size_t)n_steps * n + i] : 0.0;
@@ -337,6 +343,8 @@ int oracle_adjoint(int mode, double dt, double delta, double a_min, double gap_f
                     nv[h] += mu * r.d_vh;
                 }
                 for (int j = 0; j < 5; ++j) g_prm[(size_t)j * n + i] += mu * r.d_prm[j];
+                if (g_abs)
+                    for (int j = 0; j < 5; ++j) g_abs[(size_t)j * n + i] += fabs(mu * r.d_prm[j]);
             }
         }
         memcpy(lp, np_, sizeof(double) * (size_t)n);

@@ -273,10 +273,12 @@ __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf
                 float dh = r ? d[r - 1] : L.x;
                 float vh = r ? v[r - 1] : L.y;
                 // the lane model's gap (as in accel), counted when the floor
-                // is active: one compare per vehicle-step, the wave's count
-                // kept in scalar registers
+                // is active at a vehicle (a padding slot behind a lane tail
+                // sees that tail's state and never counts): one compare per
+                // vehicle-step, the wave's count kept in scalar registers
                 const float gap = q[r].g0 + (dh - d[r]);
-                n_floor += (uint64_t)__builtin_popcountll(__ballot(!(gap > A.gap_floor)));
+                n_floor += (uint64_t)__builtin_popcountll(
+                    __ballot(q[r].g >= 0 && !(gap > A.gap_floor)));
                 acc[r] = accel_gd<MODE>(q[r], v[r], gap, v[r] - vh, A.inv_dt, A.a_min,
                                         A.gap_floor);
             }

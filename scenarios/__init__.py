@@ -184,9 +184,10 @@ def uneven(n_lanes: int = 10000, n_steps: int = 300, mu: float = 5.0, sigma: flo
 
 def congested(n_lanes: int = 64, lane_len: int = 12, n_steps: int = 200, dt: float = 0.1,
               c: int = 11, speed_max: float = 15.0, gap_range=(5.0, 15.0),
-              mode: int = MODE_SOFTPLUS, **kw) -> Scenario:
+              mode: int = MODE_SOFTPLUS, head_speed=(0.5, 3.0), **kw) -> Scenario:
     """Stop-and-go lanes for the speed bounds of Sec. III-C: every lane head
-    creeps (desired speed U[0.5, 3] m/s, starting at rest) and its followers
+    creeps (desired speed U[head_speed], by default U[0.5, 3] m/s, starting
+    at rest) and its followers
     start at speeds U[0, speed_max] with bumper-to-bumper gaps drawn from
     gap_range, so the queues brake hard and speeds reach 0.  Parameters are the
     usual draws apart from the heads' desired speeds (seed 1000 + c); heads,
@@ -195,7 +196,7 @@ def congested(n_lanes: int = 64, lane_len: int = 12, n_steps: int = 200, dt: flo
     params = draw_params(np.random.default_rng(1000 + c), int(off[-1]))
     rng = np.random.default_rng(3000 + c)
     heads = off[:-1]
-    params["v0"][heads] = _f32(rng.uniform(0.5, 3.0, len(heads)))
+    params["v0"][heads] = _f32(rng.uniform(head_speed[0], head_speed[1], len(heads)))
     p0, v = place_lanes(rng, off, params["length"], gap_range=gap_range,
                         speed_range=(0.0, speed_max))
     v = v.copy()

@@ -125,3 +125,37 @@ def kink_margins(sc, ref, lb_tol=1e-2, clamp_rtol=1e-4, gap_min=0.05):
     counts = dict(lower_bound=int(lower[:, mask].sum()), clamp=int(clamp[:, mask].sum()),
                   excluded=int((~mask).sum()), floor_hits=int(ref["floor_hits"]))
     return mask, counts
+
+
+def fp32_state_conditioning(sc, steps=None, target=None, dense=None, ref=None, mask=None):
+    """How well an FP32 state determines the oracle's gradients here: the
+    oracle is stepped one step at a time with the displacement d = p - p0 and
+    the speed rounded to FP32 after every step (the resolution at which the
+    HIP path carries its state), and its adjoint along that trajectory is
+    compared with the FP64 one at grad_close's limits.  Returns the worst
+    error / limit per gradient row (v0, T, a, b, s0, p0, v0-initial) over the
+    vehicles in `mask`.  Everything here is the oracle's own arithmetic."""
+    import oracle
+    pb1 = oracle.Problem.from_scenario(sc, n_steps=1)
+    S, n = sc.n_steps, sc.n
+    P = np.empty((S + 1, n))
+    V = np.empty((S + 1, n))
+    P[0], V[0] = sc.p0, sc.v_init
+    for k in range(S):
+        pb1.p0 = np.ascontiguousarray(P[k])
+        pb1.v_init = np.ascontiguousarray(V[k])
+        Pk, Vk, _, _ = oracle.forward(pb1)
+        P[k + 1] = sc.p0 + (Pk[1] - sc.p0).astype(np.float32).astype(np.float64)
+        V[k + 1] = Vk[1].astype(np.float32).astype(np.float64)
+    gP = np.zeros_like(P)
+    if target is not None:
+        gP += oracle.mse(P, steps, target.astype(np.float64))[1]
+    if dense is not None:
+        gP += dense.astype(np.float64).reshape(gP.shape)
+    g, gp0, gv0 = oracle.adjoint(oracle.Problem.from_scenario(sc), P, V, gP)
+    if dense is not None:
+        gp0 = gp0 - dense.astype(np.float64).reshape(gP.shape).sum(axis=0)
+    m = np.ones(n, bool) if mask is None else mask
+    rows = list(g) + [gp0, gv0]
+    refs = list(ref["g"]) + [ref["gp0"], ref["gv0"]]
+    return [grad_close(a[m], b[m])[1] for a, b in zip(rows, refs)]

@@ -16,15 +16,25 @@ import pytest
 import scenarios
 from scenarios import MODE_CLAMP, MODE_SOFTPLUS
 
-from _util import (disp_close, grad_close, kink_margins, oracle_reference, oracle_targets,
-                   pos_close)
+from _util import (disp_close, fp32_state_conditioning, grad_close, kink_margins,
+                   oracle_reference, oracle_targets, pos_close)
 from gpu_run import gpu_run, log
 
 pytestmark = pytest.mark.gpu
 
-# (mode, dt, top initial speed, initial gap range): queues that brake to a stop
-CASES = [(MODE_SOFTPLUS, 0.1, 15.0, (5.0, 15.0)), (MODE_SOFTPLUS, 0.5, 15.0, (5.0, 15.0)),
-         (MODE_CLAMP, 0.1, 30.0, (3.0, 12.0)), (MODE_CLAMP, 0.5, 15.0, (5.0, 15.0))]
+# (mode, dt, steps, top initial speed, initial gap range, heads' desired
+# speeds): queues that brake to a stop.  Explicit Euler on the free-road
+# equation dv/dt = a (1 - (v/v0)^4) is unstable once dt 4a/v0 > 2: a head
+# creeping at v0 < 2 a dt then oscillates and amplifies every rounding, so with
+# dt = 0.5 s (a up to 2) the heads' desired speeds are drawn from [3, 6] m/s.
+# In a stopped queue the b gradient sums v (v - v_h) c / (2b) over creeping
+# steps whose tiny motions an FP32 position no longer resolves after long
+# standstills; the step counts keep every gradient row determined by an FP32
+# state (asserted through fp32_state_conditioning before the GPU runs).
+CASES = [(MODE_SOFTPLUS, 0.1, 150, 15.0, (5.0, 15.0), (0.5, 3.0)),
+         (MODE_SOFTPLUS, 0.5, 40, 15.0, (5.0, 15.0), (3.0, 6.0)),
+         (MODE_CLAMP, 0.1, 150, 30.0, (3.0, 12.0), (0.5, 3.0)),
+         (MODE_CLAMP, 0.5, 40, 15.0, (5.0, 15.0), (3.0, 6.0))]
 
 
 def _floor_ambiguous(sc, ref, tol=1e-3):
@@ -55,12 +65,15 @@ def _compare(sc, ref, out, mask, what):
 @pytest.mark.parametrize("case", CASES)
 @pytest.mark.parametrize("shape", [(64, 1, 16, 16), (64, 4, 16, 8), (1024, 1, 32, 16)])
 def test_stop_and_go_lanes(case, shape):
-    """64 lanes x 12 vehicles, 200 steps; fused MSE every other step plus a
+    """64 lanes x 12 vehicles, 150 or 40 steps; fused MSE every other step plus a
     dense upstream gradient; whole lanes in one bundle (1024 x 1 with K = 32
     takes the backward that keeps half a checkpoint block in LDS)."""
-    mode, dt, vmax, gaps = case
+    mode, dt, n_steps, vmax, gaps, heads = case
     threads, per, K, KB = shape
-    sc = scenarios.congested(dt=dt, speed_max=vmax, gap_range=gaps, mode=mode, ckpt_every=K)
+    sc = scenarios.congested(n_steps=n_steps, dt=dt, speed_max=vmax, gap_range=gaps, mode=mode,
+                             ckpt_every=K, head_speed=heads)
+    hd = sc.lane_offsets[:-1]
+    assert np.all(dt * 4.0 * sc.params["a"][hd] / sc.params["v0"][hd] < 2.0)
     steps = np.arange(2, sc.n_steps + 1, 2)
     tgt = oracle_targets(sc, steps, c=12)
     dense = np.random.default_rng(12).normal(0, 1e-3, (sc.n_steps + 1, sc.n)).astype(np.float32)
@@ -72,6 +85,10 @@ def test_stop_and_go_lanes(case, shape):
     # at compared vehicles
     assert counts["lower_bound" if mode == MODE_SOFTPLUS else "clamp"] > 0
     assert mask.sum() >= 0.7 * sc.n
+    cond = fp32_state_conditioning(sc, steps, tgt, dense, ref, mask)
+    log("%s: oracle with FP32-rounded state, gradient worst/limit per row %s"
+        % (what, ["%.3f" % c for c in cond]))
+    assert max(cond) <= 0.5
     out = gpu_run(sc, steps, tgt, dense, threads=threads, per_thread=per, tuning_k=K, block=KB)
     _compare(sc, ref, out, mask, what)
     amb = _floor_ambiguous(sc, ref)
@@ -97,6 +114,10 @@ def test_stop_and_go_lanes_cut_into_pieces(mode, shape):
     what = "stop-and-go pieces mode=%d shape=%s" % (mode, shape)
     log("%s: oracle %s" % (what, counts))
     assert counts["lower_bound" if mode == MODE_SOFTPLUS else "clamp"] > 0
+    cond = fp32_state_conditioning(sc, steps, tgt, None, ref, mask)
+    log("%s: oracle with FP32-rounded state, gradient worst/limit per row %s"
+        % (what, ["%.3f" % c for c in cond]))
+    assert max(cond) <= 0.5
     out = gpu_run(sc, steps, tgt, threads=threads, per_thread=per, tuning_k=K, block=KB)
     assert out["info"]["n_boundaries"] > 0
     _compare(sc, ref, out, mask, what)
