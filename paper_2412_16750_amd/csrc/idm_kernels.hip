@@ -235,7 +235,15 @@ __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf
             }
         }
         lds_barrier();
-        uint64_t n_floor = 0;  // this wave's gap-floor evaluations
+        // gap-floor diagnostics: each thread counts its evaluations ABOVE the
+        // floor (one compare and one add on the vector unit, nothing that
+        // makes the scalar unit wait for it); the floor count is the
+        // complement, taken once after the last step.  A padding slot's
+        // threshold is +inf, so it never counts as an evaluation.
+        uint32_t n_ok = 0;
+        float thr[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) thr[r] = q[r].g >= 0 ? A.gap_floor : INFINITY;
         int to_ckpt = A.K;  // steps until the next checkpoint
         // trajectory rows through raw buffer resources: the row address is
         // advanced by scalar adds, each lane stores at its loop-invariant byte
@@ -272,13 +280,10 @@ __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf
                 // interaction term
                 float dh = r ? d[r - 1] : L.x;
                 float vh = r ? v[r - 1] : L.y;
-                // the lane model's gap (as in accel), counted when the floor
-                // is active at a vehicle (a padding slot behind a lane tail
-                // sees that tail's state and never counts): one compare per
-                // vehicle-step, the wave's count kept in scalar registers
+                // the lane model's gap (as in accel); a NaN gap counts as
+                // floored, as the floor treats it
                 const float gap = q[r].g0 + (dh - d[r]);
-                n_floor += (uint64_t)__builtin_popcountll(
-                    __ballot(q[r].g >= 0 && !(gap > A.gap_floor)));
+                n_ok += (gap > thr[r]) ? 1u : 0u;
                 acc[r] = accel_gd<MODE>(q[r], v[r], gap, v[r] - vh, A.inv_dt, A.a_min,
                                         A.gap_floor);
             }
@@ -333,6 +338,12 @@ __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf
             for (int r = 0; r < R; ++r)
                 n_bad += (uint64_t)__builtin_popcountll(
                     __ballot(q[r].g >= 0 && !(isfinite(d[r]) && isfinite(v[r]))));
+            uint32_t n_real = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) n_real += q[r].g >= 0 ? 1u : 0u;
+            uint64_t n_floor = (uint64_t)(n_real * (uint32_t)S - n_ok);  // S < 2^27, R <= 4
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) n_floor += __shfl_down(n_floor, off, 64);
             if ((t & 63) == 0) {
                 dred[0][t >> 6] = n_floor;
                 dred[1][t >> 6] = n_bad;
@@ -352,8 +363,12 @@ __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf
 }
 
 
+// Scalar registers: two 1024-thread work-groups share a compute unit only
+// while a wave holds at most 80 SGPRs as the runtime counts them (96 halved
+// the measured occupancy, 58 -> 31 resident waves per CU, and cost 55 % of
+// the forward's time); the cap keeps the allocator below that.
 template <int MODE, int R, int NT>
-__global__ __launch_bounds__(NT) void k_forward(SimArgs A) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_num_sgpr(72))) void k_forward(SimArgs A) {
     forward_body<MODE, R, NT, false>(A, nullptr);
 }
 
