@@ -230,6 +230,34 @@ idm_status idm_sim_backward(idm_plan *plan, const idm_params *prm, const double 
                             double *grad_p0, double *grad_v0, double *loss_out, void *workspace,
                             void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * gradient of idm_sim_backward with no workspace argument.  One call runs the
+ * forward (checkpoints only, no trajectory) and then the backward, the same
+ * kernels as idm_sim_forward + idm_sim_backward on a caller workspace, with
+ * the library's static device scratch array in that workspace's place; the
+ * outputs (grad_params, grad_p0, grad_v0, loss_out, same layout and meaning
+ * as idm_sim_backward) are bitwise equal to that pair's.
+ *   - Allocates nothing: no hipMalloc, hipFree or allocating library call.
+ *     The scratch array, IDM_STATIC_SCRATCH_BYTES (256 MiB) per GPU, is part
+ *     of the library's device code and is held until the process ends; its
+ *     address is looked up once per device (first call on that device).
+ *   - A plan whose workspace (idm_workspace_bytes) exceeds the array is
+ *     rejected with IDM_ERR_WORKSPACE before anything is launched (the
+ *     2000 x 1000-vehicle, 100-step, K = 32 problem needs 176 MiB and fits).
+ *   - Every call on one GPU shares that GPU's array and leaves its contents
+ *     there; nothing in it needs to start at zero (each region the kernels
+ *     read is written earlier in the same call).  Calls that overlap on one
+ *     GPU (two streams, two threads) race on the array: serialize them.
+ *   - idm_plan_diagnostics cannot read this call's counts (the scratch is
+ *     not a caller workspace). */
+#define IDM_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+idm_status idm_sim_backward_noalloc(idm_plan *plan, const idm_params *prm, const double *p0,
+                                    const float *v_init, const float *grad_traj_d,
+                                    const float *grad_traj_v, const idm_obs *obs,
+                                    double *grad_params, double *grad_p0, double *grad_v0,
+                                    double *loss_out, void *stream);
+
 /* One gradient step of the trajectory fit (Sec. IV-A): forward (checkpoints
  * only), fused MSE loss and backward, then Adam on NORMALISED parameters
  * u = (theta - lo) / (hi - lo) followed by projection of u onto [0, 1] (the

@@ -103,7 +103,8 @@ class IdmStepArgs(ctypes.Structure):
 # every symbol declared in include/idm.h
 EXPORTS = ("idm_plan_create", "idm_plan_destroy", "idm_workspace_bytes", "idm_plan_get_info",
            "idm_problem_check", "idm_problem_layout", "idm_problem_bundles",
-           "idm_sim_forward", "idm_sim_backward", "idm_plan_diagnostics", "idm_fit_init", "idm_fit_step", "idm_fit_run",
+           "idm_sim_forward", "idm_sim_backward", "idm_sim_backward_noalloc", "idm_plan_diagnostics",
+           "idm_fit_init", "idm_fit_step", "idm_fit_run",
            "idm_step_graph_launch", "idm_plan_autotune", "idm_copy_bytes", "idm_last_error",
            "idm_version", "idm_mlp_param_count", "idm_mlp_weight_bf16_count",
            "idm_mlp_workspace_bytes", "idm_mlp_sync", "idm_mlp_features", "idm_mlp_forward",
@@ -146,6 +147,9 @@ def load() -> ctypes.CDLL:
     L.idm_sim_backward.argtypes = [c_void_p, P(IdmParams), c_void_p, c_void_p, c_void_p, c_void_p,
                                    P(IdmObs), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p]
+    L.idm_sim_backward_noalloc.argtypes = [c_void_p, P(IdmParams), c_void_p, c_void_p, c_void_p,
+                                           c_void_p, P(IdmObs), c_void_p, c_void_p, c_void_p,
+                                           c_void_p, c_void_p]
     L.idm_plan_diagnostics.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
     L.idm_fit_init.argtypes = [c_void_p, P(IdmFitState), c_void_p, c_void_p]
     L.idm_fit_step.argtypes = [c_void_p, P(IdmFitState), c_void_p, c_void_p, P(IdmObs), c_void_p,
@@ -202,7 +206,8 @@ def load() -> ctypes.CDLL:
     L.idm_version.restype = ctypes.c_char_p
     for name in ("idm_problem_check", "idm_problem_layout", "idm_problem_bundles", "idm_plan_create",
                  "idm_plan_destroy", "idm_plan_get_info", "idm_sim_forward",
-                 "idm_sim_backward", "idm_plan_diagnostics", "idm_fit_init", "idm_fit_step",
+                 "idm_sim_backward", "idm_sim_backward_noalloc", "idm_plan_diagnostics",
+                 "idm_fit_init", "idm_fit_step",
                  "idm_fit_run", "idm_step_graph_launch",
                  "idm_plan_autotune"):
         getattr(L, name).restype = c_int32

@@ -12,10 +12,16 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 using namespace idmx;
+
+// Device scratch of idm_sim_backward_noalloc (its workspace), one copy per
+// GPU.  Host code never uses this name as an address: the device address of
+// each GPU's copy comes from hipGetSymbolAddress (static_scratch below).
+static __device__ __align__(256) char scratch[IDM_STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -788,6 +794,33 @@ int32_t plan_steps(const idm_plan *p) { return p ? p->pb.n_steps : 0; }
 float plan_dt(const idm_plan *p) { return p ? p->pb.dt : 0.0f; }
 }  // namespace idmx
 
+namespace {
+
+// Device address of the current GPU's copy of `scratch`, looked up once per
+// device (hipGetSymbolAddress, with that device current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+idm_status static_scratch(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(IDM_ERR_UNSUPPORTED, "device index %d", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(IDM_ERR_HIP, "hipGetSymbolAddress(scratch) gave no address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return IDM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *idm_last_error(void) { return g_err.c_str(); }
@@ -948,6 +981,32 @@ idm_status idm_sim_backward(idm_plan *p, const idm_params *prm, const double *p0
     if (r != IDM_OK) return r;
     return run_backward(p, prm, p0, v_init, gd, gv, obs, g_prm, g_p0, g_v0, loss_out, ws,
                         (hipStream_t)stream);
+}
+
+idm_status idm_sim_backward_noalloc(idm_plan *p, const idm_params *prm, const double *p0,
+                                    const float *v_init, const float *gd, const float *gv,
+                                    const idm_obs *obs, double *g_prm, double *g_p0,
+                                    double *g_v0, double *loss_out, void *stream) {
+    if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
+    idm_status r = check_params(prm);
+    if (r != IDM_OK) return r;
+    if (!p0 || !v_init) return fail(IDM_ERR_INVALID_ARG, "p0 / v_init null");
+    if (!g_prm || !g_p0 || !g_v0) return fail(IDM_ERR_INVALID_ARG, "gradient outputs null");
+    r = check_obs(p, obs);
+    if (r != IDM_OK) return r;
+    const size_t need = ws_total(p, p->sh.K, p->n_bnd);
+    if (need > IDM_STATIC_SCRATCH_BYTES)
+        return fail(IDM_ERR_WORKSPACE,
+                    "the problem needs a %zu-byte workspace; the static scratch holds %zu bytes "
+                    "(use idm_sim_forward / idm_sim_backward with a caller workspace)",
+                    need, (size_t)IDM_STATIC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    r = static_scratch(&ws);
+    if (r != IDM_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    r = run_forward(p, prm, p0, v_init, nullptr, nullptr, ws, s);
+    if (r != IDM_OK) return r;
+    return run_backward(p, prm, p0, v_init, gd, gv, obs, g_prm, g_p0, g_v0, loss_out, ws, s);
 }
 
 idm_status idm_fit_init(idm_plan *p, const idm_fit_state *st, const float *init_params,

@@ -187,6 +187,35 @@ def idm_sim_backward(plan: Plan, params: torch.Tensor, length: torch.Tensor, p0:
                                    _stream(stream)), "idm_sim_backward")
 
 
+def idm_sim_backward_noalloc(plan: Plan, params: torch.Tensor, length: torch.Tensor,
+                             p0: torch.Tensor, v_init: torch.Tensor, grad_params: torch.Tensor,
+                             grad_p0: torch.Tensor, grad_v0: torch.Tensor,
+                             grad_traj_d: Optional[torch.Tensor] = None,
+                             grad_traj_v: Optional[torch.Tensor] = None, obs: Optional[Obs] = None,
+                             loss_out: Optional[torch.Tensor] = None, stream=None) -> None:
+    """idm_sim_backward with no workspace: the library runs the forward
+    (checkpoints) and the backward in its static device scratch array."""
+    n, S = plan.n, plan.n_steps
+    prm = _params_c(plan, params, length)
+    _need(p0, "p0", torch.float64, n)
+    _need(v_init, "v_init", torch.float32, n)
+    _need(grad_params, "grad_params", torch.float64, 5 * n)
+    _need(grad_p0, "grad_p0", torch.float64, n)
+    _need(grad_v0, "grad_v0", torch.float64, n)
+    _opt(grad_traj_d, "grad_traj_d", torch.float32, (S + 1) * n)
+    _opt(grad_traj_v, "grad_traj_v", torch.float32, (S + 1) * n)
+    _opt(loss_out, "loss_out", torch.float64, 1)
+    oc = None
+    if obs is not None:
+        _need(obs.target, "obs.target", torch.float32, obs.n_obs * n)
+        oc = ctypes.byref(obs.c())
+    check(plan._L.idm_sim_backward_noalloc(plan.handle, ctypes.byref(prm), _ptr(p0), _ptr(v_init),
+                                           _ptr(grad_traj_d), _ptr(grad_traj_v), oc,
+                                           _ptr(grad_params), _ptr(grad_p0), _ptr(grad_v0),
+                                           _ptr(loss_out), _stream(stream)),
+          "idm_sim_backward_noalloc")
+
+
 def idm_plan_diagnostics(plan: Plan, workspace: torch.Tensor, out: Optional[torch.Tensor] = None,
                          stream=None) -> torch.Tensor:
     """Anomaly counts of the last forward that wrote `workspace`: a device int64
