@@ -261,14 +261,18 @@ idm_status idm_sim_backward_noalloc(idm_plan *plan, const idm_params *prm, const
 /* One gradient step of the trajectory fit (Sec. IV-A): forward (checkpoints
  * only), fused MSE loss and backward, then Adam on NORMALISED parameters
  * u = (theta - lo) / (hi - lo) followed by projection of u onto [0, 1] (the
- * paper's box constraints).  The physical parameters params[5*N] are
- * rewritten from u after the step and are what the simulation reads.
+ * paper's box constraints), or, with raw_units = 1, Adam on the physical
+ * parameters theta themselves with the learning rate in their own units
+ * followed by projection onto [lo, hi] (the paper's fitting, Sec. IV-A and
+ * Sec. V-B3).  The physical parameters params[5*N] are rewritten after the
+ * step and are what the simulation reads; u always holds
+ * (theta - lo) / (hi - lo).
  * All state lives in device memory, so a call can be captured in a HIP graph
  * and replayed (see idm_fit_run). */
 typedef struct {
     float *u;              /* [5*N] normalised parameters, updated */
-    float *m;              /* [5*N] Adam first moment, updated */
-    float *v;              /* [5*N] Adam second moment, updated */
+    float *m;              /* [5*N] Adam first moment (of dL/du, or of dL/dtheta with raw_units), updated */
+    float *v;              /* [5*N] Adam second moment (same variable), updated */
     float *params;         /* [5*N] physical parameters (v0, T, a, b, s0 blocks), rewritten */
     const float *length;   /* [N] vehicle lengths */
     int32_t *step;         /* device int32: Adam step counter t (0 before the first step), updated */
@@ -278,6 +282,7 @@ typedef struct {
     float lr0, lr1;        /* learning rate, linear from lr0 (t=0) to lr1 (t >= lr_steps) */
     int32_t lr_steps;      /* >= 1 */
     float beta1, beta2, eps;
+    int32_t raw_units;     /* 0: Adam on u; 1: Adam on theta (lr in the parameters' units) */
 } idm_fit_state;
 
 /* Start a fit from physical parameters init_params [5*N] (device FP32):

@@ -55,7 +55,7 @@ class IdmFitState(ctypes.Structure):
                 ("length", c_void_p), ("step", c_void_p), ("loss_hist", c_void_p),
                 ("hist_len", c_int32), ("lo", c_float * 5), ("hi", c_float * 5),
                 ("lr0", c_float), ("lr1", c_float), ("lr_steps", c_int32),
-                ("beta1", c_float), ("beta2", c_float), ("eps", c_float)]
+                ("beta1", c_float), ("beta2", c_float), ("eps", c_float), ("raw_units", c_int32)]
 
 
 class IdmMlpState(ctypes.Structure):

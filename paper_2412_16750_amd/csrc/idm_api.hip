@@ -619,6 +619,7 @@ AdamArgs adam_args(const idm_plan *p, const idm_fit_state *st, const double *gra
     a.beta1 = st->beta1;
     a.beta2 = st->beta2;
     a.eps = st->eps;
+    a.raw = st->raw_units ? 1 : 0;
     return a;
 }
 

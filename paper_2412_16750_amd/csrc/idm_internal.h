@@ -75,6 +75,7 @@ struct AdamArgs {
     float lr0, lr1;
     int32_t lr_steps;
     float beta1, beta2, eps;
+    int32_t raw;          // 1: Adam on the physical parameters (moments of dL/dtheta)
 };
 
 // Ego-only reconstruction (one vehicle per trajectory, per-step free gap and

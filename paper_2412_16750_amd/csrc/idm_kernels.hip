@@ -939,16 +939,24 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs A) {
          i += (int64_t)gridDim.x * blockDim.x) {
         int p = (int)(i / A.n);
         float span = A.hi[p] - A.lo[p];
-        float g = (float)(A.grad[i] * (double)span);
+        // normalised: the moments follow dL/du = span dL/dtheta; raw units
+        // (Sec. IV-A): they follow dL/dtheta and theta itself takes the step
+        float g = A.raw ? (float)A.grad[i] : (float)(A.grad[i] * (double)span);
         float m = A.beta1 * A.m[i] + (1.0f - A.beta1) * g;
         float v = A.beta2 * A.v[i] + (1.0f - A.beta2) * g * g;
         A.m[i] = m;
         A.v[i] = v;
         float mh = m / bc1, vh = v / bc2;
-        float u = A.u[i] - lr * mh / (sqrtf(vh) + A.eps);
-        u = fminf(fmaxf(u, 0.0f), 1.0f);
-        A.u[i] = u;
-        A.params[i] = A.lo[p] + u * span;
+        float step = lr * mh / (sqrtf(vh) + A.eps);
+        if (A.raw) {
+            float th = fminf(fmaxf(A.params[i] - step, A.lo[p]), A.hi[p]);
+            A.params[i] = th;
+            A.u[i] = (th - A.lo[p]) / span;
+        } else {
+            float u = fminf(fmaxf(A.u[i] - step, 0.0f), 1.0f);
+            A.u[i] = u;
+            A.params[i] = A.lo[p] + u * span;
+        }
     }
 }
 
@@ -964,7 +972,8 @@ __global__ __launch_bounds__(256) void k_fit_init(AdamArgs A, const float *init)
         A.u[i] = u;
         A.m[i] = 0.0f;
         A.v[i] = 0.0f;
-        A.params[i] = A.lo[p] + u * span;
+        // raw units start from theta itself (projected onto the box)
+        A.params[i] = A.raw ? fminf(fmaxf(init[i], A.lo[p]), A.hi[p]) : A.lo[p] + u * span;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *A.step_rw = 0;
 }

@@ -26,7 +26,8 @@ class Fitter:
     def __init__(self, plan: "sim.Plan", length: torch.Tensor, p0: torch.Tensor,
                  v_init: torch.Tensor, obs: "sim.Obs", boxes: Sequence = DEFAULT_BOXES,
                  lr0: float = 1e-2, lr1: Optional[float] = None, lr_steps: int = 1,
-                 hist_len: int = 4096, betas=(0.9, 0.999), eps: float = 1e-8):
+                 hist_len: int = 4096, betas=(0.9, 0.999), eps: float = 1e-8,
+                 raw_units: bool = False):
         n = plan.n
         dev = p0.device
         sim._need(length, "length", torch.float32, n)
@@ -54,6 +55,7 @@ class Fitter:
         st.lr1 = float(lr0 if lr1 is None else lr1)
         st.lr_steps = int(max(1, lr_steps))
         st.beta1, st.beta2, st.eps = float(betas[0]), float(betas[1]), float(eps)
+        st.raw_units = 1 if raw_units else 0
         self._st = st
         self._obs_c = obs.c()
         self.boxes = np.asarray(boxes, dtype=np.float64)

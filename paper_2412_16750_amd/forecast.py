@@ -1,6 +1,9 @@
 """Training-free trajectory forecasting (Sec. V-C): fit every vehicle's IDM
-parameters to a short observed history with the lane fit (Adam, box
-constraints) and roll the fitted lanes out from the starting state.
+parameters to a short observed history with the lane fit and roll the fitted
+lanes out from the starting state.  The fit follows the paper's optimisation
+(Sec. IV-A, Sec. V-B3): Adam on the parameters in their own units with the
+learning rate falling linearly from 0.1 to 0.01, then projection onto the
+boxes.
 
 Argument marshalling and evaluation only: the fit and the rollout are the
 library's fit graph and forward kernel.
@@ -18,12 +21,12 @@ from .fit import DEFAULT_BOXES, Fitter
 def fit_and_rollout(plan_history: "sim.Plan", plan_rollout: "sim.Plan", length: torch.Tensor,
                     p0: torch.Tensor, v_init: torch.Tensor, obs: "sim.Obs",
                     init_params: torch.Tensor, iters: int = 500, lr0: float = 0.1,
-                    lr1: float = 0.01, boxes: Sequence = DEFAULT_BOXES):
+                    lr1: float = 0.01, boxes: Sequence = DEFAULT_BOXES, raw_units: bool = True):
     """Fit on the history plan's steps, then simulate the rollout plan's steps
     from the same starting state; returns (params [5, N], displacements
     [(S_rollout + 1), N], fitter)."""
     f = Fitter(plan_history, length, p0, v_init, obs, boxes=boxes, lr0=lr0, lr1=lr1,
-               lr_steps=iters)
+               lr_steps=iters, raw_units=raw_units)
     f.init(init_params)
     f.run(iters)
     traj = torch.empty(plan_rollout.n_steps + 1, plan_rollout.n, dtype=torch.float32,

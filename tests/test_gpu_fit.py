@@ -113,3 +113,64 @@ def test_fit_reduces_the_loss_within_the_boxes():
     assert np.all(prm >= BOX_LO[:, None] - 1e-6) and np.all(prm <= BOX_HI[:, None] + 1e-6)
     u = f.u.cpu().numpy()
     assert u.min() >= 0.0 and u.max() <= 1.0
+
+
+@pytest.mark.parametrize("raw_units", [False, True])
+def test_scheduled_fit_matches_oracle_over_eight_steps(raw_units):
+    """Eight fit steps with the learning rate falling linearly from 0.1 to
+    0.01 (the schedule of Sec. V-B3) against the oracle's own eight steps from
+    the same start: oracle.fit.lr_at for the rate, adam_box_step (Adam on the
+    normalised parameters) or adam_raw_step (Adam on the parameters in their
+    own units, Sec. IV-A) for the update, the oracle's loss and adjoint for
+    the gradient.  The loss history agrees step by step, and the first step's
+    moments element by element."""
+    import torch
+    from oracle.fit import adam_raw_step, lr_at
+    sc, steps, tgt = _problem(seed_c=7)
+    lr0, lr1, n = 0.1, 0.01, 8
+    f, x = _fitter(sc, steps, tgt, lr=lr0, lr1=lr1, lr_steps=n, raw_units=raw_units)
+    f.init(_cold(sc.n, MID))
+    moments = None
+    for t in range(n):
+        f.step()
+        if t == 0:
+            torch.cuda.synchronize()
+            moments = (f.m.double().cpu().numpy(), f.v.double().cpu().numpy(),
+                       f.params.double().cpu().numpy())
+    torch.cuda.synchronize()
+    L_gpu = f.losses()
+    lo, hi = BOX_LO[:, None], BOX_HI[:, None]
+    th = np.repeat(MID[:, None], sc.n, axis=1).astype(np.float64)
+    u = (th - lo) / (hi - lo)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    L_or = []
+    for t in range(1, n + 1):
+        prm = {k: th[i] for i, k in enumerate(oracle.PARAM_NAMES)}
+        prm["length"] = sc.params["length"]
+        pb = oracle.Problem.from_scenario(sc, params=prm)
+        P, V, _, _ = oracle.forward(pb)
+        loss, gP = oracle.mse(P, steps, tgt.astype(np.float64))
+        g, _, _ = oracle.adjoint(pb, P, V, gP)
+        L_or.append(loss)
+        lr = lr_at(t, lr0, lr1, n)
+        if raw_units:
+            th, m, v = adam_raw_step(th, m, v, g, lo, hi, t, lr)
+        else:
+            u, m, v, th = adam_box_step(u, m, v, g, lo, hi, t, lr)
+        if t == 1:
+            ok_m, w_m = grad_close(moments[0], m)
+            ok_v, w_v = grad_close(moments[1], v)
+            d_th = float(np.max(np.abs(moments[2] - th) / (hi - lo)))
+            log("scheduled fit raw=%s step 1: moments worst/limit %.3f %.3f, params %.2e of the box"
+                % (raw_units, w_m, w_v, d_th))
+            assert ok_m and ok_v and d_th < 1e-5
+    L_or = np.asarray(L_or)
+    rel = np.abs(L_gpu - L_or) / L_or
+    log("scheduled fit raw=%s: loss gpu %s oracle %s, max rel %.2e"
+        % (raw_units, np.array2string(L_gpu, precision=5), np.array2string(L_or, precision=5),
+           rel.max()))
+    assert len(L_gpu) == n and rel.max() <= 1e-3
+    assert L_or[-1] < L_or[0]
+    # the rate really falls: the oracle's schedule reaches lr1 on the last step
+    assert lr_at(n + 1, lr0, lr1, n) == pytest.approx(lr1) and lr_at(1, lr0, lr1, n) == lr0
