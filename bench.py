@@ -33,8 +33,11 @@ if ROOT not in sys.path:
 # term by term in the design doc.
 FLOP_FWD = 40
 FLOP_BWD = 130
-# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA) with non-packed FP32.
-PEAK_FP32_VECTOR_TFLOPS = 78.6
+# MI355X published FP32 vector peak (packed FP32: two lanes' worth per
+# instruction); the kernels are built without packed FP32, so their own
+# ceiling is half of it: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA).
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_FP32_NON_PACKED_TFLOPS = 78.6
 PEAK_HBM_GBPS = 8000.0
 # Paper, Fig. 1 / Sec. V-A: < 30 ms per step for 2M vehicles in each of the
 # forward and backward passes (Xeon W-2255 x16 threads or RTX A5000).
@@ -182,23 +185,93 @@ def mlp_rates(ws, data, batch: int = 4096, steps: int = 100, reps: int = 5) -> d
             "flop_per_sample": {"forward": MLP_FWD_FLOP, "train": MLP_TRAIN_FLOP}}
 
 
-def copy_ms(dev, nbytes: int, reps: int) -> float:
-    """Mean time of the library's streaming copy kernel over `nbytes` bytes."""
+def copy_ms(dev, nbytes: int, reps: int, torch_copy: bool = False) -> float:
+    """Mean time of a streaming copy of `nbytes` bytes: the library's copy
+    kernel, or torch's own dst.copy_(src)."""
     import torch
     from paper_2412_16750_amd import sim
     a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     b = torch.empty_like(a)
     a.fill_(1)
+    run = (lambda: b.copy_(a)) if torch_copy else (lambda: sim.idm_copy_bytes(b, a))
     for _ in range(3):
-        sim.idm_copy_bytes(b, a)
+        run()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        sim.idm_copy_bytes(b, a)
+        run()
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def copy_ceiling(dev) -> dict:
+    """Measured HBM ceiling: read + write rate of a 1 GiB copy, the faster of
+    the library's unrolled non-temporal copy kernel and torch's copy_."""
+    nbytes = 1 << 30
+    lib = 2 * nbytes / (copy_ms(dev, nbytes, 10) / 1e3) / 1e9
+    tch = 2 * nbytes / (copy_ms(dev, nbytes, 10, torch_copy=True) / 1e3) / 1e9
+    return {"GBps": max(lib, tch), "library_copy_GBps": round(lib, 1),
+            "torch_copy_GBps": round(tch, 1)}
+
+
+def diagnostics(plan, ws) -> dict:
+    """Anomaly counts of the most recent forward that wrote `ws`."""
+    from paper_2412_16750_amd import sim
+    c = sim.idm_plan_diagnostics(plan, ws).cpu().tolist()
+    return {"gap_floor_evaluations": int(c[0]), "non_finite_vehicles": int(c[1])}
+
+
+def c1_latency(dev, log_fn, reps: int = 20) -> dict:
+    """Latency of one forward + backward on the single-lane workload (1 open
+    lane x 100 vehicles, 1000 steps of 0.1 s, fused MSE against a trajectory
+    simulated from a second parameter draw plus N(0, 0.5 m) noise), in both
+    bound modes; median over `reps` event-timed repetitions."""
+    import numpy as np
+    import torch
+    import scenarios
+    from paper_2412_16750_amd import sim
+    out = {}
+    for mode, name in ((scenarios.MODE_SOFTPLUS, "softplus"), (scenarios.MODE_CLAMP, "clamp")):
+        sc = scenarios.single_lane(mode=mode)
+        plan = sim.Plan.for_scenario(sc)
+        x = dict(prm=sim.params_tensor(sc.params, dev),
+                 length=torch.from_numpy(np.ascontiguousarray(sc.params["length"])).to(dev),
+                 p0=torch.from_numpy(np.ascontiguousarray(sc.p0)).to(dev),
+                 v=torch.from_numpy(np.ascontiguousarray(sc.v_init)).to(dev))
+        # target: the same lane under a second parameter draw, simulated here,
+        # plus noise (the seeded recipe of the parity tests)
+        tp = sim.params_tensor(scenarios.second_params(sc, 1), dev)
+        tr = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device=dev)
+        sim.idm_sim_forward(plan, tp, x["length"], x["p0"], x["v"], tr, None, None)
+        noise = torch.from_numpy(scenarios.noise((sc.n_steps, sc.n), 1).astype(np.float32)).to(dev)
+        tgt = (tr[1:].double() + x["p0"][None, :] + noise.double()).float().contiguous()
+        obs = sim.Obs(tgt, 1, 1)
+        ws = plan.workspace(dev)
+        gp = torch.empty(5, sc.n, dtype=torch.float64, device=dev)
+        g0 = torch.empty(sc.n, dtype=torch.float64, device=dev)
+        g1 = torch.empty_like(g0)
+        traj = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device=dev)
+        fwd = lambda: sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj, None, ws)
+        bwd = lambda: sim.idm_sim_backward(plan, x["prm"], x["length"], x["p0"], x["v"], gp, g0, g1,
+                                           ws, obs=obs)
+        fwd(); bwd()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        tf, tb = [], []
+        for _ in range(reps):
+            ev[0].record(); fwd(); ev[1].record(); bwd(); ev[2].record()
+            torch.cuda.synchronize()
+            tf.append(ev[0].elapsed_time(ev[1]))
+            tb.append(ev[1].elapsed_time(ev[2]))
+        out[name] = {"forward_ms": float(np.median(tf)), "backward_ms": float(np.median(tb)),
+                     "fwd_plus_bwd_ms": float(np.median(np.asarray(tf) + np.asarray(tb))),
+                     "diagnostics": diagnostics(plan, ws)}
+        log_fn("bench: single lane %s fwd %.3f ms bwd %.3f ms" % (name, out[name]["forward_ms"],
+                                                                out[name]["backward_ms"]))
+    return {"workload": "1 open lane x 100 vehicles, 1000 steps of 0.1 s, fused MSE vs a second "
+                        "parameter draw + N(0, 0.5 m)", **out}
 
 
 def fit_report(dev, log_fn, cap: int = 2000) -> dict:
@@ -270,7 +343,8 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
         perr[k] = float(np.median(rel[i, mask]))
     out["cold_200"] = {"ms_per_iteration": e0.elapsed_time(e1) / 200, "rmse_m": rmse200,
                        "median_rel_param_error": perr,
-                       "loss_first_last": [float(f.losses()[0]), float(f.losses()[-1])]}
+                       "loss_first_last": [float(f.losses()[0]), float(f.losses()[-1])],
+                       "diagnostics_last_iteration": diagnostics(plan, f.workspace)}
     # time to 0.5 m RMSE, cold and warm
     f = Fitter(plan, length, p0, v, obs, lr0=1e-2)
     f.init(cold)
@@ -452,7 +526,8 @@ def batched_report(dev, log_fn, reps: int = 10) -> dict:
             "autotuned_shape": tuned_info, "autotuned_ms": ms_tuned,
             "autotuned_vehicle_steps_per_s": vsteps / (ms_tuned / 1e3),
             "autotune_seconds": tune_s, "loss": loss_default,
-            "loss_after_autotune": b.loss.item()}
+            "loss_after_autotune": b.loss.item(),
+            "diagnostics": diagnostics(plan, b.workspace)}
 
 
 def forecast_report(dev, log_fn, iters: int = 500) -> dict:
@@ -530,6 +605,8 @@ def main():
                     help="skip the time-per-step against vehicle-count sweep")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the many-uneven-lanes graph replay and autotuner section")
+    ap.add_argument("--no-c1", action="store_true",
+                    help="skip the single-lane (100 vehicles x 1000 steps) latency section")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -565,8 +642,11 @@ def main():
     if args.copy_only:
         nbytes = 1 << 30
         ms = copy_ms(dev, nbytes, 20)
+        tms = copy_ms(dev, nbytes, 20, torch_copy=True)
         print(json.dumps({"copy_bytes": nbytes, "copy_ms": ms,
-                          "copy_GBps_read_plus_write": 2 * nbytes / ms / 1e6}))
+                          "copy_GBps_read_plus_write": 2 * nbytes / ms / 1e6,
+                          "torch_copy_ms": tms,
+                          "torch_copy_GBps_read_plus_write": 2 * nbytes / tms / 1e6}))
         return
 
     sc = scenarios.scale(ckpt_every=args.ckpt)
@@ -632,19 +712,24 @@ def main():
     same_kernel = h.hexdigest() == TRAFFIC_KERNEL_SHA256
     traffic = TRAFFIC_BWD_BYTES if (same_kernel and info["ckpt_every"] == 32 and info["block"] == 16
                                     and info["threads"] == 1024 and info["per_thread"] == 1) else None
+    diag = diagnostics(plan, ws)
     # measured HBM ceiling: read + write rate of a 1 GiB streaming copy
-    copy_gbps = 2 * (1 << 30) / (copy_ms(dev, 1 << 30, 10) / 1e3) / 1e9
+    ceil = copy_ceiling(dev)
+    copy_gbps = ceil["GBps"]
     bwd_gbps = bwd_bytes / (bwd_ms / 1e3) / 1e9
     fwd_gbps = fwd_bytes / (fwd_ms / 1e3) / 1e9
     roofline = {
         "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
+        "peak_non_packed": PEAK_FP32_NON_PACKED_TFLOPS,
+        "frac_non_packed": round(achieved / PEAK_FP32_NON_PACKED_TFLOPS, 4),
         "kernel": "k_backward<softplus,R=%d,threads=%d,KB=%d> (K=%d)"
                   % (info["per_thread"], info["threads"], info["block"], info["ckpt_every"]),
         "kernel_ms": round(bwd_ms, 4), "flop_per_vehicle_step": FLOP_BWD,
         "hbm_algorithmic_GBps": round(bwd_gbps, 1),
         "hbm_frac": round(bwd_gbps / PEAK_HBM_GBPS, 4),
         "copy_ceiling_GBps": round(copy_gbps, 1),
+        "copy_ceiling": {k: v for k, v in ceil.items() if k != "GBps"},
         "hbm_frac_of_copy": round(bwd_gbps / copy_gbps, 4),
         "forward": {"kernel_ms": round(fwd_ms, 4),
                     "achieved_TFLOPs": round(FLOP_FWD * vsteps / (fwd_ms / 1e3) / 1e12, 3),
@@ -666,7 +751,13 @@ def main():
                    "n_vehicles": N, "n_steps": S, "ckpt_every": info["ckpt_every"],
                    "threads": info["threads"], "per_thread": info["per_thread"]},
         "roofline": roofline,
+        "us_per_simulated_step": {"forward": round(1e3 * fwd_ms / S, 4),
+                                  "backward": round(1e3 * bwd_ms / S, 4),
+                                  "fwd_plus_bwd": round(1e3 * ms_per_step / S, 4)},
+        "diagnostics": diag,
     }
+    if not args.no_c1:
+        out["single_lane_latency"] = c1_latency(dev, log)
     if not args.no_fit:
         log("bench: fitting and warm start")
         del x, obs, traj_d, ws, gp, gp0, gv0

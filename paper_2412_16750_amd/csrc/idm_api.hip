@@ -834,8 +834,8 @@ idm_status idm_copy_bytes(void *dst, const void *src, size_t bytes, void *stream
         return fail(IDM_ERR_INVALID_ARG, "copy needs 16-byte aligned pointers and sizes");
     if (bytes == 0) return IDM_OK;
     int64_t n16 = (int64_t)(bytes / 16);
-    int64_t g = (n16 + 255) / 256;
-    int grid = (int)std::min<int64_t>(g, 256 * 32);
+    int64_t g = (n16 + 1023) / 1024;  // chunks of 1024 16-byte words per work-group
+    int grid = (int)std::min<int64_t>(g, 256 * 16);
     hipError_t e = launch_copy(src, dst, n16, grid, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "copy launch");
     return IDM_OK;

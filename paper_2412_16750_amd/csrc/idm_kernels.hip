@@ -991,11 +991,26 @@ __global__ __launch_bounds__(256) void k_params_from_u(AdamArgs A) {
 
 // Plain streaming copy (16-byte vectors, grid-stride): the measured HBM ceiling
 // and the calibration reference of the hardware byte counters.
-__global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+// Streaming copy (HBM ceiling and byte-counter calibration): each work-group
+// moves chunks of 1024 16-byte words, four coalesced loads in flight per
+// thread before its four stores, all non-temporal (the data is touched once).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
                                               int64_t n16) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
-         i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const int64_t stride = (int64_t)gridDim.x * 1024;
+    for (int64_t base = (int64_t)blockIdx.x * 1024; base < n16; base += stride) {
+        u32x4 x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = base + j * 256 + threadIdx.x;
+            if (i < n16) x[j] = __builtin_nontemporal_load(&src[i]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = base + j * 256 + threadIdx.x;
+            if (i < n16) __builtin_nontemporal_store(x[j], &dst[i]);
+        }
+    }
 }
 
 // Observed positions from a displacement trajectory: out[j][i] =
@@ -1199,7 +1214,7 @@ static int elementwise_grid(int64_t total) {
 }
 
 hipError_t launch_copy(const void *src, void *dst, int64_t n16, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n16);
+    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, s, (const u32x4 *)src, (u32x4 *)dst, n16);
     return hipGetLastError();
 }
 
