@@ -558,7 +558,8 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
 #pragma unroll
         for (int r = 0; r < R; ++r) lossf[r] = 0.0f;
         // upstream of the last step (the seed), and prefetch of step S-1
-        Up seed[R], nxt[R];
+        // (two steps ahead: nxt = step k-1, nxt2 = step k-2 while step k is swept)
+        Up seed[R], nxt[R], nxt2[R];
         UpCursor cur_k;
         cursor_init(A, S, cur_k);
         fetch_up<R, DN>(A, cur_k, q, true, seed);
@@ -566,6 +567,9 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
         cursor_dec(A, cur_k);
         fetch_up<R, DN>(A, cur_k, q, S > 0, nxt);
         bool obs_nxt = S > 0 && cursor_obs(cur_k);
+        cursor_dec(A, cur_k);
+        fetch_up<R, DN>(A, cur_k, q, S > 1, nxt2);
+        bool obs_nxt2 = S > 1 && cursor_obs(cur_k);
         // checkpoint of the last block
         float ckd[R], ckv[R];
 #pragma unroll
@@ -731,12 +735,16 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
                     const int k = ks + j;
                     Up cur[R];
 #pragma unroll
-                    for (int r = 0; r < R; ++r) cur[r] = nxt[r];
+                    for (int r = 0; r < R; ++r) {
+                        cur[r] = nxt[r];
+                        nxt[r] = nxt2[r];
+                    }
                     const bool obs_cur = obs_nxt;
-                    // prefetch step k-1 (nothing is read past step 0)
+                    obs_nxt = obs_nxt2;
+                    // prefetch step k-2 (nothing is read past step 0)
                     cursor_dec(A, cur_k);
-                    fetch_up<R, DN>(A, cur_k, q, k > 0, nxt);
-                    obs_nxt = k > 0 && cursor_obs(cur_k);
+                    fetch_up<R, DN>(A, cur_k, q, k > 1, nxt2);
+                    obs_nxt2 = k > 1 && cursor_obs(cur_k);
                     // boundary rows of this step: the leader state of step k-1
                     // and the next piece head's contribution at step k
                     float2 Xl = make_float2(0.0f, 0.0f), Xf = make_float2(0.0f, 0.0f);
