@@ -488,11 +488,16 @@ def batched_report(dev, log_fn, reps: int = 10) -> dict:
     import torch
     import scenarios
     from paper_2412_16750_amd import sim
-    sc = scenarios.uneven(ckpt_every=32)
+    # the checkpoint interval K is left free (ckpt_every = 0): the default plan
+    # takes K = 32, the autotuner chooses K with the launch shape, among the
+    # shapes whose workspace fits the room given for K = 8
+    sc = scenarios.uneven(ckpt_every=0)
     x, obs = build_inputs(sc, dev)
     plan = sim.Plan.for_scenario(sc)
+    room = sim.Plan.for_scenario(sc, ckpt_every=8, threads=1024, per_thread=1).workspace_bytes
     traj = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device=dev)
-    b = sim.StepBuffers(plan, x["prm"], x["length"], x["p0"], x["v"], traj_d=traj, obs=obs)
+    b = sim.StepBuffers(plan, x["prm"], x["length"], x["p0"], x["v"], traj_d=traj, obs=obs,
+                        workspace_bytes=room)
     vsteps = float(sc.n) * sc.n_steps
 
     def timed():
@@ -515,6 +520,14 @@ def batched_report(dev, log_fn, reps: int = 10) -> dict:
     tune_s = time.perf_counter() - t0
     tuned_info = {k: tuned[k] for k in keep}
     ms_tuned = timed()
+    # an equal problem again: the cached choice, no timing
+    plan2 = sim.Plan.for_scenario(sc)
+    b2 = sim.StepBuffers(plan2, x["prm"], x["length"], x["p0"], x["v"], traj_d=traj, obs=obs,
+                         workspace_bytes=room)
+    t0 = time.perf_counter()
+    again = sim.idm_plan_autotune(b2, reps=2)
+    again_s = time.perf_counter() - t0
+    del b2, plan2
     sizes = np.diff(sc.lane_offsets)
     log_fn("bench: uneven %d lanes, %d vehicles: default %s %.3f ms, autotuned %s %.3f ms"
            % (sc.n_lanes, sc.n, default_info, ms_default, tuned_info, ms_tuned))
@@ -525,7 +538,10 @@ def batched_report(dev, log_fn, reps: int = 10) -> dict:
             "default_vehicle_steps_per_s": vsteps / (ms_default / 1e3),
             "autotuned_shape": tuned_info, "autotuned_ms": ms_tuned,
             "autotuned_vehicle_steps_per_s": vsteps / (ms_tuned / 1e3),
-            "autotune_seconds": tune_s, "loss": loss_default,
+            "autotune_seconds": tune_s,
+            "autotune_again": {"cached": bool(again["autotune_cached"]), "seconds": again_s,
+                               "same_shape": {k: again[k] for k in keep} == tuned_info},
+            "loss": loss_default,
             "loss_after_autotune": b.loss.item(),
             "diagnostics": diagnostics(plan, b.workspace)}
 

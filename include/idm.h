@@ -148,6 +148,7 @@ typedef struct {
     double fill;            /* N / n_slots */
     int32_t n_levels;       /* launches per pass: 1 + most extra pieces of one lane */
     int32_t n_boundaries;   /* piece boundaries of lanes longer than a bundle */
+    int32_t autotune_cached; /* 1: the last idm_plan_autotune took its shape from the cache */
 } idm_plan_info;
 idm_status idm_plan_get_info(const idm_plan *plan, idm_plan_info *out);
 
@@ -323,10 +324,16 @@ typedef struct {
 idm_status idm_step_graph_launch(idm_plan *plan, const idm_step_args *args, void *stream);
 
 /* Autotuner: times forward + backward of every candidate launch shape
- * (threads x per_thread x KB, with K the problem's or, left free, KB and 2 KB
- * where the LDS stash exists) whose lanes fit and whose workspace fits in
- * `workspace_bytes`, `reps` times each, on the real inputs, and switches the
- * plan to the fastest.  Shapes whose backward spills registers are timed only
+ * (threads x per_thread x KB, with K the problem's or, left free
+ * (ckpt_every = 0 at plan creation), KB and 2 KB where the LDS stash exists)
+ * whose lanes fit and whose workspace fits in `workspace_bytes`, `reps` times
+ * each, on the real inputs, and switches the plan to the fastest.  The choice
+ * is cached for the process, keyed by the sorted lane sizes (the lane-size
+ * histogram), S, the bound mode, the kind of upstream gradient, a fixed K
+ * and the device's compute-unit count: a later call for an equal problem
+ * takes the cached shape without timing (idm_plan_info.autotune_cached = 1)
+ * when its workspace fits.  To keep a choice across processes, read it with
+ * idm_plan_get_info and pass it as idm_tuning to idm_plan_create.  Shapes whose backward spills registers are timed only
  * when no other shape holds the longest lane (lanes above 2048 vehicles).  Synchronises `stream`.  Results of the timed runs are
  * discarded (they overwrite the output buffers).  Any graph captured by the
  * plan is dropped. */

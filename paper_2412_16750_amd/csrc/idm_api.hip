@@ -109,6 +109,7 @@ struct idm_plan {
     // get a plan-owned side stream (default priority), joined by events
     hipStream_t side = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int32_t tuned_cached = 0;  // the last autotune took its shape from the cache
 };
 
 namespace {
@@ -797,6 +798,33 @@ float plan_dt(const idm_plan *p) { return p ? p->pb.dt : 0.0f; }
 
 namespace {
 
+// Autotuner cache: the shape chosen for a problem signature, kept for the
+// process (FNV-1a over the sorted lane sizes and the problem's scalars).
+std::mutex g_tune_mu;
+std::map<uint64_t, Shape> g_tune_cache;
+
+uint64_t tune_key(const idm_plan *p, bool dense, bool obs, int cus) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](uint64_t x) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (x >> (8 * i)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    };
+    std::vector<int32_t> sizes((size_t)p->pb.n_lanes);
+    for (int l = 0; l < p->pb.n_lanes; ++l) sizes[l] = p->offsets[l + 1] - p->offsets[l];
+    std::sort(sizes.begin(), sizes.end());
+    mix(sizes.size());
+    for (int32_t z : sizes) mix((uint64_t)(uint32_t)z);
+    mix((uint64_t)p->pb.n_steps);
+    mix((uint64_t)p->pb.bound);
+    mix((uint64_t)(uint32_t)p->pb.ckpt_every);  // 0 = free
+    mix(dense ? 1 : 0);
+    mix(obs ? 1 : 0);
+    mix((uint64_t)cus);
+    return h;
+}
+
 // Device address of the current GPU's copy of `scratch`, looked up once per
 // device (hipGetSymbolAddress, with that device current) and kept.
 constexpr int kMaxDevices = 64;
@@ -946,6 +974,7 @@ idm_status idm_plan_get_info(const idm_plan *p, idm_plan_info *o) {
     o->fill = p->n_slots ? (double)p->pb.n_vehicles / (double)p->n_slots : 0.0;
     o->n_levels = n_levels(p);
     o->n_boundaries = p->n_bnd;
+    o->autotune_cached = p->tuned_cached;
     return IDM_OK;
 }
 
@@ -1145,6 +1174,22 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (cus <= 0) cus = 256;
+    const uint64_t key = tune_key(p, dense, a->obs_target != nullptr, cus);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            const Shape c = it->second;
+            const int64_t nb = count_boundaries(p->offsets, p->pb.n_lanes,
+                                                (int64_t)c.threads * c.per_thread);
+            if (ws_total(p, c.K, nb) <= ws_bytes) {
+                r = build_layout(p, c);
+                if (r != IDM_OK) return r;
+                p->tuned_cached = 1;
+                return IDM_OK;
+            }
+        }
+    }
     std::vector<Shape> cands, spilling;
     // the checkpoint interval the caller fixed is kept; otherwise K = KB
     const bool k_fixed = p->pb.ckpt_every > 0;
@@ -1232,6 +1277,11 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
     hipEventDestroy(e1);
     idm_status r2 = build_layout(p, r == IDM_OK ? best_sh : orig);
     if (r != IDM_OK) return r;
+    if (r2 == IDM_OK) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune_cache[key] = best_sh;
+        p->tuned_cached = 0;
+    }
     return r2;
 }
 
@@ -1246,6 +1296,7 @@ struct idm_ego_plan {
     std::vector<unsigned char> fit_key;
     hipStream_t side = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int32_t tuned_cached = 0;  // the last autotune took its shape from the cache
 };
 
 namespace {

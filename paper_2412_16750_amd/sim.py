@@ -234,7 +234,11 @@ class StepBuffers:
     the autotuner and the benchmark)."""
 
     def __init__(self, plan: Plan, params, length, p0, v_init, traj_d=None, traj_v=None,
-                 grad_traj_d=None, grad_traj_v=None, obs: Optional[Obs] = None, device="cuda"):
+                 grad_traj_d=None, grad_traj_v=None, obs: Optional[Obs] = None, device="cuda",
+                 workspace_bytes: int = 0):
+        """workspace_bytes: room beyond the plan's own need (the autotuner
+        only times shapes whose workspace fits, e.g. shorter checkpoint
+        intervals when K is left free)."""
         n = plan.n
         self.plan = plan
         self.params, self.length, self.p0, self.v_init = params, length, p0, v_init
@@ -245,7 +249,8 @@ class StepBuffers:
         self.grad_p0 = torch.empty(n, dtype=torch.float64, device=device)
         self.grad_v0 = torch.empty(n, dtype=torch.float64, device=device)
         self.loss = torch.zeros(1, dtype=torch.float64, device=device)
-        self.workspace = plan.workspace(device)
+        self.workspace = torch.empty(max(plan.workspace_bytes, int(workspace_bytes), 1),
+                                     dtype=torch.uint8, device=device)
         self._validate()
 
     def _validate(self):

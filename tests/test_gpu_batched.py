@@ -127,3 +127,57 @@ def test_uneven_workload_full_size_sampled_lanes():
     ok1, w1 = grad_close(b.grad_v0[it].cpu().numpy(), ref["gv0"] * fac)
     log("uneven full: gradient worst/limit %.3f %.3f %.3f" % (wg, w0, w1))
     assert okg and ok0 and ok1
+
+
+def test_autotuner_chooses_k_and_caches_the_choice():
+    """With the checkpoint interval left free the autotuner also picks K (KB
+    or 2 KB of each candidate's backward block) from the shapes whose
+    workspace fits: the tuned plan's trajectory is bitwise the default's (the
+    forward does not depend on K), its gradients match the oracle and the
+    default's to within the FP32 block sums' regrouping; a second plan for the
+    same problem takes the cached shape without timing."""
+    import torch
+    from paper_2412_16750_amd import sim
+    sc = _uneven(400, 1024, 64, K=0, c=33)
+    steps = np.arange(1, sc.n_steps + 1)
+    P2, _, _, _ = oracle.forward(oracle.Problem.from_scenario(sc, params=scenarios.second_params(sc, 33)))
+    tgt = (P2[steps] + scenarios.noise((len(steps), sc.n), 33)).astype(np.float32)
+    # room for the shortest checkpoint interval a candidate can take (K = 8)
+    room = sim.Plan.for_scenario(sc, ckpt_every=8, threads=1024, per_thread=1).workspace_bytes
+    plan, b = _buffers(sc, steps, tgt)
+    b = sim.StepBuffers(plan, b.params, b.length, b.p0, b.v_init, traj_d=b.traj_d, obs=b.obs,
+                        workspace_bytes=room)
+    default = plan.info()
+    b.run_eager()
+    torch.cuda.synchronize()
+    before = _snapshot(b)
+    info = sim.idm_plan_autotune(b, reps=2)
+    log("autotuner, free K: default %s -> chose %s" % (default, info))
+    assert info["autotune_cached"] == 0
+    assert info["ckpt_every"] in (8, 16, 32, 64) and info["ckpt_every"] % info["block"] == 0
+    b.run_eager()
+    torch.cuda.synchronize()
+    after = _snapshot(b)
+    assert torch.equal(after[0], before[0])
+    ref = oracle_reference(sc, steps, tgt)
+    for name, a_, e_, r_ in (("params", after[1], before[1], ref["g"]),
+                             ("p0", after[2], before[2], ref["gp0"]),
+                             ("v0", after[3], before[3], ref["gv0"])):
+        ok, w = grad_close(a_.cpu().numpy(), r_)
+        rel = float((a_ - e_).abs().max() / e_.abs().max())
+        log("autotuned K=%d: %s gradient worst/limit %.3f vs oracle, max |diff| / max |g| %.2e "
+            "vs the default K" % (info["ckpt_every"], name, w, rel))
+        assert ok and rel <= 1e-5
+    assert abs(after[4].item() - ref["loss"]) <= 1e-4 * ref["loss"]
+    # a second plan for the same problem: the cached choice, no timing
+    plan2, b2 = _buffers(sc, steps, tgt)
+    b2 = sim.StepBuffers(plan2, b2.params, b2.length, b2.p0, b2.v_init, traj_d=b2.traj_d,
+                         obs=b2.obs, workspace_bytes=room)
+    info2 = sim.idm_plan_autotune(b2, reps=2)
+    log("autotuner, second plan: %s" % info2)
+    assert info2["autotune_cached"] == 1
+    keep = ("threads", "per_thread", "ckpt_every", "block", "grid", "n_bundles")
+    assert {k: info2[k] for k in keep} == {k: info[k] for k in keep}
+    b2.run_eager()
+    torch.cuda.synchronize()
+    assert torch.equal(b2.grad_params, after[1]) and torch.equal(b2.traj_d, after[0])
