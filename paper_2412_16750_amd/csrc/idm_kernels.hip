@@ -906,18 +906,31 @@ __global__ __launch_bounds__(256) void k_loss_finalize(const double *part, int32
     if (threadIdx.x == 0) *out = tot * scale;
 }
 
-// Fixed-order sum of the per-bundle diagnostic counts [n][2] (one thread:
-// the counts are small and integer sums need no tree).
-__global__ __launch_bounds__(64) void k_diag_finalize(const uint64_t *part, int32_t n,
-                                                      int64_t *out) {
-    if (threadIdx.x != 0) return;
+// Sum of the per-bundle diagnostic counts [n][2]: integer sums, so the
+// result does not depend on the order; 256 threads stride over the bundles,
+// then a shared-memory tree.
+__global__ __launch_bounds__(256) void k_diag_finalize(const uint64_t *part, int32_t n,
+                                                       int64_t *out) {
+    __shared__ uint64_t red[2][256];
     uint64_t s0 = 0, s1 = 0;
-    for (int i = 0; i < n; ++i) {
+    for (int i = threadIdx.x; i < n; i += 256) {
         s0 += part[2 * (int64_t)i];
         s1 += part[2 * (int64_t)i + 1];
     }
-    out[0] = (int64_t)s0;
-    out[1] = (int64_t)s1;
+    red[0][threadIdx.x] = s0;
+    red[1][threadIdx.x] = s1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = (int64_t)red[0][0];
+        out[1] = (int64_t)red[1][0];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_fit_finalize(const double *part, int32_t n, double scale,
@@ -1205,7 +1218,7 @@ hipError_t launch_loss_finalize(const double *part, int32_t n_part, double scale
 }
 
 hipError_t launch_diag_finalize(const uint64_t *part, int32_t n_part, int64_t *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_diag_finalize, dim3(1), dim3(64), 0, s, part, n_part, out);
+    hipLaunchKernelGGL(k_diag_finalize, dim3(1), dim3(256), 0, s, part, n_part, out);
     return hipGetLastError();
 }
 
