@@ -428,6 +428,33 @@ idm_status idm_mlp_train_step(const idm_mlp_state *st, const uint16_t *X, const 
                               int64_t batch, int32_t t, double *loss_out, void *workspace,
                               void *stream);
 
+/* Training loop state that lives in device memory, so that every step of a
+ * loop is the same call and one step can be captured in a HIP graph and
+ * replayed (the learning rate, the step number and the batch rows are read
+ * on the device). */
+typedef struct {
+    int32_t *step;        /* device int32: steps done (0 before the first), incremented */
+    float lr0, lr_final;  /* learning rate of step t: lr_final + (lr0 - lr_final) *
+                             (1 + cos(pi (t - 1) / total_steps)) / 2, in FP64 then rounded */
+    int32_t total_steps;  /* >= 1 */
+    double *loss_hist;    /* device [hist_len] FP64: loss of step t at (t - 1) % hist_len */
+    int32_t hist_len;     /* >= 1 */
+} idm_mlp_schedule;
+
+/* One scheduled Adam step: t = ++(*sched->step); the batch is rows
+ * perm[((t - 1) % (n_rows / batch)) * batch + i], i < batch, of X_all
+ * [n_rows x IN_PAD] (BF16) and U_all [n_rows x 5] (FP32), gathered into Xb
+ * [batch x IN_PAD] and Ub [batch x 5] (device, caller-owned); then the step of
+ * idm_mlp_train_step with that t and the scheduled rate, and the loss into
+ * loss_hist.  perm (device int64 [n_rows], a permutation) may be rewritten
+ * between calls (one epoch per permutation).  batch <= n_rows; workspace as
+ * idm_mlp_workspace_bytes(batch).  No host synchronisation, no allocation:
+ * graph-capturable. */
+idm_status idm_mlp_train_step_scheduled(const idm_mlp_state *st, const uint16_t *X_all,
+                                        const float *U_all, int64_t n_rows, const int64_t *perm,
+                                        int64_t batch, const idm_mlp_schedule *sched,
+                                        uint16_t *Xb, float *Ub, void *workspace, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Ego-only reconstruction (Sec. IV-A, trajectory filtering and reconstruction).
  * Every trajectory is one vehicle starting at p(0) = 0 whose leader is not

@@ -64,6 +64,11 @@ class IdmMlpState(ctypes.Structure):
                 ("eps", c_float)]
 
 
+class IdmMlpSchedule(ctypes.Structure):
+    _fields_ = [("step", c_void_p), ("lr0", c_float), ("lr_final", c_float),
+                ("total_steps", c_int32), ("loss_hist", c_void_p), ("hist_len", c_int32)]
+
+
 MLP_IN, MLP_IN_PAD, MLP_HIDDEN, MLP_OUT, MLP_OUT_PAD = 150, 160, 256, 5, 16
 
 
@@ -108,7 +113,8 @@ EXPORTS = ("idm_plan_create", "idm_plan_destroy", "idm_workspace_bytes", "idm_pl
            "idm_step_graph_launch", "idm_plan_autotune", "idm_copy_bytes", "idm_last_error",
            "idm_version", "idm_mlp_param_count", "idm_mlp_weight_bf16_count",
            "idm_mlp_workspace_bytes", "idm_mlp_sync", "idm_mlp_features", "idm_mlp_forward",
-           "idm_mlp_gradients", "idm_mlp_train_step", "idm_fit_init_normalized", "idm_observe",
+           "idm_mlp_gradients", "idm_mlp_train_step", "idm_mlp_train_step_scheduled",
+           "idm_fit_init_normalized", "idm_observe",
            "idm_lane_loss", "idm_select_by_lane",
            "idm_ego_plan_create", "idm_ego_plan_destroy", "idm_ego_workspace_bytes",
            "idm_ego_match_steps", "idm_ego_initial_speed", "idm_ego_forward", "idm_ego_backward",
@@ -172,6 +178,9 @@ def load() -> ctypes.CDLL:
                                     c_void_p, c_void_p]
     L.idm_mlp_train_step.argtypes = [P(IdmMlpState), c_void_p, c_void_p, c_int64, c_int32, c_void_p,
                                      c_void_p, c_void_p]
+    L.idm_mlp_train_step_scheduled.argtypes = [P(IdmMlpState), c_void_p, c_void_p, c_int64,
+                                               c_void_p, c_int64, P(IdmMlpSchedule), c_void_p,
+                                               c_void_p, c_void_p, c_void_p]
     L.idm_fit_init_normalized.argtypes = [c_void_p, P(IdmFitState), c_void_p, c_int32, c_void_p]
     L.idm_observe.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32,
                               c_void_p, c_void_p]
@@ -179,7 +188,8 @@ def load() -> ctypes.CDLL:
     L.idm_select_by_lane.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_void_p]
     for name in ("idm_mlp_sync", "idm_mlp_features", "idm_mlp_forward", "idm_mlp_gradients",
-                 "idm_mlp_train_step", "idm_fit_init_normalized", "idm_observe", "idm_lane_loss",
+                 "idm_mlp_train_step", "idm_mlp_train_step_scheduled", "idm_fit_init_normalized",
+                 "idm_observe", "idm_lane_loss",
                  "idm_select_by_lane"):
         getattr(L, name).restype = c_int32
     L.idm_ego_plan_create.argtypes = [P(IdmEgoProblem), P(c_void_p)]

@@ -21,7 +21,7 @@ import numpy as np
 import torch
 
 from . import _lib, sim
-from ._lib import MLP_IN_PAD, MLP_OUT, MLP_OUT_PAD, IdmMlpState, IdmObs, check
+from ._lib import MLP_IN_PAD, MLP_OUT, MLP_OUT_PAD, IdmMlpSchedule, IdmMlpState, IdmObs, check
 from .fit import DEFAULT_BOXES, Fitter
 
 
@@ -87,6 +87,91 @@ class MLP:
                                              self.t, sim._ptr(loss_out),
                                              sim._ptr(self.workspace(B)), sim._stream()),
               "idm_mlp_train_step")
+
+
+class ScheduledTrainer:
+    """Device-side state of a training loop whose steps are all the same call
+    (idm_mlp_train_step_scheduled): step counter, learning-rate cosine, the
+    epoch's row permutation and fixed batch buffers.  `step()` runs one step
+    eagerly; `capture()` records one step in a HIP graph, which `replay()`
+    launches (the counter, the rate and the batch rows advance on the device,
+    so every replay is the next step)."""
+
+    def __init__(self, mlp: "MLP", data: "Dataset", batch: int, total_steps: int,
+                 lr_final: Optional[float] = None):
+        dev = data.X.device
+        n = int(data.X.shape[0])
+        if batch > n:
+            raise ValueError("batch larger than the data")
+        self.mlp, self.data, self.batch = mlp, data, int(batch)
+        self.n_batches = n // self.batch
+        self.perm = torch.arange(n, dtype=torch.int64, device=dev)
+        self.Xb = torch.empty(self.batch, MLP_IN_PAD, dtype=torch.bfloat16, device=dev)
+        self.Ub = torch.empty(self.batch, MLP_OUT, dtype=torch.float32, device=dev)
+        self.counter = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.loss_hist = torch.zeros(max(self.n_batches, 1), dtype=torch.float64, device=dev)
+        self.ws = torch.empty(int(_lib.load().idm_mlp_workspace_bytes(self.batch)),
+                              dtype=torch.uint8, device=dev)
+        sc = IdmMlpSchedule()
+        sc.step, sc.loss_hist = self.counter.data_ptr(), self.loss_hist.data_ptr()
+        sc.lr0 = float(mlp._st.lr)
+        sc.lr_final = float(mlp._st.lr if lr_final is None else lr_final)
+        sc.total_steps = int(max(1, total_steps))
+        sc.hist_len = int(self.loss_hist.numel())
+        self._sc = sc
+        self.graph = None
+
+    def set_permutation(self, perm: torch.Tensor) -> None:
+        """Rows of the next epoch (copied into the fixed permutation buffer)."""
+        self.perm.copy_(perm.to(self.perm.device, non_blocking=False))
+
+    def step(self) -> None:
+        check(_lib.load().idm_mlp_train_step_scheduled(
+            ctypes.byref(self.mlp._st), sim._ptr(self.data.X), sim._ptr(self.data.U),
+            int(self.data.X.shape[0]), sim._ptr(self.perm), self.batch, ctypes.byref(self._sc),
+            sim._ptr(self.Xb), sim._ptr(self.Ub), sim._ptr(self.ws), sim._stream()),
+            "idm_mlp_train_step_scheduled")
+
+    def capture(self) -> None:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        self.graph = g
+
+    def replay(self) -> None:
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()
+
+    def steps_done(self) -> int:
+        return int(self.counter.item())
+
+
+def train_graph(mlp: "MLP", data: "Dataset", batch: int = 4096, epochs: int = 10, seed: int = 0,
+                log=None, lr_final: Optional[float] = None) -> dict:
+    """The minibatch Adam loop of `train` with every step a replay of one
+    captured HIP graph: a fresh row permutation per epoch (the same generator
+    and seed as `train`), the learning-rate cosine and the step counter on the
+    device.  The epoch's training loss is the mean of its steps' losses."""
+    n = data.X.shape[0]
+    nb = n // batch
+    tr = ScheduledTrainer(mlp, data, batch, max(epochs * nb, 1), lr_final)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    hist = []
+    tr.capture()  # records one step; nothing runs yet
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        tr.set_permutation(torch.randperm(n, generator=g))
+        for _ in range(nb):
+            tr.replay()
+        rec = {"epoch": ep, "train_mse": float(tr.loss_hist[:nb].mean().item())}
+        hist.append(rec)
+        if log:
+            log("mlp epoch %d: %s" % (ep, rec))
+    torch.cuda.synchronize()
+    mlp.t = tr.steps_done()
+    return {"history": hist, "seconds": time.perf_counter() - t0, "steps": epochs * nb}
 
 
 def observe(plan, traj_d, p0, noise, obs_first, obs_stride, n_obs) -> torch.Tensor:

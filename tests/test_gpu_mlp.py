@@ -293,3 +293,81 @@ def test_warm_start_end_to_end_small():
             % (mode, res[mode]["curve"][0][1], res[mode]["iterations"], res[mode]["rmse"]))
     assert res["warm"]["curve"][0][1] < res["cold"]["curve"][0][1]
     assert res["warm"]["reached"] and res["warm"]["iterations"] < res["cold"]["iterations"]
+
+
+def _random_pairs(n, seed):
+    import torch
+    from paper_2412_16750_amd import warmstart as ws
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    X = torch.zeros(n, 160)
+    X[:, :150] = torch.randn(n, 150, generator=g)
+    U = torch.rand(n, 5, generator=g)
+    return ws.Dataset(X.to(torch.bfloat16).cuda(), U.cuda())
+
+
+def test_scheduled_training_step_graph_replays_match_eager_steps():
+    """One scheduled training step captured in a HIP graph and replayed: after
+    every replay (with unrelated eager work and synchronisations between the
+    replays) the weights, BF16 copies, Adam moments, step counter and loss
+    history equal those of the same number of eager calls, bit for bit, across
+    a change of the row permutation (a new epoch)."""
+    import torch
+    from paper_2412_16750_amd import warmstart as ws
+    data = _random_pairs(3 * 512 + 100, 41)
+    nets = [ws.MLP(scenarios.mlp_init_params(12), lr=2e-3) for _ in range(2)]
+    trs = [ws.ScheduledTrainer(n, data, 512, total_steps=6, lr_final=1e-4) for n in nets]
+    eager, graph = trs
+    graph.capture()
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    for step in range(6):
+        if step % 3 == 0:
+            perm = torch.randperm(data.X.shape[0], generator=gen)
+            for t in trs:
+                t.set_permutation(perm)
+        eager.step()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        junk = torch.randn(4096, device="cuda").square().sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        del junk
+        a, b = nets
+        for x, y in ((a.params, b.params), (a.w16, b.w16), (a.m, b.m), (a.v, b.v)):
+            assert torch.equal(x, y), step
+        assert eager.steps_done() == graph.steps_done() == step + 1
+        assert torch.equal(eager.loss_hist, graph.loss_hist)
+    log("scheduled MLP steps: losses %s" % eager.loss_hist.cpu().numpy())
+
+
+def test_scheduled_training_step_is_the_train_step_with_the_cosine_rate():
+    """The scheduled step on the permuted rows equals idm_mlp_train_step on
+    the same rows (index_select) with the learning rate of the cosine computed
+    on the host: same weights to FP32 rounding of the rate, same losses."""
+    import math
+    import torch
+    from paper_2412_16750_amd import warmstart as ws
+    data = _random_pairs(2 * 512, 42)
+    a = ws.MLP(scenarios.mlp_init_params(13), lr=3e-3)
+    b = ws.MLP(scenarios.mlp_init_params(13), lr=3e-3)
+    total, lr0, lr1 = 4, 3e-3, 2e-4
+    tr = ws.ScheduledTrainer(a, data, 512, total_steps=total, lr_final=lr1)
+    perm = torch.randperm(data.X.shape[0], generator=torch.Generator().manual_seed(3))
+    tr.set_permutation(perm)
+    pd = perm.cuda()
+    losses = []
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for t in range(1, total + 1):
+        tr.step()
+        rows = pd[((t - 1) % 2) * 512:((t - 1) % 2 + 1) * 512]
+        b._st.lr = lr1 + 0.5 * (lr0 - lr1) * (1.0 + math.cos(math.pi * (t - 1) / total))
+        b.train_step(data.X.index_select(0, rows).contiguous(),
+                     data.U.index_select(0, rows).contiguous(), loss)
+        losses.append(float(loss.item()))
+    torch.cuda.synchronize()
+    pa, pb = a.params.double().cpu().numpy(), b.params.double().cpu().numpy()
+    rel = float(np.max(np.abs(pa - pb)) / np.max(np.abs(pb)))
+    log("scheduled vs train_step: max param diff / max |param| %.2e, losses %s vs %s"
+        % (rel, tr.loss_hist.cpu().numpy()[:total], losses))
+    assert rel <= 1e-6
+    # the history holds one epoch (2 batches): steps 3 and 4 after four steps
+    assert np.allclose(tr.loss_hist.cpu().numpy(), losses[2:4], rtol=1e-6, atol=0.0)
