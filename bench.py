@@ -42,12 +42,13 @@ PEAK_HBM_GBPS = 8000.0
 # Paper, Fig. 1 / Sec. V-A: < 30 ms per step for 2M vehicles in each of the
 # forward and backward passes (Xeon W-2255 x16 threads or RTX A5000).
 PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
-# HBM bytes of one backward launch on this workload from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE (scaled by the copy-kernel calibration, 2.000 and 1.000), valid
-# only for the kernel source they were taken with (sha256 of idm_kernels.hip
-# followed by idm_device.h).
-TRAFFIC_BWD_BYTES = 1.1654e+09
-TRAFFIC_KERNEL_SHA256 = "663f54cd62894545f999e0cc70f8588c86e04864cd7c848336ba65adeb36149c"
+# HBM bytes of one backward (and one forward) launch on this workload from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by the copy-kernel calibration,
+# 2.000 and 1.000), valid only for the kernel source they were taken with
+# (sha256 of idm_kernels.hip followed by idm_device.h).
+TRAFFIC_BWD_BYTES = 1.2062e+09
+TRAFFIC_FWD_BYTES = 9.820e+08
+TRAFFIC_KERNEL_SHA256 = "5e4439fd76ead072ef94458f2b354583ed21d490f611fe692802ab3af8731547"
 
 
 # Warm-start network training: Adam over 1M pairs, batch 4096, learning rate
@@ -730,8 +731,10 @@ def main():
     for f in ("idm_kernels.hip", "idm_device.h"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     same_kernel = h.hexdigest() == TRAFFIC_KERNEL_SHA256
-    traffic = TRAFFIC_BWD_BYTES if (same_kernel and info["ckpt_every"] == 32 and info["block"] == 16
-                                    and info["threads"] == 1024 and info["per_thread"] == 1) else None
+    same_shape = (same_kernel and info["ckpt_every"] == 32 and info["block"] == 16
+                  and info["threads"] == 1024 and info["per_thread"] == 1)
+    traffic = TRAFFIC_BWD_BYTES if same_shape else None
+    traffic_fwd = TRAFFIC_FWD_BYTES if same_shape else None
     diag = diagnostics(plan, ws)
     # measured HBM ceiling: read + write rate of a 1 GiB streaming copy
     ceil = copy_ceiling(dev)
@@ -751,7 +754,7 @@ def main():
         "copy_ceiling_GBps": round(copy_gbps, 1),
         "copy_ceiling": {k: v for k, v in ceil.items() if k != "GBps"},
         "hbm_frac_of_copy": round(bwd_gbps / copy_gbps, 4),
-        "forward": {"kernel_ms": round(fwd_ms, 4),
+        "forward": {"kernel_ms": round(fwd_ms, 4), "traffic": traffic_fwd,
                     "achieved_TFLOPs": round(FLOP_FWD * vsteps / (fwd_ms / 1e3) / 1e12, 3),
                     "hbm_algorithmic_GBps": round(fwd_gbps, 1),
                     "hbm_frac": round(fwd_gbps / PEAK_HBM_GBPS, 4),

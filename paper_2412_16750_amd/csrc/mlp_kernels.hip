@@ -483,13 +483,20 @@ __global__ __launch_bounds__(256) void k_out_grad(const float *Y, const float *U
     if (t == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ __launch_bounds__(64) void k_sum_f64(const double *part, int n, double scale,
-                                                double *out) {
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += part[i];
-        *out = s * scale;
+// Fixed-order sum of n FP64 partials: 256 threads take every 256th one, then
+// a shared-memory tree (the same order on every call).
+__global__ __launch_bounds__(256) void k_sum_f64(const double *part, int n, double scale,
+                                                 double *out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *out = red[0] * scale;
 }
 
 // Adam on the FP32 master parameters, then BF16 copies of the weights.
@@ -806,7 +813,7 @@ hipError_t mlp_backward(const idm_mlp_state *st, const uint16_t *X, const float 
     hipLaunchKernelGGL(k_out_grad, dim3(lgrid), dim3(256), 0, s, Y, U, B, W16 + H16_W3, H2, dY,
                        dH2, lpart);
     if (loss_out)
-        hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(64), 0, s, lpart, lgrid,
+        hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, s, lpart, lgrid,
                            1.0 / ((double)B * IDM_MLP_OUT), loss_out);
     // one launch: [dW3; db3] = [H2^T; 1] dY, [dW2; db2] = [H1^T; 1] dH2 and
     // dH1 = (dH2 W2^T) * [H1 > 0]

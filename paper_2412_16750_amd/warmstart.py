@@ -120,6 +120,7 @@ class ScheduledTrainer:
         sc.hist_len = int(self.loss_hist.numel())
         self._sc = sc
         self.graph = None
+        self.graph_steps = 0
 
     def set_permutation(self, perm: torch.Tensor) -> None:
         """Rows of the next epoch (copied into the fixed permutation buffer)."""
@@ -132,13 +133,18 @@ class ScheduledTrainer:
             sim._ptr(self.Xb), sim._ptr(self.Ub), sim._ptr(self.ws), sim._stream()),
             "idm_mlp_train_step_scheduled")
 
-    def capture(self) -> None:
+    def capture(self, steps: int = 1) -> None:
+        """Record `steps` consecutive steps in one graph (every step is the
+        same call; the state that advances lives on the device)."""
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self.step()
+            for _ in range(int(steps)):
+                self.step()
         self.graph = g
+        self.graph_steps = int(steps)
 
     def replay(self) -> None:
+        """Launch the captured graph: its `graph_steps` steps."""
         if self.graph is None:
             self.capture()
         self.graph.replay()
@@ -149,22 +155,22 @@ class ScheduledTrainer:
 
 def train_graph(mlp: "MLP", data: "Dataset", batch: int = 4096, epochs: int = 10, seed: int = 0,
                 log=None, lr_final: Optional[float] = None) -> dict:
-    """The minibatch Adam loop of `train` with every step a replay of one
-    captured HIP graph: a fresh row permutation per epoch (the same generator
-    and seed as `train`), the learning-rate cosine and the step counter on the
-    device.  The epoch's training loss is the mean of its steps' losses."""
+    """The minibatch Adam loop of `train` as one HIP graph launch per epoch:
+    the graph holds the epoch's steps (each the same captured call), a fresh
+    row permutation per epoch (the same generator and seed as `train`), the
+    learning-rate cosine and the step counter on the device.  The epoch's
+    training loss is the mean of its steps' losses."""
     n = data.X.shape[0]
     nb = n // batch
     tr = ScheduledTrainer(mlp, data, batch, max(epochs * nb, 1), lr_final)
     g = torch.Generator(device="cpu").manual_seed(seed)
     hist = []
-    tr.capture()  # records one step; nothing runs yet
+    tr.capture(nb)  # records one epoch of steps; nothing runs yet
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for ep in range(epochs):
         tr.set_permutation(torch.randperm(n, generator=g))
-        for _ in range(nb):
-            tr.replay()
+        tr.replay()
         rec = {"epoch": ep, "train_mse": float(tr.loss_hist[:nb].mean().item())}
         hist.append(rec)
         if log:

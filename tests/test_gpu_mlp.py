@@ -306,25 +306,33 @@ def _random_pairs(n, seed):
 
 
 def test_scheduled_training_step_graph_replays_match_eager_steps():
-    """One scheduled training step captured in a HIP graph and replayed: after
-    every replay (with unrelated eager work and synchronisations between the
-    replays) the weights, BF16 copies, Adam moments, step counter and loss
-    history equal those of the same number of eager calls, bit for bit, across
-    a change of the row permutation (a new epoch)."""
+    """Scheduled training steps captured in a HIP graph (one step, and an
+    epoch of three steps) and replayed: after every replay (with unrelated
+    eager work and synchronisations between the replays) the weights, BF16
+    copies, Adam moments, step counter and loss history equal those of the
+    same number of eager calls, bit for bit, across changes of the row
+    permutation (new epochs)."""
     import torch
     from paper_2412_16750_amd import warmstart as ws
     data = _random_pairs(3 * 512 + 100, 41)
+    for per_graph in (1, 3):
+        _graph_vs_eager(ws, data, per_graph)
+
+
+def _graph_vs_eager(ws, data, per_graph):
+    import torch
     nets = [ws.MLP(scenarios.mlp_init_params(12), lr=2e-3) for _ in range(2)]
-    trs = [ws.ScheduledTrainer(n, data, 512, total_steps=6, lr_final=1e-4) for n in nets]
+    trs = [ws.ScheduledTrainer(n, data, 512, total_steps=9, lr_final=1e-4) for n in nets]
     eager, graph = trs
-    graph.capture()
+    graph.capture(per_graph)
     gen = torch.Generator(device="cpu").manual_seed(5)
-    for step in range(6):
+    for step in range(0, 9, per_graph):
         if step % 3 == 0:
             perm = torch.randperm(data.X.shape[0], generator=gen)
             for t in trs:
                 t.set_permutation(perm)
-        eager.step()
+        for _ in range(per_graph):
+            eager.step()
         torch.cuda.synchronize()
         graph.replay()
         torch.cuda.synchronize()
@@ -334,9 +342,9 @@ def test_scheduled_training_step_graph_replays_match_eager_steps():
         a, b = nets
         for x, y in ((a.params, b.params), (a.w16, b.w16), (a.m, b.m), (a.v, b.v)):
             assert torch.equal(x, y), step
-        assert eager.steps_done() == graph.steps_done() == step + 1
+        assert eager.steps_done() == graph.steps_done() == step + per_graph
         assert torch.equal(eager.loss_hist, graph.loss_hist)
-    log("scheduled MLP steps: losses %s" % eager.loss_hist.cpu().numpy())
+    log("scheduled MLP steps, %d per graph: losses %s" % (per_graph, eager.loss_hist.cpu().numpy()))
 
 
 def test_scheduled_training_step_is_the_train_step_with_the_cosine_rate():
