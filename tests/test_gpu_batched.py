@@ -97,18 +97,21 @@ def test_autotuner_keeps_results():
     assert torch.equal(b.grad_params, before[1])
 
 
-def test_uneven_workload_full_size_sampled_lanes():
+@pytest.mark.parametrize("shape", [{}, {"ckpt_every": 16, "grid": 256}])
+def test_uneven_workload_full_size_sampled_lanes(shape):
     """The 10,000-lane workload (lognormal(5, 1.2) sizes clipped to [10, 4096],
-    about 3.0M vehicles, 300 steps) as one graph; 8 lanes (including the
-    longest) are recomputed by the oracle."""
+    about 3.0M vehicles, 300 steps) as one graph, in the default plan (K = 32,
+    one work-group per bundle) and in the shape the autotuner picks for it on
+    the benchmark (K = 16, a persistent grid of 256 work-groups); 8 lanes
+    (including the longest) are recomputed by the oracle."""
     import torch
     from paper_2412_16750_amd import sim
     sc = scenarios.uneven()
     sizes = np.diff(sc.lane_offsets)
-    log("uneven full: N=%d lanes=%d max lane %d" % (sc.n, sc.n_lanes, sizes.max()))
+    log("uneven full: N=%d lanes=%d max lane %d, shape %s" % (sc.n, sc.n_lanes, sizes.max(), shape))
     steps = np.arange(10, sc.n_steps + 1, 10)
     tgt = scenarios.constant_speed_targets(sc, steps, 3)
-    plan, b = _buffers(sc, steps, tgt)
+    plan, b = _buffers(sc, steps, tgt, **shape)
     log("uneven full: plan %s" % plan.info())
     sim.idm_step_graph_launch(b)
     torch.cuda.synchronize()
