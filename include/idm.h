@@ -447,7 +447,8 @@ typedef struct {
  * [batch x IN_PAD] and Ub [batch x 5] (device, caller-owned); then the step of
  * idm_mlp_train_step with that t and the scheduled rate, and the loss into
  * loss_hist.  perm (device int64 [n_rows], a permutation) may be rewritten
- * between calls (one epoch per permutation).  batch <= n_rows; workspace as
+ * between calls (one epoch per permutation); an entry outside [0, n_rows)
+ * gathers a zero row.  batch <= n_rows; workspace as
  * idm_mlp_workspace_bytes(batch).  No host synchronisation, no allocation:
  * graph-capturable. */
 idm_status idm_mlp_train_step_scheduled(const idm_mlp_state *st, const uint16_t *X_all,

@@ -799,30 +799,23 @@ float plan_dt(const idm_plan *p) { return p ? p->pb.dt : 0.0f; }
 namespace {
 
 // Autotuner cache: the shape chosen for a problem signature, kept for the
-// process (FNV-1a over the sorted lane sizes and the problem's scalars).
+// process.  The signature is the sorted lane sizes (the lane-size histogram)
+// followed by S, the bound mode, a fixed K (0 = free), the kind of upstream
+// gradient and the device's compute-unit count, compared in full.
 std::mutex g_tune_mu;
-std::map<uint64_t, Shape> g_tune_cache;
+std::map<std::vector<int64_t>, Shape> g_tune_cache;
 
-uint64_t tune_key(const idm_plan *p, bool dense, bool obs, int cus) {
-    uint64_t h = 1469598103934665603ull;
-    auto mix = [&h](uint64_t x) {
-        for (int i = 0; i < 8; ++i) {
-            h ^= (x >> (8 * i)) & 0xffu;
-            h *= 1099511628211ull;
-        }
-    };
-    std::vector<int32_t> sizes((size_t)p->pb.n_lanes);
-    for (int l = 0; l < p->pb.n_lanes; ++l) sizes[l] = p->offsets[l + 1] - p->offsets[l];
-    std::sort(sizes.begin(), sizes.end());
-    mix(sizes.size());
-    for (int32_t z : sizes) mix((uint64_t)(uint32_t)z);
-    mix((uint64_t)p->pb.n_steps);
-    mix((uint64_t)p->pb.bound);
-    mix((uint64_t)(uint32_t)p->pb.ckpt_every);  // 0 = free
-    mix(dense ? 1 : 0);
-    mix(obs ? 1 : 0);
-    mix((uint64_t)cus);
-    return h;
+std::vector<int64_t> tune_key(const idm_plan *p, bool dense, bool obs, int cus) {
+    std::vector<int64_t> k((size_t)p->pb.n_lanes);
+    for (int l = 0; l < p->pb.n_lanes; ++l) k[(size_t)l] = p->offsets[l + 1] - p->offsets[l];
+    std::sort(k.begin(), k.end());
+    k.push_back(p->pb.n_steps);
+    k.push_back((int64_t)p->pb.bound);
+    k.push_back(p->pb.ckpt_every);
+    k.push_back(dense ? 1 : 0);
+    k.push_back(obs ? 1 : 0);
+    k.push_back(cus);
+    return k;
 }
 
 // Device address of the current GPU's copy of `scratch`, looked up once per
@@ -1174,17 +1167,24 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (cus <= 0) cus = 256;
-    const uint64_t key = tune_key(p, dense, a->obs_target != nullptr, cus);
+    const std::vector<int64_t> key = tune_key(p, dense, a->obs_target != nullptr, cus);
     {
-        std::lock_guard<std::mutex> lock(g_tune_mu);
-        auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
-            const Shape c = it->second;
+        bool hit = false;
+        Shape c;
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                hit = true;
+                c = it->second;
+            }
+        }
+        if (hit) {
             const int64_t nb = count_boundaries(p->offsets, p->pb.n_lanes,
                                                 (int64_t)c.threads * c.per_thread);
-            if (ws_total(p, c.K, nb) <= ws_bytes) {
-                r = build_layout(p, c);
-                if (r != IDM_OK) return r;
+            // the cached shape is taken when its workspace fits and its layout
+            // builds; otherwise the shapes are timed again
+            if (ws_total(p, c.K, nb) <= ws_bytes && build_layout(p, c) == IDM_OK) {
                 p->tuned_cached = 1;
                 return IDM_OK;
             }

@@ -584,10 +584,12 @@ __global__ void k_mlp_tick(int32_t *step, float lr0, float lr_final, int32_t tot
 
 // Batch rows of the scheduled step: row i of the batch is perm[b * B + i] with
 // b = (t - 1) mod (rows per epoch / B); 16-byte pieces of the BF16 feature rows
-// (IN_PAD * 2 = 320 B) and the 5 FP32 targets.
+// (IN_PAD * 2 = 320 B) and the 5 FP32 targets.  A permutation entry outside
+// [0, n_rows) gives a zero row instead of a read outside the data.
 __global__ __launch_bounds__(256) void k_mlp_gather(const uint4 *X_all, const float *U_all,
-                                                    const int64_t *perm, int64_t n_batches, int B,
-                                                    const int32_t *step, uint4 *Xb, float *Ub) {
+                                                    const int64_t *perm, int64_t n_rows,
+                                                    int64_t n_batches, int B, const int32_t *step,
+                                                    uint4 *Xb, float *Ub) {
     constexpr int XQ = IDM_MLP_IN_PAD * 2 / 16;  // 16-byte pieces per feature row
     const int64_t b = (int64_t)(*step - 1) % n_batches;
     const int64_t total = (int64_t)B * (XQ + IDM_MLP_OUT);
@@ -595,10 +597,11 @@ __global__ __launch_bounds__(256) void k_mlp_gather(const uint4 *X_all, const fl
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t row = i / (XQ + IDM_MLP_OUT), c = i % (XQ + IDM_MLP_OUT);
         const int64_t src = perm[b * B + row];
+        const bool in = src >= 0 && src < n_rows;
         if (c < XQ)
-            Xb[row * XQ + c] = X_all[src * XQ + c];
+            Xb[row * XQ + c] = in ? X_all[src * XQ + c] : make_uint4(0u, 0u, 0u, 0u);
         else
-            Ub[row * IDM_MLP_OUT + (c - XQ)] = U_all[src * IDM_MLP_OUT + (c - XQ)];
+            Ub[row * IDM_MLP_OUT + (c - XQ)] = in ? U_all[src * IDM_MLP_OUT + (c - XQ)] : 0.0f;
     }
 }
 
@@ -986,8 +989,8 @@ idm_status idm_mlp_train_step_scheduled(const idm_mlp_state *st, const uint16_t 
     hipLaunchKernelGGL(k_mlp_tick, dim3(1), dim3(64), 0, s, sched->step, sched->lr0,
                        sched->lr_final, sched->total_steps, lr);
     hipLaunchKernelGGL(k_mlp_gather, dim3(grid_for(batch * (IDM_MLP_IN_PAD * 2 / 16 + IDM_MLP_OUT))),
-                       dim3(256), 0, s, (const uint4 *)X_all, U_all, perm, n_rows / batch,
-                       (int)batch, (const int32_t *)sched->step, (uint4 *)Xb, Ub);
+                       dim3(256), 0, s, (const uint4 *)X_all, U_all, perm, n_rows,
+                       n_rows / batch, (int)batch, (const int32_t *)sched->step, (uint4 *)Xb, Ub);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = mlp_backward(st, Xb, Ub, batch, ws, nullptr, loss, s);
     if (e == hipSuccess) {
