@@ -122,9 +122,10 @@ class ScheduledTrainer:
         self.graph = None
         self.graph_steps = 0
 
-    def set_permutation(self, perm: torch.Tensor) -> None:
-        """Rows of the next epoch (copied into the fixed permutation buffer)."""
-        self.perm.copy_(perm.to(self.perm.device, non_blocking=False))
+    def set_permutation(self, perm: torch.Tensor, non_blocking: bool = False) -> None:
+        """Rows of the next epoch, copied into the fixed permutation buffer in
+        stream order (after the steps already launched)."""
+        self.perm.copy_(perm, non_blocking=non_blocking)
 
     def step(self) -> None:
         check(_lib.load().idm_mlp_train_step_scheduled(
@@ -158,26 +159,46 @@ def train_graph(mlp: "MLP", data: "Dataset", batch: int = 4096, epochs: int = 10
     """The minibatch Adam loop of `train` as one HIP graph launch per epoch:
     the graph holds the epoch's steps (each the same captured call), a fresh
     row permutation per epoch (the same generator and seed as `train`), the
-    learning-rate cosine and the step counter on the device.  The epoch's
-    training loss is the mean of its steps' losses."""
+    learning-rate cosine and the step counter on the device.  The next epoch's
+    permutation is drawn on the host while the GPU runs the current one and
+    copied in stream order from pinned memory; the epoch losses (mean of the
+    steps' losses) are read once at the end."""
     n = data.X.shape[0]
     nb = n // batch
     tr = ScheduledTrainer(mlp, data, batch, max(epochs * nb, 1), lr_final)
     g = torch.Generator(device="cpu").manual_seed(seed)
-    hist = []
+    dev = data.X.device
+    # two pinned host buffers for the permutations, each guarded by the event
+    # recorded after its last copy
+    pinned = [torch.empty(n, dtype=torch.int64, pin_memory=True) for _ in range(2)]
+    copied = [None, None]
+    ep_loss = torch.zeros(max(epochs, 1), dtype=torch.float64, device=dev)
     tr.capture(nb)  # records one epoch of steps; nothing runs yet
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    nxt = torch.randperm(n, generator=g)
     for ep in range(epochs):
-        tr.set_permutation(torch.randperm(n, generator=g))
+        buf = pinned[ep & 1]
+        if copied[ep & 1] is not None:
+            copied[ep & 1].synchronize()
+        buf.copy_(nxt)
+        tr.set_permutation(buf, non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record()
+        copied[ep & 1] = ev
         tr.replay()
-        rec = {"epoch": ep, "train_mse": float(tr.loss_hist[:nb].mean().item())}
-        hist.append(rec)
-        if log:
-            log("mlp epoch %d: %s" % (ep, rec))
+        ep_loss[ep] = tr.loss_hist[:nb].mean()
+        if ep + 1 < epochs:
+            nxt = torch.randperm(n, generator=g)  # overlaps the epoch on the GPU
     torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    losses = ep_loss.cpu().tolist()
+    hist = [{"epoch": ep, "train_mse": losses[ep]} for ep in range(epochs)]
+    if log:
+        for rec in hist:
+            log("mlp epoch %d: %s" % (rec["epoch"], rec))
     mlp.t = tr.steps_done()
-    return {"history": hist, "seconds": time.perf_counter() - t0, "steps": epochs * nb}
+    return {"history": hist, "seconds": secs, "steps": epochs * nb}
 
 
 def observe(plan, traj_d, p0, noise, obs_first, obs_stride, n_obs) -> torch.Tensor:
