@@ -441,7 +441,8 @@ typedef struct {
     int32_t hist_len;     /* >= 1 */
 } idm_mlp_schedule;
 
-/* One scheduled Adam step: t = ++(*sched->step); the batch is rows
+/* One scheduled Adam step t = *sched->step + 1 (the counter is advanced by
+ * the call's last kernel); the batch is rows
  * perm[((t - 1) % (n_rows / batch)) * batch + i], i < batch, of X_all
  * [n_rows x IN_PAD] (BF16) and U_all [n_rows x 5] (FP32), gathered into Xb
  * [batch x IN_PAD] and Ub [batch x 5] (device, caller-owned); then the step of

@@ -508,8 +508,11 @@ struct MlpAdam {
     int64_t n;
     int32_t t;        // step number of this update (1-based)
     float lr, beta1, beta2, eps;
-    const int32_t *t_dev;  // nullable: the step number, read on the device
-    const float *lr_dev;   // nullable: the learning rate, read on the device
+    // nullable: the step number is *t_dev + 1 (steps done before this one),
+    // and the rate follows the cosine from lr0 to lr_final over total steps
+    const int32_t *t_dev;
+    float lr0, lr_final;
+    int32_t total;
     uint16_t *w16;    // BF16 copies of the weight blocks
     int64_t w1_off, w1_n, w2_off, w2_n, w3_off, w3_n;  // ranges in p / w16 offsets
     int64_t w16_w2, w16_w3;
@@ -537,9 +540,18 @@ __device__ __forceinline__ float slab_grad(const MlpAdam &A, int64_t i) {
     return s;
 }
 
+// Learning rate of scheduled step t: cosine from lr0 (t = 1) to lr_final
+// (t = total + 1), in FP64, rounded once.
+__device__ __forceinline__ float cosine_rate(int32_t t, float lr0, float lr_final, int32_t total) {
+    const double c = cos(3.14159265358979323846 * (double)(t - 1) / (double)total);
+    return (float)((double)lr_final + 0.5 * ((double)lr0 - (double)lr_final) * (1.0 + c));
+}
+
 __global__ __launch_bounds__(256) void k_mlp_adam(MlpAdam A) {
-    if (A.t_dev) A.t = *A.t_dev;
-    if (A.lr_dev) A.lr = *A.lr_dev;
+    if (A.t_dev) {
+        A.t = *A.t_dev + 1;
+        A.lr = cosine_rate(A.t, A.lr0, A.lr_final, A.total);
+    }
     const float bc1 = 1.0f - powf(A.beta1, (float)A.t);
     const float bc2 = 1.0f - powf(A.beta2, (float)A.t);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n;
@@ -572,16 +584,6 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float *x, int rows, int c
     }
 }
 
-// Scheduled training step: advance the device step counter and write the
-// step's learning rate (cosine from lr0 to lr_final over total steps).
-__global__ void k_mlp_tick(int32_t *step, float lr0, float lr_final, int32_t total, float *lr_out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int32_t t = *step + 1;
-    *step = t;
-    const double c = cos(3.14159265358979323846 * (double)(t - 1) / (double)total);
-    *lr_out = (float)((double)lr_final + 0.5 * ((double)lr0 - (double)lr_final) * (1.0 + c));
-}
-
 // Batch rows of the scheduled step: row i of the batch is perm[b * B + i] with
 // b = (t - 1) mod (rows per epoch / B); 16-byte pieces of the BF16 feature rows
 // (IN_PAD * 2 = 320 B) and the 5 FP32 targets.  A permutation entry outside
@@ -591,7 +593,7 @@ __global__ __launch_bounds__(256) void k_mlp_gather(const uint4 *X_all, const fl
                                                     int64_t n_batches, int B, const int32_t *step,
                                                     uint4 *Xb, float *Ub) {
     constexpr int XQ = IDM_MLP_IN_PAD * 2 / 16;  // 16-byte pieces per feature row
-    const int64_t b = (int64_t)(*step - 1) % n_batches;
+    const int64_t b = (int64_t)(*step) % n_batches;  // step t = *step + 1
     const int64_t total = (int64_t)B * (XQ + IDM_MLP_OUT);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -605,9 +607,15 @@ __global__ __launch_bounds__(256) void k_mlp_gather(const uint4 *X_all, const fl
     }
 }
 
-// Loss of the scheduled step into its slot of the history.
-__global__ void k_mlp_log_loss(const int32_t *step, const double *loss, double *hist, int32_t len) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) hist[(*step - 1) % len] = *loss;
+// End of a scheduled step t = *step + 1: its loss into slot (t - 1) % len of
+// the history, and the step counter advanced (the last kernel of the step, so
+// every earlier kernel read the counter before this write).
+__global__ void k_mlp_end_step(int32_t *step, const double *loss, double *hist, int32_t len) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int32_t t = *step + 1;
+        hist[(t - 1) % len] = *loss;
+        *step = t;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_fill_f32(float *x, int64_t n, float v) {
@@ -740,7 +748,7 @@ MlpWs mlp_ws(int64_t B) {
     // layer block [OFF_Wl, OFF_Wl + n_l) at part + slabs * OFF_Wl, [slab][n_l]
     w.part = o; o += al(4 * slabs * N_PARAMS);
     w.lpart = o; o += al(8 * 8192);
-    w.sched = o; o += al(16);  // scheduled step: its loss (FP64) and learning rate (FP32)
+    w.sched = o; o += al(16);  // scheduled step: its loss (FP64)
     w.total = o;
     return w;
 }
@@ -954,7 +962,7 @@ idm_status idm_mlp_train_step(const idm_mlp_state *st, const uint16_t *X, const 
         A.slabs = (int)((batch + slab_rows(batch) - 1) / slab_rows(batch));
         A.t = t;
         A.lr = st->lr; A.beta1 = st->beta1; A.beta2 = st->beta2; A.eps = st->eps;
-        A.t_dev = nullptr; A.lr_dev = nullptr;
+        A.t_dev = nullptr; A.lr0 = A.lr_final = 0.0f; A.total = 1;
         A.w16 = st->weights_bf16;
         A.w1_off = OFF_W1; A.w1_n = N_W1; A.w2_off = OFF_W2; A.w2_n = N_W2; A.w3_off = OFF_W3; A.w3_n = N_W3;
         A.w16_w2 = H16_W2; A.w16_w3 = H16_W3;
@@ -985,9 +993,6 @@ idm_status idm_mlp_train_step_scheduled(const idm_mlp_state *st, const uint16_t 
     char *ws = (char *)workspace;
     const MlpWs w = mlp_ws(batch);
     double *loss = (double *)(ws + w.sched);
-    float *lr = (float *)(ws + w.sched + 8);
-    hipLaunchKernelGGL(k_mlp_tick, dim3(1), dim3(64), 0, s, sched->step, sched->lr0,
-                       sched->lr_final, sched->total_steps, lr);
     hipLaunchKernelGGL(k_mlp_gather, dim3(grid_for(batch * (IDM_MLP_IN_PAD * 2 / 16 + IDM_MLP_OUT))),
                        dim3(256), 0, s, (const uint4 *)X_all, U_all, perm, n_rows,
                        n_rows / batch, (int)batch, (const int32_t *)sched->step, (uint4 *)Xb, Ub);
@@ -1000,13 +1005,14 @@ idm_status idm_mlp_train_step_scheduled(const idm_mlp_state *st, const uint16_t 
         A.slabs = (int)((batch + slab_rows(batch) - 1) / slab_rows(batch));
         A.t = 1;
         A.lr = 0.0f; A.beta1 = st->beta1; A.beta2 = st->beta2; A.eps = st->eps;
-        A.t_dev = sched->step; A.lr_dev = lr;
+        A.t_dev = sched->step;
+        A.lr0 = sched->lr0; A.lr_final = sched->lr_final; A.total = sched->total_steps;
         A.w16 = st->weights_bf16;
         A.w1_off = OFF_W1; A.w1_n = N_W1; A.w2_off = OFF_W2; A.w2_n = N_W2; A.w3_off = OFF_W3; A.w3_n = N_W3;
         A.w16_w2 = H16_W2; A.w16_w3 = H16_W3;
         A.t16_w1 = T16_W1; A.t16_w2 = T16_W2; A.t16_w3 = T16_W3;
         hipLaunchKernelGGL(k_mlp_adam, dim3(grid_for(N_PARAMS)), dim3(256), 0, s, A);
-        hipLaunchKernelGGL(k_mlp_log_loss, dim3(1), dim3(64), 0, s, (const int32_t *)sched->step,
+        hipLaunchKernelGGL(k_mlp_end_step, dim3(1), dim3(64), 0, s, sched->step,
                            (const double *)loss, sched->loss_hist, sched->hist_len);
         e = hipGetLastError();
     }
