@@ -325,7 +325,8 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
                        "N(0, 0.5 m) noise; Adam lr 1e-2 on normalised parameters",
            "mlp": {"pairs": n_pairs, "batch": 4096, "epochs": MLP_EPOCHS,
                    "lr": "cosine %.0e -> %.0e" % (MLP_LR, MLP_LR_FINAL), "steps": rep["steps"],
-                   "training_loop": "one captured HIP graph replayed per step",
+                   "training_loop": "one HIP graph launch per epoch (the epoch's steps, each the "
+                                    "same captured call with device-side step, rate and batch)",
                    "data_seconds": round(gen_s, 3), "train_seconds": round(rep["seconds"], 3),
                    "train_mse": rep["history"][-1]["train_mse"], "heldout_mse": heldout_mse,
                    **rates}}
