@@ -48,11 +48,14 @@ PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
 # (sha256 of idm_kernels.hip followed by idm_device.h).
 TRAFFIC_BWD_BYTES = 1.2062e+09
 TRAFFIC_FWD_BYTES = 9.820e+08
-# Share of the SIMD cycles with a VALU instruction issuing (4 x SQ_ACTIVE_INST_VALU
-# over 1024 SIMDs x 2.4 GHz x the kernel time), and VALU instructions per wave
-# and simulated step, from the SQ counter runs of the same kernel source.
-VALU_BUSY_BWD, VALU_PER_WAVE_STEP_BWD = 0.822, 119.1
-VALU_BUSY_FWD, VALU_PER_WAVE_STEP_FWD = 0.888, 36.5
+# Share of the SIMD cycles with a VALU instruction issuing: 4 x SQ_ACTIVE_INST_VALU
+# (quad-cycles summed over waves; a transcendental counts two) over 1024 SIMDs x
+# the kernel's cycles, GRBM_COUNT / 8 (the counter sums the 8 XCDs), both from
+# one counter pass; the clock those cycles give (cycles over the launch
+# duration), and VALU instructions per wave and simulated step.  Same kernel
+# source as the traffic figures.
+VALU_BUSY_BWD, VALU_PER_WAVE_STEP_BWD, CLOCK_GHZ_BWD = 0.861, 119.1, 2.337
+VALU_BUSY_FWD, VALU_PER_WAVE_STEP_FWD, CLOCK_GHZ_FWD = 0.936, 36.5, 2.318
 TRAFFIC_KERNEL_SHA256 = "5e4439fd76ead072ef94458f2b354583ed21d490f611fe692802ab3af8731547"
 
 
@@ -762,9 +765,11 @@ def main():
         "hbm_frac_of_copy": round(bwd_gbps / copy_gbps, 4),
         "valu_busy": VALU_BUSY_BWD if same_shape else None,
         "valu_per_wave_step": VALU_PER_WAVE_STEP_BWD if same_shape else None,
+        "clock_GHz_counters": CLOCK_GHZ_BWD if same_shape else None,
         "forward": {"kernel_ms": round(fwd_ms, 4), "traffic": traffic_fwd,
                     "valu_busy": VALU_BUSY_FWD if same_shape else None,
                     "valu_per_wave_step": VALU_PER_WAVE_STEP_FWD if same_shape else None,
+                    "clock_GHz_counters": CLOCK_GHZ_FWD if same_shape else None,
                     "achieved_TFLOPs": round(FLOP_FWD * vsteps / (fwd_ms / 1e3) / 1e12, 3),
                     "hbm_algorithmic_GBps": round(fwd_gbps, 1),
                     "hbm_frac": round(fwd_gbps / PEAK_HBM_GBPS, 4),
