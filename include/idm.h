@@ -98,6 +98,14 @@ typedef struct {
                            on (512 or 1024 threads x 1, 512 x 2, 256 x 4 with KB = 8) the
                            backward keeps the lower sub-block's states in LDS and computes
                            every state of a block once */
+    int32_t store_states; /* 1: the forward keeps every step's displacements and speeds in
+                           the workspace (8 (S+1) N bytes, no checkpoints) and the backward
+                           reads them instead of recomputing them from checkpoints (the
+                           kernel of idm_sim_backward_stored; same results bit for bit, K
+                           then only groups the FP32 gradient sums).  Fastest where a step's
+                           latency, not the chip's throughput, sets the time (few lanes,
+                           e.g. a fit of 100 lanes); whole lanes only (a plan whose bundles
+                           would cut a lane is IDM_ERR_UNSUPPORTED).  0: checkpoints */
 } idm_tuning;
 
 /* Per-vehicle IDM parameters (Sec. III-A), FP32 [N] each, all > 0. */
@@ -149,6 +157,7 @@ typedef struct {
     int32_t n_levels;       /* launches per pass: 1 + most extra pieces of one lane */
     int32_t n_boundaries;   /* piece boundaries of lanes longer than a bundle */
     int32_t autotune_cached; /* 1: the last idm_plan_autotune took its shape from the cache */
+    int32_t store_states;   /* 1: every step's states are kept (idm_tuning.store_states) */
 } idm_plan_info;
 idm_status idm_plan_get_info(const idm_plan *plan, idm_plan_info *out);
 
@@ -230,6 +239,28 @@ idm_status idm_sim_backward(idm_plan *plan, const idm_params *prm, const double 
                             const float *grad_traj_v, const idm_obs *obs, double *grad_params,
                             double *grad_p0, double *grad_v0, double *loss_out, void *workspace,
                             void *stream);
+
+/* The gradient of idm_sim_backward computed from the forward's stored
+ * trajectory instead of checkpoints (the same reverse pass through the
+ * simulation of Sec. III-B, with every state kept).  traj_d and traj_v
+ * [(S+1)*N] FP32 are the displacements and speeds idm_sim_forward wrote for
+ * the same plan and inputs (both required, read only; that forward needs no
+ * workspace, since no checkpoints are read).  Each step's states are read
+ * instead of recomputed, which removes the recomputation's third of the
+ * backward's arithmetic for 8 more bytes read per vehicle-step, and keeps the
+ * 8 (S+1) N bytes of trajectory in device memory in place of the checkpoints.
+ * grad_traj_d, grad_traj_v, obs, the outputs and their meaning as in
+ * idm_sim_backward; the workspace (idm_workspace_bytes) receives only the
+ * loss partials.  Results equal idm_sim_backward's bit for bit for the same
+ * plan (the same K-step blocks of FP32 gradient sums).  A plan that cuts
+ * lanes into pieces (idm_plan_info.n_boundaries > 0) is IDM_ERR_UNSUPPORTED:
+ * use idm_sim_backward. */
+idm_status idm_sim_backward_stored(idm_plan *plan, const idm_params *prm, const double *p0,
+                                   const float *traj_d, const float *traj_v,
+                                   const float *grad_traj_d, const float *grad_traj_v,
+                                   const idm_obs *obs, double *grad_params, double *grad_p0,
+                                   double *grad_v0, double *loss_out, void *workspace,
+                                   void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the

@@ -30,7 +30,7 @@ class IdmProblem(ctypes.Structure):
 
 class IdmTuning(ctypes.Structure):
     _fields_ = [("threads", c_int32), ("per_thread", c_int32), ("ckpt_every", c_int32),
-                ("grid", c_int32), ("block", c_int32)]
+                ("grid", c_int32), ("block", c_int32), ("store_states", c_int32)]
 
 
 class IdmParams(ctypes.Structure):
@@ -47,7 +47,8 @@ class IdmPlanInfo(ctypes.Structure):
     _fields_ = [("threads", c_int32), ("per_thread", c_int32), ("ckpt_every", c_int32),
                 ("grid", c_int32), ("block", c_int32), ("n_bundles", c_int32), ("max_lane", c_int32),
                 ("n_slots", c_int64), ("fill", c_double), ("n_levels", c_int32),
-                ("n_boundaries", c_int32), ("autotune_cached", c_int32)]
+                ("n_boundaries", c_int32), ("autotune_cached", c_int32),
+                ("store_states", c_int32)]
 
 
 class IdmFitState(ctypes.Structure):
@@ -108,7 +109,8 @@ class IdmStepArgs(ctypes.Structure):
 # every symbol declared in include/idm.h
 EXPORTS = ("idm_plan_create", "idm_plan_destroy", "idm_workspace_bytes", "idm_plan_get_info",
            "idm_problem_check", "idm_problem_layout", "idm_problem_bundles",
-           "idm_sim_forward", "idm_sim_backward", "idm_sim_backward_noalloc", "idm_plan_diagnostics",
+           "idm_sim_forward", "idm_sim_backward", "idm_sim_backward_stored",
+           "idm_sim_backward_noalloc", "idm_plan_diagnostics",
            "idm_fit_init", "idm_fit_step", "idm_fit_run",
            "idm_step_graph_launch", "idm_plan_autotune", "idm_copy_bytes", "idm_last_error",
            "idm_version", "idm_mlp_param_count", "idm_mlp_weight_bf16_count",
@@ -137,6 +139,12 @@ def load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError("libidmx.so not found at %s: run __graft_entry__.build() or "
                           "python paper_2412_16750_amd/build.py" % LIB_PATH)
+    # torch first: its wheel carries its own HIP and HSA runtimes under the
+    # same sonames as ROCm's, so whichever loads first serves the process.
+    # Loading torch's makes this library bind to it, as torch's kernels do;
+    # loading this library first would bring in a second HSA runtime next to
+    # torch's, after which this library's HIP calls find no device.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     L.idm_plan_create.argtypes = [P(IdmProblem), P(IdmTuning), P(c_void_p)]
@@ -153,6 +161,9 @@ def load() -> ctypes.CDLL:
     L.idm_sim_backward.argtypes = [c_void_p, P(IdmParams), c_void_p, c_void_p, c_void_p, c_void_p,
                                    P(IdmObs), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p]
+    L.idm_sim_backward_stored.argtypes = [c_void_p, P(IdmParams), c_void_p, c_void_p, c_void_p,
+                                          c_void_p, c_void_p, P(IdmObs), c_void_p, c_void_p,
+                                          c_void_p, c_void_p, c_void_p, c_void_p]
     L.idm_sim_backward_noalloc.argtypes = [c_void_p, P(IdmParams), c_void_p, c_void_p, c_void_p,
                                            c_void_p, P(IdmObs), c_void_p, c_void_p, c_void_p,
                                            c_void_p, c_void_p]
@@ -216,7 +227,8 @@ def load() -> ctypes.CDLL:
     L.idm_version.restype = ctypes.c_char_p
     for name in ("idm_problem_check", "idm_problem_layout", "idm_problem_bundles", "idm_plan_create",
                  "idm_plan_destroy", "idm_plan_get_info", "idm_sim_forward",
-                 "idm_sim_backward", "idm_sim_backward_noalloc", "idm_plan_diagnostics",
+                 "idm_sim_backward", "idm_sim_backward_stored", "idm_sim_backward_noalloc",
+                 "idm_plan_diagnostics",
                  "idm_fit_init", "idm_fit_step",
                  "idm_fit_run", "idm_step_graph_launch",
                  "idm_plan_autotune"):

@@ -53,6 +53,7 @@ struct Shape {
     int K = 0;   // checkpoint interval
     int KB = 0;  // backward register block (divides K)
     int grid = 0;
+    bool stored = false;  // the forward keeps every step's states for the backward
 };
 
 bool valid_threads(int t) { return t == 64 || t == 128 || t == 256 || t == 512 || t == 1024; }
@@ -132,7 +133,9 @@ int64_t count_boundaries(const std::vector<int32_t> &offsets, int L, int64_t cap
 // Workspace layout: [loss partials: one double per bundle (at most one per
 // lane piece)][forward diagnostics: two uint64 per bundle][fit: 7N doubles]
 // [checkpoints][boundary states: n_bnd x (S+1) float2][boundary adjoint
-// contributions: n_bnd x S float2]
+// contributions: n_bnd x S float2][stored states: (S+1) x N displacements,
+// then (S+1) x N speeds].  A plan that keeps every step's states has no
+// checkpoints and no piece boundaries; any other has no stored states.
 size_t ws_loss_off(const idm_plan *) { return 0; }
 size_t ws_diag_off(const idm_plan *p, int64_t nbnd) {
     return align_up(sizeof(double) * ((size_t)p->pb.n_lanes + (size_t)nbnd));
@@ -144,19 +147,29 @@ size_t ws_fit_off(const idm_plan *p, int64_t nbnd) {
 size_t ws_ckpt_off(const idm_plan *p, int64_t nbnd) {
     return ws_fit_off(p, nbnd) + align_up(sizeof(double) * 7 * (size_t)p->pb.n_vehicles);
 }
-size_t ckpt_bytes(const idm_plan *p, int K) {
+size_t ckpt_bytes(const idm_plan *p, int K, bool stored) {
+    if (stored) return 0;
     size_t nb = p->pb.n_steps == 0 ? 0 : (size_t)(p->pb.n_steps + K - 1) / K;
     return align_up(nb * 2 * sizeof(float) * (size_t)p->pb.n_vehicles);
 }
-size_t ws_ext_off(const idm_plan *p, int K, int64_t nbnd) {
-    return ws_ckpt_off(p, nbnd) + ckpt_bytes(p, K);
+size_t ws_ext_off(const idm_plan *p, int K, int64_t nbnd, bool stored) {
+    return ws_ckpt_off(p, nbnd) + ckpt_bytes(p, K, stored);
+}
+size_t state_rows_bytes(const idm_plan *p) {
+    return align_up(((size_t)p->pb.n_steps + 1) * sizeof(float) * (size_t)p->pb.n_vehicles);
 }
 size_t ext_state_bytes(const idm_plan *p, int64_t nbnd) {
     return align_up((size_t)nbnd * ((size_t)p->pb.n_steps + 1) * 2 * sizeof(float));
 }
-size_t ws_total(const idm_plan *p, int K, int64_t nbnd) {
-    return ws_ext_off(p, K, nbnd) + ext_state_bytes(p, nbnd) +
+size_t ws_states_off(const idm_plan *p, int K, int64_t nbnd, bool stored) {
+    return ws_ext_off(p, K, nbnd, stored) + ext_state_bytes(p, nbnd) +
            align_up((size_t)nbnd * (size_t)p->pb.n_steps * 2 * sizeof(float));
+}
+size_t ws_total(const idm_plan *p, int K, int64_t nbnd, bool stored) {
+    return ws_states_off(p, K, nbnd, stored) + (stored ? 2 * state_rows_bytes(p) : 0);
+}
+size_t ws_total(const idm_plan *p, int K, int64_t nbnd) {
+    return ws_total(p, K, nbnd, p->sh.stored);
 }
 size_t ws_fit_off(const idm_plan *p) { return ws_fit_off(p, p->n_bnd); }
 size_t ws_diag_off(const idm_plan *p) { return ws_diag_off(p, p->n_bnd); }
@@ -314,6 +327,11 @@ idm_status compute_layout(const std::vector<int32_t> &offsets, int L, const Shap
         }
     }
     for (int32_t lv = 0; lv < n_levels; ++lv) out.level_start[lv + 1] += out.level_start[lv];
+    if (sh.stored && out.n_bnd > 0)
+        return fail(IDM_ERR_UNSUPPORTED,
+                    "keeping every step's states needs whole lanes in a bundle: a %d x %d bundle "
+                    "cuts the longest lane into pieces",
+                    sh.threads, sh.per_thread);
     return IDM_OK;
 }
 
@@ -457,6 +475,7 @@ idm_status choose_shape(const idm_plan *p, const idm_tuning *tu, Shape &sh) {
     sh.K = K;
     sh.KB = KB;
     sh.grid = (tu && tu->grid > 0) ? tu->grid : 0;
+    sh.stored = tu && tu->store_states > 0;
     return IDM_OK;
 }
 
@@ -521,7 +540,7 @@ int32_t level_args(const idm_plan *p, int32_t lv, SimArgs &a, double *loss_base,
 
 void ext_args(const idm_plan *p, void *ws, SimArgs &a) {
     if (p->n_bnd == 0) return;
-    char *base = (char *)ws + ws_ext_off(p, p->sh.K, p->n_bnd);
+    char *base = (char *)ws + ws_ext_off(p, p->sh.K, p->n_bnd, p->sh.stored);
     a.ext_state = (float2 *)base;
     a.ext_adj = (float2 *)(base + ext_state_bytes(p, p->n_bnd));
 }
@@ -536,6 +555,16 @@ idm_status run_forward(idm_plan *p, const idm_params *prm, const double *p0, con
     a.traj_v = traj_v;
     a.ckpt = ws ? (float *)((char *)ws + ws_ckpt_off(p)) : nullptr;
     if (p->pb.n_steps == 0 && a.ckpt) a.ckpt = nullptr;
+    // a plan that keeps every step's states writes them into the workspace
+    // (no checkpoints) and copies them out for a caller that asked for them
+    float *st_d = nullptr, *st_v = nullptr;
+    if (p->sh.stored && ws) {
+        st_d = (float *)((char *)ws + ws_states_off(p, p->sh.K, p->n_bnd, true));
+        st_v = (float *)((char *)st_d + state_rows_bytes(p));
+        a.traj_d = st_d;
+        a.traj_v = st_v;
+        a.ckpt = nullptr;
+    }
     if (p->n_bnd > 0) {
         if (!ws)
             return fail(IDM_ERR_WORKSPACE,
@@ -553,12 +582,33 @@ idm_status run_forward(idm_plan *p, const idm_params *prm, const double *p0, con
         hipError_t e = launch_sim(fn, grid_of(p, nb), p->sh.threads, a, s);
         if (e != hipSuccess) return hip_fail(e, "forward launch");
     }
+    const size_t rows = ((size_t)p->pb.n_steps + 1) * sizeof(float) * (size_t)p->pb.n_vehicles;
+    for (int i = 0; i < 2; ++i) {
+        float *dst = i ? traj_v : traj_d;
+        const float *src = i ? st_v : st_d;
+        if (!src || !dst || rows == 0) continue;
+        hipError_t e = hipMemcpyAsync(dst, src, rows, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "trajectory copy");
+    }
     return IDM_OK;
 }
+
+idm_status run_backward_stored(idm_plan *p, const idm_params *prm, const double *p0,
+                               const float *traj_d, const float *traj_v, const float *gd,
+                               const float *gv, const idm_obs *obs, double *g_prm,
+                               double *g_p0, double *g_v0, double *loss_out, void *ws,
+                               hipStream_t s);
 
 idm_status run_backward(idm_plan *p, const idm_params *prm, const double *p0, const float *v_init,
                         const float *gd, const float *gv, const idm_obs *obs, double *g_prm,
                         double *g_p0, double *g_v0, double *loss_out, void *ws, hipStream_t s) {
+    if (p->sh.stored) {
+        // the states the forward kept in the workspace
+        const float *st_d = (const float *)((char *)ws + ws_states_off(p, p->sh.K, p->n_bnd, true));
+        const float *st_v = (const float *)((const char *)st_d + state_rows_bytes(p));
+        return run_backward_stored(p, prm, p0, st_d, st_v, gd, gv, obs, g_prm, g_p0, g_v0,
+                                   loss_out, ws, s);
+    }
     SimArgs a = base_args(p);
     a.v0 = prm->v0; a.T = prm->T; a.a = prm->a; a.b = prm->b; a.s0 = prm->s0; a.len = prm->length;
     a.p0 = p0;
@@ -590,6 +640,53 @@ idm_status run_backward(idm_plan *p, const idm_params *prm, const double *p0, co
         if (nb == 0) continue;
         hipError_t e = launch_sim(fn, grid_of(p, nb), p->sh.threads, a, s);
         if (e != hipSuccess) return hip_fail(e, "backward launch");
+    }
+    if (loss_out) {
+        hipError_t e = launch_loss_finalize(loss_base, p->n_bundles, obs ? a.inv_count : 0.0,
+                                            loss_out, s);
+        if (e != hipSuccess) return hip_fail(e, "loss finalize launch");
+    }
+    return IDM_OK;
+}
+
+// The adjoint from the forward's stored trajectory (whole lanes: one launch
+// level).  The workspace holds the loss partials only.
+idm_status run_backward_stored(idm_plan *p, const idm_params *prm, const double *p0,
+                               const float *traj_d, const float *traj_v, const float *gd,
+                               const float *gv, const idm_obs *obs, double *g_prm,
+                               double *g_p0, double *g_v0, double *loss_out, void *ws,
+                               hipStream_t s) {
+    if (p->n_bnd > 0 || n_levels(p) != 1)
+        return fail(IDM_ERR_UNSUPPORTED,
+                    "the backward from stored states handles whole lanes only; this plan cuts "
+                    "lanes longer than a bundle into pieces (use idm_sim_backward)");
+    SimArgs a = base_args(p);
+    a.v0 = prm->v0; a.T = prm->T; a.a = prm->a; a.b = prm->b; a.s0 = prm->s0; a.len = prm->length;
+    a.p0 = p0;
+    a.traj_d = const_cast<float *>(traj_d);
+    a.traj_v = const_cast<float *>(traj_v);
+    a.gd = gd;
+    a.gv = gv;
+    if (obs) {
+        a.target = obs->target;
+        a.n_obs = obs->n_obs;
+        a.obs_first = obs->obs_first;
+        a.obs_stride = obs->obs_stride;
+        a.inv_count = 1.0 / ((double)obs->n_obs * (double)p->pb.n_vehicles);
+        a.two_inv_count = 2.0 * a.inv_count;
+    } else {
+        a.obs_stride = 1;
+    }
+    a.g_prm = g_prm;
+    a.g_p0 = g_p0;
+    a.g_v0 = g_v0;
+    double *loss_base = (double *)((char *)ws + ws_loss_off(p));
+    KernelFn fn = backward_stored_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, gd || gv);
+    if (!fn) return fail(IDM_ERR_UNSUPPORTED, "no stored-state backward kernel for this shape");
+    const int32_t nb = level_args(p, 0, a, loss_base);
+    if (nb > 0) {
+        hipError_t e = launch_sim(fn, grid_of(p, nb), p->sh.threads, a, s);
+        if (e != hipSuccess) return hip_fail(e, "stored-state backward launch");
     }
     if (loss_out) {
         hipError_t e = launch_loss_finalize(loss_base, p->n_bundles, obs ? a.inv_count : 0.0,
@@ -747,6 +844,8 @@ idm_status host_plan(const idm_problem *pb, const idm_tuning *tu, idm_plan *p, S
     }
     if (tu && (tu->grid < 0 || tu->ckpt_every < 0 || tu->block < 0))
         return fail(IDM_ERR_INVALID_ARG, "tuning: negative grid, ckpt_every or block");
+    if (tu && tu->store_states != 0 && tu->store_states != 1)
+        return fail(IDM_ERR_INVALID_ARG, "tuning: store_states must be 0 or 1");
     p->pb = *pb;
     p->offsets.assign(off, off + pb->n_lanes + 1);
     p->pb.lane_offsets_host = nullptr;
@@ -815,6 +914,7 @@ std::vector<int64_t> tune_key(const idm_plan *p, bool dense, bool obs, int cus) 
     k.push_back(dense ? 1 : 0);
     k.push_back(obs ? 1 : 0);
     k.push_back(cus);
+    k.push_back(p->sh.stored ? 1 : 0);
     return k;
 }
 
@@ -968,6 +1068,7 @@ idm_status idm_plan_get_info(const idm_plan *p, idm_plan_info *o) {
     o->n_levels = n_levels(p);
     o->n_boundaries = p->n_bnd;
     o->autotune_cached = p->tuned_cached;
+    o->store_states = p->sh.stored ? 1 : 0;
     return IDM_OK;
 }
 
@@ -1004,6 +1105,25 @@ idm_status idm_sim_backward(idm_plan *p, const idm_params *prm, const double *p0
     if (r != IDM_OK) return r;
     return run_backward(p, prm, p0, v_init, gd, gv, obs, g_prm, g_p0, g_v0, loss_out, ws,
                         (hipStream_t)stream);
+}
+
+idm_status idm_sim_backward_stored(idm_plan *p, const idm_params *prm, const double *p0,
+                                   const float *traj_d, const float *traj_v, const float *gd,
+                                   const float *gv, const idm_obs *obs, double *g_prm,
+                                   double *g_p0, double *g_v0, double *loss_out, void *ws,
+                                   void *stream) {
+    if (!p) return fail(IDM_ERR_INVALID_ARG, "plan is null");
+    idm_status r = check_params(prm);
+    if (r != IDM_OK) return r;
+    if (!p0) return fail(IDM_ERR_INVALID_ARG, "p0 null");
+    if (!traj_d || !traj_v)
+        return fail(IDM_ERR_INVALID_ARG, "traj_d / traj_v null: the stored trajectory is required");
+    if (!g_prm || !g_p0 || !g_v0) return fail(IDM_ERR_INVALID_ARG, "gradient outputs null");
+    if (!ws) return fail(IDM_ERR_WORKSPACE, "workspace is null");
+    r = check_obs(p, obs);
+    if (r != IDM_OK) return r;
+    return run_backward_stored(p, prm, p0, traj_d, traj_v, gd, gv, obs, g_prm, g_p0, g_v0,
+                               loss_out, ws, (hipStream_t)stream);
 }
 
 idm_status idm_sim_backward_noalloc(idm_plan *p, const idm_params *prm, const double *p0,
@@ -1184,7 +1304,7 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
                                                 (int64_t)c.threads * c.per_thread);
             // the cached shape is taken when its workspace fits and its layout
             // builds; otherwise the shapes are timed again
-            if (ws_total(p, c.K, nb) <= ws_bytes && build_layout(p, c) == IDM_OK) {
+            if (ws_total(p, c.K, nb, c.stored) <= ws_bytes && build_layout(p, c) == IDM_OK) {
                 p->tuned_cached = 1;
                 return IDM_OK;
             }
@@ -1202,6 +1322,21 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
             if (cap < p->max_lane && (rr != 1 || (cap * 8 < p->max_lane && t < 1024))) continue;
             if (cap > 8 * std::max<int64_t>(p->max_lane, 64)) continue;
             const int64_t nbnd = count_boundaries(p->offsets, p->pb.n_lanes, cap);
+            if (p->sh.stored) {
+                // every step's states kept: whole lanes, the plan's K (it only
+                // groups the FP32 gradient sums), no register block to choose
+                if (nbnd > 0 || ws_total(p, p->sh.K, 0, true) > ws_bytes) continue;
+                if (!backward_stored_kernel(p->pb.bound, rr, t, dense)) continue;
+                Shape sh;
+                sh.threads = t;
+                sh.per_thread = rr;
+                sh.K = p->sh.K;
+                sh.KB = default_kb(rr, sh.K) > 0 ? default_kb(rr, sh.K) : kbs_for(rr)[0];
+                sh.grid = 0;
+                sh.stored = true;
+                cands.push_back(sh);
+                continue;
+            }
             for (int KB : kbs_for(rr)) {
                 // K = KB, and K = 2 KB where a stash variant exists for the shape
                 for (int twice = 0; twice < 2; ++twice) {
@@ -1239,9 +1374,12 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
             Shape s2 = sh;
             if (persistent) {
                 KernelFn fb =
-                    backward_kernel(p->pb.bound, sh.per_thread, sh.threads, sh.KB, sh.K, dense,
-                                    count_boundaries(p->offsets, p->pb.n_lanes,
-                                                     (int64_t)sh.threads * sh.per_thread) > 0);
+                    sh.stored
+                        ? backward_stored_kernel(p->pb.bound, sh.per_thread, sh.threads, dense)
+                        : backward_kernel(p->pb.bound, sh.per_thread, sh.threads, sh.KB, sh.K,
+                                          dense,
+                                          count_boundaries(p->offsets, p->pb.n_lanes,
+                                                           (int64_t)sh.threads * sh.per_thread) > 0);
                 int occ = 0;
                 if (!fb || hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fb, sh.threads, 0) !=
                                hipSuccess || occ < 1)

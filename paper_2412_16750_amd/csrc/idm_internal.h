@@ -124,6 +124,9 @@ KernelFn forward_kernel(int mode, int per_thread, int threads, bool pieces);
 // selects the variant that reads dense upstream gradients.
 KernelFn backward_kernel(int mode, int per_thread, int threads, int KB, int K, bool dense,
                          bool pieces);
+// Backward that reads every step's states from the forward's stored
+// trajectory (whole lanes only).
+KernelFn backward_stored_kernel(int mode, int per_thread, int threads, bool dense);
 
 // Launch helpers (return the HIP error of the launch).
 hipError_t launch_sim(KernelFn fn, int grid, int threads, const SimArgs &a, hipStream_t s);

@@ -895,6 +895,238 @@ __global__ __launch_bounds__(NT) void k_backward(SimArgs A) {
     }
 }
 
+// ---------------------------------------------------------------- backward from stored states
+//
+// The adjoint of k_backward for a caller that kept the forward's whole
+// trajectory, displacements and speeds of every step ([S+1][N] each): the
+// states of a step are read from it instead of being recomputed from
+// checkpoints, so a step costs the partials and the adjoint update only.  A
+// vehicle's leader is the previous vehicle of its lane, one index lower, so
+// its state comes from the same rows (the first vehicle of a thread reads it
+// at index g - 1, the others take it from registers) and the only exchange
+// left is the follower's contribution, one LDS round trip and one barrier per
+// step.  Every operation is the one k_backward performs, in the same order,
+// and the FP32 gradient statistics are flushed into FP64 at the same
+// K-step block boundaries, so the results equal k_backward's bit for bit for
+// the same K.  Whole lanes only (no lane pieces).
+struct StRow {
+    float d, v;
+};
+
+// States of one step (row byte offset `row`): own vehicles and the first
+// vehicle's leader.  `live` = false reads nothing and gives zeros.
+template <int R>
+__device__ __forceinline__ void fetch_states(const SimArgs &A, int64_t row, bool live,
+                                             const int (&off)[R], int offl, StRow (&o)[R],
+                                             StRow &lead) {
+    const uint32_t NB = live ? (uint32_t)(A.n * 4) : 0u;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        o[r].d = load_rec(A.traj_d, row, NB, off[r]);
+        o[r].v = load_rec(A.traj_v, row, NB, off[r]);
+    }
+    lead.d = load_rec(A.traj_d, row, NB, offl);
+    lead.v = load_rec(A.traj_v, row, NB, offl);
+}
+
+template <int MODE, int R, int NT, bool DN>
+__global__ __launch_bounds__(NT) void k_backward_stored(SimArgs A) {
+    __shared__ float2 cbuf[2][NT];
+    double *red = reinterpret_cast<double *>(&cbuf[0][0]);
+    static_assert((NT / 64 + 1) * sizeof(double) <= sizeof(cbuf), "reduction scratch");
+    const int t = threadIdx.x;
+    const int tf = follow_thread<NT>(t);
+    const int64_t N = A.n;
+    const int64_t NB = N * 4;
+    const int S = A.n_steps;
+    const int K = A.K;
+    const float dt = A.dt;
+    const float two_inv = (float)A.two_inv_count;
+    for (int bidx = blockIdx.x; bidx < A.n_bundles; bidx += gridDim.x) {
+        Veh q[R];
+        load_vehicles<R>(A, (int64_t)bidx * (NT * R) + t * R, q);
+        // byte offsets in a row: own vehicles (padding reads vehicle 0) and
+        // the first vehicle's leader (a lane head, whose leader terms are
+        // exactly zero, reads its own state)
+        int off[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) off[r] = (q[r].g > 0 ? q[r].g : 0) * 4;
+        const int offl = q[0].head ? off[0] : (q[0].g - 1) * 4;
+        float p0h[R], p0l[R], ld[R], lv[R], gp0[R], lossf[R];
+        float gs[5][R];
+        double gacc[5][R];
+        double loss = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int32_t gl = q[r].g > 0 ? q[r].g : 0;
+            const double p0 = q[r].g >= 0 ? A.p0[gl] : 0.0;
+            p0h[r] = (float)p0;
+            p0l[r] = (float)(p0 - (double)p0h[r]);
+            ld[r] = 0.0f;
+            lv[r] = 0.0f;
+            gp0[r] = 0.0f;
+            lossf[r] = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                gs[j][r] = 0.0f;
+                gacc[j][r] = 0.0;
+            }
+        }
+        // Three-slot rings of upstream inputs and states, read two steps
+        // ahead: the step on step k reads slot `us` and refills slot `fs`,
+        // the one the previous step read, with step k - 2 (a slot is never
+        // refilled while its old values are still in use, so no value is
+        // copied between registers and no load waits on a newer one).
+        Up seed[R], up[3][R];
+        bool obs_up[3];
+        StRow st[3][R], lt[3];
+        UpCursor cur_k;
+        cursor_init(A, S, cur_k);
+        fetch_up<R, DN>(A, cur_k, q, true, seed);
+        const bool obs_S = cursor_obs(cur_k);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            cursor_dec(A, cur_k);
+            fetch_up<R, DN>(A, cur_k, q, S > i, up[i]);
+            obs_up[i] = S > i && cursor_obs(cur_k);
+            fetch_states<R>(A, (int64_t)(S - 1 - i) * NB, S > i, off, offl, st[i], lt[i]);
+        }
+        // seed: upstream gradient at step S (at S = 0 the state is the
+        // initial one, displacement 0)
+        {
+            StRow sS[R], lS;
+            fetch_states<R>(A, (int64_t)S * NB, S > 0, off, offl, sS, lS);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float dS = S > 0 ? sS[r].d : 0.0f;
+                const float um = mse_up(obs_S, q[r].g >= 0, seed[r], dS, p0h[r], p0l[r],
+                                        two_inv, lossf[r]);
+                gp0[r] += um;
+                ld[r] += seed[r].gd + um;
+                lv[r] += seed[r].gv;
+            }
+        }
+        // first step of the current K-step block (its statistics are flushed
+        // into FP64 after that step)
+        int kflush = S > 0 ? ((S - 1) / K) * K : 0;
+        auto step = [&](const int k, auto use_slot, auto fill_slot) {
+            constexpr int us = decltype(use_slot)::value;
+            constexpr int fs = decltype(fill_slot)::value;
+            Up cur[R];
+            float sd[R], sv[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                cur[r] = up[us][r];
+                sd[r] = st[us][r].d;
+                sv[r] = st[us][r].v;
+            }
+            const bool obs_cur = obs_up[us];
+            const float2 Lk = make_float2(lt[us].d, lt[us].v);
+            // step k - 2 (nothing is read before step 0)
+            cursor_dec(A, cur_k);
+            fetch_up<R, DN>(A, cur_k, q, k > 1, up[fs]);
+            obs_up[fs] = k > 1 && cursor_obs(cur_k);
+            fetch_states<R>(A, (int64_t)(k - 2) * NB, k > 1, off, offl, st[fs], lt[fs]);
+            Part P[R];
+            float mu[R], mw[R], mwAs[R], um[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float dh = r ? sd[r - 1] : Lk.x;
+                const float vh = r ? sv[r - 1] : Lk.y;
+                partials<MODE>(q[r], sd[r], sv[r], dh, vh, dt, A.inv_dt, A.a_min, A.gap_floor,
+                               P[r]);
+                mu[r] = (MODE == 0) ? dt * lv[r] : P[r].gate * dt * lv[r];
+                mw[r] = mu[r] * P[r].w;
+                mwAs[r] = mw[r] * P[r].As;
+                um[r] = mse_up(obs_cur, q[r].g >= 0, cur[r], sd[r], p0h[r], p0l[r], two_inv,
+                               lossf[r]);
+            }
+            // my first vehicle's contribution to its leader, gathered by the
+            // previous thread after the barrier (a lane head's is exactly 0)
+            cbuf[k & 1][t] = make_float2(mw[0] * P[0].hg, -mwAs[0] * P[0].vc);
+            lds_barrier();
+            const float2 F = cbuf[k & 1][tf];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float fd, fv;
+                if (r + 1 < R) {
+                    fd = mw[r + 1] * P[r + 1].hg;
+                    fv = -mwAs[r + 1] * P[r + 1].vc;
+                } else {
+                    fd = F.x;
+                    fv = F.y;
+                }
+                const float gterm = fmaf(-mw[r], P[r].hg, fd);
+                const float gu = gterm + um[r];
+                float nlv = fmaf(dt, ld[r], P[r].carry * lv[r]);
+                nlv = fmaf(mwAs[r], P[r].u1, nlv);
+                nlv = fmaf(-mw[r] * q[r].fa_v0, P[r].x3, nlv);
+                nlv += fv;
+                gs[0][r] = fmaf(mw[r], P[r].x4, gs[0][r]);
+                gs[1][r] = fmaf(mwAs[r], sv[r], gs[1][r]);
+                gs[2][r] = fmaf(mw[r], P[r].rest, gs[2][r]);
+                gs[3][r] = fmaf(mwAs[r], P[r].vdvc, gs[3][r]);
+                gs[4][r] += mwAs[r];
+                gp0[r] += gu;
+                if constexpr (DN) {
+                    ld[r] = (ld[r] + gu) + cur[r].gd;
+                    lv[r] = nlv + cur[r].gv;
+                } else {
+                    ld[r] += gu;
+                    lv[r] = nlv;
+                }
+            }
+            if (k == kflush) {
+                // FP32 statistics of the block into FP64
+                kflush -= K;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    gacc[0][r] += (double)q[r].fa_v0 * (double)gs[0][r];
+                    gacc[1][r] += (double)gs[1][r];
+                    gacc[2][r] += (double)gs[2][r] - (double)q[r].i2a * (double)gs[3][r];
+                    gacc[3][r] -= (double)q[r].i2b * (double)gs[3][r];
+                    gacc[4][r] += (double)gs[4][r];
+                    loss += (double)lossf[r];
+                    lossf[r] = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < 5; ++j) gs[j][r] = 0.0f;
+                }
+            }
+        };
+        using C0 = std::integral_constant<int, 0>;
+        using C1 = std::integral_constant<int, 1>;
+        using C2 = std::integral_constant<int, 2>;
+        // slot 0 holds step k, slot 1 step k - 1 at the top of each iteration
+        int k = S - 1;
+        for (; k >= 2; k -= 3) {
+            step(k, C0{}, C2{});
+            step(k - 1, C1{}, C0{});
+            step(k - 2, C2{}, C1{});
+        }
+        if (k == 1) {
+            step(1, C0{}, C2{});
+            step(0, C1{}, C0{});
+        } else if (k == 0) {
+            step(0, C0{}, C2{});
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) loss += (double)lossf[r];  // S = 0: the seed's residual
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            int32_t g = q[r].g;
+            if (g >= 0) {
+#pragma unroll
+                for (int p = 0; p < 5; ++p) A.g_prm[(int64_t)p * N + g] = gacc[p][r];
+                A.g_p0[g] = (double)gp0[r];
+                A.g_v0[g] = (double)lv[r];
+            }
+        }
+        __syncthreads();  // every cbuf read is done before the reduction reuses it
+        double tot = block_sum(loss, red);
+        if (t == 0 && A.loss_part) A.loss_part[bidx] = tot;
+    }
+}
+
 // ---------------------------------------------------------------- small kernels
 
 __global__ __launch_bounds__(256) void k_loss_finalize(const double *part, int32_t n, double scale,
@@ -1105,9 +1337,10 @@ __global__ __launch_bounds__(256) void k_fit_init_u(AdamArgs A, const float *u_r
 
 // ---------------------------------------------------------------- dispatch
 //
-// The file is compiled nine times (IDM_PART = 0..8) so the backward
+// The file is compiled ten times (IDM_PART = 0..9) so the backward
 // instantiations of the two bound modes, with and without dense upstream
-// gradients, with and without lane pieces, build in parallel.
+// gradients, with and without lane pieces, and the backward from stored
+// states (part 9) build in parallel.
 #ifndef IDM_PART
 #define IDM_PART 0
 #endif
@@ -1181,6 +1414,21 @@ KernelFn backward_kernel_cl_d_ch(int mode, int per_thread, int threads, int KB, 
     return nullptr;
 }
 #endif
+#define IDM_BWS_CASE(M, R, NT)                                                 \
+    if (mode == M && per_thread == R && threads == NT)                          \
+        return dense ? (KernelFn)&k_backward_stored<M, R, NT, true>              \
+                     : (KernelFn)&k_backward_stored<M, R, NT, false>;
+#define IDM_BWS_R(M, R) \
+    IDM_BWS_CASE(M, R, 64) IDM_BWS_CASE(M, R, 128) IDM_BWS_CASE(M, R, 256) \
+    IDM_BWS_CASE(M, R, 512) IDM_BWS_CASE(M, R, 1024)
+#if IDM_PART == 9
+KernelFn backward_stored_kernel(int mode, int per_thread, int threads, bool dense) {
+    IDM_BWS_R(0, 1) IDM_BWS_R(0, 2) IDM_BWS_R(0, 4)
+    IDM_BWS_R(1, 1) IDM_BWS_R(1, 2) IDM_BWS_R(1, 4)
+    return nullptr;
+}
+#endif
+
 #if IDM_PART == 0
 KernelFn backward_kernel_sp_t(int, int, int, int, int);
 KernelFn backward_kernel_cl_t(int, int, int, int, int);

@@ -72,7 +72,7 @@ class Plan:
     def __init__(self, lane_offsets, n_steps: int, dt: float = 0.1, a_min: float = -10.0,
                  gap_floor: float = 1e-3, bound: int = BOUND_SOFTPLUS, ckpt_every: int = 0,
                  delta: float = 4.0, threads: int = 0, per_thread: int = 0, grid: int = 0,
-                 tuning_k: int = 0, block: int = 0):
+                 tuning_k: int = 0, block: int = 0, store_states: bool = False):
         L = _lib.load()
         self._L = L
         self.offsets = np.ascontiguousarray(np.asarray(lane_offsets, dtype=np.int32))
@@ -83,7 +83,8 @@ class Plan:
         pb = IdmProblem(self.n, self.n_lanes, self.n_steps, int(ckpt_every), float(dt), float(delta),
                         float(a_min), float(gap_floor), self.bound,
                         self.offsets.ctypes.data_as(ctypes.c_void_p))
-        tu = IdmTuning(int(threads), int(per_thread), int(tuning_k), int(grid), int(block))
+        tu = IdmTuning(int(threads), int(per_thread), int(tuning_k), int(grid), int(block),
+                       int(bool(store_states)))
         h = ctypes.c_void_p()
         check(L.idm_plan_create(ctypes.byref(pb), ctypes.byref(tu), ctypes.byref(h)), "idm_plan_create")
         self.handle = h
@@ -185,6 +186,38 @@ def idm_sim_backward(plan: Plan, params: torch.Tensor, length: torch.Tensor, p0:
                                    _ptr(grad_traj_d), _ptr(grad_traj_v), oc, _ptr(grad_params),
                                    _ptr(grad_p0), _ptr(grad_v0), _ptr(loss_out), _ptr(workspace),
                                    _stream(stream)), "idm_sim_backward")
+
+
+def idm_sim_backward_stored(plan: Plan, params: torch.Tensor, length: torch.Tensor,
+                            p0: torch.Tensor, traj_d: torch.Tensor, traj_v: torch.Tensor,
+                            grad_params: torch.Tensor, grad_p0: torch.Tensor,
+                            grad_v0: torch.Tensor, workspace: torch.Tensor,
+                            grad_traj_d: Optional[torch.Tensor] = None,
+                            grad_traj_v: Optional[torch.Tensor] = None, obs: Optional[Obs] = None,
+                            loss_out: Optional[torch.Tensor] = None, stream=None) -> None:
+    """idm_sim_backward from the forward's stored trajectory: traj_d and
+    traj_v [S+1, N] as idm_sim_forward wrote them (read, not recomputed)."""
+    n, S = plan.n, plan.n_steps
+    prm = _params_c(plan, params, length)
+    _need(p0, "p0", torch.float64, n)
+    _need(traj_d, "traj_d", torch.float32, (S + 1) * n)
+    _need(traj_v, "traj_v", torch.float32, (S + 1) * n)
+    _need(grad_params, "grad_params", torch.float64, 5 * n)
+    _need(grad_p0, "grad_p0", torch.float64, n)
+    _need(grad_v0, "grad_v0", torch.float64, n)
+    _opt(grad_traj_d, "grad_traj_d", torch.float32, (S + 1) * n)
+    _opt(grad_traj_v, "grad_traj_v", torch.float32, (S + 1) * n)
+    _opt(loss_out, "loss_out", torch.float64, 1)
+    _check_ws(plan, workspace, True)
+    oc = None
+    if obs is not None:
+        _need(obs.target, "obs.target", torch.float32, obs.n_obs * n)
+        oc = ctypes.byref(obs.c())
+    check(plan._L.idm_sim_backward_stored(plan.handle, ctypes.byref(prm), _ptr(p0), _ptr(traj_d),
+                                          _ptr(traj_v), _ptr(grad_traj_d), _ptr(grad_traj_v), oc,
+                                          _ptr(grad_params), _ptr(grad_p0), _ptr(grad_v0),
+                                          _ptr(loss_out), _ptr(workspace), _stream(stream)),
+          "idm_sim_backward_stored")
 
 
 def idm_sim_backward_noalloc(plan: Plan, params: torch.Tensor, length: torch.Tensor,

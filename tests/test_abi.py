@@ -109,6 +109,26 @@ def test_invalid_tuning(L):
     assert st == 0 and (info.per_thread, info.block) == (1, 16)
 
 
+def test_store_states_workspace_and_limits(L):
+    """A plan that keeps every step's states: the workspace has no
+    checkpoints and holds (S+1) x N displacements and speeds; lanes cut into
+    pieces and values other than 0 / 1 are rejected."""
+    off = np.arange(0, 2000 * 1000 + 1, 1000)
+    N, S, K = 2_000_000, 100, 32
+    align = lambda x: (x + 255) // 256 * 256
+    st, info, ws = _check(L, off, tuning=(0, 0, 0, 0, 0, 1), S=S, K=K)
+    assert st == 0 and info.store_states == 1 and info.n_boundaries == 0
+    expect = (align(8 * 2000) + align(16 * 2000) + align(8 * 7 * N)
+              + 2 * align((S + 1) * 4 * N))
+    assert ws == expect
+    st, info, _ = _check(L, off, tuning=(0, 0, 0, 0, 0, 0), S=S, K=K)
+    assert st == 0 and info.store_states == 0
+    # a 1500-vehicle lane needs a 1024-slot bundle cut in two
+    st, _, _ = _check(L, [0, 1500, 1600], tuning=(0, 0, 0, 0, 0, 1))
+    assert st == -3 and b"pieces" in L.idm_last_error()
+    assert _check(L, [0, 100], tuning=(0, 0, 0, 0, 0, 2))[0] == -1
+
+
 def _layout(L, offsets, tuning):
     from paper_2412_16750_amd._lib import IdmTuning
     st, info, _ = _check(L, offsets, tuning=tuning)
