@@ -236,7 +236,9 @@ def c1_latency(dev, log_fn, reps: int = 20) -> dict:
     """Latency of one forward + backward on the single-lane workload (1 open
     lane x 100 vehicles, 1000 steps of 0.1 s, fused MSE against a trajectory
     simulated from a second parameter draw plus N(0, 0.5 m) noise), in both
-    bound modes; median over `reps` event-timed repetitions."""
+    bound modes and with both backwards (checkpoints every 32 steps, or every
+    step's states kept by the forward); median over `reps` event-timed
+    repetitions."""
     import numpy as np
     import torch
     import scenarios
@@ -244,43 +246,86 @@ def c1_latency(dev, log_fn, reps: int = 20) -> dict:
     out = {}
     for mode, name in ((scenarios.MODE_SOFTPLUS, "softplus"), (scenarios.MODE_CLAMP, "clamp")):
         sc = scenarios.single_lane(mode=mode)
-        plan = sim.Plan.for_scenario(sc)
         x = dict(prm=sim.params_tensor(sc.params, dev),
                  length=torch.from_numpy(np.ascontiguousarray(sc.params["length"])).to(dev),
                  p0=torch.from_numpy(np.ascontiguousarray(sc.p0)).to(dev),
                  v=torch.from_numpy(np.ascontiguousarray(sc.v_init)).to(dev))
         # target: the same lane under a second parameter draw, simulated here,
         # plus noise (the seeded recipe of the parity tests)
+        plan0 = sim.Plan.for_scenario(sc)
         tp = sim.params_tensor(scenarios.second_params(sc, 1), dev)
         tr = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device=dev)
-        sim.idm_sim_forward(plan, tp, x["length"], x["p0"], x["v"], tr, None, None)
+        sim.idm_sim_forward(plan0, tp, x["length"], x["p0"], x["v"], tr, None, None)
         noise = torch.from_numpy(scenarios.noise((sc.n_steps, sc.n), 1).astype(np.float32)).to(dev)
         tgt = (tr[1:].double() + x["p0"][None, :] + noise.double()).float().contiguous()
         obs = sim.Obs(tgt, 1, 1)
-        ws = plan.workspace(dev)
-        gp = torch.empty(5, sc.n, dtype=torch.float64, device=dev)
-        g0 = torch.empty(sc.n, dtype=torch.float64, device=dev)
-        g1 = torch.empty_like(g0)
-        traj = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device=dev)
-        fwd = lambda: sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj, None, ws)
-        bwd = lambda: sim.idm_sim_backward(plan, x["prm"], x["length"], x["p0"], x["v"], gp, g0, g1,
-                                           ws, obs=obs)
-        fwd(); bwd()
-        torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        tf, tb = [], []
-        for _ in range(reps):
-            ev[0].record(); fwd(); ev[1].record(); bwd(); ev[2].record()
+        for stored in (False, True):
+            plan = sim.Plan.for_scenario(sc, store_states=stored)
+            ws = plan.workspace(dev)
+            gp = torch.empty(5, sc.n, dtype=torch.float64, device=dev)
+            g0 = torch.empty(sc.n, dtype=torch.float64, device=dev)
+            g1 = torch.empty_like(g0)
+            traj = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device=dev)
+            fwd = lambda: sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj,
+                                              None, ws)
+            bwd = lambda: sim.idm_sim_backward(plan, x["prm"], x["length"], x["p0"], x["v"], gp,
+                                               g0, g1, ws, obs=obs)
+            fwd(); bwd()
             torch.cuda.synchronize()
-            tf.append(ev[0].elapsed_time(ev[1]))
-            tb.append(ev[1].elapsed_time(ev[2]))
-        out[name] = {"forward_ms": float(np.median(tf)), "backward_ms": float(np.median(tb)),
-                     "fwd_plus_bwd_ms": float(np.median(np.asarray(tf) + np.asarray(tb))),
-                     "diagnostics": diagnostics(plan, ws)}
-        log_fn("bench: single lane %s fwd %.3f ms bwd %.3f ms" % (name, out[name]["forward_ms"],
-                                                                out[name]["backward_ms"]))
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            tf, tb = [], []
+            for _ in range(reps):
+                ev[0].record(); fwd(); ev[1].record(); bwd(); ev[2].record()
+                torch.cuda.synchronize()
+                tf.append(ev[0].elapsed_time(ev[1]))
+                tb.append(ev[1].elapsed_time(ev[2]))
+            r = {"forward_ms": float(np.median(tf)), "backward_ms": float(np.median(tb)),
+                 "fwd_plus_bwd_ms": float(np.median(np.asarray(tf) + np.asarray(tb))),
+                 "diagnostics": diagnostics(plan, ws)}
+            key = name + ("_stored_states" if stored else "")
+            out[key] = r
+            log_fn("bench: single lane %s fwd %.3f ms bwd %.3f ms" % (key, r["forward_ms"],
+                                                                    r["backward_ms"]))
     return {"workload": "1 open lane x 100 vehicles, 1000 steps of 0.1 s, fused MSE vs a second "
-                        "parameter draw + N(0, 0.5 m)", **out}
+                        "parameter draw + N(0, 0.5 m); *_stored_states: the forward keeps every "
+                        "step's states and the backward reads them (no checkpoints)", **out}
+
+
+def stored_variant(plan, x, obs, traj_d, gp, gp0, gv0, stream, log_fn, reps: int = 10) -> dict:
+    """The same forward + backward with every step's states kept: the forward
+    also writes the speeds ([S+1, N], 0.8 GB here) and idm_sim_backward_stored
+    reads both rows instead of recomputing them from checkpoints.  Timed after
+    the headline loop (not part of it); its gradients must equal the
+    checkpointed backward's bit for bit."""
+    import numpy as np
+    import torch
+    from paper_2412_16750_amd import sim
+    S, N = plan.n_steps, plan.n
+    ref = (gp.clone(), gp0.clone(), gv0.clone())
+    traj_v = torch.empty(S + 1, N, dtype=torch.float32, device=traj_d.device)
+    ws = plan.workspace(traj_d.device)
+    lo = torch.zeros(1, dtype=torch.float64, device=traj_d.device)
+    fwd = lambda: sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj_d, traj_v,
+                                      None, stream)
+    bwd = lambda: sim.idm_sim_backward_stored(plan, x["prm"], x["length"], x["p0"], traj_d, traj_v,
+                                              gp, gp0, gv0, ws, obs=obs, loss_out=lo,
+                                              stream=stream)
+    fwd(); bwd()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+    for i in range(reps):
+        ev[i][0].record(stream); fwd(); ev[i][1].record(stream); bwd(); ev[i][2].record(stream)
+    torch.cuda.synchronize()
+    f_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    b_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    same = all(bool(torch.equal(a, b)) for a, b in zip(ref, (gp, gp0, gv0)))
+    log_fn("bench: stored-states variant fwd %.3f ms bwd %.3f ms (bitwise equal: %s)"
+           % (f_ms, b_ms, same))
+    del traj_v, ws
+    return {"forward_ms": round(f_ms, 4), "backward_ms": round(b_ms, 4),
+            "fwd_plus_bwd_ms": round(f_ms + b_ms, 4), "gradients_bitwise_equal": same,
+            "note": "the forward also writes every step's speeds; the backward reads both rows "
+                    "instead of recomputing them (idm_sim_backward_stored)"}
 
 
 def fit_report(dev, log_fn, cap: int = 2000) -> dict:
@@ -308,9 +353,12 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
     n_pairs = int(data.X.shape[0])
     rates = mlp_rates(ws, data)
     del data
-    # the fitting problem, hidden parameters = the scenario's draw
+    # the fitting problem, hidden parameters = the scenario's draw; the fit's
+    # plan keeps every step's states (0.4 GB here) so its backward reads them
+    # instead of recomputing them: a fit step is latency-bound (100 lanes, one
+    # work-group each), and that removes a third of each backward step
     sc = scenarios.fit()
-    plan = sim.Plan.for_scenario(sc)
+    plan = sim.Plan.for_scenario(sc, store_states=True)
     prm = sim.params_tensor(sc.params, dev)
     length = torch.from_numpy(np.ascontiguousarray(sc.params["length"])).to(dev)
     p0 = torch.from_numpy(np.ascontiguousarray(sc.p0)).to(dev)
@@ -325,7 +373,8 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
     Uh = torch.from_numpy(scenarios.normalized_params(sc.params)).to(dev)
     heldout_mse = ws.evaluate(net, ws.Dataset(X, Uh))
     out = {"workload": "100 lanes x 1000 vehicles, 500 steps, observed every 10th step, "
-                       "N(0, 0.5 m) noise; Adam lr 1e-2 on normalised parameters",
+                       "N(0, 0.5 m) noise; Adam lr 1e-2 on normalised parameters; every "
+                       "step's states kept for the backward",
            "mlp": {"pairs": n_pairs, "batch": 4096, "epochs": MLP_EPOCHS,
                    "lr": "cosine %.0e -> %.0e" % (MLP_LR, MLP_LR_FINAL), "steps": rep["steps"],
                    "training_loop": "one HIP graph launch per epoch (the epoch's steps, each the "
@@ -355,7 +404,23 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
     for i, k in enumerate(scenarios.PARAM_NAMES):
         mask = ~heads if k in ("T", "b", "s0") else np.ones(sc.n, bool)
         perr[k] = float(np.median(rel[i, mask]))
-    out["cold_200"] = {"ms_per_iteration": e0.elapsed_time(e1) / 200, "rmse_m": rmse200,
+    # the same 200 iterations on a plan with checkpoints every 32 steps
+    plan_ck = sim.Plan.for_scenario(sc)
+    fck = Fitter(plan_ck, length, p0, v, obs, lr0=1e-2)
+    fck.init(cold)
+    fck.run(5)
+    fck.init(cold)
+    torch.cuda.synchronize()
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e2.record()
+    fck.run(200)
+    e3.record()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(fck.params, f.params))
+    del fck, plan_ck
+    out["cold_200"] = {"ms_per_iteration": e0.elapsed_time(e1) / 200,
+                       "ms_per_iteration_checkpointed": e2.elapsed_time(e3) / 200,
+                       "checkpointed_params_bitwise_equal": same, "rmse_m": rmse200,
                        "median_rel_param_error": perr,
                        "loss_first_last": [float(f.losses()[0]), float(f.losses()[-1])],
                        "diagnostics_last_iteration": diagnostics(plan, f.workspace)}
@@ -635,6 +700,8 @@ def main():
                     help="skip the time-per-step against vehicle-count sweep")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the many-uneven-lanes graph replay and autotuner section")
+    ap.add_argument("--no-stored-variant", dest="stored_variant", action="store_false",
+                    help="skip the stored-states forward + backward timed after the headline")
     ap.add_argument("--no-c1", action="store_true",
                     help="skip the single-lane (100 vehicles x 1000 steps) latency section")
     args = ap.parse_args()
@@ -724,6 +791,8 @@ def main():
     value = vsteps / (ms_per_step / 1e3)
     log("bench: fwd %.3f ms, bwd %.3f ms, step %.3f ms, loss %.6e" % (fwd_ms, bwd_ms, ms_per_step,
                                                                     loss.item()))
+    stored = stored_variant(plan, x, obs, traj_d, gp, gp0, gv0, stream, log) \
+        if args.stored_variant else None
 
     # dominant kernel: the backward (recompute + adjoint + fused loss)
     bwd_flops = FLOP_BWD * vsteps
@@ -793,6 +862,7 @@ def main():
                                   "backward": round(1e3 * bwd_ms / S, 4),
                                   "fwd_plus_bwd": round(1e3 * ms_per_step / S, 4)},
         "diagnostics": diag,
+        "stored_states_variant": stored,
     }
     if not args.no_c1:
         out["single_lane_latency"] = c1_latency(dev, log)
