@@ -33,6 +33,8 @@ if ROOT not in sys.path:
 # term by term in the design doc.
 FLOP_FWD = 40
 FLOP_BWD = 130
+# the backward from stored states: the recompute's 40 gone
+FLOP_BWD_STORED = 90
 # MI355X published FP32 vector peak (packed FP32: two lanes' worth per
 # instruction); the kernels are built without packed FP32, so their own
 # ceiling is half of it: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA).
@@ -45,18 +47,23 @@ PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
 # HBM bytes of one backward (and one forward) launch on this workload from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by the copy-kernel calibration,
 # 2.000 and 1.000), valid only for the kernel source they were taken with
-# (sha256 of idm_kernels.hip followed by idm_device.h).
-TRAFFIC_BWD_BYTES = 1.2062e+09
-TRAFFIC_FWD_BYTES = 9.820e+08
+# (sha256 of idm_kernels.hip followed by idm_device.h): COUNTERS below.
 # Share of the SIMD cycles with a VALU instruction issuing: 4 x SQ_ACTIVE_INST_VALU
 # (quad-cycles summed over waves; a transcendental counts two) over 1024 SIMDs x
 # the kernel's cycles, GRBM_COUNT / 8 (the counter sums the 8 XCDs), both from
 # one counter pass; the clock those cycles give (cycles over the launch
 # duration), and VALU instructions per wave and simulated step.  Same kernel
-# source as the traffic figures.
-VALU_BUSY_BWD, VALU_PER_WAVE_STEP_BWD, CLOCK_GHZ_BWD = 0.861, 119.1, 2.337
-VALU_BUSY_FWD, VALU_PER_WAVE_STEP_FWD, CLOCK_GHZ_FWD = 0.936, 36.5, 2.318
-TRAFFIC_KERNEL_SHA256 = "5e4439fd76ead072ef94458f2b354583ed21d490f611fe692802ab3af8731547"
+# source as the traffic figures; per headline mode (the backward from stored
+# states with its forward writing both rows, or the checkpointed pair).
+COUNTERS = {
+    "stored": {"traffic_bwd": 2.6714e+09, "traffic_fwd": 1.7812e+09,
+               "valu_busy_bwd": 0.748, "valu_per_wave_step_bwd": 79.2, "clock_bwd": 2.263,
+               "valu_busy_fwd": 0.525, "valu_per_wave_step_fwd": 36.8, "clock_fwd": 2.329},
+    "checkpointed": {"traffic_bwd": 1.2063e+09, "traffic_fwd": 9.8465e+08,
+                     "valu_busy_bwd": 0.849, "valu_per_wave_step_bwd": 119.1, "clock_bwd": 2.391,
+                     "valu_busy_fwd": 0.868, "valu_per_wave_step_fwd": 37.2, "clock_fwd": 2.378},
+}
+TRAFFIC_KERNEL_SHA256 = "28834cee17d4cb71e91bc76f9f286ec5c0c8aa140e7e636f7bc5d9fcb3e25afa"
 
 
 # Warm-start network training: Adam over 1M pairs, batch 4096, learning rate
@@ -291,25 +298,34 @@ def c1_latency(dev, log_fn, reps: int = 20) -> dict:
                         "step's states and the backward reads them (no checkpoints)", **out}
 
 
-def stored_variant(plan, x, obs, traj_d, gp, gp0, gv0, stream, log_fn, reps: int = 10) -> dict:
-    """The same forward + backward with every step's states kept: the forward
-    also writes the speeds ([S+1, N], 0.8 GB here) and idm_sim_backward_stored
-    reads both rows instead of recomputing them from checkpoints.  Timed after
-    the headline loop (not part of it); its gradients must equal the
-    checkpointed backward's bit for bit."""
+def other_variant(plan, x, obs, traj_d, gp, gp0, gv0, stream, log_fn, stored: bool,
+                  reps: int = 10) -> dict:
+    """The headline's forward + backward done the other way, timed after the
+    headline loop (not part of it): with `stored`, the forward also writes
+    every step's speeds and idm_sim_backward_stored reads both rows; without
+    it, the forward writes displacements and checkpoints every K steps and
+    idm_sim_backward recomputes each block.  Its gradients must equal the
+    headline's bit for bit."""
     import numpy as np
     import torch
     from paper_2412_16750_amd import sim
     S, N = plan.n_steps, plan.n
     ref = (gp.clone(), gp0.clone(), gv0.clone())
-    traj_v = torch.empty(S + 1, N, dtype=torch.float32, device=traj_d.device)
-    ws = plan.workspace(traj_d.device)
-    lo = torch.zeros(1, dtype=torch.float64, device=traj_d.device)
-    fwd = lambda: sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj_d, traj_v,
-                                      None, stream)
-    bwd = lambda: sim.idm_sim_backward_stored(plan, x["prm"], x["length"], x["p0"], traj_d, traj_v,
-                                              gp, gp0, gv0, ws, obs=obs, loss_out=lo,
-                                              stream=stream)
+    dev = traj_d.device
+    traj_v = torch.empty(S + 1, N, dtype=torch.float32, device=dev) if stored else None
+    ws = plan.workspace(dev)
+    lo = torch.zeros(1, dtype=torch.float64, device=dev)
+    if stored:
+        fwd = lambda: sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj_d,
+                                          traj_v, None, stream)
+        bwd = lambda: sim.idm_sim_backward_stored(plan, x["prm"], x["length"], x["p0"], traj_d,
+                                                  traj_v, gp, gp0, gv0, ws, obs=obs, loss_out=lo,
+                                                  stream=stream)
+    else:
+        fwd = lambda: sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj_d,
+                                          None, ws, stream)
+        bwd = lambda: sim.idm_sim_backward(plan, x["prm"], x["length"], x["p0"], x["v"], gp, gp0,
+                                           gv0, ws, obs=obs, loss_out=lo, stream=stream)
     fwd(); bwd()
     torch.cuda.synchronize()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
@@ -319,13 +335,16 @@ def stored_variant(plan, x, obs, traj_d, gp, gp0, gv0, stream, log_fn, reps: int
     f_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
     b_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
     same = all(bool(torch.equal(a, b)) for a, b in zip(ref, (gp, gp0, gv0)))
-    log_fn("bench: stored-states variant fwd %.3f ms bwd %.3f ms (bitwise equal: %s)"
-           % (f_ms, b_ms, same))
+    log_fn("bench: %s variant fwd %.3f ms bwd %.3f ms (bitwise equal: %s)"
+           % ("stored-states" if stored else "checkpointed", f_ms, b_ms, same))
     del traj_v, ws
+    note = ("the forward also writes every step's speeds; the backward reads both rows instead of "
+            "recomputing them (idm_sim_backward_stored)" if stored else
+            "the forward writes displacements and checkpoints every K steps; the backward "
+            "recomputes each K-step block from its checkpoint (idm_sim_backward)")
     return {"forward_ms": round(f_ms, 4), "backward_ms": round(b_ms, 4),
             "fwd_plus_bwd_ms": round(f_ms + b_ms, 4), "gradients_bitwise_equal": same,
-            "note": "the forward also writes every step's speeds; the backward reads both rows "
-                    "instead of recomputing them (idm_sim_backward_stored)"}
+            "note": note}
 
 
 def fit_report(dev, log_fn, cap: int = 2000) -> dict:
@@ -700,8 +719,12 @@ def main():
                     help="skip the time-per-step against vehicle-count sweep")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the many-uneven-lanes graph replay and autotuner section")
-    ap.add_argument("--no-stored-variant", dest="stored_variant", action="store_false",
-                    help="skip the stored-states forward + backward timed after the headline")
+    ap.add_argument("--stored", action="store_true",
+                    help="time the forward writing every step's states and the backward reading "
+                         "them as the headline step")
+    ap.add_argument("--no-other-variant", dest="other_variant", action="store_false",
+                    help="skip the other backward (checkpointed or stored states) timed after "
+                         "the headline")
     ap.add_argument("--no-c1", action="store_true",
                     help="skip the single-lane (100 vehicles x 1000 steps) latency section")
     args = ap.parse_args()
@@ -752,7 +775,15 @@ def main():
     x, obs = build_inputs(sc, dev)
     plan = sim.Plan.for_scenario(sc, threads=args.threads, per_thread=args.per_thread)
     info = plan.info()
+    # The step: the forward writes the displacement trajectory and checkpoints
+    # every K steps, the backward recomputes each K-step block from them;
+    # --stored times the forward writing displacements and speeds of every
+    # step and the backward reading them (idm_sim_backward_stored) instead.
+    # Both give the same gradients bit for bit; the other one is timed after
+    # the headline loop.
+    stored_mode = args.stored
     traj_d = torch.empty(S + 1, N, dtype=torch.float32, device=dev)
+    traj_v = torch.empty(S + 1, N, dtype=torch.float32, device=dev) if stored_mode else None
     ws = plan.workspace(dev)
     gp = torch.empty(5, N, dtype=torch.float64, device=dev)
     gp0 = torch.empty(N, dtype=torch.float64, device=dev)
@@ -761,13 +792,22 @@ def main():
     stream = torch.cuda.current_stream()
 
     def fwd():
-        sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj_d, None, ws, stream)
+        if stored_mode:
+            sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj_d, traj_v, None,
+                                stream)
+        else:
+            sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj_d, None, ws,
+                                stream)
 
     def bwd():
-        sim.idm_sim_backward(plan, x["prm"], x["length"], x["p0"], x["v"], gp, gp0, gv0, ws,
-                             obs=obs, loss_out=loss, stream=stream)
+        if stored_mode:
+            sim.idm_sim_backward_stored(plan, x["prm"], x["length"], x["p0"], traj_d, traj_v, gp,
+                                        gp0, gv0, ws, obs=obs, loss_out=loss, stream=stream)
+        else:
+            sim.idm_sim_backward(plan, x["prm"], x["length"], x["p0"], x["v"], gp, gp0, gv0, ws,
+                                 obs=obs, loss_out=loss, stream=stream)
 
-    log("bench: plan %s" % info)
+    log("bench: plan %s, %s" % (info, "states kept" if stored_mode else "checkpoints"))
     for _ in range(args.warmup):
         fwd()
         bwd()
@@ -791,18 +831,40 @@ def main():
     value = vsteps / (ms_per_step / 1e3)
     log("bench: fwd %.3f ms, bwd %.3f ms, step %.3f ms, loss %.6e" % (fwd_ms, bwd_ms, ms_per_step,
                                                                     loss.item()))
-    stored = stored_variant(plan, x, obs, traj_d, gp, gp0, gv0, stream, log) \
-        if args.stored_variant else None
+    if stored_mode:
+        # anomaly counts: one more forward (untimed) that writes them into the
+        # workspace (the timed forward is given none)
+        sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], None, None, ws, stream)
+    diag = diagnostics(plan, ws)
+    other = other_variant(plan, x, obs, traj_d, gp, gp0, gv0, stream, log, not stored_mode) \
+        if args.other_variant else None
 
-    # dominant kernel: the backward (recompute + adjoint + fused loss)
-    bwd_flops = FLOP_BWD * vsteps
-    achieved = bwd_flops / (bwd_ms / 1e3) / 1e12
-    # algorithmic HBM bytes of one backward launch: checkpoints (2 x 4 B x N per
-    # block), params 5 x 4 B, length, p0 (8 B) x N, targets 4 B x N x S,
-    # FP64 gradients 7 x 8 B x N
     nblk = -(-S // info["ckpt_every"])
-    bwd_bytes = N * (nblk * 8 + 20 + 4 + 16 + 4 * S + 56)
-    fwd_bytes = N * (20 + 4 + 16 + 4 + 4 * (S + 1) + nblk * 8)
+    if stored_mode:
+        # dominant kernel: the backward from stored states (adjoint + fused
+        # loss).  Algorithmic HBM bytes of one launch: own displacement and
+        # speed of steps 0..S-1 and the displacement of step S (the leader's
+        # entries are the neighbour's, the same rows), targets 4 B x N x S,
+        # params 5 x 4 B, length, p0 (8 B) and the leader's p0 and length,
+        # FP64 gradients 7 x 8 B x N; the forward writes both rows of every
+        # step and reads the same inputs plus v_init
+        flop_bwd = FLOP_BWD_STORED
+        bwd_bytes = N * (8 * S + 4 + 4 * S + 20 + 4 + 16 + 56)
+        fwd_bytes = N * (20 + 4 + 16 + 4 + 8 * (S + 1))
+        kname = ("k_backward_stored<softplus,R=%d,threads=%d> (FP32 sums flushed every %d steps)"
+                 % (info["per_thread"], info["threads"], info["ckpt_every"]))
+    else:
+        # dominant kernel: the backward (recompute + adjoint + fused loss).
+        # Algorithmic HBM bytes of one launch: checkpoints (2 x 4 B x N per
+        # block), params 5 x 4 B, length, p0 (8 B) x N, targets 4 B x N x S,
+        # FP64 gradients 7 x 8 B x N
+        flop_bwd = FLOP_BWD
+        bwd_bytes = N * (nblk * 8 + 20 + 4 + 16 + 4 * S + 56)
+        fwd_bytes = N * (20 + 4 + 16 + 4 + 4 * (S + 1) + nblk * 8)
+        kname = ("k_backward<softplus,R=%d,threads=%d,KB=%d> (K=%d)"
+                 % (info["per_thread"], info["threads"], info["block"], info["ckpt_every"]))
+    bwd_flops = flop_bwd * vsteps
+    achieved = bwd_flops / (bwd_ms / 1e3) / 1e12
     import hashlib
     csrc = os.path.join(ROOT, "paper_2412_16750_amd", "csrc")
     h = hashlib.sha256()
@@ -811,34 +873,46 @@ def main():
     same_kernel = h.hexdigest() == TRAFFIC_KERNEL_SHA256
     same_shape = (same_kernel and info["ckpt_every"] == 32 and info["block"] == 16
                   and info["threads"] == 1024 and info["per_thread"] == 1)
-    traffic = TRAFFIC_BWD_BYTES if same_shape else None
-    traffic_fwd = TRAFFIC_FWD_BYTES if same_shape else None
-    diag = diagnostics(plan, ws)
+    cnt = COUNTERS["stored" if stored_mode else "checkpointed"] if same_shape else None
+    traffic = cnt["traffic_bwd"] if cnt else None
+    traffic_fwd = cnt["traffic_fwd"] if cnt else None
     # measured HBM ceiling: read + write rate of a 1 GiB streaming copy
     ceil = copy_ceiling(dev)
     copy_gbps = ceil["GBps"]
     bwd_gbps = bwd_bytes / (bwd_ms / 1e3) / 1e9
     fwd_gbps = fwd_bytes / (fwd_ms / 1e3) / 1e9
+    if other is not None:
+        # the other pair's algorithmic bytes and, for this kernel build, its
+        # measured traffic and VALU figures
+        if stored_mode:
+            other["hbm_algorithmic_bytes"] = {
+                "backward": N * (nblk * 8 + 20 + 4 + 16 + 4 * S + 56),
+                "forward": N * (20 + 4 + 16 + 4 + 4 * (S + 1) + nblk * 8)}
+        else:
+            other["hbm_algorithmic_bytes"] = {"backward": N * (8 * S + 4 + 4 * S + 20 + 4 + 16 + 56),
+                                              "forward": N * (20 + 4 + 16 + 4 + 8 * (S + 1))}
+        other["counters"] = COUNTERS["checkpointed" if stored_mode else "stored"] \
+            if same_shape else None
     roofline = {
         "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
         "peak_non_packed": PEAK_FP32_NON_PACKED_TFLOPS,
         "frac_non_packed": round(achieved / PEAK_FP32_NON_PACKED_TFLOPS, 4),
-        "kernel": "k_backward<softplus,R=%d,threads=%d,KB=%d> (K=%d)"
-                  % (info["per_thread"], info["threads"], info["block"], info["ckpt_every"]),
-        "kernel_ms": round(bwd_ms, 4), "flop_per_vehicle_step": FLOP_BWD,
+        "kernel": kname, "kernel_ms": round(bwd_ms, 4), "flop_per_vehicle_step": flop_bwd,
+        "hbm_algorithmic_bytes": bwd_bytes,
         "hbm_algorithmic_GBps": round(bwd_gbps, 1),
         "hbm_frac": round(bwd_gbps / PEAK_HBM_GBPS, 4),
         "copy_ceiling_GBps": round(copy_gbps, 1),
         "copy_ceiling": {k: v for k, v in ceil.items() if k != "GBps"},
         "hbm_frac_of_copy": round(bwd_gbps / copy_gbps, 4),
-        "valu_busy": VALU_BUSY_BWD if same_shape else None,
-        "valu_per_wave_step": VALU_PER_WAVE_STEP_BWD if same_shape else None,
-        "clock_GHz_counters": CLOCK_GHZ_BWD if same_shape else None,
+        "valu_busy": cnt["valu_busy_bwd"] if cnt else None,
+        "valu_per_wave_step": cnt["valu_per_wave_step_bwd"] if cnt else None,
+        "clock_GHz_counters": cnt["clock_bwd"] if cnt else None,
         "forward": {"kernel_ms": round(fwd_ms, 4), "traffic": traffic_fwd,
-                    "valu_busy": VALU_BUSY_FWD if same_shape else None,
-                    "valu_per_wave_step": VALU_PER_WAVE_STEP_FWD if same_shape else None,
-                    "clock_GHz_counters": CLOCK_GHZ_FWD if same_shape else None,
+                    "hbm_algorithmic_bytes": fwd_bytes,
+                    "valu_busy": cnt["valu_busy_fwd"] if cnt else None,
+                    "valu_per_wave_step": cnt["valu_per_wave_step_fwd"] if cnt else None,
+                    "clock_GHz_counters": cnt["clock_fwd"] if cnt else None,
                     "achieved_TFLOPs": round(FLOP_FWD * vsteps / (fwd_ms / 1e3) / 1e12, 3),
                     "hbm_algorithmic_GBps": round(fwd_gbps, 1),
                     "hbm_frac": round(fwd_gbps / PEAK_HBM_GBPS, 4),
@@ -853,16 +927,20 @@ def main():
         "vs_baseline": value / PAPER_FWD_BWD_VEH_STEPS_PER_S,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "scale: 2000 lanes x 1000 vehicles = 2M, 100 steps of 0.1 s, "
-                               "softplus bounds, checkpoints every %d, fused MSE vs dense targets"
-                               % info["ckpt_every"],
+                               "softplus bounds, fused MSE vs dense targets; %s"
+                               % ("the forward writes every step's displacements and speeds, the "
+                                  "backward reads them" if stored_mode else
+                                  "checkpoints every %d steps, the backward recomputes each block"
+                                  % info["ckpt_every"]),
                    "n_vehicles": N, "n_steps": S, "ckpt_every": info["ckpt_every"],
+                   "backward": "stored states" if stored_mode else "checkpoint/recompute",
                    "threads": info["threads"], "per_thread": info["per_thread"]},
         "roofline": roofline,
         "us_per_simulated_step": {"forward": round(1e3 * fwd_ms / S, 4),
                                   "backward": round(1e3 * bwd_ms / S, 4),
                                   "fwd_plus_bwd": round(1e3 * ms_per_step / S, 4)},
         "diagnostics": diag,
-        "stored_states_variant": stored,
+        ("checkpointed_variant" if stored_mode else "stored_states_variant"): other,
     }
     if not args.no_c1:
         out["single_lane_latency"] = c1_latency(dev, log)
