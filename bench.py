@@ -372,12 +372,13 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
     n_pairs = int(data.X.shape[0])
     rates = mlp_rates(ws, data)
     del data
-    # the fitting problem, hidden parameters = the scenario's draw; the fit's
-    # plan keeps every step's states (0.4 GB here) so its backward reads them
-    # instead of recomputing them: a fit step is latency-bound (100 lanes, one
-    # work-group each), and that removes a third of each backward step
+    # the fitting problem, hidden parameters = the scenario's draw.  The fit's
+    # plan leaves the backward to the autotuner (store_states "auto"), given
+    # room for every step's states (0.4 GB here): a fit step is latency-bound
+    # (100 lanes, one work-group each), and reading the states instead of
+    # recomputing them removes a third of each backward step
     sc = scenarios.fit()
-    plan = sim.Plan.for_scenario(sc, store_states=True)
+    plan = sim.Plan.for_scenario(sc, store_states="auto")
     prm = sim.params_tensor(sc.params, dev)
     length = torch.from_numpy(np.ascontiguousarray(sc.params["length"])).to(dev)
     p0 = torch.from_numpy(np.ascontiguousarray(sc.p0)).to(dev)
@@ -388,12 +389,22 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
     noise = torch.from_numpy(scenarios.noise((n_obs, sc.n), 4).astype(np.float32)).to(dev)
     obs = sim.Obs(ws.observe(plan, hidden, p0, noise, 10, 10, n_obs), 10, 10)
     cold = sim.params_tensor(scenarios.cold_params(sc), dev)
+    room = sim.Plan.for_scenario(sc, store_states=True).workspace_bytes
+    tb = sim.StepBuffers(plan, cold, length, p0, v, obs=obs, workspace_bytes=room)
+    t0 = time.perf_counter()
+    tuned = sim.idm_plan_autotune(tb, reps=3)
+    tune_s = time.perf_counter() - t0
+    del tb
+    log_fn("bench: fit plan autotuned %s in %.3f s" % (tuned, tune_s))
     X = ws.features(plan, obs, p0, length)
     Uh = torch.from_numpy(scenarios.normalized_params(sc.params)).to(dev)
     heldout_mse = ws.evaluate(net, ws.Dataset(X, Uh))
     out = {"workload": "100 lanes x 1000 vehicles, 500 steps, observed every 10th step, "
-                       "N(0, 0.5 m) noise; Adam lr 1e-2 on normalised parameters; every "
-                       "step's states kept for the backward",
+                       "N(0, 0.5 m) noise; Adam lr 1e-2 on normalised parameters; launch shape "
+                       "and backward (checkpoints or kept states) chosen by the autotuner",
+           "plan": {**{k: tuned[k] for k in ("threads", "per_thread", "ckpt_every", "block",
+                                             "grid", "store_states")},
+                    "autotune_seconds": round(tune_s, 3)},
            "mlp": {"pairs": n_pairs, "batch": 4096, "epochs": MLP_EPOCHS,
                    "lr": "cosine %.0e -> %.0e" % (MLP_LR, MLP_LR_FINAL), "steps": rep["steps"],
                    "training_loop": "one HIP graph launch per epoch (the epoch's steps, each the "

@@ -105,7 +105,10 @@ typedef struct {
                            then only groups the FP32 gradient sums).  Fastest where a step's
                            latency, not the chip's throughput, sets the time (few lanes,
                            e.g. a fit of 100 lanes); whole lanes only (a plan whose bundles
-                           would cut a lane is IDM_ERR_UNSUPPORTED).  0: checkpoints */
+                           would cut a lane is IDM_ERR_UNSUPPORTED).  0: checkpoints.
+                           2: start with checkpoints and let idm_plan_autotune time both
+                           backwards (the kept states only where the workspace it is given
+                           holds them) and keep the faster */
 } idm_tuning;
 
 /* Per-vehicle IDM parameters (Sec. III-A), FP32 [N] each, all > 0. */
@@ -157,7 +160,8 @@ typedef struct {
     int32_t n_levels;       /* launches per pass: 1 + most extra pieces of one lane */
     int32_t n_boundaries;   /* piece boundaries of lanes longer than a bundle */
     int32_t autotune_cached; /* 1: the last idm_plan_autotune took its shape from the cache */
-    int32_t store_states;   /* 1: every step's states are kept (idm_tuning.store_states) */
+    int32_t store_states;   /* 1: every step's states are kept (idm_tuning.store_states 1, or
+                               2 after the autotuner chose them) */
 } idm_plan_info;
 idm_status idm_plan_get_info(const idm_plan *plan, idm_plan_info *out);
 

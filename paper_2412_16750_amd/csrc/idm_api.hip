@@ -111,6 +111,7 @@ struct idm_plan {
     hipStream_t side = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     int32_t tuned_cached = 0;  // the last autotune took its shape from the cache
+    int32_t store_pref = 0;    // idm_tuning.store_states: 0, 1, or 2 = the autotuner chooses
 };
 
 namespace {
@@ -475,7 +476,7 @@ idm_status choose_shape(const idm_plan *p, const idm_tuning *tu, Shape &sh) {
     sh.K = K;
     sh.KB = KB;
     sh.grid = (tu && tu->grid > 0) ? tu->grid : 0;
-    sh.stored = tu && tu->store_states > 0;
+    sh.stored = tu && tu->store_states == 1;  // 2: checkpoints until the autotuner chooses
     return IDM_OK;
 }
 
@@ -844,12 +845,13 @@ idm_status host_plan(const idm_problem *pb, const idm_tuning *tu, idm_plan *p, S
     }
     if (tu && (tu->grid < 0 || tu->ckpt_every < 0 || tu->block < 0))
         return fail(IDM_ERR_INVALID_ARG, "tuning: negative grid, ckpt_every or block");
-    if (tu && tu->store_states != 0 && tu->store_states != 1)
-        return fail(IDM_ERR_INVALID_ARG, "tuning: store_states must be 0 or 1");
+    if (tu && (tu->store_states < 0 || tu->store_states > 2))
+        return fail(IDM_ERR_INVALID_ARG, "tuning: store_states must be 0, 1 or 2");
     p->pb = *pb;
     p->offsets.assign(off, off + pb->n_lanes + 1);
     p->pb.lane_offsets_host = nullptr;
     p->max_lane = max_lane;
+    p->store_pref = tu ? tu->store_states : 0;
     return choose_shape(p, tu, sh);
 }
 
@@ -914,7 +916,7 @@ std::vector<int64_t> tune_key(const idm_plan *p, bool dense, bool obs, int cus) 
     k.push_back(dense ? 1 : 0);
     k.push_back(obs ? 1 : 0);
     k.push_back(cus);
-    k.push_back(p->sh.stored ? 1 : 0);
+    k.push_back(p->store_pref);
     return k;
 }
 
@@ -1322,11 +1324,12 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
             if (cap < p->max_lane && (rr != 1 || (cap * 8 < p->max_lane && t < 1024))) continue;
             if (cap > 8 * std::max<int64_t>(p->max_lane, 64)) continue;
             const int64_t nbnd = count_boundaries(p->offsets, p->pb.n_lanes, cap);
-            if (p->sh.stored) {
-                // every step's states kept: whole lanes, the plan's K (it only
-                // groups the FP32 gradient sums), no register block to choose
-                if (nbnd > 0 || ws_total(p, p->sh.K, 0, true) > ws_bytes) continue;
-                if (!backward_stored_kernel(p->pb.bound, rr, t, dense)) continue;
+            // keeping every step's states (a plan made with store_states = 1,
+            // or 2: the autotuner weighs both backwards): whole lanes, the
+            // plan's K (it only groups the FP32 gradient sums), no register
+            // block to choose
+            if (p->store_pref >= 1 && nbnd == 0 && ws_total(p, p->sh.K, 0, true) <= ws_bytes &&
+                backward_stored_kernel(p->pb.bound, rr, t, dense)) {
                 Shape sh;
                 sh.threads = t;
                 sh.per_thread = rr;
@@ -1335,14 +1338,14 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
                 sh.grid = 0;
                 sh.stored = true;
                 cands.push_back(sh);
-                continue;
             }
+            if (p->store_pref == 1) continue;
             for (int KB : kbs_for(rr)) {
                 // K = KB, and K = 2 KB where a stash variant exists for the shape
                 for (int twice = 0; twice < 2; ++twice) {
                     const int K = k_fixed ? p->pb.ckpt_every : (twice ? 2 * KB : KB);
                     if (k_fixed && twice) break;
-                    if (K % KB != 0 || ws_total(p, K, nbnd) > ws_bytes) continue;
+                    if (K % KB != 0 || ws_total(p, K, nbnd, false) > ws_bytes) continue;
                     KernelFn fb = backward_kernel(p->pb.bound, rr, t, KB, K, dense, nbnd > 0);
                     if (twice && fb == backward_kernel(p->pb.bound, rr, t, KB, KB, dense, nbnd > 0))
                         continue;

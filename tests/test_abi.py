@@ -112,7 +112,8 @@ def test_invalid_tuning(L):
 def test_store_states_workspace_and_limits(L):
     """A plan that keeps every step's states: the workspace has no
     checkpoints and holds (S+1) x N displacements and speeds; lanes cut into
-    pieces and values other than 0 / 1 are rejected."""
+    pieces and values other than 0, 1 and 2 (the autotuner chooses; the
+    plan starts with checkpoints) are rejected."""
     off = np.arange(0, 2000 * 1000 + 1, 1000)
     N, S, K = 2_000_000, 100, 32
     align = lambda x: (x + 255) // 256 * 256
@@ -126,7 +127,9 @@ def test_store_states_workspace_and_limits(L):
     # a 1500-vehicle lane needs a 1024-slot bundle cut in two
     st, _, _ = _check(L, [0, 1500, 1600], tuning=(0, 0, 0, 0, 0, 1))
     assert st == -3 and b"pieces" in L.idm_last_error()
-    assert _check(L, [0, 100], tuning=(0, 0, 0, 0, 0, 2))[0] == -1
+    assert _check(L, [0, 100], tuning=(0, 0, 0, 0, 0, 3))[0] == -1
+    st, info, _ = _check(L, [0, 100], tuning=(0, 0, 0, 0, 0, 2))   # the autotuner chooses
+    assert st == 0 and info.store_states == 0
 
 
 def _layout(L, offsets, tuning):

@@ -282,3 +282,47 @@ def test_stored_plan_step_graph_autotune_and_autograd():
         (d[-1].double() ** 2).sum().backward()
         grads.append(prm.grad.cpu().numpy())
     assert np.array_equal(grads[0], grads[1])
+
+
+def test_autotuner_weighs_both_backwards():
+    """store_states = 2: the plan starts with checkpoints and idm_plan_autotune
+    times both backwards, the kept states only when the workspace it is given
+    holds them; with K fixed every choice gives the checkpointed plan's
+    gradients bit for bit, and the choice is cached per problem."""
+    import torch
+    from paper_2412_16750_amd import sim
+    sc = ragged_scenario([400, 300, 500, 20], 400, ckpt_every=32)
+    steps = np.arange(1, sc.n_steps + 1)
+    tgt = torch.from_numpy(oracle_targets(sc, steps, c=21)).cuda()
+    obs = sim.Obs(tgt, 1, 1)
+    x = device_inputs(sc)
+    ref_plan = sim.Plan.for_scenario(sc)
+    ref = sim.StepBuffers(ref_plan, x["prm"], x["length"], x["p0"], x["v"], obs=obs)
+    sim.idm_step_graph_launch(ref)
+    room = sim.Plan.for_scenario(sc, store_states=True).workspace_bytes
+    # no room for the states: checkpoints stay
+    auto = sim.Plan.for_scenario(sc, store_states="auto")
+    assert auto.info()["store_states"] == 0
+    b = sim.StepBuffers(auto, x["prm"], x["length"], x["p0"], x["v"], obs=obs,
+                        workspace_bytes=auto.workspace_bytes)
+    info = sim.idm_plan_autotune(b, reps=2)
+    assert info["store_states"] == 0
+    # room for them: the faster of the two
+    auto2 = sim.Plan.for_scenario(sc, store_states="auto", tuning_k=32)
+    b2 = sim.StepBuffers(auto2, x["prm"], x["length"], x["p0"], x["v"], obs=obs,
+                         workspace_bytes=room)
+    info2 = sim.idm_plan_autotune(b2, reps=2)
+    log("autotune with room for the states: %s" % info2)
+    sim.idm_step_graph_launch(b2)
+    torch.cuda.synchronize()
+    assert np.array_equal(b2.grad_params.cpu().numpy(), ref.grad_params.cpu().numpy())
+    assert np.array_equal(b2.grad_v0.cpu().numpy(), ref.grad_v0.cpu().numpy())
+    # the same problem again: the cached choice
+    auto3 = sim.Plan.for_scenario(sc, store_states="auto", tuning_k=32)
+    b3 = sim.StepBuffers(auto3, x["prm"], x["length"], x["p0"], x["v"], obs=obs,
+                         workspace_bytes=room)
+    info3 = sim.idm_plan_autotune(b3, reps=2)
+    assert info3["autotune_cached"] == 1 and info3["store_states"] == info2["store_states"]
+    sim.idm_step_graph_launch(b3)
+    torch.cuda.synchronize()
+    assert np.array_equal(b3.grad_params.cpu().numpy(), ref.grad_params.cpu().numpy())
