@@ -134,7 +134,7 @@ __device__ __forceinline__ void partials_gd(const Veh &q, float v, float gap, fl
     float x = v * q.inv_v0;
     float x2 = x * x;
     bool floored = !(gap > gap_floor);
-    float sg = floored ? gap_floor : gap;
+    float sg = fmaxf(gap, gap_floor);  // = floored ? gap_floor : gap (a NaN gap too), as in accel_gd
     float inv_sg = rcp_fast(sg);
     float vdv = v * dv;
     float s_opt = fmaf(vdv, q.c, fmaf(v, q.T, q.s0));
@@ -154,7 +154,7 @@ __device__ __forceinline__ void partials_gd(const Veh &q, float v, float gap, fl
         // a_lb = max(-v/dt, a_min) (tie -> a_min branch), entering as -a_lb
         float pv = v * inv_dt;
         bool on_v = pv < -a_min;
-        float mlb = on_v ? pv : -a_min;
+        float mlb = fminf(pv, -a_min);  // = on_v ? pv : -a_min, as in accel_gd
         P.w = logistic(fmaf(q.a, P.rest, mlb));       // ahat - a_lb
         P.gate = 1.0f;
         P.carry = on_v ? P.w : 1.0f;

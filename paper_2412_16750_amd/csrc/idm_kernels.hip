@@ -500,6 +500,27 @@ __device__ __forceinline__ void fetch_up(const SimArgs &A, const UpCursor &c, co
     }
 }
 
+// fetch_up with explicit per-vehicle byte offsets (an offset beyond the row
+// reads 0).
+template <int R, bool DN>
+__device__ __forceinline__ void fetch_up_at(const SimArgs &A, const UpCursor &c,
+                                            const int (&off)[R], bool live, Up (&u)[R]) {
+    const uint32_t NB = live ? (uint32_t)(A.n * 4) : 0u;
+    const uint32_t bgd = A.gd ? NB : 0u, bgv = A.gv ? NB : 0u;
+    const uint32_t btg = cursor_obs(c) ? NB : 0u;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if constexpr (DN) {
+            u[r].gd = load_rec(A.gd, c.row, bgd, off[r]);
+            u[r].gv = load_rec(A.gv, c.row, bgv, off[r]);
+        } else {
+            u[r].gd = 0.0f;
+            u[r].gv = 0.0f;
+        }
+        u[r].tg = load_rec(A.target, c.tg_row, btg, off[r]);
+    }
+}
+
 // Fused loss at one step: returns 2 (p - target) / |O| and adds the squared
 // residual to `lossf`; 0 when the step is not observed.  p0 = p0h + p0l is
 // split into two floats, and the residual is formed as ((p0h - target) + d)
@@ -969,7 +990,9 @@ __device__ __forceinline__ void fetch_states(const SimArgs &A, int64_t row, bool
 
 template <int MODE, int R, int NT, bool DN>
 __global__ __launch_bounds__(NT) void k_backward_stored(SimArgs A) {
-    __shared__ float2 cbuf[2][NT];
+    // one exchange buffer per ring slot: consecutive steps use different ones,
+    // at addresses fixed at compile time
+    __shared__ float2 cbuf[3][NT];
     double *red = reinterpret_cast<double *>(&cbuf[0][0]);
     static_assert((NT / 64 + 1) * sizeof(double) <= sizeof(cbuf), "reduction scratch");
     const int t = threadIdx.x;
@@ -983,12 +1006,14 @@ __global__ __launch_bounds__(NT) void k_backward_stored(SimArgs A) {
     for (int bidx = blockIdx.x; bidx < A.n_bundles; bidx += gridDim.x) {
         Veh q[R];
         load_vehicles<R>(A, (int64_t)bidx * (NT * R) + t * R, q);
-        // byte offsets in a row: own vehicles (padding reads vehicle 0) and
-        // the first vehicle's leader (a lane head, whose leader terms are
-        // exactly zero, reads its own state)
+        // byte offsets in a row: own vehicles and the first vehicle's leader
+        // (a lane head, whose leader terms are exactly zero, reads its own
+        // state).  A padding slot's offset lies beyond every row, so its
+        // states, upstream inputs and target all read 0 and its residual is
+        // exactly 0 without a select.
         int off[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) off[r] = (q[r].g > 0 ? q[r].g : 0) * 4;
+        for (int r = 0; r < R; ++r) off[r] = q[r].g >= 0 ? q[r].g * 4 : INT_MAX - 3;
         const int offl = q[0].head ? off[0] : (q[0].g - 1) * 4;
         float p0h[R], p0l[R], ld[R], lv[R], gp0[R], lossf[R];
         float gs[5][R];
@@ -1020,12 +1045,12 @@ __global__ __launch_bounds__(NT) void k_backward_stored(SimArgs A) {
         StRow st[3][R], lt[3];
         UpCursor cur_k;
         cursor_init(A, S, cur_k);
-        fetch_up<R, DN>(A, cur_k, q, true, seed);
+        fetch_up_at<R, DN>(A, cur_k, off, true, seed);
         const bool obs_S = cursor_obs(cur_k);
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             cursor_dec(A, cur_k);
-            fetch_up<R, DN>(A, cur_k, q, S > i, up[i]);
+            fetch_up_at<R, DN>(A, cur_k, off, S > i, up[i]);
             obs_up[i] = S > i && cursor_obs(cur_k);
             fetch_states<R>(A, (int64_t)(S - 1 - i) * NB, S > i, off, offl, st[i], lt[i]);
         }
@@ -1037,8 +1062,8 @@ __global__ __launch_bounds__(NT) void k_backward_stored(SimArgs A) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const float dS = S > 0 ? sS[r].d : 0.0f;
-                const float um = mse_up(obs_S, q[r].g >= 0, seed[r], dS, p0h[r], p0l[r],
-                                        two_inv, lossf[r]);
+                const float um = mse_up(obs_S, true, seed[r], dS, p0h[r], p0l[r], two_inv,
+                                        lossf[r]);
                 gp0[r] += um;
                 ld[r] += seed[r].gd + um;
                 lv[r] += seed[r].gv;
@@ -1062,7 +1087,7 @@ __global__ __launch_bounds__(NT) void k_backward_stored(SimArgs A) {
             const float2 Lk = make_float2(lt[us].d, lt[us].v);
             // step k - 2 (nothing is read before step 0)
             cursor_dec(A, cur_k);
-            fetch_up<R, DN>(A, cur_k, q, k > 1, up[fs]);
+            fetch_up_at<R, DN>(A, cur_k, off, k > 1, up[fs]);
             obs_up[fs] = k > 1 && cursor_obs(cur_k);
             fetch_states<R>(A, (int64_t)(k - 2) * NB, k > 1, off, offl, st[fs], lt[fs]);
             Part P[R];
@@ -1076,14 +1101,13 @@ __global__ __launch_bounds__(NT) void k_backward_stored(SimArgs A) {
                 mu[r] = (MODE == 0) ? dt * lv[r] : P[r].gate * dt * lv[r];
                 mw[r] = mu[r] * P[r].w;
                 mwAs[r] = mw[r] * P[r].As;
-                um[r] = mse_up(obs_cur, q[r].g >= 0, cur[r], sd[r], p0h[r], p0l[r], two_inv,
-                               lossf[r]);
+                um[r] = mse_up(obs_cur, true, cur[r], sd[r], p0h[r], p0l[r], two_inv, lossf[r]);
             }
             // my first vehicle's contribution to its leader, gathered by the
             // previous thread after the barrier (a lane head's is exactly 0)
-            cbuf[k & 1][t] = make_float2(mw[0] * P[0].hg, -mwAs[0] * P[0].vc);
+            cbuf[us][t] = make_float2(mw[0] * P[0].hg, -mwAs[0] * P[0].vc);
             lds_barrier();
-            const float2 F = cbuf[k & 1][tf];
+            const float2 F = cbuf[us][tf];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 float fd, fv;
