@@ -56,14 +56,14 @@ PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
 # source as the traffic figures; per headline mode (the backward from stored
 # states with its forward writing both rows, or the checkpointed pair).
 COUNTERS = {
-    "stored": {"traffic_bwd": 2.6714e+09, "traffic_fwd": 1.7812e+09,
-               "valu_busy_bwd": 0.748, "valu_per_wave_step_bwd": 79.2, "clock_bwd": 2.263,
-               "valu_busy_fwd": 0.525, "valu_per_wave_step_fwd": 36.8, "clock_fwd": 2.329},
-    "checkpointed": {"traffic_bwd": 1.2063e+09, "traffic_fwd": 9.8465e+08,
-                     "valu_busy_bwd": 0.849, "valu_per_wave_step_bwd": 119.1, "clock_bwd": 2.391,
-                     "valu_busy_fwd": 0.868, "valu_per_wave_step_fwd": 37.2, "clock_fwd": 2.378},
+    "stored": {"traffic_bwd": 2.6628e+09, "traffic_fwd": 1.7826e+09,
+               "valu_busy_bwd": 0.707, "valu_per_wave_step_bwd": 74.8, "clock_bwd": 2.302,
+               "valu_busy_fwd": 0.512, "valu_per_wave_step_fwd": 36.8, "clock_fwd": 2.371},
+    "checkpointed": {"traffic_bwd": 1.2382e+09, "traffic_fwd": 9.8466e+08,
+                     "valu_busy_bwd": 0.841, "valu_per_wave_step_bwd": 118.3, "clock_bwd": 2.336,
+                     "valu_busy_fwd": 0.878, "valu_per_wave_step_fwd": 37.2, "clock_fwd": 2.328},
 }
-TRAFFIC_KERNEL_SHA256 = "28834cee17d4cb71e91bc76f9f286ec5c0c8aa140e7e636f7bc5d9fcb3e25afa"
+TRAFFIC_KERNEL_SHA256 = "06e03fd9d9f994203ec9176f42ea353eba14d490bd562c767ed19b55d93fa024"
 
 
 # Warm-start network training: Adam over 1M pairs, batch 4096, learning rate
