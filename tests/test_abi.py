@@ -132,6 +132,21 @@ def test_store_states_workspace_and_limits(L):
     assert st == 0 and info.store_states == 0
 
 
+def test_backward_entry_points_reject_null_arguments(L):
+    """Argument checks that run before any device work: a null plan, and
+    (through a null plan) the stored-state backward's required trajectories."""
+    from paper_2412_16750_amd._lib import IdmParams
+    prm = IdmParams(1, 1, 1, 1, 1, 1)
+    for call in (lambda: L.idm_sim_backward_stored(None, ctypes.byref(prm), 8, 8, 8, None, None,
+                                                   None, 8, 8, 8, None, 8, None),
+                 lambda: L.idm_sim_backward(None, ctypes.byref(prm), 8, 8, None, None, None, 8, 8,
+                                            8, None, 8, None),
+                 lambda: L.idm_sim_backward_noalloc(None, ctypes.byref(prm), 8, 8, None, None,
+                                                    None, 8, 8, 8, None, None)):
+        assert call() == -1
+        assert b"plan is null" in L.idm_last_error()
+
+
 def _layout(L, offsets, tuning):
     from paper_2412_16750_amd._lib import IdmTuning
     st, info, _ = _check(L, offsets, tuning=tuning)
