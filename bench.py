@@ -56,14 +56,14 @@ PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
 # source as the traffic figures; per headline mode (the backward from stored
 # states with its forward writing both rows, or the checkpointed pair).
 COUNTERS = {
-    "stored": {"traffic_bwd": 2.6628e+09, "traffic_fwd": 1.7826e+09,
-               "valu_busy_bwd": 0.707, "valu_per_wave_step_bwd": 74.8, "clock_bwd": 2.302,
-               "valu_busy_fwd": 0.512, "valu_per_wave_step_fwd": 36.8, "clock_fwd": 2.371},
-    "checkpointed": {"traffic_bwd": 1.2382e+09, "traffic_fwd": 9.8466e+08,
-                     "valu_busy_bwd": 0.841, "valu_per_wave_step_bwd": 118.3, "clock_bwd": 2.336,
-                     "valu_busy_fwd": 0.878, "valu_per_wave_step_fwd": 37.2, "clock_fwd": 2.328},
+    "stored": {"traffic_bwd": 2.6627e+09, "traffic_fwd": 1.7821e+09,
+               "valu_busy_bwd": 0.701, "valu_per_wave_step_bwd": 74.8, "clock_bwd": 2.324,
+               "valu_busy_fwd": 0.511, "valu_per_wave_step_fwd": 37.0, "clock_fwd": 2.388},
+    "checkpointed": {"traffic_bwd": 1.2382e+09, "traffic_fwd": 9.8218e+08,
+                     "valu_busy_bwd": 0.847, "valu_per_wave_step_bwd": 118.3, "clock_bwd": 2.360,
+                     "valu_busy_fwd": 0.930, "valu_per_wave_step_fwd": 36.5, "clock_fwd": 2.349},
 }
-TRAFFIC_KERNEL_SHA256 = "06e03fd9d9f994203ec9176f42ea353eba14d490bd562c767ed19b55d93fa024"
+TRAFFIC_KERNEL_SHA256 = "b363833fafa545a11dcd28ceae44704f2f639e102122daac74151d528a28075d"
 
 
 # Warm-start network training: Adam over 1M pairs, batch 4096, learning rate

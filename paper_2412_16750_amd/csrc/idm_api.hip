@@ -573,7 +573,8 @@ idm_status run_forward(idm_plan *p, const idm_params *prm, const double *p0, con
                         "workspace; the forward needs it");
         ext_args(p, ws, a);
     }
-    KernelFn fn = forward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, p->n_bnd > 0);
+    KernelFn fn = forward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, p->n_bnd > 0,
+                                 a.traj_d && a.traj_v);
     if (!fn) return fail(IDM_ERR_UNSUPPORTED, "no forward kernel for this shape");
     uint64_t *diag = ws ? (uint64_t *)((char *)ws + ws_diag_off(p)) : nullptr;
     // pieces of long lanes: level l reads the boundary states level l-1 wrote

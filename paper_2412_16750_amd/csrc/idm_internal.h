@@ -118,7 +118,9 @@ struct EgoAdamArgs {
 using KernelFn = const void *;
 
 // Lookup of compiled kernel instantiations; nullptr when not instantiated.
-KernelFn forward_kernel(int mode, int per_thread, int threads, bool pieces);
+// two_rows: both trajectory rows are written (the kernel's bundle-edge waves
+// then store through the cache).
+KernelFn forward_kernel(int mode, int per_thread, int threads, bool pieces, bool two_rows);
 // Backward kernel for a register block KB and checkpoint interval K (the
 // stash variant when K = 2 KB and one is instantiated for the shape); `dense`
 // selects the variant that reads dense upstream gradients.

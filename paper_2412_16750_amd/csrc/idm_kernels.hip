@@ -199,7 +199,11 @@ __device__ __forceinline__ void lead_pipe_step(const ExtRs &xr, LeadPipe &lp, in
 }
 
 // CH: bundles may hold lane pieces (see k_backward).
-template <int MODE, int R, int NT, bool CH>
+// ER: both trajectory rows (displacements and speeds) are written, with the
+// bundle-edge waves storing through the cache (see below); a separate
+// instantiation, since the extra control flow costs the one-row forward 6-8 %
+// even when it is not taken.
+template <int MODE, int R, int NT, bool CH, bool ER>
 __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf)[64]) {
     __shared__ float2 sbuf[2][NT];
     __shared__ uint64_t dred[2][NT / 64];  // per-wave diagnostic counts
@@ -263,7 +267,7 @@ __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf
         // store both rows through the cache when both are written: 0.39 ms.
         // (With one row the streamed stores are faster everywhere.)
         bool edge_cached = false;
-        if (A.traj_d && A.traj_v) {
+        if constexpr (ER) {
             const int w = t >> 6;
             const int32_t first_g = __shfl(q[0].g, 0, 64);
             const int32_t last_g = __shfl(q[R - 1].g, 63, 64);
@@ -405,9 +409,9 @@ if (edge_cached) {
 // while a wave holds at most 80 SGPRs as the runtime counts them (96 halved
 // the measured occupancy, 58 -> 31 resident waves per CU, and cost 55 % of
 // the forward's time); the cap keeps the allocator below that.
-template <int MODE, int R, int NT>
+template <int MODE, int R, int NT, bool ER>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_num_sgpr(72))) void k_forward(SimArgs A) {
-    forward_body<MODE, R, NT, false>(A, nullptr);
+    forward_body<MODE, R, NT, false, ER>(A, nullptr);
 }
 
 // Lane pieces (one vehicle per thread), with the register budget of 8 waves
@@ -416,7 +420,7 @@ template <int MODE, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_forward_pieces(
     SimArgs A) {
     __shared__ float2 lead_buf[2][64];
-    forward_body<MODE, 1, NT, true>(A, lead_buf);
+    forward_body<MODE, 1, NT, true, false>(A, lead_buf);
 }
 
 // ---------------------------------------------------------------- backward
@@ -1410,13 +1414,14 @@ __global__ __launch_bounds__(256) void k_fit_init_u(AdamArgs A, const float *u_r
 #define IDM_FWD_CASE(M, R, NT)                                                \
     if (mode == M && per_thread == R && threads == NT)                        \
         return pieces ? (R == 1 ? (KernelFn)&k_forward_pieces<M, NT> : nullptr)  \
-                      : (KernelFn)&k_forward<M, R, NT>;
+                      : (two_rows ? (KernelFn)&k_forward<M, R, NT, true>          \
+                                  : (KernelFn)&k_forward<M, R, NT, false>);
 #define IDM_FWD_R(M, R) \
     IDM_FWD_CASE(M, R, 64) IDM_FWD_CASE(M, R, 128) IDM_FWD_CASE(M, R, 256) \
     IDM_FWD_CASE(M, R, 512) IDM_FWD_CASE(M, R, 1024)
 
 #if IDM_PART == 0
-KernelFn forward_kernel(int mode, int per_thread, int threads, bool pieces) {
+KernelFn forward_kernel(int mode, int per_thread, int threads, bool pieces, bool two_rows) {
     IDM_FWD_R(0, 1) IDM_FWD_R(0, 2) IDM_FWD_R(0, 4)
     IDM_FWD_R(1, 1) IDM_FWD_R(1, 2) IDM_FWD_R(1, 4)
     return nullptr;
