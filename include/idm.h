@@ -109,6 +109,20 @@ typedef struct {
                            2: start with checkpoints and let idm_plan_autotune time both
                            backwards (the kept states only where the workspace it is given
                            holds them) and keep the faster */
+    int32_t tile_steps;   /* J > 0: halo tiles (needs store_states 1, one vehicle per
+                           thread and explicit threads of 256, 512 or 1024; J even, a
+                           multiple of K and below threads).  Every lane longer than a
+                           work-group is cut into tiles of at most threads - J owned
+                           vehicles, one work-group each (a lane that fits one work-group
+                           is one tile), and the steps into blocks of J run as successive
+                           launches: a tile also simulates the J vehicles ahead of its own
+                           in the forward and the J behind them in the backward, so that
+                           information, which moves one vehicle per step, cannot reach
+                           its owned vehicles from outside within a launch (Sec. III-B's
+                           synchronous update).  Owned results equal the whole-lane
+                           kernels' bit for bit.  For few long lanes, whose work-groups
+                           leave most compute units idle.  With store_states 2 the
+                           autotuner also times tile shapes; 0: whole lanes */
 } idm_tuning;
 
 /* Per-vehicle IDM parameters (Sec. III-A), FP32 [N] each, all > 0. */
@@ -145,8 +159,11 @@ idm_status idm_plan_destroy(idm_plan *plan);
  * checkpoints ceil(S/K) * 2 * N * 4 B, per-bundle loss partials and
  * diagnostic counts (see idm_plan_diagnostics), the FP64
  * gradient buffer used by idm_fit_step and, with lanes longer than a bundle,
- * (2 S + 1) * 8 B per piece boundary.  256-byte aligned.  With piece
- * boundaries, idm_sim_forward needs the workspace too. */
+ * (2 S + 1) * 8 B per piece boundary.  A plan that keeps every step's states
+ * holds them instead of the checkpoints (8 (S+1) N B), and with halo tiles
+ * 68 N B more for the adjoints and sums carried between launches.  256-byte
+ * aligned.  With piece boundaries, idm_sim_forward needs the workspace too;
+ * with halo tiles it needs the workspace or both trajectory outputs. */
 size_t idm_workspace_bytes(const idm_plan *plan);
 
 /* Chosen launch shape and packing statistics. */
@@ -162,6 +179,7 @@ typedef struct {
     int32_t autotune_cached; /* 1: the last idm_plan_autotune took its shape from the cache */
     int32_t store_states;   /* 1: every step's states are kept (idm_tuning.store_states 1, or
                                2 after the autotuner chose them) */
+    int32_t tile_steps;     /* J of halo tiles (n_bundles then counts tiles), 0: whole lanes */
 } idm_plan_info;
 idm_status idm_plan_get_info(const idm_plan *plan, idm_plan_info *out);
 

@@ -30,7 +30,8 @@ class IdmProblem(ctypes.Structure):
 
 class IdmTuning(ctypes.Structure):
     _fields_ = [("threads", c_int32), ("per_thread", c_int32), ("ckpt_every", c_int32),
-                ("grid", c_int32), ("block", c_int32), ("store_states", c_int32)]
+                ("grid", c_int32), ("block", c_int32), ("store_states", c_int32),
+                ("tile_steps", c_int32)]
 
 
 class IdmParams(ctypes.Structure):
@@ -48,7 +49,7 @@ class IdmPlanInfo(ctypes.Structure):
                 ("grid", c_int32), ("block", c_int32), ("n_bundles", c_int32), ("max_lane", c_int32),
                 ("n_slots", c_int64), ("fill", c_double), ("n_levels", c_int32),
                 ("n_boundaries", c_int32), ("autotune_cached", c_int32),
-                ("store_states", c_int32)]
+                ("store_states", c_int32), ("tile_steps", c_int32)]
 
 
 class IdmFitState(ctypes.Structure):

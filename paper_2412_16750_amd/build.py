@@ -1,7 +1,7 @@
 """Compile the HIP library ``libidmx.so`` for gfx950, in-tree.
 
 hipcc cross-compiles, so this runs without a GPU.  The kernels file is built
-ten times (IDM_PART = 0..9) in parallel to shorten the build.
+eleven times (IDM_PART = 0..10) in parallel to shorten the build.
 """
 from __future__ import annotations
 
@@ -51,7 +51,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(bdir, exist_ok=True)
     cc = hipcc()
     units = []
-    for part in range(10):
+    for part in range(11):
         units.append((os.path.join(CSRC, "idm_kernels.hip"), os.path.join(bdir, "idm_kernels_%d.o" % part),
                       ["-DIDM_PART=%d" % part]))
     units.append((os.path.join(CSRC, "idm_api.hip"), os.path.join(bdir, "idm_api.o"), []))

@@ -54,6 +54,8 @@ struct Shape {
     int KB = 0;  // backward register block (divides K)
     int grid = 0;
     bool stored = false;  // the forward keeps every step's states for the backward
+    int tile = 0;         // J > 0: halo tiles advancing J steps per launch (stored, one
+                          // vehicle per thread)
 };
 
 bool valid_threads(int t) { return t == 64 || t == 128 || t == 256 || t == 512 || t == 1024; }
@@ -112,6 +114,7 @@ struct idm_plan {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     int32_t tuned_cached = 0;  // the last autotune took its shape from the cache
     int32_t store_pref = 0;    // idm_tuning.store_states: 0, 1, or 2 = the autotuner chooses
+    int32_t n_tiles = 0;       // halo tiles (= n_bundles) when sh.tile > 0, else 0
 };
 
 namespace {
@@ -131,50 +134,93 @@ int64_t count_boundaries(const std::vector<int32_t> &offsets, int L, int64_t cap
     return n;
 }
 
-// Workspace layout: [loss partials: one double per bundle (at most one per
-// lane piece)][forward diagnostics: two uint64 per bundle][fit: 7N doubles]
-// [checkpoints][boundary states: n_bnd x (S+1) float2][boundary adjoint
-// contributions: n_bnd x S float2][stored states: (S+1) x N displacements,
-// then (S+1) x N speeds].  A plan that keeps every step's states has no
-// checkpoints and no piece boundaries; any other has no stored states.
+// Workspace dimensions of a launch shape: checkpoint interval, piece
+// boundaries, kept states and halo tiles.
+struct WsDims {
+    int K = 0;
+    int64_t nbnd = 0;
+    bool stored = false;
+    int64_t ntile = 0;  // halo tiles, 0 for bundles
+};
+
+WsDims dims_of(const idm_plan *p) {
+    WsDims w;
+    w.K = p->sh.K;
+    w.nbnd = p->n_bnd;
+    w.stored = p->sh.stored;
+    w.ntile = p->n_tiles;
+    return w;
+}
+
+WsDims dims(int K, int64_t nbnd, bool stored, int64_t ntile = 0) {
+    WsDims w;
+    w.K = K;
+    w.nbnd = nbnd;
+    w.stored = stored;
+    w.ntile = ntile;
+    return w;
+}
+
+// Per-work-group partials: one per bundle (at most one per lane piece), or
+// one per halo tile.
+int64_t n_parts(const idm_plan *p, const WsDims &w) {
+    return w.ntile > 0 ? w.ntile : (int64_t)p->pb.n_lanes + w.nbnd;
+}
+
+// Workspace layout: [loss partials: one double per bundle or tile][forward
+// diagnostics: two uint64 per bundle or tile][fit: 7N doubles][checkpoints]
+// [boundary states: n_bnd x (S+1) float2][boundary adjoint contributions:
+// n_bnd x S float2][stored states: (S+1) x N displacements, then (S+1) x N
+// speeds][halo tiles: carried adjoints 2 x [2][N] floats, gp0 sums [N]
+// floats, parameter and loss sums [6][N] doubles].  A plan that keeps every
+// step's states has no checkpoints and no piece boundaries; any other has no
+// stored states; only halo tiles have the last part.
 size_t ws_loss_off(const idm_plan *) { return 0; }
-size_t ws_diag_off(const idm_plan *p, int64_t nbnd) {
-    return align_up(sizeof(double) * ((size_t)p->pb.n_lanes + (size_t)nbnd));
+size_t ws_diag_off(const idm_plan *p, const WsDims &w) {
+    return align_up(sizeof(double) * (size_t)n_parts(p, w));
 }
-size_t ws_fit_off(const idm_plan *p, int64_t nbnd) {
-    return ws_diag_off(p, nbnd) +
-           align_up(2 * sizeof(uint64_t) * ((size_t)p->pb.n_lanes + (size_t)nbnd));
+size_t ws_fit_off(const idm_plan *p, const WsDims &w) {
+    return ws_diag_off(p, w) + align_up(2 * sizeof(uint64_t) * (size_t)n_parts(p, w));
 }
-size_t ws_ckpt_off(const idm_plan *p, int64_t nbnd) {
-    return ws_fit_off(p, nbnd) + align_up(sizeof(double) * 7 * (size_t)p->pb.n_vehicles);
+size_t ws_ckpt_off(const idm_plan *p, const WsDims &w) {
+    return ws_fit_off(p, w) + align_up(sizeof(double) * 7 * (size_t)p->pb.n_vehicles);
 }
-size_t ckpt_bytes(const idm_plan *p, int K, bool stored) {
-    if (stored) return 0;
-    size_t nb = p->pb.n_steps == 0 ? 0 : (size_t)(p->pb.n_steps + K - 1) / K;
+size_t ckpt_bytes(const idm_plan *p, const WsDims &w) {
+    if (w.stored) return 0;
+    size_t nb = p->pb.n_steps == 0 ? 0 : (size_t)(p->pb.n_steps + w.K - 1) / w.K;
     return align_up(nb * 2 * sizeof(float) * (size_t)p->pb.n_vehicles);
 }
-size_t ws_ext_off(const idm_plan *p, int K, int64_t nbnd, bool stored) {
-    return ws_ckpt_off(p, nbnd) + ckpt_bytes(p, K, stored);
-}
+size_t ws_ext_off(const idm_plan *p, const WsDims &w) { return ws_ckpt_off(p, w) + ckpt_bytes(p, w); }
 size_t state_rows_bytes(const idm_plan *p) {
     return align_up(((size_t)p->pb.n_steps + 1) * sizeof(float) * (size_t)p->pb.n_vehicles);
 }
 size_t ext_state_bytes(const idm_plan *p, int64_t nbnd) {
     return align_up((size_t)nbnd * ((size_t)p->pb.n_steps + 1) * 2 * sizeof(float));
 }
-size_t ws_states_off(const idm_plan *p, int K, int64_t nbnd, bool stored) {
-    return ws_ext_off(p, K, nbnd, stored) + ext_state_bytes(p, nbnd) +
-           align_up((size_t)nbnd * (size_t)p->pb.n_steps * 2 * sizeof(float));
+size_t ws_states_off(const idm_plan *p, const WsDims &w) {
+    return ws_ext_off(p, w) + ext_state_bytes(p, w.nbnd) +
+           align_up((size_t)w.nbnd * (size_t)p->pb.n_steps * 2 * sizeof(float));
 }
-size_t ws_total(const idm_plan *p, int K, int64_t nbnd, bool stored) {
-    return ws_states_off(p, K, nbnd, stored) + (stored ? 2 * state_rows_bytes(p) : 0);
+size_t ws_tile_off(const idm_plan *p, const WsDims &w) {
+    return ws_states_off(p, w) + (w.stored ? 2 * state_rows_bytes(p) : 0);
 }
-size_t ws_total(const idm_plan *p, int K, int64_t nbnd) {
-    return ws_total(p, K, nbnd, p->sh.stored);
+size_t tile_carry_bytes(const idm_plan *p) {
+    return align_up(2 * sizeof(float) * (size_t)p->pb.n_vehicles);
 }
-size_t ws_fit_off(const idm_plan *p) { return ws_fit_off(p, p->n_bnd); }
-size_t ws_diag_off(const idm_plan *p) { return ws_diag_off(p, p->n_bnd); }
-size_t ws_ckpt_off(const idm_plan *p) { return ws_ckpt_off(p, p->n_bnd); }
+size_t tile_gp0_bytes(const idm_plan *p) {
+    return align_up(sizeof(float) * (size_t)p->pb.n_vehicles);
+}
+size_t tile_bytes(const idm_plan *p, const WsDims &w) {
+    if (w.ntile == 0) return 0;
+    return 2 * tile_carry_bytes(p) + tile_gp0_bytes(p) +
+           align_up(6 * sizeof(double) * (size_t)p->pb.n_vehicles);
+}
+size_t ws_total(const idm_plan *p, const WsDims &w) { return ws_tile_off(p, w) + tile_bytes(p, w); }
+size_t ws_total(const idm_plan *p) { return ws_total(p, dims_of(p)); }
+size_t ws_fit_off(const idm_plan *p) { return ws_fit_off(p, dims_of(p)); }
+size_t ws_diag_off(const idm_plan *p) { return ws_diag_off(p, dims_of(p)); }
+size_t ws_ckpt_off(const idm_plan *p) { return ws_ckpt_off(p, dims_of(p)); }
+size_t ws_states_off(const idm_plan *p) { return ws_states_off(p, dims_of(p)); }
 
 void drop_graphs(idm_plan *p) {
     if (p->step_exec) hipGraphExecDestroy(p->step_exec);
@@ -204,7 +250,84 @@ struct Layout {
     std::vector<int32_t> level, level_start;
 };
 
+// Halo tiles of `threads` slots advancing J steps per launch: a lane of at
+// most `threads` vehicles is one tile; a longer one is cut into
+// ceil(n / (threads - J)) tiles of nearly equal owned ranges.
+template <class F>
+void for_each_tile(const std::vector<int32_t> &offsets, int L, int threads, int J, F fn) {
+    const int64_t own_cap = threads - J;
+    for (int l = 0; l < L; ++l) {
+        const int32_t s0 = offsets[l], e0 = offsets[l + 1];
+        const int64_t n = e0 - s0;
+        if (n == 0) continue;
+        if (n <= threads) {
+            fn(s0, e0, s0, e0);
+            continue;
+        }
+        const int64_t nt = (n + own_cap - 1) / own_cap;
+        const int64_t base = n / nt, rem = n % nt;
+        int32_t lo = s0;
+        for (int64_t j = 0; j < nt; ++j) {
+            const int32_t hi = lo + (int32_t)(base + (j < rem ? 1 : 0));
+            fn(s0, e0, lo, hi);
+            lo = hi;
+        }
+    }
+}
+
+int64_t count_tiles(const std::vector<int32_t> &offsets, int L, int threads, int J) {
+    int64_t n = 0;
+    for_each_tile(offsets, L, threads, J, [&](int32_t, int32_t, int32_t, int32_t) { ++n; });
+    return n;
+}
+
+// Slot tables of halo tiles: tiles x threads forward slots (up to J halo
+// vehicles ahead of the owned ones, the first slot flagged as a lane head),
+// then tiles x threads backward slots (the owned vehicles, then up to J halo
+// vehicles behind them, the head flag only on a true lane head).
+idm_status compute_tiles(const std::vector<int32_t> &offsets, int L, const Shape &sh, Layout &out) {
+    const int NT = sh.threads, J = sh.tile;
+    const int64_t nb = count_tiles(offsets, L, NT, J);
+    if (2 * nb * NT >= ((int64_t)1 << 40) || nb >= ((int64_t)1 << 31))
+        return fail(IDM_ERR_LAYOUT, "layout too large");
+    out.n_bundles = nb;
+    out.cap = NT;
+    out.n_bnd = 0;
+    out.gidx.assign((size_t)(2 * nb * NT), -1);
+    out.flags.assign((size_t)(2 * nb * NT), 0);
+    out.bnd_in.assign((size_t)nb, -1);
+    out.bnd_out.assign((size_t)nb, -1);
+    out.level.assign((size_t)nb, 0);
+    out.level_start = {0, (int32_t)nb};
+    int64_t b = 0;
+    for_each_tile(offsets, L, NT, J, [&](int32_t ls, int32_t le, int32_t lo, int32_t hi) {
+        int64_t s = b * NT;
+        const int32_t f0 = std::max<int32_t>(ls, lo - J);
+        for (int32_t i = f0; i < hi; ++i, ++s) {
+            out.gidx[(size_t)s] = i;
+            uint8_t f = SLOT_VALID;
+            if (i == f0) f |= SLOT_HEAD;
+            if (i >= lo) f |= SLOT_OWNED;
+            if (i == le - 1) f |= SLOT_TAIL;
+            out.flags[(size_t)s] = f;
+        }
+        s = (nb + b) * NT;
+        const int32_t b1 = (int32_t)std::min<int64_t>(le, (int64_t)hi + J);
+        for (int32_t i = lo; i < b1; ++i, ++s) {
+            out.gidx[(size_t)s] = i;
+            uint8_t f = SLOT_VALID;
+            if (i == ls) f |= SLOT_HEAD;
+            if (i < hi) f |= SLOT_OWNED;
+            if (i == le - 1) f |= SLOT_TAIL;
+            out.flags[(size_t)s] = f;
+        }
+        ++b;
+    });
+    return IDM_OK;
+}
+
 idm_status compute_layout(const std::vector<int32_t> &offsets, int L, const Shape &sh, Layout &out) {
+    if (sh.tile > 0) return compute_tiles(offsets, L, sh, out);
     const int64_t cap = (int64_t)sh.threads * sh.per_thread;
     struct Item {
         int32_t lo, hi;
@@ -419,6 +542,7 @@ idm_status build_layout(idm_plan *p, const Shape &sh) {
     p->n_bnd = lay.n_bnd;
     p->level_start = lay.level_start;
     p->sh = sh;
+    p->n_tiles = sh.tile > 0 ? p->n_bundles : 0;
     if (p->sh.grid > p->n_bundles) p->sh.grid = p->n_bundles;
     drop_graphs(p);
     return IDM_OK;
@@ -477,6 +601,25 @@ idm_status choose_shape(const idm_plan *p, const idm_tuning *tu, Shape &sh) {
     sh.KB = KB;
     sh.grid = (tu && tu->grid > 0) ? tu->grid : 0;
     sh.stored = tu && tu->store_states == 1;  // 2: checkpoints until the autotuner chooses
+    sh.tile = tu ? tu->tile_steps : 0;
+    if (sh.tile < 0) return fail(IDM_ERR_INVALID_ARG, "tuning: tile_steps < 0");
+    if (sh.tile > 0) {
+        if (!sh.stored)
+            return fail(IDM_ERR_UNSUPPORTED, "halo tiles (tile_steps %d) need store_states = 1",
+                        sh.tile);
+        if (!(tu->threads == 256 || tu->threads == 512 || tu->threads == 1024) ||
+            tu->per_thread != 1)
+            return fail(IDM_ERR_UNSUPPORTED,
+                        "halo tiles need threads of 256, 512 or 1024 and per_thread = 1 in the "
+                        "tuning; got %d x %d",
+                        tu->threads, tu->per_thread);
+        if (sh.tile >= sh.threads || sh.tile % 2 != 0 || sh.tile % K != 0)
+            return fail(IDM_ERR_UNSUPPORTED,
+                        "tile_steps %d must be even, a multiple of K = %d and below threads = %d",
+                        sh.tile, K, sh.threads);
+        if (sh.grid > 0)
+            return fail(IDM_ERR_UNSUPPORTED, "halo tiles run one work-group per tile (grid 0)");
+    }
     return IDM_OK;
 }
 
@@ -541,9 +684,57 @@ int32_t level_args(const idm_plan *p, int32_t lv, SimArgs &a, double *loss_base,
 
 void ext_args(const idm_plan *p, void *ws, SimArgs &a) {
     if (p->n_bnd == 0) return;
-    char *base = (char *)ws + ws_ext_off(p, p->sh.K, p->n_bnd, p->sh.stored);
+    char *base = (char *)ws + ws_ext_off(p, dims_of(p));
     a.ext_state = (float2 *)base;
     a.ext_adj = (float2 *)(base + ext_state_bytes(p, p->n_bnd));
+}
+
+// Launches of a halo-tile plan: blocks of J steps, [j J, min((j + 1) J, S)),
+// at least one (S = 0 writes the initial row).
+int32_t tile_launches(const idm_plan *p) {
+    const int32_t S = p->pb.n_steps, J = p->sh.tile;
+    return S == 0 ? 1 : (S + J - 1) / J;
+}
+
+// The halo-tile forward: every launch advances every tile J steps, reading
+// the states its halo starts from in the rows the previous launch wrote.
+idm_status run_forward_tiled(idm_plan *p, SimArgs a, float *traj_d, float *traj_v, void *ws,
+                             hipStream_t s) {
+    float *st_d = nullptr, *st_v = nullptr;
+    if (ws) {
+        st_d = (float *)((char *)ws + ws_states_off(p));
+        st_v = (float *)((char *)st_d + state_rows_bytes(p));
+    } else if (traj_d && traj_v) {
+        st_d = traj_d;  // no workspace: the caller's rows hold the states
+        st_v = traj_v;
+        traj_d = traj_v = nullptr;
+    } else {
+        return fail(IDM_ERR_WORKSPACE,
+                    "a halo-tile forward reads each launch's start states from the trajectory "
+                    "rows: pass the workspace or both trajectory outputs");
+    }
+    a.traj_d = st_d;
+    a.traj_v = st_v;
+    a.ckpt = nullptr;
+    a.diag = ws ? (uint64_t *)((char *)ws + ws_diag_off(p)) : nullptr;
+    KernelFn fn = forward_tiled_kernel(p->pb.bound, p->sh.threads);
+    if (!fn) return fail(IDM_ERR_UNSUPPORTED, "no halo-tile forward for %d threads", p->sh.threads);
+    const int32_t S = p->pb.n_steps, J = p->sh.tile;
+    for (int32_t j = 0; j < tile_launches(p); ++j) {
+        a.k_lo = j * J;
+        a.k_hi = std::min(S, (j + 1) * J);
+        hipError_t e = launch_sim(fn, p->n_tiles, p->sh.threads, a, s);
+        if (e != hipSuccess) return hip_fail(e, "halo-tile forward launch");
+    }
+    const size_t rows = ((size_t)S + 1) * sizeof(float) * (size_t)p->pb.n_vehicles;
+    for (int i = 0; i < 2; ++i) {
+        float *dst = i ? traj_v : traj_d;
+        const float *src = i ? st_v : st_d;
+        if (!dst || rows == 0) continue;
+        hipError_t e = hipMemcpyAsync(dst, src, rows, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "trajectory copy");
+    }
+    return IDM_OK;
 }
 
 idm_status run_forward(idm_plan *p, const idm_params *prm, const double *p0, const float *v_init,
@@ -552,6 +743,7 @@ idm_status run_forward(idm_plan *p, const idm_params *prm, const double *p0, con
     a.v0 = prm->v0; a.T = prm->T; a.a = prm->a; a.b = prm->b; a.s0 = prm->s0; a.len = prm->length;
     a.p0 = p0;
     a.v_init = v_init;
+    if (p->sh.tile > 0) return run_forward_tiled(p, a, traj_d, traj_v, ws, s);
     a.traj_d = traj_d;
     a.traj_v = traj_v;
     a.ckpt = ws ? (float *)((char *)ws + ws_ckpt_off(p)) : nullptr;
@@ -560,7 +752,7 @@ idm_status run_forward(idm_plan *p, const idm_params *prm, const double *p0, con
     // (no checkpoints) and copies them out for a caller that asked for them
     float *st_d = nullptr, *st_v = nullptr;
     if (p->sh.stored && ws) {
-        st_d = (float *)((char *)ws + ws_states_off(p, p->sh.K, p->n_bnd, true));
+        st_d = (float *)((char *)ws + ws_states_off(p));
         st_v = (float *)((char *)st_d + state_rows_bytes(p));
         a.traj_d = st_d;
         a.traj_v = st_v;
@@ -606,7 +798,7 @@ idm_status run_backward(idm_plan *p, const idm_params *prm, const double *p0, co
                         double *g_p0, double *g_v0, double *loss_out, void *ws, hipStream_t s) {
     if (p->sh.stored) {
         // the states the forward kept in the workspace
-        const float *st_d = (const float *)((char *)ws + ws_states_off(p, p->sh.K, p->n_bnd, true));
+        const float *st_d = (const float *)((char *)ws + ws_states_off(p));
         const float *st_v = (const float *)((const char *)st_d + state_rows_bytes(p));
         return run_backward_stored(p, prm, p0, st_d, st_v, gd, gv, obs, g_prm, g_p0, g_v0,
                                    loss_out, ws, s);
@@ -683,6 +875,38 @@ idm_status run_backward_stored(idm_plan *p, const idm_params *prm, const double 
     a.g_p0 = g_p0;
     a.g_v0 = g_v0;
     double *loss_base = (double *)((char *)ws + ws_loss_off(p));
+    if (p->sh.tile > 0) {
+        // halo tiles: blocks of J steps from the last to the first, the
+        // adjoints carried between launches through two alternating buffers
+        KernelFn fn = backward_tiled_kernel(p->pb.bound, p->sh.threads, gd || gv);
+        if (!fn)
+            return fail(IDM_ERR_UNSUPPORTED, "no halo-tile backward for %d threads", p->sh.threads);
+        char *tb = (char *)ws + ws_tile_off(p, dims_of(p));
+        float *carry[2] = {(float *)tb, (float *)(tb + tile_carry_bytes(p))};
+        a.t_gp0 = (float *)(tb + 2 * tile_carry_bytes(p));
+        a.t_acc = (double *)(tb + 2 * tile_carry_bytes(p) + tile_gp0_bytes(p));
+        const int64_t cap = (int64_t)p->sh.threads;
+        a.slot_gidx = p->d_gidx + (int64_t)p->n_tiles * cap;  // the backward tables
+        a.slot_flags = p->d_flags + (int64_t)p->n_tiles * cap;
+        a.n_bundles = p->n_tiles;
+        a.loss_part = loss_base;
+        const int32_t S = p->pb.n_steps, J = p->sh.tile, nl = tile_launches(p);
+        for (int32_t i = 0; i < nl; ++i) {
+            const int32_t j = nl - 1 - i;
+            a.k_lo = j * J;
+            a.k_hi = std::min(S, (j + 1) * J);
+            a.tc_in = carry[i & 1];
+            a.tc_out = carry[(i + 1) & 1];
+            hipError_t e = launch_sim(fn, p->n_tiles, p->sh.threads, a, s);
+            if (e != hipSuccess) return hip_fail(e, "halo-tile backward launch");
+        }
+        if (loss_out) {
+            hipError_t e = launch_loss_finalize(loss_base, p->n_tiles, obs ? a.inv_count : 0.0,
+                                                loss_out, s);
+            if (e != hipSuccess) return hip_fail(e, "loss finalize launch");
+        }
+        return IDM_OK;
+    }
     KernelFn fn = backward_stored_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, gd || gv);
     if (!fn) return fail(IDM_ERR_UNSUPPORTED, "no stored-state backward kernel for this shape");
     const int32_t nb = level_args(p, 0, a, loss_base);
@@ -995,7 +1219,8 @@ idm_status idm_problem_check(const idm_problem *pb, const idm_tuning *tu, idm_pl
     p.n_bnd = lay.n_bnd;
     p.level_start = lay.level_start;
     if (p.sh.grid > p.n_bundles) p.sh.grid = p.n_bundles;
-    if (workspace_bytes) *workspace_bytes = ws_total(&p, sh.K, p.n_bnd);
+    p.n_tiles = sh.tile > 0 ? p.n_bundles : 0;
+    if (workspace_bytes) *workspace_bytes = ws_total(&p);
     if (info) return idm_plan_get_info(&p, info);
     return IDM_OK;
 }
@@ -1055,7 +1280,7 @@ idm_status idm_plan_destroy(idm_plan *p) {
     return IDM_OK;
 }
 
-size_t idm_workspace_bytes(const idm_plan *p) { return p ? ws_total(p, p->sh.K, p->n_bnd) : 0; }
+size_t idm_workspace_bytes(const idm_plan *p) { return p ? ws_total(p) : 0; }
 
 idm_status idm_plan_get_info(const idm_plan *p, idm_plan_info *o) {
     if (!p || !o) return fail(IDM_ERR_INVALID_ARG, "null argument");
@@ -1072,6 +1297,7 @@ idm_status idm_plan_get_info(const idm_plan *p, idm_plan_info *o) {
     o->n_boundaries = p->n_bnd;
     o->autotune_cached = p->tuned_cached;
     o->store_states = p->sh.stored ? 1 : 0;
+    o->tile_steps = p->sh.tile;
     return IDM_OK;
 }
 
@@ -1140,7 +1366,7 @@ idm_status idm_sim_backward_noalloc(idm_plan *p, const idm_params *prm, const do
     if (!g_prm || !g_p0 || !g_v0) return fail(IDM_ERR_INVALID_ARG, "gradient outputs null");
     r = check_obs(p, obs);
     if (r != IDM_OK) return r;
-    const size_t need = ws_total(p, p->sh.K, p->n_bnd);
+    const size_t need = ws_total(p);
     if (need > IDM_STATIC_SCRATCH_BYTES)
         return fail(IDM_ERR_WORKSPACE,
                     "the problem needs a %zu-byte workspace; the static scratch holds %zu bytes "
@@ -1303,11 +1529,15 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
             }
         }
         if (hit) {
-            const int64_t nb = count_boundaries(p->offsets, p->pb.n_lanes,
-                                                (int64_t)c.threads * c.per_thread);
+            const int64_t nb = c.tile > 0 ? 0
+                                          : count_boundaries(p->offsets, p->pb.n_lanes,
+                                                             (int64_t)c.threads * c.per_thread);
+            const int64_t nt =
+                c.tile > 0 ? count_tiles(p->offsets, p->pb.n_lanes, c.threads, c.tile) : 0;
             // the cached shape is taken when its workspace fits and its layout
             // builds; otherwise the shapes are timed again
-            if (ws_total(p, c.K, nb, c.stored) <= ws_bytes && build_layout(p, c) == IDM_OK) {
+            if (ws_total(p, dims(c.K, nb, c.stored, nt)) <= ws_bytes &&
+                build_layout(p, c) == IDM_OK) {
                 p->tuned_cached = 1;
                 return IDM_OK;
             }
@@ -1329,7 +1559,7 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
             // or 2: the autotuner weighs both backwards): whole lanes, the
             // plan's K (it only groups the FP32 gradient sums), no register
             // block to choose
-            if (p->store_pref >= 1 && nbnd == 0 && ws_total(p, p->sh.K, 0, true) <= ws_bytes &&
+            if (p->store_pref >= 1 && nbnd == 0 && ws_total(p, dims(p->sh.K, 0, true)) <= ws_bytes &&
                 backward_stored_kernel(p->pb.bound, rr, t, dense)) {
                 Shape sh;
                 sh.threads = t;
@@ -1346,7 +1576,7 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
                 for (int twice = 0; twice < 2; ++twice) {
                     const int K = k_fixed ? p->pb.ckpt_every : (twice ? 2 * KB : KB);
                     if (k_fixed && twice) break;
-                    if (K % KB != 0 || ws_total(p, K, nbnd, false) > ws_bytes) continue;
+                    if (K % KB != 0 || ws_total(p, dims(K, nbnd, false)) > ws_bytes) continue;
                     KernelFn fb = backward_kernel(p->pb.bound, rr, t, KB, K, dense, nbnd > 0);
                     if (twice && fb == backward_kernel(p->pb.bound, rr, t, KB, KB, dense, nbnd > 0))
                         continue;
@@ -1365,6 +1595,30 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
                 }
             }
         }
+    // halo tiles (kept states, one vehicle per thread) where a lane is longer
+    // than the work-group: J steps per launch, J a multiple of the plan's K
+    if (p->store_pref >= 1) {
+        const int tile_cands[][2] = {{256, 64}, {256, 128}, {512, 64}, {512, 128},
+                                     {512, 256}, {1024, 128}, {1024, 256}};
+        for (const auto &tc : tile_cands) {
+            const int t = tc[0], J = tc[1];
+            if (p->max_lane <= t || J % p->sh.K != 0) continue;
+            const int64_t nt = count_tiles(p->offsets, p->pb.n_lanes, t, J);
+            if (ws_total(p, dims(p->sh.K, 0, true, nt)) > ws_bytes) continue;
+            if (!forward_tiled_kernel(p->pb.bound, t) ||
+                !backward_tiled_kernel(p->pb.bound, t, dense))
+                continue;
+            Shape sh;
+            sh.threads = t;
+            sh.per_thread = 1;
+            sh.K = p->sh.K;
+            sh.KB = default_kb(1, sh.K) > 0 ? default_kb(1, sh.K) : kbs_for(1)[0];
+            sh.grid = 0;
+            sh.stored = true;
+            sh.tile = J;
+            cands.push_back(sh);
+        }
+    }
     if (cands.empty()) cands.swap(spilling);
     if (cands.empty()) return fail(IDM_ERR_WORKSPACE, "no launch shape fits the workspace");
     const Shape orig = p->sh;
@@ -1376,6 +1630,7 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
     for (Shape sh : cands) {
         for (int persistent = 0; persistent < 2; ++persistent) {
             Shape s2 = sh;
+            if (persistent && sh.tile > 0) continue;  // one work-group per tile
             if (persistent) {
                 KernelFn fb =
                     sh.stored

@@ -13,7 +13,9 @@ namespace idmx {
 // Slot flags: a bundle is threads*per_thread consecutive slots holding whole
 // lanes (head -> tail) followed by padding; a lane longer than a bundle is cut
 // into pieces, a piece after the first opening its bundle without a head flag.
-enum : uint8_t { SLOT_HEAD = 1u, SLOT_TAIL = 2u, SLOT_VALID = 4u };
+// A halo tile (one lane's vehicles, see the tile kernels) also marks the
+// vehicles whose results it owns.
+enum : uint8_t { SLOT_HEAD = 1u, SLOT_TAIL = 2u, SLOT_VALID = 4u, SLOT_OWNED = 8u };
 
 // Everything a simulation kernel reads, passed by value as the kernel argument.
 struct SimArgs {
@@ -63,6 +65,19 @@ struct SimArgs {
     const int32_t *bnd_in, *bnd_out;  // [n_bundles], -1 = none
     float2 *ext_state;                // [n_boundaries][S+1]
     float2 *ext_adj;                  // [n_boundaries][S]
+
+    // halo tiles: the launch runs steps [k_lo, k_hi) (the forward upwards, the
+    // backward downwards).  The backward carries each vehicle's adjoint of
+    // (d, v) between launches through tc_in / tc_out ([2][N], two buffers
+    // used alternately, since a tile reads its halo's entries while their
+    // owners write the next ones), and the owned vehicles' running sums
+    // through t_gp0 ([N], FP32) and t_acc ([6][N]: the five FP64 parameter
+    // sums, then the FP64 loss).
+    int32_t k_lo, k_hi;
+    const float *tc_in;
+    float *tc_out;
+    float *t_gp0;
+    double *t_acc;
 };
 
 struct AdamArgs {
@@ -129,6 +144,10 @@ KernelFn backward_kernel(int mode, int per_thread, int threads, int KB, int K, b
 // Backward that reads every step's states from the forward's stored
 // trajectory (whole lanes only).
 KernelFn backward_stored_kernel(int mode, int per_thread, int threads, bool dense);
+// Halo-tile forward and backward (one vehicle per thread; nullptr when the
+// work-group size has no instantiation).
+KernelFn forward_tiled_kernel(int mode, int threads);
+KernelFn backward_tiled_kernel(int mode, int threads, bool dense);
 
 // Launch helpers (return the HIP error of the launch).
 hipError_t launch_sim(KernelFn fn, int grid, int threads, const SimArgs &a, hipStream_t s);

@@ -423,6 +423,109 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     forward_body<MODE, 1, NT, true, false>(A, lead_buf);
 }
 
+// Halo tiles: a lane too long to fill the chip with one work-group per lane
+// is cut into tiles of threads - J owned vehicles, each run by its own
+// work-group, and the steps into blocks of J run as successive launches.  A
+// tile's forward slots are up to J vehicles ahead of the owned ones (the
+// halo), then the owned vehicles, then padding; the first slot is flagged as
+// a lane head.  Information travels one vehicle per step from leader to
+// follower, so a halo vehicle without its true leader drifts from the true
+// state from the front one vehicle per step, and after J steps the drift has
+// not reached the owned vehicles.  The states at the block's first step are
+// read from the trajectory rows, which the owners wrote in the previous
+// launch; only owned vehicles write rows and count anomalies.  The per-vehicle
+// arithmetic is the whole-lane forward's (accel_gd, euler), so the owned
+// states equal it bit for bit.
+template <int MODE, int NT>
+__global__ __launch_bounds__(NT) void k_forward_tiled(SimArgs A) {
+    __shared__ float2 sbuf[2][NT];
+    __shared__ uint64_t dred[2][NT / 64];
+    const int t = threadIdx.x;
+    const int tl = lead_thread(t);
+    const int64_t N = A.n;
+    const int S = A.n_steps;
+    const int k_lo = A.k_lo, k_hi = A.k_hi;
+    const uint32_t NB = (uint32_t)(N * 4);
+    for (int bidx = blockIdx.x; bidx < A.n_bundles; bidx += gridDim.x) {
+        const int64_t slot = (int64_t)bidx * NT + t;
+        Veh q[1];
+        load_vehicles<1>(A, slot, q);
+        const int32_t g = q[0].g;
+        const bool own = g >= 0 && (A.slot_flags[slot] & SLOT_OWNED) != 0;
+        float d = 0.0f, v = 0.0f;
+        if (g >= 0) {
+            if (k_lo == 0) {
+                v = A.v_init[g];
+            } else {
+                d = A.traj_d[(int64_t)k_lo * N + g];
+                v = A.traj_v[(int64_t)k_lo * N + g];
+            }
+        }
+        if (k_lo == 0 && own) {
+            A.traj_d[g] = 0.0f;
+            A.traj_v[g] = v;
+        }
+        sbuf[0][t] = make_float2(d, v);
+        lds_barrier();
+        // evaluations above the gap floor (owned vehicles only; see forward_body)
+        uint32_t n_ok = 0;
+        const float thr = own ? A.gap_floor : INFINITY;
+        // a slot that is not owned stores at the row size: outside the row
+        const int32_t voff = (int32_t)(own ? (uint32_t)g * 4u : NB);
+        const char *trow_d = reinterpret_cast<const char *>(A.traj_d) + (int64_t)k_lo * NB;
+        const char *trow_v = reinterpret_cast<const char *>(A.traj_v) + (int64_t)k_lo * NB;
+        auto step = [&](auto parity) {
+            constexpr int P = decltype(parity)::value;
+            const float2 L = sbuf[P][tl];
+            const float gap = q[0].g0 + (L.x - d);
+            n_ok += (gap > thr) ? 1u : 0u;
+            const float acc = accel_gd<MODE>(q[0], v, gap, v - L.y, A.inv_dt, A.a_min, A.gap_floor);
+            euler<MODE>(d, v, acc, A.dt);
+            sbuf[P ^ 1][t] = make_float2(d, v);
+            trow_d += NB;
+            trow_v += NB;
+            const __amdgpu_buffer_rsrc_t rd =
+                __builtin_amdgcn_make_buffer_rsrc((void *)trow_d, (short)0, (int)NB, 0x00020000);
+            const __amdgpu_buffer_rsrc_t rv =
+                __builtin_amdgcn_make_buffer_rsrc((void *)trow_v, (short)0, (int)NB, 0x00020000);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(d), rd, voff, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rv, voff, 0, 0);
+            lds_barrier();
+        };
+        int k = k_lo;
+        for (; k + 1 < k_hi; k += 2) {
+            step(std::integral_constant<int, 0>{});
+            step(std::integral_constant<int, 1>{});
+        }
+        if (k < k_hi) step(std::integral_constant<int, 0>{});
+        if (A.diag) {
+            // floor counts add up over the launches; the non-finite count is
+            // taken from the final state (see forward_body)
+            uint64_t n_bad = (uint64_t)__builtin_popcountll(
+                __ballot(own && !(isfinite(d) && isfinite(v))));
+            uint64_t n_floor = (uint64_t)((own ? (uint32_t)(k_hi - k_lo) : 0u) - n_ok);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) n_floor += __shfl_down(n_floor, off, 64);
+            if ((t & 63) == 0) {
+                dred[0][t >> 6] = n_floor;
+                dred[1][t >> 6] = n_bad;
+            }
+            lds_barrier();
+            if (t == 0) {
+                uint64_t s0 = 0, s1 = 0;
+                for (int w = 0; w < NT / 64; ++w) {
+                    s0 += dred[0][w];
+                    s1 += dred[1][w];
+                }
+                const uint64_t prev = k_lo == 0 ? 0 : A.diag[2 * (int64_t)bidx];
+                A.diag[2 * (int64_t)bidx] = prev + s0;
+                A.diag[2 * (int64_t)bidx + 1] = k_hi == S ? s1 : 0;
+            }
+        }
+        __syncthreads();  // sbuf and dred are free before the next tile
+    }
+}
+
 // ---------------------------------------------------------------- backward
 
 // Raw upstream inputs of one (vehicle, step): dense dL/dd, dense dL/dv and the
@@ -992,8 +1095,18 @@ __device__ __forceinline__ void fetch_states(const SimArgs &A, int64_t row, bool
     lead.v = load_rec(A.traj_v, row, NB, offl);
 }
 
-template <int MODE, int R, int NT, bool DN>
+//
+// TL: a halo-tile launch (one vehicle per thread): it runs steps [k_lo, k_hi)
+// of a tile whose slots are the owned vehicles followed by up to k_hi - k_lo
+// halo followers.  The adjoint flows from follower to leader one vehicle per
+// step; the tile's last vehicle lacks its follower's contribution, so the
+// halo's adjoints go wrong from the back one vehicle per step, and after at
+// most k_hi - k_lo steps the owned ones are still exact.  Every vehicle starts
+// from the adjoint its owner carried out of the previous launch; only owned
+// vehicles write results.  The arithmetic is the whole-lane kernel's.
+template <int MODE, int R, int NT, bool DN, bool TL = false>
 __global__ __launch_bounds__(NT) void k_backward_stored(SimArgs A) {
+    static_assert(!TL || R == 1, "tiles hold one vehicle per thread");
     // one exchange buffer per ring slot: consecutive steps use different ones,
     // at addresses fixed at compile time
     __shared__ float2 cbuf[3][NT];
@@ -1007,9 +1120,15 @@ __global__ __launch_bounds__(NT) void k_backward_stored(SimArgs A) {
     const int K = A.K;
     const float dt = A.dt;
     const float two_inv = (float)A.two_inv_count;
+    // the launch's steps: all of them, or one block of a tile launch
+    const int k_hi = TL ? A.k_hi : S;
+    const int k_lo = TL ? A.k_lo : 0;
+    const bool top = !TL || k_hi == S;
     for (int bidx = blockIdx.x; bidx < A.n_bundles; bidx += gridDim.x) {
         Veh q[R];
         load_vehicles<R>(A, (int64_t)bidx * (NT * R) + t * R, q);
+        bool own = true;
+        if constexpr (TL) own = (A.slot_flags[(int64_t)bidx * NT + t] & SLOT_OWNED) != 0;
         // byte offsets in a row: own vehicles and the first vehicle's leader
         // (a lane head, whose leader terms are exactly zero, reads its own
         // state).  A padding slot's offset lies beyond every row, so its
@@ -1039,6 +1158,22 @@ __global__ __launch_bounds__(NT) void k_backward_stored(SimArgs A) {
                 gacc[j][r] = 0.0;
             }
         }
+        if constexpr (TL) {
+            // below the top block: the adjoints carried out of the previous
+            // launch (a halo vehicle's from its owner), and the owned
+            // vehicles' running sums
+            const int32_t g = q[0].g;
+            if (!top && g >= 0) {
+                ld[0] = A.tc_in[g];
+                lv[0] = A.tc_in[N + g];
+                if (own) {
+                    gp0[0] = A.t_gp0[g];
+#pragma unroll
+                    for (int j = 0; j < 5; ++j) gacc[j][0] = A.t_acc[(int64_t)j * N + g];
+                    loss = A.t_acc[5 * N + g];
+                }
+            }
+        }
         // Three-slot rings of upstream inputs and states, read two steps
         // ahead: the step on step k reads slot `us` and refills slot `fs`,
         // the one the previous step read, with step k - 2 (a slot is never
@@ -1048,19 +1183,19 @@ __global__ __launch_bounds__(NT) void k_backward_stored(SimArgs A) {
         bool obs_up[3];
         StRow st[3][R], lt[3];
         UpCursor cur_k;
-        cursor_init(A, S, cur_k);
-        fetch_up_at<R, DN>(A, cur_k, off, true, seed);
+        cursor_init(A, k_hi, cur_k);
+        if (top) fetch_up_at<R, DN>(A, cur_k, off, true, seed);
         const bool obs_S = cursor_obs(cur_k);
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             cursor_dec(A, cur_k);
-            fetch_up_at<R, DN>(A, cur_k, off, S > i, up[i]);
-            obs_up[i] = S > i && cursor_obs(cur_k);
-            fetch_states<R>(A, (int64_t)(S - 1 - i) * NB, S > i, off, offl, st[i], lt[i]);
+            fetch_up_at<R, DN>(A, cur_k, off, k_hi > i, up[i]);
+            obs_up[i] = k_hi > i && cursor_obs(cur_k);
+            fetch_states<R>(A, (int64_t)(k_hi - 1 - i) * NB, k_hi > i, off, offl, st[i], lt[i]);
         }
         // seed: upstream gradient at step S (at S = 0 the state is the
         // initial one, displacement 0)
-        {
+        if (top) {
             StRow sS[R], lS;
             fetch_states<R>(A, (int64_t)S * NB, S > 0, off, offl, sS, lS);
 #pragma unroll
@@ -1075,7 +1210,7 @@ __global__ __launch_bounds__(NT) void k_backward_stored(SimArgs A) {
         }
         // first step of the current K-step block (its statistics are flushed
         // into FP64 after that step)
-        int kflush = S > 0 ? ((S - 1) / K) * K : 0;
+        int kflush = k_hi > 0 ? ((k_hi - 1) / K) * K : 0;
         auto step = [&](const int k, auto use_slot, auto fill_slot) {
             constexpr int us = decltype(use_slot)::value;
             constexpr int fs = decltype(fill_slot)::value;
@@ -1163,24 +1298,43 @@ __global__ __launch_bounds__(NT) void k_backward_stored(SimArgs A) {
         using C1 = std::integral_constant<int, 1>;
         using C2 = std::integral_constant<int, 2>;
         // slot 0 holds step k, slot 1 step k - 1 at the top of each iteration
-        int k = S - 1;
-        for (; k >= 2; k -= 3) {
+        int k = k_hi - 1;
+        for (; k >= k_lo + 2; k -= 3) {
             step(k, C0{}, C2{});
             step(k - 1, C1{}, C0{});
             step(k - 2, C2{}, C1{});
         }
-        if (k == 1) {
-            step(1, C0{}, C2{});
-            step(0, C1{}, C0{});
-        } else if (k == 0) {
-            step(0, C0{}, C2{});
+        if (k == k_lo + 1) {
+            step(k_lo + 1, C0{}, C2{});
+            step(k_lo, C1{}, C0{});
+        } else if (k == k_lo) {
+            step(k_lo, C0{}, C2{});
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) loss += (double)lossf[r];  // S = 0: the seed's residual
+        if constexpr (TL) {
+            if (k_lo > 0) {
+                // carried into the next launch: every owned vehicle's
+                // adjoint and running sums (a tile's k_lo is a multiple of K,
+                // so its FP32 statistics were just flushed)
+                const int32_t g = q[0].g;
+                if (g >= 0 && own) {
+                    A.tc_out[g] = ld[0];
+                    A.tc_out[N + g] = lv[0];
+                    A.t_gp0[g] = gp0[0];
+#pragma unroll
+                    for (int j = 0; j < 5; ++j) A.t_acc[(int64_t)j * N + g] = gacc[j][0];
+                    A.t_acc[5 * N + g] = loss;
+                }
+                __syncthreads();  // every cbuf read is done before the next tile writes it
+                continue;
+            }
+            if (!own) loss = 0.0;
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             int32_t g = q[r].g;
-            if (g >= 0) {
+            if (g >= 0 && own) {
 #pragma unroll
                 for (int p = 0; p < 5; ++p) A.g_prm[(int64_t)p * N + g] = gacc[p][r];
                 A.g_p0[g] = (double)gp0[r];
@@ -1403,10 +1557,10 @@ __global__ __launch_bounds__(256) void k_fit_init_u(AdamArgs A, const float *u_r
 
 // ---------------------------------------------------------------- dispatch
 //
-// The file is compiled ten times (IDM_PART = 0..9) so the backward
+// The file is compiled eleven times (IDM_PART = 0..10) so the backward
 // instantiations of the two bound modes, with and without dense upstream
-// gradients, with and without lane pieces, and the backward from stored
-// states (part 9) build in parallel.
+// gradients, with and without lane pieces, the backward from stored states
+// (part 9) and the halo-tile kernels (part 10) build in parallel.
 #ifndef IDM_PART
 #define IDM_PART 0
 #endif
@@ -1492,6 +1646,26 @@ KernelFn backward_kernel_cl_d_ch(int mode, int per_thread, int threads, int KB, 
 KernelFn backward_stored_kernel(int mode, int per_thread, int threads, bool dense) {
     IDM_BWS_R(0, 1) IDM_BWS_R(0, 2) IDM_BWS_R(0, 4)
     IDM_BWS_R(1, 1) IDM_BWS_R(1, 2) IDM_BWS_R(1, 4)
+    return nullptr;
+}
+#endif
+
+// part 10: the halo-tile kernels
+#define IDM_TILE_CASE(M, NT)                                                   \
+    if (mode == M && threads == NT) return (KernelFn)&k_forward_tiled<M, NT>;
+#define IDM_TILE_BWD(M, NT)                                                    \
+    if (mode == M && threads == NT)                                             \
+        return dense ? (KernelFn)&k_backward_stored<M, 1, NT, true, true>        \
+                     : (KernelFn)&k_backward_stored<M, 1, NT, false, true>;
+#if IDM_PART == 10
+KernelFn forward_tiled_kernel(int mode, int threads) {
+    IDM_TILE_CASE(0, 256) IDM_TILE_CASE(0, 512) IDM_TILE_CASE(0, 1024)
+    IDM_TILE_CASE(1, 256) IDM_TILE_CASE(1, 512) IDM_TILE_CASE(1, 1024)
+    return nullptr;
+}
+KernelFn backward_tiled_kernel(int mode, int threads, bool dense) {
+    IDM_TILE_BWD(0, 256) IDM_TILE_BWD(0, 512) IDM_TILE_BWD(0, 1024)
+    IDM_TILE_BWD(1, 256) IDM_TILE_BWD(1, 512) IDM_TILE_BWD(1, 1024)
     return nullptr;
 }
 #endif

@@ -72,7 +72,7 @@ class Plan:
     def __init__(self, lane_offsets, n_steps: int, dt: float = 0.1, a_min: float = -10.0,
                  gap_floor: float = 1e-3, bound: int = BOUND_SOFTPLUS, ckpt_every: int = 0,
                  delta: float = 4.0, threads: int = 0, per_thread: int = 0, grid: int = 0,
-                 tuning_k: int = 0, block: int = 0, store_states=False):
+                 tuning_k: int = 0, block: int = 0, store_states=False, tile_steps: int = 0):
         L = _lib.load()
         self._L = L
         self.offsets = np.ascontiguousarray(np.asarray(lane_offsets, dtype=np.int32))
@@ -83,9 +83,12 @@ class Plan:
         pb = IdmProblem(self.n, self.n_lanes, self.n_steps, int(ckpt_every), float(dt), float(delta),
                         float(a_min), float(gap_floor), self.bound,
                         self.offsets.ctypes.data_as(ctypes.c_void_p))
-        # store_states: False / True, or "auto" (the autotuner weighs both backwards)
+        # store_states: False / True, or "auto" (the autotuner weighs both
+        # backwards, and halo tiles); tile_steps > 0: halo tiles advancing that
+        # many steps per launch (with store_states=True and explicit threads)
         st = 2 if store_states == "auto" else int(bool(store_states))
-        tu = IdmTuning(int(threads), int(per_thread), int(tuning_k), int(grid), int(block), st)
+        tu = IdmTuning(int(threads), int(per_thread), int(tuning_k), int(grid), int(block), st,
+                       int(tile_steps))
         h = ctypes.c_void_p()
         check(L.idm_plan_create(ctypes.byref(pb), ctypes.byref(tu), ctypes.byref(h)), "idm_plan_create")
         self.handle = h

@@ -132,6 +132,110 @@ def test_store_states_workspace_and_limits(L):
     assert st == 0 and info.store_states == 0
 
 
+def _tile_layout(L, offsets, threads, J, K=16, S=100):
+    """Both slot tables of a halo-tile plan: [2][tiles][threads] (forward, then
+    backward)."""
+    from paper_2412_16750_amd._lib import IdmTuning
+    tuning = (threads, 1, K, 0, 0, 1, J)
+    st, info, ws = _check(L, offsets, tuning=tuning, S=S, K=K)
+    assert st == 0, L.idm_last_error()
+    assert info.tile_steps == J and info.store_states == 1 and info.n_levels == 1
+    pb, off = _problem(offsets, S=S, K=K)
+    tu = IdmTuning(*tuning)
+    n = 2 * info.n_slots
+    gidx = np.empty(n, dtype=np.int32)
+    flags = np.empty(n, dtype=np.uint8)
+    args = (ctypes.byref(pb), ctypes.byref(tu), gidx.ctypes.data_as(ctypes.c_void_p),
+            flags.ctypes.data_as(ctypes.c_void_p))
+    assert L.idm_problem_layout(*args, n - 1) == -1
+    assert L.idm_problem_layout(*args, n) == 0
+    nt = info.n_bundles
+    return info, ws, gidx.reshape(2, nt, threads), flags.reshape(2, nt, threads)
+
+
+@pytest.mark.parametrize("threads, J, K", [(256, 64, 16), (512, 128, 32), (256, 32, 16),
+                                           (1024, 256, 32), (512, 64, 64)])
+def test_halo_tile_layout(L, threads, J, K):
+    """Halo tiles (Sec. III-B: a step moves information one vehicle): every
+    vehicle is owned by exactly one tile; a tile owns at most threads - J
+    consecutive vehicles of one lane; its forward slots add up to J vehicles
+    ahead (fewer only where the lane starts), the first slot flagged as a
+    lane head; its backward slots are the owned vehicles and up to J behind
+    (fewer only where the lane ends), flagged as a head only on a true lane
+    head; a lane that fits the work-group is one tile; the workspace adds the
+    carried adjoints and sums (68 B per vehicle) to the kept states."""
+    import scenarios
+    sizes = scenarios.lognormal_lane_sizes(300, np.log(threads) + 0.3, 1.0, 1, 6 * threads, 41)
+    sizes[[2, 9, 17, 30]] = [threads, threads + 1, 5 * threads, threads - J]
+    sizes[::37] = 0
+    off = scenarios.offsets_from_sizes(sizes)
+    S = 100
+    info, ws, gidx, flags = _tile_layout(L, off, threads, J, K=K, S=S)
+    N = int(off[-1])
+    lane_of = np.repeat(np.arange(len(sizes)), sizes)
+    owned_all = []
+    tiles_of_lane = np.zeros(len(sizes), dtype=np.int64)
+    for b in range(info.n_bundles):
+        gf, ff = gidx[0, b], flags[0, b]
+        gb, fb = gidx[1, b], flags[1, b]
+        kf, kb = int(np.sum(gf >= 0)), int(np.sum(gb >= 0))
+        assert np.all(gf[kf:] == -1) and np.all(ff[kf:] == 0)
+        assert np.all(gb[kb:] == -1) and np.all(fb[kb:] == 0)
+        seg_f, seg_b = gf[:kf], gb[:kb]
+        lane = lane_of[seg_f[0]]
+        tiles_of_lane[lane] += 1
+        ls, le = off[lane], off[lane + 1]
+        assert np.array_equal(seg_f, np.arange(seg_f[0], seg_f[0] + kf))
+        assert np.array_equal(seg_b, np.arange(seg_b[0], seg_b[0] + kb))
+        own_f = seg_f[(ff[:kf] & 8) != 0]
+        own_b = seg_b[(fb[:kb] & 8) != 0]
+        assert np.array_equal(own_f, own_b) and len(own_f) >= 1
+        lo, hi = int(own_f[0]), int(own_f[-1]) + 1
+        assert np.array_equal(own_f, np.arange(lo, hi))
+        assert ls <= lo and hi <= le
+        if le - ls > threads:
+            assert hi - lo <= threads - J
+        else:
+            assert (lo, hi) == (ls, le)
+        # forward: halo ahead, then owned; head flag on the first slot only
+        assert seg_f[0] == max(ls, lo - J) and seg_f[-1] == hi - 1
+        assert (ff[0] & 1) and not np.any(ff[1:kf] & 1)
+        # backward: owned, then the halo behind; head flag only on a lane head
+        assert seg_b[0] == lo and seg_b[-1] == min(le, hi + J) - 1
+        heads = seg_b[(fb[:kb] & 1) != 0]
+        assert np.array_equal(heads, [ls] if lo == ls else [])
+        owned_all.append(own_f)
+    owned_all = np.concatenate(owned_all)
+    assert np.array_equal(np.sort(owned_all), np.arange(N))
+    assert len(owned_all) == N
+    align = lambda x: (x + 255) // 256 * 256
+    nt = info.n_bundles
+    expect = (align(8 * nt) + align(16 * nt) + align(8 * 7 * N) + 2 * align((S + 1) * 4 * N)
+              + 2 * align(8 * N) + align(4 * N) + align(48 * N))
+    assert ws == expect
+
+
+def test_halo_tile_tuning_limits(L):
+    """Halo tiles need kept states, one vehicle per thread, explicit threads of
+    256, 512 or 1024, an even J that is a multiple of K and below the
+    work-group, and one work-group per tile."""
+    off = [0, 3000, 3500]
+    ok = (512, 1, 32, 0, 0, 1, 64)
+    assert _check(L, off, tuning=ok, K=32)[0] == 0
+    for bad in [(512, 1, 32, 0, 0, 0, 64),     # checkpoints
+                (512, 1, 32, 0, 0, 2, 64),     # autotuner's choice pending
+                (512, 2, 32, 0, 0, 1, 64),     # two vehicles per thread
+                (0, 0, 32, 0, 0, 1, 64),       # no explicit shape
+                (128, 1, 32, 0, 0, 1, 64),     # no 128-thread tile kernels
+                (512, 1, 32, 0, 0, 1, 512),    # J >= threads
+                (512, 1, 32, 0, 0, 1, 48),     # not a multiple of K
+                (512, 1, 8, 0, 0, 1, 36),      # not a multiple of K = 8 (the tuning K)
+                (512, 1, 32, 64, 0, 1, 64)]:   # persistent grid
+        st = _check(L, off, tuning=bad, K=32)[0]
+        assert st == -3, (bad, st)
+    assert _check(L, off, tuning=(512, 1, 32, 0, 0, 1, -64), K=32)[0] == -1
+
+
 def test_backward_entry_points_reject_null_arguments(L):
     """Argument checks that run before any device work: a null plan, and
     (through a null plan) the stored-state backward's required trajectories."""
