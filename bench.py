@@ -374,9 +374,10 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
     del data
     # the fitting problem, hidden parameters = the scenario's draw.  The fit's
     # plan leaves the backward to the autotuner (store_states "auto"), given
-    # room for every step's states (0.4 GB here): a fit step is latency-bound
-    # (100 lanes, one work-group each), and reading the states instead of
-    # recomputing them removes a third of each backward step
+    # room for every step's states (0.4 GB here) and for halo tiles: a fit
+    # step is latency-bound (100 lanes, one work-group each), reading the
+    # states instead of recomputing them removes a third of each backward
+    # step, and tiles spread the lanes over more compute units
     sc = scenarios.fit()
     plan = sim.Plan.for_scenario(sc, store_states="auto")
     prm = sim.params_tensor(sc.params, dev)
@@ -389,7 +390,9 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
     noise = torch.from_numpy(scenarios.noise((n_obs, sc.n), 4).astype(np.float32)).to(dev)
     obs = sim.Obs(ws.observe(plan, hidden, p0, noise, 10, 10, n_obs), 10, 10)
     cold = sim.params_tensor(scenarios.cold_params(sc), dev)
-    room = sim.Plan.for_scenario(sc, store_states=True).workspace_bytes
+    room = max(sim.Plan.for_scenario(sc, store_states=True).workspace_bytes,
+               sim.Plan.for_scenario(sc, store_states=True, threads=256, per_thread=1,
+                                     tile_steps=64).workspace_bytes)
     tb = sim.StepBuffers(plan, cold, length, p0, v, obs=obs, workspace_bytes=room)
     t0 = time.perf_counter()
     tuned = sim.idm_plan_autotune(tb, reps=3)
@@ -400,10 +403,12 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
     Uh = torch.from_numpy(scenarios.normalized_params(sc.params)).to(dev)
     heldout_mse = ws.evaluate(net, ws.Dataset(X, Uh))
     out = {"workload": "100 lanes x 1000 vehicles, 500 steps, observed every 10th step, "
-                       "N(0, 0.5 m) noise; Adam lr 1e-2 on normalised parameters; launch shape "
-                       "and backward (checkpoints or kept states) chosen by the autotuner",
+                       "N(0, 0.5 m) noise; Adam lr 1e-2 on normalised parameters; launch shape, "
+                       "backward (checkpoints or kept states) and halo tiles chosen by the "
+                       "autotuner",
            "plan": {**{k: tuned[k] for k in ("threads", "per_thread", "ckpt_every", "block",
-                                             "grid", "store_states")},
+                                             "grid", "store_states", "tile_steps",
+                                             "n_bundles")},
                     "autotune_seconds": round(tune_s, 3)},
            "mlp": {"pairs": n_pairs, "batch": 4096, "epochs": MLP_EPOCHS,
                    "lr": "cosine %.0e -> %.0e" % (MLP_LR, MLP_LR_FINAL), "steps": rep["steps"],
@@ -434,23 +439,29 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
     for i, k in enumerate(scenarios.PARAM_NAMES):
         mask = ~heads if k in ("T", "b", "s0") else np.ones(sc.n, bool)
         perr[k] = float(np.median(rel[i, mask]))
-    # the same 200 iterations on a plan with checkpoints every 32 steps
-    plan_ck = sim.Plan.for_scenario(sc)
-    fck = Fitter(plan_ck, length, p0, v, obs, lr0=1e-2)
-    fck.init(cold)
-    fck.run(5)
-    fck.init(cold)
-    torch.cuda.synchronize()
-    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e2.record()
-    fck.run(200)
-    e3.record()
-    torch.cuda.synchronize()
-    same = bool(torch.equal(fck.params, f.params))
-    del fck, plan_ck
+    # the same 200 iterations on whole-lane plans: checkpoints every 32 steps,
+    # and every step's states kept
+    alt = {}
+    for tag, kw in (("checkpointed", {}), ("stored_whole_lanes", {"store_states": True})):
+        plan_alt = sim.Plan.for_scenario(sc, **kw)
+        fa = Fitter(plan_alt, length, p0, v, obs, lr0=1e-2)
+        fa.init(cold)
+        fa.run(5)
+        fa.init(cold)
+        torch.cuda.synchronize()
+        e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e2.record()
+        fa.run(200)
+        e3.record()
+        torch.cuda.synchronize()
+        alt[tag] = (e2.elapsed_time(e3) / 200, bool(torch.equal(fa.params, f.params)))
+        del fa, plan_alt
     out["cold_200"] = {"ms_per_iteration": e0.elapsed_time(e1) / 200,
-                       "ms_per_iteration_checkpointed": e2.elapsed_time(e3) / 200,
-                       "checkpointed_params_bitwise_equal": same, "rmse_m": rmse200,
+                       "ms_per_iteration_checkpointed": alt["checkpointed"][0],
+                       "checkpointed_params_bitwise_equal": alt["checkpointed"][1],
+                       "ms_per_iteration_stored_whole_lanes": alt["stored_whole_lanes"][0],
+                       "stored_whole_lanes_params_bitwise_equal": alt["stored_whole_lanes"][1],
+                       "rmse_m": rmse200,
                        "median_rel_param_error": perr,
                        "loss_first_last": [float(f.losses()[0]), float(f.losses()[-1])],
                        "diagnostics_last_iteration": diagnostics(plan, f.workspace)}

@@ -88,7 +88,7 @@ typedef struct {
  * workspace.  Results do not depend on the cut (the same arithmetic in the
  * same order).  The default is 1024 threads x 1 for lanes above 1024. */
 typedef struct {
-    int32_t threads;    /* 64, 128, 256, 512 or 1024 */
+    int32_t threads;    /* 64, 128, 256, 512 or 1024 (768 with halo tiles) */
     int32_t per_thread; /* vehicles per thread: 1, 2 or 4 */
     int32_t ckpt_every; /* K, overrides the problem's K when > 0 */
     int32_t grid;       /* >0: persistent grid of that many work-groups walking the bundle
@@ -110,19 +110,21 @@ typedef struct {
                            backwards (the kept states only where the workspace it is given
                            holds them) and keep the faster */
     int32_t tile_steps;   /* J > 0: halo tiles (needs store_states 1, one vehicle per
-                           thread and explicit threads of 256, 512 or 1024; J even, a
-                           multiple of K and below threads).  Every lane longer than a
-                           work-group is cut into tiles of at most threads - J owned
-                           vehicles, one work-group each (a lane that fits one work-group
-                           is one tile), and the steps into blocks of J run as successive
-                           launches: a tile also simulates the J vehicles ahead of its own
-                           in the forward and the J behind them in the backward, so that
-                           information, which moves one vehicle per step, cannot reach
-                           its owned vehicles from outside within a launch (Sec. III-B's
-                           synchronous update).  Owned results equal the whole-lane
-                           kernels' bit for bit.  For few long lanes, whose work-groups
-                           leave most compute units idle.  With store_states 2 the
-                           autotuner also times tile shapes; 0: whole lanes */
+                           thread and explicit threads of 256, 512, 768 (tiles only) or
+                           1024; J even, a
+                           multiple of K and below threads).  A lane longer than
+                           threads - J vehicles is cut into ceil(n / (threads - J)) tiles
+                           of nearly equal owned parts, one work-group each (a shorter
+                           lane is one tile), and the steps into blocks of J run as
+                           successive launches: a tile also simulates the J vehicles
+                           ahead of its own in the forward and the J behind them in the
+                           backward, so that information, which moves one vehicle per
+                           step (Sec. III-B's synchronous update), cannot reach its owned
+                           vehicles from outside within a launch.  Owned results equal
+                           the whole-lane kernels' bit for bit.  For few long lanes, whose
+                           work-groups leave most compute units idle.  With
+                           store_states 2 the autotuner also times tile shapes; 0: whole
+                           lanes */
 } idm_tuning;
 
 /* Per-vehicle IDM parameters (Sec. III-A), FP32 [N] each, all > 0. */

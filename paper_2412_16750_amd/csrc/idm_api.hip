@@ -251,8 +251,10 @@ struct Layout {
 };
 
 // Halo tiles of `threads` slots advancing J steps per launch: a lane of at
-// most `threads` vehicles is one tile; a longer one is cut into
-// ceil(n / (threads - J)) tiles of nearly equal owned ranges.
+// most threads - J vehicles is one tile (no halo); a longer one is cut into
+// ceil(n / (threads - J)) tiles of nearly equal owned ranges (a lane that
+// would fit one work-group is cut too: the point of tiles is to spread few
+// lanes over more compute units).
 template <class F>
 void for_each_tile(const std::vector<int32_t> &offsets, int L, int threads, int J, F fn) {
     const int64_t own_cap = threads - J;
@@ -260,7 +262,7 @@ void for_each_tile(const std::vector<int32_t> &offsets, int L, int threads, int 
         const int32_t s0 = offsets[l], e0 = offsets[l + 1];
         const int64_t n = e0 - s0;
         if (n == 0) continue;
-        if (n <= threads) {
+        if (n <= own_cap) {
             fn(s0, e0, s0, e0);
             continue;
         }
@@ -557,7 +559,9 @@ idm_status choose_shape(const idm_plan *p, const idm_tuning *tu, Shape &sh) {
     const int KB_req = tu ? tu->block : 0;
     if (K <= 0) K = KB_req > 0 ? KB_req : 32;
     if (tu && (tu->threads || tu->per_thread)) {
-        if (!valid_threads(tu->threads) || !valid_per_thread(tu->per_thread))
+        // 768 threads: halo tiles only (checked below)
+        if (!(valid_threads(tu->threads) || (tu->threads == 768 && tu->tile_steps > 0)) ||
+            !valid_per_thread(tu->per_thread))
             return fail(IDM_ERR_UNSUPPORTED, "tuning threads=%d per_thread=%d not supported",
                         tu->threads, tu->per_thread);
         sh.threads = tu->threads;
@@ -607,11 +611,12 @@ idm_status choose_shape(const idm_plan *p, const idm_tuning *tu, Shape &sh) {
         if (!sh.stored)
             return fail(IDM_ERR_UNSUPPORTED, "halo tiles (tile_steps %d) need store_states = 1",
                         sh.tile);
-        if (!(tu->threads == 256 || tu->threads == 512 || tu->threads == 1024) ||
+        if (!(tu->threads == 256 || tu->threads == 512 || tu->threads == 768 ||
+              tu->threads == 1024) ||
             tu->per_thread != 1)
             return fail(IDM_ERR_UNSUPPORTED,
-                        "halo tiles need threads of 256, 512 or 1024 and per_thread = 1 in the "
-                        "tuning; got %d x %d",
+                        "halo tiles need threads of 256, 512, 768 or 1024 and per_thread = 1 in "
+                        "the tuning; got %d x %d",
                         tu->threads, tu->per_thread);
         if (sh.tile >= sh.threads || sh.tile % 2 != 0 || sh.tile % K != 0)
             return fail(IDM_ERR_UNSUPPORTED,
@@ -1596,13 +1601,13 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
             }
         }
     // halo tiles (kept states, one vehicle per thread) where a lane is longer
-    // than the work-group: J steps per launch, J a multiple of the plan's K
+    // than a tile's owned part: J steps per launch, J a multiple of the plan's K
     if (p->store_pref >= 1) {
-        const int tile_cands[][2] = {{256, 64}, {256, 128}, {512, 64}, {512, 128},
-                                     {512, 256}, {1024, 128}, {1024, 256}};
+        const int tile_cands[][2] = {{256, 64}, {256, 128}, {512, 128}, {512, 256},
+                                     {768, 256}, {1024, 128}, {1024, 256}};
         for (const auto &tc : tile_cands) {
             const int t = tc[0], J = tc[1];
-            if (p->max_lane <= t || J % p->sh.K != 0) continue;
+            if (p->max_lane <= t - J || J % p->sh.K != 0) continue;
             const int64_t nt = count_tiles(p->offsets, p->pb.n_lanes, t, J);
             if (ws_total(p, dims(p->sh.K, 0, true, nt)) > ws_bytes) continue;
             if (!forward_tiled_kernel(p->pb.bound, t) ||

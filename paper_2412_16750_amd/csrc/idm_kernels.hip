@@ -96,8 +96,10 @@ __device__ __forceinline__ void load_vehicles(const SimArgs &A, int64_t slot0, V
 __device__ __forceinline__ int lead_thread(int t) { return t > 0 ? t - 1 : 0; }
 template <int NT>
 __device__ __forceinline__ int follow_thread(int t) {
-    static_assert((NT & (NT - 1)) == 0, "power-of-two work-group");
-    return (t + 1) & (NT - 1);
+    if constexpr ((NT & (NT - 1)) == 0)
+        return (t + 1) & (NT - 1);
+    else
+        return t + 1 < NT ? t + 1 : 0;  // the 768-thread halo tiles
 }
 
 // Boundary rows of bundle `bidx` (uniform): the external leader's states and
@@ -1658,14 +1660,17 @@ KernelFn backward_stored_kernel(int mode, int per_thread, int threads, bool dens
         return dense ? (KernelFn)&k_backward_stored<M, 1, NT, true, true>        \
                      : (KernelFn)&k_backward_stored<M, 1, NT, false, true>;
 #if IDM_PART == 10
+// 768 threads: a 1000-vehicle lane in two tiles of 500 owned vehicles with
+// J = 256 uses at most 756 slots, and twelve waves instead of sixteen share
+// the compute unit
 KernelFn forward_tiled_kernel(int mode, int threads) {
-    IDM_TILE_CASE(0, 256) IDM_TILE_CASE(0, 512) IDM_TILE_CASE(0, 1024)
-    IDM_TILE_CASE(1, 256) IDM_TILE_CASE(1, 512) IDM_TILE_CASE(1, 1024)
+    IDM_TILE_CASE(0, 256) IDM_TILE_CASE(0, 512) IDM_TILE_CASE(0, 768) IDM_TILE_CASE(0, 1024)
+    IDM_TILE_CASE(1, 256) IDM_TILE_CASE(1, 512) IDM_TILE_CASE(1, 768) IDM_TILE_CASE(1, 1024)
     return nullptr;
 }
 KernelFn backward_tiled_kernel(int mode, int threads, bool dense) {
-    IDM_TILE_BWD(0, 256) IDM_TILE_BWD(0, 512) IDM_TILE_BWD(0, 1024)
-    IDM_TILE_BWD(1, 256) IDM_TILE_BWD(1, 512) IDM_TILE_BWD(1, 1024)
+    IDM_TILE_BWD(0, 256) IDM_TILE_BWD(0, 512) IDM_TILE_BWD(0, 768) IDM_TILE_BWD(0, 1024)
+    IDM_TILE_BWD(1, 256) IDM_TILE_BWD(1, 512) IDM_TILE_BWD(1, 768) IDM_TILE_BWD(1, 1024)
     return nullptr;
 }
 #endif

@@ -114,9 +114,10 @@ class Plan:
 
     def forward_workspace(self, device="cuda") -> Optional[torch.Tensor]:
         """A workspace for forward-only calls: None unless lanes longer than a
-        bundle exchange boundary states through it (then one buffer, kept by
-        the plan and reused)."""
-        if self.info()["n_boundaries"] == 0:
+        bundle exchange boundary states through it, or halo tiles keep their
+        states in it (then one buffer, kept by the plan and reused)."""
+        info = self.info()
+        if info["n_boundaries"] == 0 and info["tile_steps"] == 0:
             return None
         ws = getattr(self, "_fws", None)
         if ws is None or ws.device != torch.device(device):

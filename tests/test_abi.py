@@ -154,7 +154,7 @@ def _tile_layout(L, offsets, threads, J, K=16, S=100):
 
 
 @pytest.mark.parametrize("threads, J, K", [(256, 64, 16), (512, 128, 32), (256, 32, 16),
-                                           (1024, 256, 32), (512, 64, 64)])
+                                           (1024, 256, 32), (512, 64, 64), (768, 256, 32)])
 def test_halo_tile_layout(L, threads, J, K):
     """Halo tiles (Sec. III-B: a step moves information one vehicle): every
     vehicle is owned by exactly one tile; a tile owns at most threads - J
@@ -162,7 +162,8 @@ def test_halo_tile_layout(L, threads, J, K):
     ahead (fewer only where the lane starts), the first slot flagged as a
     lane head; its backward slots are the owned vehicles and up to J behind
     (fewer only where the lane ends), flagged as a head only on a true lane
-    head; a lane that fits the work-group is one tile; the workspace adds the
+    head; a lane of at most threads - J vehicles is one tile, a longer one
+    ceil(n / (threads - J)) tiles; the workspace adds the
     carried adjoints and sums (68 B per vehicle) to the kept states."""
     import scenarios
     sizes = scenarios.lognormal_lane_sizes(300, np.log(threads) + 0.3, 1.0, 1, 6 * threads, 41)
@@ -175,6 +176,7 @@ def test_halo_tile_layout(L, threads, J, K):
     lane_of = np.repeat(np.arange(len(sizes)), sizes)
     owned_all = []
     tiles_of_lane = np.zeros(len(sizes), dtype=np.int64)
+    tiles_need = -(-np.asarray(sizes) // (threads - J))
     for b in range(info.n_bundles):
         gf, ff = gidx[0, b], flags[0, b]
         gb, fb = gidx[1, b], flags[1, b]
@@ -193,8 +195,8 @@ def test_halo_tile_layout(L, threads, J, K):
         lo, hi = int(own_f[0]), int(own_f[-1]) + 1
         assert np.array_equal(own_f, np.arange(lo, hi))
         assert ls <= lo and hi <= le
-        if le - ls > threads:
-            assert hi - lo <= threads - J
+        if le - ls > threads - J:
+            assert hi - lo <= threads - J and tiles_need[lane] > 1
         else:
             assert (lo, hi) == (ls, le)
         # forward: halo ahead, then owned; head flag on the first slot only
@@ -206,6 +208,7 @@ def test_halo_tile_layout(L, threads, J, K):
         assert np.array_equal(heads, [ls] if lo == ls else [])
         owned_all.append(own_f)
     owned_all = np.concatenate(owned_all)
+    assert np.array_equal(tiles_of_lane, tiles_need)
     assert np.array_equal(np.sort(owned_all), np.arange(N))
     assert len(owned_all) == N
     align = lambda x: (x + 255) // 256 * 256
@@ -217,8 +220,8 @@ def test_halo_tile_layout(L, threads, J, K):
 
 def test_halo_tile_tuning_limits(L):
     """Halo tiles need kept states, one vehicle per thread, explicit threads of
-    256, 512 or 1024, an even J that is a multiple of K and below the
-    work-group, and one work-group per tile."""
+    256, 512, 768 or 1024 (768 for tiles only), an even J that is a multiple
+    of K and below the work-group, and one work-group per tile."""
     off = [0, 3000, 3500]
     ok = (512, 1, 32, 0, 0, 1, 64)
     assert _check(L, off, tuning=ok, K=32)[0] == 0
@@ -234,6 +237,8 @@ def test_halo_tile_tuning_limits(L):
         st = _check(L, off, tuning=bad, K=32)[0]
         assert st == -3, (bad, st)
     assert _check(L, off, tuning=(512, 1, 32, 0, 0, 1, -64), K=32)[0] == -1
+    assert _check(L, off, tuning=(768, 1, 32, 0, 0, 1, 256), K=32)[0] == 0
+    assert _check(L, off, tuning=(768, 1, 32, 0, 0, 1, 0), K=32)[0] == -3
 
 
 def test_backward_entry_points_reject_null_arguments(L):

@@ -77,7 +77,7 @@ def _tiled(threads, J, K):
 
 @pytest.mark.parametrize("mode", [MODE_SOFTPLUS, MODE_CLAMP])
 @pytest.mark.parametrize("shape", [(256, 64, 16), (512, 128, 32), (256, 32, 32),
-                                   (1024, 256, 32)])
+                                   (1024, 256, 32), (768, 256, 32)])
 def test_tiles_bitwise_equal_whole_lanes(mode, shape):
     """Lanes of 1 to 3000 vehicles (exactly a work-group, one more, one tile's
     owned count, several tiles), S = 203 (a ragged last block of J and of K),
