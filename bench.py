@@ -57,13 +57,13 @@ PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
 # states with its forward writing both rows, or the checkpointed pair).
 COUNTERS = {
     "stored": {"traffic_bwd": 2.6627e+09, "traffic_fwd": 1.7821e+09,
-               "valu_busy_bwd": 0.701, "valu_per_wave_step_bwd": 74.8, "clock_bwd": 2.324,
-               "valu_busy_fwd": 0.511, "valu_per_wave_step_fwd": 37.0, "clock_fwd": 2.388},
-    "checkpointed": {"traffic_bwd": 1.2382e+09, "traffic_fwd": 9.8218e+08,
-                     "valu_busy_bwd": 0.847, "valu_per_wave_step_bwd": 118.3, "clock_bwd": 2.360,
-                     "valu_busy_fwd": 0.930, "valu_per_wave_step_fwd": 36.5, "clock_fwd": 2.349},
+               "valu_busy_bwd": 0.695, "valu_per_wave_step_bwd": 74.8, "clock_bwd": 2.347,
+               "valu_busy_fwd": 0.508, "valu_per_wave_step_fwd": 37.0, "clock_fwd": 2.399},
+    "checkpointed": {"traffic_bwd": 1.2382e+09, "traffic_fwd": 9.8217e+08,
+                     "valu_busy_bwd": 0.841, "valu_per_wave_step_bwd": 118.3, "clock_bwd": 2.352,
+                     "valu_busy_fwd": 0.932, "valu_per_wave_step_fwd": 36.5, "clock_fwd": 2.322},
 }
-TRAFFIC_KERNEL_SHA256 = "b363833fafa545a11dcd28ceae44704f2f639e102122daac74151d528a28075d"
+TRAFFIC_KERNEL_SHA256 = "061453c0a4682868a87f03421e7ec9d312e2d85d741fe0647389174bfcbed530"
 
 
 # Warm-start network training: Adam over 1M pairs, batch 4096, learning rate
@@ -491,6 +491,63 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
     return out
 
 
+def fit_plans(dev, log_fn, iters: int = 50) -> dict:
+    """The fit workload's plans side by side, without the warm-start network:
+    whole lanes with checkpoints, whole lanes keeping every step's states,
+    and the autotuner's pick when given room for halo tiles; `iters` fit
+    iterations of each as graph replays (event-timed), parameters compared
+    bit for bit.  For kernel traces of the fit's kernels (`--fit-plans-only`)."""
+    import numpy as np
+    import torch
+    import scenarios
+    from paper_2412_16750_amd import sim
+    from paper_2412_16750_amd.fit import Fitter
+    sc = scenarios.fit()
+    length = torch.from_numpy(np.ascontiguousarray(sc.params["length"])).to(dev)
+    p0 = torch.from_numpy(np.ascontiguousarray(sc.p0)).to(dev)
+    v = torch.from_numpy(np.ascontiguousarray(sc.v_init)).to(dev)
+    prm = sim.params_tensor(sc.params, dev)
+    plan0 = sim.Plan.for_scenario(sc)
+    hidden = torch.empty(sc.n_steps + 1, sc.n, dtype=torch.float32, device=dev)
+    sim.idm_sim_forward(plan0, prm, length, p0, v, hidden, None, None)
+    n_obs = sc.n_steps // 10
+    noise = torch.from_numpy(scenarios.noise((n_obs, sc.n), 4).astype(np.float32)).to(dev)
+    tgt = (hidden[10::10].double() + p0[None, :] + noise.double()).float().contiguous()
+    obs = sim.Obs(tgt, 10, 10)
+    cold = sim.params_tensor(scenarios.cold_params(sc), dev)
+    tuned = sim.Plan.for_scenario(sc, store_states="auto")
+    room = max(sim.Plan.for_scenario(sc, store_states=True).workspace_bytes,
+               sim.Plan.for_scenario(sc, store_states=True, threads=256, per_thread=1,
+                                     tile_steps=64).workspace_bytes)
+    tb = sim.StepBuffers(tuned, cold, length, p0, v, obs=obs, workspace_bytes=room)
+    info = sim.idm_plan_autotune(tb, reps=3)
+    del tb
+    out, ref = {"workload": "100 lanes x 1000 vehicles, 500 steps, observed every 10th step",
+                "iterations": iters}, None
+    for tag, plan in (("checkpointed", plan0), ("stored_whole_lanes",
+                                                 sim.Plan.for_scenario(sc, store_states=True)),
+                      ("autotuned", tuned)):
+        f = Fitter(plan, length, p0, v, obs, lr0=1e-2)
+        f.init(cold)
+        f.run(3)
+        f.init(cold)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        f.run(iters)
+        e1.record()
+        torch.cuda.synchronize()
+        ref = f.params.clone() if ref is None else ref
+        pi = plan.info()
+        out[tag] = {"ms_per_iteration": e0.elapsed_time(e1) / iters,
+                    "params_bitwise_equal_to_checkpointed": bool(torch.equal(f.params, ref)),
+                    "plan": {k: pi[k] for k in ("threads", "ckpt_every", "store_states",
+                                                "tile_steps", "n_bundles")}}
+        log_fn("bench: fit plan %s %.3f ms per iteration (%s)" % (tag, out[tag]["ms_per_iteration"],
+                                                                  out[tag]["plan"]))
+    return out
+
+
 # Paper, Table 1 (own data, Xeon W-2255 + RTX A5000): reconstruction Pos. 0.13 %,
 # |a| 0.3 / 1.1 m/s^2, 0 % implausible, 0.164 s per trajectory; filtering 0.08 %,
 # 0.5 / 0.5, 0 %, 0.308 s per trajectory.
@@ -728,6 +785,9 @@ def main():
                          "the 1M simulated pairs (no training run)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the streaming copy kernel (byte-counter calibration)")
+    ap.add_argument("--fit-plans-only", action="store_true",
+                    help="only time fit iterations on the fit workload's plans (whole lanes with "
+                         "checkpoints or kept states, the autotuner's pick with halo tiles)")
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--per-thread", type=int, default=0)
     ap.add_argument("--ckpt", type=int, default=32)
@@ -761,7 +821,8 @@ def main():
     import scenarios
 
     cpu = None
-    if not args.copy_only and not args.mlp_only and not args.no_cpu_baseline:
+    if (not args.copy_only and not args.mlp_only and not args.fit_plans_only
+            and not args.no_cpu_baseline):
         # before anything loads the HIP runtime: the baseline forks workers
         log("bench: CPU oracle baseline")
         cpu = cpu_baseline(scenarios.scale(ckpt_every=args.ckpt), args.cpu_lanes)
@@ -779,6 +840,10 @@ def main():
         from paper_2412_16750_amd import warmstart as ws
         data = ws.make_pairs(scenarios.warm_training())
         print(json.dumps({"pairs": int(data.X.shape[0]), **mlp_rates(ws, data)}))
+        return
+
+    if args.fit_plans_only:
+        print(json.dumps(fit_plans(dev, log)))
         return
 
     if args.copy_only:
@@ -890,7 +955,7 @@ def main():
     import hashlib
     csrc = os.path.join(ROOT, "paper_2412_16750_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("idm_kernels.hip", "idm_device.h"):
+    for f in ("idm_kernels.hip", "idm_device.h", "idm_internal.h"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     same_kernel = h.hexdigest() == TRAFFIC_KERNEL_SHA256
     same_shape = (same_kernel and info["ckpt_every"] == 32 and info["block"] == 16
