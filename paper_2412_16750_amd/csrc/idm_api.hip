@@ -770,8 +770,13 @@ idm_status run_forward(idm_plan *p, const idm_params *prm, const double *p0, con
                         "workspace; the forward needs it");
         ext_args(p, ws, a);
     }
+    // bundle-edge waves store through the cache when both rows are written by
+    // a launch that fills the chip (there the half-written boundary lines of
+    // streamed stores cost HBM write rate); a launch of few work-groups is
+    // bound by each step's latency, which streamed stores keep lower
+    const bool edge_cached = a.traj_d && a.traj_v && p->n_bundles >= kRoundCUs;
     KernelFn fn = forward_kernel(p->pb.bound, p->sh.per_thread, p->sh.threads, p->n_bnd > 0,
-                                 a.traj_d && a.traj_v);
+                                 edge_cached);
     if (!fn) return fail(IDM_ERR_UNSUPPORTED, "no forward kernel for this shape");
     uint64_t *diag = ws ? (uint64_t *)((char *)ws + ws_diag_off(p)) : nullptr;
     // pieces of long lanes: level l reads the boundary states level l-1 wrote

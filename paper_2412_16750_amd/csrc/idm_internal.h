@@ -133,9 +133,10 @@ struct EgoAdamArgs {
 using KernelFn = const void *;
 
 // Lookup of compiled kernel instantiations; nullptr when not instantiated.
-// two_rows: both trajectory rows are written (the kernel's bundle-edge waves
-// then store through the cache).
-KernelFn forward_kernel(int mode, int per_thread, int threads, bool pieces, bool two_rows);
+// edge_cached: the instantiation whose bundle-edge waves store both
+// trajectory rows through the cache (for launches that write both rows and
+// fill the chip); otherwise every store is streamed.
+KernelFn forward_kernel(int mode, int per_thread, int threads, bool pieces, bool edge_cached);
 // Backward kernel for a register block KB and checkpoint interval K (the
 // stash variant when K = 2 KB and one is instantiated for the shape); `dense`
 // selects the variant that reads dense upstream gradients.

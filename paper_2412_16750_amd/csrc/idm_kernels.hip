@@ -267,7 +267,8 @@ __device__ __forceinline__ void forward_body(const SimArgs &A, float2 (*lead_buf
         // at 3.4 TB/s (0.46 ms on 2000 x 1000 vehicles, 0.32 ms with lanes of
         // 1024).  The waves holding a bundle's first or last vehicle therefore
         // store both rows through the cache when both are written: 0.39 ms.
-        // (With one row the streamed stores are faster everywhere.)
+        // (With one row, and in launches of few work-groups, where a step's
+        // latency sets the time, the streamed stores are faster everywhere.)
         bool edge_cached = false;
         if constexpr (ER) {
             const int w = t >> 6;
@@ -490,8 +491,8 @@ __global__ __launch_bounds__(NT) void k_forward_tiled(SimArgs A) {
                 __builtin_amdgcn_make_buffer_rsrc((void *)trow_d, (short)0, (int)NB, 0x00020000);
             const __amdgpu_buffer_rsrc_t rv =
                 __builtin_amdgcn_make_buffer_rsrc((void *)trow_v, (short)0, (int)NB, 0x00020000);
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(d), rd, voff, 0, 0);
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rv, voff, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(d), rd, voff, 0, kStreamNT);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rv, voff, 0, kStreamNT);
             lds_barrier();
         };
         int k = k_lo;
@@ -1570,14 +1571,14 @@ __global__ __launch_bounds__(256) void k_fit_init_u(AdamArgs A, const float *u_r
 #define IDM_FWD_CASE(M, R, NT)                                                \
     if (mode == M && per_thread == R && threads == NT)                        \
         return pieces ? (R == 1 ? (KernelFn)&k_forward_pieces<M, NT> : nullptr)  \
-                      : (two_rows ? (KernelFn)&k_forward<M, R, NT, true>          \
-                                  : (KernelFn)&k_forward<M, R, NT, false>);
+                      : (edge_cached ? (KernelFn)&k_forward<M, R, NT, true>       \
+                                     : (KernelFn)&k_forward<M, R, NT, false>);
 #define IDM_FWD_R(M, R) \
     IDM_FWD_CASE(M, R, 64) IDM_FWD_CASE(M, R, 128) IDM_FWD_CASE(M, R, 256) \
     IDM_FWD_CASE(M, R, 512) IDM_FWD_CASE(M, R, 1024)
 
 #if IDM_PART == 0
-KernelFn forward_kernel(int mode, int per_thread, int threads, bool pieces, bool two_rows) {
+KernelFn forward_kernel(int mode, int per_thread, int threads, bool pieces, bool edge_cached) {
     IDM_FWD_R(0, 1) IDM_FWD_R(0, 2) IDM_FWD_R(0, 4)
     IDM_FWD_R(1, 1) IDM_FWD_R(1, 2) IDM_FWD_R(1, 4)
     return nullptr;
