@@ -274,3 +274,60 @@ def test_tiles_autotune_and_full_fit_workload():
     assert np.array_equal(gp.cpu().numpy(), ref["g"])
     assert np.array_equal(g0.cpu().numpy(), ref["gp0"])
     assert np.array_equal(g1.cpu().numpy(), ref["gv0"])
+
+
+def test_tiles_step_graph_autograd_noalloc_and_forward_helper():
+    """A tiled plan under the other entry points: the step graph with
+    trajectory outputs (several launches and the row copies inside one
+    graph) replayed three times with eager work in between, autograd, the
+    no-allocation gradient and a forward-only call through the plan's
+    forward workspace all equal the whole-lane plan's results."""
+    import torch
+    from paper_2412_16750_amd import autograd, sim
+    sc = ragged_scenario([900, 33, 700, 1, 300], 150, ckpt_every=16)
+    steps = np.arange(1, sc.n_steps + 1)
+    tgt = torch.from_numpy(oracle_targets(sc, steps, c=23)).cuda()
+    obs = sim.Obs(tgt, 1, 1)
+    x = device_inputs(sc)
+    S, n = sc.n_steps, sc.n
+    tiled = sim.Plan.for_scenario(sc, **_tiled(256, 64, 16))
+    whole = sim.Plan.for_scenario(sc, ckpt_every=16)
+    ref = sim.StepBuffers(whole, x["prm"], x["length"], x["p0"], x["v"],
+                          traj_d=torch.empty(S + 1, n, device="cuda"),
+                          traj_v=torch.empty(S + 1, n, device="cuda"), obs=obs)
+    ref.run_eager()
+    torch.cuda.synchronize()
+    b = sim.StepBuffers(tiled, x["prm"], x["length"], x["p0"], x["v"],
+                        traj_d=torch.empty(S + 1, n, device="cuda"),
+                        traj_v=torch.empty(S + 1, n, device="cuda"), obs=obs)
+    for rep in range(3):
+        for t in (b.traj_d, b.traj_v, b.grad_params, b.grad_p0, b.grad_v0):
+            t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        sim.idm_step_graph_launch(b)
+        torch.cuda.synchronize()
+        for k in ("traj_d", "traj_v", "grad_params", "grad_p0", "grad_v0"):
+            assert torch.equal(getattr(b, k), getattr(ref, k)), (rep, k)
+        assert abs(b.loss.item() - ref.loss.item()) <= 1e-12 * ref.loss.item()
+    grads = []
+    for plan in (whole, tiled):
+        prm = x["prm"].clone().requires_grad_(True)
+        d = autograd.simulate(plan, prm, x["p0"], x["v"], x["length"])
+        (d[-1].double() ** 2).sum().backward()
+        grads.append(prm.grad.cpu().numpy())
+    assert np.array_equal(grads[0], grads[1])
+    outs = []
+    for plan in (whole, tiled):
+        gp = torch.empty(5, n, dtype=torch.float64, device="cuda")
+        g0 = torch.empty(n, dtype=torch.float64, device="cuda")
+        g1 = torch.empty(n, dtype=torch.float64, device="cuda")
+        sim.idm_sim_backward_noalloc(plan, x["prm"], x["length"], x["p0"], x["v"], gp, g0, g1,
+                                     obs=obs)
+        traj = torch.empty(S + 1, n, device="cuda")
+        sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], traj, None,
+                            plan.forward_workspace())
+        torch.cuda.synchronize()
+        outs.append((gp.cpu().numpy(), g0.cpu().numpy(), g1.cpu().numpy(), traj.cpu().numpy()))
+    for a, c in zip(outs[0], outs[1]):
+        assert np.array_equal(a, c)
+    assert np.array_equal(outs[1][3], ref.traj_d.cpu().numpy())
