@@ -196,7 +196,12 @@ idm_status idm_problem_check(const idm_problem *problem, const idm_tuning *tunin
  * bundle b is element b*threads*per_thread + s; slot_vehicle_host receives the
  * vehicle index (-1 = padding) and slot_flags_host bit 0 = lane head, bit 1 =
  * lane tail, bit 2 = occupied.  Both arrays must hold `capacity` >= n_slots
- * entries (see idm_problem_check), else IDM_ERR_INVALID_ARG. */
+ * entries (see idm_problem_check), else IDM_ERR_INVALID_ARG.  With halo tiles
+ * (tile_steps > 0; n_bundles counts tiles) there are two tables of n_slots
+ * each, so capacity >= 2 n_slots: the forward's (the halo ahead, then the
+ * owned vehicles; bit 0 on the first slot) then the backward's (the owned
+ * vehicles, then the halo behind; bit 0 only on a true lane head); bit 3
+ * marks the vehicles a tile owns. */
 idm_status idm_problem_layout(const idm_problem *problem, const idm_tuning *tuning,
                               int32_t *slot_vehicle_host, uint8_t *slot_flags_host,
                               int64_t capacity);
