@@ -109,22 +109,19 @@ typedef struct {
                            2: start with checkpoints and let idm_plan_autotune time both
                            backwards (the kept states only where the workspace it is given
                            holds them) and keep the faster */
-    int32_t tile_steps;   /* J > 0: halo tiles (needs store_states 1, one vehicle per
-                           thread and explicit threads of 256, 512, 768 (tiles only) or
-                           1024; J even, a
-                           multiple of K and below threads).  A lane longer than
-                           threads - J vehicles is cut into ceil(n / (threads - J)) tiles
-                           of nearly equal owned parts, one work-group each (a shorter
-                           lane is one tile), and the steps into blocks of J run as
-                           successive launches: a tile also simulates the J vehicles
-                           ahead of its own in the forward and the J behind them in the
-                           backward, so that information, which moves one vehicle per
-                           step (Sec. III-B's synchronous update), cannot reach its owned
-                           vehicles from outside within a launch.  Owned results equal
+    int32_t tile_steps;   /* J > 0: halo tiles (needs store_states 1, one vehicle per thread and
+                           explicit threads of 256, 512, 768 (tiles only) or 1024; J even, a
+                           multiple of K and below threads; grid 0).  A lane longer than
+                           threads - J vehicles is cut into ceil(n / (threads - J)) tiles of
+                           nearly equal owned parts, one work-group each (a shorter lane is one
+                           tile), and the steps into blocks of J run as successive launches: a
+                           tile also simulates the J vehicles ahead of its own in the forward and
+                           the J behind them in the backward, so that information, which moves
+                           one vehicle per step (Sec. III-B's synchronous update), cannot reach
+                           its owned vehicles from outside within a launch.  Owned results equal
                            the whole-lane kernels' bit for bit.  For few long lanes, whose
-                           work-groups leave most compute units idle.  With
-                           store_states 2 the autotuner also times tile shapes; 0: whole
-                           lanes */
+                           work-groups leave most compute units idle.  With store_states 2 the
+                           autotuner also times tile shapes; 0: whole lanes */
 } idm_tuning;
 
 /* Per-vehicle IDM parameters (Sec. III-A), FP32 [N] each, all > 0. */
