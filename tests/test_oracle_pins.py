@@ -282,6 +282,67 @@ def test_causality_bitwise():
         assert not np.array_equal(P2[:, j], P[:, j])
 
 
+def _sub_lane(pb, P, V, first, last, k0, steps):
+    """Vehicles first..last-1 of a one-lane problem as a lane of their own
+    (the first one driving on a free road), started from the full run's
+    exact states at step k0."""
+    idx = np.arange(first, last)
+    prm = {k: pb.params[k][idx] for k in pb.params}
+    prm["length"] = pb.length[idx]
+    return Problem([0, len(idx)], prm, P[k0, idx], V[k0, idx], steps, pb.dt, pb.delta, pb.a_min,
+                   pb.gap_floor, pb.mode)
+
+
+@pytest.mark.parametrize("mode", [MODE_SOFTPLUS, MODE_CLAMP])
+@pytest.mark.parametrize("J", [1, 2, 3, 6])
+def test_information_moves_one_vehicle_per_step(mode, J):
+    """Sec. III-B's synchronous update (each vehicle's next state from its own
+    and its leader's current state, Eqs. 1-3) moves information one vehicle
+    per step: the reading the halo tiles rest on.  Forward: a sub-lane started
+    from the exact states at step k0 with J vehicles ahead of the owned ones
+    keeps the owned ones bitwise exact for J steps; with J - 1 the first owned
+    vehicle is exact through step J - 1 and wrong at step J.  Backward (the
+    last J steps, upstream gradients on every step's positions and speeds):
+    with J + 1 vehicles ahead and J behind, the owned vehicles' adjoints at k0
+    and parameter gradients equal the full lane's bit for bit; with J - 1
+    behind the last owned vehicle's do not (a follower reaches its leader
+    through its speed adjoint, so the speed upstream makes the bound tight)."""
+    import scenarios
+    # free flow (the single-lane workload's draws: gaps 20-40 m), where every
+    # coupling is far from vanishing in FP64; a stop-and-go queue braking at
+    # the bound has speed derivatives below FP64 resolution
+    pb = Problem.from_scenario(scenarios.single_lane(n_vehicles=40, n_steps=30, mode=mode))
+    P, V, _, _ = oracle.forward(pb)
+    a, b, k0 = 18, 24, 12
+    Ps, Vs, _, _ = oracle.forward(_sub_lane(pb, P, V, a - J, b, k0, J))
+    assert np.array_equal(Ps[:, J:], P[k0:k0 + J + 1, a:b])
+    assert np.array_equal(Vs[:, J:], V[k0:k0 + J + 1, a:b])
+    Ps, Vs, _, _ = oracle.forward(_sub_lane(pb, P, V, a - J + 1, b, k0, J))
+    assert np.array_equal(Vs[:J, J - 1], V[k0:k0 + J, a])
+    assert Vs[J, J - 1] != V[k0 + J, a]
+    # backward over the last J steps of the run
+    S = pb.n_steps
+    k1 = S - J
+    rng = np.random.default_rng(5)
+    gP = rng.normal(0.0, 1.0, (J + 1, pb.n))
+    gV = rng.normal(0.0, 1.0, (J + 1, pb.n))
+    tail = _sub_lane(pb, P, V, 0, pb.n, k1, J)
+    g, gp0, gv0 = oracle.adjoint(tail, P[k1:], V[k1:], gP, gV)
+
+    def sub_adjoint(behind):
+        lo, hi = a - J - 1, min(pb.n, b + behind)
+        sp = _sub_lane(pb, P, V, lo, hi, k1, J)
+        Ps, Vs, _, _ = oracle.forward(sp)
+        return oracle.adjoint(sp, Ps, Vs, gP[:, lo:hi], gV[:, lo:hi]), a - lo
+
+    (gs, gp0s, gv0s), off = sub_adjoint(J)
+    own = slice(off, off + b - a)
+    assert np.array_equal(gp0s[own], gp0[a:b]) and np.array_equal(gv0s[own], gv0[a:b])
+    assert np.array_equal(gs[:, own], g[:, a:b])
+    (gs, gp0s, gv0s), off = sub_adjoint(J - 1)
+    assert gv0s[off + b - a - 1] != gv0[b - 1]
+
+
 def test_lanes_are_independent_bitwise():
     """Two lanes simulated together equal each simulated alone."""
     a = _harsh(MODE_SOFTPLUS, n=10, seed=1)
