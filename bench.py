@@ -395,7 +395,7 @@ def fit_report(dev, log_fn, cap: int = 2000) -> dict:
                                      tile_steps=64).workspace_bytes)
     tb = sim.StepBuffers(plan, cold, length, p0, v, obs=obs, workspace_bytes=room)
     t0 = time.perf_counter()
-    tuned = sim.idm_plan_autotune(tb, reps=3)
+    tuned = sim.idm_plan_autotune(tb, reps=10)
     tune_s = time.perf_counter() - t0
     del tb
     log_fn("bench: fit plan autotuned %s in %.3f s" % (tuned, tune_s))
@@ -520,7 +520,7 @@ def fit_plans(dev, log_fn, iters: int = 50) -> dict:
                sim.Plan.for_scenario(sc, store_states=True, threads=256, per_thread=1,
                                      tile_steps=64).workspace_bytes)
     tb = sim.StepBuffers(tuned, cold, length, p0, v, obs=obs, workspace_bytes=room)
-    info = sim.idm_plan_autotune(tb, reps=3)
+    info = sim.idm_plan_autotune(tb, reps=10)
     del tb
     out, ref = {"workload": "100 lanes x 1000 vehicles, 500 steps, observed every 10th step",
                 "iterations": iters}, None

@@ -250,43 +250,53 @@ struct Layout {
     std::vector<int32_t> level, level_start;
 };
 
-// Halo tiles of `threads` slots advancing J steps per launch: a lane of at
-// most threads - J vehicles is one tile (no halo); a longer one is cut into
-// ceil(n / (threads - J)) tiles of nearly equal owned ranges (a lane that
-// would fit one work-group is cut too: the point of tiles is to spread few
-// lanes over more compute units).
+// Halo tiles of T = `threads` slots advancing J steps per launch.  A lane of
+// n <= T vehicles is one tile (no halo).  A longer one is cut into the
+// fewest tiles that hold it, m = ceil((n - J) / (T - J)): the forward's first
+// tile (the lane head) and the backward's last (the lane tail) need no halo
+// on that side, so each direction splits the lane on its own, the m tiles'
+// slot counts (owned vehicles plus halo) as equal as integers allow.
+// fn(lane start, lane end, tile j, m, forward owned [lo, hi), backward owned
+// [lo, hi)).
 template <class F>
 void for_each_tile(const std::vector<int32_t> &offsets, int L, int threads, int J, F fn) {
-    const int64_t own_cap = threads - J;
     for (int l = 0; l < L; ++l) {
         const int32_t s0 = offsets[l], e0 = offsets[l + 1];
         const int64_t n = e0 - s0;
         if (n == 0) continue;
-        if (n <= own_cap) {
-            fn(s0, e0, s0, e0);
+        if (n <= threads) {
+            fn(s0, e0, 0, 1, s0, e0, s0, e0);
             continue;
         }
-        const int64_t nt = (n + own_cap - 1) / own_cap;
-        const int64_t base = n / nt, rem = n % nt;
-        int32_t lo = s0;
-        for (int64_t j = 0; j < nt; ++j) {
-            const int32_t hi = lo + (int32_t)(base + (j < rem ? 1 : 0));
-            fn(s0, e0, lo, hi);
-            lo = hi;
+        const int64_t m = (n - J + (threads - J) - 1) / (threads - J);
+        const int64_t q = n + (m - 1) * J;  // slots over all tiles
+        const int64_t base = q / m, rem = q % m;
+        auto slots = [&](int64_t j) { return base + (j < rem ? 1 : 0); };
+        // forward: tile 0 has no halo ahead; backward: tile m - 1 none behind
+        int32_t flo = s0, blo = s0;
+        for (int64_t j = 0; j < m; ++j) {
+            const int32_t fhi = flo + (int32_t)(slots(j) - (j > 0 ? J : 0));
+            const int32_t bhi = blo + (int32_t)(slots(m - 1 - j) - (j < m - 1 ? J : 0));
+            fn(s0, e0, (int)j, (int)m, flo, fhi, blo, bhi);
+            flo = fhi;
+            blo = bhi;
         }
     }
 }
 
 int64_t count_tiles(const std::vector<int32_t> &offsets, int L, int threads, int J) {
     int64_t n = 0;
-    for_each_tile(offsets, L, threads, J, [&](int32_t, int32_t, int32_t, int32_t) { ++n; });
+    for_each_tile(offsets, L, threads, J,
+                  [&](int32_t, int32_t, int, int, int32_t, int32_t, int32_t, int32_t) { ++n; });
     return n;
 }
 
 // Slot tables of halo tiles: tiles x threads forward slots (up to J halo
 // vehicles ahead of the owned ones, the first slot flagged as a lane head),
 // then tiles x threads backward slots (the owned vehicles, then up to J halo
-// vehicles behind them, the head flag only on a true lane head).
+// vehicles behind them, the head flag only on a true lane head).  Tile b of
+// the forward and tile b of the backward cover the same lane but may own
+// different vehicles.
 idm_status compute_tiles(const std::vector<int32_t> &offsets, int L, const Shape &sh, Layout &out) {
     const int NT = sh.threads, J = sh.tile;
     const int64_t nb = count_tiles(offsets, L, NT, J);
@@ -302,29 +312,31 @@ idm_status compute_tiles(const std::vector<int32_t> &offsets, int L, const Shape
     out.level.assign((size_t)nb, 0);
     out.level_start = {0, (int32_t)nb};
     int64_t b = 0;
-    for_each_tile(offsets, L, NT, J, [&](int32_t ls, int32_t le, int32_t lo, int32_t hi) {
-        int64_t s = b * NT;
-        const int32_t f0 = std::max<int32_t>(ls, lo - J);
-        for (int32_t i = f0; i < hi; ++i, ++s) {
-            out.gidx[(size_t)s] = i;
-            uint8_t f = SLOT_VALID;
-            if (i == f0) f |= SLOT_HEAD;
-            if (i >= lo) f |= SLOT_OWNED;
-            if (i == le - 1) f |= SLOT_TAIL;
-            out.flags[(size_t)s] = f;
-        }
-        s = (nb + b) * NT;
-        const int32_t b1 = (int32_t)std::min<int64_t>(le, (int64_t)hi + J);
-        for (int32_t i = lo; i < b1; ++i, ++s) {
-            out.gidx[(size_t)s] = i;
-            uint8_t f = SLOT_VALID;
-            if (i == ls) f |= SLOT_HEAD;
-            if (i < hi) f |= SLOT_OWNED;
-            if (i == le - 1) f |= SLOT_TAIL;
-            out.flags[(size_t)s] = f;
-        }
-        ++b;
-    });
+    for_each_tile(offsets, L, NT, J,
+                  [&](int32_t ls, int32_t le, int, int, int32_t flo, int32_t fhi, int32_t blo,
+                      int32_t bhi) {
+                      int64_t s = b * NT;
+                      const int32_t f0 = std::max<int32_t>(ls, flo - J);
+                      for (int32_t i = f0; i < fhi; ++i, ++s) {
+                          out.gidx[(size_t)s] = i;
+                          uint8_t f = SLOT_VALID;
+                          if (i == f0) f |= SLOT_HEAD;
+                          if (i >= flo) f |= SLOT_OWNED;
+                          if (i == le - 1) f |= SLOT_TAIL;
+                          out.flags[(size_t)s] = f;
+                      }
+                      s = (nb + b) * NT;
+                      const int32_t b1 = (int32_t)std::min<int64_t>(le, (int64_t)bhi + J);
+                      for (int32_t i = blo; i < b1; ++i, ++s) {
+                          out.gidx[(size_t)s] = i;
+                          uint8_t f = SLOT_VALID;
+                          if (i == ls) f |= SLOT_HEAD;
+                          if (i < bhi) f |= SLOT_OWNED;
+                          if (i == le - 1) f |= SLOT_TAIL;
+                          out.flags[(size_t)s] = f;
+                      }
+                      ++b;
+                  });
     return IDM_OK;
 }
 
@@ -559,8 +571,10 @@ idm_status choose_shape(const idm_plan *p, const idm_tuning *tu, Shape &sh) {
     const int KB_req = tu ? tu->block : 0;
     if (K <= 0) K = KB_req > 0 ? KB_req : 32;
     if (tu && (tu->threads || tu->per_thread)) {
-        // 768 threads: halo tiles only (checked below)
-        if (!(valid_threads(tu->threads) || (tu->threads == 768 && tu->tile_steps > 0)) ||
+        // 576, 640 and 768 threads: halo tiles only (checked below)
+        const bool tile_threads =
+            tu->threads == 576 || tu->threads == 640 || tu->threads == 768;
+        if (!(valid_threads(tu->threads) || (tile_threads && tu->tile_steps > 0)) ||
             !valid_per_thread(tu->per_thread))
             return fail(IDM_ERR_UNSUPPORTED, "tuning threads=%d per_thread=%d not supported",
                         tu->threads, tu->per_thread);
@@ -611,12 +625,10 @@ idm_status choose_shape(const idm_plan *p, const idm_tuning *tu, Shape &sh) {
         if (!sh.stored)
             return fail(IDM_ERR_UNSUPPORTED, "halo tiles (tile_steps %d) need store_states = 1",
                         sh.tile);
-        if (!(tu->threads == 256 || tu->threads == 512 || tu->threads == 768 ||
-              tu->threads == 1024) ||
-            tu->per_thread != 1)
+        if (!forward_tiled_kernel(p->pb.bound, tu->threads) || tu->per_thread != 1)
             return fail(IDM_ERR_UNSUPPORTED,
-                        "halo tiles need threads of 256, 512, 768 or 1024 and per_thread = 1 in "
-                        "the tuning; got %d x %d",
+                        "halo tiles need threads of 256, 512, 576, 640, 768 or 1024 and "
+                        "per_thread = 1 in the tuning; got %d x %d",
                         tu->threads, tu->per_thread);
         if (sh.tile >= sh.threads || sh.tile % 2 != 0 || sh.tile % K != 0)
             return fail(IDM_ERR_UNSUPPORTED,
@@ -1608,11 +1620,12 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
     // halo tiles (kept states, one vehicle per thread) where a lane is longer
     // than a tile's owned part: J steps per launch, J a multiple of the plan's K
     if (p->store_pref >= 1) {
-        const int tile_cands[][2] = {{256, 64}, {256, 128}, {512, 128}, {512, 256},
-                                     {768, 256}, {1024, 128}, {1024, 256}};
+        const int tile_cands[][2] = {{256, 64},  {256, 128}, {512, 128}, {512, 256},
+                                     {576, 128}, {640, 128}, {640, 256}, {768, 256},
+                                     {1024, 256}};
         for (const auto &tc : tile_cands) {
             const int t = tc[0], J = tc[1];
-            if (p->max_lane <= t - J || J % p->sh.K != 0) continue;
+            if (p->max_lane <= t || J % p->sh.K != 0) continue;
             const int64_t nt = count_tiles(p->offsets, p->pb.n_lanes, t, J);
             if (ws_total(p, dims(p->sh.K, 0, true, nt)) > ws_bytes) continue;
             if (!forward_tiled_kernel(p->pb.bound, t) ||
@@ -1632,6 +1645,13 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
     if (cands.empty()) cands.swap(spilling);
     if (cands.empty()) return fail(IDM_ERR_WORKSPACE, "no launch shape fits the workspace");
     const Shape orig = p->sh;
+    // every candidate is timed as replays of its captured forward + backward
+    // (the way the step and fit graphs run it: a shape with more launches per
+    // pass pays only their in-graph gaps), on the caller's stream or, for the
+    // null stream, the plan's side stream
+    hipStream_t gs = nullptr;
+    r = graph_stream_enter(p, s, &gs);
+    if (r != IDM_OK) return r;
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
@@ -1658,17 +1678,17 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
             r = build_layout(p, s2);
             if (r != IDM_OK) continue;
             if (persistent && p->n_bundles <= s2.grid) continue;  // same as non-persistent
-            r = run_step(p, a, s);  // warm-up
+            hipGraphExec_t ex = nullptr;
+            r = capture(gs, &ex, [&]() { return run_step(p, a, gs); });
             if (r != IDM_OK) break;
-            hipEventRecord(e0, s);
-            for (int i = 0; i < reps; ++i) {
-                r = run_step(p, a, s);
-                if (r != IDM_OK) break;
-            }
-            hipEventRecord(e1, s);
-            hipError_t he = hipEventSynchronize(e1);
-            if (r != IDM_OK || he != hipSuccess) {
-                if (he != hipSuccess) r = hip_fail(he, "autotune timing");
+            hipError_t he = hipGraphLaunch(ex, gs);  // warm-up
+            if (he == hipSuccess) he = hipEventRecord(e0, gs);
+            for (int i = 0; i < reps && he == hipSuccess; ++i) he = hipGraphLaunch(ex, gs);
+            if (he == hipSuccess) he = hipEventRecord(e1, gs);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            hipGraphExecDestroy(ex);
+            if (he != hipSuccess) {
+                r = hip_fail(he, "autotune timing");
                 break;
             }
             float ms = 0.0f;
@@ -1683,6 +1703,8 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     idm_status r2 = build_layout(p, r == IDM_OK ? best_sh : orig);
+    if (r != IDM_OK) return r;
+    r = graph_stream_leave(p, s);
     if (r != IDM_OK) return r;
     if (r2 == IDM_OK) {
         std::lock_guard<std::mutex> lock(g_tune_mu);

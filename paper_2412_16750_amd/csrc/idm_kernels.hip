@@ -99,7 +99,7 @@ __device__ __forceinline__ int follow_thread(int t) {
     if constexpr ((NT & (NT - 1)) == 0)
         return (t + 1) & (NT - 1);
     else
-        return t + 1 < NT ? t + 1 : 0;  // the 768-thread halo tiles
+        return t + 1 < NT ? t + 1 : 0;  // halo tiles of 576, 640 or 768 threads
 }
 
 // Boundary rows of bundle `bidx` (uniform): the external leader's states and
@@ -1661,17 +1661,17 @@ KernelFn backward_stored_kernel(int mode, int per_thread, int threads, bool dens
         return dense ? (KernelFn)&k_backward_stored<M, 1, NT, true, true>        \
                      : (KernelFn)&k_backward_stored<M, 1, NT, false, true>;
 #if IDM_PART == 10
-// 768 threads: a 1000-vehicle lane in two tiles of 500 owned vehicles with
-// J = 256 uses at most 756 slots, and twelve waves instead of sixteen share
-// the compute unit
+// 576, 640 and 768 threads: a work-group only as wide as the tile needs
+// (a 1000-vehicle lane in two tiles takes at most 564 slots at J = 128 and
+// 628 at J = 256), since every wave of a work-group runs every step, padding
+// or not
+#define IDM_TILE_NT(X, M) X(M, 256) X(M, 512) X(M, 576) X(M, 640) X(M, 768) X(M, 1024)
 KernelFn forward_tiled_kernel(int mode, int threads) {
-    IDM_TILE_CASE(0, 256) IDM_TILE_CASE(0, 512) IDM_TILE_CASE(0, 768) IDM_TILE_CASE(0, 1024)
-    IDM_TILE_CASE(1, 256) IDM_TILE_CASE(1, 512) IDM_TILE_CASE(1, 768) IDM_TILE_CASE(1, 1024)
+    IDM_TILE_NT(IDM_TILE_CASE, 0) IDM_TILE_NT(IDM_TILE_CASE, 1)
     return nullptr;
 }
 KernelFn backward_tiled_kernel(int mode, int threads, bool dense) {
-    IDM_TILE_BWD(0, 256) IDM_TILE_BWD(0, 512) IDM_TILE_BWD(0, 768) IDM_TILE_BWD(0, 1024)
-    IDM_TILE_BWD(1, 256) IDM_TILE_BWD(1, 512) IDM_TILE_BWD(1, 768) IDM_TILE_BWD(1, 1024)
+    IDM_TILE_NT(IDM_TILE_BWD, 0) IDM_TILE_NT(IDM_TILE_BWD, 1)
     return nullptr;
 }
 #endif

@@ -154,63 +154,69 @@ def _tile_layout(L, offsets, threads, J, K=16, S=100):
 
 
 @pytest.mark.parametrize("threads, J, K", [(256, 64, 16), (512, 128, 32), (256, 32, 16),
-                                           (1024, 256, 32), (512, 64, 64), (768, 256, 32)])
+                                           (1024, 256, 32), (512, 64, 64), (768, 256, 32),
+                                           (640, 256, 32), (576, 128, 32)])
 def test_halo_tile_layout(L, threads, J, K):
-    """Halo tiles (Sec. III-B: a step moves information one vehicle): every
-    vehicle is owned by exactly one tile; a tile owns at most threads - J
-    consecutive vehicles of one lane; its forward slots add up to J vehicles
-    ahead (fewer only where the lane starts), the first slot flagged as a
-    lane head; its backward slots are the owned vehicles and up to J behind
-    (fewer only where the lane ends), flagged as a head only on a true lane
-    head; a lane of at most threads - J vehicles is one tile, a longer one
-    ceil(n / (threads - J)) tiles; the workspace adds the
-    carried adjoints and sums (68 B per vehicle) to the kept states."""
+    """Halo tiles (Sec. III-B: a step moves information one vehicle).  In each
+    direction every vehicle is owned by exactly one tile, and a tile's owned
+    vehicles are consecutive vehicles of one lane; its forward slots are up
+    to J vehicles ahead (fewer only where the lane starts, the first slot
+    flagged as a lane head) and the owned ones; its backward slots the owned
+    ones and up to J behind (fewer only where the lane ends, flagged as a
+    head only on a true lane head).  A lane of at most `threads` vehicles is
+    one tile; a longer one is cut into m = ceil((n - J) / (threads - J))
+    tiles, tile b of the forward and of the backward on the same lane, their
+    slot counts within one of each other in each direction and never above
+    `threads`.  The workspace adds the carried adjoints and sums (68 B per
+    vehicle) to the kept states."""
     import scenarios
     sizes = scenarios.lognormal_lane_sizes(300, np.log(threads) + 0.3, 1.0, 1, 6 * threads, 41)
-    sizes[[2, 9, 17, 30]] = [threads, threads + 1, 5 * threads, threads - J]
+    sizes[[2, 9, 17, 30, 31]] = [threads, threads + 1, 5 * threads, threads - J, 2 * threads - J]
     sizes[::37] = 0
     off = scenarios.offsets_from_sizes(sizes)
     S = 100
     info, ws, gidx, flags = _tile_layout(L, off, threads, J, K=K, S=S)
     N = int(off[-1])
+    sz = np.asarray(sizes, dtype=np.int64)
+    need = np.where(sz > threads, -(-(sz - J) // (threads - J)), np.minimum(sz, 1))
     lane_of = np.repeat(np.arange(len(sizes)), sizes)
-    owned_all = []
+    owned = {0: [], 1: []}
     tiles_of_lane = np.zeros(len(sizes), dtype=np.int64)
-    tiles_need = -(-np.asarray(sizes) // (threads - J))
+    counts = {}
     for b in range(info.n_bundles):
-        gf, ff = gidx[0, b], flags[0, b]
-        gb, fb = gidx[1, b], flags[1, b]
-        kf, kb = int(np.sum(gf >= 0)), int(np.sum(gb >= 0))
-        assert np.all(gf[kf:] == -1) and np.all(ff[kf:] == 0)
-        assert np.all(gb[kb:] == -1) and np.all(fb[kb:] == 0)
-        seg_f, seg_b = gf[:kf], gb[:kb]
-        lane = lane_of[seg_f[0]]
-        tiles_of_lane[lane] += 1
-        ls, le = off[lane], off[lane + 1]
-        assert np.array_equal(seg_f, np.arange(seg_f[0], seg_f[0] + kf))
-        assert np.array_equal(seg_b, np.arange(seg_b[0], seg_b[0] + kb))
-        own_f = seg_f[(ff[:kf] & 8) != 0]
-        own_b = seg_b[(fb[:kb] & 8) != 0]
-        assert np.array_equal(own_f, own_b) and len(own_f) >= 1
-        lo, hi = int(own_f[0]), int(own_f[-1]) + 1
-        assert np.array_equal(own_f, np.arange(lo, hi))
-        assert ls <= lo and hi <= le
-        if le - ls > threads - J:
-            assert hi - lo <= threads - J and tiles_need[lane] > 1
-        else:
-            assert (lo, hi) == (ls, le)
-        # forward: halo ahead, then owned; head flag on the first slot only
-        assert seg_f[0] == max(ls, lo - J) and seg_f[-1] == hi - 1
-        assert (ff[0] & 1) and not np.any(ff[1:kf] & 1)
-        # backward: owned, then the halo behind; head flag only on a lane head
-        assert seg_b[0] == lo and seg_b[-1] == min(le, hi + J) - 1
-        heads = seg_b[(fb[:kb] & 1) != 0]
-        assert np.array_equal(heads, [ls] if lo == ls else [])
-        owned_all.append(own_f)
-    owned_all = np.concatenate(owned_all)
-    assert np.array_equal(tiles_of_lane, tiles_need)
-    assert np.array_equal(np.sort(owned_all), np.arange(N))
-    assert len(owned_all) == N
+        lanes = []
+        for d in (0, 1):
+            g, f = gidx[d, b], flags[d, b]
+            k = int(np.sum(g >= 0))
+            assert 1 <= k <= threads
+            assert np.all(g[k:] == -1) and np.all(f[k:] == 0)
+            seg = g[:k]
+            assert np.array_equal(seg, np.arange(seg[0], seg[0] + k))
+            lane = lane_of[seg[0]]
+            assert lane_of[seg[-1]] == lane
+            lanes.append(lane)
+            ls, le = off[lane], off[lane + 1]
+            own = seg[(f[:k] & 8) != 0]
+            assert len(own) >= 1
+            lo, hi = int(own[0]), int(own[-1]) + 1
+            assert np.array_equal(own, np.arange(lo, hi))
+            if d == 0:   # halo ahead, then owned; head flag on the first slot only
+                assert seg[0] == max(ls, lo - J) and seg[-1] == hi - 1
+                assert (f[0] & 1) and not np.any(f[1:k] & 1)
+            else:        # owned, then the halo behind; head flag only on a lane head
+                assert seg[0] == lo and seg[-1] == min(le, hi + J) - 1
+                heads = seg[(f[:k] & 1) != 0]
+                assert np.array_equal(heads, [ls] if lo == ls else [])
+            owned[d].append(own)
+            counts.setdefault((lane, d), []).append(k)
+        assert lanes[0] == lanes[1]
+        tiles_of_lane[lanes[0]] += 1
+    assert np.array_equal(tiles_of_lane, need)
+    for d in (0, 1):
+        o = np.concatenate(owned[d])
+        assert len(o) == N and np.array_equal(np.sort(o), np.arange(N))
+    for (lane, d), ks in counts.items():
+        assert max(ks) - min(ks) <= 1, (lane, d, ks)
     align = lambda x: (x + 255) // 256 * 256
     nt = info.n_bundles
     expect = (align(8 * nt) + align(16 * nt) + align(8 * 7 * N) + 2 * align((S + 1) * 4 * N)
@@ -220,8 +226,9 @@ def test_halo_tile_layout(L, threads, J, K):
 
 def test_halo_tile_tuning_limits(L):
     """Halo tiles need kept states, one vehicle per thread, explicit threads of
-    256, 512, 768 or 1024 (768 for tiles only), an even J that is a multiple
-    of K and below the work-group, and one work-group per tile."""
+    256, 512, 576, 640, 768 or 1024 (576, 640 and 768 for tiles only), an
+    even J that is a multiple of K and below the work-group, and one
+    work-group per tile."""
     off = [0, 3000, 3500]
     ok = (512, 1, 32, 0, 0, 1, 64)
     assert _check(L, off, tuning=ok, K=32)[0] == 0
@@ -237,8 +244,10 @@ def test_halo_tile_tuning_limits(L):
         st = _check(L, off, tuning=bad, K=32)[0]
         assert st == -3, (bad, st)
     assert _check(L, off, tuning=(512, 1, 32, 0, 0, 1, -64), K=32)[0] == -1
-    assert _check(L, off, tuning=(768, 1, 32, 0, 0, 1, 256), K=32)[0] == 0
-    assert _check(L, off, tuning=(768, 1, 32, 0, 0, 1, 0), K=32)[0] == -3
+    for t in (576, 640, 768):
+        assert _check(L, off, tuning=(t, 1, 32, 0, 0, 1, 256), K=32)[0] == 0
+        assert _check(L, off, tuning=(t, 1, 32, 0, 0, 1, 0), K=32)[0] == -3
+    assert _check(L, off, tuning=(384, 1, 32, 0, 0, 1, 128), K=32)[0] == -3
 
 
 def test_backward_entry_points_reject_null_arguments(L):

@@ -77,10 +77,12 @@ def _tiled(threads, J, K):
 
 @pytest.mark.parametrize("mode", [MODE_SOFTPLUS, MODE_CLAMP])
 @pytest.mark.parametrize("shape", [(256, 64, 16), (512, 128, 32), (256, 32, 32),
-                                   (1024, 256, 32), (768, 256, 32)])
+                                   (1024, 256, 32), (768, 256, 32), (640, 256, 32),
+                                   (576, 128, 32)])
 def test_tiles_bitwise_equal_whole_lanes(mode, shape):
-    """Lanes of 1 to 3000 vehicles (exactly a work-group, one more, one tile's
-    owned count, several tiles), S = 203 (a ragged last block of J and of K),
+    """Lanes of 1 to 3000 vehicles (exactly a work-group, one more, a
+    work-group less the halo, several tiles), S = 203 (a ragged last block of
+    J and of K),
     fused MSE on every 5th step plus a dense upstream gradient: equal to the
     default plan (whole lanes, lanes above 1024 cut into pieces) with the
     same K; the oracle on the tiled result."""
