@@ -56,14 +56,14 @@ PAPER_FWD_BWD_VEH_STEPS_PER_S = 2.0e6 / 0.060
 # source as the traffic figures; per headline mode (the backward from stored
 # states with its forward writing both rows, or the checkpointed pair).
 COUNTERS = {
-    "stored": {"traffic_bwd": 2.6629e+09, "traffic_fwd": 1.7825e+09,
-               "valu_busy_bwd": 0.704, "valu_per_wave_step_bwd": 74.8, "clock_bwd": 2.309,
-               "valu_busy_fwd": 0.512, "valu_per_wave_step_fwd": 37.0, "clock_fwd": 2.371},
-    "checkpointed": {"traffic_bwd": 1.2374e+09, "traffic_fwd": 9.8230e+08,
+    "stored": {"traffic_bwd": 2.6631e+09, "traffic_fwd": 1.7825e+09,
+               "valu_busy_bwd": 0.696, "valu_per_wave_step_bwd": 74.8, "clock_bwd": 2.343,
+               "valu_busy_fwd": 0.509, "valu_per_wave_step_fwd": 37.0, "clock_fwd": 2.400},
+    "checkpointed": {"traffic_bwd": 1.2380e+09, "traffic_fwd": 9.8223e+08,
                      "valu_busy_bwd": 0.839, "valu_per_wave_step_bwd": 118.3, "clock_bwd": 2.350,
-                     "valu_busy_fwd": 0.929, "valu_per_wave_step_fwd": 36.5, "clock_fwd": 2.317},
+                     "valu_busy_fwd": 0.928, "valu_per_wave_step_fwd": 36.5, "clock_fwd": 2.319},
 }
-TRAFFIC_KERNEL_SHA256 = "a782db34f25e0784daf398ac4996e452b5bb02f416d4bed7e8eb292845511f78"
+TRAFFIC_KERNEL_SHA256 = "5e9ff5e3573633ba8062167c4bb1b1e79cbafed87534d057b492ffef5a7a37ef"
 
 
 # Warm-start network training: Adam over 1M pairs, batch 4096, learning rate
