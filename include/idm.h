@@ -88,7 +88,7 @@ typedef struct {
  * workspace.  Results do not depend on the cut (the same arithmetic in the
  * same order).  The default is 1024 threads x 1 for lanes above 1024. */
 typedef struct {
-    int32_t threads;    /* 64, 128, 256, 512 or 1024 (768 with halo tiles) */
+    int32_t threads;    /* 64, 128, 256, 512 or 1024 (576, 640, 768 with halo tiles) */
     int32_t per_thread; /* vehicles per thread: 1, 2 or 4 */
     int32_t ckpt_every; /* K, overrides the problem's K when > 0 */
     int32_t grid;       /* >0: persistent grid of that many work-groups walking the bundle
@@ -110,16 +110,18 @@ typedef struct {
                            backwards (the kept states only where the workspace it is given
                            holds them) and keep the faster */
     int32_t tile_steps;   /* J > 0: halo tiles (needs store_states 1, one vehicle per thread and
-                           explicit threads of 256, 512, 768 (tiles only) or 1024; J even, a
-                           multiple of K and below threads; grid 0).  A lane longer than
-                           threads - J vehicles is cut into ceil(n / (threads - J)) tiles of
-                           nearly equal owned parts, one work-group each (a shorter lane is one
-                           tile), and the steps into blocks of J run as successive launches: a
-                           tile also simulates the J vehicles ahead of its own in the forward and
-                           the J behind them in the backward, so that information, which moves
-                           one vehicle per step (Sec. III-B's synchronous update), cannot reach
-                           its owned vehicles from outside within a launch.  Owned results equal
-                           the whole-lane kernels' bit for bit.  For few long lanes, whose
+                           explicit threads of 256, 512, 576, 640, 768 (those three for tiles
+                           only) or 1024; J even, a multiple of K and below threads; grid 0).  A
+                           lane of n > threads vehicles is cut into the fewest tiles that hold
+                           it, ceil((n - J) / (threads - J)), one work-group each (a shorter lane
+                           is one tile), and the steps into blocks of J run as successive
+                           launches: a tile also simulates up to J vehicles ahead of its own in
+                           the forward and up to J behind them in the backward (each direction
+                           splits the lane on its own: the lane head needs no halo ahead, the
+                           tail none behind), so that information, which moves one vehicle per
+                           step (Sec. III-B's synchronous update), cannot reach its owned
+                           vehicles from outside within a launch.  Owned results equal the
+                           whole-lane kernels' bit for bit.  For few long lanes, whose
                            work-groups leave most compute units idle.  With store_states 2 the
                            autotuner also times tile shapes; 0: whole lanes */
 } idm_tuning;
