@@ -1,6 +1,8 @@
 """The device-side trajectory fit (idm_fit_init / idm_fit_step / idm_fit_run)
 against the oracle's gradient + Adam step, graph replay against eager steps,
 and convergence on a small problem."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -25,11 +27,11 @@ def _problem(sizes=(30, 20, 1, 12), S=200, every=10, seed_c=4):
     return sc, steps, tgt
 
 
-def _fitter(sc, steps, tgt, lr=1e-2, **kw):
+def _fitter(sc, steps, tgt, lr=1e-2, plan_kw=None, **kw):
     import torch
     from paper_2412_16750_amd import sim
     from paper_2412_16750_amd.fit import Fitter
-    plan = sim.Plan.for_scenario(sc)
+    plan = sim.Plan.for_scenario(sc, **(plan_kw or {}))
     x = device_inputs(sc)
     obs = sim.Obs(torch.from_numpy(tgt).cuda(), int(steps[0]), int(steps[1] - steps[0]))
     f = Fitter(plan, x["length"], x["p0"], x["v"], obs, lr0=lr, **kw)
@@ -176,21 +178,14 @@ def test_scheduled_fit_matches_oracle_over_eight_steps(raw_units):
     assert lr_at(n + 1, lr0, lr1, n) == pytest.approx(lr1) and lr_at(1, lr0, lr1, n) == lr0
 
 
-def test_first_fit_step_on_the_full_fit_workload_sampled_lanes():
-    """The fit workload at full size (100 lanes x 1000 vehicles, 500 steps,
-    observed every 10th step) in the launch configuration the benchmark times:
-    after one fit step from the box midpoints, the Adam first moment of three
-    sampled lanes equals (1 - beta1) times the oracle's gradient of the same
-    loss (normalised over all 100,000 vehicles), element by element, and the
-    loss matches."""
-    import torch
+@functools.lru_cache(maxsize=1)
+def _full_fit_reference():
+    """The oracle's side of the full fit workload test: the Adam first moment
+    after one step from the box midpoints on three sampled lanes, and the loss
+    over all 100,000 vehicles."""
     sc = scenarios.fit()
     steps = scenarios.obs_steps(sc.n_steps, sc.extra["obs_first"], sc.extra["obs_stride"])
     tgt = scenarios.constant_speed_targets(sc, steps, 44)
-    f, x = _fitter(sc, steps, tgt)
-    f.init(_cold(sc.n, MID))
-    f.step()
-    torch.cuda.synchronize()
     lanes = [0, 57, 99]
     sub = scenarios.subset_lanes(sc, lanes)
     idx = sub.extra["vehicle_index"]
@@ -198,18 +193,41 @@ def test_first_fit_step_on_the_full_fit_workload_sampled_lanes():
     prm["length"] = sub.params["length"]
     pb = oracle.Problem.from_scenario(sub, params=prm)
     P, V, _, _ = oracle.forward(pb)
-    loss_sub, gP = oracle.mse(P, steps, tgt[:, idx].astype(np.float64))
+    _, gP = oracle.mse(P, steps, tgt[:, idx].astype(np.float64))
     g, _, _ = oracle.adjoint(pb, P, V, gP)
     fac = sub.n / sc.n  # the loss is normalised over all N vehicles
     m_ref = 0.1 * g * fac * (BOX_HI - BOX_LO)[:, None]
-    m_gpu = f.m.double().cpu().numpy()[:, idx]
-    ok, w = grad_close(m_gpu, m_ref)
-    log("full fit workload, step 1: Adam first moment on lanes %s worst/limit %.3f" % (lanes, w))
-    assert ok
-    # the loss over all 100,000 vehicles (oracle forward of every lane)
     prm_all = {k: np.full(sc.n, MID[i], np.float32) for i, k in enumerate(oracle.PARAM_NAMES)}
     prm_all["length"] = sc.params["length"]
     P_all, _, _, _ = oracle.forward(oracle.Problem.from_scenario(sc, params=prm_all))
     loss_all, _ = oracle.mse(P_all, steps, tgt.astype(np.float64))
-    log("full fit workload, step 1: loss gpu %.9e oracle %.9e" % (f.losses()[0], loss_all))
+    return sc, steps, tgt, lanes, idx, m_ref, loss_all
+
+
+@pytest.mark.parametrize("plan_kw", [
+    {},
+    dict(store_states=True, threads=640, per_thread=1, tile_steps=256),
+    dict(store_states=True, threads=256, per_thread=1, tile_steps=64)],
+    ids=["checkpoints", "tiles640x256", "tiles256x64"])
+def test_first_fit_step_on_the_full_fit_workload_sampled_lanes(plan_kw):
+    """The fit workload at full size (100 lanes x 1000 vehicles, 500 steps,
+    observed every 10th step) in the launch configurations the benchmark times
+    (the default plan, and the halo tiles its autotuner picks among): after
+    one fit step from the box midpoints, the Adam first moment of three
+    sampled lanes equals (1 - beta1) times the oracle's gradient of the same
+    loss (normalised over all 100,000 vehicles), element by element, and the
+    loss matches."""
+    import torch
+    sc, steps, tgt, lanes, idx, m_ref, loss_all = _full_fit_reference()
+    f, x = _fitter(sc, steps, tgt, plan_kw=plan_kw)
+    f.init(_cold(sc.n, MID))
+    f.step()
+    torch.cuda.synchronize()
+    m_gpu = f.m.double().cpu().numpy()[:, idx]
+    ok, w = grad_close(m_gpu, m_ref)
+    log("full fit workload %s, step 1: Adam first moment on lanes %s worst/limit %.3f"
+        % (plan_kw, lanes, w))
+    assert ok
+    log("full fit workload %s, step 1: loss gpu %.9e oracle %.9e" % (plan_kw, f.losses()[0],
+                                                                    loss_all))
     assert abs(f.losses()[0] - loss_all) <= 1e-4 * loss_all
