@@ -112,16 +112,16 @@ typedef struct {
     int32_t tile_steps;   /* J > 0: halo tiles (needs store_states 1, one vehicle per thread and
                            explicit threads of 256, 512, 576, 640, 768 (those three for tiles
                            only) or 1024; J even, a multiple of K and below threads; grid 0).  A
-                           lane of n > threads vehicles is cut into the fewest tiles that hold
-                           it, ceil((n - J) / (threads - J)), one work-group each (a shorter lane
-                           is one tile), and the steps into blocks of J run as successive
-                           launches: a tile also simulates up to J vehicles ahead of its own in
-                           the forward and up to J behind them in the backward (each direction
-                           splits the lane on its own: the lane head needs no halo ahead, the
-                           tail none behind), so that information, which moves one vehicle per
-                           step (Sec. III-B's synchronous update), cannot reach its owned
-                           vehicles from outside within a launch.  Owned results equal the
-                           whole-lane kernels' bit for bit.  For few long lanes, whose
+                           lane of n > threads vehicles is cut into the fewest tiles of at most
+                           threads - 1 slots that hold it, ceil((n - J) / (threads - 1 - J)), one
+                           work-group each (a shorter lane is one tile), and the steps into
+                           blocks of J run as successive launches: a tile also simulates up to J
+                           vehicles ahead of its own in the forward and up to J behind them in
+                           the backward (each direction splits the lane on its own: the lane head
+                           needs no halo ahead, the tail none behind), so that information, which
+                           moves one vehicle per step (Sec. III-B's synchronous update), cannot
+                           reach its owned vehicles from outside within a launch.  Owned results
+                           equal the whole-lane kernels' bit for bit.  For few long lanes, whose
                            work-groups leave most compute units idle.  With store_states 2 the
                            autotuner also times tile shapes; 0: whole lanes */
 } idm_tuning;

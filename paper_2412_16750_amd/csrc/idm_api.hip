@@ -252,10 +252,15 @@ struct Layout {
 
 // Halo tiles of T = `threads` slots advancing J steps per launch.  A lane of
 // n <= T vehicles is one tile (no halo).  A longer one is cut into the
-// fewest tiles that hold it, m = ceil((n - J) / (T - J)): the forward's first
-// tile (the lane head) and the backward's last (the lane tail) need no halo
-// on that side, so each direction splits the lane on its own, the m tiles'
-// slot counts (owned vehicles plus halo) as equal as integers allow.
+// fewest tiles of at most T - 1 slots that hold it, m = ceil((n - J) /
+// (T - 1 - J)): the forward's first tile (the lane head) and the backward's
+// last (the lane tail) need no halo on that side, so each direction splits
+// the lane on its own, the m tiles' slot counts (owned vehicles plus halo) as
+// equal as integers allow.  A cut tile never fills its work-group: in the
+// backward the last thread gathers the contribution of thread 0 (the slot
+// after it, modulo T), which is exactly zero only for padding or a lane
+// head, so the slot after a lane tail must be padding (a whole lane in one
+// tile starts with its head).
 // fn(lane start, lane end, tile j, m, forward owned [lo, hi), backward owned
 // [lo, hi)).
 template <class F>
@@ -268,7 +273,8 @@ void for_each_tile(const std::vector<int32_t> &offsets, int L, int threads, int 
             fn(s0, e0, 0, 1, s0, e0, s0, e0);
             continue;
         }
-        const int64_t m = (n - J + (threads - J) - 1) / (threads - J);
+        const int64_t cap = threads - 1;  // J < T, both even: cap - J >= 1
+        const int64_t m = (n - J + (cap - J) - 1) / (cap - J);
         const int64_t q = n + (m - 1) * J;  // slots over all tiles
         const int64_t base = q / m, rem = q % m;
         auto slots = [&](int64_t j) { return base + (j < rem ? 1 : 0); };

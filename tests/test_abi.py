@@ -164,21 +164,26 @@ def test_halo_tile_layout(L, threads, J, K):
     flagged as a lane head) and the owned ones; its backward slots the owned
     ones and up to J behind (fewer only where the lane ends, flagged as a
     head only on a true lane head).  A lane of at most `threads` vehicles is
-    one tile; a longer one is cut into m = ceil((n - J) / (threads - J))
+    one tile; a longer one is cut into m = ceil((n - J) / (threads - 1 - J))
     tiles, tile b of the forward and of the backward on the same lane, their
-    slot counts within one of each other in each direction and never above
-    `threads`.  The workspace adds the carried adjoints and sums (68 B per
-    vehicle) to the kept states."""
+    slot counts within one of each other in each direction and at most
+    threads - 1 (the slot after a cut tile's last vehicle is padding, whose
+    contribution to a lane tail the backward's last thread gathers).  The
+    workspace adds the carried adjoints and sums (68 B per vehicle) to the
+    kept states."""
     import scenarios
     sizes = scenarios.lognormal_lane_sizes(300, np.log(threads) + 0.3, 1.0, 1, 6 * threads, 41)
-    sizes[[2, 9, 17, 30, 31]] = [threads, threads + 1, 5 * threads, threads - J, 2 * threads - J]
+    # lane 40: n + (m - 1) J divisible by m with T slots per tile (a tile
+    # would exactly fill its work-group without the T - 1 cap)
+    sizes[[2, 9, 17, 30, 31, 40]] = [threads, threads + 1, 5 * threads, threads - J,
+                                     2 * threads - J, 3 * threads - 2 * J]
     sizes[::37] = 0
     off = scenarios.offsets_from_sizes(sizes)
     S = 100
     info, ws, gidx, flags = _tile_layout(L, off, threads, J, K=K, S=S)
     N = int(off[-1])
     sz = np.asarray(sizes, dtype=np.int64)
-    need = np.where(sz > threads, -(-(sz - J) // (threads - J)), np.minimum(sz, 1))
+    need = np.where(sz > threads, -(-(sz - J) // (threads - 1 - J)), np.minimum(sz, 1))
     lane_of = np.repeat(np.arange(len(sizes)), sizes)
     owned = {0: [], 1: []}
     tiles_of_lane = np.zeros(len(sizes), dtype=np.int64)
@@ -189,6 +194,8 @@ def test_halo_tile_layout(L, threads, J, K):
             g, f = gidx[d, b], flags[d, b]
             k = int(np.sum(g >= 0))
             assert 1 <= k <= threads
+            lane_n = int(sz[lane_of[g[0]]])
+            assert lane_n <= threads or k <= threads - 1
             assert np.all(g[k:] == -1) and np.all(f[k:] == 0)
             seg = g[:k]
             assert np.array_equal(seg, np.arange(seg[0], seg[0] + k))

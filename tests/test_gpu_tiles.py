@@ -81,13 +81,16 @@ def _tiled(threads, J, K):
                                    (576, 128, 32)])
 def test_tiles_bitwise_equal_whole_lanes(mode, shape):
     """Lanes of 1 to 3000 vehicles (exactly a work-group, one more, a
-    work-group less the halo, several tiles), S = 203 (a ragged last block of
-    J and of K),
+    work-group less the halo, several tiles, a lane whose even split would
+    fill every tile), S = 203 (a ragged last block of J and of K),
     fused MSE on every 5th step plus a dense upstream gradient: equal to the
     default plan (whole lanes, lanes above 1024 cut into pieces) with the
     same K; the oracle on the tiled result."""
     threads, J, K = shape
-    sizes = [1, 2, threads - J, threads, threads + 1, 600, 1000, 3000, 63, 0, 17, 2 * threads + 5]
+    # 3 T - 2 J: three tiles of exactly T slots without the T - 1 cap, the
+    # backward's tail tile then ending on the lane tail at the last thread
+    sizes = [1, 2, threads - J, threads, threads + 1, 600, 1000, 3000, 63, 0, 17, 2 * threads + 5,
+             3 * threads - 2 * J]
     sc = ragged_scenario(sizes, 203, mode=mode, ckpt_every=K)
     steps = np.arange(3, sc.n_steps + 1, 5)
     tgt = oracle_targets(sc, steps, c=3)
@@ -333,3 +336,33 @@ def test_tiles_step_graph_autograd_noalloc_and_forward_helper():
     for a, c in zip(outs[0], outs[1]):
         assert np.array_equal(a, c)
     assert np.array_equal(outs[1][3], ref.traj_d.cpu().numpy())
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_tiles_bitwise(seed):
+    """Random lane mixes, tile widths, halo lengths, step counts, checkpoint
+    intervals, bound modes and upstream kinds: halo tiles give the
+    trajectories, gradients and anomaly counts of the whole-lane plan with
+    the same K, bit for bit."""
+    rng = np.random.default_rng(300 + seed)
+    K = int(rng.choice([8, 16, 32]))
+    threads = int(rng.choice([256, 512, 576, 640, 768, 1024]))
+    Js = [j for j in range(K, threads, K) if j % 2 == 0 and j <= 256]
+    J = int(rng.choice(Js))
+    n = int(rng.integers(3, 20))
+    sizes = rng.integers(1, 3 * threads + 1, n)
+    sizes[rng.integers(0, n)] = int(2.5 * threads)       # at least one lane cut several times
+    S = int(rng.integers(1, 3 * J + 2))
+    mode = int(rng.integers(0, 2))
+    sc = ragged_scenario(sizes, S, mode=mode, seed_c=80 + seed, ckpt_every=K)
+    steps = np.arange(1, S + 1)
+    tgt = oracle_targets(sc, steps, c=80 + seed)
+    dense = None
+    if rng.integers(0, 2):
+        dense = np.random.default_rng(seed).normal(0, 1e-3, (S + 1, sc.n)).astype(np.float32)
+    t = _run(sc, steps, tgt, dense, **_tiled(threads, J, K))
+    ref = _run(sc, steps, tgt, dense, tuning_k=K)
+    log("random tiles seed %d: %d x J %d, K %d, S %d, mode %d, dense %s, %d tiles"
+        % (seed, threads, J, K, S, mode, dense is not None, t["info"]["n_bundles"]))
+    assert t["info"]["n_bundles"] > n
+    _same(t, ref, "seed %d" % seed)
