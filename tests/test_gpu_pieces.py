@@ -217,11 +217,13 @@ def test_autotuner_with_pieces():
         assert torch.equal(a, e)
 
 
-@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("seed", range(10))
 def test_random_cuts_bitwise(seed):
-    """Random lane mixes, bundle sizes, step counts, checkpoint intervals and
-    bound modes: lanes cut into pieces give the trajectories and gradients of
-    the same lanes held whole by 1024-slot bundles, bit for bit."""
+    """Random lane mixes, bundle sizes, step counts, checkpoint intervals,
+    bound modes and upstream kinds (targets, or targets and a dense upstream
+    gradient from seed 6 on): lanes cut into pieces give the trajectories
+    and gradients of the same lanes held whole by 1024-slot bundles, bit for
+    bit."""
     rng = np.random.default_rng(100 + seed)
     cap = int(rng.choice([64, 128, 256]))
     n = int(rng.integers(5, 40))
@@ -233,9 +235,12 @@ def test_random_cuts_bitwise(seed):
     sc = ragged_scenario(sizes, S, mode=mode, seed_c=60 + seed, ckpt_every=K)
     steps = np.arange(1, S + 1)
     tgt = oracle_targets(sc, steps, c=60 + seed)
-    whole = gpu_run(sc, steps, tgt, threads=1024, per_thread=1, block=8)
-    cut = gpu_run(sc, steps, tgt, threads=cap, per_thread=1, block=8)
-    log("random cut seed %d: cap %d, S %d, K %d, mode %d, levels %d" %
-        (seed, cap, S, K, mode, cut["info"]["n_levels"]))
+    dense = None
+    if seed >= 6:
+        dense = np.random.default_rng(seed).normal(0, 1e-3, (S + 1, sc.n)).astype(np.float32)
+    whole = gpu_run(sc, steps, tgt, dense, threads=1024, per_thread=1, block=8)
+    cut = gpu_run(sc, steps, tgt, dense, threads=cap, per_thread=1, block=8)
+    log("random cut seed %d: cap %d, S %d, K %d, mode %d, dense %s, levels %d" %
+        (seed, cap, S, K, mode, dense is not None, cut["info"]["n_levels"]))
     assert cut["info"]["n_levels"] >= 3
     _same(cut, whole, "seed %d" % seed)
