@@ -368,3 +368,31 @@ def test_stored_plan_graph_with_trajectory_outputs():
         # the program's own eager work between replays
         sim.idm_sim_forward(plan, x["prm"], x["length"], x["p0"], x["v"], other, None, None)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_stored_backward_bitwise(seed):
+    """Random lane mixes, launch shapes (1, 2 or 4 vehicles per thread), K,
+    step counts, observation schedules, bound modes and upstream kinds: the
+    backward from stored states equals the checkpointed one bit for bit."""
+    rng = np.random.default_rng(500 + seed)
+    threads = int(rng.choice([64, 128, 256, 512, 1024]))
+    per = int(rng.choice([1, 2, 4]))
+    K = int(rng.choice([8, 16] if per == 4 else [8, 16, 32]))
+    cap = threads * per
+    n = int(rng.integers(2, 30))
+    sizes = rng.integers(1, cap + 1, n)
+    S = int(rng.integers(1, 120))
+    first = int(rng.integers(1, min(S, 6) + 1))
+    stride = int(rng.integers(1, 8))
+    steps = np.arange(first, S + 1, stride)
+    mode = int(rng.integers(0, 2))
+    sc = ragged_scenario(sizes, S, mode=mode, seed_c=90 + seed, ckpt_every=K)
+    tgt = oracle_targets(sc, steps, c=90 + seed)
+    dense = None
+    if rng.integers(0, 2):
+        dense = np.random.default_rng(seed).normal(0, 1e-3, (S + 1, sc.n)).astype(np.float32)
+    out = _both(sc, steps, tgt, dense, threads=threads, per_thread=per, tuning_k=K)
+    log("random stored seed %d: %d x %d, K %d, S %d, obs %d:%d, mode %d, dense %s"
+        % (seed, threads, per, K, S, first, stride, mode, dense is not None))
+    _same(out, "seed %d" % seed)
