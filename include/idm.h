@@ -386,9 +386,10 @@ idm_status idm_step_graph_launch(idm_plan *plan, const idm_step_args *args, void
  * (threads x per_thread x KB, with K the problem's or, left free
  * (ckpt_every = 0 at plan creation), KB and 2 KB where the LDS stash exists;
  * with store_states 2 also the kept-state backward and halo tiles) whose
- * lanes fit and whose workspace fits in `workspace_bytes`, as `reps` replays
- * of the candidate's captured forward + backward graph (after one untimed
- * replay), on the real inputs, and switches the plan to the fastest.  The choice
+ * lanes fit and whose workspace fits in `workspace_bytes`, as the best of
+ * three batches of `reps` replays of the candidate's captured forward +
+ * backward graph (after `reps` untimed ones), on the real inputs, and
+ * switches the plan to the fastest.  The choice
  * is cached for the process, keyed by the sorted lane sizes (the lane-size
  * histogram), S, the bound mode, the kind of upstream gradient, a fixed K
  * and the device's compute-unit count: a later call for an equal problem
