@@ -1623,8 +1623,9 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
                 }
             }
         }
-    // halo tiles (kept states, one vehicle per thread) where a lane is longer
-    // than a tile's owned part: J steps per launch, J a multiple of the plan's K
+    // halo tiles (kept states, one vehicle per thread) where some lane is
+    // longer than the work-group (shorter lanes are one tile each, which only
+    // adds launches): J steps per launch, J a multiple of the plan's K
     if (p->store_pref >= 1) {
         const int tile_cands[][2] = {{256, 64},  {256, 128}, {512, 128}, {512, 256},
                                      {576, 128}, {640, 128}, {640, 256}, {768, 256},
