@@ -343,6 +343,64 @@ def test_information_moves_one_vehicle_per_step(mode, J):
     assert gv0s[off + b - a - 1] != gv0[b - 1]
 
 
+@pytest.mark.parametrize("mode", [MODE_SOFTPLUS, MODE_CLAMP])
+def test_halo_tiles_reproduce_the_lane_oracle(mode):
+    """The halo-tile scheme carried out on the oracle itself (R25): one lane
+    of 70 vehicles cut into tiles owning [0, 25), [25, 50), [50, 70), the 37
+    steps into blocks of J = 8.  Forward: each block restarts every tile from
+    the states its owners reached at the block's first step, simulating J
+    vehicles ahead of the owned ones (the first of them as a free-road head).
+    Adjoint, blocks from the last to the first: each tile runs the oracle's
+    adjoint on the exact states of its owned vehicles, their leader and J
+    followers, seeded at the block's last step with the adjoints the owners
+    carried out of the block above (the upstream of the block's steps below
+    it as given).  The owned states and the initial-state adjoints equal the
+    whole-lane oracle's bit for bit, the parameter gradients (summed over the
+    blocks in another association) to 1e-12."""
+    import scenarios
+    pb = Problem.from_scenario(scenarios.single_lane(n_vehicles=70, n_steps=37, mode=mode))
+    P, V, _, _ = oracle.forward(pb)
+    n, S, J = pb.n, pb.n_steps, 8
+    rng = np.random.default_rng(7)
+    gP = rng.normal(0.0, 1.0, (S + 1, n))
+    gV = rng.normal(0.0, 1.0, (S + 1, n))
+    g, gp0, gv0 = oracle.adjoint(pb, P, V, gP, gV)
+    owned = [(0, 25), (25, 50), (50, 70)]
+    blocks = [(k, min(S, k + J)) for k in range(0, S, J)]
+    # forward, block by block
+    Pt = np.full_like(P, np.nan)
+    Vt = np.full_like(V, np.nan)
+    Pt[0], Vt[0] = P[0], V[0]
+    for k0, k1 in blocks:
+        for lo, hi in owned:
+            first = max(0, lo - J)
+            sub = _sub_lane(pb, Pt, Vt, first, hi, k0, k1 - k0)
+            Ps, Vs, _, _ = oracle.forward(sub)
+            Pt[k0 + 1:k1 + 1, lo:hi] = Ps[1:, lo - first:]
+            Vt[k0 + 1:k1 + 1, lo:hi] = Vs[1:, lo - first:]
+    assert np.array_equal(Pt, P) and np.array_equal(Vt, V)
+    # adjoint, from the last block to the first; lam holds every vehicle's
+    # adjoint of (p, v) at the current block boundary
+    lam_p, lam_v = gP[S].copy(), gV[S].copy()
+    gt = np.zeros_like(g)
+    for k0, k1 in reversed(blocks):
+        new_p, new_v = np.full(n, np.nan), np.full(n, np.nan)
+        for lo, hi in owned:
+            first, last = max(0, lo - 1), min(n, hi + J)
+            idx = np.arange(first, last)
+            sub = _sub_lane(pb, P, V, first, last, k0, k1 - k0)
+            up_p = gP[k0:k1 + 1, idx].copy()
+            up_v = gV[k0:k1 + 1, idx].copy()
+            up_p[-1], up_v[-1] = lam_p[idx], lam_v[idx]   # carried out of the block above
+            gs, ps, vs = oracle.adjoint(sub, P[k0:k1 + 1, idx], V[k0:k1 + 1, idx], up_p, up_v)
+            own = slice(lo - first, hi - first)
+            new_p[lo:hi], new_v[lo:hi] = ps[own], vs[own]
+            gt[:, lo:hi] += gs[:, own]
+        lam_p, lam_v = new_p, new_v
+    assert np.array_equal(lam_p, gp0) and np.array_equal(lam_v, gv0)
+    np.testing.assert_allclose(gt, g, rtol=1e-12, atol=1e-12 * np.abs(g).max())
+
+
 def test_lanes_are_independent_bitwise():
     """Two lanes simulated together equal each simulated alone."""
     a = _harsh(MODE_SOFTPLUS, n=10, seed=1)
