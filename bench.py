@@ -677,13 +677,14 @@ def batched_report(dev, log_fn, reps: int = 10) -> dict:
                         workspace_bytes=room)
     vsteps = float(sc.n) * sc.n_steps
 
-    def timed():
-        sim.idm_step_graph_launch(b)          # capture (first use) + warm-up
+    def timed(bb=None):
+        bb = b if bb is None else bb
+        sim.idm_step_graph_launch(bb)          # capture (first use) + warm-up
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            sim.idm_step_graph_launch(b)
+            sim.idm_step_graph_launch(bb)
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
@@ -705,6 +706,26 @@ def batched_report(dev, log_fn, reps: int = 10) -> dict:
     again = sim.idm_plan_autotune(b2, reps=2)
     again_s = time.perf_counter() - t0
     del b2, plan2
+    # halo tiles keeping every step's states (7.2 GB here), and the autotuner
+    # given room for them; lanes up to the work-group share tiles
+    tile_kw = dict(store_states=True, threads=1024, per_thread=1, tuning_k=32, tile_steps=256)
+    plan_t = sim.Plan.for_scenario(sc, **tile_kw)
+    room_t = plan_t.workspace_bytes
+    bt = sim.StepBuffers(plan_t, x["prm"], x["length"], x["p0"], x["v"], traj_d=traj, obs=obs)
+    ms_tiles = timed(bt)
+    tiles = {"shape": "1024 threads, J = 256, K = 32", "tiles": plan_t.info()["n_bundles"],
+             "ms": ms_tiles, "loss": bt.loss.item()}
+    del bt, plan_t
+    plan_a = sim.Plan.for_scenario(sc, store_states="auto")
+    ba = sim.StepBuffers(plan_a, x["prm"], x["length"], x["p0"], x["v"], traj_d=traj, obs=obs,
+                         workspace_bytes=max(room, room_t))
+    picked = sim.idm_plan_autotune(ba, reps=2)
+    tiles["autotuned_with_room_for_tiles"] = {k: picked[k] for k in keep + ("store_states",
+                                                                           "tile_steps")}
+    del ba, plan_a
+    torch.cuda.empty_cache()
+    log_fn("bench: uneven halo tiles %s: %.3f ms; autotuner given room for them: %s"
+           % (tiles["shape"], ms_tiles, tiles["autotuned_with_room_for_tiles"]))
     sizes = np.diff(sc.lane_offsets)
     log_fn("bench: uneven %d lanes, %d vehicles: default %s %.3f ms, autotuned %s %.3f ms"
            % (sc.n_lanes, sc.n, default_info, ms_default, tuned_info, ms_tuned))
@@ -720,6 +741,7 @@ def batched_report(dev, log_fn, reps: int = 10) -> dict:
                                "same_shape": {k: again[k] for k in keep} == tuned_info},
             "loss": loss_default,
             "loss_after_autotune": b.loss.item(),
+            "kept_states_halo_tiles": tiles,
             "diagnostics": diagnostics(plan, b.workspace)}
 
 

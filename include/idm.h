@@ -114,7 +114,8 @@ typedef struct {
                            only) or 1024; J even, a multiple of K and below threads; grid 0).  A
                            lane of n > threads vehicles is cut into the fewest tiles of at most
                            threads - 1 slots that hold it, ceil((n - J) / (threads - 1 - J)), one
-                           work-group each (a shorter lane is one tile), and the steps into
+                           work-group each (shorter lanes share tiles of threads slots, packed
+                           best-fit decreasing as bundles are), and the steps into
                            blocks of J run as successive launches: a tile also simulates up to J
                            vehicles ahead of its own in the forward and up to J behind them in
                            the backward (each direction splits the lane on its own: the lane head

@@ -250,29 +250,24 @@ struct Layout {
     std::vector<int32_t> level, level_start;
 };
 
-// Halo tiles of T = `threads` slots advancing J steps per launch.  A lane of
-// n <= T vehicles is one tile (no halo).  A longer one is cut into the
-// fewest tiles of at most T - 1 slots that hold it, m = ceil((n - J) /
+// Halo tiles of T = `threads` slots advancing J steps per launch.  Lanes of
+// n <= T vehicles share tiles (pack_whole_lanes).  A longer lane is cut into
+// the fewest tiles of at most T - 1 slots that hold it, m = ceil((n - J) /
 // (T - 1 - J)): the forward's first tile (the lane head) and the backward's
 // last (the lane tail) need no halo on that side, so each direction splits
 // the lane on its own, the m tiles' slot counts (owned vehicles plus halo) as
 // equal as integers allow.  A cut tile never fills its work-group: in the
 // backward the last thread gathers the contribution of thread 0 (the slot
 // after it, modulo T), which is exactly zero only for padding or a lane
-// head, so the slot after a lane tail must be padding (a whole lane in one
-// tile starts with its head).
+// head, so the slot after a lane tail must be padding or a lane head.
 // fn(lane start, lane end, tile j, m, forward owned [lo, hi), backward owned
-// [lo, hi)).
+// [lo, hi)) for every cut tile, lane by lane.
 template <class F>
 void for_each_tile(const std::vector<int32_t> &offsets, int L, int threads, int J, F fn) {
     for (int l = 0; l < L; ++l) {
         const int32_t s0 = offsets[l], e0 = offsets[l + 1];
         const int64_t n = e0 - s0;
-        if (n == 0) continue;
-        if (n <= threads) {
-            fn(s0, e0, 0, 1, s0, e0, s0, e0);
-            continue;
-        }
+        if (n <= threads) continue;
         const int64_t cap = threads - 1;  // J < T, both even: cap - J >= 1
         const int64_t m = (n - J + (cap - J) - 1) / (cap - J);
         const int64_t q = n + (m - 1) * J;  // slots over all tiles
@@ -290,19 +285,59 @@ void for_each_tile(const std::vector<int32_t> &offsets, int L, int threads, int 
     }
 }
 
+// Lanes of at most T vehicles share tiles of T slots: best-fit decreasing
+// (ties keep lane order), as bundles of whole lanes are packed; a tile holds
+// its lanes one after another, in the order they were placed.  Each such tile
+// starts with a lane head, so even a full one gives its last thread an exactly
+// zero contribution from thread 0, and every vehicle in it is owned for any
+// number of steps (no halo).  Returns the lanes of each tile.
+std::vector<std::vector<int>> pack_whole_lanes(const std::vector<int32_t> &offsets, int L,
+                                               int threads) {
+    std::vector<int> order;
+    for (int l = 0; l < L; ++l) {
+        const int64_t sz = offsets[l + 1] - offsets[l];
+        if (sz > 0 && sz <= threads) order.push_back(l);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return (offsets[x + 1] - offsets[x]) > (offsets[y + 1] - offsets[y]);
+    });
+    std::vector<std::vector<int>> tiles;
+    std::vector<int64_t> fill;
+    std::multimap<int64_t, int> room;  // free slots -> tile
+    for (int l : order) {
+        const int64_t sz = offsets[l + 1] - offsets[l];
+        auto it = room.lower_bound(sz);
+        int b;
+        if (it == room.end()) {
+            b = (int)tiles.size();
+            tiles.emplace_back();
+            fill.push_back(0);
+        } else {
+            b = it->second;
+            room.erase(it);
+        }
+        tiles[b].push_back(l);
+        fill[b] += sz;
+        if (threads - fill[b] > 0) room.emplace(threads - fill[b], b);
+    }
+    return tiles;
+}
+
 int64_t count_tiles(const std::vector<int32_t> &offsets, int L, int threads, int J) {
     int64_t n = 0;
     for_each_tile(offsets, L, threads, J,
                   [&](int32_t, int32_t, int, int, int32_t, int32_t, int32_t, int32_t) { ++n; });
-    return n;
+    return n + (int64_t)pack_whole_lanes(offsets, L, threads).size();
 }
 
-// Slot tables of halo tiles: tiles x threads forward slots (up to J halo
-// vehicles ahead of the owned ones, the first slot flagged as a lane head),
-// then tiles x threads backward slots (the owned vehicles, then up to J halo
-// vehicles behind them, the head flag only on a true lane head).  Tile b of
-// the forward and tile b of the backward cover the same lane but may own
-// different vehicles.
+// Slot tables of halo tiles: tiles x threads forward slots, then tiles x
+// threads backward slots; the cut lanes' tiles first, then the shared tiles of
+// whole lanes.  A cut tile's forward slots hold up to J halo vehicles ahead of
+// the owned ones, the first slot flagged as a lane head; its backward slots
+// the owned vehicles, then up to J halo vehicles behind them, the head flag
+// only on a true lane head.  Tile b of the forward and tile b of the backward
+// cover the same lane but may own different vehicles.  A shared tile is the
+// same in both tables: its lanes whole, every vehicle owned.
 idm_status compute_tiles(const std::vector<int32_t> &offsets, int L, const Shape &sh, Layout &out) {
     const int NT = sh.threads, J = sh.tile;
     const int64_t nb = count_tiles(offsets, L, NT, J);
@@ -343,6 +378,19 @@ idm_status compute_tiles(const std::vector<int32_t> &offsets, int L, const Shape
                       }
                       ++b;
                   });
+    for (const std::vector<int> &lanes : pack_whole_lanes(offsets, L, NT)) {
+        int64_t s = b * NT;
+        for (int l : lanes) {
+            for (int32_t i = offsets[l]; i < offsets[l + 1]; ++i, ++s) {
+                uint8_t f = SLOT_VALID | SLOT_OWNED;
+                if (i == offsets[l]) f |= SLOT_HEAD;
+                if (i == offsets[l + 1] - 1) f |= SLOT_TAIL;
+                out.gidx[(size_t)s] = out.gidx[(size_t)(s + nb * NT)] = i;
+                out.flags[(size_t)s] = out.flags[(size_t)(s + nb * NT)] = f;
+            }
+        }
+        ++b;
+    }
     return IDM_OK;
 }
 
@@ -1624,8 +1672,8 @@ idm_status idm_plan_autotune(idm_plan *p, const idm_step_args *a, size_t ws_byte
             }
         }
     // halo tiles (kept states, one vehicle per thread) where some lane is
-    // longer than the work-group (shorter lanes are one tile each, which only
-    // adds launches): J steps per launch, J a multiple of the plan's K
+    // longer than the work-group (otherwise they are whole-lane bundles with
+    // more launches): J steps per launch, J a multiple of the plan's K
     if (p->store_pref >= 1) {
         const int tile_cands[][2] = {{256, 64},  {256, 128}, {512, 128}, {512, 256},
                                      {576, 128}, {640, 128}, {640, 256}, {768, 256},

@@ -158,49 +158,77 @@ def _tile_layout(L, offsets, threads, J, K=16, S=100):
                                            (640, 256, 32), (576, 128, 32)])
 def test_halo_tile_layout(L, threads, J, K):
     """Halo tiles (Sec. III-B: a step moves information one vehicle).  In each
-    direction every vehicle is owned by exactly one tile, and a tile's owned
-    vehicles are consecutive vehicles of one lane; its forward slots are up
-    to J vehicles ahead (fewer only where the lane starts, the first slot
-    flagged as a lane head) and the owned ones; its backward slots the owned
-    ones and up to J behind (fewer only where the lane ends, flagged as a
-    head only on a true lane head).  A lane of at most `threads` vehicles is
-    one tile; a longer one is cut into m = ceil((n - J) / (threads - 1 - J))
-    tiles, tile b of the forward and of the backward on the same lane, their
-    slot counts within one of each other in each direction and at most
-    threads - 1 (the slot after a cut tile's last vehicle is padding, whose
-    contribution to a lane tail the backward's last thread gathers).  The
-    workspace adds the carried adjoints and sums (68 B per vehicle) to the
-    kept states."""
+    direction every vehicle is owned by exactly one tile.  Lanes of at most
+    `threads` vehicles share tiles, packed best-fit decreasing: such a tile is
+    the same in both tables, holds whole lanes one after another (head and
+    tail flags exact, every vehicle owned), and any two of them together would
+    overflow a work-group (when the later one was opened, the earlier lacked
+    room for its first lane).  A longer lane is cut into m = ceil((n - J) /
+    (threads - 1 - J)) tiles of its own, tile b of the forward and of the
+    backward on the same lane; a cut tile's owned vehicles are consecutive; its
+    forward slots are up to J vehicles ahead (fewer only where the lane starts,
+    the first slot flagged as a lane head) and the owned ones; its backward
+    slots the owned ones and up to J behind (fewer only where the lane ends,
+    flagged as a head only on a true lane head); its slot counts within one of
+    each other in each direction and at most threads - 1 (the slot after a cut
+    tile's last vehicle is padding, whose contribution to a lane tail the
+    backward's last thread gathers).  The workspace adds the carried adjoints
+    and sums (68 B per vehicle) to the kept states."""
     import scenarios
     sizes = scenarios.lognormal_lane_sizes(300, np.log(threads) + 0.3, 1.0, 1, 6 * threads, 41)
     # lane 40: n + (m - 1) J divisible by m with T slots per tile (a tile
     # would exactly fill its work-group without the T - 1 cap)
     sizes[[2, 9, 17, 30, 31, 40]] = [threads, threads + 1, 5 * threads, threads - J,
                                      2 * threads - J, 3 * threads - 2 * J]
+    # short lanes to share tiles, two of which fill one exactly
+    sizes[[50, 51, 52, 53, 54]] = [1, 2, threads // 2, threads // 2, 3]
     sizes[::37] = 0
     off = scenarios.offsets_from_sizes(sizes)
     S = 100
     info, ws, gidx, flags = _tile_layout(L, off, threads, J, K=K, S=S)
     N = int(off[-1])
     sz = np.asarray(sizes, dtype=np.int64)
-    need = np.where(sz > threads, -(-(sz - J) // (threads - 1 - J)), np.minimum(sz, 1))
+    need = np.where(sz > threads, -(-(sz - J) // (threads - 1 - J)), 0)
     lane_of = np.repeat(np.arange(len(sizes)), sizes)
     owned = {0: [], 1: []}
     tiles_of_lane = np.zeros(len(sizes), dtype=np.int64)
+    whole_seen = np.zeros(len(sizes), dtype=np.int64)
+    shared_fill = []
     counts = {}
     for b in range(info.n_bundles):
+        g0 = gidx[0, b]
+        if sz[lane_of[g0[0]]] <= threads:
+            # a shared tile of whole lanes
+            assert np.array_equal(gidx[0, b], gidx[1, b]) and np.array_equal(flags[0, b], flags[1, b])
+            k = int(np.sum(g0 >= 0))
+            assert 1 <= k <= threads
+            assert np.all(g0[k:] == -1) and np.all(flags[0, b, k:] == 0)
+            i = 0
+            while i < k:
+                lane = lane_of[g0[i]]
+                ls, le = int(off[lane]), int(off[lane + 1])
+                assert g0[i] == ls and le - ls <= threads
+                seg, f = g0[i:i + le - ls], flags[0, b, i:i + le - ls]
+                assert np.array_equal(seg, np.arange(ls, le))
+                assert np.all((f & 8) != 0) and np.all((f & 4) != 0)   # owned, valid
+                assert np.array_equal(np.nonzero(f & 1)[0], [0])          # head
+                assert np.array_equal(np.nonzero(f & 2)[0], [le - ls - 1])  # tail
+                whole_seen[lane] += 1
+                i += le - ls
+            for d in (0, 1):
+                owned[d].append(g0[:k])
+            shared_fill.append(k)
+            continue
         lanes = []
         for d in (0, 1):
             g, f = gidx[d, b], flags[d, b]
             k = int(np.sum(g >= 0))
-            assert 1 <= k <= threads
-            lane_n = int(sz[lane_of[g[0]]])
-            assert lane_n <= threads or k <= threads - 1
+            assert 1 <= k <= threads - 1
             assert np.all(g[k:] == -1) and np.all(f[k:] == 0)
             seg = g[:k]
             assert np.array_equal(seg, np.arange(seg[0], seg[0] + k))
             lane = lane_of[seg[0]]
-            assert lane_of[seg[-1]] == lane
+            assert lane_of[seg[-1]] == lane and sz[lane] > threads
             lanes.append(lane)
             ls, le = off[lane], off[lane + 1]
             own = seg[(f[:k] & 8) != 0]
@@ -219,6 +247,12 @@ def test_halo_tile_layout(L, threads, J, K):
         assert lanes[0] == lanes[1]
         tiles_of_lane[lanes[0]] += 1
     assert np.array_equal(tiles_of_lane, need)
+    assert np.array_equal(whole_seen, ((sz > 0) & (sz <= threads)).astype(np.int64))
+    fill = np.asarray(shared_fill)
+    assert len(fill) >= 1 and threads in fill
+    pair = fill[:, None] + fill[None, :]
+    np.fill_diagonal(pair, threads + 1)
+    assert np.all(pair > threads)
     for d in (0, 1):
         o = np.concatenate(owned[d])
         assert len(o) == N and np.array_equal(np.sort(o), np.arange(N))

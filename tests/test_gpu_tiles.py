@@ -167,8 +167,8 @@ def test_tiles_stop_and_go_counts(mode):
     log("tiles stop-and-go mode %d: counts %s, min speed %.3f" % (mode, t["diag"],
                                                                   float(np.min(t["v"]))))
     _same(t, ref, "stop-and-go mode %d" % mode)
-    # overlapping vehicles: lanes of 8, one tile each at 256 threads, so a
-    # long lane is added to cut
+    # overlapping vehicles (negative gaps) on three 700-vehicle lanes, each cut
+    # into tiles
     n_lanes, lane_len = 3, 700
     off = scenarios.uniform_lanes(n_lanes, lane_len)
     n = int(off[-1])
