@@ -134,12 +134,14 @@ def test_tiles_targets_only_and_dense_only(dense_only):
 
 def test_tiles_edge_steps():
     """S = 0 (one launch writing the initial row), S = 1, S below, at and just
-    above one block of J, two blocks; single vehicles and lanes just longer
-    than a tile."""
+    above one block of J, two blocks; single vehicles, lanes just longer than
+    a tile, and two short lanes sharing a tile they fill exactly (its last
+    thread, a lane tail, gathers from thread 0, the other lane's head)."""
     for sizes, S, threads, J, K in (([1, 300], 0, 256, 64, 16), ([300, 1], 1, 256, 64, 16),
                                     ([700], 63, 256, 64, 16), ([700, 2], 64, 256, 64, 16),
                                     ([257, 9], 65, 256, 32, 8), ([900], 128, 512, 128, 32),
-                                    ([1, 513, 40], 129, 512, 128, 64)):
+                                    ([1, 513, 40], 129, 512, 128, 64),
+                                    ([128, 700, 128, 2, 1], 70, 256, 64, 16)):
         sc = ragged_scenario(sizes, S, ckpt_every=K)
         dense = scenarios.noise((S + 1, sc.n), 5, sigma=1.0).astype(np.float32)
         if S > 0:
