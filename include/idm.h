@@ -369,7 +369,11 @@ idm_status idm_fit_run(idm_plan *plan, const idm_fit_state *st, const double *p0
 
 /* Forward + backward as one HIP graph (captured on first use for a given
  * argument set, then replayed): the batched launch for many independent
- * lanes.  Arguments as in idm_sim_forward / idm_sim_backward. */
+ * lanes.  Arguments as in idm_sim_forward / idm_sim_backward, except that a
+ * plan keeping every step's states (store_states 1) keeps them in traj_d /
+ * traj_v where those are given, instead of in the workspace, and the step's
+ * backward reads them there (no copy between the two); a later
+ * idm_sim_backward on that workspace does not see them. */
 typedef struct {
     idm_params prm;
     const double *p0;

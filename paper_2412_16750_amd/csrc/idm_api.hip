@@ -767,14 +767,27 @@ int32_t tile_launches(const idm_plan *p) {
     return S == 0 ? 1 : (S + J - 1) / J;
 }
 
+// Where a forward that keeps every step's states writes them: the
+// workspace's rows, or with `direct` (forward + backward of one step, whose
+// backward reads them where they are) the caller's trajectory outputs where
+// given, which then need no copy.
+void kept_rows(const idm_plan *p, void *ws, bool direct, float *&traj_d, float *&traj_v,
+               float *&st_d, float *&st_v) {
+    st_d = (float *)((char *)ws + ws_states_off(p));
+    st_v = (float *)((char *)st_d + state_rows_bytes(p));
+    if (!direct) return;
+    if (traj_d) st_d = traj_d;
+    if (traj_v) st_v = traj_v;
+    traj_d = traj_v = nullptr;
+}
+
 // The halo-tile forward: every launch advances every tile J steps, reading
 // the states its halo starts from in the rows the previous launch wrote.
 idm_status run_forward_tiled(idm_plan *p, SimArgs a, float *traj_d, float *traj_v, void *ws,
-                             hipStream_t s) {
+                             hipStream_t s, bool direct) {
     float *st_d = nullptr, *st_v = nullptr;
     if (ws) {
-        st_d = (float *)((char *)ws + ws_states_off(p));
-        st_v = (float *)((char *)st_d + state_rows_bytes(p));
+        kept_rows(p, ws, direct, traj_d, traj_v, st_d, st_v);
     } else if (traj_d && traj_v) {
         st_d = traj_d;  // no workspace: the caller's rows hold the states
         st_v = traj_v;
@@ -809,12 +822,13 @@ idm_status run_forward_tiled(idm_plan *p, SimArgs a, float *traj_d, float *traj_
 }
 
 idm_status run_forward(idm_plan *p, const idm_params *prm, const double *p0, const float *v_init,
-                       float *traj_d, float *traj_v, void *ws, hipStream_t s) {
+                       float *traj_d, float *traj_v, void *ws, hipStream_t s,
+                       bool direct = false) {
     SimArgs a = base_args(p);
     a.v0 = prm->v0; a.T = prm->T; a.a = prm->a; a.b = prm->b; a.s0 = prm->s0; a.len = prm->length;
     a.p0 = p0;
     a.v_init = v_init;
-    if (p->sh.tile > 0) return run_forward_tiled(p, a, traj_d, traj_v, ws, s);
+    if (p->sh.tile > 0) return run_forward_tiled(p, a, traj_d, traj_v, ws, s, direct);
     a.traj_d = traj_d;
     a.traj_v = traj_v;
     a.ckpt = ws ? (float *)((char *)ws + ws_ckpt_off(p)) : nullptr;
@@ -823,8 +837,7 @@ idm_status run_forward(idm_plan *p, const idm_params *prm, const double *p0, con
     // (no checkpoints) and copies them out for a caller that asked for them
     float *st_d = nullptr, *st_v = nullptr;
     if (p->sh.stored && ws) {
-        st_d = (float *)((char *)ws + ws_states_off(p));
-        st_v = (float *)((char *)st_d + state_rows_bytes(p));
+        kept_rows(p, ws, direct, traj_d, traj_v, st_d, st_v);
         a.traj_d = st_d;
         a.traj_v = st_v;
         a.ckpt = nullptr;
@@ -1069,9 +1082,19 @@ idm_status run_fit_step(idm_plan *p, const idm_fit_state *st, const double *p0, 
 }
 
 idm_status run_step(idm_plan *p, const idm_step_args *a, hipStream_t s) {
-    idm_status r = run_forward(p, &a->prm, a->p0, a->v_init, a->traj_d, a->traj_v, a->workspace, s);
+    // a plan that keeps states writes them straight into the trajectory
+    // outputs the caller asked for, and the backward reads them there
+    idm_status r = run_forward(p, &a->prm, a->p0, a->v_init, a->traj_d, a->traj_v, a->workspace,
+                               s, true);
     if (r != IDM_OK) return r;
     idm_obs obs{a->obs_target, a->n_obs, a->obs_first, a->obs_stride};
+    if (p->sh.stored) {
+        float *td = a->traj_d, *tv = a->traj_v, *st_d = nullptr, *st_v = nullptr;
+        kept_rows(p, a->workspace, true, td, tv, st_d, st_v);
+        return run_backward_stored(p, &a->prm, a->p0, st_d, st_v, a->grad_traj_d, a->grad_traj_v,
+                                   a->obs_target ? &obs : nullptr, a->grad_params, a->grad_p0,
+                                   a->grad_v0, a->loss_out, a->workspace, s);
+    }
     return run_backward(p, &a->prm, a->p0, a->v_init, a->grad_traj_d, a->grad_traj_v,
                         a->obs_target ? &obs : nullptr, a->grad_params, a->grad_p0, a->grad_v0,
                         a->loss_out, a->workspace, s);

@@ -285,10 +285,13 @@ def test_tiles_autotune_and_full_fit_workload():
 
 def test_tiles_step_graph_autograd_noalloc_and_forward_helper():
     """A tiled plan under the other entry points: the step graph with
-    trajectory outputs (several launches and the row copies inside one
-    graph) replayed three times with eager work in between, autograd, the
-    no-allocation gradient and a forward-only call through the plan's
-    forward workspace all equal the whole-lane plan's results."""
+    trajectory outputs (several launches inside one graph, the kept states
+    written straight into the outputs and read back from them) replayed three
+    times with eager work in between, the step graph with only the
+    displacement output (speeds kept in the workspace), also on a whole-lane
+    plan keeping states, autograd, the no-allocation gradient and a
+    forward-only call through the plan's forward workspace all equal the
+    whole-lane plan's results."""
     import torch
     from paper_2412_16750_amd import autograd, sim
     sc = ragged_scenario([900, 33, 700, 1, 300], 150, ckpt_every=16)
@@ -316,6 +319,19 @@ def test_tiles_step_graph_autograd_noalloc_and_forward_helper():
         for k in ("traj_d", "traj_v", "grad_params", "grad_p0", "grad_v0"):
             assert torch.equal(getattr(b, k), getattr(ref, k)), (rep, k)
         assert abs(b.loss.item() - ref.loss.item()) <= 1e-12 * ref.loss.item()
+    kept = sim.Plan.for_scenario(sc, ckpt_every=16, store_states=True)
+    for plan in (tiled, kept):
+        bd = sim.StepBuffers(plan, x["prm"], x["length"], x["p0"], x["v"],
+                             traj_d=torch.full((S + 1, n), float("nan"), device="cuda"), obs=obs)
+        for rep in range(2):
+            bd.grad_params.fill_(float("nan"))
+            torch.cuda.synchronize()
+            sim.idm_step_graph_launch(bd)
+            torch.cuda.synchronize()
+            for k in ("traj_d", "grad_params", "grad_p0", "grad_v0"):
+                assert torch.equal(getattr(bd, k), getattr(ref, k)), (plan.info()["tile_steps"], k)
+            assert abs(bd.loss.item() - ref.loss.item()) <= 1e-12 * ref.loss.item()
+        del bd
     grads = []
     for plan in (whole, tiled):
         prm = x["prm"].clone().requires_grad_(True)
